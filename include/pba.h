@@ -1,0 +1,205 @@
+/*
+ * pba.h - C ABI of libpba, photometric bundle adjustment on one MI355X (gfx950).
+ *
+ * The library runs the Gauss-Newton iteration of photometric bundle adjustment
+ * over 6-DoF frame poses and per-point inverse depths (Ham, Lucey & Singh,
+ * "Proxy Templates for Inverse Compositional Photometric Bundle Adjustment",
+ * arXiv 1704.06967), in two forms:
+ *   - forward compositional (FC): the Jacobian and the Hessian are rebuilt and
+ *     factorized at every iteration (the paper's baseline, Sec. 1-2);
+ *   - inverse compositional with proxy templates (IC): the Jacobian (Sec. 3.4,
+ *     3.5) and H = J^T W0 J are built once per pyramid level; each iteration
+ *     recomputes the Huber weights, forms g = J^T W r, solves dp = -H^{-1} g and
+ *     composes the warps (Sec. 3.5 steps 1-4, Sec. 3.6 update equations).
+ *
+ * Problem (eq:energy, eq:warp): frames f with images I_f and world->camera
+ * poses (R_f, t_f); points n with a host frame h(n), a host pixel, one inverse
+ * depth d_n shared by the points' patch pixels, and the list of frames that
+ * observe them. One residual per (point, observing frame, patch pixel):
+ *   r = I_h(x) - I_f(W(x; p)),  W(x; p) = <R x~ + d t>,
+ * with (R, t) the pose of f relative to h. Images are bilinear functions
+ * (Notation); the energy is the Huber norm of the residuals (eq:energy).
+ *
+ * Conventions (the paper states none):
+ *   - pixel centres at integer coordinates, u = column, v = row;
+ *   - intrinsics per frame (fx, fy, cx, cy) at level 0; level l uses f / 2^l
+ *     and (c + 0.5) / 2^l - 0.5; level l+1 is the 2x2 box average of level l;
+ *   - a pose is 12 doubles: R row-major, then t (X_cam = R X_world + t);
+ *   - pose increments are decoupled left increments R <- exp(w) R, t <- t + dt,
+ *     ordered (w_x, w_y, w_z, t_x, t_y, t_z);
+ *   - a residual is usable when its host pattern pixel and its target pixel lie
+ *     in [1, W_l - 3] x [1, H_l - 3], the point is in front of the target
+ *     camera and d > 0. The usable set is frozen at the start of a level; a
+ *     frozen residual that leaves the image later gets weight 0;
+ *   - the reduced pose system pins one frame (identity rows, zero rhs) and
+ *     damps pose and depth diagonals by damping_rel times their mean.
+ *
+ * Ownership: pba_set_* deep-copy their inputs (host or device memory, per the
+ * `mem` argument); the caller may free them on return. Output buffers are owned
+ * by the caller. The context owns every device buffer it allocates.
+ *
+ * Errors: every entry point returns a pba_status; nothing aborts or throws
+ * across the ABI. Arguments are validated before any device work; on error the
+ * context state is unchanged and pba_last_error() describes the cause.
+ *
+ * Calls on one context are synchronous with respect to the host (they return
+ * after the device work they enqueue has finished). One context must not be
+ * used from two threads at once; distinct contexts are independent.
+ */
+#ifndef PBA_H
+#define PBA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct pba_ctx pba_ctx;
+
+typedef enum {
+    PBA_OK = 0,
+    PBA_E_INVALID = -1,      /* an argument is out of range or inconsistent */
+    PBA_E_STATE = -2,        /* call out of order (e.g. iterate before set_points) */
+    PBA_E_OOM = -3,          /* device allocation failed */
+    PBA_E_DEVICE = -4,       /* no usable gfx950 device, or a HIP call failed */
+    PBA_E_NUMERIC = -5,      /* reduced system not positive definite; parameters unchanged */
+    PBA_E_NOT_CONVERGED = -6 /* pba_solve hit its iteration cap on the finest level */
+} pba_status;
+
+enum { PBA_FC = 0, PBA_IC_PROXY = 1 };                        /* pba_config.mode */
+enum { PBA_FP64 = 0, PBA_FP32 = 1, PBA_MIXED_BF16 = 2 };      /* pba_config.precision */
+enum { PBA_SOLVER_CHOL = 0 };                                 /* pba_config.solver */
+enum { PBA_HOST = 0, PBA_DEVICE = 1 };                        /* memory of input pointers */
+enum { PBA_FLAG_TIMING = 1 };                                 /* pba_config.flags */
+
+#define PBA_MAX_PATTERN 8
+#define PBA_MAX_LEVELS 4
+
+typedef struct {
+    int32_t mode;        /* PBA_FC or PBA_IC_PROXY */
+    int32_t precision;   /* PBA_FP64: all arithmetic in double. PBA_FP32: residuals,
+                            Jacobians and per-observation blocks in float, reductions,
+                            Schur complement and Cholesky in double */
+    int32_t n_levels;    /* image pyramid levels, 1..PBA_MAX_LEVELS */
+    int32_t pattern_n;   /* patch pixels per point, 1..PBA_MAX_PATTERN */
+    int32_t pattern_uv[2 * PBA_MAX_PATTERN]; /* (du, dv) offsets in level pixels, |du|,|dv| <= 4 */
+    double huber_k;      /* Huber threshold in intensity units (> 0; +inf = least squares) */
+    double damping_rel;  /* diagonal damping relative to the mean diagonal (>= 0) */
+    int32_t pinned_frame;/* frame whose pose is held fixed (gauge), or -1 */
+    int32_t solver;      /* PBA_SOLVER_CHOL */
+    int32_t n_windows;   /* independent problems held by the context; must be 1 */
+    int32_t flags;       /* PBA_FLAG_TIMING: time the residual kernel with HIP events */
+    void *stream;        /* hipStream_t to run on, or NULL for a library-owned stream */
+} pba_config;
+
+typedef struct {
+    int32_t level;          /* pyramid level of this iteration */
+    int32_t iter;           /* iteration index within the level */
+    int64_t n_active;       /* residuals that contributed (weight > 0) */
+    double energy;          /* sum of Huber norms at the parameters the iteration started from */
+    double sq;              /* sum of squared residuals over the same set */
+    double rmse;            /* sqrt(sq / n_active) */
+    double max_disp_px;     /* largest level-0 displacement of any observation's point
+                               centre caused by this iteration's update (Sec. 4.1 test) */
+    double max_step_pose;   /* max |dtheta| over all frames and components */
+    double max_step_depth;  /* max |dd| over all points */
+} pba_iter_stats;
+
+typedef struct {
+    int32_t iters[PBA_MAX_LEVELS]; /* iterations run per level (index = level) */
+    int32_t total_iters;
+    int32_t converged;             /* 1 if the finest level met conv_px */
+    double final_energy;           /* at the returned parameters, level 0, fresh usable set */
+    double final_rmse;
+    int64_t final_active;
+} pba_result;
+
+typedef struct {
+    int64_t residual_launches;     /* launches of the per-iteration residual kernel */
+    double residual_ms;            /* their summed duration (HIP events; needs PBA_FLAG_TIMING) */
+    int64_t residuals_processed;   /* residual slots those launches covered */
+} pba_timing;
+
+/* Debug / verification buffers for pba_debug_fetch (element type in brackets;
+ * "real" is double for PBA_FP64, float otherwise). */
+enum {
+    PBA_DBG_S = 1,          /* [double 6F x 6F] damped, pinned Schur complement of the last
+                               system assembled (row-major); for 6F > 192 the buffer holds
+                               its Cholesky factor (lower triangle) once it has been factored */
+    PBA_DBG_B = 2,          /* [double 6F] reduced right-hand side of the last iteration */
+    PBA_DBG_OBS_REC = 3,    /* [real O x 40] per-observation blocks: 0-20 upper triangle of
+                               sum w J_th^T J_th (row-major), 21-26 sum w J_th J_d, 27 sum w J_d^2,
+                               28-33 sum w J_th r, 34 sum w J_d r, 35 energy, 36 sum r^2,
+                               37 active count (relative-pose coordinates) */
+    PBA_DBG_TEMPLATE = 4,   /* [real N x P x 4] (I0, dI0/du, dI0/dv, usable) at the current level */
+    PBA_DBG_HDD = 5,        /* [double N] damped depth diagonal of the last system */
+    PBA_DBG_MASK = 6,       /* [uint8 O] bit j set if patch pixel j is in the frozen usable set */
+    PBA_DBG_DTHETA = 7      /* [double 6F] pose step of the last iteration */
+};
+
+/* Fill *cfg with defaults: IC, FP32, 1 level, the 8-pixel diamond pattern
+ * {(0,0),(0,-2),(-1,-1),(1,-1),(-2,0),(2,0),(-1,1),(1,1)}, Huber 9/255,
+ * damping 1e-6, frame 0 pinned, Cholesky, one window, no flags, own stream. */
+pba_status pba_config_default(pba_config *cfg);
+
+/* Create a context on the current HIP device (must be gfx950). Validates *cfg. */
+pba_status pba_create(const pba_config *cfg, pba_ctx **out);
+
+/* Define the frames: n_frames images of width x height pixels
+ * (images [F][H][W] float32, row-major), intrinsics [F][4] (fx, fy, cx, cy,
+ * level-0 pixels), poses [F][12] world->camera. window must be 0. Resets any
+ * points previously set. Width and height must be >= 8 * 2^(n_levels-1). */
+pba_status pba_set_frames(pba_ctx *ctx, int32_t window, int32_t n_frames, int32_t width, int32_t height,
+                          const float *images, const double *intrinsics, const double *poses, int32_t mem);
+
+/* Define the points: host_frame [N], host_uv [N][2] (level-0 pixel of the point
+ * centre), inv_depth [N] (> 0), and the observing frames in CSR form
+ * (obs_ptr [N+1], obs_frame [O]; per point strictly increasing, never the
+ * host). These parameters become the starting point of the next level. */
+pba_status pba_set_points(pba_ctx *ctx, int32_t window, int32_t n_points, const int32_t *host_frame,
+                          const float *host_uv, const double *inv_depth, const int32_t *obs_ptr,
+                          const int32_t *obs_frame, int32_t mem);
+
+/* Run exactly n_iters Gauss-Newton iterations on pyramid `level`. If the
+ * context's current level differs (or parameters were set since), the level
+ * starts over: p(0) := current parameters, usable set frozen, and in IC mode
+ * the constant system is built and factorized. stats: n_iters entries or NULL. */
+pba_status pba_iterate(pba_ctx *ctx, int32_t level, int32_t n_iters, pba_iter_stats *stats);
+
+/* Coarse-to-fine solve: for each level from n_levels-1 down to 0, start the
+ * level and iterate until max_disp_px < conv_px (the paper uses 5e-3) or
+ * max_iters_per_level iterations. Returns PBA_E_NOT_CONVERGED (with *out
+ * filled and parameters updated) if level 0 did not converge. */
+pba_status pba_solve(pba_ctx *ctx, int32_t max_iters_per_level, double conv_px, pba_result *out);
+
+/* Energy / RMSE at the current parameters on `level` over the residuals usable
+ * at those parameters (not the frozen set). Fills level, n_active, energy, sq, rmse. */
+pba_status pba_evaluate(pba_ctx *ctx, int32_t level, pba_iter_stats *out);
+
+/* Copy the current parameters out (host memory): poses [F][12], inv_depth [N]. */
+pba_status pba_get_params(pba_ctx *ctx, int32_t window, double *poses, double *inv_depth);
+
+/* Overwrite the current parameters (host memory); the next iterate restarts the level. */
+pba_status pba_set_params(pba_ctx *ctx, int32_t window, const double *poses, const double *inv_depth);
+
+/* Copy an internal buffer (PBA_DBG_*) to host memory; bytes must match its size exactly. */
+pba_status pba_debug_fetch(pba_ctx *ctx, int32_t what, void *out, size_t bytes);
+
+/* Kernel timing accumulated since the last call (then reset). */
+pba_status pba_get_timing(pba_ctx *ctx, pba_timing *out);
+
+/* Release the context and all its device memory. NULL is allowed. */
+void pba_destroy(pba_ctx *ctx);
+
+/* Message of the last error on this context (never NULL; "" if none). */
+const char *pba_last_error(const pba_ctx *ctx);
+
+/* Static name of a status code. */
+const char *pba_status_string(pba_status s);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PBA_H */

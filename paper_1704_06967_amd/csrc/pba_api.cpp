@@ -1,0 +1,861 @@
+// Host runtime of libpba: the C ABI declared in include/pba.h.
+//
+// Every entry point validates its arguments on the host before touching the
+// device, so error paths are testable without a GPU. Device work is enqueued on
+// the context's stream; each entry point synchronizes that stream before it
+// returns.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "pba_internal.hpp"
+
+namespace pba {
+void launch_fill(hipStream_t s, double *p, size_t n, double v);
+}
+
+using namespace pba;
+
+struct pba_ctx {
+    Ctx c;
+};
+
+namespace {
+
+thread_local std::string g_create_err;
+
+constexpr int GRAM_CHUNK = 128;  // points per Gram workgroup
+
+pba_status fail(Ctx *c, pba_status s, const std::string &msg) {
+    if (c)
+        c->err = msg;
+    else
+        g_create_err = msg;
+    return s;
+}
+
+#define HIPCHK(expr)                                                                               \
+    do {                                                                                           \
+        hipError_t e_ = (expr);                                                                    \
+        if (e_ != hipSuccess)                                                                      \
+            return fail(&c, e_ == hipErrorOutOfMemory ? PBA_E_OOM : PBA_E_DEVICE,                  \
+                        std::string(#expr) + ": " + hipGetErrorString(e_));                        \
+    } while (0)
+
+template <typename P>
+hipError_t dalloc(P *&p, size_t bytes) {
+    if (p) {
+        hipFree((void *)p);
+        p = nullptr;
+    }
+    if (bytes == 0) bytes = 8;
+    return hipMalloc((void **)&p, bytes);
+}
+
+template <typename P>
+void dfree(P *&p) {
+    if (p) hipFree((void *)p);
+    p = nullptr;
+}
+
+bool finite_all(const double *p, size_t n) {
+    for (size_t i = 0; i < n; ++i)
+        if (!std::isfinite(p[i])) return false;
+    return true;
+}
+
+// Copy n elements of caller memory (host or device) into a host vector.
+template <typename V>
+hipError_t fetch(std::vector<V> &dst, const V *src, size_t n, int mem) {
+    dst.resize(n);
+    if (n == 0) return hipSuccess;
+    if (mem == PBA_DEVICE) return hipMemcpy(dst.data(), src, n * sizeof(V), hipMemcpyDeviceToHost);
+    std::memcpy(dst.data(), src, n * sizeof(V));
+    return hipSuccess;
+}
+
+template <typename V>
+hipError_t upload(Ctx &c, V *&dptr, const std::vector<V> &v) {
+    hipError_t e = dalloc(dptr, v.size() * sizeof(V));
+    if (e != hipSuccess) return e;
+    if (v.empty()) return hipSuccess;
+    return hipMemcpyAsync(dptr, v.data(), v.size() * sizeof(V), hipMemcpyHostToDevice, c.stream);
+}
+
+void release_points(Ctx &c) {
+    for (int **p : {&c.d_host_frame, &c.d_obs_ptr, &c.d_obs_frame, &c.d_obs_point, &c.d_obs_pair, &c.d_pair_host,
+                    &c.d_pair_target, &c.d_pair_obs_ptr, &c.d_pair_obs_idx, &c.d_frame_pair_ptr,
+                    &c.d_frame_pair_item, &c.d_pair_local, &c.d_pair_hidx, &c.d_host_m, &c.d_host_frames,
+                    &c.d_host_pts, &c.d_chunk_host, &c.d_chunk_begin, &c.d_chunk_end, &c.d_chunk_off,
+                    &c.d_host_chunk_ptr, &c.d_blk_fa, &c.d_blk_fb, &c.d_blk_pp_ptr, &c.d_blk_pp_item,
+                    &c.d_blk_g_ptr, &c.d_blk_g_item})
+        dfree(*p);
+    dfree(c.d_host_uv);
+    dfree(c.d_mask);
+    dfree(c.d_rec);
+    dfree(c.d_depth);
+    dfree(c.d_depth0);
+    for (double **p : {&c.d_geo0, &c.d_geo_a, &c.d_geo_b, &c.d_pairH, &c.d_pairY, &c.d_Hdd, &c.d_gd,
+                       &c.d_hdd_part, &c.d_gram, &c.d_dth_rel})
+        dfree(*p);
+    dfree(c.d_rel0);
+    dfree(c.d_rel_a);
+    dfree(c.d_rel_b);
+    for (int l = 0; l < PBA_MAX_LEVELS; ++l) {
+        dfree(c.lv[l].tmpl);
+        c.lv[l].tmpl_valid = false;
+    }
+    c.have_points = false;
+    c.cur_level = -1;
+    c.N = c.O = 0;
+}
+
+void release_frames(Ctx &c) {
+    release_points(c);
+    for (int l = 0; l < PBA_MAX_LEVELS; ++l) {
+        dfree(c.lv[l].img);
+        dfree(c.lv[l].K);
+        c.lv[l].W = c.lv[l].H = 0;
+    }
+    for (double **p : {&c.d_poses, &c.d_poses0, &c.d_K0, &c.d_S, &c.d_Sinv, &c.d_b, &c.d_dtheta, &c.d_stats,
+                       &c.d_mu})
+        dfree(*p);
+    dfree(c.d_flag);
+    c.stats_cap = 0;
+    c.have_frames = false;
+    c.F = 0;
+}
+
+std::string validate_config(const pba_config *cfg) {
+    if (!cfg) return "cfg is NULL";
+    if (cfg->mode != PBA_FC && cfg->mode != PBA_IC_PROXY) return "mode must be PBA_FC or PBA_IC_PROXY";
+    if (cfg->precision != PBA_FP64 && cfg->precision != PBA_FP32 && cfg->precision != PBA_MIXED_BF16)
+        return "unknown precision";
+    if (cfg->precision == PBA_MIXED_BF16) return "PBA_MIXED_BF16 is not available in this build";
+    if (cfg->n_levels < 1 || cfg->n_levels > PBA_MAX_LEVELS) return "n_levels must be in 1..4";
+    if (cfg->pattern_n < 1 || cfg->pattern_n > PBA_MAX_PATTERN) return "pattern_n must be in 1..8";
+    for (int j = 0; j < cfg->pattern_n; ++j)
+        if (std::abs(cfg->pattern_uv[2 * j]) > 4 || std::abs(cfg->pattern_uv[2 * j + 1]) > 4)
+            return "pattern offsets must satisfy |du|, |dv| <= 4";
+    if (!(cfg->huber_k > 0.0)) return "huber_k must be > 0";
+    if (!(cfg->damping_rel >= 0.0) || !std::isfinite(cfg->damping_rel)) return "damping_rel must be finite and >= 0";
+    if (cfg->pinned_frame < -1) return "pinned_frame must be >= -1";
+    if (cfg->solver != PBA_SOLVER_CHOL) return "solver must be PBA_SOLVER_CHOL";
+    if (cfg->n_windows != 1) return "n_windows must be 1";
+    if (cfg->flags & ~PBA_FLAG_TIMING) return "unknown flag bits";
+    return "";
+}
+
+bool is_fp64(const Ctx &c) { return c.cfg.precision == PBA_FP64; }
+
+// ---- structure of the problem: pairs, host groups, Gram chunks, nonzero blocks
+std::string build_structure(Ctx &c, const std::vector<int> &host_frame, const std::vector<int> &obs_ptr,
+                            const std::vector<int> &obs_frame) {
+    Structure &s = c.st;
+    s = Structure();
+    const int N = c.N, O = c.O, F = c.F;
+    s.obs_point.resize(O);
+    for (int n = 0; n < N; ++n)
+        for (int o = obs_ptr[n]; o < obs_ptr[n + 1]; ++o) s.obs_point[o] = n;
+    std::map<long long, int> pid;
+    for (int o = 0; o < O; ++o) pid[(long long)host_frame[s.obs_point[o]] * F + obs_frame[o]] = 0;
+    s.n_pairs = 0;
+    for (auto &kv : pid) {
+        kv.second = s.n_pairs++;
+        s.pair_host.push_back((int)(kv.first / F));
+        s.pair_target.push_back((int)(kv.first % F));
+    }
+    const int Pn = s.n_pairs;
+    s.obs_pair.resize(O);
+    for (int o = 0; o < O; ++o) s.obs_pair[o] = pid[(long long)host_frame[s.obs_point[o]] * F + obs_frame[o]];
+    s.pair_obs_ptr.assign(Pn + 1, 0);
+    for (int o = 0; o < O; ++o) s.pair_obs_ptr[s.obs_pair[o] + 1]++;
+    for (int p = 0; p < Pn; ++p) s.pair_obs_ptr[p + 1] += s.pair_obs_ptr[p];
+    s.pair_obs_idx.resize(O);
+    {
+        std::vector<int> fill(s.pair_obs_ptr.begin(), s.pair_obs_ptr.end() - 1);
+        for (int o = 0; o < O; ++o) s.pair_obs_idx[fill[s.obs_pair[o]]++] = o;
+    }
+    s.frame_pair_ptr.assign(F + 1, 0);
+    for (int p = 0; p < Pn; ++p) {
+        s.frame_pair_ptr[s.pair_target[p] + 1]++;
+        s.frame_pair_ptr[s.pair_host[p] + 1]++;
+    }
+    for (int f = 0; f < F; ++f) s.frame_pair_ptr[f + 1] += s.frame_pair_ptr[f];
+    s.frame_pair_item.resize(2 * Pn);
+    {
+        std::vector<int> fill(s.frame_pair_ptr.begin(), s.frame_pair_ptr.end() - 1);
+        for (int p = 0; p < Pn; ++p) {  // pair order inside every frame list
+            s.frame_pair_item[fill[s.pair_target[p]]++] = p * 2;
+            s.frame_pair_item[fill[s.pair_host[p]]++] = p * 2 + 1;
+        }
+    }
+    // host groups (pairs are sorted by host, then target)
+    std::vector<int> hidx_of_frame(F, -1);
+    s.pair_local.resize(Pn);
+    s.pair_hidx.resize(Pn);
+    for (int p = 0; p < Pn; ++p) {
+        const int h = s.pair_host[p];
+        if (hidx_of_frame[h] < 0) {
+            hidx_of_frame[h] = (int)s.hosts.size();
+            s.hosts.push_back(h);
+            s.host_m.push_back(0);
+        }
+        const int hi = hidx_of_frame[h];
+        s.pair_hidx[p] = hi;
+        s.pair_local[p] = s.host_m[hi]++;
+    }
+    for (size_t hi = 0; hi < s.hosts.size(); ++hi)
+        if (s.host_m[hi] > MAX_HOST_TARGETS)
+            return "host frame " + std::to_string(s.hosts[hi]) + " has " + std::to_string(s.host_m[hi]) +
+                   " distinct target frames (limit " + std::to_string(MAX_HOST_TARGETS) + ")";
+    const int NH = (int)s.hosts.size();
+    // points grouped by host (points without observations are skipped)
+    std::vector<std::vector<int>> by_host(NH);
+    for (int n = 0; n < N; ++n)
+        if (obs_ptr[n + 1] > obs_ptr[n]) by_host[hidx_of_frame[host_frame[n]]].push_back(n);
+    s.host_chunk_ptr.assign(NH + 1, 0);
+    size_t off = 0;
+    for (int hi = 0; hi < NH; ++hi) {
+        const int E = 6 * (s.host_m[hi] + 1);
+        const int b0 = (int)s.host_pts.size();
+        for (int n : by_host[hi]) s.host_pts.push_back(n);
+        const int b1 = (int)s.host_pts.size();
+        for (int b = b0; b < b1; b += GRAM_CHUNK) {
+            s.chunk_host.push_back(hi);
+            s.chunk_begin.push_back(b);
+            s.chunk_end.push_back(std::min(b1, b + GRAM_CHUNK));
+            s.chunk_off.push_back((int)off);
+            off += (size_t)E * E;
+        }
+        s.host_chunk_ptr[hi + 1] = (int)s.chunk_host.size();
+    }
+    s.gram_floats = off;
+    if (off > (size_t)INT32_MAX) return "too many points for the Schur Gram buffers";
+    // nonzero blocks of S
+    std::map<long long, std::pair<std::vector<int>, std::vector<int>>> blk;
+    auto key = [F](int a, int b) { return (long long)a * F + b; };
+    for (int f = 0; f < F; ++f) blk[key(f, f)];
+    for (int p = 0; p < Pn; ++p) {
+        const int t = s.pair_target[p], h = s.pair_host[p];
+        blk[key(t, t)].first.push_back(p * 4 + 0);
+        blk[key(h, h)].first.push_back(p * 4 + 1);
+        blk[key(t, h)].first.push_back(p * 4 + 2);
+        blk[key(h, t)].first.push_back(p * 4 + 3);
+    }
+    for (int hi = 0; hi < NH; ++hi) {
+        std::vector<int> ext;
+        for (int p = 0; p < Pn; ++p)
+            if (s.pair_hidx[p] == hi) ext.push_back(s.pair_target[p]);
+        ext.push_back(s.hosts[hi]);
+        for (int a = 0; a < (int)ext.size(); ++a)
+            for (int b = 0; b < (int)ext.size(); ++b)
+                blk[key(ext[a], ext[b])].second.push_back(hi * 4096 + a * 64 + b);
+    }
+    s.blk_pp_ptr.push_back(0);
+    s.blk_g_ptr.push_back(0);
+    for (auto &kv : blk) {
+        s.blk_fa.push_back((int)(kv.first / F));
+        s.blk_fb.push_back((int)(kv.first % F));
+        for (int it : kv.second.first) s.blk_pp_item.push_back(it);
+        for (int it : kv.second.second) s.blk_g_item.push_back(it);
+        s.blk_pp_ptr.push_back((int)s.blk_pp_item.size());
+        s.blk_g_ptr.push_back((int)s.blk_g_item.size());
+    }
+    return "";
+}
+
+// ---- level start and iterations, per element type
+template <typename T>
+pba_status start_level(Ctx &c, int level) {
+    hipStream_t s = c.stream;
+    if (!c.lv[level].tmpl_valid) {
+        Launch<T>::make_template(s, c, level);
+        c.lv[level].tmpl_valid = true;
+    }
+    const size_t F12 = (size_t)c.F * 12 * sizeof(double);
+    HIPCHK(hipMemcpyAsync(c.d_poses0, c.d_poses, F12, hipMemcpyDeviceToDevice, s));
+    HIPCHK(hipMemcpyAsync(c.d_depth0, c.d_depth, std::max<size_t>(1, c.N) * sizeof(double),
+                          hipMemcpyDeviceToDevice, s));
+    Launch<T>::relpose(s, c, c.d_poses0, c.d_geo0, (T *)c.d_rel0);
+    Launch<T>::relpose(s, c, c.d_poses0, c.d_geo_a, (T *)c.d_rel_a);
+    c.flip = false;
+    if (c.cfg.mode == PBA_IC_PROXY) {
+        // J (Sec. 3.4) and W0 at p(0); H = J^T W0 J, depth Schur complement, Cholesky, inverse
+        Launch<T>::ic_linearize(s, c, level);
+        Launch<T>::point_reduce(s, c, true);
+        Launch<T>::pair_reduce_H(s, c);
+        launch_mu(s, c, c.d_geo0);
+        launch_gram(s, c, c.d_geo0, c.d_rec, is_fp64(c));
+        launch_assemble_s(s, c, c.d_geo0);
+        launch_ic_factor(s, c);
+    }
+    HIPCHK(hipGetLastError());
+    c.cur_level = level;
+    c.iters_in_level = 0;
+    return PBA_OK;
+}
+
+template <typename T>
+pba_status one_iteration(Ctx &c, int level, double *stat, hipEvent_t ev0, hipEvent_t ev1) {
+    hipStream_t s = c.stream;
+    double *geo_cur = c.flip ? c.d_geo_b : c.d_geo_a;
+    double *geo_next = c.flip ? c.d_geo_a : c.d_geo_b;
+    T *rel_cur = (T *)(c.flip ? c.d_rel_b : c.d_rel_a);
+    T *rel_next = (T *)(c.flip ? c.d_rel_a : c.d_rel_b);
+    if (c.cfg.mode == PBA_IC_PROXY) {
+        if (ev0) HIPCHK(hipEventRecord(ev0, s));
+        Launch<T>::ic_residual(s, c, level, rel_cur);
+        if (ev1) HIPCHK(hipEventRecord(ev1, s));
+        Launch<T>::point_reduce(s, c, false);
+        Launch<T>::pair_reduce_y(s, c);
+        launch_solve(s, c, c.d_geo0, geo_next, rel_next, is_fp64(c), stat);
+    } else {
+        if (ev0) HIPCHK(hipEventRecord(ev0, s));
+        Launch<T>::fc_linearize(s, c, level, rel_cur, c.iters_in_level == 0);
+        if (ev1) HIPCHK(hipEventRecord(ev1, s));
+        Launch<T>::point_reduce(s, c, true);
+        Launch<T>::pair_reduce_H(s, c);
+        launch_mu(s, c, geo_cur);
+        launch_gram(s, c, geo_cur, c.d_rec, is_fp64(c));
+        launch_assemble_s(s, c, geo_cur);
+        Launch<T>::pair_reduce_y(s, c);
+        launch_solve(s, c, geo_cur, geo_next, rel_next, is_fp64(c), stat);
+    }
+    Launch<T>::depth_update(s, c, geo_cur, geo_next, stat);
+    HIPCHK(hipGetLastError());
+    c.flip = !c.flip;
+    c.iters_in_level++;
+    return PBA_OK;
+}
+
+pba_status ensure_stats(Ctx &c, int n) {
+    if (n <= c.stats_cap) return PBA_OK;
+    int cap = std::max(n, 64);
+    HIPCHK(dalloc(c.d_stats, (size_t)cap * ST_STRIDE * sizeof(double)));
+    c.stats_cap = cap;
+    return PBA_OK;
+}
+
+pba_status ensure_events(Ctx &c, size_t n) {
+    while (c.ev_pool.size() < n) {
+        hipEvent_t e;
+        HIPCHK(hipEventCreate(&e));
+        c.ev_pool.push_back(e);
+    }
+    return PBA_OK;
+}
+
+pba_status run_iterations(Ctx &c, int level, int n_iters, pba_iter_stats *out) {
+    pba_status st;
+    if ((st = ensure_stats(c, n_iters)) != PBA_OK) return st;
+    const bool timing = (c.cfg.flags & PBA_FLAG_TIMING) != 0;
+    if (timing && (st = ensure_events(c, 2 * (size_t)n_iters)) != PBA_OK) return st;
+    HIPCHK(hipMemsetAsync(c.d_flag, 0, sizeof(int), c.stream));
+    for (int k = 0; k < n_iters; ++k) {
+        hipEvent_t e0 = timing ? c.ev_pool[2 * k] : nullptr, e1 = timing ? c.ev_pool[2 * k + 1] : nullptr;
+        double *stat = c.d_stats + (size_t)k * ST_STRIDE;
+        st = is_fp64(c) ? one_iteration<double>(c, level, stat, e0, e1) : one_iteration<float>(c, level, stat, e0, e1);
+        if (st != PBA_OK) return st;
+    }
+    std::vector<double> hs((size_t)n_iters * ST_STRIDE);
+    int flag = 0;
+    if (n_iters > 0)
+        HIPCHK(hipMemcpyAsync(hs.data(), c.d_stats, hs.size() * sizeof(double), hipMemcpyDeviceToHost, c.stream));
+    HIPCHK(hipMemcpyAsync(&flag, c.d_flag, sizeof(int), hipMemcpyDeviceToHost, c.stream));
+    HIPCHK(hipStreamSynchronize(c.stream));
+    if (timing) {
+        for (int k = 0; k < n_iters; ++k) {
+            float ms = 0.f;
+            HIPCHK(hipEventElapsedTime(&ms, c.ev_pool[2 * k], c.ev_pool[2 * k + 1]));
+            c.t_ms += ms;
+            c.t_launches++;
+            c.t_res += (int64_t)c.O * LANES_PER_OBS;
+        }
+    }
+    if (out) {
+        for (int k = 0; k < n_iters; ++k) {
+            const double *h = hs.data() + (size_t)k * ST_STRIDE;
+            pba_iter_stats &o = out[k];
+            o.level = level;
+            o.iter = c.iters_in_level - n_iters + k;
+            o.n_active = (int64_t)std::llround(h[ST_CNT]);
+            o.energy = h[ST_E];
+            o.sq = h[ST_SQ];
+            o.rmse = o.n_active > 0 ? std::sqrt(h[ST_SQ] / (double)o.n_active) : 0.0;
+            o.max_disp_px = h[ST_DISP];
+            o.max_step_pose = h[ST_STEP_P];
+            o.max_step_depth = h[ST_STEP_D];
+        }
+    }
+    if (flag) return fail(&c, PBA_E_NUMERIC, "reduced pose system is not positive definite");
+    return PBA_OK;
+}
+
+pba_status do_start_level(Ctx &c, int level) {
+    HIPCHK(hipMemsetAsync(c.d_flag, 0, sizeof(int), c.stream));
+    pba_status st = is_fp64(c) ? start_level<double>(c, level) : start_level<float>(c, level);
+    if (st != PBA_OK) return st;
+    if (c.cfg.mode == PBA_IC_PROXY) {
+        int flag = 0;
+        HIPCHK(hipMemcpyAsync(&flag, c.d_flag, sizeof(int), hipMemcpyDeviceToHost, c.stream));
+        HIPCHK(hipStreamSynchronize(c.stream));
+        if (flag) {
+            c.cur_level = -1;
+            return fail(&c, PBA_E_NUMERIC, "reduced pose system at p(0) is not positive definite");
+        }
+    }
+    return PBA_OK;
+}
+
+}  // namespace
+
+// ================================================================ C ABI
+
+extern "C" {
+
+const char *pba_status_string(pba_status s) {
+    switch (s) {
+        case PBA_OK: return "PBA_OK";
+        case PBA_E_INVALID: return "PBA_E_INVALID";
+        case PBA_E_STATE: return "PBA_E_STATE";
+        case PBA_E_OOM: return "PBA_E_OOM";
+        case PBA_E_DEVICE: return "PBA_E_DEVICE";
+        case PBA_E_NUMERIC: return "PBA_E_NUMERIC";
+        case PBA_E_NOT_CONVERGED: return "PBA_E_NOT_CONVERGED";
+    }
+    return "unknown status";
+}
+
+const char *pba_last_error(const pba_ctx *ctx) { return ctx ? ctx->c.err.c_str() : g_create_err.c_str(); }
+
+pba_status pba_config_default(pba_config *cfg) {
+    if (!cfg) return fail(nullptr, PBA_E_INVALID, "cfg is NULL");
+    std::memset(cfg, 0, sizeof(*cfg));
+    cfg->mode = PBA_IC_PROXY;
+    cfg->precision = PBA_FP32;
+    cfg->n_levels = 1;
+    cfg->pattern_n = 8;
+    const int pat[16] = {0, 0, 0, -2, -1, -1, 1, -1, -2, 0, 2, 0, -1, 1, 1, 1};
+    std::memcpy(cfg->pattern_uv, pat, sizeof(pat));
+    cfg->huber_k = 9.0 / 255.0;
+    cfg->damping_rel = 1e-6;
+    cfg->pinned_frame = 0;
+    cfg->solver = PBA_SOLVER_CHOL;
+    cfg->n_windows = 1;
+    cfg->flags = 0;
+    cfg->stream = nullptr;
+    return PBA_OK;
+}
+
+pba_status pba_create(const pba_config *cfg, pba_ctx **out) {
+    if (!out) return fail(nullptr, PBA_E_INVALID, "out is NULL");
+    *out = nullptr;
+    const std::string v = validate_config(cfg);
+    if (!v.empty()) return fail(nullptr, PBA_E_INVALID, v);
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev == 0) return fail(nullptr, PBA_E_DEVICE, "no HIP device");
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return fail(nullptr, PBA_E_DEVICE, "hipGetDevice failed");
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return fail(nullptr, PBA_E_DEVICE, "hipGetDeviceProperties failed");
+    if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+        return fail(nullptr, PBA_E_DEVICE, std::string("device is ") + prop.gcnArchName + ", libpba needs gfx950");
+    pba_ctx *ctx = new pba_ctx();
+    Ctx &c = ctx->c;
+    c.cfg = *cfg;
+    c.device = dev;
+    c.P = cfg->pattern_n;
+    c.real_size = cfg->precision == PBA_FP64 ? sizeof(double) : sizeof(float);
+    if (cfg->stream) {
+        c.stream = (hipStream_t)cfg->stream;
+        c.own_stream = false;
+    } else {
+        if (hipStreamCreateWithFlags(&c.stream, hipStreamNonBlocking) != hipSuccess) {
+            delete ctx;
+            return fail(nullptr, PBA_E_DEVICE, "hipStreamCreate failed");
+        }
+        c.own_stream = true;
+    }
+    *out = ctx;
+    return PBA_OK;
+}
+
+void pba_destroy(pba_ctx *ctx) {
+    if (!ctx) return;
+    Ctx &c = ctx->c;
+    if (c.stream) (void)hipStreamSynchronize(c.stream);
+    release_frames(c);
+    for (hipEvent_t e : c.ev_pool) (void)hipEventDestroy(e);
+    if (c.own_stream && c.stream) (void)hipStreamDestroy(c.stream);
+    delete ctx;
+}
+
+pba_status pba_set_frames(pba_ctx *ctx, int32_t window, int32_t n_frames, int32_t width, int32_t height,
+                          const float *images, const double *intrinsics, const double *poses, int32_t mem) {
+    if (!ctx) return fail(nullptr, PBA_E_INVALID, "ctx is NULL");
+    Ctx &c = ctx->c;
+    if (window != 0) return fail(&c, PBA_E_INVALID, "window must be 0");
+    if (mem != PBA_HOST && mem != PBA_DEVICE) return fail(&c, PBA_E_INVALID, "mem must be PBA_HOST or PBA_DEVICE");
+    if (n_frames < 1) return fail(&c, PBA_E_INVALID, "n_frames must be >= 1");
+    const int minsz = 8 << (c.cfg.n_levels - 1);
+    if (width < minsz || height < minsz)
+        return fail(&c, PBA_E_INVALID, "width and height must be >= " + std::to_string(minsz));
+    if ((long long)n_frames * width * height > (1LL << 34)) return fail(&c, PBA_E_INVALID, "images too large");
+    if (!images || !intrinsics || !poses) return fail(&c, PBA_E_INVALID, "NULL input array");
+    if (c.cfg.pinned_frame >= n_frames) return fail(&c, PBA_E_INVALID, "pinned_frame >= n_frames");
+    std::vector<double> K, Pz;
+    HIPCHK(fetch(K, intrinsics, (size_t)n_frames * 4, mem));
+    HIPCHK(fetch(Pz, poses, (size_t)n_frames * 12, mem));
+    if (!finite_all(K.data(), K.size())) return fail(&c, PBA_E_INVALID, "intrinsics not finite");
+    for (int f = 0; f < n_frames; ++f)
+        if (!(K[4 * f] > 0.0) || !(K[4 * f + 1] > 0.0)) return fail(&c, PBA_E_INVALID, "focal lengths must be > 0");
+    if (!finite_all(Pz.data(), Pz.size())) return fail(&c, PBA_E_INVALID, "poses not finite");
+    for (int f = 0; f < n_frames; ++f) {
+        const double *R = Pz.data() + 12 * f;
+        for (int i = 0; i < 3; ++i)
+            for (int j = 0; j < 3; ++j) {
+                double s = 0.0;
+                for (int k = 0; k < 3; ++k) s += R[3 * i + k] * R[3 * j + k];
+                if (std::fabs(s - (i == j ? 1.0 : 0.0)) > 1e-6)
+                    return fail(&c, PBA_E_INVALID, "pose " + std::to_string(f) + " rotation is not orthonormal");
+            }
+    }
+    const size_t npx = (size_t)n_frames * width * height;
+    if (mem == PBA_HOST) {
+        for (size_t i = 0; i < npx; ++i)
+            if (!std::isfinite(images[i])) return fail(&c, PBA_E_INVALID, "images contain non-finite values");
+    }
+    // (re)allocate
+    HIPCHK(hipStreamSynchronize(c.stream));
+    release_frames(c);
+    c.F = n_frames;
+    c.W = width;
+    c.H = height;
+    c.K0 = K;
+    const size_t rs = c.real_size;
+    int W = width, H = height;
+    for (int l = 0; l < c.cfg.n_levels; ++l) {
+        c.lv[l].W = W;
+        c.lv[l].H = H;
+        HIPCHK(dalloc(c.lv[l].img, (size_t)n_frames * W * H * rs));
+        HIPCHK(dalloc(c.lv[l].K, (size_t)n_frames * 4 * rs));
+        W /= 2;
+        H /= 2;
+    }
+    float *staging = nullptr;
+    HIPCHK(dalloc(staging, npx * sizeof(float)));
+    HIPCHK(hipMemcpyAsync(staging, images, npx * sizeof(float),
+                          mem == PBA_HOST ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice, c.stream));
+    HIPCHK(dalloc(c.d_K0, K.size() * sizeof(double)));
+    HIPCHK(hipMemcpyAsync(c.d_K0, K.data(), K.size() * sizeof(double), hipMemcpyHostToDevice, c.stream));
+    if (is_fp64(c)) {
+        Launch<double>::convert_images(c.stream, staging, (double *)c.lv[0].img, npx);
+        for (int l = 1; l < c.cfg.n_levels; ++l)
+            Launch<double>::downsample(c.stream, (double *)c.lv[l - 1].img, (double *)c.lv[l].img, n_frames,
+                                       c.lv[l - 1].W, c.lv[l - 1].H, c.lv[l].W, c.lv[l].H);
+        for (int l = 0; l < c.cfg.n_levels; ++l) Launch<double>::level_K(c.stream, c.d_K0, (double *)c.lv[l].K, n_frames, l);
+    } else {
+        Launch<float>::convert_images(c.stream, staging, (float *)c.lv[0].img, npx);
+        for (int l = 1; l < c.cfg.n_levels; ++l)
+            Launch<float>::downsample(c.stream, (float *)c.lv[l - 1].img, (float *)c.lv[l].img, n_frames,
+                                      c.lv[l - 1].W, c.lv[l - 1].H, c.lv[l].W, c.lv[l].H);
+        for (int l = 0; l < c.cfg.n_levels; ++l) Launch<float>::level_K(c.stream, c.d_K0, (float *)c.lv[l].K, n_frames, l);
+    }
+    const size_t n6 = 6 * (size_t)n_frames;
+    HIPCHK(dalloc(c.d_poses, Pz.size() * sizeof(double)));
+    HIPCHK(dalloc(c.d_poses0, Pz.size() * sizeof(double)));
+    HIPCHK(hipMemcpyAsync(c.d_poses, Pz.data(), Pz.size() * sizeof(double), hipMemcpyHostToDevice, c.stream));
+    HIPCHK(dalloc(c.d_S, n6 * n6 * sizeof(double)));
+    if (c.cfg.mode == PBA_IC_PROXY) HIPCHK(dalloc(c.d_Sinv, n6 * n6 * sizeof(double)));
+    HIPCHK(dalloc(c.d_b, 2 * n6 * sizeof(double)));
+    HIPCHK(dalloc(c.d_dtheta, n6 * sizeof(double)));
+    HIPCHK(dalloc(c.d_mu, 2 * sizeof(double)));
+    HIPCHK(dalloc(c.d_flag, sizeof(int)));
+    HIPCHK(hipMemsetAsync(c.d_flag, 0, sizeof(int), c.stream));
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(c.stream));
+    dfree(staging);
+    c.have_frames = true;
+    c.cur_level = -1;
+    return PBA_OK;
+}
+
+pba_status pba_set_points(pba_ctx *ctx, int32_t window, int32_t n_points, const int32_t *host_frame,
+                          const float *host_uv, const double *inv_depth, const int32_t *obs_ptr,
+                          const int32_t *obs_frame, int32_t mem) {
+    if (!ctx) return fail(nullptr, PBA_E_INVALID, "ctx is NULL");
+    Ctx &c = ctx->c;
+    if (!c.have_frames) return fail(&c, PBA_E_STATE, "pba_set_frames must be called first");
+    if (window != 0) return fail(&c, PBA_E_INVALID, "window must be 0");
+    if (mem != PBA_HOST && mem != PBA_DEVICE) return fail(&c, PBA_E_INVALID, "mem must be PBA_HOST or PBA_DEVICE");
+    if (n_points < 0) return fail(&c, PBA_E_INVALID, "n_points must be >= 0");
+    if (n_points > 0 && (!host_frame || !host_uv || !inv_depth || !obs_ptr))
+        return fail(&c, PBA_E_INVALID, "NULL input array");
+    if (!obs_ptr) return fail(&c, PBA_E_INVALID, "obs_ptr is NULL");
+    std::vector<int> hf, optr, ofr;
+    std::vector<float> uv;
+    std::vector<double> d;
+    HIPCHK(fetch(optr, obs_ptr, (size_t)n_points + 1, mem));
+    if (optr[0] != 0) return fail(&c, PBA_E_INVALID, "obs_ptr[0] must be 0");
+    for (int n = 0; n < n_points; ++n)
+        if (optr[n + 1] < optr[n]) return fail(&c, PBA_E_INVALID, "obs_ptr must be non-decreasing");
+    const long long O = optr[n_points];
+    if (O > (1LL << 28)) return fail(&c, PBA_E_INVALID, "too many observations");
+    if (O > 0 && !obs_frame) return fail(&c, PBA_E_INVALID, "obs_frame is NULL");
+    HIPCHK(fetch(hf, host_frame, (size_t)n_points, mem));
+    HIPCHK(fetch(uv, host_uv, 2 * (size_t)n_points, mem));
+    HIPCHK(fetch(d, inv_depth, (size_t)n_points, mem));
+    HIPCHK(fetch(ofr, obs_frame, (size_t)O, mem));
+    for (int n = 0; n < n_points; ++n) {
+        if (hf[n] < 0 || hf[n] >= c.F) return fail(&c, PBA_E_INVALID, "host_frame out of range at point " + std::to_string(n));
+        if (!std::isfinite(d[n]) || !(d[n] > 0.0))
+            return fail(&c, PBA_E_INVALID, "inv_depth must be finite and > 0 at point " + std::to_string(n));
+        if (!std::isfinite(uv[2 * n]) || !std::isfinite(uv[2 * n + 1]) || uv[2 * n] < 0 || uv[2 * n] > c.W - 1 ||
+            uv[2 * n + 1] < 0 || uv[2 * n + 1] > c.H - 1)
+            return fail(&c, PBA_E_INVALID, "host_uv outside the image at point " + std::to_string(n));
+        for (int o = optr[n]; o < optr[n + 1]; ++o) {
+            if (ofr[o] < 0 || ofr[o] >= c.F) return fail(&c, PBA_E_INVALID, "obs_frame out of range");
+            if (ofr[o] == hf[n]) return fail(&c, PBA_E_INVALID, "a point cannot observe its own host frame");
+            if (o > optr[n] && ofr[o] <= ofr[o - 1])
+                return fail(&c, PBA_E_INVALID, "obs_frame must be strictly increasing within a point");
+        }
+    }
+    HIPCHK(hipStreamSynchronize(c.stream));
+    release_points(c);
+    c.N = n_points;
+    c.O = (int)O;
+    const std::string e = build_structure(c, hf, optr, ofr);
+    if (!e.empty()) {
+        c.N = c.O = 0;
+        return fail(&c, PBA_E_INVALID, e);
+    }
+    const Structure &s = c.st;
+    HIPCHK(upload(c, c.d_host_frame, hf));
+    HIPCHK(upload(c, c.d_obs_ptr, optr));
+    HIPCHK(upload(c, c.d_obs_frame, ofr));
+    HIPCHK(upload(c, c.d_host_uv, uv));
+    HIPCHK(upload(c, c.d_obs_point, s.obs_point));
+    HIPCHK(upload(c, c.d_obs_pair, s.obs_pair));
+    HIPCHK(upload(c, c.d_pair_host, s.pair_host));
+    HIPCHK(upload(c, c.d_pair_target, s.pair_target));
+    HIPCHK(upload(c, c.d_pair_obs_ptr, s.pair_obs_ptr));
+    HIPCHK(upload(c, c.d_pair_obs_idx, s.pair_obs_idx));
+    HIPCHK(upload(c, c.d_frame_pair_ptr, s.frame_pair_ptr));
+    HIPCHK(upload(c, c.d_frame_pair_item, s.frame_pair_item));
+    HIPCHK(upload(c, c.d_pair_local, s.pair_local));
+    HIPCHK(upload(c, c.d_pair_hidx, s.pair_hidx));
+    HIPCHK(upload(c, c.d_host_m, s.host_m));
+    HIPCHK(upload(c, c.d_host_frames, s.hosts));
+    HIPCHK(upload(c, c.d_host_pts, s.host_pts));
+    HIPCHK(upload(c, c.d_chunk_host, s.chunk_host));
+    HIPCHK(upload(c, c.d_chunk_begin, s.chunk_begin));
+    HIPCHK(upload(c, c.d_chunk_end, s.chunk_end));
+    HIPCHK(upload(c, c.d_chunk_off, s.chunk_off));
+    HIPCHK(upload(c, c.d_host_chunk_ptr, s.host_chunk_ptr));
+    HIPCHK(upload(c, c.d_blk_fa, s.blk_fa));
+    HIPCHK(upload(c, c.d_blk_fb, s.blk_fb));
+    HIPCHK(upload(c, c.d_blk_pp_ptr, s.blk_pp_ptr));
+    HIPCHK(upload(c, c.d_blk_pp_item, s.blk_pp_item));
+    HIPCHK(upload(c, c.d_blk_g_ptr, s.blk_g_ptr));
+    HIPCHK(upload(c, c.d_blk_g_item, s.blk_g_item));
+    HIPCHK(upload(c, c.d_depth, d));
+    HIPCHK(dalloc(c.d_depth0, std::max<size_t>(1, n_points) * sizeof(double)));
+    const size_t rs = c.real_size;
+    const int Pn = s.n_pairs;
+    HIPCHK(dalloc(c.d_mask, std::max<size_t>(1, O)));
+    HIPCHK(dalloc(c.d_rec, (size_t)O * REC_STRIDE * rs));
+    HIPCHK(dalloc(c.d_geo0, (size_t)Pn * GEO_STRIDE * sizeof(double)));
+    HIPCHK(dalloc(c.d_geo_a, (size_t)Pn * GEO_STRIDE * sizeof(double)));
+    HIPCHK(dalloc(c.d_geo_b, (size_t)Pn * GEO_STRIDE * sizeof(double)));
+    HIPCHK(dalloc(c.d_rel0, (size_t)Pn * REL_STRIDE * rs));
+    HIPCHK(dalloc(c.d_rel_a, (size_t)Pn * REL_STRIDE * rs));
+    HIPCHK(dalloc(c.d_rel_b, (size_t)Pn * REL_STRIDE * rs));
+    HIPCHK(dalloc(c.d_pairH, (size_t)Pn * 21 * sizeof(double)));
+    HIPCHK(dalloc(c.d_pairY, (size_t)Pn * 9 * sizeof(double)));
+    HIPCHK(dalloc(c.d_Hdd, (size_t)n_points * sizeof(double)));
+    HIPCHK(dalloc(c.d_gd, (size_t)n_points * sizeof(double)));
+    c.hdd_blocks = (n_points + 255) / 256;
+    HIPCHK(dalloc(c.d_hdd_part, (size_t)std::max(1, c.hdd_blocks) * sizeof(double)));
+    HIPCHK(dalloc(c.d_gram, s.gram_floats * sizeof(double)));
+    HIPCHK(dalloc(c.d_dth_rel, (size_t)Pn * 6 * sizeof(double)));
+    for (int l = 0; l < c.cfg.n_levels; ++l) {
+        HIPCHK(dalloc(c.lv[l].tmpl, (size_t)n_points * c.P * 4 * rs));
+        c.lv[l].tmpl_valid = false;
+    }
+    if (c.hdd_blocks == 0) launch_fill(c.stream, c.d_hdd_part, 1, 0.0);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(c.stream));
+    c.have_points = true;
+    c.cur_level = -1;
+    return PBA_OK;
+}
+
+pba_status pba_iterate(pba_ctx *ctx, int32_t level, int32_t n_iters, pba_iter_stats *stats) {
+    if (!ctx) return fail(nullptr, PBA_E_INVALID, "ctx is NULL");
+    Ctx &c = ctx->c;
+    if (!c.have_points) return fail(&c, PBA_E_STATE, "pba_set_frames and pba_set_points must be called first");
+    if (level < 0 || level >= c.cfg.n_levels) return fail(&c, PBA_E_INVALID, "level out of range");
+    if (n_iters < 0) return fail(&c, PBA_E_INVALID, "n_iters must be >= 0");
+    pba_status st;
+    if (c.cur_level != level && (st = do_start_level(c, level)) != PBA_OK) return st;
+    return run_iterations(c, level, n_iters, stats);
+}
+
+pba_status pba_evaluate(pba_ctx *ctx, int32_t level, pba_iter_stats *out) {
+    if (!ctx) return fail(nullptr, PBA_E_INVALID, "ctx is NULL");
+    Ctx &c = ctx->c;
+    if (!c.have_points) return fail(&c, PBA_E_STATE, "pba_set_frames and pba_set_points must be called first");
+    if (level < 0 || level >= c.cfg.n_levels) return fail(&c, PBA_E_INVALID, "level out of range");
+    if (!out) return fail(&c, PBA_E_INVALID, "out is NULL");
+    hipStream_t s = c.stream;
+    // relative poses at the current parameters go to the buffer the next iteration reads
+    double *geo = c.flip ? c.d_geo_b : c.d_geo_a;
+    double *tot = nullptr;
+    HIPCHK(dalloc(tot, 3 * sizeof(double)));
+    if (is_fp64(c)) {
+        if (!c.lv[level].tmpl_valid) Launch<double>::make_template(s, c, level);
+        Launch<double>::relpose(s, c, c.d_poses, geo, (double *)(c.flip ? c.d_rel_b : c.d_rel_a));
+        Launch<double>::evaluate(s, c, level);
+    } else {
+        if (!c.lv[level].tmpl_valid) Launch<float>::make_template(s, c, level);
+        Launch<float>::relpose(s, c, c.d_poses, geo, (float *)(c.flip ? c.d_rel_b : c.d_rel_a));
+        Launch<float>::evaluate(s, c, level);
+    }
+    c.lv[level].tmpl_valid = true;
+    if (c.O > 0)
+        launch_sum_stats(s, c, c.d_rec, is_fp64(c), tot);
+    else
+        launch_fill(s, tot, 3, 0.0);
+    double h[3];
+    HIPCHK(hipMemcpyAsync(h, tot, sizeof(h), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    dfree(tot);
+    std::memset(out, 0, sizeof(*out));
+    out->level = level;
+    out->n_active = (int64_t)std::llround(h[2]);
+    out->energy = h[0];
+    out->sq = h[1];
+    out->rmse = out->n_active > 0 ? std::sqrt(h[1] / (double)out->n_active) : 0.0;
+    return PBA_OK;
+}
+
+pba_status pba_solve(pba_ctx *ctx, int32_t max_iters_per_level, double conv_px, pba_result *out) {
+    if (!ctx) return fail(nullptr, PBA_E_INVALID, "ctx is NULL");
+    Ctx &c = ctx->c;
+    if (!c.have_points) return fail(&c, PBA_E_STATE, "pba_set_frames and pba_set_points must be called first");
+    if (max_iters_per_level < 1) return fail(&c, PBA_E_INVALID, "max_iters_per_level must be >= 1");
+    if (!(conv_px >= 0.0)) return fail(&c, PBA_E_INVALID, "conv_px must be >= 0");
+    pba_result res;
+    std::memset(&res, 0, sizeof(res));
+    pba_status st;
+    for (int level = c.cfg.n_levels - 1; level >= 0; --level) {
+        if ((st = do_start_level(c, level)) != PBA_OK) return st;
+        int k = 0;
+        bool conv = false;
+        while (k < max_iters_per_level) {
+            pba_iter_stats it;
+            if ((st = run_iterations(c, level, 1, &it)) != PBA_OK) return st;
+            ++k;
+            if (it.max_disp_px < conv_px) {
+                conv = true;
+                break;
+            }
+        }
+        res.iters[level] = k;
+        res.total_iters += k;
+        if (level == 0) res.converged = conv ? 1 : 0;
+    }
+    pba_iter_stats ev;
+    if ((st = pba_evaluate(ctx, 0, &ev)) != PBA_OK) return st;
+    res.final_energy = ev.energy;
+    res.final_rmse = ev.rmse;
+    res.final_active = ev.n_active;
+    if (out) *out = res;
+    if (!res.converged) return fail(&c, PBA_E_NOT_CONVERGED, "level 0 did not reach conv_px");
+    return PBA_OK;
+}
+
+pba_status pba_get_params(pba_ctx *ctx, int32_t window, double *poses, double *inv_depth) {
+    if (!ctx) return fail(nullptr, PBA_E_INVALID, "ctx is NULL");
+    Ctx &c = ctx->c;
+    if (window != 0) return fail(&c, PBA_E_INVALID, "window must be 0");
+    if (!c.have_frames) return fail(&c, PBA_E_STATE, "no frames set");
+    if (poses)
+        HIPCHK(hipMemcpyAsync(poses, c.d_poses, (size_t)c.F * 12 * sizeof(double), hipMemcpyDeviceToHost, c.stream));
+    if (inv_depth && c.have_points && c.N > 0)
+        HIPCHK(hipMemcpyAsync(inv_depth, c.d_depth, (size_t)c.N * sizeof(double), hipMemcpyDeviceToHost, c.stream));
+    HIPCHK(hipStreamSynchronize(c.stream));
+    return PBA_OK;
+}
+
+pba_status pba_set_params(pba_ctx *ctx, int32_t window, const double *poses, const double *inv_depth) {
+    if (!ctx) return fail(nullptr, PBA_E_INVALID, "ctx is NULL");
+    Ctx &c = ctx->c;
+    if (window != 0) return fail(&c, PBA_E_INVALID, "window must be 0");
+    if (!c.have_points) return fail(&c, PBA_E_STATE, "pba_set_frames and pba_set_points must be called first");
+    if (poses && !finite_all(poses, (size_t)c.F * 12)) return fail(&c, PBA_E_INVALID, "poses not finite");
+    if (inv_depth) {
+        for (int n = 0; n < c.N; ++n)
+            if (!std::isfinite(inv_depth[n]) || !(inv_depth[n] > 0.0))
+                return fail(&c, PBA_E_INVALID, "inv_depth must be finite and > 0");
+    }
+    if (poses)
+        HIPCHK(hipMemcpyAsync(c.d_poses, poses, (size_t)c.F * 12 * sizeof(double), hipMemcpyHostToDevice, c.stream));
+    if (inv_depth && c.N > 0)
+        HIPCHK(hipMemcpyAsync(c.d_depth, inv_depth, (size_t)c.N * sizeof(double), hipMemcpyHostToDevice, c.stream));
+    HIPCHK(hipStreamSynchronize(c.stream));
+    c.cur_level = -1;
+    return PBA_OK;
+}
+
+pba_status pba_debug_fetch(pba_ctx *ctx, int32_t what, void *out, size_t bytes) {
+    if (!ctx) return fail(nullptr, PBA_E_INVALID, "ctx is NULL");
+    Ctx &c = ctx->c;
+    if (!out) return fail(&c, PBA_E_INVALID, "out is NULL");
+    if (!c.have_points) return fail(&c, PBA_E_STATE, "no problem set");
+    const size_t n6 = 6 * (size_t)c.F;
+    const void *src = nullptr;
+    size_t need = 0;
+    switch (what) {
+        case PBA_DBG_S: src = c.d_S; need = n6 * n6 * sizeof(double); break;
+        case PBA_DBG_B: src = c.d_b; need = n6 * sizeof(double); break;
+        case PBA_DBG_OBS_REC: src = c.d_rec; need = (size_t)c.O * REC_STRIDE * c.real_size; break;
+        case PBA_DBG_TEMPLATE: {
+            const int l = c.cur_level < 0 ? 0 : c.cur_level;
+            src = c.lv[l].tmpl;
+            need = (size_t)c.N * c.P * 4 * c.real_size;
+            break;
+        }
+        case PBA_DBG_HDD: src = c.d_Hdd; need = (size_t)c.N * sizeof(double); break;
+        case PBA_DBG_MASK: src = c.d_mask; need = (size_t)c.O; break;
+        case PBA_DBG_DTHETA: src = c.d_dtheta; need = n6 * sizeof(double); break;
+        default: return fail(&c, PBA_E_INVALID, "unknown debug buffer");
+    }
+    if (bytes != need) return fail(&c, PBA_E_INVALID, "bytes must be " + std::to_string(need));
+    if (need) HIPCHK(hipMemcpyAsync(out, src, need, hipMemcpyDeviceToHost, c.stream));
+    HIPCHK(hipStreamSynchronize(c.stream));
+    return PBA_OK;
+}
+
+pba_status pba_get_timing(pba_ctx *ctx, pba_timing *out) {
+    if (!ctx) return fail(nullptr, PBA_E_INVALID, "ctx is NULL");
+    Ctx &c = ctx->c;
+    if (!out) return fail(&c, PBA_E_INVALID, "out is NULL");
+    out->residual_launches = c.t_launches;
+    out->residual_ms = c.t_ms;
+    out->residuals_processed = c.t_res;
+    c.t_launches = 0;
+    c.t_ms = 0.0;
+    c.t_res = 0;
+    return PBA_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,251 @@
+// Device-side math of libpba: bilinear image functions, warps, the proxy-template
+// and forward-compositional Jacobian rows, and small 6x6 helpers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace pba {
+
+struct PatternArg {
+    int n;
+    int du[8];
+    int dv[8];
+};
+
+template <typename T>
+__device__ __forceinline__ bool usable(T u, T v, int W, int H) {
+    return u >= T(1) && u <= T(W - 3) && v >= T(1) && v <= T(H - 3);
+}
+
+// Bilinear interpolation of a row-major image at (u, v) (Notation: image
+// functions are bilinear interpolants of the pixel grid).
+template <typename T>
+__device__ __forceinline__ T bilinear(const T *__restrict__ im, int W, T u, T v) {
+    const int j0 = (int)floor(u), i0 = (int)floor(v);
+    const T a = u - T(j0), b = v - T(i0);
+    const T *r0 = im + (size_t)i0 * W + j0;
+    const T *r1 = r0 + W;
+    return (T(1) - a) * (T(1) - b) * r0[0] + a * (T(1) - b) * r0[1] + (T(1) - a) * b * r1[0] + a * b * r1[1];
+}
+
+// Intensity and gradient at (u, v): the gradient is the central difference on
+// the grid, bilinearly interpolated between the four surrounding pixel centres.
+template <typename T>
+__device__ __forceinline__ void bilinear_grad(const T *__restrict__ im, int W, T u, T v, T &I, T &gu, T &gv) {
+    const int j0 = (int)floor(u), i0 = (int)floor(v);
+    const T a = u - T(j0), b = v - T(i0);
+    const T *rm = im + (size_t)(i0 - 1) * W + j0;  // row i0-1
+    const T *r0 = rm + W;
+    const T *r1 = r0 + W;
+    const T *r2 = r1 + W;
+    const T i00 = r0[0], i01 = r0[1], i10 = r1[0], i11 = r1[1];
+    const T gu00 = T(0.5) * (r0[1] - r0[-1]), gu01 = T(0.5) * (r0[2] - r0[0]);
+    const T gu10 = T(0.5) * (r1[1] - r1[-1]), gu11 = T(0.5) * (r1[2] - r1[0]);
+    const T gv00 = T(0.5) * (r1[0] - rm[0]), gv01 = T(0.5) * (r1[1] - rm[1]);
+    const T gv10 = T(0.5) * (r2[0] - r0[0]), gv11 = T(0.5) * (r2[1] - r0[1]);
+    const T w00 = (T(1) - a) * (T(1) - b), w01 = a * (T(1) - b), w10 = (T(1) - a) * b, w11 = a * b;
+    I = w00 * i00 + w01 * i01 + w10 * i10 + w11 * i11;
+    gu = w00 * gu00 + w01 * gu01 + w10 * gu10 + w11 * gu11;
+    gv = w00 * gv00 + w01 * gv01 + w10 * gv10 + w11 * gv11;
+}
+
+// Huber IRLS weight and norm (eq:energy).
+template <typename T>
+__device__ __forceinline__ void huber(T r, T k, T &w, T &rho) {
+    const T a = fabs(r);
+    if (a <= k) {
+        w = T(1);
+        rho = T(0.5) * r * r;
+    } else {
+        w = k / a;
+        rho = k * a - T(0.5) * k * k;
+    }
+}
+
+// Inverse-compositional Jacobian row with proxy templates (Sec. 3.4, 3.5):
+// J = [fx gu, fy gv] d phi / d dp at dp = 0, with
+//   d phi / d dp = (1/zb) [[1, 0, -x], [0, 1, -y]] [-M [R0 x~]_x | d0 M | M t0],
+//   M = R0^T (zb I - t0 e3^T),  zb = [R0 x~ + d0 t0]_z / d0.
+// With q = (1/zb)(a0, a1, -a0 x - a1 y) and m = M^T q = zb R0 q - (t0 . R0 q) e3
+// the row is J_w = (R0 x~) x m, J_t = d0 m, J_d = m . t0.
+template <typename T>
+__device__ __forceinline__ void ic_jacobian(T x, T y, const T *R0, const T *t0, T d0, T gu, T gv, T fx, T fy,
+                                            T J[7]) {
+    const T Rx0 = R0[0] * x + R0[1] * y + R0[2];
+    const T Rx1 = R0[3] * x + R0[4] * y + R0[5];
+    const T Rx2 = R0[6] * x + R0[7] * y + R0[8];
+    const T zb = (Rx2 + d0 * t0[2]) / d0;
+    const T iz = T(1) / zb;
+    const T a0 = fx * gu, a1 = fy * gv;
+    const T q0 = a0 * iz, q1 = a1 * iz, q2 = -(a0 * x + a1 * y) * iz;
+    const T Rq0 = R0[0] * q0 + R0[1] * q1 + R0[2] * q2;
+    const T Rq1 = R0[3] * q0 + R0[4] * q1 + R0[5] * q2;
+    const T Rq2 = R0[6] * q0 + R0[7] * q1 + R0[8] * q2;
+    const T m0 = zb * Rq0, m1 = zb * Rq1;
+    const T m2 = zb * Rq2 - (Rq0 * t0[0] + Rq1 * t0[1] + Rq2 * t0[2]);
+    J[0] = Rx1 * m2 - Rx2 * m1;
+    J[1] = Rx2 * m0 - Rx0 * m2;
+    J[2] = Rx0 * m1 - Rx1 * m0;
+    J[3] = d0 * m0;
+    J[4] = d0 * m1;
+    J[5] = d0 * m2;
+    J[6] = m0 * t0[0] + m1 * t0[1] + m2 * t0[2];
+}
+
+// Forward-compositional Jacobian row of r = I0 - I_f(W) at the current
+// parameters: J = -[fx gu, fy gv] (1/v_z)[[1,0,-u_x],[0,1,-u_y]] [-[R x~]_x | d I | t],
+// i.e. with q = -(1/v_z)(a0, a1, -a0 u_x - a1 u_y): J_w = (R x~) x q, J_t = d q, J_d = q . t.
+template <typename T>
+__device__ __forceinline__ void fc_jacobian(T Rx0, T Rx1, T Rx2, T vz, T ux, T uy, const T *t, T d, T gu, T gv,
+                                            T fx, T fy, T J[7]) {
+    const T a0 = fx * gu, a1 = fy * gv;
+    const T iz = -T(1) / vz;
+    const T q0 = a0 * iz, q1 = a1 * iz, q2 = -(a0 * ux + a1 * uy) * iz;
+    J[0] = Rx1 * q2 - Rx2 * q1;
+    J[1] = Rx2 * q0 - Rx0 * q2;
+    J[2] = Rx0 * q1 - Rx1 * q0;
+    J[3] = d * q0;
+    J[4] = d * q1;
+    J[5] = d * q2;
+    J[6] = q0 * t[0] + q1 * t[1] + q2 * t[2];
+}
+
+// Constant maps from absolute left increments of target f and host h to the
+// left increment of their relative pose R_fh = R_f R_h^T, t_fh = t_f - R_fh t_h:
+//   A = [[I, 0], [[R_fh t_h]_x, I]],  B = [[-R_fh, 0], [-R_fh [t_h]_x, -R_fh]].
+__device__ __forceinline__ void abs_maps(const double *geo, double A[36], double B[36]) {
+    const double *R = geo;
+    const double *th = geo + 12;
+    const double Rt0 = R[0] * th[0] + R[1] * th[1] + R[2] * th[2];
+    const double Rt1 = R[3] * th[0] + R[4] * th[1] + R[5] * th[2];
+    const double Rt2 = R[6] * th[0] + R[7] * th[1] + R[8] * th[2];
+    for (int i = 0; i < 36; ++i) {
+        A[i] = 0.0;
+        B[i] = 0.0;
+    }
+    for (int i = 0; i < 6; ++i) A[i * 6 + i] = 1.0;
+    // [R t_h]_x in the lower-left block of A
+    A[3 * 6 + 1] = -Rt2;
+    A[3 * 6 + 2] = Rt1;
+    A[4 * 6 + 0] = Rt2;
+    A[4 * 6 + 2] = -Rt0;
+    A[5 * 6 + 0] = -Rt1;
+    A[5 * 6 + 1] = Rt0;
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) {
+            B[i * 6 + j] = -R[i * 3 + j];
+            B[(i + 3) * 6 + (j + 3)] = -R[i * 3 + j];
+        }
+    // -R [t_h]_x
+    const double K[9] = {0.0, -th[2], th[1], th[2], 0.0, -th[0], -th[1], th[0], 0.0};
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) {
+            double s = 0.0;
+            for (int k = 0; k < 3; ++k) s += R[i * 3 + k] * K[k * 3 + j];
+            B[(i + 3) * 6 + j] = -s;
+        }
+}
+
+// The same maps applied to 6-vectors without forming them (geo = R_fh, t_fh, t_h):
+//   A x   = (x_w, (R t_h) x x_w + x_t)            A^T y = (y_w - (R t_h) x y_t, y_t)
+//   B x   = (-R x_w, -R (t_h x x_w + x_t))        B^T y = (-R^T y_w + t_h x (R^T y_t), -R^T y_t)
+__device__ __forceinline__ void cross3(const double *a, const double *b, double *c) {
+    c[0] = a[1] * b[2] - a[2] * b[1];
+    c[1] = a[2] * b[0] - a[0] * b[2];
+    c[2] = a[0] * b[1] - a[1] * b[0];
+}
+__device__ __forceinline__ void geo_Rth(const double *geo, double *Rt) {
+    const double *R = geo, *th = geo + 12;
+    for (int i = 0; i < 3; ++i) Rt[i] = R[3 * i] * th[0] + R[3 * i + 1] * th[1] + R[3 * i + 2] * th[2];
+}
+__device__ __forceinline__ void apply_A(const double *geo, const double *x, double *out) {
+    double Rt[3], c[3];
+    geo_Rth(geo, Rt);
+    cross3(Rt, x, c);
+    for (int i = 0; i < 3; ++i) {
+        out[i] = x[i];
+        out[3 + i] = c[i] + x[3 + i];
+    }
+}
+__device__ __forceinline__ void apply_At(const double *geo, const double *y, double *out) {
+    double Rt[3], c[3];
+    geo_Rth(geo, Rt);
+    cross3(Rt, y + 3, c);
+    for (int i = 0; i < 3; ++i) {
+        out[i] = y[i] - c[i];
+        out[3 + i] = y[3 + i];
+    }
+}
+__device__ __forceinline__ void apply_B(const double *geo, const double *x, double *out) {
+    const double *R = geo, *th = geo + 12;
+    double c[3];
+    cross3(th, x, c);
+    for (int i = 0; i < 3; ++i) c[i] += x[3 + i];
+    for (int i = 0; i < 3; ++i) {
+        out[i] = -(R[3 * i] * x[0] + R[3 * i + 1] * x[1] + R[3 * i + 2] * x[2]);
+        out[3 + i] = -(R[3 * i] * c[0] + R[3 * i + 1] * c[1] + R[3 * i + 2] * c[2]);
+    }
+}
+__device__ __forceinline__ void apply_Bt(const double *geo, const double *y, double *out) {
+    const double *R = geo, *th = geo + 12;
+    double a[3], b[3], c[3];
+    for (int i = 0; i < 3; ++i) {
+        a[i] = R[i] * y[0] + R[3 + i] * y[1] + R[6 + i] * y[2];          // R^T y_w
+        b[i] = R[i] * y[3] + R[3 + i] * y[4] + R[6 + i] * y[5];          // R^T y_t
+    }
+    cross3(th, b, c);
+    for (int i = 0; i < 3; ++i) {
+        out[i] = -a[i] + c[i];
+        out[3 + i] = -b[i];
+    }
+}
+
+// Rodrigues' formula exp([w]_x) (row-major 3x3).
+__device__ __forceinline__ void so3_exp(const double w[3], double R[9]) {
+    const double th2 = w[0] * w[0] + w[1] * w[1] + w[2] * w[2];
+    double a, b;
+    if (th2 < 1e-16) {
+        a = 1.0 - th2 / 6.0;
+        b = 0.5 - th2 / 24.0;
+    } else {
+        const double th = sqrt(th2);
+        a = sin(th) / th;
+        b = (1.0 - cos(th)) / th2;
+    }
+    const double K[9] = {0.0, -w[2], w[1], w[2], 0.0, -w[0], -w[1], w[0], 0.0};
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) {
+            double kk = 0.0;
+            for (int k = 0; k < 3; ++k) kk += K[i * 3 + k] * K[k * 3 + j];
+            R[i * 3 + j] = (i == j ? 1.0 : 0.0) + a * K[i * 3 + j] + b * kk;
+        }
+}
+
+__device__ __forceinline__ void mat3_mul(const double *A, const double *B, double *C) {
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) {
+            double s = 0.0;
+            for (int k = 0; k < 3; ++k) s += A[i * 3 + k] * B[k * 3 + j];
+            C[i * 3 + j] = s;
+        }
+}
+
+// C = A B^T
+__device__ __forceinline__ void mat3_mul_bt(const double *A, const double *B, double *C) {
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) {
+            double s = 0.0;
+            for (int k = 0; k < 3; ++k) s += A[i * 3 + k] * B[j * 3 + k];
+            C[i * 3 + j] = s;
+        }
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_sum8(T v) {
+    v += __shfl_xor(v, 1, 64);
+    v += __shfl_xor(v, 2, 64);
+    v += __shfl_xor(v, 4, 64);
+    return v;
+}
+
+}  // namespace pba

@@ -1,0 +1,161 @@
+// Internal declarations of libpba: context state, device buffer layout and the
+// kernel launch interface shared by the host runtime and the kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/pba.h"
+
+namespace pba {
+
+// Per-observation record (T = float or double), one per (point, observing
+// frame): blocks of the Gauss-Newton system in relative-pose coordinates.
+enum RecField : int {
+    REC_H = 0,        // 21: upper triangle (row-major) of sum w J_th^T J_th
+    REC_h = 21,       // 6: sum w J_th J_d
+    REC_HDD = 27,     // 1: sum w J_d^2
+    REC_G = 28,       // 6: sum w J_th r
+    REC_GD = 34,      // 1: sum w J_d r
+    REC_E = 35,       // 1: sum of Huber norms
+    REC_SQ = 36,      // 1: sum r^2
+    REC_CNT = 37,     // 1: number of contributing residuals
+    REC_STRIDE = 40
+};
+
+// Per-pair geometry in double: R_fh (9), t_fh (3), t_h (3), pad.
+constexpr int GEO_STRIDE = 16;
+// Per-pair relative pose for the residual kernels: R (9), t (3).
+constexpr int REL_STRIDE = 12;
+// Per-iteration statistics slot layout (double).
+enum StatField : int {
+    ST_E = 0, ST_SQ = 1, ST_CNT = 2, ST_DISP = 3, ST_STEP_P = 4, ST_STEP_D = 5, ST_STRIDE = 8
+};
+
+constexpr int WAVE = 64;
+constexpr int LANES_PER_OBS = 8;   // one lane per patch pixel
+constexpr int BLOCK = 256;         // threads per block for residual kernels
+constexpr int MAX_HOST_TARGETS = 20;  // target frames per host frame (Schur Gram size)
+
+struct LevelDev {
+    int W = 0, H = 0;
+    void *img = nullptr;      // T [F][H][W]
+    void *K = nullptr;        // T [F][4] level intrinsics
+    void *tmpl = nullptr;     // T [N][P][4] (I0, gu, gv, usable) at the host patch pixels
+    bool tmpl_valid = false;
+};
+
+// Static structure derived from the observation lists (built on the host at set_points).
+struct Structure {
+    int n_pairs = 0;
+    std::vector<int> obs_point, obs_pair;             // [O]
+    std::vector<int> pair_host, pair_target;          // [Pn]
+    std::vector<int> pair_obs_ptr, pair_obs_idx;      // CSR pair -> obs
+    std::vector<int> frame_pair_ptr, frame_pair_item; // CSR frame -> (pair*2 + is_host)
+    // hosts and their extended frame sets for the depth Schur Gram
+    std::vector<int> hosts;                           // distinct host frames
+    std::vector<int> host_m;                          // targets per host
+    std::vector<int> pair_local;                      // [Pn] index of the pair within its host
+    std::vector<int> pair_hidx;                       // [Pn] host index
+    std::vector<int> host_pts;                        // points grouped by host
+    std::vector<int> chunk_host, chunk_begin, chunk_end, chunk_off; // Gram chunks (into host_pts)
+    std::vector<int> host_chunk_ptr;                  // CSR host -> chunks
+    // nonzero 6x6 blocks of the reduced system and their contributions
+    std::vector<int> blk_fa, blk_fb;                  // [nblk]
+    std::vector<int> blk_pp_ptr, blk_pp_item;         // (pair*4 + kind) kind 0 AtHA 1 BtHB 2 AtHB 3 BtHA
+    std::vector<int> blk_g_ptr, blk_g_item;           // (host index, a, b) packed: hidx*4096 + a*64 + b
+    size_t gram_floats = 0;                           // total doubles of all chunk partials
+};
+
+struct Ctx {
+    pba_config cfg{};
+    std::string err;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    int device = 0;
+    size_t real_size = 4;  // sizeof(T)
+
+    // state machine
+    bool have_frames = false, have_points = false;
+    int cur_level = -1;            // level whose linearization / frozen set is current
+    int iters_in_level = 0;
+
+    // frames
+    int F = 0, W = 0, H = 0;
+    std::vector<double> K0;        // [F][4]
+    LevelDev lv[PBA_MAX_LEVELS];
+
+    // points
+    int N = 0, O = 0, P = 0;
+    Structure st;
+
+    // device buffers (generic pointers; element type per precision)
+    double *d_poses = nullptr, *d_poses0 = nullptr;   // [F][12]
+    double *d_K0 = nullptr;                           // [F][4] level-0 intrinsics
+    double *d_depth = nullptr, *d_depth0 = nullptr;   // [N]
+    int *d_host_frame = nullptr, *d_obs_ptr = nullptr, *d_obs_frame = nullptr, *d_obs_point = nullptr,
+        *d_obs_pair = nullptr, *d_pair_host = nullptr, *d_pair_target = nullptr, *d_pair_obs_ptr = nullptr,
+        *d_pair_obs_idx = nullptr, *d_frame_pair_ptr = nullptr, *d_frame_pair_item = nullptr,
+        *d_pair_local = nullptr, *d_pair_hidx = nullptr, *d_host_m = nullptr, *d_host_frames = nullptr,
+        *d_host_pts = nullptr, *d_chunk_host = nullptr, *d_chunk_begin = nullptr, *d_chunk_end = nullptr,
+        *d_chunk_off = nullptr, *d_host_chunk_ptr = nullptr, *d_blk_fa = nullptr, *d_blk_fb = nullptr,
+        *d_blk_pp_ptr = nullptr, *d_blk_pp_item = nullptr, *d_blk_g_ptr = nullptr, *d_blk_g_item = nullptr;
+    float *d_host_uv = nullptr;                        // [N][2]
+    uint8_t *d_mask = nullptr;                         // [O]
+    void *d_rec = nullptr;                             // T [O][REC_STRIDE]
+    double *d_geo0 = nullptr, *d_geo_a = nullptr, *d_geo_b = nullptr;   // [Pn][GEO_STRIDE]
+    void *d_rel0 = nullptr, *d_rel_a = nullptr, *d_rel_b = nullptr;      // T [Pn][REL_STRIDE]
+    double *d_pairH = nullptr;                         // [Pn][21]
+    double *d_pairY = nullptr;                         // [Pn][9] (6 + e, sq, cnt)
+    double *d_Hdd = nullptr, *d_gd = nullptr;          // [N] (Hdd damped after assembly)
+    double *d_hdd_part = nullptr;                      // partial sums for the depth damping
+    double *d_mu = nullptr;                            // [2] mu_p, mu_d
+    double *d_gram = nullptr;                          // chunk partials
+    double *d_S = nullptr;                             // [6F][6F] reduced system / factor
+    double *d_Sinv = nullptr;                          // [6F][6F] IC: inverse of the reduced system
+    double *d_b = nullptr, *d_dtheta = nullptr;        // [6F]
+    double *d_dth_rel = nullptr;                       // [Pn][6]
+    double *d_stats = nullptr;                         // [cap][ST_STRIDE]
+    int stats_cap = 0;
+    int *d_flag = nullptr;                             // device error flag (non-SPD)
+    int hdd_blocks = 0;
+
+    // current double-buffer orientation
+    bool flip = false;
+
+    // timing
+    std::vector<hipEvent_t> ev_pool;
+    int64_t t_launches = 0, t_res = 0;
+    double t_ms = 0.0;
+};
+
+// ---- kernel launchers (pba_kernels.hip); T selects float or double.
+template <typename T> struct Launch {
+    static void convert_images(hipStream_t s, const float *src, T *dst, size_t n);
+    static void downsample(hipStream_t s, const T *src, T *dst, int F, int Ws, int Hs, int Wd, int Hd);
+    static void level_K(hipStream_t s, const double *K0, T *K, int F, int level);
+    static void make_template(hipStream_t s, Ctx &c, int level);
+    static void relpose(hipStream_t s, Ctx &c, const double *poses, double *geo, T *rel);
+    static void ic_linearize(hipStream_t s, Ctx &c, int level);
+    static void ic_residual(hipStream_t s, Ctx &c, int level, const T *rel_cur);
+    static void fc_linearize(hipStream_t s, Ctx &c, int level, const T *rel_cur, bool write_mask);
+    static void evaluate(hipStream_t s, Ctx &c, int level);
+    static void point_reduce(hipStream_t s, Ctx &c, bool with_hdd);
+    static void pair_reduce_H(hipStream_t s, Ctx &c);
+    static void pair_reduce_y(hipStream_t s, Ctx &c);
+    static void depth_update(hipStream_t s, Ctx &c, const double *geo_old, const double *geo_new, double *stat);
+};
+
+// precision-independent launchers (double only)
+void launch_mu(hipStream_t s, Ctx &c, const double *geo);
+void launch_gram(hipStream_t s, Ctx &c, const double *geo, const void *rec, bool rec_double);
+void launch_assemble_s(hipStream_t s, Ctx &c, const double *geo);
+void launch_ic_factor(hipStream_t s, Ctx &c);
+void launch_solve(hipStream_t s, Ctx &c, const double *geo_lin, double *geo_next, void *rel_next,
+                  bool rel_double, double *stat);
+void launch_sum_stats(hipStream_t s, Ctx &c, const void *rec, bool rec_double, double *out3);
+
+}  // namespace pba

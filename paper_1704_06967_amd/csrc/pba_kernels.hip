@@ -1,0 +1,628 @@
+// HIP kernels of libpba for CDNA4 (gfx950, wave64).
+//
+// Residual-level kernels put one observation (point n seen in frame f) on 8
+// consecutive lanes, one lane per patch pixel, 8 observations per wavefront.
+// Each observation reduces its lanes with cross-lane shuffles and writes one
+// record of Gauss-Newton blocks in relative-pose coordinates. Every later
+// reduction (per point, per pair, per frame) runs in a fixed order in FP64, so
+// results are bitwise reproducible run to run (no floating-point atomics).
+#include "pba_device.hpp"
+#include "pba_internal.hpp"
+
+namespace pba {
+
+#define CHECK_LAUNCH() (void)hipGetLastError()
+
+// ------------------------------------------------------------ images
+
+template <typename T>
+__global__ void k_convert(const float *__restrict__ src, T *__restrict__ dst, size_t n) {
+    size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) dst[i] = (T)src[i];
+}
+
+// Level l+1 = 2x2 box average of level l.
+template <typename T>
+__global__ void k_downsample(const T *__restrict__ src, T *__restrict__ dst, int F, int Ws, int Hs, int Wd,
+                             int Hd) {
+    size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    size_t total = (size_t)F * Wd * Hd;
+    if (i >= total) return;
+    int x = i % Wd;
+    int y = (i / Wd) % Hd;
+    int f = i / ((size_t)Wd * Hd);
+    const T *s = src + (size_t)f * Ws * Hs + (size_t)(2 * y) * Ws + 2 * x;
+    dst[i] = T(0.25) * (((s[0] + s[1]) + s[Ws]) + s[Ws + 1]);
+}
+
+template <typename T>
+__global__ void k_level_K(const double *__restrict__ K0, T *__restrict__ K, int F, int level) {
+    int f = blockIdx.x * blockDim.x + threadIdx.x;
+    if (f >= F) return;
+    const double s = 1.0 / (double)(1 << level);
+    K[4 * f + 0] = (T)(K0[4 * f + 0] * s);
+    K[4 * f + 1] = (T)(K0[4 * f + 1] * s);
+    K[4 * f + 2] = (T)((K0[4 * f + 2] + 0.5) * s - 0.5);
+    K[4 * f + 3] = (T)((K0[4 * f + 3] + 0.5) * s - 0.5);
+}
+
+// Template data at every host patch pixel: I0, the interpolated central-difference
+// gradient, and whether the pixel is usable at this level.
+template <typename T>
+__global__ void k_template(int N, int P, PatternArg pat, const float *__restrict__ host_uv,
+                           const int *__restrict__ host_frame, const T *__restrict__ img, int W, int H, T scale,
+                           T *__restrict__ tmpl) {
+    int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= N * P) return;
+    int n = idx / P, j = idx % P;
+    const T u = ((T)host_uv[2 * n] + T(0.5)) * scale - T(0.5) + (T)pat.du[j];
+    const T v = ((T)host_uv[2 * n + 1] + T(0.5)) * scale - T(0.5) + (T)pat.dv[j];
+    T I = 0, gu = 0, gv = 0, ok = 0;
+    if (usable(u, v, W, H)) {
+        bilinear_grad(img + (size_t)host_frame[n] * W * H, W, u, v, I, gu, gv);
+        ok = 1;
+    }
+    tmpl[4 * idx + 0] = I;
+    tmpl[4 * idx + 1] = gu;
+    tmpl[4 * idx + 2] = gv;
+    tmpl[4 * idx + 3] = ok;
+}
+
+// ------------------------------------------------------------ poses
+
+// Relative pose of every (host, target) pair: R = R_f R_h^T, t = t_f - R t_h.
+template <typename T>
+__global__ void k_relpose(int Pn, const int *__restrict__ pair_host, const int *__restrict__ pair_target,
+                          const double *__restrict__ poses, double *__restrict__ geo, T *__restrict__ rel) {
+    int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= Pn) return;
+    const double *Ph = poses + 12 * pair_host[p];
+    const double *Pf = poses + 12 * pair_target[p];
+    double R[9];
+    mat3_mul_bt(Pf, Ph, R);
+    double t[3];
+    for (int i = 0; i < 3; ++i) t[i] = Pf[9 + i] - (R[i * 3] * Ph[9] + R[i * 3 + 1] * Ph[10] + R[i * 3 + 2] * Ph[11]);
+    double *g = geo + GEO_STRIDE * p;
+    for (int i = 0; i < 9; ++i) g[i] = R[i];
+    for (int i = 0; i < 3; ++i) g[9 + i] = t[i];
+    for (int i = 0; i < 3; ++i) g[12 + i] = Ph[9 + i];
+    g[15] = 0.0;
+    T *r = rel + REL_STRIDE * p;
+    for (int i = 0; i < 9; ++i) r[i] = (T)R[i];
+    for (int i = 0; i < 3; ++i) r[9 + i] = (T)t[i];
+}
+
+// ------------------------------------------------------------ residual kernels
+
+template <typename T>
+struct ResArgs {
+    int O, P, W, H;
+    PatternArg pat;
+    T scale;             // 1 / 2^level
+    T huber_k;
+    const int *obs_point, *obs_pair, *pair_host, *pair_target;
+    const float *host_uv;
+    const T *img;        // level image stack
+    const T *K;          // level intrinsics [F][4]
+    const T *tmpl;       // [N][P][4]
+    const T *rel;        // current relative poses
+    const T *rel0;       // relative poses at p(0) (IC)
+    const double *depth, *depth0;
+    uint8_t *mask;
+    T *rec;
+};
+
+// Normalized template coordinates of patch pixel j of point n (host intrinsics).
+template <typename T>
+__device__ __forceinline__ void template_xy(const ResArgs<T> &a, int n, int j, const T *Kh, T &x, T &y) {
+    const T u = ((T)a.host_uv[2 * n] + T(0.5)) * a.scale - T(0.5) + (T)a.pat.du[j];
+    const T v = ((T)a.host_uv[2 * n + 1] + T(0.5)) * a.scale - T(0.5) + (T)a.pat.dv[j];
+    x = (u - Kh[2]) / Kh[0];
+    y = (v - Kh[3]) / Kh[1];
+}
+
+// Linearization of one residual, shared by the FC iteration and the IC setup.
+// IC: J from the proxy warp at p(0) (Sec. 3.4) and W0 from the residual at p(0).
+// FC: J at the current parameters from the target gradient.
+// Writes the 38-value record of its observation (lane j == 0).
+template <typename T, bool IC>
+__global__ __launch_bounds__(BLOCK) void k_linearize(ResArgs<T> a, int write_mask) {
+    const int gid = blockIdx.x * BLOCK + threadIdx.x;
+    const int o = gid >> 3, j = gid & 7;
+    T J[7] = {0, 0, 0, 0, 0, 0, 0};
+    T r = 0, w = 0, rho = 0;
+    bool valid = false;
+    if (o < a.O && j < a.P) {
+        const int n = a.obs_point[o], pr = a.obs_pair[o];
+        const int h = a.pair_host[pr], f = a.pair_target[pr];
+        const T *Kh = a.K + 4 * h;
+        const T *Kt = a.K + 4 * f;
+        const T *tp = a.tmpl + 4 * ((size_t)n * a.P + j);
+        const T I0 = tp[0], gu0 = tp[1], gv0 = tp[2];
+        const bool host_ok = tp[3] != T(0);
+        bool frozen = true;
+        if (!write_mask) frozen = (a.mask[o] >> j) & 1;
+        T x, y;
+        template_xy(a, n, j, Kh, x, y);
+        const T *R = a.rel + REL_STRIDE * pr;
+        const T *t = R + 9;
+        const T d = (T)a.depth[n];
+        const T Rx0 = R[0] * x + R[1] * y + R[2];
+        const T Rx1 = R[3] * x + R[4] * y + R[5];
+        const T Rx2 = R[6] * x + R[7] * y + R[8];
+        const T vx = Rx0 + d * t[0], vy = Rx1 + d * t[1], vz = Rx2 + d * t[2];
+        if (host_ok && frozen && d > T(0) && vz > T(0)) {
+            const T ux = vx / vz, uy = vy / vz;
+            const T qu = Kt[0] * ux + Kt[2], qv = Kt[1] * uy + Kt[3];
+            if (usable(qu, qv, a.W, a.H)) {
+                valid = true;
+                const T *imf = a.img + (size_t)f * a.W * a.H;
+                T If, gu, gv;
+                if (IC) {
+                    If = bilinear(imf, a.W, qu, qv);
+                    const T *R0 = a.rel0 + REL_STRIDE * pr;
+                    ic_jacobian(x, y, R0, R0 + 9, (T)a.depth0[n], gu0, gv0, Kh[0], Kh[1], J);
+                } else {
+                    bilinear_grad(imf, a.W, qu, qv, If, gu, gv);
+                    fc_jacobian(Rx0, Rx1, Rx2, vz, ux, uy, t, d, gu, gv, Kt[0], Kt[1], J);
+                }
+                r = I0 - If;
+                huber(r, a.huber_k, w, rho);
+            }
+        }
+    }
+    if (write_mask) {
+        const unsigned long long bal = __ballot(valid);
+        if (j == 0 && o < a.O) a.mask[o] = (uint8_t)((bal >> (threadIdx.x & 56)) & 0xFFull);
+    }
+    T v[38];
+    int k = 0;
+    for (int p = 0; p < 6; ++p)
+        for (int q = p; q < 6; ++q) v[k++] = w * J[p] * J[q];
+    for (int p = 0; p < 6; ++p) v[21 + p] = w * J[p] * J[6];
+    v[27] = w * J[6] * J[6];
+    for (int p = 0; p < 7; ++p) v[28 + p] = w * J[p] * r;
+    v[35] = valid ? rho : T(0);
+    v[36] = valid ? r * r : T(0);
+    v[37] = valid ? T(1) : T(0);
+#pragma unroll
+    for (int p = 0; p < 38; ++p) v[p] = wave_sum8(v[p]);
+    if (j == 0 && o < a.O) {
+        T *rec = a.rec + (size_t)o * REC_STRIDE;
+#pragma unroll
+        for (int p = 0; p < 38; ++p) rec[p] = v[p];
+    }
+}
+
+// IC iteration: residuals at the current parameters, Huber weights, and
+// g = J^T W r with the constant proxy Jacobian (Sec. 3.5 steps 1-2).
+template <typename T>
+__global__ __launch_bounds__(BLOCK) void k_ic_residual(ResArgs<T> a) {
+    const int gid = blockIdx.x * BLOCK + threadIdx.x;
+    const int o = gid >> 3, j = gid & 7;
+    T c[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+    if (o < a.O && j < a.P && ((a.mask[o] >> j) & 1)) {
+        const int n = a.obs_point[o], pr = a.obs_pair[o];
+        const int h = a.pair_host[pr], f = a.pair_target[pr];
+        const T *Kh = a.K + 4 * h;
+        const T *Kt = a.K + 4 * f;
+        T x, y;
+        template_xy(a, n, j, Kh, x, y);
+        const T *R = a.rel + REL_STRIDE * pr;
+        const T *t = R + 9;
+        const T d = (T)a.depth[n];
+        const T vz = R[6] * x + R[7] * y + R[8] + d * t[2];
+        if (d > T(0) && vz > T(0)) {
+            const T vx = R[0] * x + R[1] * y + R[2] + d * t[0];
+            const T vy = R[3] * x + R[4] * y + R[5] + d * t[1];
+            const T qu = Kt[0] * (vx / vz) + Kt[2], qv = Kt[1] * (vy / vz) + Kt[3];
+            if (usable(qu, qv, a.W, a.H)) {
+                const T *tp = a.tmpl + 4 * ((size_t)n * a.P + j);
+                const T If = bilinear(a.img + (size_t)f * a.W * a.H, a.W, qu, qv);
+                const T r = tp[0] - If;
+                T w, rho;
+                huber(r, a.huber_k, w, rho);
+                T J[7];
+                const T *R0 = a.rel0 + REL_STRIDE * pr;
+                ic_jacobian(x, y, R0, R0 + 9, (T)a.depth0[n], tp[1], tp[2], Kh[0], Kh[1], J);
+                const T wr = w * r;
+#pragma unroll
+                for (int p = 0; p < 7; ++p) c[p] = wr * J[p];
+                c[7] = rho;
+                c[8] = r * r;
+                c[9] = T(1);
+            }
+        }
+    }
+#pragma unroll
+    for (int p = 0; p < 10; ++p) c[p] = wave_sum8(c[p]);
+    if (j == 0 && o < a.O) {
+        T *rec = a.rec + (size_t)o * REC_STRIDE;
+#pragma unroll
+        for (int p = 0; p < 7; ++p) rec[REC_G + p] = c[p];
+        rec[REC_E] = c[7];
+        rec[REC_SQ] = c[8];
+        rec[REC_CNT] = c[9];
+    }
+}
+
+// Energy and RMSE at the current parameters over the residuals usable at those
+// parameters (fresh set); writes the record's statistics fields only.
+template <typename T>
+__global__ __launch_bounds__(BLOCK) void k_evaluate(ResArgs<T> a) {
+    const int gid = blockIdx.x * BLOCK + threadIdx.x;
+    const int o = gid >> 3, j = gid & 7;
+    T c[3] = {0, 0, 0};
+    if (o < a.O && j < a.P) {
+        const int n = a.obs_point[o], pr = a.obs_pair[o];
+        const int h = a.pair_host[pr], f = a.pair_target[pr];
+        const T *Kh = a.K + 4 * h;
+        const T *Kt = a.K + 4 * f;
+        const T *tp = a.tmpl + 4 * ((size_t)n * a.P + j);
+        T x, y;
+        template_xy(a, n, j, Kh, x, y);
+        const T *R = a.rel + REL_STRIDE * pr;
+        const T *t = R + 9;
+        const T d = (T)a.depth[n];
+        const T vz = R[6] * x + R[7] * y + R[8] + d * t[2];
+        if (tp[3] != T(0) && d > T(0) && vz > T(0)) {
+            const T vx = R[0] * x + R[1] * y + R[2] + d * t[0];
+            const T vy = R[3] * x + R[4] * y + R[5] + d * t[1];
+            const T qu = Kt[0] * (vx / vz) + Kt[2], qv = Kt[1] * (vy / vz) + Kt[3];
+            if (usable(qu, qv, a.W, a.H)) {
+                const T r = tp[0] - bilinear(a.img + (size_t)f * a.W * a.H, a.W, qu, qv);
+                T w, rho;
+                huber(r, a.huber_k, w, rho);
+                c[0] = rho;
+                c[1] = r * r;
+                c[2] = T(1);
+            }
+        }
+    }
+    for (int p = 0; p < 3; ++p) c[p] = wave_sum8(c[p]);
+    if (j == 0 && o < a.O) {
+        T *rec = a.rec + (size_t)o * REC_STRIDE;
+        rec[REC_E] = c[0];
+        rec[REC_SQ] = c[1];
+        rec[REC_CNT] = c[2];
+    }
+}
+
+// ------------------------------------------------------------ reductions
+
+// Block-wide sum of NV doubles per thread in a fixed order (wave shuffles, then
+// the waves in index order). Result valid in thread 0.
+template <int NV>
+__device__ __forceinline__ void block_sum(double v[NV], double *lds /* [NV * 16] */) {
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    for (int p = 0; p < NV; ++p)
+        for (int s = 32; s >= 1; s >>= 1) v[p] += __shfl_xor(v[p], s, 64);
+    if (lane == 0)
+        for (int p = 0; p < NV; ++p) lds[wv * NV + p] = v[p];
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const int nw = (blockDim.x + 63) >> 6;
+        for (int p = 0; p < NV; ++p) {
+            double s = 0.0;
+            for (int k = 0; k < nw; ++k) s += lds[k * NV + p];
+            v[p] = s;
+        }
+    }
+    __syncthreads();
+}
+
+// Per point: sum of the depth blocks over the point's observations; block
+// partial sums of H_dd for the depth damping.
+template <typename T>
+__global__ __launch_bounds__(256) void k_point_reduce(int N, const int *__restrict__ obs_ptr,
+                                                      const T *__restrict__ rec, double *__restrict__ Hdd,
+                                                      double *__restrict__ gd, double *__restrict__ part,
+                                                      int with_hdd) {
+    __shared__ double lds[16];
+    const int n = blockIdx.x * blockDim.x + threadIdx.x;
+    double hs = 0.0, gs = 0.0;
+    if (n < N) {
+        for (int o = obs_ptr[n]; o < obs_ptr[n + 1]; ++o) {
+            const T *r = rec + (size_t)o * REC_STRIDE;
+            hs += (double)r[REC_HDD];
+            gs += (double)r[REC_GD];
+        }
+        gd[n] = gs;
+        if (with_hdd) Hdd[n] = hs;
+    }
+    if (with_hdd) {
+        double v[1] = {hs};
+        block_sum<1>(v, lds);
+        if (threadIdx.x == 0) part[blockIdx.x] = v[0];
+    }
+}
+
+// Per pair: sum over its observations of the pose-pose block (21 values).
+template <typename T>
+__global__ __launch_bounds__(256) void k_pair_reduce_H(const int *__restrict__ pair_obs_ptr,
+                                                       const int *__restrict__ pair_obs_idx,
+                                                       const T *__restrict__ rec, double *__restrict__ pairH) {
+    __shared__ double lds[21 * 16];
+    const int p = blockIdx.x;
+    double v[21];
+    for (int k = 0; k < 21; ++k) v[k] = 0.0;
+    for (int i = pair_obs_ptr[p] + threadIdx.x; i < pair_obs_ptr[p + 1]; i += blockDim.x) {
+        const T *r = rec + (size_t)pair_obs_idx[i] * REC_STRIDE;
+        for (int k = 0; k < 21; ++k) v[k] += (double)r[REC_H + k];
+    }
+    block_sum<21>(v, lds);
+    if (threadIdx.x == 0)
+        for (int k = 0; k < 21; ++k) pairH[21 * p + k] = v[k];
+}
+
+// Per pair: reduced right-hand side contribution sum_o (g_o - h_o g_d,n / H_dd,n)
+// (depth elimination of the gradient) and the energy statistics.
+template <typename T>
+__global__ __launch_bounds__(256) void k_pair_reduce_y(const int *__restrict__ pair_obs_ptr,
+                                                       const int *__restrict__ pair_obs_idx,
+                                                       const int *__restrict__ obs_point, const T *__restrict__ rec,
+                                                       const double *__restrict__ Hdd, const double *__restrict__ gd,
+                                                       double *__restrict__ pairY) {
+    __shared__ double lds[9 * 16];
+    const int p = blockIdx.x;
+    double v[9];
+    for (int k = 0; k < 9; ++k) v[k] = 0.0;
+    for (int i = pair_obs_ptr[p] + threadIdx.x; i < pair_obs_ptr[p + 1]; i += blockDim.x) {
+        const int o = pair_obs_idx[i];
+        const T *r = rec + (size_t)o * REC_STRIDE;
+        const int n = obs_point[o];
+        const double s = gd[n] / Hdd[n];
+        for (int k = 0; k < 6; ++k) v[k] += (double)r[REC_G + k] - (double)r[REC_h + k] * s;
+        v[6] += (double)r[REC_E];
+        v[7] += (double)r[REC_SQ];
+        v[8] += (double)r[REC_CNT];
+    }
+    block_sum<9>(v, lds);
+    if (threadIdx.x == 0)
+        for (int k = 0; k < 9; ++k) pairY[9 * p + k] = v[k];
+}
+
+// Sum of the record statistics over all observations (single block).
+template <typename T>
+__global__ __launch_bounds__(1024) void k_sum_stats(int O, const T *__restrict__ rec, double *__restrict__ out) {
+    __shared__ double lds[3 * 16];
+    double v[3] = {0.0, 0.0, 0.0};
+    for (int o = threadIdx.x; o < O; o += blockDim.x) {
+        const T *r = rec + (size_t)o * REC_STRIDE;
+        v[0] += (double)r[REC_E];
+        v[1] += (double)r[REC_SQ];
+        v[2] += (double)r[REC_CNT];
+    }
+    block_sum<3>(v, lds);
+    if (threadIdx.x == 0)
+        for (int k = 0; k < 3; ++k) out[k] = v[k];
+}
+
+// ------------------------------------------------------------ depth update
+
+__device__ __forceinline__ void atomic_max_nonneg(double *addr, double v) {
+    // non-negative doubles order like their bit patterns as unsigned integers
+    atomicMax(reinterpret_cast<unsigned long long *>(addr), (unsigned long long)__double_as_longlong(v));
+}
+
+// Back-substitution of the depths, dd_n = -(g_d,n + h_n^T dtheta) / H_dd,n, the
+// depth update (IC: d_{k+1} = d_k (d0 - dd) / d0, Sec. 3.6; FC: d + dd), and
+// the largest level-0 displacement of any observation's point centre.
+template <typename T>
+__global__ __launch_bounds__(256) void k_depth_update(int N, int ic, const int *__restrict__ obs_ptr,
+                                                      const int *__restrict__ obs_pair,
+                                                      const int *__restrict__ host_frame,
+                                                      const float *__restrict__ host_uv,
+                                                      const double *__restrict__ K0, const int *__restrict__ pair_target,
+                                                      const T *__restrict__ rec, const double *__restrict__ Hdd,
+                                                      const double *__restrict__ gd,
+                                                      const double *__restrict__ dth_rel,
+                                                      const double *__restrict__ geo_old,
+                                                      const double *__restrict__ geo_new, double *__restrict__ depth,
+                                                      const double *__restrict__ depth0, double *__restrict__ stat) {
+    __shared__ double red[2][4];
+    const int n = blockIdx.x * blockDim.x + threadIdx.x;
+    double mdisp = 0.0, mstep = 0.0;
+    if (n < N) {
+        double s = gd[n];
+        for (int o = obs_ptr[n]; o < obs_ptr[n + 1]; ++o) {
+            const T *r = rec + (size_t)o * REC_STRIDE;
+            const double *dr = dth_rel + 6 * obs_pair[o];
+            for (int k = 0; k < 6; ++k) s += (double)r[REC_h + k] * dr[k];
+        }
+        const double dd = -s / Hdd[n];
+        const double d_old = depth[n];
+        const double d_new = ic ? d_old * (depth0[n] - dd) / depth0[n] : d_old + dd;
+        depth[n] = d_new;
+        mstep = fabs(dd);
+        const int h = host_frame[n];
+        const double x = ((double)host_uv[2 * n] - K0[4 * h + 2]) / K0[4 * h + 0];
+        const double y = ((double)host_uv[2 * n + 1] - K0[4 * h + 3]) / K0[4 * h + 1];
+        for (int o = obs_ptr[n]; o < obs_ptr[n + 1]; ++o) {
+            const int p = obs_pair[o];
+            const double *Kt = K0 + 4 * pair_target[p];
+            double q[2][2];
+            bool ok = true;
+            for (int s2 = 0; s2 < 2; ++s2) {
+                const double *g = s2 ? geo_new + GEO_STRIDE * p : geo_old + GEO_STRIDE * p;
+                const double d = s2 ? d_new : d_old;
+                const double vx = g[0] * x + g[1] * y + g[2] + d * g[9];
+                const double vy = g[3] * x + g[4] * y + g[5] + d * g[10];
+                const double vz = g[6] * x + g[7] * y + g[8] + d * g[11];
+                ok = ok && vz > 0.0;
+                const double vzs = vz > 0.0 ? vz : 1.0;
+                q[s2][0] = Kt[0] * vx / vzs + Kt[2];
+                q[s2][1] = Kt[1] * vy / vzs + Kt[3];
+            }
+            if (ok) mdisp = fmax(mdisp, hypot(q[1][0] - q[0][0], q[1][1] - q[0][1]));
+        }
+    }
+    for (int s = 32; s >= 1; s >>= 1) {
+        mdisp = fmax(mdisp, __shfl_xor(mdisp, s, 64));
+        mstep = fmax(mstep, __shfl_xor(mstep, s, 64));
+    }
+    if ((threadIdx.x & 63) == 0) {
+        red[0][threadIdx.x >> 6] = mdisp;
+        red[1][threadIdx.x >> 6] = mstep;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int k = 1; k < 4; ++k) {
+            mdisp = fmax(mdisp, red[0][k]);
+            mstep = fmax(mstep, red[1][k]);
+        }
+        atomic_max_nonneg(stat + ST_DISP, mdisp);
+        atomic_max_nonneg(stat + ST_STEP_D, mstep);
+    }
+}
+
+// ------------------------------------------------------------ launchers
+
+static inline unsigned nblk(size_t n, unsigned b) { return (unsigned)((n + b - 1) / b); }
+
+template <typename T>
+static ResArgs<T> res_args(Ctx &c, int level, const T *rel_cur) {
+    ResArgs<T> a{};
+    a.O = c.O;
+    a.P = c.P;
+    a.W = c.lv[level].W;
+    a.H = c.lv[level].H;
+    a.pat.n = c.cfg.pattern_n;
+    for (int j = 0; j < 8; ++j) {
+        a.pat.du[j] = j < c.cfg.pattern_n ? c.cfg.pattern_uv[2 * j] : 0;
+        a.pat.dv[j] = j < c.cfg.pattern_n ? c.cfg.pattern_uv[2 * j + 1] : 0;
+    }
+    a.scale = T(1) / T(1 << level);
+    a.huber_k = (T)c.cfg.huber_k;
+    a.obs_point = c.d_obs_point;
+    a.obs_pair = c.d_obs_pair;
+    a.pair_host = c.d_pair_host;
+    a.pair_target = c.d_pair_target;
+    a.host_uv = c.d_host_uv;
+    a.img = (const T *)c.lv[level].img;
+    a.K = (const T *)c.lv[level].K;
+    a.tmpl = (const T *)c.lv[level].tmpl;
+    a.rel = rel_cur;
+    a.rel0 = (const T *)c.d_rel0;
+    a.depth = c.d_depth;
+    a.depth0 = c.d_depth0;
+    a.mask = c.d_mask;
+    a.rec = (T *)c.d_rec;
+    return a;
+}
+
+template <typename T>
+void Launch<T>::convert_images(hipStream_t s, const float *src, T *dst, size_t n) {
+    k_convert<T><<<nblk(n, 256), 256, 0, s>>>(src, dst, n);
+    CHECK_LAUNCH();
+}
+
+template <typename T>
+void Launch<T>::downsample(hipStream_t s, const T *src, T *dst, int F, int Ws, int Hs, int Wd, int Hd) {
+    k_downsample<T><<<nblk((size_t)F * Wd * Hd, 256), 256, 0, s>>>(src, dst, F, Ws, Hs, Wd, Hd);
+    CHECK_LAUNCH();
+}
+
+template <typename T>
+void Launch<T>::level_K(hipStream_t s, const double *K0, T *K, int F, int level) {
+    k_level_K<T><<<nblk(F, 64), 64, 0, s>>>(K0, K, F, level);
+    CHECK_LAUNCH();
+}
+
+template <typename T>
+void Launch<T>::make_template(hipStream_t s, Ctx &c, int level) {
+    ResArgs<T> a = res_args<T>(c, level, nullptr);
+    const size_t n = (size_t)c.N * c.P;
+    if (n == 0) return;
+    k_template<T><<<nblk(n, 256), 256, 0, s>>>(c.N, c.P, a.pat, c.d_host_uv, c.d_host_frame, a.img, a.W, a.H,
+                                               a.scale, (T *)c.lv[level].tmpl);
+    CHECK_LAUNCH();
+}
+
+template <typename T>
+void Launch<T>::relpose(hipStream_t s, Ctx &c, const double *poses, double *geo, T *rel) {
+    if (c.st.n_pairs == 0) return;
+    k_relpose<T><<<nblk(c.st.n_pairs, 64), 64, 0, s>>>(c.st.n_pairs, c.d_pair_host, c.d_pair_target, poses, geo,
+                                                       rel);
+    CHECK_LAUNCH();
+}
+
+template <typename T>
+void Launch<T>::ic_linearize(hipStream_t s, Ctx &c, int level) {
+    if (c.O == 0) return;
+    ResArgs<T> a = res_args<T>(c, level, (const T *)c.d_rel0);
+    k_linearize<T, true><<<nblk((size_t)c.O * LANES_PER_OBS, BLOCK), BLOCK, 0, s>>>(a, 1);
+    CHECK_LAUNCH();
+}
+
+template <typename T>
+void Launch<T>::fc_linearize(hipStream_t s, Ctx &c, int level, const T *rel_cur, bool write_mask) {
+    if (c.O == 0) return;
+    ResArgs<T> a = res_args<T>(c, level, rel_cur);
+    k_linearize<T, false><<<nblk((size_t)c.O * LANES_PER_OBS, BLOCK), BLOCK, 0, s>>>(a, write_mask ? 1 : 0);
+    CHECK_LAUNCH();
+}
+
+template <typename T>
+void Launch<T>::ic_residual(hipStream_t s, Ctx &c, int level, const T *rel_cur) {
+    if (c.O == 0) return;
+    ResArgs<T> a = res_args<T>(c, level, rel_cur);
+    k_ic_residual<T><<<nblk((size_t)c.O * LANES_PER_OBS, BLOCK), BLOCK, 0, s>>>(a);
+    CHECK_LAUNCH();
+}
+
+template <typename T>
+void Launch<T>::evaluate(hipStream_t s, Ctx &c, int level) {
+    if (c.O == 0) return;
+    const T *rel = (const T *)(c.flip ? c.d_rel_b : c.d_rel_a);
+    ResArgs<T> a = res_args<T>(c, level, rel);
+    k_evaluate<T><<<nblk((size_t)c.O * LANES_PER_OBS, BLOCK), BLOCK, 0, s>>>(a);
+    CHECK_LAUNCH();
+}
+
+template <typename T>
+void Launch<T>::point_reduce(hipStream_t s, Ctx &c, bool with_hdd) {
+    if (c.N == 0) return;
+    k_point_reduce<T><<<c.hdd_blocks, 256, 0, s>>>(c.N, c.d_obs_ptr, (const T *)c.d_rec, c.d_Hdd, c.d_gd,
+                                                   c.d_hdd_part, with_hdd ? 1 : 0);
+    CHECK_LAUNCH();
+}
+
+template <typename T>
+void Launch<T>::pair_reduce_H(hipStream_t s, Ctx &c) {
+    if (c.st.n_pairs == 0) return;
+    k_pair_reduce_H<T><<<c.st.n_pairs, 256, 0, s>>>(c.d_pair_obs_ptr, c.d_pair_obs_idx, (const T *)c.d_rec,
+                                                    c.d_pairH);
+    CHECK_LAUNCH();
+}
+
+template <typename T>
+void Launch<T>::pair_reduce_y(hipStream_t s, Ctx &c) {
+    if (c.st.n_pairs == 0) return;
+    k_pair_reduce_y<T><<<c.st.n_pairs, 256, 0, s>>>(c.d_pair_obs_ptr, c.d_pair_obs_idx, c.d_obs_point,
+                                                    (const T *)c.d_rec, c.d_Hdd, c.d_gd, c.d_pairY);
+    CHECK_LAUNCH();
+}
+
+template <typename T>
+void Launch<T>::depth_update(hipStream_t s, Ctx &c, const double *geo_old, const double *geo_new, double *stat) {
+    if (c.N == 0) return;
+    k_depth_update<T><<<nblk(c.N, 256), 256, 0, s>>>(
+        c.N, c.cfg.mode == PBA_IC_PROXY ? 1 : 0, c.d_obs_ptr, c.d_obs_pair, c.d_host_frame, c.d_host_uv, c.d_K0,
+        c.d_pair_target, (const T *)c.d_rec, c.d_Hdd, c.d_gd, c.d_dth_rel, geo_old, geo_new, c.d_depth,
+        c.d_depth0, stat);
+    CHECK_LAUNCH();
+}
+
+void launch_sum_stats(hipStream_t s, Ctx &c, const void *rec, bool rec_double, double *out3) {
+    if (rec_double)
+        k_sum_stats<double><<<1, 1024, 0, s>>>(c.O, (const double *)rec, out3);
+    else
+        k_sum_stats<float><<<1, 1024, 0, s>>>(c.O, (const float *)rec, out3);
+    CHECK_LAUNCH();
+}
+
+template struct Launch<float>;
+template struct Launch<double>;
+
+}  // namespace pba

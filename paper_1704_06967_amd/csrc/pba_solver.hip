@@ -1,0 +1,483 @@
+// FP64 kernels of the reduced pose system: depth damping, the per-host Gram of
+// the depth Schur complement, assembly of S, Cholesky, the IC inverse, and the
+// single-workgroup solve + pose update of every iteration.
+#include "pba_device.hpp"
+#include "pba_internal.hpp"
+
+namespace pba {
+
+constexpr int SOLVE_THREADS = 1024;
+constexpr int LDS_DOUBLES = 150 * 1024 / 8;   // packed lower triangle of S when it fits
+constexpr int LDS_MAX_N = 192;                // n (n + 1) / 2 <= LDS_DOUBLES - 2 n
+constexpr int GRAM_G = 8;                     // points per Gram step
+constexpr int GRAM_EMAX = 6 * (MAX_HOST_TARGETS + 1);
+constexpr int GRAM_KMAX = (GRAM_EMAX * GRAM_EMAX + 255) / 256;
+
+__device__ __forceinline__ double sym21(const double *u, int a, int b) {
+    // upper triangle (row-major) of a symmetric 6x6
+    if (a > b) {
+        int t = a;
+        a = b;
+        b = t;
+    }
+    return u[a * 6 - a * (a - 1) / 2 + (b - a)];
+}
+
+// X^T H Y entry (r, c) for 6x6 X, Y and H given by its upper triangle.
+__device__ __forceinline__ double xthy(const double *X, const double *H21, const double *Y, int r, int c) {
+    double s = 0.0;
+    for (int a = 0; a < 6; ++a) {
+        double t = 0.0;
+        for (int b = 0; b < 6; ++b) t += sym21(H21, a, b) * Y[b * 6 + c];
+        s += X[a * 6 + r] * t;
+    }
+    return s;
+}
+
+__global__ void k_fill(double *__restrict__ p, size_t n, double v) {
+    size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+// Damping of the pose and depth diagonals: mu = damping_rel x mean diagonal of
+// the undamped blocks.
+__global__ __launch_bounds__(256) void k_mu(int Pn, int F, int N, int hdd_blocks, double damping,
+                                             const double *__restrict__ pairH, const double *__restrict__ geo,
+                                             const double *__restrict__ hdd_part, double *__restrict__ mu) {
+    __shared__ double lds[16];
+    double s = 0.0;
+    for (int e = threadIdx.x; e < Pn * 6; e += blockDim.x) {
+        const int p = e / 6, r = e % 6;
+        double A[36], B[36];
+        abs_maps(geo + GEO_STRIDE * p, A, B);
+        s += xthy(A, pairH + 21 * p, A, r, r) + xthy(B, pairH + 21 * p, B, r, r);
+    }
+    double v[1] = {s};
+    for (int k = 32; k >= 1; k >>= 1) v[0] += __shfl_xor(v[0], k, 64);
+    if ((threadIdx.x & 63) == 0) lds[threadIdx.x >> 6] = v[0];
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double tot = 0.0;
+        for (int k = 0; k < (int)(blockDim.x >> 6); ++k) tot += lds[k];
+        double hs = 0.0;
+        for (int k = 0; k < hdd_blocks; ++k) hs += hdd_part[k];
+        mu[0] = damping * tot / (6.0 * F);
+        mu[1] = N > 0 ? damping * hs / N : 0.0;
+    }
+}
+
+__global__ void k_damp_hdd(int N, double *__restrict__ Hdd, const double *__restrict__ mu) {
+    int n = blockIdx.x * blockDim.x + threadIdx.x;
+    if (n < N) Hdd[n] += mu[1];
+}
+
+// Depth Schur complement, one chunk of one host frame's points per block:
+// T += u_n u_n^T with u_n = [A_1^T h_1, ..., A_m^T h_m, sum_o B_o^T h_o] / sqrt(H_dd,n),
+// the coupling of point n to each of the host's target frames and to the host,
+// in absolute coordinates. T is (6(m+1))^2, every entry owned by one thread.
+template <typename T>
+__global__ __launch_bounds__(256) void k_gram(const int *__restrict__ chunk_host, const int *__restrict__ chunk_begin,
+                                              const int *__restrict__ chunk_end, const int *__restrict__ chunk_off,
+                                              const int *__restrict__ host_m, const int *__restrict__ host_pts,
+                                              const int *__restrict__ obs_ptr, const int *__restrict__ obs_pair,
+                                              const int *__restrict__ pair_local, const T *__restrict__ rec,
+                                              const double *__restrict__ Hdd, const double *__restrict__ geo,
+                                              double *__restrict__ gram) {
+    __shared__ double u[GRAM_G][GRAM_EMAX];
+    const int c = blockIdx.x;
+    const int m = host_m[chunk_host[c]];
+    const int E = 6 * (m + 1);
+    const int EE = E * E;
+    double acc[GRAM_KMAX];
+#pragma unroll
+    for (int k = 0; k < GRAM_KMAX; ++k) acc[k] = 0.0;
+    for (int base = chunk_begin[c]; base < chunk_end[c]; base += GRAM_G) {
+        const int G = min(GRAM_G, chunk_end[c] - base);
+        for (int e = threadIdx.x; e < GRAM_G * GRAM_EMAX; e += blockDim.x) (&u[0][0])[e] = 0.0;
+        __syncthreads();
+        if (threadIdx.x < G * 6) {
+            const int q = threadIdx.x / 6, r = threadIdx.x % 6;
+            const int n = host_pts[base + q];
+            const double s = 1.0 / sqrt(Hdd[n]);
+            double hb = 0.0;
+            for (int o = obs_ptr[n]; o < obs_ptr[n + 1]; ++o) {
+                const int p = obs_pair[o];
+                const T *h = rec + (size_t)o * REC_STRIDE + REC_h;
+                double hv[6], ua[6], ub[6];
+                for (int a = 0; a < 6; ++a) hv[a] = (double)h[a];
+                apply_At(geo + GEO_STRIDE * p, hv, ua);
+                apply_Bt(geo + GEO_STRIDE * p, hv, ub);
+                u[q][6 * pair_local[p] + r] = ua[r] * s;
+                hb += ub[r] * s;
+            }
+            u[q][6 * m + r] = hb;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < GRAM_KMAX; ++k) {
+            const int e = threadIdx.x + 256 * k;
+            if (e < EE) {
+                const int a = e / E, b = e % E;
+                double s = 0.0;
+                for (int q = 0; q < G; ++q) s += u[q][a] * u[q][b];
+                acc[k] += s;
+            }
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int k = 0; k < GRAM_KMAX; ++k) {
+        const int e = threadIdx.x + 256 * k;
+        if (e < EE) gram[(size_t)chunk_off[c] + e] = acc[k];
+    }
+}
+
+// Reduced pose system S = H_pp + mu_p I - sum_n h_n h_n^T / H_dd,n, one nonzero
+// 6x6 block per workgroup: mapped pair blocks (A^T H A, B^T H B, A^T H B, B^T H A)
+// minus the host Gram blocks, then the gauge pin (identity rows / columns).
+__global__ __launch_bounds__(64) void k_assemble_s(int n6, int pinned, const int *__restrict__ blk_fa,
+                                                   const int *__restrict__ blk_fb, const int *__restrict__ pp_ptr,
+                                                   const int *__restrict__ pp_item, const int *__restrict__ g_ptr,
+                                                   const int *__restrict__ g_item, const int *__restrict__ host_m,
+                                                   const int *__restrict__ host_chunk_ptr,
+                                                   const int *__restrict__ chunk_off, const double *__restrict__ pairH,
+                                                   const double *__restrict__ geo, const double *__restrict__ gram,
+                                                   const double *__restrict__ mu, double *__restrict__ S) {
+    const int b = blockIdx.x;
+    if (threadIdx.x >= 36) return;
+    const int r = threadIdx.x / 6, c = threadIdx.x % 6;
+    const int fa = blk_fa[b], fb = blk_fb[b];
+    double val = 0.0;
+    for (int i = pp_ptr[b]; i < pp_ptr[b + 1]; ++i) {
+        const int p = pp_item[i] >> 2, kind = pp_item[i] & 3;
+        double A[36], B[36];
+        abs_maps(geo + GEO_STRIDE * p, A, B);
+        const double *X = (kind == 0 || kind == 2) ? A : B;
+        const double *Y = (kind == 0 || kind == 3) ? A : B;
+        val += xthy(X, pairH + 21 * p, Y, r, c);
+    }
+    for (int i = g_ptr[b]; i < g_ptr[b + 1]; ++i) {
+        const int it = g_item[i];
+        const int hi = it >> 12, a = (it >> 6) & 63, bb = it & 63;
+        const int E = 6 * (host_m[hi] + 1);
+        const size_t idx = (size_t)(6 * a + r) * E + 6 * bb + c;
+        for (int ch = host_chunk_ptr[hi]; ch < host_chunk_ptr[hi + 1]; ++ch) val -= gram[(size_t)chunk_off[ch] + idx];
+    }
+    if (fa == fb && r == c) val += mu[0];
+    if (pinned >= 0 && (fa == pinned || fb == pinned)) val = (fa == fb && r == c) ? 1.0 : 0.0;
+    S[(size_t)(6 * fa + r) * n6 + 6 * fb + c] = val;
+}
+
+// ---- dense SPD helpers for one workgroup (packed lower triangle in LDS, or the
+// full row-major matrix in global memory when it does not fit)
+
+struct PackedLds {
+    double *p;
+    __device__ double &operator()(int i, int j) const { return p[i * (i + 1) / 2 + j]; }
+};
+struct FullGlobal {
+    double *p;
+    int n;
+    __device__ double &operator()(int i, int j) const { return p[(size_t)i * n + j]; }
+};
+
+// In-place Cholesky (lower) of the first n rows; returns false if a pivot is
+// not positive. Right-looking, one column per step.
+template <class M>
+__device__ bool chol_block(M A, int n, int *fail) {
+    for (int k = 0; k < n; ++k) {
+        if (threadIdx.x == 0) {
+            const double d = A(k, k);
+            if (!(d > 0.0))
+                *fail = 1;
+            else
+                A(k, k) = sqrt(d);
+        }
+        __syncthreads();
+        if (*fail) return false;
+        const double lkk = A(k, k);
+        for (int i = k + 1 + threadIdx.x; i < n; i += blockDim.x) A(i, k) /= lkk;
+        __syncthreads();
+        const int m = n - k - 1;
+        for (int e = threadIdx.x; e < m * m; e += blockDim.x) {
+            const int i = k + 1 + e / m, j = k + 1 + e % m;
+            if (j <= i) A(i, j) -= A(i, k) * A(j, k);
+        }
+        __syncthreads();
+    }
+    return true;
+}
+
+// Solve L L^T x = b in place (x overwrites b; b lives in LDS).
+template <class M>
+__device__ void chol_solve_block(M L, int n, double *b) {
+    for (int k = 0; k < n; ++k) {
+        if (threadIdx.x == 0) b[k] /= L(k, k);
+        __syncthreads();
+        const double yk = b[k];
+        for (int i = k + 1 + threadIdx.x; i < n; i += blockDim.x) b[i] -= L(i, k) * yk;
+        __syncthreads();
+    }
+    for (int k = n - 1; k >= 0; --k) {
+        if (threadIdx.x == 0) b[k] /= L(k, k);
+        __syncthreads();
+        const double xk = b[k];
+        for (int i = threadIdx.x; i < k; i += blockDim.x) b[i] -= L(k, i) * xk;
+        __syncthreads();
+    }
+}
+
+// IC setup: Cholesky of S and its explicit inverse (the paper's H^{-1}, formed
+// once per level; every iteration then needs one matrix-vector product).
+__global__ __launch_bounds__(SOLVE_THREADS) void k_ic_factor(int n, double *__restrict__ S,
+                                                             double *__restrict__ Sinv, int *__restrict__ flag) {
+    __shared__ double lds[LDS_DOUBLES];
+    __shared__ int fail;
+    if (threadIdx.x == 0) fail = 0;
+    __syncthreads();
+    const bool packed = n <= LDS_MAX_N;
+    bool ok;
+    if (packed) {
+        PackedLds A{lds};
+        for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
+            const int i = e / n, j = e % n;
+            if (j <= i) A(i, j) = S[e];
+        }
+        __syncthreads();
+        ok = chol_block(A, n, &fail);  // the factor stays in LDS; S keeps the assembled system
+    } else {
+        ok = chol_block(FullGlobal{S, n}, n, &fail);
+    }
+    if (!ok) {
+        if (threadIdx.x == 0) *flag = 1;
+        return;
+    }
+    __syncthreads();
+    // column c of S^{-1}: L y = e_c, L^T x = y (one thread per column)
+    for (int c = threadIdx.x; c < n; c += blockDim.x) {
+        double *x = Sinv + (size_t)c * n;  // row c of the symmetric inverse
+        for (int i = 0; i < n; ++i) {
+            double s = (i == c) ? 1.0 : 0.0;
+            if (i > c) {
+                for (int k = c; k < i; ++k) s -= (packed ? PackedLds{lds}(i, k) : S[(size_t)i * n + k]) * x[k];
+            } else if (i < c) {
+                s = 0.0;
+            }
+            x[i] = s / (packed ? PackedLds{lds}(i, i) : S[(size_t)i * n + i]);
+        }
+        for (int i = n - 1; i >= 0; --i) {
+            double s = x[i];
+            for (int k = i + 1; k < n; ++k) s -= (packed ? PackedLds{lds}(k, i) : S[(size_t)k * n + i]) * x[k];
+            x[i] = s / (packed ? PackedLds{lds}(i, i) : S[(size_t)i * n + i]);
+        }
+    }
+}
+
+// One solve per iteration (single workgroup):
+//  1. reduced right-hand side b_f = sum over the frame's pairs of A^T y (target) or
+//     B^T y (host), zero on the pinned frame;
+//  2. dtheta = -S^{-1} b (IC: product with the stored inverse; FC: Cholesky of the
+//     freshly assembled S and two triangular solves);
+//  3. pose update: IC R <- R_k R0^T exp(dw)^T R0, t <- t_k - R_k R0^T dt (Sec. 3.6);
+//     FC R <- exp(dw) R, t <- t + dt;
+//  4. the next relative poses of every pair and the relative steps A dth_f + B dth_h.
+template <typename T>
+__global__ __launch_bounds__(SOLVE_THREADS) void k_solve(
+    int ic, int F, int Pn, int pinned, const int *__restrict__ frame_pair_ptr, const int *__restrict__ frame_pair_item,
+    const int *__restrict__ pair_host, const int *__restrict__ pair_target, const double *__restrict__ pairY,
+    const double *__restrict__ geo_lin, double *__restrict__ S, const double *__restrict__ Sinv,
+    double *__restrict__ poses, const double *__restrict__ poses0, double *__restrict__ b_out,
+    double *__restrict__ dth_out, double *__restrict__ dth_rel, double *__restrict__ geo_next, T *__restrict__ rel_next,
+    double *__restrict__ stat, int *__restrict__ flag) {
+    __shared__ double lds[LDS_DOUBLES];
+    __shared__ double red[16];
+    __shared__ int fail;
+    if (*flag) return;
+    const int n = 6 * F;
+    const bool packed = !ic && n <= LDS_MAX_N;
+    double *bx = packed ? lds + (size_t)n * (n + 1) / 2 : b_out + n;  // rhs / solution vector
+    if (threadIdx.x == 0) {
+        fail = 0;
+        double e = 0, sq = 0, cnt = 0;
+        for (int p = 0; p < Pn; ++p) {
+            e += pairY[9 * p + 6];
+            sq += pairY[9 * p + 7];
+            cnt += pairY[9 * p + 8];
+        }
+        stat[ST_E] = e;
+        stat[ST_SQ] = sq;
+        stat[ST_CNT] = cnt;
+        stat[ST_DISP] = 0.0;
+        stat[ST_STEP_D] = 0.0;
+    }
+    for (int e = threadIdx.x; e < n; e += blockDim.x) {
+        const int f = e / 6, r = e % 6;
+        double s = 0.0;
+        if (f != pinned) {
+            for (int i = frame_pair_ptr[f]; i < frame_pair_ptr[f + 1]; ++i) {
+                const int p = frame_pair_item[i] >> 1, is_host = frame_pair_item[i] & 1;
+                double yv[6], out[6];
+                for (int a = 0; a < 6; ++a) yv[a] = pairY[9 * p + a];
+                if (is_host)
+                    apply_Bt(geo_lin + GEO_STRIDE * p, yv, out);
+                else
+                    apply_At(geo_lin + GEO_STRIDE * p, yv, out);
+                s += out[r];
+            }
+        }
+        b_out[e] = s;
+        bx[e] = s;
+    }
+    __syncthreads();
+    if (ic) {
+        // dtheta = -S^{-1} b; the product goes to dth_out
+        for (int i = threadIdx.x; i < n; i += blockDim.x) {
+            const double *row = Sinv + (size_t)i * n;
+            double s = 0.0;
+            for (int j = 0; j < n; ++j) s += row[j] * b_out[j];
+            dth_out[i] = -s;
+        }
+    } else {
+        bool ok;
+        if (packed) {
+            PackedLds A{lds};
+            for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
+                const int i = e / n, j = e % n;
+                if (j <= i) A(i, j) = S[e];
+            }
+            __syncthreads();
+            ok = chol_block(A, n, &fail);
+            if (ok) chol_solve_block(A, n, bx);
+        } else {
+            FullGlobal A{S, n};
+            ok = chol_block(A, n, &fail);
+            if (ok) chol_solve_block(A, n, bx);
+        }
+        if (!ok) {
+            if (threadIdx.x == 0) *flag = 1;
+            return;
+        }
+        for (int i = threadIdx.x; i < n; i += blockDim.x) dth_out[i] = -bx[i];
+    }
+    __threadfence_block();
+    __syncthreads();
+    // largest pose step
+    double mx = 0.0;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) mx = fmax(mx, fabs(dth_out[i]));
+    for (int k = 32; k >= 1; k >>= 1) mx = fmax(mx, __shfl_xor(mx, k, 64));
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = mx;
+    // pose update
+    for (int f = threadIdx.x; f < F; f += blockDim.x) {
+        const double *x = dth_out + 6 * f;
+        double dR[9], Rn[9], tn[3];
+        so3_exp(x, dR);
+        double *P = poses + 12 * f;
+        if (ic) {
+            const double *P0 = poses0 + 12 * f;
+            double A[9], Bm[9], Q[9];
+            mat3_mul_bt(P, P0, Q);       // R_k R0^T
+            mat3_mul_bt(Q, dR, A);       // R_k R0^T dR^T
+            mat3_mul(A, P0, Rn);         // ... R0
+            for (int i = 0; i < 3; ++i) tn[i] = P[9 + i] - (Q[3 * i] * x[3] + Q[3 * i + 1] * x[4] + Q[3 * i + 2] * x[5]);
+            (void)Bm;
+        } else {
+            mat3_mul(dR, P, Rn);
+            for (int i = 0; i < 3; ++i) tn[i] = P[9 + i] + x[3 + i];
+        }
+        for (int i = 0; i < 9; ++i) P[i] = Rn[i];
+        for (int i = 0; i < 3; ++i) P[9 + i] = tn[i];
+    }
+    __threadfence_block();
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double m2 = 0.0;
+        for (int k = 0; k < (int)(blockDim.x >> 6); ++k) m2 = fmax(m2, red[k]);
+        stat[ST_STEP_P] = m2;
+    }
+    // next relative poses and relative steps per pair
+    for (int p = threadIdx.x; p < Pn; p += blockDim.x) {
+        const double *Ph = poses + 12 * pair_host[p];
+        const double *Pf = poses + 12 * pair_target[p];
+        double R[9];
+        mat3_mul_bt(Pf, Ph, R);
+        double *g = geo_next + GEO_STRIDE * p;
+        T *rl = rel_next + REL_STRIDE * p;
+        for (int i = 0; i < 9; ++i) {
+            g[i] = R[i];
+            rl[i] = (T)R[i];
+        }
+        for (int i = 0; i < 3; ++i) {
+            const double ti = Pf[9 + i] - (R[3 * i] * Ph[9] + R[3 * i + 1] * Ph[10] + R[3 * i + 2] * Ph[11]);
+            g[9 + i] = ti;
+            rl[9 + i] = (T)ti;
+            g[12 + i] = Ph[9 + i];
+        }
+        g[15] = 0.0;
+        double xf[6], xh[6], af[6], bh[6];
+        for (int a = 0; a < 6; ++a) {
+            xf[a] = dth_out[6 * pair_target[p] + a];
+            xh[a] = dth_out[6 * pair_host[p] + a];
+        }
+        apply_A(geo_lin + GEO_STRIDE * p, xf, af);
+        apply_B(geo_lin + GEO_STRIDE * p, xh, bh);
+        for (int r = 0; r < 6; ++r) dth_rel[6 * p + r] = af[r] + bh[r];
+    }
+}
+
+// ------------------------------------------------------------ launchers
+
+static inline unsigned nb(size_t n, unsigned b) { return (unsigned)((n + b - 1) / b); }
+
+void launch_fill(hipStream_t s, double *p, size_t n, double v) {
+    if (n == 0) return;
+    k_fill<<<nb(n, 256), 256, 0, s>>>(p, n, v);
+}
+
+void launch_mu(hipStream_t s, Ctx &c, const double *geo) {
+    k_mu<<<1, 256, 0, s>>>(c.st.n_pairs, c.F, c.N, c.hdd_blocks, c.cfg.damping_rel, c.d_pairH, geo, c.d_hdd_part,
+                            c.d_mu);
+    if (c.N) k_damp_hdd<<<nb(c.N, 256), 256, 0, s>>>(c.N, c.d_Hdd, c.d_mu);
+}
+
+void launch_gram(hipStream_t s, Ctx &c, const double *geo, const void *rec, bool rec_double) {
+    const int nch = (int)c.st.chunk_host.size();
+    if (nch == 0) return;
+    if (rec_double)
+        k_gram<double><<<nch, 256, 0, s>>>(c.d_chunk_host, c.d_chunk_begin, c.d_chunk_end, c.d_chunk_off, c.d_host_m,
+                                           c.d_host_pts, c.d_obs_ptr, c.d_obs_pair, c.d_pair_local,
+                                           (const double *)rec, c.d_Hdd, geo, c.d_gram);
+    else
+        k_gram<float><<<nch, 256, 0, s>>>(c.d_chunk_host, c.d_chunk_begin, c.d_chunk_end, c.d_chunk_off, c.d_host_m,
+                                          c.d_host_pts, c.d_obs_ptr, c.d_obs_pair, c.d_pair_local,
+                                          (const float *)rec, c.d_Hdd, geo, c.d_gram);
+}
+
+void launch_assemble_s(hipStream_t s, Ctx &c, const double *geo) {
+    const size_t n6 = 6 * (size_t)c.F;
+    launch_fill(s, c.d_S, n6 * n6, 0.0);
+    const int nbk = (int)c.st.blk_fa.size();
+    k_assemble_s<<<nbk, 64, 0, s>>>((int)n6, c.cfg.pinned_frame, c.d_blk_fa, c.d_blk_fb, c.d_blk_pp_ptr,
+                                    c.d_blk_pp_item, c.d_blk_g_ptr, c.d_blk_g_item, c.d_host_m, c.d_host_chunk_ptr,
+                                    c.d_chunk_off, c.d_pairH, geo, c.d_gram, c.d_mu, c.d_S);
+}
+
+void launch_ic_factor(hipStream_t s, Ctx &c) {
+    k_ic_factor<<<1, SOLVE_THREADS, 0, s>>>(6 * c.F, c.d_S, c.d_Sinv, c.d_flag);
+}
+
+void launch_solve(hipStream_t s, Ctx &c, const double *geo_lin, double *geo_next, void *rel_next, bool rel_double,
+                  double *stat) {
+    const int ic = c.cfg.mode == PBA_IC_PROXY ? 1 : 0;
+    if (rel_double)
+        k_solve<double><<<1, SOLVE_THREADS, 0, s>>>(
+            ic, c.F, c.st.n_pairs, c.cfg.pinned_frame, c.d_frame_pair_ptr, c.d_frame_pair_item, c.d_pair_host,
+            c.d_pair_target, c.d_pairY, geo_lin, c.d_S, c.d_Sinv, c.d_poses, c.d_poses0, c.d_b, c.d_dtheta,
+            c.d_dth_rel, geo_next, (double *)rel_next, stat, c.d_flag);
+    else
+        k_solve<float><<<1, SOLVE_THREADS, 0, s>>>(
+            ic, c.F, c.st.n_pairs, c.cfg.pinned_frame, c.d_frame_pair_ptr, c.d_frame_pair_item, c.d_pair_host,
+            c.d_pair_target, c.d_pairY, geo_lin, c.d_S, c.d_Sinv, c.d_poses, c.d_poses0, c.d_b, c.d_dtheta,
+            c.d_dth_rel, geo_next, (float *)rel_next, stat, c.d_flag);
+}
+
+}  // namespace pba

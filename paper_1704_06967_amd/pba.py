@@ -1,0 +1,215 @@
+"""ctypes binding of libpba (include/pba.h).
+
+Argument marshalling only: every step of the Gauss-Newton path runs in the HIP
+library. Importing this module fails loudly when libpba.so has not been built;
+there is no fallback implementation.
+"""
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libpba.so")
+
+PBA_OK, PBA_E_INVALID, PBA_E_STATE, PBA_E_OOM, PBA_E_DEVICE, PBA_E_NUMERIC, PBA_E_NOT_CONVERGED = 0, -1, -2, -3, -4, -5, -6
+PBA_FC, PBA_IC_PROXY = 0, 1
+PBA_FP64, PBA_FP32, PBA_MIXED_BF16 = 0, 1, 2
+PBA_SOLVER_CHOL = 0
+PBA_HOST, PBA_DEVICE = 0, 1
+PBA_FLAG_TIMING = 1
+PBA_MAX_PATTERN = 8
+PBA_MAX_LEVELS = 4
+PBA_DBG_S, PBA_DBG_B, PBA_DBG_OBS_REC, PBA_DBG_TEMPLATE, PBA_DBG_HDD, PBA_DBG_MASK, PBA_DBG_DTHETA = 1, 2, 3, 4, 5, 6, 7
+REC_STRIDE = 40
+
+
+class pba_config(C.Structure):
+    _fields_ = [
+        ("mode", C.c_int32), ("precision", C.c_int32), ("n_levels", C.c_int32), ("pattern_n", C.c_int32),
+        ("pattern_uv", C.c_int32 * (2 * PBA_MAX_PATTERN)), ("huber_k", C.c_double), ("damping_rel", C.c_double),
+        ("pinned_frame", C.c_int32), ("solver", C.c_int32), ("n_windows", C.c_int32), ("flags", C.c_int32),
+        ("stream", C.c_void_p),
+    ]
+
+
+class pba_iter_stats(C.Structure):
+    _fields_ = [
+        ("level", C.c_int32), ("iter", C.c_int32), ("n_active", C.c_int64), ("energy", C.c_double),
+        ("sq", C.c_double), ("rmse", C.c_double), ("max_disp_px", C.c_double), ("max_step_pose", C.c_double),
+        ("max_step_depth", C.c_double),
+    ]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class pba_result(C.Structure):
+    _fields_ = [
+        ("iters", C.c_int32 * PBA_MAX_LEVELS), ("total_iters", C.c_int32), ("converged", C.c_int32),
+        ("final_energy", C.c_double), ("final_rmse", C.c_double), ("final_active", C.c_int64),
+    ]
+
+
+class pba_timing(C.Structure):
+    _fields_ = [("residual_launches", C.c_int64), ("residual_ms", C.c_double), ("residuals_processed", C.c_int64)]
+
+
+class PbaError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{status_string(status)}: {msg}")
+        self.status = status
+
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is missing: build it with `python -c 'import __graft_entry__ as g; g.build()'`")
+_lib = C.CDLL(LIB_PATH)
+
+_P = C.c_void_p
+_sig = {
+    "pba_config_default": (C.c_int, [C.POINTER(pba_config)]),
+    "pba_create": (C.c_int, [C.POINTER(pba_config), C.POINTER(_P)]),
+    "pba_set_frames": (C.c_int, [_P, C.c_int32, C.c_int32, C.c_int32, C.c_int32, _P, _P, _P, C.c_int32]),
+    "pba_set_points": (C.c_int, [_P, C.c_int32, C.c_int32, _P, _P, _P, _P, _P, C.c_int32]),
+    "pba_iterate": (C.c_int, [_P, C.c_int32, C.c_int32, C.POINTER(pba_iter_stats)]),
+    "pba_solve": (C.c_int, [_P, C.c_int32, C.c_double, C.POINTER(pba_result)]),
+    "pba_evaluate": (C.c_int, [_P, C.c_int32, C.POINTER(pba_iter_stats)]),
+    "pba_get_params": (C.c_int, [_P, C.c_int32, _P, _P]),
+    "pba_set_params": (C.c_int, [_P, C.c_int32, _P, _P]),
+    "pba_debug_fetch": (C.c_int, [_P, C.c_int32, _P, C.c_size_t]),
+    "pba_get_timing": (C.c_int, [_P, C.POINTER(pba_timing)]),
+    "pba_destroy": (None, [_P]),
+    "pba_last_error": (C.c_char_p, [_P]),
+    "pba_status_string": (C.c_char_p, [C.c_int]),
+}
+for _name, (_res, _args) in _sig.items():
+    _f = getattr(_lib, _name)
+    _f.restype = _res
+    _f.argtypes = _args
+    globals()[_name] = _f
+
+EXPORTED = tuple(_sig)
+
+
+def status_string(s):
+    return pba_status_string(s).decode()
+
+
+def last_error(ctx=None):
+    return pba_last_error(ctx).decode()
+
+
+def _ptr(a):
+    return a.ctypes.data_as(C.c_void_p) if a is not None else None
+
+
+def check(status, ctx=None):
+    if status != PBA_OK:
+        raise PbaError(status, last_error(ctx))
+    return status
+
+
+def default_config(**kw):
+    cfg = pba_config()
+    check(pba_config_default(C.byref(cfg)))
+    for k, v in kw.items():
+        if k == "pattern":
+            pat = np.asarray(v, np.int32).reshape(-1, 2)
+            cfg.pattern_n = pat.shape[0]
+            for i, x in enumerate(pat.reshape(-1)):
+                cfg.pattern_uv[i] = int(x)
+        else:
+            setattr(cfg, k, v)
+    return cfg
+
+
+class Solver:
+    """One context of the library (marshalling only)."""
+
+    def __init__(self, **cfg_kw):
+        self.cfg = default_config(**cfg_kw)
+        h = C.c_void_p()
+        check(pba_create(C.byref(self.cfg), C.byref(h)))
+        self.ctx = h
+        self.real = np.float64 if self.cfg.precision == PBA_FP64 else np.float32
+
+    def close(self):
+        if self.ctx:
+            pba_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _chk(self, s):
+        return check(s, self.ctx)
+
+    def set_frames(self, images, intrinsics, poses):
+        images = np.ascontiguousarray(images, np.float32)
+        self.F, self.H, self.W = images.shape
+        self._chk(pba_set_frames(self.ctx, 0, self.F, self.W, self.H, _ptr(images),
+                                 _ptr(np.ascontiguousarray(intrinsics, np.float64)),
+                                 _ptr(np.ascontiguousarray(poses, np.float64)), PBA_HOST))
+
+    def set_points(self, host_frame, host_uv, inv_depth, obs_ptr, obs_frame):
+        hf = np.ascontiguousarray(host_frame, np.int32)
+        self.N = hf.shape[0]
+        optr = np.ascontiguousarray(obs_ptr, np.int32)
+        self.O = int(optr[-1])
+        self._chk(pba_set_points(self.ctx, 0, self.N, _ptr(hf), _ptr(np.ascontiguousarray(host_uv, np.float32)),
+                                 _ptr(np.ascontiguousarray(inv_depth, np.float64)), _ptr(optr),
+                                 _ptr(np.ascontiguousarray(obs_frame, np.int32)), PBA_HOST))
+
+    def set_scene(self, scene, poses=None, inv_depth=None):
+        self.set_frames(scene.images, scene.intrinsics, scene.poses_init if poses is None else poses)
+        self.set_points(scene.host_frame, scene.host_uv, scene.inv_depth_init if inv_depth is None else inv_depth,
+                        scene.obs_ptr, scene.obs_frame)
+
+    def iterate(self, level, n_iters):
+        st = (pba_iter_stats * max(1, n_iters))()
+        self._chk(pba_iterate(self.ctx, level, n_iters, st))
+        return [st[i].as_dict() for i in range(n_iters)]
+
+    def solve(self, max_iters_per_level, conv_px=5e-3):
+        res = pba_result()
+        s = pba_solve(self.ctx, max_iters_per_level, conv_px, C.byref(res))
+        if s not in (PBA_OK, PBA_E_NOT_CONVERGED):
+            self._chk(s)
+        return res, s
+
+    def evaluate(self, level=0):
+        st = pba_iter_stats()
+        self._chk(pba_evaluate(self.ctx, level, C.byref(st)))
+        return st.as_dict()
+
+    def get_params(self):
+        poses = np.zeros((self.F, 12))
+        d = np.zeros(self.N)
+        self._chk(pba_get_params(self.ctx, 0, _ptr(poses), _ptr(d)))
+        return poses, d
+
+    def set_params(self, poses, inv_depth):
+        self._chk(pba_set_params(self.ctx, 0, _ptr(np.ascontiguousarray(poses, np.float64)),
+                                 _ptr(np.ascontiguousarray(inv_depth, np.float64))))
+
+    def fetch(self, what):
+        n6 = 6 * self.F
+        shapes = {
+            PBA_DBG_S: ((n6, n6), np.float64), PBA_DBG_B: ((n6,), np.float64),
+            PBA_DBG_OBS_REC: ((self.O, REC_STRIDE), self.real),
+            PBA_DBG_TEMPLATE: ((self.N, self.cfg.pattern_n, 4), self.real),
+            PBA_DBG_HDD: ((self.N,), np.float64), PBA_DBG_MASK: ((self.O,), np.uint8),
+            PBA_DBG_DTHETA: ((n6,), np.float64),
+        }
+        shape, dt = shapes[what]
+        out = np.zeros(shape, dt)
+        self._chk(pba_debug_fetch(self.ctx, what, _ptr(out), out.nbytes))
+        return out
+
+    def timing(self):
+        t = pba_timing()
+        self._chk(pba_get_timing(self.ctx, C.byref(t)))
+        return {k: getattr(t, k) for k, _ in t._fields_}

@@ -1,0 +1,219 @@
+"""GPU parity: the HIP library (through its C ABI) against the FP64 oracle on the
+same seeded inputs.
+
+Tolerances: FP64 library vs FP64 oracle agree to rounding (relative 1e-9 on
+iterates after 10 iterations). FP32 library vs FP64 oracle uses the bar of the
+measurement contract: poses <= 1e-5 rad and 1e-5 relative translation, inverse
+depths <= 1e-5 relative, final photometric RMSE <= 1e-4 relative.
+"""
+import numpy as np
+import pytest
+
+import scenes
+from oracle import residuals as RS
+from oracle.gn import GaussNewton, Problem
+from scenes.planar import planar
+from tests.oracle_refs import obs_records, rot_err, trans_rel_err
+
+pytestmark = pytest.mark.gpu
+
+pba = pytest.importorskip("paper_1704_06967_amd.pba")
+
+
+def make(scene, mode, precision, **kw):
+    s = pba.Solver(mode=pba.PBA_IC_PROXY if mode == "ic" else pba.PBA_FC, precision=precision,
+                   n_levels=scene.n_levels, pattern=scene.pattern, huber_k=scene.huber_k, **kw)
+    s.set_scene(scene)
+    return s
+
+
+@pytest.fixture(scope="module")
+def tiny():
+    return scenes.tiny()
+
+
+@pytest.fixture(scope="module")
+def mid_small():
+    return scenes.mid(n_per_host=300)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_template_parity(tiny, precision):
+    s = make(tiny, "ic", precision)
+    s.iterate(0, 1)
+    tm = s.fetch(pba.PBA_DBG_TEMPLATE)
+    L = Problem.from_scene(tiny).layout(0)
+    P = tiny.pattern.shape[0]
+    ok = L.host_ok.reshape(-1, P)
+    assert np.array_equal(tm[..., 3] != 0, ok)
+    tol = 1e-13 if precision == 0 else 2e-6
+    np.testing.assert_allclose(tm[..., 0][ok], L.I0.reshape(-1, P)[ok], atol=tol)
+    np.testing.assert_allclose(tm[..., 1][ok], L.g0[:, 0].reshape(-1, P)[ok], atol=tol)
+    np.testing.assert_allclose(tm[..., 2][ok], L.g0[:, 1].reshape(-1, P)[ok], atol=tol)
+
+
+def test_fc_first_iteration_blocks_fp64(tiny):
+    """FC at p(0): per-observation blocks, frozen mask, reduced system S, rhs b,
+    pose step and updated parameters."""
+    s = make(tiny, "fc", 0)
+    s.iterate(0, 1)
+    gn = GaussNewton(Problem.from_scene(tiny), "fc")
+    gn.iterate(0, 1)
+    L, last = gn.L, gn.last
+    ref = obs_records(L, last["J"], last["w"], last["r"], last["act"], tiny.huber_k)
+    rec = s.fetch(pba.PBA_DBG_OBS_REC)
+    scale = np.abs(ref).max(0) + 1e-30
+    np.testing.assert_allclose(rec[:, :38] / scale[:38], ref[:, :38] / scale[:38], atol=1e-11)
+    mask = s.fetch(pba.PBA_DBG_MASK)
+    ref_mask = np.zeros(L.n_obs, np.uint8)
+    np.bitwise_or.at(ref_mask, L.res_obs, (gn.frozen.astype(np.uint8) << L.res_pat.astype(np.uint8)))
+    assert np.array_equal(mask, ref_mask)
+    S = s.fetch(pba.PBA_DBG_S)
+    np.testing.assert_allclose(S, last["S"], rtol=1e-10, atol=1e-10 * np.abs(last["S"]).max())
+    b = s.fetch(pba.PBA_DBG_B)
+    np.testing.assert_allclose(b, last["b"], rtol=1e-9, atol=1e-11 * np.abs(last["b"]).max())
+    poses, d = s.get_params()
+    np.testing.assert_allclose(poses, gn.poses, atol=1e-11)
+    np.testing.assert_allclose(d, gn.d, rtol=1e-10)
+
+
+def test_ic_setup_system_fp64(tiny):
+    """IC: H = J^T W0 J assembled once (pose blocks, depth blocks, Schur S) and
+    g = J^T W r of the first iteration."""
+    s = make(tiny, "ic", 0)
+    s.iterate(0, 1)
+    gn = GaussNewton(Problem.from_scene(tiny), "ic")
+    gn.iterate(0, 1)
+    S = s.fetch(pba.PBA_DBG_S)
+    np.testing.assert_allclose(S, gn.red.S, rtol=1e-10, atol=1e-10 * np.abs(gn.red.S).max())
+    Hdd = s.fetch(pba.PBA_DBG_HDD)
+    np.testing.assert_allclose(Hdd, gn.red.Hdd, rtol=1e-10)
+    b = s.fetch(pba.PBA_DBG_B)
+    np.testing.assert_allclose(b, gn.last["b"], rtol=1e-9, atol=1e-11 * np.abs(gn.last["b"]).max())
+    dth = s.fetch(pba.PBA_DBG_DTHETA)
+    ref_dth = -np.linalg.solve(gn.red.S, gn.last["b"])
+    np.testing.assert_allclose(dth, ref_dth, rtol=1e-8, atol=1e-10 * np.abs(ref_dth).max())
+
+
+@pytest.mark.parametrize("mode", ["ic", "fc"])
+def test_tiny_fp64_ten_iterations(tiny, mode):
+    s = make(tiny, mode, 0)
+    st = s.iterate(0, 10)
+    poses, d = s.get_params()
+    gn = GaussNewton(Problem.from_scene(tiny), mode)
+    ost = gn.iterate(0, 10)
+    for a, o in zip(st, ost):
+        assert a["n_active"] == o["n_active"]
+        assert abs(a["energy"] - o["energy"]) <= 1e-9 * o["energy"]
+        assert abs(a["max_disp_px"] - o["max_disp_px"]) <= 1e-7 * max(1.0, o["max_disp_px"])
+    assert rot_err(poses, gn.poses).max() < 1e-9
+    assert trans_rel_err(poses, gn.poses).max() < 1e-9
+    assert np.abs(d / gn.d - 1).max() < 1e-8
+    ev = s.evaluate(0)
+    oev = gn.evaluate(0)
+    assert ev["n_active"] == oev["n_active"]
+    assert abs(ev["rmse"] / oev["rmse"] - 1) < 1e-10
+
+
+@pytest.mark.parametrize("mode", ["ic", "fc"])
+def test_mid_fp32_pyramid_parity(mid_small, mode):
+    """FP32 library vs FP64 oracle over the 3-level pyramid, 4 iterations per level."""
+    s = make(mid_small, mode, 1)
+    gn = GaussNewton(Problem.from_scene(mid_small), mode)
+    for level in (2, 1, 0):
+        s.iterate(level, 4)
+        gn.iterate(level, 4)
+    poses, d = s.get_params()
+    assert rot_err(poses, gn.poses).max() <= 1e-5
+    assert trans_rel_err(poses, gn.poses).max() <= 1e-5
+    assert np.abs(d / gn.d - 1).max() <= 1e-5
+    ev, oev = s.evaluate(0), gn.evaluate(0)
+    assert abs(ev["rmse"] / oev["rmse"] - 1) <= 1e-4
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_planar_zero_residual_at_truth(precision):
+    sc = planar(n_levels=3, n_points=50)
+    for mode in ("ic", "fc"):
+        s = make(sc, mode, precision)
+        for level in (2, 1, 0):
+            ev = s.evaluate(level)
+            assert ev["n_active"] > 0.9 * sc.n_residuals()
+            assert ev["rmse"] < (1e-7 if precision == 1 else 1e-12)
+            st = s.iterate(level, 1)
+            assert st[0]["max_step_pose"] < (1e-4 if precision == 1 else 1e-10)
+
+
+def test_edge_cases_fp64():
+    """Ragged and degenerate inputs: points without observations, a frame
+    nobody observes, a 5-pixel pattern, no pinned frame (damping only)."""
+    sc = scenes.tiny(n_points=60)
+    # drop the observations of every 7th point, and add an unobserved 5th frame
+    keep_ptr, keep_frames = [0], []
+    for n in range(sc.n_points):
+        fr = sc.obs_frame[sc.obs_ptr[n]:sc.obs_ptr[n + 1]]
+        if n % 7 == 3:
+            fr = fr[:0]
+        keep_frames.extend(fr.tolist())
+        keep_ptr.append(len(keep_frames))
+    sc.obs_ptr = np.array(keep_ptr, np.int32)
+    sc.obs_frame = np.array(keep_frames, np.int32)
+    sc.images = np.concatenate([sc.images, sc.images[-1:]], 0)
+    sc.intrinsics = np.concatenate([sc.intrinsics, sc.intrinsics[-1:]], 0)
+    sc.poses_init = np.concatenate([sc.poses_init, sc.poses_init[-1:]], 0)
+    sc.pattern = sc.pattern[:5]
+    for mode in ("ic", "fc"):
+        for pinned in (0, -1):
+            s = make(sc, mode, 0, pinned_frame=pinned, damping_rel=1e-4)
+            st = s.iterate(0, 3)
+            poses, d = s.get_params()
+            gn = GaussNewton(Problem.from_scene(sc, pinned_frame=pinned, damping_rel=1e-4), mode)
+            ost = gn.iterate(0, 3)
+            assert [a["n_active"] for a in st] == [o["n_active"] for o in ost]
+            assert rot_err(poses, gn.poses).max() < 1e-9
+            assert np.abs(d / gn.d - 1).max() < 1e-8
+            np.testing.assert_allclose(poses[4], sc.poses_init[4], atol=1e-12 if pinned == 0 else 1e-3)
+
+
+def test_empty_points():
+    sc = scenes.tiny(n_points=10)
+    s = pba.Solver(mode=pba.PBA_IC_PROXY, precision=pba.PBA_FP64)
+    s.set_frames(sc.images, sc.intrinsics, sc.poses_init)
+    s.set_points(np.zeros(0, np.int32), np.zeros((0, 2), np.float32), np.zeros(0), np.zeros(1, np.int32),
+                 np.zeros(0, np.int32))
+    st = s.iterate(0, 2)
+    assert st[-1]["n_active"] == 0
+    poses, _ = s.get_params()
+    np.testing.assert_allclose(poses, sc.poses_init, atol=1e-15)
+
+
+def test_deterministic_replay():
+    sc = scenes.tiny(n_points=200)
+    out = []
+    for _ in range(2):
+        s = make(sc, "fc", 1)
+        s.iterate(0, 3)
+        out.append(s.get_params())
+        s.close()
+    assert np.array_equal(out[0][0], out[1][0]) and np.array_equal(out[0][1], out[1][1])
+
+
+def test_solve_matches_oracle_iteration_counts(mid_small):
+    s = make(mid_small, "ic", 1)
+    res, status = s.solve(6, 5e-3)
+    gn = GaussNewton(Problem.from_scene(mid_small), "ic")
+    iters = gn.solve(6, 5e-3)
+    assert [res.iters[l] for l in range(2, -1, -1)] == iters
+    assert abs(res.final_rmse / gn.evaluate(0)["rmse"] - 1) <= 1e-4
+
+
+def test_invalid_arguments_leave_state():
+    sc = scenes.tiny(n_points=20)
+    s = make(sc, "ic", 0)
+    bad = sc.obs_frame.copy()
+    bad[0] = sc.host_frame[0]
+    with pytest.raises(pba.PbaError) as e:
+        s.set_points(sc.host_frame, sc.host_uv, sc.inv_depth_init, sc.obs_ptr, bad)
+    assert e.value.status == pba.PBA_E_INVALID
+    st = s.iterate(0, 1)  # the previous points are still set
+    assert st[0]["n_active"] > 0
