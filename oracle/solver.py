@@ -9,7 +9,7 @@ The paper assumes H invertible; it is not (the scale of the scene and, with
 several hosts, the world frame are free). Reading used: the pose rows/columns
 of one frame are replaced by the identity with a zero right-hand side, and
 both diagonal blocks are damped by damping_rel times the mean of their
-diagonal (computed before the pin). The depths are eliminated by a Schur
+diagonal (computed before the pin; damping_rel itself when that mean is 0). The depths are eliminated by a Schur
 complement; the reduced pose system is solved by Cholesky.
 """
 import numpy as np
@@ -44,6 +44,13 @@ def normal_equations(J, w, r):
     return H, np.asarray(g).reshape(-1)
 
 
+def damping_value(damping_rel, diag):
+    """damping_rel times the mean of a block's diagonal; a block whose diagonal
+    is all zero (nothing observed) is damped by damping_rel itself."""
+    m = float(np.mean(diag)) if diag.size else 0.0
+    return damping_rel * m if m > 0.0 else damping_rel
+
+
 class Reduced:
     """Damped, pinned system split into pose and depth parts, its Schur
     complement S = Hpp - Hpd Hdd^{-1} Hdp and Cholesky factor."""
@@ -53,8 +60,8 @@ class Reduced:
         Hpp = H[:n6, :n6].toarray()
         self.Hpd = H[:n6, n6:].tocsr()
         Hdd = H[n6:, n6:].diagonal().copy()
-        self.mu_p = damping_rel * np.mean(np.diag(Hpp))
-        self.mu_d = damping_rel * np.mean(Hdd) if Hdd.size else 0.0
+        self.mu_p = damping_value(damping_rel, np.diag(Hpp))
+        self.mu_d = damping_value(damping_rel, Hdd)
         Hpp = Hpp + self.mu_p * np.eye(n6)
         self.Hdd = Hdd + self.mu_d
         self.Hpp = Hpp
@@ -89,8 +96,8 @@ def dense_solve(H, g, n_frames, damping_rel, pinned_frame):
     (used to check the Schur path on small problems)."""
     n6 = 6 * n_frames
     Hd = H.toarray() if sp.issparse(H) else np.array(H)
-    mu_p = damping_rel * np.mean(np.diag(Hd)[:n6])
-    mu_d = damping_rel * np.mean(np.diag(Hd)[n6:])
+    mu_p = damping_value(damping_rel, np.diag(Hd)[:n6])
+    mu_d = damping_value(damping_rel, np.diag(Hd)[n6:])
     Hd[np.arange(n6), np.arange(n6)] += mu_p
     Hd[np.arange(n6, Hd.shape[0]), np.arange(n6, Hd.shape[0])] += mu_d
     g = g.copy()

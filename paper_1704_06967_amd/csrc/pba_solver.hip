@@ -40,7 +40,7 @@ __global__ void k_fill(double *__restrict__ p, size_t n, double v) {
 }
 
 // Damping of the pose and depth diagonals: mu = damping_rel x mean diagonal of
-// the undamped blocks.
+// the undamped blocks (damping_rel when that mean is zero).
 __global__ __launch_bounds__(256) void k_mu(int Pn, int F, int N, int hdd_blocks, double damping,
                                              const double *__restrict__ pairH, const double *__restrict__ geo,
                                              const double *__restrict__ hdd_part, double *__restrict__ mu) {
@@ -61,8 +61,10 @@ __global__ __launch_bounds__(256) void k_mu(int Pn, int F, int N, int hdd_blocks
         for (int k = 0; k < (int)(blockDim.x >> 6); ++k) tot += lds[k];
         double hs = 0.0;
         for (int k = 0; k < hdd_blocks; ++k) hs += hdd_part[k];
-        mu[0] = damping * tot / (6.0 * F);
-        mu[1] = N > 0 ? damping * hs / N : 0.0;
+        // a block whose mean diagonal is zero (nothing observed) is damped by damping itself
+        const double mp = tot / (6.0 * F), md = N > 0 ? hs / N : 0.0;
+        mu[0] = mp > 0.0 ? damping * mp : damping;
+        mu[1] = md > 0.0 ? damping * md : damping;
     }
 }
 
