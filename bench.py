@@ -1,0 +1,264 @@
+#!/usr/bin/env python3
+"""Throughput of proxy-template inverse-compositional photometric bundle
+adjustment on one MI355X, against forward-compositional Gauss-Newton on the
+same GPU and the FP64 CPU oracle.
+
+Workload: the mid problem - 30 frames 640x480 (float32) on a 360-degree orbit
+around a seeded value-noise ellipsoid (axes 1.0/0.8/0.6), 3-level pyramid,
+5 host frames x 4000 points, 8-pixel patches, Huber k = 9/255, image noise
+sigma 2/255; residuals and Jacobians in FP32, reductions, Schur complement and
+Cholesky in FP64.
+
+One step = one coarse-to-fine solve (3 levels, at most --max-iters Gauss-Newton
+iterations per level, convergence at 5e-3 px) from the same perturbed start,
+inputs resident on the GPU. The library's calls are synchronous on its own
+stream, so wall-clock time around them brackets the device work.
+
+Prints one JSON line.
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "GN iters/s & residuals/s, IC-proxy vs FC on same GPU at equal final photo-RMSE"
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def level_pixels(scene, level):
+    """Level-`level` target pixels of every residual at the scene's starting
+    parameters (host patch pixel -> warp -> projection), for byte counting."""
+    P = scene.pattern.shape[0]
+    N = scene.n_points
+    obs_point = np.repeat(np.arange(N), np.diff(scene.obs_ptr))
+    host = scene.host_frame[obs_point]
+    tgt = scene.obs_frame
+    s = 2.0 ** level
+    K = scene.intrinsics
+    uv = (scene.host_uv[obs_point].astype(float) + 0.5) / s - 0.5
+    pu = uv[:, None, 0] + scene.pattern[None, :, 0]
+    pv = uv[:, None, 1] + scene.pattern[None, :, 1]
+    Kh, Kt = K[host] / np.array([s, s, 1, 1]), K[tgt] / np.array([s, s, 1, 1])
+    Kh[:, 2:] = (K[host, 2:] + 0.5) / s - 0.5
+    Kt[:, 2:] = (K[tgt, 2:] + 0.5) / s - 0.5
+    x = (pu - Kh[:, None, 2]) / Kh[:, None, 0]
+    y = (pv - Kh[:, None, 3]) / Kh[:, None, 1]
+    Rp = scene.poses_init[:, :9].reshape(-1, 3, 3)
+    tp = scene.poses_init[:, 9:]
+    R = Rp[tgt] @ np.swapaxes(Rp[host], 1, 2)
+    t = tp[tgt] - np.einsum("oij,oj->oi", R, tp[host])
+    d = scene.inv_depth_init[obs_point]
+    v = (R[:, None, :, 0] * x[..., None] + R[:, None, :, 1] * y[..., None] + R[:, None, :, 2]
+         + d[:, None, None] * t[:, None, :])
+    qu = Kt[:, None, 0] * v[..., 0] / v[..., 2] + Kt[:, None, 2]
+    qv = Kt[:, None, 1] * v[..., 1] / v[..., 2] + Kt[:, None, 3]
+    return tgt, qu, qv
+
+
+def ic_residual_bytes(scene, level=0, real=4):
+    """Algorithmic bytes of one launch of the IC residual kernel at `level`:
+    per observation its point and pair index, mask byte and the 10-value record
+    it writes; per observed point its pixel, two depths and the 8 template
+    records (I0, gradient, usable); per pair two relative poses; the target
+    texels touched by the bilinear 2x2 footprints, each counted once."""
+    O = scene.n_obs
+    P = scene.pattern.shape[0]
+    n_obs_pts = int(np.count_nonzero(np.diff(scene.obs_ptr)))
+    host = scene.host_frame[np.repeat(np.arange(scene.n_points), np.diff(scene.obs_ptr))]
+    n_pairs = len(set(zip(host.tolist(), scene.obs_frame.tolist())))
+    F, H, W = scene.images.shape
+    Wl, Hl = W >> level, H >> level
+    tgt, qu, qv = level_pixels(scene, level)
+    ok = (qu >= 1) & (qu <= Wl - 3) & (qv >= 1) & (qv <= Hl - 3)
+    j0 = np.floor(qu[ok]).astype(np.int64)
+    i0 = np.floor(qv[ok]).astype(np.int64)
+    f = np.broadcast_to(tgt[:, None], qu.shape)[ok].astype(np.int64)
+    base = (f * Hl + i0) * Wl + j0
+    texels = np.unique(np.concatenate([base, base + 1, base + Wl, base + Wl + 1])).size
+    reads = O * (4 + 4 + 1) + n_obs_pts * (8 + 8 + 8 + P * 4 * real) + n_pairs * 2 * 12 * real + texels * real
+    writes = O * 10 * real
+    return {"bytes": int(reads + writes), "reads": int(reads), "writes": int(writes), "unique_texels": int(texels),
+            "observations": O, "residual_slots": O * 8}
+
+
+def run_steps(solver, poses0, d0, steps, max_iters, conv_px):
+    times, iters, active, results = [], 0, 0, []
+    for _ in range(steps):
+        t0 = time.perf_counter()
+        solver.set_params(poses0, d0)
+        res, _ = solver.solve(max_iters, conv_px)
+        times.append(time.perf_counter() - t0)
+        iters += res.total_iters
+        active += res.active_residuals
+        results.append(res.as_dict())
+    return times, iters, active, results
+
+
+def trace(solver, poses0, d0, n_levels, max_iters, conv_px):
+    """Per-iteration level-0 photometric RMSE against cumulative solver time
+    (the evaluation after each iteration is not timed)."""
+    from paper_1704_06967_amd import pba  # noqa: F401
+
+    solver.set_params(poses0, d0)
+    t, pts = 0.0, [(0.0, solver.evaluate(0)["rmse"])]
+    for level in reversed(range(n_levels)):
+        for _ in range(max_iters):
+            t0 = time.perf_counter()
+            st = solver.iterate(level, 1)[0]
+            t += time.perf_counter() - t0
+            pts.append((t, solver.evaluate(0)["rmse"]))
+            if st["max_disp_px"] < conv_px:
+                break
+    return pts
+
+
+def time_to(pts, target):
+    for t, r in pts:
+        if r <= target:
+            return t
+    return math.inf
+
+
+def cpu_baseline(scene, n_iters=10):
+    """The FP64 oracle on a bounded sample of the same workload: level 0 of the
+    mid problem, IC setup plus n_iters iterations, one BLAS thread."""
+    from threadpoolctl import threadpool_limits
+
+    from oracle.gn import GaussNewton, Problem
+
+    with threadpool_limits(1):
+        P = Problem.from_scene(scene)
+        P.layout(0)
+        t0 = time.perf_counter()
+        gn = GaussNewton(P, "ic")
+        gn.iterate(0, n_iters)
+        dt = time.perf_counter() - t0
+    return {"value": n_iters / dt, "unit": "GN iters/s", "cores": 1, "kind": "oracle",
+            "sample": f"mid workload, level 0 only: IC setup + {n_iters} iterations (960k residuals each), "
+                      f"{dt:.1f} s on 1 thread",
+            "seconds": dt}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--max-iters", type=int, default=10)
+    ap.add_argument("--conv-px", type=float, default=5e-3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-trace", action="store_true")
+    ap.add_argument("--fc-steps", type=int, default=None, help="FC solves to time (default: --steps)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}): the solver has no multi-GPU path; "
+              "see DESIGN.md for how it would shard.", file=sys.stderr)
+        sys.exit(2)
+
+    import scenes
+    from paper_1704_06967_amd import pba
+
+    t0 = time.perf_counter()
+    scene = scenes.mid()
+    log(f"scene mid: {scene.n_points} points, {scene.n_obs} observations, {scene.n_residuals()} residuals "
+        f"({time.perf_counter() - t0:.1f} s)")
+    kw = dict(precision=pba.PBA_FP32, n_levels=scene.n_levels, pattern=scene.pattern, huber_k=scene.huber_k,
+              flags=pba.PBA_FLAG_TIMING)
+    ic = pba.Solver(mode=pba.PBA_IC_PROXY, **kw)
+    fc = pba.Solver(mode=pba.PBA_FC, **kw)
+    ic.set_scene(scene)
+    fc.set_scene(scene)
+    p0, d0 = scene.poses_init, scene.inv_depth_init
+
+    for _ in range(args.warmup):
+        for s in (ic, fc):
+            s.set_params(p0, d0)
+            s.solve(args.max_iters, args.conv_px)
+    ic.timing()
+    fc.timing()
+    log("warmup done")
+
+    ic_t, ic_iters, ic_active, ic_res = run_steps(ic, p0, d0, args.steps, args.max_iters, args.conv_px)
+    ic_tm = ic.timing()
+    log(f"IC: {args.steps} solves, {np.mean(ic_t) * 1e3:.3f} ms each")
+    fc_steps = args.fc_steps or args.steps
+    fc_t, fc_iters, fc_active, fc_res = run_steps(fc, p0, d0, fc_steps, args.max_iters, args.conv_px)
+    fc_tm = fc.timing()
+    log(f"FC: {fc_steps} solves, {np.mean(fc_t) * 1e3:.3f} ms each")
+
+    total = float(np.sum(ic_t))
+    value = ic_iters / total
+    ic_res_s = ic_active / total
+    fc_total = float(np.sum(fc_t))
+
+    # roofline of the dominant kernel: the IC residual / J^T W r kernel, level 0
+    nb = ic_residual_bytes(scene, 0, 4)
+    launches0 = ic_tm["residual_launches"][0]
+    avg_ms = ic_tm["residual_ms"][0] / max(1, launches0)
+    achieved = nb["bytes"] / (avg_ms * 1e-3) / 1e9 if launches0 else 0.0
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "kernel": "k_ic_residual<float> (level 0)", "avg_launch_us": round(avg_ms * 1e3, 3),
+                "launches": int(launches0), "algorithmic_bytes_per_launch": nb["bytes"],
+                "bytes_detail": nb}
+
+    line = {
+        "metric": METRIC,
+        "value": round(value, 2),
+        "unit": "GN iters/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(total / args.steps * 1e3, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "mid: 30 frames 640x480 f32, 360-deg orbit of a value-noise ellipsoid, 3-level "
+                               "pyramid, 5 hosts x 4000 points, 8-px patches, Huber 9/255, noise 2/255; "
+                               "FP32 residuals/Jacobians, FP64 reductions/Schur/Cholesky",
+                   "points": scene.n_points, "observations": scene.n_obs, "residuals_per_iter": scene.n_residuals(),
+                   "frames": scene.n_frames, "reduced_system": 6 * scene.n_frames, "max_iters_per_level":
+                       args.max_iters, "conv_px": args.conv_px, "mode": "IC-proxy (value), FC (comparison)"},
+        "residuals_per_s": round(ic_res_s, 1),
+        "ic": {"ms_per_solve": round(np.mean(ic_t) * 1e3, 4), "ms_per_solve_p50": round(np.median(ic_t) * 1e3, 4),
+               "iters_per_solve": ic_res[-1]["iters"], "gn_iters_per_s": round(value, 2),
+               "residuals_per_s": round(ic_res_s, 1), "final_rmse": ic_res[-1]["final_rmse"]},
+        "fc": {"ms_per_solve": round(np.mean(fc_t) * 1e3, 4), "iters_per_solve": fc_res[-1]["iters"],
+               "gn_iters_per_s": round(fc_iters / fc_total, 2), "residuals_per_s": round(fc_active / fc_total, 1),
+               "final_rmse": fc_res[-1]["final_rmse"],
+               "linearize_avg_us_level0": round(fc_tm["residual_ms"][0] / max(1, fc_tm["residual_launches"][0])
+                                                * 1e3, 3)},
+        "ic_speedup_per_solve": round(np.mean(fc_t) / np.mean(ic_t), 3),
+        "roofline": roofline,
+    }
+    if not args.no_trace:
+        tr_ic = trace(ic, p0, d0, scene.n_levels, args.max_iters, args.conv_px)
+        tr_fc = trace(fc, p0, d0, scene.n_levels, args.max_iters, args.conv_px)
+        r_star = max(tr_ic[-1][1], tr_fc[-1][1])
+        t_ic, t_fc = time_to(tr_ic, r_star * (1 + 1e-3)), time_to(tr_fc, r_star * (1 + 1e-3))
+        line["equal_rmse"] = {"r_star": r_star, "ic_ms": round(t_ic * 1e3, 3), "fc_ms": round(t_fc * 1e3, 3),
+                              "ic_speedup": round(t_fc / t_ic, 3) if t_ic > 0 and math.isfinite(t_fc) else None,
+                              "note": "per-iteration synchronous calls; level-0 RMSE after each iteration"}
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle) ...")
+        line["cpu_baseline"] = cpu_baseline(scene)
+    ic.close()
+    fc.close()
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

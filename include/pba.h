@@ -114,12 +114,16 @@ typedef struct {
     double final_energy;           /* at the returned parameters, level 0, fresh usable set */
     double final_rmse;
     int64_t final_active;
+    int64_t active_residuals;      /* sum over the iterations that ran of their n_active */
 } pba_result;
 
 typedef struct {
-    int64_t residual_launches;     /* launches of the per-iteration residual kernel */
-    double residual_ms;            /* their summed duration (HIP events; needs PBA_FLAG_TIMING) */
-    int64_t residuals_processed;   /* residual slots those launches covered */
+    /* per pyramid level, launches of the per-iteration residual kernel (IC: the
+       residual / J^T W r kernel; FC: the linearization kernel) that did work */
+    int64_t residual_launches[PBA_MAX_LEVELS];
+    double residual_ms[PBA_MAX_LEVELS];         /* their summed duration (HIP events on the
+                                                   context's stream; needs PBA_FLAG_TIMING) */
+    int64_t residuals_processed[PBA_MAX_LEVELS];/* residual slots those launches covered */
 } pba_timing;
 
 /* Debug / verification buffers for pba_debug_fetch (element type in brackets;

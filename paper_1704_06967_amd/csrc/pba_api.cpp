@@ -17,10 +17,6 @@
 
 #include "pba_internal.hpp"
 
-namespace pba {
-void launch_fill(hipStream_t s, double *p, size_t n, double v);
-}
-
 using namespace pba;
 
 struct pba_ctx {
@@ -52,7 +48,7 @@ pba_status fail(Ctx *c, pba_status s, const std::string &msg) {
 template <typename P>
 hipError_t dalloc(P *&p, size_t bytes) {
     if (p) {
-        hipFree((void *)p);
+        (void)hipFree((void *)p);
         p = nullptr;
     }
     if (bytes == 0) bytes = 8;
@@ -61,7 +57,7 @@ hipError_t dalloc(P *&p, size_t bytes) {
 
 template <typename P>
 void dfree(P *&p) {
-    if (p) hipFree((void *)p);
+    if (p) (void)hipFree((void *)p);
     p = nullptr;
 }
 
@@ -128,6 +124,8 @@ void release_frames(Ctx &c) {
                        &c.d_mu})
         dfree(*p);
     dfree(c.d_flag);
+    dfree(c.d_gate);
+    dfree(c.d_count);
     c.stats_cap = 0;
     c.have_frames = false;
     c.F = 0;
@@ -336,6 +334,13 @@ pba_status one_iteration(Ctx &c, int level, double *stat, hipEvent_t ev0, hipEve
     return PBA_OK;
 }
 
+pba_status open_gate(Ctx &c) {
+    const int one = 1;
+    HIPCHK(hipMemcpyAsync(c.d_gate, &one, sizeof(int), hipMemcpyHostToDevice, c.stream));
+    HIPCHK(hipMemsetAsync(c.d_count, 0, sizeof(int), c.stream));
+    return PBA_OK;
+}
+
 pba_status ensure_stats(Ctx &c, int n) {
     if (n <= c.stats_cap) return PBA_OK;
     int cap = std::max(n, 64);
@@ -353,31 +358,47 @@ pba_status ensure_events(Ctx &c, size_t n) {
     return PBA_OK;
 }
 
-pba_status run_iterations(Ctx &c, int level, int n_iters, pba_iter_stats *out) {
+// Enqueue n_iters iterations without host synchronization. With conv_px >= 0
+// the device closes the gate after the first iteration whose largest
+// point-centre displacement is below conv_px and the remaining launches return
+// at once. Returns the number of iterations that ran in *ran.
+pba_status run_iterations(Ctx &c, int level, int n_iters, pba_iter_stats *out, double conv_px = -1.0,
+                          int *ran = nullptr) {
     pba_status st;
     if ((st = ensure_stats(c, n_iters)) != PBA_OK) return st;
     const bool timing = (c.cfg.flags & PBA_FLAG_TIMING) != 0;
     if (timing && (st = ensure_events(c, 2 * (size_t)n_iters)) != PBA_OK) return st;
     HIPCHK(hipMemsetAsync(c.d_flag, 0, sizeof(int), c.stream));
+    if ((st = open_gate(c)) != PBA_OK) return st;
+    const int it0 = c.iters_in_level;
+    const bool flip0 = c.flip;
     for (int k = 0; k < n_iters; ++k) {
         hipEvent_t e0 = timing ? c.ev_pool[2 * k] : nullptr, e1 = timing ? c.ev_pool[2 * k + 1] : nullptr;
         double *stat = c.d_stats + (size_t)k * ST_STRIDE;
         st = is_fp64(c) ? one_iteration<double>(c, level, stat, e0, e1) : one_iteration<float>(c, level, stat, e0, e1);
         if (st != PBA_OK) return st;
+        if (conv_px >= 0.0) launch_conv(c.stream, c, stat, conv_px);
     }
     std::vector<double> hs((size_t)n_iters * ST_STRIDE);
-    int flag = 0;
+    int flag = 0, count = n_iters;
     if (n_iters > 0)
         HIPCHK(hipMemcpyAsync(hs.data(), c.d_stats, hs.size() * sizeof(double), hipMemcpyDeviceToHost, c.stream));
     HIPCHK(hipMemcpyAsync(&flag, c.d_flag, sizeof(int), hipMemcpyDeviceToHost, c.stream));
+    if (conv_px >= 0.0) HIPCHK(hipMemcpyAsync(&count, c.d_count, sizeof(int), hipMemcpyDeviceToHost, c.stream));
     HIPCHK(hipStreamSynchronize(c.stream));
+    HIPCHK(hipGetLastError());
+    // host view of the double buffers follows the iterations that actually ran
+    c.iters_in_level = it0 + count;
+    c.flip = (count % 2 == 1) ? !flip0 : flip0;
+    n_iters = count;
+    if (ran) *ran = count;
     if (timing) {
         for (int k = 0; k < n_iters; ++k) {
             float ms = 0.f;
             HIPCHK(hipEventElapsedTime(&ms, c.ev_pool[2 * k], c.ev_pool[2 * k + 1]));
-            c.t_ms += ms;
-            c.t_launches++;
-            c.t_res += (int64_t)c.O * LANES_PER_OBS;
+            c.t_ms[level] += ms;
+            c.t_launches[level]++;
+            c.t_res[level] += (int64_t)c.O * LANES_PER_OBS;
         }
     }
     if (out) {
@@ -385,7 +406,7 @@ pba_status run_iterations(Ctx &c, int level, int n_iters, pba_iter_stats *out) {
             const double *h = hs.data() + (size_t)k * ST_STRIDE;
             pba_iter_stats &o = out[k];
             o.level = level;
-            o.iter = c.iters_in_level - n_iters + k;
+            o.iter = it0 + k;
             o.n_active = (int64_t)std::llround(h[ST_CNT]);
             o.energy = h[ST_E];
             o.sq = h[ST_SQ];
@@ -401,6 +422,8 @@ pba_status run_iterations(Ctx &c, int level, int n_iters, pba_iter_stats *out) {
 
 pba_status do_start_level(Ctx &c, int level) {
     HIPCHK(hipMemsetAsync(c.d_flag, 0, sizeof(int), c.stream));
+    pba_status st0 = open_gate(c);
+    if (st0 != PBA_OK) return st0;
     pba_status st = is_fp64(c) ? start_level<double>(c, level) : start_level<float>(c, level);
     if (st != PBA_OK) return st;
     if (c.cfg.mode == PBA_IC_PROXY) {
@@ -579,6 +602,8 @@ pba_status pba_set_frames(pba_ctx *ctx, int32_t window, int32_t n_frames, int32_
     HIPCHK(dalloc(c.d_dtheta, n6 * sizeof(double)));
     HIPCHK(dalloc(c.d_mu, 2 * sizeof(double)));
     HIPCHK(dalloc(c.d_flag, sizeof(int)));
+    HIPCHK(dalloc(c.d_gate, sizeof(int)));
+    HIPCHK(dalloc(c.d_count, sizeof(int)));
     HIPCHK(hipMemsetAsync(c.d_flag, 0, sizeof(int), c.stream));
     HIPCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize(c.stream));
@@ -690,7 +715,7 @@ pba_status pba_set_points(pba_ctx *ctx, int32_t window, int32_t n_points, const 
         HIPCHK(dalloc(c.lv[l].tmpl, (size_t)n_points * c.P * 4 * rs));
         c.lv[l].tmpl_valid = false;
     }
-    if (c.hdd_blocks == 0) launch_fill(c.stream, c.d_hdd_part, 1, 0.0);
+    if (c.hdd_blocks == 0) launch_fill(c.stream, c.d_hdd_part, 1, 0.0, nullptr);
     HIPCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize(c.stream));
     c.have_points = true;
@@ -733,7 +758,7 @@ pba_status pba_evaluate(pba_ctx *ctx, int32_t level, pba_iter_stats *out) {
     if (c.O > 0)
         launch_sum_stats(s, c, c.d_rec, is_fp64(c), tot);
     else
-        launch_fill(s, tot, 3, 0.0);
+        launch_fill(s, tot, 3, 0.0, nullptr);
     double h[3];
     HIPCHK(hipMemcpyAsync(h, tot, sizeof(h), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
@@ -758,17 +783,11 @@ pba_status pba_solve(pba_ctx *ctx, int32_t max_iters_per_level, double conv_px, 
     pba_status st;
     for (int level = c.cfg.n_levels - 1; level >= 0; --level) {
         if ((st = do_start_level(c, level)) != PBA_OK) return st;
+        std::vector<pba_iter_stats> its(max_iters_per_level);
         int k = 0;
-        bool conv = false;
-        while (k < max_iters_per_level) {
-            pba_iter_stats it;
-            if ((st = run_iterations(c, level, 1, &it)) != PBA_OK) return st;
-            ++k;
-            if (it.max_disp_px < conv_px) {
-                conv = true;
-                break;
-            }
-        }
+        if ((st = run_iterations(c, level, max_iters_per_level, its.data(), conv_px, &k)) != PBA_OK) return st;
+        const bool conv = k > 0 && its[k - 1].max_disp_px < conv_px;
+        for (int i = 0; i < k; ++i) res.active_residuals += its[i].n_active;
         res.iters[level] = k;
         res.total_iters += k;
         if (level == 0) res.converged = conv ? 1 : 0;
@@ -849,12 +868,14 @@ pba_status pba_get_timing(pba_ctx *ctx, pba_timing *out) {
     if (!ctx) return fail(nullptr, PBA_E_INVALID, "ctx is NULL");
     Ctx &c = ctx->c;
     if (!out) return fail(&c, PBA_E_INVALID, "out is NULL");
-    out->residual_launches = c.t_launches;
-    out->residual_ms = c.t_ms;
-    out->residuals_processed = c.t_res;
-    c.t_launches = 0;
-    c.t_ms = 0.0;
-    c.t_res = 0;
+    for (int l = 0; l < PBA_MAX_LEVELS; ++l) {
+        out->residual_launches[l] = c.t_launches[l];
+        out->residual_ms[l] = c.t_ms[l];
+        out->residuals_processed[l] = c.t_res[l];
+        c.t_launches[l] = 0;
+        c.t_ms[l] = 0.0;
+        c.t_res[l] = 0;
+    }
     return PBA_OK;
 }
 

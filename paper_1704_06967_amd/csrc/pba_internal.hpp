@@ -121,6 +121,8 @@ struct Ctx {
     double *d_stats = nullptr;                         // [cap][ST_STRIDE]
     int stats_cap = 0;
     int *d_flag = nullptr;                             // device error flag (non-SPD)
+    int *d_gate = nullptr;                             // 1 while the current solve level runs
+    int *d_count = nullptr;                            // iterations run in the current level
     int hdd_blocks = 0;
 
     // current double-buffer orientation
@@ -128,8 +130,8 @@ struct Ctx {
 
     // timing
     std::vector<hipEvent_t> ev_pool;
-    int64_t t_launches = 0, t_res = 0;
-    double t_ms = 0.0;
+    int64_t t_launches[PBA_MAX_LEVELS] = {0, 0, 0, 0}, t_res[PBA_MAX_LEVELS] = {0, 0, 0, 0};
+    double t_ms[PBA_MAX_LEVELS] = {0.0, 0.0, 0.0, 0.0};
 };
 
 // ---- kernel launchers (pba_kernels.hip); T selects float or double.
@@ -157,5 +159,7 @@ void launch_ic_factor(hipStream_t s, Ctx &c);
 void launch_solve(hipStream_t s, Ctx &c, const double *geo_lin, double *geo_next, void *rel_next,
                   bool rel_double, double *stat);
 void launch_sum_stats(hipStream_t s, Ctx &c, const void *rec, bool rec_double, double *out3);
+void launch_conv(hipStream_t s, Ctx &c, const double *stat, double conv_px);
+void launch_fill(hipStream_t s, double *p, size_t n, double v, const int *gate);
 
 }  // namespace pba

@@ -110,6 +110,7 @@ struct ResArgs {
     const double *depth, *depth0;
     uint8_t *mask;
     T *rec;
+    const int *gate;     // device flag: 0 = the solve has converged, skip the work
 };
 
 // Normalized template coordinates of patch pixel j of point n (host intrinsics).
@@ -127,6 +128,7 @@ __device__ __forceinline__ void template_xy(const ResArgs<T> &a, int n, int j, c
 // Writes the 38-value record of its observation (lane j == 0).
 template <typename T, bool IC>
 __global__ __launch_bounds__(BLOCK) void k_linearize(ResArgs<T> a, int write_mask) {
+    if (*a.gate == 0) return;
     const int gid = blockIdx.x * BLOCK + threadIdx.x;
     const int o = gid >> 3, j = gid & 7;
     T J[7] = {0, 0, 0, 0, 0, 0, 0};
@@ -198,6 +200,7 @@ __global__ __launch_bounds__(BLOCK) void k_linearize(ResArgs<T> a, int write_mas
 // g = J^T W r with the constant proxy Jacobian (Sec. 3.5 steps 1-2).
 template <typename T>
 __global__ __launch_bounds__(BLOCK) void k_ic_residual(ResArgs<T> a) {
+    if (*a.gate == 0) return;
     const int gid = blockIdx.x * BLOCK + threadIdx.x;
     const int o = gid >> 3, j = gid & 7;
     T c[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
@@ -317,8 +320,9 @@ template <typename T>
 __global__ __launch_bounds__(256) void k_point_reduce(int N, const int *__restrict__ obs_ptr,
                                                       const T *__restrict__ rec, double *__restrict__ Hdd,
                                                       double *__restrict__ gd, double *__restrict__ part,
-                                                      int with_hdd) {
+                                                      int with_hdd, const int *__restrict__ gate) {
     __shared__ double lds[16];
+    if (*gate == 0) return;
     const int n = blockIdx.x * blockDim.x + threadIdx.x;
     double hs = 0.0, gs = 0.0;
     if (n < N) {
@@ -341,8 +345,10 @@ __global__ __launch_bounds__(256) void k_point_reduce(int N, const int *__restri
 template <typename T>
 __global__ __launch_bounds__(256) void k_pair_reduce_H(const int *__restrict__ pair_obs_ptr,
                                                        const int *__restrict__ pair_obs_idx,
-                                                       const T *__restrict__ rec, double *__restrict__ pairH) {
+                                                       const T *__restrict__ rec, double *__restrict__ pairH,
+                                                       const int *__restrict__ gate) {
     __shared__ double lds[21 * 16];
+    if (*gate == 0) return;
     const int p = blockIdx.x;
     double v[21];
     for (int k = 0; k < 21; ++k) v[k] = 0.0;
@@ -362,8 +368,9 @@ __global__ __launch_bounds__(256) void k_pair_reduce_y(const int *__restrict__ p
                                                        const int *__restrict__ pair_obs_idx,
                                                        const int *__restrict__ obs_point, const T *__restrict__ rec,
                                                        const double *__restrict__ Hdd, const double *__restrict__ gd,
-                                                       double *__restrict__ pairY) {
+                                                       double *__restrict__ pairY, const int *__restrict__ gate) {
     __shared__ double lds[9 * 16];
+    if (*gate == 0) return;
     const int p = blockIdx.x;
     double v[9];
     for (int k = 0; k < 9; ++k) v[k] = 0.0;
@@ -419,8 +426,10 @@ __global__ __launch_bounds__(256) void k_depth_update(int N, int ic, const int *
                                                       const double *__restrict__ dth_rel,
                                                       const double *__restrict__ geo_old,
                                                       const double *__restrict__ geo_new, double *__restrict__ depth,
-                                                      const double *__restrict__ depth0, double *__restrict__ stat) {
+                                                      const double *__restrict__ depth0, double *__restrict__ stat,
+                                                      const int *__restrict__ gate, const int *__restrict__ flag) {
     __shared__ double red[2][4];
+    if (*gate == 0 || *flag) return;
     const int n = blockIdx.x * blockDim.x + threadIdx.x;
     double mdisp = 0.0, mstep = 0.0;
     if (n < N) {
@@ -508,6 +517,7 @@ static ResArgs<T> res_args(Ctx &c, int level, const T *rel_cur) {
     a.depth0 = c.d_depth0;
     a.mask = c.d_mask;
     a.rec = (T *)c.d_rec;
+    a.gate = c.d_gate;
     return a;
 }
 
@@ -584,7 +594,7 @@ template <typename T>
 void Launch<T>::point_reduce(hipStream_t s, Ctx &c, bool with_hdd) {
     if (c.N == 0) return;
     k_point_reduce<T><<<c.hdd_blocks, 256, 0, s>>>(c.N, c.d_obs_ptr, (const T *)c.d_rec, c.d_Hdd, c.d_gd,
-                                                   c.d_hdd_part, with_hdd ? 1 : 0);
+                                                   c.d_hdd_part, with_hdd ? 1 : 0, c.d_gate);
     CHECK_LAUNCH();
 }
 
@@ -592,7 +602,7 @@ template <typename T>
 void Launch<T>::pair_reduce_H(hipStream_t s, Ctx &c) {
     if (c.st.n_pairs == 0) return;
     k_pair_reduce_H<T><<<c.st.n_pairs, 256, 0, s>>>(c.d_pair_obs_ptr, c.d_pair_obs_idx, (const T *)c.d_rec,
-                                                    c.d_pairH);
+                                                    c.d_pairH, c.d_gate);
     CHECK_LAUNCH();
 }
 
@@ -600,7 +610,7 @@ template <typename T>
 void Launch<T>::pair_reduce_y(hipStream_t s, Ctx &c) {
     if (c.st.n_pairs == 0) return;
     k_pair_reduce_y<T><<<c.st.n_pairs, 256, 0, s>>>(c.d_pair_obs_ptr, c.d_pair_obs_idx, c.d_obs_point,
-                                                    (const T *)c.d_rec, c.d_Hdd, c.d_gd, c.d_pairY);
+                                                    (const T *)c.d_rec, c.d_Hdd, c.d_gd, c.d_pairY, c.d_gate);
     CHECK_LAUNCH();
 }
 
@@ -610,7 +620,26 @@ void Launch<T>::depth_update(hipStream_t s, Ctx &c, const double *geo_old, const
     k_depth_update<T><<<nblk(c.N, 256), 256, 0, s>>>(
         c.N, c.cfg.mode == PBA_IC_PROXY ? 1 : 0, c.d_obs_ptr, c.d_obs_pair, c.d_host_frame, c.d_host_uv, c.d_K0,
         c.d_pair_target, (const T *)c.d_rec, c.d_Hdd, c.d_gd, c.d_dth_rel, geo_old, geo_new, c.d_depth,
-        c.d_depth0, stat);
+        c.d_depth0, stat, c.d_gate, c.d_flag);
+    CHECK_LAUNCH();
+}
+
+// Convergence test of the coarse-to-fine solve (Sec. 4.1): after an iteration
+// that ran, count it and close the gate once the largest point-centre
+// displacement is below conv_px; later iterations of the level are skipped.
+__global__ void k_conv(const double *__restrict__ stat, double conv_px, int *__restrict__ gate,
+                       int *__restrict__ count, const int *__restrict__ flag) {
+    if (*gate == 0) return;
+    if (*flag) {
+        *gate = 0;
+        return;
+    }
+    *count += 1;
+    if (stat[ST_DISP] < conv_px) *gate = 0;
+}
+
+void launch_conv(hipStream_t s, Ctx &c, const double *stat, double conv_px) {
+    k_conv<<<1, 1, 0, s>>>(stat, conv_px, c.d_gate, c.d_count, c.d_flag);
     CHECK_LAUNCH();
 }
 

@@ -34,7 +34,8 @@ __device__ __forceinline__ double xthy(const double *X, const double *H21, const
     return s;
 }
 
-__global__ void k_fill(double *__restrict__ p, size_t n, double v) {
+__global__ void k_fill(double *__restrict__ p, size_t n, double v, const int *__restrict__ gate) {
+    if (gate && *gate == 0) return;
     size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) p[i] = v;
 }
@@ -43,8 +44,10 @@ __global__ void k_fill(double *__restrict__ p, size_t n, double v) {
 // the undamped blocks (damping_rel when that mean is zero).
 __global__ __launch_bounds__(256) void k_mu(int Pn, int F, int N, int hdd_blocks, double damping,
                                              const double *__restrict__ pairH, const double *__restrict__ geo,
-                                             const double *__restrict__ hdd_part, double *__restrict__ mu) {
+                                             const double *__restrict__ hdd_part, double *__restrict__ mu,
+                                             const int *__restrict__ gate) {
     __shared__ double lds[16];
+    if (*gate == 0) return;
     double s = 0.0;
     for (int e = threadIdx.x; e < Pn * 6; e += blockDim.x) {
         const int p = e / 6, r = e % 6;
@@ -68,7 +71,9 @@ __global__ __launch_bounds__(256) void k_mu(int Pn, int F, int N, int hdd_blocks
     }
 }
 
-__global__ void k_damp_hdd(int N, double *__restrict__ Hdd, const double *__restrict__ mu) {
+__global__ void k_damp_hdd(int N, double *__restrict__ Hdd, const double *__restrict__ mu,
+                           const int *__restrict__ gate) {
+    if (*gate == 0) return;
     int n = blockIdx.x * blockDim.x + threadIdx.x;
     if (n < N) Hdd[n] += mu[1];
 }
@@ -84,8 +89,9 @@ __global__ __launch_bounds__(256) void k_gram(const int *__restrict__ chunk_host
                                               const int *__restrict__ obs_ptr, const int *__restrict__ obs_pair,
                                               const int *__restrict__ pair_local, const T *__restrict__ rec,
                                               const double *__restrict__ Hdd, const double *__restrict__ geo,
-                                              double *__restrict__ gram) {
+                                              double *__restrict__ gram, const int *__restrict__ gate) {
     __shared__ double u[GRAM_G][GRAM_EMAX];
+    if (*gate == 0) return;
     const int c = blockIdx.x;
     const int m = host_m[chunk_host[c]];
     const int E = 6 * (m + 1);
@@ -144,7 +150,9 @@ __global__ __launch_bounds__(64) void k_assemble_s(int n6, int pinned, const int
                                                    const int *__restrict__ host_chunk_ptr,
                                                    const int *__restrict__ chunk_off, const double *__restrict__ pairH,
                                                    const double *__restrict__ geo, const double *__restrict__ gram,
-                                                   const double *__restrict__ mu, double *__restrict__ S) {
+                                                   const double *__restrict__ mu, double *__restrict__ S,
+                                                   const int *__restrict__ gate) {
+    if (*gate == 0) return;
     const int b = blockIdx.x;
     if (threadIdx.x >= 36) return;
     const int r = threadIdx.x / 6, c = threadIdx.x % 6;
@@ -290,11 +298,11 @@ __global__ __launch_bounds__(SOLVE_THREADS) void k_solve(
     const double *__restrict__ geo_lin, double *__restrict__ S, const double *__restrict__ Sinv,
     double *__restrict__ poses, const double *__restrict__ poses0, double *__restrict__ b_out,
     double *__restrict__ dth_out, double *__restrict__ dth_rel, double *__restrict__ geo_next, T *__restrict__ rel_next,
-    double *__restrict__ stat, int *__restrict__ flag) {
+    double *__restrict__ stat, int *__restrict__ flag, const int *__restrict__ gate) {
     __shared__ double lds[LDS_DOUBLES];
     __shared__ double red[16];
     __shared__ int fail;
-    if (*flag) return;
+    if (*gate == 0 || *flag) return;
     const int n = 6 * F;
     const bool packed = !ic && n <= LDS_MAX_N;
     double *bx = packed ? lds + (size_t)n * (n + 1) / 2 : b_out + n;  // rhs / solution vector
@@ -430,15 +438,15 @@ __global__ __launch_bounds__(SOLVE_THREADS) void k_solve(
 
 static inline unsigned nb(size_t n, unsigned b) { return (unsigned)((n + b - 1) / b); }
 
-void launch_fill(hipStream_t s, double *p, size_t n, double v) {
+void launch_fill(hipStream_t s, double *p, size_t n, double v, const int *gate) {
     if (n == 0) return;
-    k_fill<<<nb(n, 256), 256, 0, s>>>(p, n, v);
+    k_fill<<<nb(n, 256), 256, 0, s>>>(p, n, v, gate);
 }
 
 void launch_mu(hipStream_t s, Ctx &c, const double *geo) {
     k_mu<<<1, 256, 0, s>>>(c.st.n_pairs, c.F, c.N, c.hdd_blocks, c.cfg.damping_rel, c.d_pairH, geo, c.d_hdd_part,
-                            c.d_mu);
-    if (c.N) k_damp_hdd<<<nb(c.N, 256), 256, 0, s>>>(c.N, c.d_Hdd, c.d_mu);
+                            c.d_mu, c.d_gate);
+    if (c.N) k_damp_hdd<<<nb(c.N, 256), 256, 0, s>>>(c.N, c.d_Hdd, c.d_mu, c.d_gate);
 }
 
 void launch_gram(hipStream_t s, Ctx &c, const double *geo, const void *rec, bool rec_double) {
@@ -447,20 +455,20 @@ void launch_gram(hipStream_t s, Ctx &c, const double *geo, const void *rec, bool
     if (rec_double)
         k_gram<double><<<nch, 256, 0, s>>>(c.d_chunk_host, c.d_chunk_begin, c.d_chunk_end, c.d_chunk_off, c.d_host_m,
                                            c.d_host_pts, c.d_obs_ptr, c.d_obs_pair, c.d_pair_local,
-                                           (const double *)rec, c.d_Hdd, geo, c.d_gram);
+                                           (const double *)rec, c.d_Hdd, geo, c.d_gram, c.d_gate);
     else
         k_gram<float><<<nch, 256, 0, s>>>(c.d_chunk_host, c.d_chunk_begin, c.d_chunk_end, c.d_chunk_off, c.d_host_m,
                                           c.d_host_pts, c.d_obs_ptr, c.d_obs_pair, c.d_pair_local,
-                                          (const float *)rec, c.d_Hdd, geo, c.d_gram);
+                                          (const float *)rec, c.d_Hdd, geo, c.d_gram, c.d_gate);
 }
 
 void launch_assemble_s(hipStream_t s, Ctx &c, const double *geo) {
     const size_t n6 = 6 * (size_t)c.F;
-    launch_fill(s, c.d_S, n6 * n6, 0.0);
+    launch_fill(s, c.d_S, n6 * n6, 0.0, c.d_gate);
     const int nbk = (int)c.st.blk_fa.size();
     k_assemble_s<<<nbk, 64, 0, s>>>((int)n6, c.cfg.pinned_frame, c.d_blk_fa, c.d_blk_fb, c.d_blk_pp_ptr,
                                     c.d_blk_pp_item, c.d_blk_g_ptr, c.d_blk_g_item, c.d_host_m, c.d_host_chunk_ptr,
-                                    c.d_chunk_off, c.d_pairH, geo, c.d_gram, c.d_mu, c.d_S);
+                                    c.d_chunk_off, c.d_pairH, geo, c.d_gram, c.d_mu, c.d_S, c.d_gate);
 }
 
 void launch_ic_factor(hipStream_t s, Ctx &c) {
@@ -474,12 +482,12 @@ void launch_solve(hipStream_t s, Ctx &c, const double *geo_lin, double *geo_next
         k_solve<double><<<1, SOLVE_THREADS, 0, s>>>(
             ic, c.F, c.st.n_pairs, c.cfg.pinned_frame, c.d_frame_pair_ptr, c.d_frame_pair_item, c.d_pair_host,
             c.d_pair_target, c.d_pairY, geo_lin, c.d_S, c.d_Sinv, c.d_poses, c.d_poses0, c.d_b, c.d_dtheta,
-            c.d_dth_rel, geo_next, (double *)rel_next, stat, c.d_flag);
+            c.d_dth_rel, geo_next, (double *)rel_next, stat, c.d_flag, c.d_gate);
     else
         k_solve<float><<<1, SOLVE_THREADS, 0, s>>>(
             ic, c.F, c.st.n_pairs, c.cfg.pinned_frame, c.d_frame_pair_ptr, c.d_frame_pair_item, c.d_pair_host,
             c.d_pair_target, c.d_pairY, geo_lin, c.d_S, c.d_Sinv, c.d_poses, c.d_poses0, c.d_b, c.d_dtheta,
-            c.d_dth_rel, geo_next, (float *)rel_next, stat, c.d_flag);
+            c.d_dth_rel, geo_next, (float *)rel_next, stat, c.d_flag, c.d_gate);
 }
 
 }  // namespace pba

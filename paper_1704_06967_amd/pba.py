@@ -48,11 +48,18 @@ class pba_result(C.Structure):
     _fields_ = [
         ("iters", C.c_int32 * PBA_MAX_LEVELS), ("total_iters", C.c_int32), ("converged", C.c_int32),
         ("final_energy", C.c_double), ("final_rmse", C.c_double), ("final_active", C.c_int64),
+        ("active_residuals", C.c_int64),
     ]
+
+    def as_dict(self):
+        d = {k: getattr(self, k) for k, _ in self._fields_}
+        d["iters"] = list(self.iters)
+        return d
 
 
 class pba_timing(C.Structure):
-    _fields_ = [("residual_launches", C.c_int64), ("residual_ms", C.c_double), ("residuals_processed", C.c_int64)]
+    _fields_ = [("residual_launches", C.c_int64 * PBA_MAX_LEVELS), ("residual_ms", C.c_double * PBA_MAX_LEVELS),
+                ("residuals_processed", C.c_int64 * PBA_MAX_LEVELS)]
 
 
 class PbaError(RuntimeError):
@@ -212,4 +219,4 @@ class Solver:
     def timing(self):
         t = pba_timing()
         self._chk(pba_get_timing(self.ctx, C.byref(t)))
-        return {k: getattr(t, k) for k, _ in t._fields_}
+        return {k: list(getattr(t, k)) for k, _ in t._fields_}
