@@ -91,7 +91,7 @@ void release_points(Ctx &c) {
                     &c.d_frame_pair_item, &c.d_pair_local, &c.d_pair_hidx, &c.d_host_m, &c.d_host_frames,
                     &c.d_host_pts, &c.d_chunk_host, &c.d_chunk_begin, &c.d_chunk_end, &c.d_chunk_off,
                     &c.d_host_chunk_ptr, &c.d_blk_fa, &c.d_blk_fb, &c.d_blk_pp_ptr, &c.d_blk_pp_item,
-                    &c.d_blk_g_ptr, &c.d_blk_g_item})
+                    &c.d_blk_g_ptr, &c.d_blk_g_item, &c.d_pchunk_begin, &c.d_pchunk_end, &c.d_pair_chunk_ptr})
         dfree(*p);
     dfree(c.d_host_uv);
     dfree(c.d_mask);
@@ -99,7 +99,7 @@ void release_points(Ctx &c) {
     dfree(c.d_depth);
     dfree(c.d_depth0);
     for (double **p : {&c.d_geo0, &c.d_geo_a, &c.d_geo_b, &c.d_pairH, &c.d_pairY, &c.d_Hdd, &c.d_gd,
-                       &c.d_hdd_part, &c.d_gram, &c.d_dth_rel})
+                       &c.d_hdd_part, &c.d_gram, &c.d_dth_rel, &c.d_partH, &c.d_partY, &c.d_obsmap})
         dfree(*p);
     dfree(c.d_rel0);
     dfree(c.d_rel_a);
@@ -180,6 +180,14 @@ std::string build_structure(Ctx &c, const std::vector<int> &host_frame, const st
     {
         std::vector<int> fill(s.pair_obs_ptr.begin(), s.pair_obs_ptr.end() - 1);
         for (int o = 0; o < O; ++o) s.pair_obs_idx[fill[s.obs_pair[o]]++] = o;
+    }
+    s.pair_chunk_ptr.assign(Pn + 1, 0);
+    for (int p = 0; p < Pn; ++p) {
+        for (int b = s.pair_obs_ptr[p]; b < s.pair_obs_ptr[p + 1]; b += PAIR_CHUNK) {
+            s.pchunk_begin.push_back(b);
+            s.pchunk_end.push_back(std::min(s.pair_obs_ptr[p + 1], b + PAIR_CHUNK));
+        }
+        s.pair_chunk_ptr[p + 1] = (int)s.pchunk_begin.size();
     }
     s.frame_pair_ptr.assign(F + 1, 0);
     for (int p = 0; p < Pn; ++p) {
@@ -691,6 +699,9 @@ pba_status pba_set_points(pba_ctx *ctx, int32_t window, int32_t n_points, const 
     HIPCHK(upload(c, c.d_blk_pp_item, s.blk_pp_item));
     HIPCHK(upload(c, c.d_blk_g_ptr, s.blk_g_ptr));
     HIPCHK(upload(c, c.d_blk_g_item, s.blk_g_item));
+    HIPCHK(upload(c, c.d_pchunk_begin, s.pchunk_begin));
+    HIPCHK(upload(c, c.d_pchunk_end, s.pchunk_end));
+    HIPCHK(upload(c, c.d_pair_chunk_ptr, s.pair_chunk_ptr));
     HIPCHK(upload(c, c.d_depth, d));
     HIPCHK(dalloc(c.d_depth0, std::max<size_t>(1, n_points) * sizeof(double)));
     const size_t rs = c.real_size;
@@ -705,6 +716,9 @@ pba_status pba_set_points(pba_ctx *ctx, int32_t window, int32_t n_points, const 
     HIPCHK(dalloc(c.d_rel_b, (size_t)Pn * REL_STRIDE * rs));
     HIPCHK(dalloc(c.d_pairH, (size_t)Pn * 21 * sizeof(double)));
     HIPCHK(dalloc(c.d_pairY, (size_t)Pn * 9 * sizeof(double)));
+    HIPCHK(dalloc(c.d_partH, s.pchunk_begin.size() * 21 * sizeof(double)));
+    HIPCHK(dalloc(c.d_partY, s.pchunk_begin.size() * 9 * sizeof(double)));
+    HIPCHK(dalloc(c.d_obsmap, (size_t)O * 12 * sizeof(double)));
     HIPCHK(dalloc(c.d_Hdd, (size_t)n_points * sizeof(double)));
     HIPCHK(dalloc(c.d_gd, (size_t)n_points * sizeof(double)));
     c.hdd_blocks = (n_points + 255) / 256;

@@ -39,6 +39,7 @@ constexpr int WAVE = 64;
 constexpr int LANES_PER_OBS = 8;   // one lane per patch pixel
 constexpr int BLOCK = 256;         // threads per block for residual kernels
 constexpr int MAX_HOST_TARGETS = 20;  // target frames per host frame (Schur Gram size)
+constexpr int PAIR_CHUNK = 512;       // observations per pair-reduction workgroup
 
 struct LevelDev {
     int W = 0, H = 0;
@@ -54,6 +55,8 @@ struct Structure {
     std::vector<int> obs_point, obs_pair;             // [O]
     std::vector<int> pair_host, pair_target;          // [Pn]
     std::vector<int> pair_obs_ptr, pair_obs_idx;      // CSR pair -> obs
+    std::vector<int> pchunk_begin, pchunk_end;        // chunks of pair_obs_idx (one pair each)
+    std::vector<int> pair_chunk_ptr;                  // CSR pair -> chunks
     std::vector<int> frame_pair_ptr, frame_pair_item; // CSR frame -> (pair*2 + is_host)
     // hosts and their extended frame sets for the depth Schur Gram
     std::vector<int> hosts;                           // distinct host frames
@@ -102,7 +105,8 @@ struct Ctx {
         *d_pair_local = nullptr, *d_pair_hidx = nullptr, *d_host_m = nullptr, *d_host_frames = nullptr,
         *d_host_pts = nullptr, *d_chunk_host = nullptr, *d_chunk_begin = nullptr, *d_chunk_end = nullptr,
         *d_chunk_off = nullptr, *d_host_chunk_ptr = nullptr, *d_blk_fa = nullptr, *d_blk_fb = nullptr,
-        *d_blk_pp_ptr = nullptr, *d_blk_pp_item = nullptr, *d_blk_g_ptr = nullptr, *d_blk_g_item = nullptr;
+        *d_blk_pp_ptr = nullptr, *d_blk_pp_item = nullptr, *d_blk_g_ptr = nullptr, *d_blk_g_item = nullptr,
+        *d_pchunk_begin = nullptr, *d_pchunk_end = nullptr, *d_pair_chunk_ptr = nullptr;
     float *d_host_uv = nullptr;                        // [N][2]
     uint8_t *d_mask = nullptr;                         // [O]
     void *d_rec = nullptr;                             // T [O][REC_STRIDE]
@@ -110,6 +114,8 @@ struct Ctx {
     void *d_rel0 = nullptr, *d_rel_a = nullptr, *d_rel_b = nullptr;      // T [Pn][REL_STRIDE]
     double *d_pairH = nullptr;                         // [Pn][21]
     double *d_pairY = nullptr;                         // [Pn][9] (6 + e, sq, cnt)
+    double *d_partH = nullptr, *d_partY = nullptr;     // per pair chunk partials [nch][21], [nch][9]
+    double *d_obsmap = nullptr;                        // [O][12] observation couplings for the Gram
     double *d_Hdd = nullptr, *d_gd = nullptr;          // [N] (Hdd damped after assembly)
     double *d_hdd_part = nullptr;                      // partial sums for the depth damping
     double *d_mu = nullptr;                            // [2] mu_p, mu_d

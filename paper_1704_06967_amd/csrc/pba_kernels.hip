@@ -341,40 +341,44 @@ __global__ __launch_bounds__(256) void k_point_reduce(int N, const int *__restri
     }
 }
 
-// Per pair: sum over its observations of the pose-pose block (21 values).
+// Per chunk of one pair's observations (at most PAIR_CHUNK, two per thread):
+// sum of the pose-pose block (21 values). Chunk partials are added per pair in
+// chunk order by the consumer.
 template <typename T>
-__global__ __launch_bounds__(256) void k_pair_reduce_H(const int *__restrict__ pair_obs_ptr,
-                                                       const int *__restrict__ pair_obs_idx,
-                                                       const T *__restrict__ rec, double *__restrict__ pairH,
-                                                       const int *__restrict__ gate) {
+__global__ __launch_bounds__(256) void k_pair_chunk_H(const int *__restrict__ chunk_begin,
+                                                      const int *__restrict__ chunk_end,
+                                                      const int *__restrict__ pair_obs_idx, const T *__restrict__ rec,
+                                                      double *__restrict__ partH, const int *__restrict__ gate) {
     __shared__ double lds[21 * 16];
     if (*gate == 0) return;
-    const int p = blockIdx.x;
+    const int c = blockIdx.x;
     double v[21];
     for (int k = 0; k < 21; ++k) v[k] = 0.0;
-    for (int i = pair_obs_ptr[p] + threadIdx.x; i < pair_obs_ptr[p + 1]; i += blockDim.x) {
+    for (int i = chunk_begin[c] + threadIdx.x; i < chunk_end[c]; i += blockDim.x) {
         const T *r = rec + (size_t)pair_obs_idx[i] * REC_STRIDE;
         for (int k = 0; k < 21; ++k) v[k] += (double)r[REC_H + k];
     }
     block_sum<21>(v, lds);
     if (threadIdx.x == 0)
-        for (int k = 0; k < 21; ++k) pairH[21 * p + k] = v[k];
+        for (int k = 0; k < 21; ++k) partH[21 * c + k] = v[k];
 }
 
-// Per pair: reduced right-hand side contribution sum_o (g_o - h_o g_d,n / H_dd,n)
-// (depth elimination of the gradient) and the energy statistics.
+// Per chunk of one pair's observations: reduced right-hand side contribution
+// sum_o (g_o - h_o g_d,n / H_dd,n) (depth elimination of the gradient) and the
+// energy statistics.
 template <typename T>
-__global__ __launch_bounds__(256) void k_pair_reduce_y(const int *__restrict__ pair_obs_ptr,
-                                                       const int *__restrict__ pair_obs_idx,
-                                                       const int *__restrict__ obs_point, const T *__restrict__ rec,
-                                                       const double *__restrict__ Hdd, const double *__restrict__ gd,
-                                                       double *__restrict__ pairY, const int *__restrict__ gate) {
+__global__ __launch_bounds__(256) void k_pair_chunk_y(const int *__restrict__ chunk_begin,
+                                                      const int *__restrict__ chunk_end,
+                                                      const int *__restrict__ pair_obs_idx,
+                                                      const int *__restrict__ obs_point, const T *__restrict__ rec,
+                                                      const double *__restrict__ Hdd, const double *__restrict__ gd,
+                                                      double *__restrict__ partY, const int *__restrict__ gate) {
     __shared__ double lds[9 * 16];
     if (*gate == 0) return;
-    const int p = blockIdx.x;
+    const int c = blockIdx.x;
     double v[9];
     for (int k = 0; k < 9; ++k) v[k] = 0.0;
-    for (int i = pair_obs_ptr[p] + threadIdx.x; i < pair_obs_ptr[p + 1]; i += blockDim.x) {
+    for (int i = chunk_begin[c] + threadIdx.x; i < chunk_end[c]; i += blockDim.x) {
         const int o = pair_obs_idx[i];
         const T *r = rec + (size_t)o * REC_STRIDE;
         const int n = obs_point[o];
@@ -386,7 +390,7 @@ __global__ __launch_bounds__(256) void k_pair_reduce_y(const int *__restrict__ p
     }
     block_sum<9>(v, lds);
     if (threadIdx.x == 0)
-        for (int k = 0; k < 9; ++k) pairY[9 * p + k] = v[k];
+        for (int k = 0; k < 9; ++k) partY[9 * c + k] = v[k];
 }
 
 // Sum of the record statistics over all observations (single block).
@@ -600,17 +604,19 @@ void Launch<T>::point_reduce(hipStream_t s, Ctx &c, bool with_hdd) {
 
 template <typename T>
 void Launch<T>::pair_reduce_H(hipStream_t s, Ctx &c) {
-    if (c.st.n_pairs == 0) return;
-    k_pair_reduce_H<T><<<c.st.n_pairs, 256, 0, s>>>(c.d_pair_obs_ptr, c.d_pair_obs_idx, (const T *)c.d_rec,
-                                                    c.d_pairH, c.d_gate);
+    const int nch = (int)c.st.pchunk_begin.size();
+    if (nch == 0) return;
+    k_pair_chunk_H<T><<<nch, 256, 0, s>>>(c.d_pchunk_begin, c.d_pchunk_end, c.d_pair_obs_idx, (const T *)c.d_rec,
+                                          c.d_partH, c.d_gate);
     CHECK_LAUNCH();
 }
 
 template <typename T>
 void Launch<T>::pair_reduce_y(hipStream_t s, Ctx &c) {
-    if (c.st.n_pairs == 0) return;
-    k_pair_reduce_y<T><<<c.st.n_pairs, 256, 0, s>>>(c.d_pair_obs_ptr, c.d_pair_obs_idx, c.d_obs_point,
-                                                    (const T *)c.d_rec, c.d_Hdd, c.d_gd, c.d_pairY, c.d_gate);
+    const int nch = (int)c.st.pchunk_begin.size();
+    if (nch == 0) return;
+    k_pair_chunk_y<T><<<nch, 256, 0, s>>>(c.d_pchunk_begin, c.d_pchunk_end, c.d_pair_obs_idx, c.d_obs_point,
+                                          (const T *)c.d_rec, c.d_Hdd, c.d_gd, c.d_partY, c.d_gate);
     CHECK_LAUNCH();
 }
 

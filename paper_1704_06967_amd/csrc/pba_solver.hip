@@ -8,8 +8,10 @@ namespace pba {
 
 constexpr int SOLVE_THREADS = 1024;
 constexpr int LDS_DOUBLES = 150 * 1024 / 8;   // packed lower triangle of S when it fits
-constexpr int LDS_MAX_N = 192;                // n (n + 1) / 2 <= LDS_DOUBLES - 2 n
-constexpr int GRAM_G = 8;                     // points per Gram step
+constexpr int LDS_MAX_N = 192;                // n (n + 1) / 2 + n <= LDS_DOUBLES; 3 rows per lane
+constexpr int WNS = 3;                        // rows per lane in the wavefront solves (n <= 192)
+constexpr int GRAM_G = 32;                    // points per Gram step
+constexpr int GRAM_SLOTS = 8;                 // observation slots per point per load pass
 constexpr int GRAM_EMAX = 6 * (MAX_HOST_TARGETS + 1);
 constexpr int GRAM_KMAX = (GRAM_EMAX * GRAM_EMAX + 255) / 256;
 
@@ -34,20 +36,50 @@ __device__ __forceinline__ double xthy(const double *X, const double *H21, const
     return s;
 }
 
+// Fixed-order block sum of NV doubles per thread; result valid in thread 0.
+template <int NV>
+__device__ __forceinline__ void block_sum_d(double v[NV], double *lds /* [NV * 16] */) {
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    for (int p = 0; p < NV; ++p)
+        for (int s = 32; s >= 1; s >>= 1) v[p] += __shfl_xor(v[p], s, 64);
+    if (lane == 0)
+        for (int p = 0; p < NV; ++p) lds[wv * NV + p] = v[p];
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const int nw = (blockDim.x + 63) >> 6;
+        for (int p = 0; p < NV; ++p) {
+            double s = 0.0;
+            for (int k = 0; k < nw; ++k) s += lds[k * NV + p];
+            v[p] = s;
+        }
+    }
+    __syncthreads();
+}
+
 __global__ void k_fill(double *__restrict__ p, size_t n, double v, const int *__restrict__ gate) {
     if (gate && *gate == 0) return;
     size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) p[i] = v;
 }
 
-// Damping of the pose and depth diagonals: mu = damping_rel x mean diagonal of
+// Pair sums of the pose-pose blocks (chunk partials added in order) and the
+// damping of the pose and depth diagonals: mu = damping_rel x mean diagonal of
 // the undamped blocks (damping_rel when that mean is zero).
 __global__ __launch_bounds__(256) void k_mu(int Pn, int F, int N, int hdd_blocks, double damping,
-                                             const double *__restrict__ pairH, const double *__restrict__ geo,
-                                             const double *__restrict__ hdd_part, double *__restrict__ mu,
-                                             const int *__restrict__ gate) {
+                                            const int *__restrict__ pair_chunk_ptr, const double *__restrict__ partH,
+                                            double *__restrict__ pairH, const double *__restrict__ geo,
+                                            const double *__restrict__ hdd_part, double *__restrict__ mu,
+                                            const int *__restrict__ gate) {
     __shared__ double lds[16];
     if (*gate == 0) return;
+    for (int e = threadIdx.x; e < Pn * 21; e += blockDim.x) {
+        const int p = e / 21, k = e % 21;
+        double s = 0.0;
+        for (int c = pair_chunk_ptr[p]; c < pair_chunk_ptr[p + 1]; ++c) s += partH[21 * c + k];
+        pairH[e] = s;
+    }
+    __threadfence_block();
+    __syncthreads();
     double s = 0.0;
     for (int e = threadIdx.x; e < Pn * 6; e += blockDim.x) {
         const int p = e / 6, r = e % 6;
@@ -56,16 +88,11 @@ __global__ __launch_bounds__(256) void k_mu(int Pn, int F, int N, int hdd_blocks
         s += xthy(A, pairH + 21 * p, A, r, r) + xthy(B, pairH + 21 * p, B, r, r);
     }
     double v[1] = {s};
-    for (int k = 32; k >= 1; k >>= 1) v[0] += __shfl_xor(v[0], k, 64);
-    if ((threadIdx.x & 63) == 0) lds[threadIdx.x >> 6] = v[0];
-    __syncthreads();
+    block_sum_d<1>(v, lds);
     if (threadIdx.x == 0) {
-        double tot = 0.0;
-        for (int k = 0; k < (int)(blockDim.x >> 6); ++k) tot += lds[k];
         double hs = 0.0;
         for (int k = 0; k < hdd_blocks; ++k) hs += hdd_part[k];
-        // a block whose mean diagonal is zero (nothing observed) is damped by damping itself
-        const double mp = tot / (6.0 * F), md = N > 0 ? hs / N : 0.0;
+        const double mp = v[0] / (6.0 * F), md = N > 0 ? hs / N : 0.0;
         mu[0] = mp > 0.0 ? damping * mp : damping;
         mu[1] = md > 0.0 ? damping * md : damping;
     }
@@ -78,19 +105,42 @@ __global__ void k_damp_hdd(int N, double *__restrict__ Hdd, const double *__rest
     if (n < N) Hdd[n] += mu[1];
 }
 
+// Coupling of every observation to its target and host poses in absolute
+// coordinates, scaled for the Schur Gram: (A^T h_o, B^T h_o) / sqrt(H_dd,n).
+template <typename T>
+__global__ __launch_bounds__(256) void k_obs_map(int O, const int *__restrict__ obs_point,
+                                                 const int *__restrict__ obs_pair, const T *__restrict__ rec,
+                                                 const double *__restrict__ Hdd, const double *__restrict__ geo,
+                                                 double *__restrict__ map, const int *__restrict__ gate) {
+    if (*gate == 0) return;
+    const int o = blockIdx.x * blockDim.x + threadIdx.x;
+    if (o >= O) return;
+    const T *h = rec + (size_t)o * REC_STRIDE + REC_h;
+    double hv[6], ua[6], ub[6];
+    for (int a = 0; a < 6; ++a) hv[a] = (double)h[a];
+    const double *g = geo + GEO_STRIDE * obs_pair[o];
+    apply_At(g, hv, ua);
+    apply_Bt(g, hv, ub);
+    const double s = 1.0 / sqrt(Hdd[obs_point[o]]);
+    double *m = map + 12 * (size_t)o;
+    for (int a = 0; a < 6; ++a) {
+        m[a] = ua[a] * s;
+        m[6 + a] = ub[a] * s;
+    }
+}
+
 // Depth Schur complement, one chunk of one host frame's points per block:
 // T += u_n u_n^T with u_n = [A_1^T h_1, ..., A_m^T h_m, sum_o B_o^T h_o] / sqrt(H_dd,n),
 // the coupling of point n to each of the host's target frames and to the host,
 // in absolute coordinates. T is (6(m+1))^2, every entry owned by one thread.
-template <typename T>
 __global__ __launch_bounds__(256) void k_gram(const int *__restrict__ chunk_host, const int *__restrict__ chunk_begin,
                                               const int *__restrict__ chunk_end, const int *__restrict__ chunk_off,
                                               const int *__restrict__ host_m, const int *__restrict__ host_pts,
                                               const int *__restrict__ obs_ptr, const int *__restrict__ obs_pair,
-                                              const int *__restrict__ pair_local, const T *__restrict__ rec,
-                                              const double *__restrict__ Hdd, const double *__restrict__ geo,
+                                              const int *__restrict__ pair_local, const double *__restrict__ map,
                                               double *__restrict__ gram, const int *__restrict__ gate) {
     __shared__ double u[GRAM_G][GRAM_EMAX];
+    __shared__ double ub[GRAM_G][GRAM_SLOTS][6];
     if (*gate == 0) return;
     const int c = blockIdx.x;
     const int m = host_m[chunk_host[c]];
@@ -103,22 +153,30 @@ __global__ __launch_bounds__(256) void k_gram(const int *__restrict__ chunk_host
         const int G = min(GRAM_G, chunk_end[c] - base);
         for (int e = threadIdx.x; e < GRAM_G * GRAM_EMAX; e += blockDim.x) (&u[0][0])[e] = 0.0;
         __syncthreads();
-        if (threadIdx.x < G * 6) {
-            const int q = threadIdx.x / 6, r = threadIdx.x % 6;
-            const int n = host_pts[base + q];
-            const double s = 1.0 / sqrt(Hdd[n]);
-            double hb = 0.0;
-            for (int o = obs_ptr[n]; o < obs_ptr[n + 1]; ++o) {
-                const int p = obs_pair[o];
-                const T *h = rec + (size_t)o * REC_STRIDE + REC_h;
-                double hv[6], ua[6], ub[6];
-                for (int a = 0; a < 6; ++a) hv[a] = (double)h[a];
-                apply_At(geo + GEO_STRIDE * p, hv, ua);
-                apply_Bt(geo + GEO_STRIDE * p, hv, ub);
-                u[q][6 * pair_local[p] + r] = ua[r] * s;
-                hb += ub[r] * s;
+        {
+            // one observation slot per thread: its target block goes straight to u,
+            // its host block is summed over the point's observations below
+            const int q = threadIdx.x / GRAM_SLOTS, slot = threadIdx.x % GRAM_SLOTS;
+            double hb[6] = {0, 0, 0, 0, 0, 0};
+            if (q < G) {
+                const int n = host_pts[base + q];
+                for (int o = obs_ptr[n] + slot; o < obs_ptr[n + 1]; o += GRAM_SLOTS) {
+                    const double *mo = map + 12 * (size_t)o;
+                    const int i6 = 6 * pair_local[obs_pair[o]];
+                    for (int r = 0; r < 6; ++r) {
+                        u[q][i6 + r] = mo[r];
+                        hb[r] += mo[6 + r];
+                    }
+                }
             }
-            u[q][6 * m + r] = hb;
+            for (int r = 0; r < 6; ++r) ub[q][slot][r] = hb[r];
+        }
+        __syncthreads();
+        if (threadIdx.x < GRAM_G * 6) {
+            const int q = threadIdx.x / 6, r = threadIdx.x % 6;
+            double s = 0.0;
+            for (int k = 0; k < GRAM_SLOTS; ++k) s += ub[q][k][r];
+            u[q][6 * m + r] = s;
         }
         __syncthreads();
 #pragma unroll
@@ -178,8 +236,9 @@ __global__ __launch_bounds__(64) void k_assemble_s(int n6, int pinned, const int
     S[(size_t)(6 * fa + r) * n6 + 6 * fb + c] = val;
 }
 
-// ---- dense SPD helpers for one workgroup (packed lower triangle in LDS, or the
-// full row-major matrix in global memory when it does not fit)
+// ---- dense SPD helpers for one workgroup of SOLVE_THREADS threads (packed
+// lower triangle in LDS, or the full row-major matrix in global memory when it
+// does not fit)
 
 struct PackedLds {
     double *p;
@@ -191,134 +250,186 @@ struct FullGlobal {
     __device__ double &operator()(int i, int j) const { return p[(size_t)i * n + j]; }
 };
 
-// In-place Cholesky (lower) of the first n rows; returns false if a pivot is
-// not positive. Right-looking, one column per step.
+// In-place Cholesky (lower) of the first n rows, right-looking, two barriers
+// per column; the trailing update runs on a 32 x 32 thread grid. Returns false
+// (in every thread) if a pivot is not positive.
 template <class M>
-__device__ bool chol_block(M A, int n, int *fail) {
+__device__ bool chol_inplace(M A, int n) {
+    const int tr = threadIdx.x >> 5, tc = threadIdx.x & 31;
     for (int k = 0; k < n; ++k) {
-        if (threadIdx.x == 0) {
-            const double d = A(k, k);
-            if (!(d > 0.0))
-                *fail = 1;
-            else
-                A(k, k) = sqrt(d);
-        }
+        const double p = A(k, k);
+        if (!(p > 0.0)) return false;
+        const double lkk = sqrt(p);
+        const double inv = 1.0 / lkk;
+        for (int i = k + 1 + threadIdx.x; i < n; i += blockDim.x) A(i, k) *= inv;
         __syncthreads();
-        if (*fail) return false;
-        const double lkk = A(k, k);
-        for (int i = k + 1 + threadIdx.x; i < n; i += blockDim.x) A(i, k) /= lkk;
-        __syncthreads();
-        const int m = n - k - 1;
-        for (int e = threadIdx.x; e < m * m; e += blockDim.x) {
-            const int i = k + 1 + e / m, j = k + 1 + e % m;
-            if (j <= i) A(i, j) -= A(i, k) * A(j, k);
+        if (threadIdx.x == 0) A(k, k) = lkk;  // A(k, k) is not read again by this factorization
+        for (int i = k + 1 + tr; i < n; i += 32) {
+            const double aik = A(i, k);
+            for (int j = k + 1 + tc; j <= i; j += 32) A(i, j) -= aik * A(j, k);
         }
         __syncthreads();
     }
     return true;
 }
 
-// Solve L L^T x = b in place (x overwrites b; b lives in LDS).
+// L L^T x = b on one wavefront without barriers: lane l owns rows l, l+64, l+128
+// and keeps them in registers; forward substitution may start at row k0 when
+// b is zero above it.
 template <class M>
-__device__ void chol_solve_block(M L, int n, double *b) {
+__device__ void wave_chol_solve(M L, int n, double (&x)[WNS], int k0) {
+    const int lane = threadIdx.x & 63;
+    for (int k = k0; k < n; ++k) {
+        const int s = k >> 6, src = k & 63;
+        double bk = 0.0;
+#pragma unroll
+        for (int q = 0; q < WNS; ++q)
+            if (q == s) bk = __shfl(x[q], src, 64);
+        const double yk = bk / L(k, k);
+#pragma unroll
+        for (int q = 0; q < WNS; ++q) {
+            const int i = lane + 64 * q;
+            if (i == k)
+                x[q] = yk;
+            else if (i > k && i < n)
+                x[q] -= L(i, k) * yk;
+        }
+    }
+    for (int k = n - 1; k >= 0; --k) {
+        const int s = k >> 6, src = k & 63;
+        double yk = 0.0;
+#pragma unroll
+        for (int q = 0; q < WNS; ++q)
+            if (q == s) yk = __shfl(x[q], src, 64);
+        const double xk = yk / L(k, k);
+#pragma unroll
+        for (int q = 0; q < WNS; ++q) {
+            const int i = lane + 64 * q;
+            if (i == k)
+                x[q] = xk;
+            else if (i < k)
+                x[q] -= L(k, i) * xk;
+        }
+    }
+}
+
+// Block-wide L L^T x = b (b in shared or global memory, overwritten), one
+// column per step; used when S does not fit in LDS.
+template <class M>
+__device__ void block_chol_solve(M L, int n, double *b) {
     for (int k = 0; k < n; ++k) {
-        if (threadIdx.x == 0) b[k] /= L(k, k);
+        const double yk = b[k] / L(k, k);
         __syncthreads();
-        const double yk = b[k];
+        if (threadIdx.x == 0) b[k] = yk;
         for (int i = k + 1 + threadIdx.x; i < n; i += blockDim.x) b[i] -= L(i, k) * yk;
         __syncthreads();
     }
     for (int k = n - 1; k >= 0; --k) {
-        if (threadIdx.x == 0) b[k] /= L(k, k);
+        const double xk = b[k] / L(k, k);
         __syncthreads();
-        const double xk = b[k];
+        if (threadIdx.x == 0) b[k] = xk;
         for (int i = threadIdx.x; i < k; i += blockDim.x) b[i] -= L(k, i) * xk;
         __syncthreads();
     }
 }
 
 // IC setup: Cholesky of S and its explicit inverse (the paper's H^{-1}, formed
-// once per level; every iteration then needs one matrix-vector product).
+// once per level; every iteration then needs one matrix-vector product). The
+// columns of S^{-1} are solved by the wavefronts of the block in parallel.
 __global__ __launch_bounds__(SOLVE_THREADS) void k_ic_factor(int n, double *__restrict__ S,
-                                                             double *__restrict__ Sinv, int *__restrict__ flag) {
+                                                             double *__restrict__ Sinv, int *__restrict__ flag,
+                                                             const int *__restrict__ gate) {
     __shared__ double lds[LDS_DOUBLES];
-    __shared__ int fail;
-    if (threadIdx.x == 0) fail = 0;
-    __syncthreads();
-    const bool packed = n <= LDS_MAX_N;
-    bool ok;
-    if (packed) {
+    if (*gate == 0) return;
+    if (n <= LDS_MAX_N) {
         PackedLds A{lds};
         for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
             const int i = e / n, j = e % n;
             if (j <= i) A(i, j) = S[e];
         }
         __syncthreads();
-        ok = chol_block(A, n, &fail);  // the factor stays in LDS; S keeps the assembled system
-    } else {
-        ok = chol_block(FullGlobal{S, n}, n, &fail);
-    }
-    if (!ok) {
-        if (threadIdx.x == 0) *flag = 1;
-        return;
-    }
-    __syncthreads();
-    // column c of S^{-1}: L y = e_c, L^T x = y (one thread per column)
-    for (int c = threadIdx.x; c < n; c += blockDim.x) {
-        double *x = Sinv + (size_t)c * n;  // row c of the symmetric inverse
-        for (int i = 0; i < n; ++i) {
-            double s = (i == c) ? 1.0 : 0.0;
-            if (i > c) {
-                for (int k = c; k < i; ++k) s -= (packed ? PackedLds{lds}(i, k) : S[(size_t)i * n + k]) * x[k];
-            } else if (i < c) {
-                s = 0.0;
-            }
-            x[i] = s / (packed ? PackedLds{lds}(i, i) : S[(size_t)i * n + i]);
+        if (!chol_inplace(A, n)) {
+            if (threadIdx.x == 0) *flag = 1;
+            return;
         }
-        for (int i = n - 1; i >= 0; --i) {
-            double s = x[i];
-            for (int k = i + 1; k < n; ++k) s -= (packed ? PackedLds{lds}(k, i) : S[(size_t)k * n + i]) * x[k];
-            x[i] = s / (packed ? PackedLds{lds}(i, i) : S[(size_t)i * n + i]);
+        __syncthreads();
+        const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
+        for (int c = wv; c < n; c += nw) {
+            double x[WNS];
+#pragma unroll
+            for (int q = 0; q < WNS; ++q) x[q] = (lane + 64 * q == c) ? 1.0 : 0.0;
+            wave_chol_solve(A, n, x, c);
+#pragma unroll
+            for (int q = 0; q < WNS; ++q) {
+                const int i = lane + 64 * q;
+                if (i < n) Sinv[(size_t)c * n + i] = x[q];
+            }
+        }
+    } else {
+        FullGlobal A{S, n};
+        if (!chol_inplace(A, n)) {
+            if (threadIdx.x == 0) *flag = 1;
+            return;
+        }
+        __syncthreads();
+        // columns of the inverse, one block-wide solve each (S^{-1} rows as scratch)
+        for (int c = 0; c < n; ++c) {
+            double *x = Sinv + (size_t)c * n;
+            for (int i = threadIdx.x; i < n; i += blockDim.x) x[i] = (i == c) ? 1.0 : 0.0;
+            __syncthreads();
+            block_chol_solve(A, n, x);
         }
     }
 }
 
 // One solve per iteration (single workgroup):
+//  0. pair sums of the reduced gradient from their chunk partials;
 //  1. reduced right-hand side b_f = sum over the frame's pairs of A^T y (target) or
 //     B^T y (host), zero on the pinned frame;
-//  2. dtheta = -S^{-1} b (IC: product with the stored inverse; FC: Cholesky of the
-//     freshly assembled S and two triangular solves);
+//  2. dtheta = -S^{-1} b (IC: product with the stored inverse, one wavefront per
+//     row; FC: Cholesky of the freshly assembled S and two triangular solves);
 //  3. pose update: IC R <- R_k R0^T exp(dw)^T R0, t <- t_k - R_k R0^T dt (Sec. 3.6);
 //     FC R <- exp(dw) R, t <- t + dt;
 //  4. the next relative poses of every pair and the relative steps A dth_f + B dth_h.
 template <typename T>
 __global__ __launch_bounds__(SOLVE_THREADS) void k_solve(
     int ic, int F, int Pn, int pinned, const int *__restrict__ frame_pair_ptr, const int *__restrict__ frame_pair_item,
-    const int *__restrict__ pair_host, const int *__restrict__ pair_target, const double *__restrict__ pairY,
-    const double *__restrict__ geo_lin, double *__restrict__ S, const double *__restrict__ Sinv,
-    double *__restrict__ poses, const double *__restrict__ poses0, double *__restrict__ b_out,
-    double *__restrict__ dth_out, double *__restrict__ dth_rel, double *__restrict__ geo_next, T *__restrict__ rel_next,
-    double *__restrict__ stat, int *__restrict__ flag, const int *__restrict__ gate) {
+    const int *__restrict__ pair_host, const int *__restrict__ pair_target, const int *__restrict__ pair_chunk_ptr,
+    const double *__restrict__ partY, double *__restrict__ pairY, const double *__restrict__ geo_lin,
+    double *__restrict__ S, const double *__restrict__ Sinv, double *__restrict__ poses,
+    const double *__restrict__ poses0, double *__restrict__ b_out, double *__restrict__ dth_out,
+    double *__restrict__ dth_rel, double *__restrict__ geo_next, T *__restrict__ rel_next, double *__restrict__ stat,
+    int *__restrict__ flag, const int *__restrict__ gate) {
     __shared__ double lds[LDS_DOUBLES];
-    __shared__ double red[16];
-    __shared__ int fail;
+    __shared__ double red[64];
     if (*gate == 0 || *flag) return;
     const int n = 6 * F;
-    const bool packed = !ic && n <= LDS_MAX_N;
-    double *bx = packed ? lds + (size_t)n * (n + 1) / 2 : b_out + n;  // rhs / solution vector
-    if (threadIdx.x == 0) {
-        fail = 0;
-        double e = 0, sq = 0, cnt = 0;
-        for (int p = 0; p < Pn; ++p) {
-            e += pairY[9 * p + 6];
-            sq += pairY[9 * p + 7];
-            cnt += pairY[9 * p + 8];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    const bool packed = n <= LDS_MAX_N;
+    double *bx = lds + ((!ic && packed) ? n * (n + 1) / 2 : 0);  // rhs / solution in LDS
+    for (int e = threadIdx.x; e < Pn * 9; e += blockDim.x) {
+        const int p = e / 9, k = e % 9;
+        double s = 0.0;
+        for (int c = pair_chunk_ptr[p]; c < pair_chunk_ptr[p + 1]; ++c) s += partY[9 * c + k];
+        pairY[e] = s;
+    }
+    __threadfence_block();
+    __syncthreads();
+    {
+        double v3[3] = {0.0, 0.0, 0.0};
+        for (int p = threadIdx.x; p < Pn; p += blockDim.x) {
+            v3[0] += pairY[9 * p + 6];
+            v3[1] += pairY[9 * p + 7];
+            v3[2] += pairY[9 * p + 8];
         }
-        stat[ST_E] = e;
-        stat[ST_SQ] = sq;
-        stat[ST_CNT] = cnt;
-        stat[ST_DISP] = 0.0;
-        stat[ST_STEP_D] = 0.0;
+        block_sum_d<3>(v3, red);
+        if (threadIdx.x == 0) {
+            stat[ST_E] = v3[0];
+            stat[ST_SQ] = v3[1];
+            stat[ST_CNT] = v3[2];
+            stat[ST_DISP] = 0.0;
+            stat[ST_STEP_D] = 0.0;
+        }
     }
     for (int e = threadIdx.x; e < n; e += blockDim.x) {
         const int f = e / 6, r = e % 6;
@@ -340,33 +451,47 @@ __global__ __launch_bounds__(SOLVE_THREADS) void k_solve(
     }
     __syncthreads();
     if (ic) {
-        // dtheta = -S^{-1} b; the product goes to dth_out
-        for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        for (int i = wv; i < n; i += nw) {
             const double *row = Sinv + (size_t)i * n;
             double s = 0.0;
-            for (int j = 0; j < n; ++j) s += row[j] * b_out[j];
-            dth_out[i] = -s;
+            for (int j = lane; j < n; j += 64) s += row[j] * bx[j];
+            for (int k = 32; k >= 1; k >>= 1) s += __shfl_xor(s, k, 64);
+            if (lane == 0) dth_out[i] = -s;
         }
-    } else {
-        bool ok;
-        if (packed) {
-            PackedLds A{lds};
-            for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
-                const int i = e / n, j = e % n;
-                if (j <= i) A(i, j) = S[e];
-            }
-            __syncthreads();
-            ok = chol_block(A, n, &fail);
-            if (ok) chol_solve_block(A, n, bx);
-        } else {
-            FullGlobal A{S, n};
-            ok = chol_block(A, n, &fail);
-            if (ok) chol_solve_block(A, n, bx);
+    } else if (packed) {
+        PackedLds A{lds};
+        for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
+            const int i = e / n, j = e % n;
+            if (j <= i) A(i, j) = S[e];
         }
-        if (!ok) {
+        __syncthreads();
+        if (!chol_inplace(A, n)) {
             if (threadIdx.x == 0) *flag = 1;
             return;
         }
+        __syncthreads();
+        if (wv == 0) {
+            double x[WNS];
+#pragma unroll
+            for (int q = 0; q < WNS; ++q) {
+                const int i = lane + 64 * q;
+                x[q] = i < n ? bx[i] : 0.0;
+            }
+            wave_chol_solve(A, n, x, 0);
+#pragma unroll
+            for (int q = 0; q < WNS; ++q) {
+                const int i = lane + 64 * q;
+                if (i < n) dth_out[i] = -x[q];
+            }
+        }
+    } else {
+        FullGlobal A{S, n};
+        if (!chol_inplace(A, n)) {
+            if (threadIdx.x == 0) *flag = 1;
+            return;
+        }
+        __syncthreads();
+        block_chol_solve(A, n, bx);
         for (int i = threadIdx.x; i < n; i += blockDim.x) dth_out[i] = -bx[i];
     }
     __threadfence_block();
@@ -375,7 +500,7 @@ __global__ __launch_bounds__(SOLVE_THREADS) void k_solve(
     double mx = 0.0;
     for (int i = threadIdx.x; i < n; i += blockDim.x) mx = fmax(mx, fabs(dth_out[i]));
     for (int k = 32; k >= 1; k >>= 1) mx = fmax(mx, __shfl_xor(mx, k, 64));
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = mx;
+    if (lane == 0) red[wv] = mx;
     // pose update
     for (int f = threadIdx.x; f < F; f += blockDim.x) {
         const double *x = dth_out + 6 * f;
@@ -384,12 +509,11 @@ __global__ __launch_bounds__(SOLVE_THREADS) void k_solve(
         double *P = poses + 12 * f;
         if (ic) {
             const double *P0 = poses0 + 12 * f;
-            double A[9], Bm[9], Q[9];
-            mat3_mul_bt(P, P0, Q);       // R_k R0^T
-            mat3_mul_bt(Q, dR, A);       // R_k R0^T dR^T
-            mat3_mul(A, P0, Rn);         // ... R0
+            double A[9], Q[9];
+            mat3_mul_bt(P, P0, Q);  // R_k R0^T
+            mat3_mul_bt(Q, dR, A);  // R_k R0^T dR^T
+            mat3_mul(A, P0, Rn);    // ... R0
             for (int i = 0; i < 3; ++i) tn[i] = P[9 + i] - (Q[3 * i] * x[3] + Q[3 * i + 1] * x[4] + Q[3 * i + 2] * x[5]);
-            (void)Bm;
         } else {
             mat3_mul(dR, P, Rn);
             for (int i = 0; i < 3; ++i) tn[i] = P[9 + i] + x[3 + i];
@@ -401,7 +525,7 @@ __global__ __launch_bounds__(SOLVE_THREADS) void k_solve(
     __syncthreads();
     if (threadIdx.x == 0) {
         double m2 = 0.0;
-        for (int k = 0; k < (int)(blockDim.x >> 6); ++k) m2 = fmax(m2, red[k]);
+        for (int k = 0; k < nw; ++k) m2 = fmax(m2, red[k]);
         stat[ST_STEP_P] = m2;
     }
     // next relative poses and relative steps per pair
@@ -444,22 +568,23 @@ void launch_fill(hipStream_t s, double *p, size_t n, double v, const int *gate) 
 }
 
 void launch_mu(hipStream_t s, Ctx &c, const double *geo) {
-    k_mu<<<1, 256, 0, s>>>(c.st.n_pairs, c.F, c.N, c.hdd_blocks, c.cfg.damping_rel, c.d_pairH, geo, c.d_hdd_part,
-                            c.d_mu, c.d_gate);
+    k_mu<<<1, 256, 0, s>>>(c.st.n_pairs, c.F, c.N, c.hdd_blocks, c.cfg.damping_rel, c.d_pair_chunk_ptr, c.d_partH,
+                           c.d_pairH, geo, c.d_hdd_part, c.d_mu, c.d_gate);
     if (c.N) k_damp_hdd<<<nb(c.N, 256), 256, 0, s>>>(c.N, c.d_Hdd, c.d_mu, c.d_gate);
 }
 
 void launch_gram(hipStream_t s, Ctx &c, const double *geo, const void *rec, bool rec_double) {
     const int nch = (int)c.st.chunk_host.size();
-    if (nch == 0) return;
+    if (nch == 0 || c.O == 0) return;
     if (rec_double)
-        k_gram<double><<<nch, 256, 0, s>>>(c.d_chunk_host, c.d_chunk_begin, c.d_chunk_end, c.d_chunk_off, c.d_host_m,
-                                           c.d_host_pts, c.d_obs_ptr, c.d_obs_pair, c.d_pair_local,
-                                           (const double *)rec, c.d_Hdd, geo, c.d_gram, c.d_gate);
+        k_obs_map<double><<<nb(c.O, 256), 256, 0, s>>>(c.O, c.d_obs_point, c.d_obs_pair, (const double *)rec,
+                                                       c.d_Hdd, geo, c.d_obsmap, c.d_gate);
     else
-        k_gram<float><<<nch, 256, 0, s>>>(c.d_chunk_host, c.d_chunk_begin, c.d_chunk_end, c.d_chunk_off, c.d_host_m,
-                                          c.d_host_pts, c.d_obs_ptr, c.d_obs_pair, c.d_pair_local,
-                                          (const float *)rec, c.d_Hdd, geo, c.d_gram, c.d_gate);
+        k_obs_map<float><<<nb(c.O, 256), 256, 0, s>>>(c.O, c.d_obs_point, c.d_obs_pair, (const float *)rec,
+                                                      c.d_Hdd, geo, c.d_obsmap, c.d_gate);
+    k_gram<<<nch, 256, 0, s>>>(c.d_chunk_host, c.d_chunk_begin, c.d_chunk_end, c.d_chunk_off, c.d_host_m,
+                               c.d_host_pts, c.d_obs_ptr, c.d_obs_pair, c.d_pair_local, c.d_obsmap, c.d_gram,
+                               c.d_gate);
 }
 
 void launch_assemble_s(hipStream_t s, Ctx &c, const double *geo) {
@@ -472,7 +597,7 @@ void launch_assemble_s(hipStream_t s, Ctx &c, const double *geo) {
 }
 
 void launch_ic_factor(hipStream_t s, Ctx &c) {
-    k_ic_factor<<<1, SOLVE_THREADS, 0, s>>>(6 * c.F, c.d_S, c.d_Sinv, c.d_flag);
+    k_ic_factor<<<1, SOLVE_THREADS, 0, s>>>(6 * c.F, c.d_S, c.d_Sinv, c.d_flag, c.d_gate);
 }
 
 void launch_solve(hipStream_t s, Ctx &c, const double *geo_lin, double *geo_next, void *rel_next, bool rel_double,
@@ -481,13 +606,13 @@ void launch_solve(hipStream_t s, Ctx &c, const double *geo_lin, double *geo_next
     if (rel_double)
         k_solve<double><<<1, SOLVE_THREADS, 0, s>>>(
             ic, c.F, c.st.n_pairs, c.cfg.pinned_frame, c.d_frame_pair_ptr, c.d_frame_pair_item, c.d_pair_host,
-            c.d_pair_target, c.d_pairY, geo_lin, c.d_S, c.d_Sinv, c.d_poses, c.d_poses0, c.d_b, c.d_dtheta,
-            c.d_dth_rel, geo_next, (double *)rel_next, stat, c.d_flag, c.d_gate);
+            c.d_pair_target, c.d_pair_chunk_ptr, c.d_partY, c.d_pairY, geo_lin, c.d_S, c.d_Sinv, c.d_poses,
+            c.d_poses0, c.d_b, c.d_dtheta, c.d_dth_rel, geo_next, (double *)rel_next, stat, c.d_flag, c.d_gate);
     else
         k_solve<float><<<1, SOLVE_THREADS, 0, s>>>(
             ic, c.F, c.st.n_pairs, c.cfg.pinned_frame, c.d_frame_pair_ptr, c.d_frame_pair_item, c.d_pair_host,
-            c.d_pair_target, c.d_pairY, geo_lin, c.d_S, c.d_Sinv, c.d_poses, c.d_poses0, c.d_b, c.d_dtheta,
-            c.d_dth_rel, geo_next, (float *)rel_next, stat, c.d_flag, c.d_gate);
+            c.d_pair_target, c.d_pair_chunk_ptr, c.d_partY, c.d_pairY, geo_lin, c.d_S, c.d_Sinv, c.d_poses,
+            c.d_poses0, c.d_b, c.d_dtheta, c.d_dth_rel, geo_next, (float *)rel_next, stat, c.d_flag, c.d_gate);
 }
 
 }  // namespace pba
