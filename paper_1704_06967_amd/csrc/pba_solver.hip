@@ -274,10 +274,10 @@ __device__ bool chol_inplace(M A, int n) {
 }
 
 // L L^T x = b on one wavefront without barriers: lane l owns rows l, l+64, l+128
-// and keeps them in registers; forward substitution may start at row k0 when
-// b is zero above it.
+// and keeps them in registers; invd holds 1 / L(k, k). Forward substitution may
+// start at row k0 when b is zero above it.
 template <class M>
-__device__ void wave_chol_solve(M L, int n, double (&x)[WNS], int k0) {
+__device__ void wave_chol_solve(M L, const double *invd, int n, double (&x)[WNS], int k0) {
     const int lane = threadIdx.x & 63;
     for (int k = k0; k < n; ++k) {
         const int s = k >> 6, src = k & 63;
@@ -285,7 +285,7 @@ __device__ void wave_chol_solve(M L, int n, double (&x)[WNS], int k0) {
 #pragma unroll
         for (int q = 0; q < WNS; ++q)
             if (q == s) bk = __shfl(x[q], src, 64);
-        const double yk = bk / L(k, k);
+        const double yk = bk * invd[k];
 #pragma unroll
         for (int q = 0; q < WNS; ++q) {
             const int i = lane + 64 * q;
@@ -301,7 +301,7 @@ __device__ void wave_chol_solve(M L, int n, double (&x)[WNS], int k0) {
 #pragma unroll
         for (int q = 0; q < WNS; ++q)
             if (q == s) yk = __shfl(x[q], src, 64);
-        const double xk = yk / L(k, k);
+        const double xk = yk * invd[k];
 #pragma unroll
         for (int q = 0; q < WNS; ++q) {
             const int i = lane + 64 * q;
@@ -333,6 +333,139 @@ __device__ void block_chol_solve(M L, int n, double *b) {
     }
 }
 
+// ---- register-tiled dense kernels for n <= 192 on a 32 x 32 thread grid:
+// thread (tr, tc) owns the entries (tr + 32 a, tc + 32 b), b <= a < 6, in
+// registers (tiles with b > a hold no lower-triangle entry); each elimination
+// step broadcasts one column (or row) through LDS.
+
+// Load the lower triangle of the row-major n x n matrix G into the tiles.
+__device__ __forceinline__ void tiles_load_lower(const double *__restrict__ G, int n, double (&t)[6][6]) {
+    const int tr = threadIdx.x >> 5, tc = threadIdx.x & 31;
+#pragma unroll
+    for (int a = 0; a < 6; ++a)
+#pragma unroll
+        for (int b = 0; b <= a; ++b) {
+            const int i = tr + 32 * a, j = tc + 32 * b;
+            t[a][b] = (i < n && j <= i) ? G[(size_t)i * n + j] : 0.0;
+        }
+}
+
+// In-register Cholesky (lower) of the tiles; col[] and piv[] are LDS scratch
+// (n and 1 doubles). Returns false in every thread if a pivot is not positive.
+__device__ bool chol_tiles(double (&t)[6][6], int n, double *col, double *piv) {
+    const int tr = threadIdx.x >> 5, tc = threadIdx.x & 31;
+    if (threadIdx.x == 0) *piv = t[0][0];
+    __syncthreads();
+    for (int k = 0; k < n; ++k) {
+        const double p = *piv;
+        if (!(p > 0.0)) return false;
+        const double lkk = sqrt(p), inv = 1.0 / lkk;
+        const int kb = k >> 5;
+        if (tc == (k & 31)) {
+#pragma unroll
+            for (int b = 0; b < 6; ++b)
+                if (b == kb) {
+#pragma unroll
+                    for (int a = b; a < 6; ++a) {
+                        const int i = tr + 32 * a;
+                        if (i > k && i < n) {
+                            t[a][b] *= inv;
+                            col[i] = t[a][b];
+                        } else if (i == k) {
+                            t[a][b] = lkk;
+                        }
+                    }
+                }
+        }
+        __syncthreads();
+        double ci[6], cj[6];
+#pragma unroll
+        for (int a = 0; a < 6; ++a) {
+            const int i = tr + 32 * a;
+            ci[a] = (i > k && i < n) ? col[i] : 0.0;
+            const int j = tc + 32 * a;
+            cj[a] = (j > k && j < n) ? col[j] : 0.0;
+        }
+#pragma unroll
+        for (int a = 0; a < 6; ++a)
+#pragma unroll
+            for (int b = 0; b <= a; ++b) {
+                const int i = tr + 32 * a, j = tc + 32 * b;
+                if (j <= i) t[a][b] -= ci[a] * cj[b];
+            }
+        const int k1 = k + 1;
+        if (k1 < n && tr == (k1 & 31) && tc == (k1 & 31)) {
+            const int kb1 = k1 >> 5;
+#pragma unroll
+            for (int a = 0; a < 6; ++a)
+                if (a == kb1) {
+#pragma unroll
+                    for (int b = 0; b <= a; ++b)
+                        if (b == kb1) *piv = t[a][b];
+                }
+        }
+        __syncthreads();
+    }
+    return true;
+}
+
+// Tiles (lower) -> packed lower triangle in LDS and the reciprocal diagonal.
+__device__ __forceinline__ void tiles_store_packed(const double (&t)[6][6], int n, double *packed, double *invd) {
+    const int tr = threadIdx.x >> 5, tc = threadIdx.x & 31;
+#pragma unroll
+    for (int a = 0; a < 6; ++a)
+#pragma unroll
+        for (int b = 0; b <= a; ++b) {
+            const int i = tr + 32 * a, j = tc + 32 * b;
+            if (i < n && j <= i) {
+                packed[i * (i + 1) / 2 + j] = t[a][b];
+                if (i == j) invd[i] = 1.0 / t[a][b];
+            }
+        }
+}
+
+// W = L^{-1} in the tiles (L packed in LDS with its reciprocal diagonal invd):
+// rows of L W = I in order, each finished row broadcast through row[].
+__device__ void trtri_tiles(const double *L, const double *invd, int n, double (&w)[6][6], double *row) {
+    const int tr = threadIdx.x >> 5, tc = threadIdx.x & 31;
+#pragma unroll
+    for (int a = 0; a < 6; ++a)
+#pragma unroll
+        for (int b = 0; b <= a; ++b) w[a][b] = (tr + 32 * a == tc + 32 * b) ? 1.0 : 0.0;
+    for (int k = 0; k < n; ++k) {
+        const int ka = k >> 5;
+        if (tr == (k & 31)) {
+            const double s = invd[k];
+#pragma unroll
+            for (int a = 0; a < 6; ++a)
+                if (a == ka) {
+#pragma unroll
+                    for (int b = 0; b <= a; ++b) {
+                        const int j = tc + 32 * b;
+                        if (j <= k) {
+                            w[a][b] *= s;
+                            row[j] = w[a][b];
+                        }
+                    }
+                }
+        }
+        __syncthreads();
+        double li[6], rj[6];
+#pragma unroll
+        for (int a = 0; a < 6; ++a) {
+            const int i = tr + 32 * a;
+            li[a] = (i > k && i < n) ? L[i * (i + 1) / 2 + k] : 0.0;
+            const int j = tc + 32 * a;
+            rj[a] = (j <= k) ? row[j] : 0.0;
+        }
+#pragma unroll
+        for (int a = 0; a < 6; ++a)
+#pragma unroll
+            for (int b = 0; b <= a; ++b) w[a][b] -= li[a] * rj[b];
+        __syncthreads();
+    }
+}
+
 // IC setup: Cholesky of S and its explicit inverse (the paper's H^{-1}, formed
 // once per level; every iteration then needs one matrix-vector product). The
 // columns of S^{-1} are solved by the wavefronts of the block in parallel.
@@ -340,31 +473,56 @@ __global__ __launch_bounds__(SOLVE_THREADS) void k_ic_factor(int n, double *__re
                                                              double *__restrict__ Sinv, int *__restrict__ flag,
                                                              const int *__restrict__ gate) {
     __shared__ double lds[LDS_DOUBLES];
+    __shared__ double vec[2 * LDS_MAX_N + 2];
     if (*gate == 0) return;
     if (n <= LDS_MAX_N) {
-        PackedLds A{lds};
-        for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
-            const int i = e / n, j = e % n;
-            if (j <= i) A(i, j) = S[e];
-        }
-        __syncthreads();
-        if (!chol_inplace(A, n)) {
+        const int tr = threadIdx.x >> 5, tc = threadIdx.x & 31;
+        double t[6][6];
+        tiles_load_lower(S, n, t);
+        if (!chol_tiles(t, n, vec, vec + LDS_MAX_N)) {
             if (threadIdx.x == 0) *flag = 1;
             return;
         }
+        double *invd = vec + LDS_MAX_N;
+        tiles_store_packed(t, n, lds, invd);
         __syncthreads();
-        const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
-        for (int c = wv; c < n; c += nw) {
-            double x[WNS];
+        trtri_tiles(lds, invd, n, t, vec);  // t := W = L^{-1}
+        // W (lower) packed into LDS, then S^{-1} = W^T W, entry (i, j) = sum_k W(k,i) W(k,j)
+        __syncthreads();
 #pragma unroll
-            for (int q = 0; q < WNS; ++q) x[q] = (lane + 64 * q == c) ? 1.0 : 0.0;
-            wave_chol_solve(A, n, x, c);
+        for (int a = 0; a < 6; ++a)
 #pragma unroll
-            for (int q = 0; q < WNS; ++q) {
-                const int i = lane + 64 * q;
-                if (i < n) Sinv[(size_t)c * n + i] = x[q];
+            for (int b = 0; b <= a; ++b) {
+                const int i = tr + 32 * a, j = tc + 32 * b;
+                if (i < n && j <= i) lds[i * (i + 1) / 2 + j] = t[a][b];
+                t[a][b] = 0.0;
             }
+        __syncthreads();
+        for (int k = 0; k < n; ++k) {
+            const double *wk = lds + k * (k + 1) / 2;  // row k of W, entries 0..k
+            double wi[6], wj[6];
+#pragma unroll
+            for (int a = 0; a < 6; ++a) {
+                const int i = tr + 32 * a, j = tc + 32 * a;
+                wi[a] = i <= k ? wk[i] : 0.0;
+                wj[a] = j <= k ? wk[j] : 0.0;
+            }
+#pragma unroll
+            for (int a = 0; a < 6; ++a)
+#pragma unroll
+                for (int b = 0; b <= a; ++b) t[a][b] += wi[a] * wj[b];
         }
+        // S^{-1} is symmetric: each lower entry is written to both halves
+#pragma unroll
+        for (int a = 0; a < 6; ++a)
+#pragma unroll
+            for (int b = 0; b <= a; ++b) {
+                const int i = tr + 32 * a, j = tc + 32 * b;
+                if (i < n && j <= i) {
+                    Sinv[(size_t)i * n + j] = t[a][b];
+                    Sinv[(size_t)j * n + i] = t[a][b];
+                }
+            }
     } else {
         FullGlobal A{S, n};
         if (!chol_inplace(A, n)) {
@@ -401,7 +559,7 @@ __global__ __launch_bounds__(SOLVE_THREADS) void k_solve(
     double *__restrict__ dth_rel, double *__restrict__ geo_next, T *__restrict__ rel_next, double *__restrict__ stat,
     int *__restrict__ flag, const int *__restrict__ gate) {
     __shared__ double lds[LDS_DOUBLES];
-    __shared__ double red[64];
+    __shared__ double red[64 + 2 * LDS_MAX_N + 2];
     if (*gate == 0 || *flag) return;
     const int n = 6 * F;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
@@ -459,16 +617,14 @@ __global__ __launch_bounds__(SOLVE_THREADS) void k_solve(
             if (lane == 0) dth_out[i] = -s;
         }
     } else if (packed) {
-        PackedLds A{lds};
-        for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
-            const int i = e / n, j = e % n;
-            if (j <= i) A(i, j) = S[e];
-        }
-        __syncthreads();
-        if (!chol_inplace(A, n)) {
+        double t[6][6];
+        tiles_load_lower(S, n, t);
+        if (!chol_tiles(t, n, red + 64, red + 64 + LDS_MAX_N)) {
             if (threadIdx.x == 0) *flag = 1;
             return;
         }
+        double *invd = red + 64 + LDS_MAX_N;
+        tiles_store_packed(t, n, lds, invd);
         __syncthreads();
         if (wv == 0) {
             double x[WNS];
@@ -477,7 +633,7 @@ __global__ __launch_bounds__(SOLVE_THREADS) void k_solve(
                 const int i = lane + 64 * q;
                 x[q] = i < n ? bx[i] : 0.0;
             }
-            wave_chol_solve(A, n, x, 0);
+            wave_chol_solve(PackedLds{lds}, invd, n, x, 0);
 #pragma unroll
             for (int q = 0; q < WNS; ++q) {
                 const int i = lane + 64 * q;
