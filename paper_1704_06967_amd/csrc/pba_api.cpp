@@ -126,6 +126,7 @@ void release_frames(Ctx &c) {
     dfree(c.d_flag);
     dfree(c.d_gate);
     dfree(c.d_count);
+    dfree(c.d_done);
     c.stats_cap = 0;
     c.have_frames = false;
     c.F = 0;
@@ -310,7 +311,7 @@ pba_status start_level(Ctx &c, int level) {
 }
 
 template <typename T>
-pba_status one_iteration(Ctx &c, int level, double *stat, hipEvent_t ev0, hipEvent_t ev1) {
+pba_status one_iteration(Ctx &c, int level, double *stat, hipEvent_t ev0, hipEvent_t ev1, double conv_px) {
     hipStream_t s = c.stream;
     double *geo_cur = c.flip ? c.d_geo_b : c.d_geo_a;
     double *geo_next = c.flip ? c.d_geo_a : c.d_geo_b;
@@ -320,7 +321,6 @@ pba_status one_iteration(Ctx &c, int level, double *stat, hipEvent_t ev0, hipEve
         if (ev0) HIPCHK(hipEventRecord(ev0, s));
         Launch<T>::ic_residual(s, c, level, rel_cur);
         if (ev1) HIPCHK(hipEventRecord(ev1, s));
-        Launch<T>::point_reduce(s, c, false);
         Launch<T>::pair_reduce_y(s, c);
         launch_solve(s, c, c.d_geo0, geo_next, rel_next, is_fp64(c), stat);
     } else {
@@ -335,7 +335,7 @@ pba_status one_iteration(Ctx &c, int level, double *stat, hipEvent_t ev0, hipEve
         Launch<T>::pair_reduce_y(s, c);
         launch_solve(s, c, geo_cur, geo_next, rel_next, is_fp64(c), stat);
     }
-    Launch<T>::depth_update(s, c, geo_cur, geo_next, stat);
+    Launch<T>::depth_update(s, c, geo_cur, geo_next, stat, conv_px);
     HIPCHK(hipGetLastError());
     c.flip = !c.flip;
     c.iters_in_level++;
@@ -383,9 +383,9 @@ pba_status run_iterations(Ctx &c, int level, int n_iters, pba_iter_stats *out, d
     for (int k = 0; k < n_iters; ++k) {
         hipEvent_t e0 = timing ? c.ev_pool[2 * k] : nullptr, e1 = timing ? c.ev_pool[2 * k + 1] : nullptr;
         double *stat = c.d_stats + (size_t)k * ST_STRIDE;
-        st = is_fp64(c) ? one_iteration<double>(c, level, stat, e0, e1) : one_iteration<float>(c, level, stat, e0, e1);
+        st = is_fp64(c) ? one_iteration<double>(c, level, stat, e0, e1, conv_px)
+                        : one_iteration<float>(c, level, stat, e0, e1, conv_px);
         if (st != PBA_OK) return st;
-        if (conv_px >= 0.0) launch_conv(c.stream, c, stat, conv_px);
     }
     std::vector<double> hs((size_t)n_iters * ST_STRIDE);
     int flag = 0, count = n_iters;
@@ -612,6 +612,7 @@ pba_status pba_set_frames(pba_ctx *ctx, int32_t window, int32_t n_frames, int32_
     HIPCHK(dalloc(c.d_flag, sizeof(int)));
     HIPCHK(dalloc(c.d_gate, sizeof(int)));
     HIPCHK(dalloc(c.d_count, sizeof(int)));
+    HIPCHK(dalloc(c.d_done, sizeof(unsigned)));
     HIPCHK(hipMemsetAsync(c.d_flag, 0, sizeof(int), c.stream));
     HIPCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize(c.stream));

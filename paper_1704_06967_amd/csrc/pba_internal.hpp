@@ -121,7 +121,7 @@ struct Ctx {
     double *d_mu = nullptr;                            // [2] mu_p, mu_d
     double *d_gram = nullptr;                          // chunk partials
     double *d_S = nullptr;                             // [6F][6F] reduced system / factor
-    double *d_Sinv = nullptr;                          // [6F][6F] IC: inverse of the reduced system
+    double *d_Sinv = nullptr;                          // IC: packed Cholesky factor of S at p(0), then 1 / L(k, k)
     double *d_b = nullptr, *d_dtheta = nullptr;        // [6F]
     double *d_dth_rel = nullptr;                       // [Pn][6]
     double *d_stats = nullptr;                         // [cap][ST_STRIDE]
@@ -129,6 +129,7 @@ struct Ctx {
     int *d_flag = nullptr;                             // device error flag (non-SPD)
     int *d_gate = nullptr;                             // 1 while the current solve level runs
     int *d_count = nullptr;                            // iterations run in the current level
+    unsigned *d_done = nullptr;                        // blocks finished in the current depth update
     int hdd_blocks = 0;
 
     // current double-buffer orientation
@@ -154,7 +155,8 @@ template <typename T> struct Launch {
     static void point_reduce(hipStream_t s, Ctx &c, bool with_hdd);
     static void pair_reduce_H(hipStream_t s, Ctx &c);
     static void pair_reduce_y(hipStream_t s, Ctx &c);
-    static void depth_update(hipStream_t s, Ctx &c, const double *geo_old, const double *geo_new, double *stat);
+    static void depth_update(hipStream_t s, Ctx &c, const double *geo_old, const double *geo_new, double *stat,
+                             double conv_px);
 };
 
 // precision-independent launchers (double only)

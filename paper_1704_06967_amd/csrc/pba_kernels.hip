@@ -370,9 +370,10 @@ template <typename T>
 __global__ __launch_bounds__(256) void k_pair_chunk_y(const int *__restrict__ chunk_begin,
                                                       const int *__restrict__ chunk_end,
                                                       const int *__restrict__ pair_obs_idx,
-                                                      const int *__restrict__ obs_point, const T *__restrict__ rec,
-                                                      const double *__restrict__ Hdd, const double *__restrict__ gd,
-                                                      double *__restrict__ partY, const int *__restrict__ gate) {
+                                                      const int *__restrict__ obs_point,
+                                                      const int *__restrict__ obs_ptr, const T *__restrict__ rec,
+                                                      const double *__restrict__ Hdd, double *__restrict__ partY,
+                                                      const int *__restrict__ gate) {
     __shared__ double lds[9 * 16];
     if (*gate == 0) return;
     const int c = blockIdx.x;
@@ -382,7 +383,9 @@ __global__ __launch_bounds__(256) void k_pair_chunk_y(const int *__restrict__ ch
         const int o = pair_obs_idx[i];
         const T *r = rec + (size_t)o * REC_STRIDE;
         const int n = obs_point[o];
-        const double s = gd[n] / Hdd[n];
+        double gdn = 0.0;  // g_d,n: the point's records in order (bitwise the per-point sum)
+        for (int q = obs_ptr[n]; q < obs_ptr[n + 1]; ++q) gdn += (double)rec[(size_t)q * REC_STRIDE + REC_GD];
+        const double s = gdn / Hdd[n];
         for (int k = 0; k < 6; ++k) v[k] += (double)r[REC_G + k] - (double)r[REC_h + k] * s;
         v[6] += (double)r[REC_E];
         v[7] += (double)r[REC_SQ];
@@ -418,61 +421,81 @@ __device__ __forceinline__ void atomic_max_nonneg(double *addr, double v) {
 
 // Back-substitution of the depths, dd_n = -(g_d,n + h_n^T dtheta) / H_dd,n, the
 // depth update (IC: d_{k+1} = d_k (d0 - dd) / d0, Sec. 3.6; FC: d + dd), and
-// the largest level-0 displacement of any observation's point centre.
+// the largest level-0 displacement of any observation's point centre. A block
+// holds 32 points with 8 observation slots each. With conv_px >= 0 the last
+// block to finish applies the convergence test (Sec. 4.1): it counts the
+// iteration and closes the gate once the displacement is below conv_px.
+constexpr int DU_PTS = 32, DU_SLOTS = 8;
+
 template <typename T>
-__global__ __launch_bounds__(256) void k_depth_update(int N, int ic, const int *__restrict__ obs_ptr,
-                                                      const int *__restrict__ obs_pair,
-                                                      const int *__restrict__ host_frame,
-                                                      const float *__restrict__ host_uv,
-                                                      const double *__restrict__ K0, const int *__restrict__ pair_target,
-                                                      const T *__restrict__ rec, const double *__restrict__ Hdd,
-                                                      const double *__restrict__ gd,
-                                                      const double *__restrict__ dth_rel,
-                                                      const double *__restrict__ geo_old,
-                                                      const double *__restrict__ geo_new, double *__restrict__ depth,
-                                                      const double *__restrict__ depth0, double *__restrict__ stat,
-                                                      const int *__restrict__ gate, const int *__restrict__ flag) {
+__global__ __launch_bounds__(256) void k_depth_update(
+    int N, int ic, const int *__restrict__ obs_ptr, const int *__restrict__ obs_pair,
+    const int *__restrict__ host_frame, const float *__restrict__ host_uv, const double *__restrict__ K0,
+    const int *__restrict__ pair_target, const T *__restrict__ rec, const double *__restrict__ Hdd,
+    const double *__restrict__ dth_rel, const double *__restrict__ geo_old, const double *__restrict__ geo_new,
+    double *__restrict__ depth, const double *__restrict__ depth0, double *__restrict__ stat, int *__restrict__ gate,
+    const int *__restrict__ flag, unsigned *__restrict__ done, int *__restrict__ count, double conv_px) {
+    __shared__ double part[DU_PTS][DU_SLOTS];
+    __shared__ double dnew[DU_PTS], dold[DU_PTS];
     __shared__ double red[2][4];
+    __shared__ int last;
     if (*gate == 0 || *flag) return;
-    const int n = blockIdx.x * blockDim.x + threadIdx.x;
-    double mdisp = 0.0, mstep = 0.0;
-    if (n < N) {
-        double s = gd[n];
-        for (int o = obs_ptr[n]; o < obs_ptr[n + 1]; ++o) {
-            const T *r = rec + (size_t)o * REC_STRIDE;
-            const double *dr = dth_rel + 6 * obs_pair[o];
-            for (int k = 0; k < 6; ++k) s += (double)r[REC_h + k] * dr[k];
-        }
-        const double dd = -s / Hdd[n];
+    const int q = threadIdx.x / DU_SLOTS, slot = threadIdx.x % DU_SLOTS;
+    const int n = blockIdx.x * DU_PTS + q;
+    const bool has = n < N;
+    const int o0 = has ? obs_ptr[n] : 0, o1 = has ? obs_ptr[n + 1] : 0;
+    // g_d,n + h_n^T dtheta, slot-parallel over the point's observations
+    double s = 0.0;
+    for (int o = o0 + slot; o < o1; o += DU_SLOTS) {
+        const T *r = rec + (size_t)o * REC_STRIDE;
+        const double *dr = dth_rel + 6 * obs_pair[o];
+        for (int k = 0; k < 6; ++k) s += (double)r[REC_h + k] * dr[k];
+    }
+    part[q][slot] = s;
+    __syncthreads();
+    double mstep = 0.0;
+    if (slot == 0 && has) {
+        // g_d,n in observation order, as every other consumer sums it
+        double g = 0.0;
+        for (int o = o0; o < o1; ++o) g += (double)rec[(size_t)o * REC_STRIDE + REC_GD];
+        double t = g;
+        for (int k = 0; k < DU_SLOTS; ++k) t += part[q][k];
+        const double dd = -t / Hdd[n];
         const double d_old = depth[n];
         const double d_new = ic ? d_old * (depth0[n] - dd) / depth0[n] : d_old + dd;
         depth[n] = d_new;
+        dold[q] = d_old;
+        dnew[q] = d_new;
         mstep = fabs(dd);
+    }
+    __syncthreads();
+    double mdisp = 0.0;
+    if (has) {
         const int h = host_frame[n];
         const double x = ((double)host_uv[2 * n] - K0[4 * h + 2]) / K0[4 * h + 0];
         const double y = ((double)host_uv[2 * n + 1] - K0[4 * h + 3]) / K0[4 * h + 1];
-        for (int o = obs_ptr[n]; o < obs_ptr[n + 1]; ++o) {
+        for (int o = o0 + slot; o < o1; o += DU_SLOTS) {
             const int p = obs_pair[o];
             const double *Kt = K0 + 4 * pair_target[p];
-            double q[2][2];
+            double qq[2][2];
             bool ok = true;
             for (int s2 = 0; s2 < 2; ++s2) {
                 const double *g = s2 ? geo_new + GEO_STRIDE * p : geo_old + GEO_STRIDE * p;
-                const double d = s2 ? d_new : d_old;
+                const double d = s2 ? dnew[q] : dold[q];
                 const double vx = g[0] * x + g[1] * y + g[2] + d * g[9];
                 const double vy = g[3] * x + g[4] * y + g[5] + d * g[10];
                 const double vz = g[6] * x + g[7] * y + g[8] + d * g[11];
                 ok = ok && vz > 0.0;
                 const double vzs = vz > 0.0 ? vz : 1.0;
-                q[s2][0] = Kt[0] * vx / vzs + Kt[2];
-                q[s2][1] = Kt[1] * vy / vzs + Kt[3];
+                qq[s2][0] = Kt[0] * vx / vzs + Kt[2];
+                qq[s2][1] = Kt[1] * vy / vzs + Kt[3];
             }
-            if (ok) mdisp = fmax(mdisp, hypot(q[1][0] - q[0][0], q[1][1] - q[0][1]));
+            if (ok) mdisp = fmax(mdisp, hypot(qq[1][0] - qq[0][0], qq[1][1] - qq[0][1]));
         }
     }
-    for (int s = 32; s >= 1; s >>= 1) {
-        mdisp = fmax(mdisp, __shfl_xor(mdisp, s, 64));
-        mstep = fmax(mstep, __shfl_xor(mstep, s, 64));
+    for (int k = 32; k >= 1; k >>= 1) {
+        mdisp = fmax(mdisp, __shfl_xor(mdisp, k, 64));
+        mstep = fmax(mstep, __shfl_xor(mstep, k, 64));
     }
     if ((threadIdx.x & 63) == 0) {
         red[0][threadIdx.x >> 6] = mdisp;
@@ -486,6 +509,19 @@ __global__ __launch_bounds__(256) void k_depth_update(int N, int ic, const int *
         }
         atomic_max_nonneg(stat + ST_DISP, mdisp);
         atomic_max_nonneg(stat + ST_STEP_D, mstep);
+        last = 0;
+        if (conv_px >= 0.0) {
+            __threadfence();
+            last = atomicAdd(done, 1u) == gridDim.x - 1;
+        }
+    }
+    __syncthreads();
+    if (last && threadIdx.x == 0) {
+        __threadfence();
+        const unsigned long long bits = atomicAdd(reinterpret_cast<unsigned long long *>(stat + ST_DISP), 0ull);
+        const double disp = __longlong_as_double((long long)bits);
+        *count += 1;
+        if (disp < conv_px) *gate = 0;
     }
 }
 
@@ -616,17 +652,21 @@ void Launch<T>::pair_reduce_y(hipStream_t s, Ctx &c) {
     const int nch = (int)c.st.pchunk_begin.size();
     if (nch == 0) return;
     k_pair_chunk_y<T><<<nch, 256, 0, s>>>(c.d_pchunk_begin, c.d_pchunk_end, c.d_pair_obs_idx, c.d_obs_point,
-                                          (const T *)c.d_rec, c.d_Hdd, c.d_gd, c.d_partY, c.d_gate);
+                                          c.d_obs_ptr, (const T *)c.d_rec, c.d_Hdd, c.d_partY, c.d_gate);
     CHECK_LAUNCH();
 }
 
 template <typename T>
-void Launch<T>::depth_update(hipStream_t s, Ctx &c, const double *geo_old, const double *geo_new, double *stat) {
-    if (c.N == 0) return;
-    k_depth_update<T><<<nblk(c.N, 256), 256, 0, s>>>(
+void Launch<T>::depth_update(hipStream_t s, Ctx &c, const double *geo_old, const double *geo_new, double *stat,
+                             double conv_px) {
+    if (c.N == 0) {
+        if (conv_px >= 0.0) launch_conv(s, c, stat, conv_px);
+        return;
+    }
+    k_depth_update<T><<<nblk(c.N, DU_PTS), 256, 0, s>>>(
         c.N, c.cfg.mode == PBA_IC_PROXY ? 1 : 0, c.d_obs_ptr, c.d_obs_pair, c.d_host_frame, c.d_host_uv, c.d_K0,
-        c.d_pair_target, (const T *)c.d_rec, c.d_Hdd, c.d_gd, c.d_dth_rel, geo_old, geo_new, c.d_depth,
-        c.d_depth0, stat, c.d_gate, c.d_flag);
+        c.d_pair_target, (const T *)c.d_rec, c.d_Hdd, c.d_dth_rel, geo_old, geo_new, c.d_depth, c.d_depth0, stat,
+        c.d_gate, c.d_flag, c.d_done, c.d_count, conv_px);
     CHECK_LAUNCH();
 }
 

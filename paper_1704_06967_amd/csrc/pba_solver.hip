@@ -7,8 +7,8 @@
 namespace pba {
 
 constexpr int SOLVE_THREADS = 1024;
-constexpr int LDS_DOUBLES = 150 * 1024 / 8;   // packed lower triangle of S when it fits
-constexpr int LDS_MAX_N = 192;                // n (n + 1) / 2 + n <= LDS_DOUBLES; 3 rows per lane
+constexpr int LDS_DOUBLES = 152 * 1024 / 8;   // packed lower triangle of S (+ panel scratch) when it fits
+constexpr int LDS_MAX_N = 180;                // n (n + 1) / 2 + 17 n <= LDS_DOUBLES; 3 rows per lane
 constexpr int WNS = 3;                        // rows per lane in the wavefront solves (n <= 192)
 constexpr int GRAM_G = 32;                    // points per Gram step
 constexpr int GRAM_SLOTS = 8;                 // observation slots per point per load pass
@@ -249,6 +249,10 @@ struct FullGlobal {
     int n;
     __device__ double &operator()(int i, int j) const { return p[(size_t)i * n + j]; }
 };
+struct PackedGlobal {
+    const double *p;
+    __device__ double operator()(int i, int j) const { return p[(size_t)i * (i + 1) / 2 + j]; }
+};
 
 // In-place Cholesky (lower) of the first n rows, right-looking, two barriers
 // per column; the trailing update runs on a 32 x 32 thread grid. Returns false
@@ -333,196 +337,109 @@ __device__ void block_chol_solve(M L, int n, double *b) {
     }
 }
 
-// ---- register-tiled dense kernels for n <= 192 on a 32 x 32 thread grid:
-// thread (tr, tc) owns the entries (tr + 32 a, tc + 32 b), b <= a < 6, in
-// registers (tiles with b > a hold no lower-triangle entry); each elimination
-// step broadcasts one column (or row) through LDS.
+// ---- blocked Cholesky of a packed lower triangle held in LDS (n <= 192),
+// panel width CHOL_NB: a single wavefront factors each diagonal block without
+// barriers, one thread per row solves the panel below it, and the trailing
+// update runs on a 32 x 32 thread grid that reads a transposed copy of the
+// panel (consecutive rows contiguous, so the reads are conflict-free).
+constexpr int CHOL_NB = 16;
 
-// Load the lower triangle of the row-major n x n matrix G into the tiles.
-__device__ __forceinline__ void tiles_load_lower(const double *__restrict__ G, int n, double (&t)[6][6]) {
-    const int tr = threadIdx.x >> 5, tc = threadIdx.x & 31;
-#pragma unroll
-    for (int a = 0; a < 6; ++a)
-#pragma unroll
-        for (int b = 0; b <= a; ++b) {
-            const int i = tr + 32 * a, j = tc + 32 * b;
-            t[a][b] = (i < n && j <= i) ? G[(size_t)i * n + j] : 0.0;
-        }
-}
+__device__ __forceinline__ int pidx(int i, int j) { return i * (i + 1) / 2 + j; }
 
-// In-register Cholesky (lower) of the tiles; col[] and piv[] are LDS scratch
-// (n and 1 doubles). Returns false in every thread if a pivot is not positive.
-__device__ bool chol_tiles(double (&t)[6][6], int n, double *col, double *piv) {
+// A: packed lower triangle (LDS), panel: CHOL_NB * n doubles of LDS scratch,
+// invd: n doubles (LDS or global) receiving 1 / L(k, k), fail: LDS flag.
+// Returns false in every thread if a pivot is not positive.
+__device__ __forceinline__ bool chol_blocked(double *A, int n, double *panel, double *invd, int *fail) {
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int tr = threadIdx.x >> 5, tc = threadIdx.x & 31;
-    if (threadIdx.x == 0) *piv = t[0][0];
+    if (threadIdx.x == 0) *fail = 0;
     __syncthreads();
-    for (int k = 0; k < n; ++k) {
-        const double p = *piv;
-        if (!(p > 0.0)) return false;
-        const double lkk = sqrt(p), inv = 1.0 / lkk;
-        const int kb = k >> 5;
-        if (tc == (k & 31)) {
-#pragma unroll
-            for (int b = 0; b < 6; ++b)
-                if (b == kb) {
-#pragma unroll
-                    for (int a = b; a < 6; ++a) {
-                        const int i = tr + 32 * a;
-                        if (i > k && i < n) {
-                            t[a][b] *= inv;
-                            col[i] = t[a][b];
-                        } else if (i == k) {
-                            t[a][b] = lkk;
-                        }
-                    }
+    for (int k0 = 0; k0 < n; k0 += CHOL_NB) {
+        const int kb = min(CHOL_NB, n - k0);
+        if (wv == 0) {
+            for (int j = 0; j < kb; ++j) {
+                const double p = A[pidx(k0 + j, k0 + j)];
+                if (!(p > 0.0)) {
+                    if (lane == 0) *fail = 1;
+                    break;
                 }
+                const double l = sqrt(p), inv = 1.0 / l;
+                double aij = 0.0;
+                if (lane > j && lane < kb) {
+                    aij = A[pidx(k0 + lane, k0 + j)] * inv;
+                    A[pidx(k0 + lane, k0 + j)] = aij;
+                }
+                if (lane == j) {
+                    A[pidx(k0 + j, k0 + j)] = l;
+                    invd[k0 + j] = inv;
+                }
+                __builtin_amdgcn_wave_barrier();
+                if (lane > j && lane < kb)
+                    for (int c = j + 1; c <= lane; ++c) A[pidx(k0 + lane, k0 + c)] -= aij * A[pidx(k0 + c, k0 + j)];
+                __builtin_amdgcn_wave_barrier();
+            }
         }
         __syncthreads();
-        double ci[6], cj[6];
+        if (*fail) return false;
+        const int k1 = k0 + kb, m = n - k1;
+        // rows below the block: x L11^T = a, kept in the transposed panel
+        for (int r = threadIdx.x; r < m; r += blockDim.x) {
+            const int i = k1 + r;
+            double x[CHOL_NB];
 #pragma unroll
-        for (int a = 0; a < 6; ++a) {
-            const int i = tr + 32 * a;
-            ci[a] = (i > k && i < n) ? col[i] : 0.0;
-            const int j = tc + 32 * a;
-            cj[a] = (j > k && j < n) ? col[j] : 0.0;
-        }
+            for (int c = 0; c < CHOL_NB; ++c) x[c] = c < kb ? A[pidx(i, k0 + c)] : 0.0;
 #pragma unroll
-        for (int a = 0; a < 6; ++a)
+            for (int c = 0; c < CHOL_NB; ++c) {
+                if (c < kb) {
+                    double s = x[c];
 #pragma unroll
-            for (int b = 0; b <= a; ++b) {
-                const int i = tr + 32 * a, j = tc + 32 * b;
-                if (j <= i) t[a][b] -= ci[a] * cj[b];
-            }
-        const int k1 = k + 1;
-        if (k1 < n && tr == (k1 & 31) && tc == (k1 & 31)) {
-            const int kb1 = k1 >> 5;
-#pragma unroll
-            for (int a = 0; a < 6; ++a)
-                if (a == kb1) {
-#pragma unroll
-                    for (int b = 0; b <= a; ++b)
-                        if (b == kb1) *piv = t[a][b];
+                    for (int q = 0; q < c; ++q) s -= x[q] * A[pidx(k0 + c, k0 + q)];
+                    x[c] = s * invd[k0 + c];
+                    A[pidx(i, k0 + c)] = x[c];
+                    panel[c * n + r] = x[c];
                 }
+            }
+        }
+        __syncthreads();
+        // trailing update A22 -= L21 L21^T (lower entries)
+        for (int ia = tr; ia < m; ia += 32) {
+            double xi[CHOL_NB];
+#pragma unroll
+            for (int c = 0; c < CHOL_NB; ++c) xi[c] = c < kb ? panel[c * n + ia] : 0.0;
+            for (int jb = tc; jb <= ia; jb += 32) {
+                double s = 0.0;
+#pragma unroll
+                for (int c = 0; c < CHOL_NB; ++c)
+                    if (c < kb) s += xi[c] * panel[c * n + jb];
+                A[pidx(k1 + ia, k1 + jb)] -= s;
+            }
         }
         __syncthreads();
     }
     return true;
 }
 
-// Tiles (lower) -> packed lower triangle in LDS and the reciprocal diagonal.
-__device__ __forceinline__ void tiles_store_packed(const double (&t)[6][6], int n, double *packed, double *invd) {
-    const int tr = threadIdx.x >> 5, tc = threadIdx.x & 31;
-#pragma unroll
-    for (int a = 0; a < 6; ++a)
-#pragma unroll
-        for (int b = 0; b <= a; ++b) {
-            const int i = tr + 32 * a, j = tc + 32 * b;
-            if (i < n && j <= i) {
-                packed[i * (i + 1) / 2 + j] = t[a][b];
-                if (i == j) invd[i] = 1.0 / t[a][b];
-            }
-        }
-}
-
-// W = L^{-1} in the tiles (L packed in LDS with its reciprocal diagonal invd):
-// rows of L W = I in order, each finished row broadcast through row[].
-__device__ void trtri_tiles(const double *L, const double *invd, int n, double (&w)[6][6], double *row) {
-    const int tr = threadIdx.x >> 5, tc = threadIdx.x & 31;
-#pragma unroll
-    for (int a = 0; a < 6; ++a)
-#pragma unroll
-        for (int b = 0; b <= a; ++b) w[a][b] = (tr + 32 * a == tc + 32 * b) ? 1.0 : 0.0;
-    for (int k = 0; k < n; ++k) {
-        const int ka = k >> 5;
-        if (tr == (k & 31)) {
-            const double s = invd[k];
-#pragma unroll
-            for (int a = 0; a < 6; ++a)
-                if (a == ka) {
-#pragma unroll
-                    for (int b = 0; b <= a; ++b) {
-                        const int j = tc + 32 * b;
-                        if (j <= k) {
-                            w[a][b] *= s;
-                            row[j] = w[a][b];
-                        }
-                    }
-                }
-        }
-        __syncthreads();
-        double li[6], rj[6];
-#pragma unroll
-        for (int a = 0; a < 6; ++a) {
-            const int i = tr + 32 * a;
-            li[a] = (i > k && i < n) ? L[i * (i + 1) / 2 + k] : 0.0;
-            const int j = tc + 32 * a;
-            rj[a] = (j <= k) ? row[j] : 0.0;
-        }
-#pragma unroll
-        for (int a = 0; a < 6; ++a)
-#pragma unroll
-            for (int b = 0; b <= a; ++b) w[a][b] -= li[a] * rj[b];
-        __syncthreads();
-    }
-}
-
-// IC setup: Cholesky of S and its explicit inverse (the paper's H^{-1}, formed
-// once per level; every iteration then needs one matrix-vector product). The
-// columns of S^{-1} are solved by the wavefronts of the block in parallel.
+// IC setup: Cholesky factorization of S, once per level (the paper's "H need
+// only be inverted once"); every iteration then runs two triangular solves.
+// The factor is stored packed (lower, row-major) followed by 1 / L(k, k).
 __global__ __launch_bounds__(SOLVE_THREADS) void k_ic_factor(int n, double *__restrict__ S,
-                                                             double *__restrict__ Sinv, int *__restrict__ flag,
+                                                             double *__restrict__ Lout, int *__restrict__ flag,
                                                              const int *__restrict__ gate) {
     __shared__ double lds[LDS_DOUBLES];
-    __shared__ double vec[2 * LDS_MAX_N + 2];
+    __shared__ int fail;
     if (*gate == 0) return;
+    const int np = n * (n + 1) / 2;
     if (n <= LDS_MAX_N) {
-        const int tr = threadIdx.x >> 5, tc = threadIdx.x & 31;
-        double t[6][6];
-        tiles_load_lower(S, n, t);
-        if (!chol_tiles(t, n, vec, vec + LDS_MAX_N)) {
+        for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
+            const int i = e / n, j = e % n;
+            if (j <= i) lds[pidx(i, j)] = S[e];
+        }
+        __syncthreads();
+        if (!chol_blocked(lds, n, lds + np, Lout + np, &fail)) {
             if (threadIdx.x == 0) *flag = 1;
             return;
         }
-        double *invd = vec + LDS_MAX_N;
-        tiles_store_packed(t, n, lds, invd);
-        __syncthreads();
-        trtri_tiles(lds, invd, n, t, vec);  // t := W = L^{-1}
-        // W (lower) packed into LDS, then S^{-1} = W^T W, entry (i, j) = sum_k W(k,i) W(k,j)
-        __syncthreads();
-#pragma unroll
-        for (int a = 0; a < 6; ++a)
-#pragma unroll
-            for (int b = 0; b <= a; ++b) {
-                const int i = tr + 32 * a, j = tc + 32 * b;
-                if (i < n && j <= i) lds[i * (i + 1) / 2 + j] = t[a][b];
-                t[a][b] = 0.0;
-            }
-        __syncthreads();
-        for (int k = 0; k < n; ++k) {
-            const double *wk = lds + k * (k + 1) / 2;  // row k of W, entries 0..k
-            double wi[6], wj[6];
-#pragma unroll
-            for (int a = 0; a < 6; ++a) {
-                const int i = tr + 32 * a, j = tc + 32 * a;
-                wi[a] = i <= k ? wk[i] : 0.0;
-                wj[a] = j <= k ? wk[j] : 0.0;
-            }
-#pragma unroll
-            for (int a = 0; a < 6; ++a)
-#pragma unroll
-                for (int b = 0; b <= a; ++b) t[a][b] += wi[a] * wj[b];
-        }
-        // S^{-1} is symmetric: each lower entry is written to both halves
-#pragma unroll
-        for (int a = 0; a < 6; ++a)
-#pragma unroll
-            for (int b = 0; b <= a; ++b) {
-                const int i = tr + 32 * a, j = tc + 32 * b;
-                if (i < n && j <= i) {
-                    Sinv[(size_t)i * n + j] = t[a][b];
-                    Sinv[(size_t)j * n + i] = t[a][b];
-                }
-            }
+        for (int e = threadIdx.x; e < np; e += blockDim.x) Lout[e] = lds[e];
     } else {
         FullGlobal A{S, n};
         if (!chol_inplace(A, n)) {
@@ -530,12 +447,10 @@ __global__ __launch_bounds__(SOLVE_THREADS) void k_ic_factor(int n, double *__re
             return;
         }
         __syncthreads();
-        // columns of the inverse, one block-wide solve each (S^{-1} rows as scratch)
-        for (int c = 0; c < n; ++c) {
-            double *x = Sinv + (size_t)c * n;
-            for (int i = threadIdx.x; i < n; i += blockDim.x) x[i] = (i == c) ? 1.0 : 0.0;
-            __syncthreads();
-            block_chol_solve(A, n, x);
+        for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
+            const int i = e / n, j = e % n;
+            if (j <= i) Lout[pidx(i, j)] = S[e];
+            if (i == j) Lout[np + i] = 1.0 / S[e];
         }
     }
 }
@@ -557,14 +472,15 @@ __global__ __launch_bounds__(SOLVE_THREADS) void k_solve(
     double *__restrict__ S, const double *__restrict__ Sinv, double *__restrict__ poses,
     const double *__restrict__ poses0, double *__restrict__ b_out, double *__restrict__ dth_out,
     double *__restrict__ dth_rel, double *__restrict__ geo_next, T *__restrict__ rel_next, double *__restrict__ stat,
-    int *__restrict__ flag, const int *__restrict__ gate) {
+    int *__restrict__ flag, int *__restrict__ gate, unsigned *__restrict__ done) {
     __shared__ double lds[LDS_DOUBLES];
     __shared__ double red[64 + 2 * LDS_MAX_N + 2];
     if (*gate == 0 || *flag) return;
     const int n = 6 * F;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
     const bool packed = n <= LDS_MAX_N;
-    double *bx = lds + ((!ic && packed) ? n * (n + 1) / 2 : 0);  // rhs / solution in LDS
+    // rhs / solution in LDS, after the packed factor (and the FC panel scratch)
+    double *bx = lds + (packed ? n * (n + 1) / 2 : 0);
     for (int e = threadIdx.x; e < Pn * 9; e += blockDim.x) {
         const int p = e / 9, k = e % 9;
         double s = 0.0;
@@ -587,6 +503,7 @@ __global__ __launch_bounds__(SOLVE_THREADS) void k_solve(
             stat[ST_CNT] = v3[2];
             stat[ST_DISP] = 0.0;
             stat[ST_STEP_D] = 0.0;
+            *done = 0u;
         }
     }
     for (int e = threadIdx.x; e < n; e += blockDim.x) {
@@ -608,24 +525,28 @@ __global__ __launch_bounds__(SOLVE_THREADS) void k_solve(
         bx[e] = s;
     }
     __syncthreads();
-    if (ic) {
-        for (int i = wv; i < n; i += nw) {
-            const double *row = Sinv + (size_t)i * n;
-            double s = 0.0;
-            for (int j = lane; j < n; j += 64) s += row[j] * bx[j];
-            for (int k = 32; k >= 1; k >>= 1) s += __shfl_xor(s, k, 64);
-            if (lane == 0) dth_out[i] = -s;
+    if (packed) {
+        // IC: the factor of S at p(0); FC: factor the S assembled this iteration
+        const int np = n * (n + 1) / 2;
+        double *invd = red + 64;
+        if (ic) {
+            for (int e = threadIdx.x; e < np; e += blockDim.x) lds[e] = Sinv[e];
+            for (int e = threadIdx.x; e < n; e += blockDim.x) invd[e] = Sinv[np + e];
+            __syncthreads();
+        } else {
+            for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
+                const int i = e / n, j = e % n;
+                if (j <= i) lds[pidx(i, j)] = S[e];
+            }
+            __syncthreads();
+            if (!chol_blocked(lds, n, lds + np + n, invd, reinterpret_cast<int *>(red + 64 + LDS_MAX_N))) {
+                if (threadIdx.x == 0) {
+                    *flag = 1;
+                    *gate = 0;
+                }
+                return;
+            }
         }
-    } else if (packed) {
-        double t[6][6];
-        tiles_load_lower(S, n, t);
-        if (!chol_tiles(t, n, red + 64, red + 64 + LDS_MAX_N)) {
-            if (threadIdx.x == 0) *flag = 1;
-            return;
-        }
-        double *invd = red + 64 + LDS_MAX_N;
-        tiles_store_packed(t, n, lds, invd);
-        __syncthreads();
         if (wv == 0) {
             double x[WNS];
 #pragma unroll
@@ -640,10 +561,17 @@ __global__ __launch_bounds__(SOLVE_THREADS) void k_solve(
                 if (i < n) dth_out[i] = -x[q];
             }
         }
+    } else if (ic) {
+        PackedGlobal L{Sinv};
+        block_chol_solve(L, n, bx);
+        for (int i = threadIdx.x; i < n; i += blockDim.x) dth_out[i] = -bx[i];
     } else {
         FullGlobal A{S, n};
         if (!chol_inplace(A, n)) {
-            if (threadIdx.x == 0) *flag = 1;
+            if (threadIdx.x == 0) {
+                *flag = 1;
+                *gate = 0;
+            }
             return;
         }
         __syncthreads();
@@ -763,12 +691,12 @@ void launch_solve(hipStream_t s, Ctx &c, const double *geo_lin, double *geo_next
         k_solve<double><<<1, SOLVE_THREADS, 0, s>>>(
             ic, c.F, c.st.n_pairs, c.cfg.pinned_frame, c.d_frame_pair_ptr, c.d_frame_pair_item, c.d_pair_host,
             c.d_pair_target, c.d_pair_chunk_ptr, c.d_partY, c.d_pairY, geo_lin, c.d_S, c.d_Sinv, c.d_poses,
-            c.d_poses0, c.d_b, c.d_dtheta, c.d_dth_rel, geo_next, (double *)rel_next, stat, c.d_flag, c.d_gate);
+            c.d_poses0, c.d_b, c.d_dtheta, c.d_dth_rel, geo_next, (double *)rel_next, stat, c.d_flag, c.d_gate, c.d_done);
     else
         k_solve<float><<<1, SOLVE_THREADS, 0, s>>>(
             ic, c.F, c.st.n_pairs, c.cfg.pinned_frame, c.d_frame_pair_ptr, c.d_frame_pair_item, c.d_pair_host,
             c.d_pair_target, c.d_pair_chunk_ptr, c.d_partY, c.d_pairY, geo_lin, c.d_S, c.d_Sinv, c.d_poses,
-            c.d_poses0, c.d_b, c.d_dtheta, c.d_dth_rel, geo_next, (float *)rel_next, stat, c.d_flag, c.d_gate);
+            c.d_poses0, c.d_b, c.d_dtheta, c.d_dth_rel, geo_next, (float *)rel_next, stat, c.d_flag, c.d_gate, c.d_done);
 }
 
 }  // namespace pba
