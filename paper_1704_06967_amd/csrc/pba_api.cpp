@@ -120,13 +120,13 @@ void release_frames(Ctx &c) {
         dfree(c.lv[l].K);
         c.lv[l].W = c.lv[l].H = 0;
     }
-    for (double **p : {&c.d_poses, &c.d_poses0, &c.d_K0, &c.d_S, &c.d_Sinv, &c.d_b, &c.d_dtheta, &c.d_stats,
+    for (double **p : {&c.d_poses, &c.d_poses0, &c.d_K0, &c.d_S, &c.d_Sinv, &c.d_Lfac, &c.d_b, &c.d_dtheta, &c.d_stats,
                        &c.d_mu})
         dfree(*p);
     dfree(c.d_flag);
     dfree(c.d_gate);
     dfree(c.d_count);
-    dfree(c.d_done);
+    dfree(c.d_du_part);
     c.stats_cap = 0;
     c.have_frames = false;
     c.F = 0;
@@ -303,6 +303,7 @@ pba_status start_level(Ctx &c, int level) {
         launch_gram(s, c, c.d_geo0, c.d_rec, is_fp64(c));
         launch_assemble_s(s, c, c.d_geo0);
         launch_ic_factor(s, c);
+        launch_ic_inverse(s, c);
     }
     HIPCHK(hipGetLastError());
     c.cur_level = level;
@@ -605,14 +606,17 @@ pba_status pba_set_frames(pba_ctx *ctx, int32_t window, int32_t n_frames, int32_
     HIPCHK(dalloc(c.d_poses0, Pz.size() * sizeof(double)));
     HIPCHK(hipMemcpyAsync(c.d_poses, Pz.data(), Pz.size() * sizeof(double), hipMemcpyHostToDevice, c.stream));
     HIPCHK(dalloc(c.d_S, n6 * n6 * sizeof(double)));
-    if (c.cfg.mode == PBA_IC_PROXY) HIPCHK(dalloc(c.d_Sinv, n6 * n6 * sizeof(double)));
+    if (c.cfg.mode == PBA_IC_PROXY) {
+        HIPCHK(dalloc(c.d_Sinv, n6 * n6 * sizeof(double)));
+        HIPCHK(dalloc(c.d_Lfac, (n6 * (n6 + 1) / 2 + n6) * sizeof(double)));
+    }
     HIPCHK(dalloc(c.d_b, 2 * n6 * sizeof(double)));
     HIPCHK(dalloc(c.d_dtheta, n6 * sizeof(double)));
     HIPCHK(dalloc(c.d_mu, 2 * sizeof(double)));
     HIPCHK(dalloc(c.d_flag, sizeof(int)));
     HIPCHK(dalloc(c.d_gate, sizeof(int)));
     HIPCHK(dalloc(c.d_count, sizeof(int)));
-    HIPCHK(dalloc(c.d_done, sizeof(unsigned)));
+
     HIPCHK(hipMemsetAsync(c.d_flag, 0, sizeof(int), c.stream));
     HIPCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize(c.stream));
@@ -726,6 +730,7 @@ pba_status pba_set_points(pba_ctx *ctx, int32_t window, int32_t n_points, const 
     HIPCHK(dalloc(c.d_hdd_part, (size_t)std::max(1, c.hdd_blocks) * sizeof(double)));
     HIPCHK(dalloc(c.d_gram, s.gram_floats * sizeof(double)));
     HIPCHK(dalloc(c.d_dth_rel, (size_t)Pn * 6 * sizeof(double)));
+    HIPCHK(dalloc(c.d_du_part, 2 * (size_t)std::max(1, (n_points + 31) / 32) * sizeof(double)));
     for (int l = 0; l < c.cfg.n_levels; ++l) {
         HIPCHK(dalloc(c.lv[l].tmpl, (size_t)n_points * c.P * 4 * rs));
         c.lv[l].tmpl_valid = false;

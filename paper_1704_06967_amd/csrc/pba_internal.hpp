@@ -121,7 +121,8 @@ struct Ctx {
     double *d_mu = nullptr;                            // [2] mu_p, mu_d
     double *d_gram = nullptr;                          // chunk partials
     double *d_S = nullptr;                             // [6F][6F] reduced system / factor
-    double *d_Sinv = nullptr;                          // IC: packed Cholesky factor of S at p(0), then 1 / L(k, k)
+    double *d_Sinv = nullptr;                          // IC: S^{-1} at p(0) [6F][6F]
+    double *d_Lfac = nullptr;                          // IC: packed Cholesky factor of S, then 1 / L(k, k)
     double *d_b = nullptr, *d_dtheta = nullptr;        // [6F]
     double *d_dth_rel = nullptr;                       // [Pn][6]
     double *d_stats = nullptr;                         // [cap][ST_STRIDE]
@@ -129,7 +130,7 @@ struct Ctx {
     int *d_flag = nullptr;                             // device error flag (non-SPD)
     int *d_gate = nullptr;                             // 1 while the current solve level runs
     int *d_count = nullptr;                            // iterations run in the current level
-    unsigned *d_done = nullptr;                        // blocks finished in the current depth update
+    double *d_du_part = nullptr;                       // depth-update block maxima [blocks][2]
     int hdd_blocks = 0;
 
     // current double-buffer orientation
@@ -167,7 +168,8 @@ void launch_ic_factor(hipStream_t s, Ctx &c);
 void launch_solve(hipStream_t s, Ctx &c, const double *geo_lin, double *geo_next, void *rel_next,
                   bool rel_double, double *stat);
 void launch_sum_stats(hipStream_t s, Ctx &c, const void *rec, bool rec_double, double *out3);
-void launch_conv(hipStream_t s, Ctx &c, const double *stat, double conv_px);
+void launch_conv(hipStream_t s, Ctx &c, double *stat, double conv_px, int nparts);
+void launch_ic_inverse(hipStream_t s, Ctx &c);
 void launch_fill(hipStream_t s, double *p, size_t n, double v, const int *gate);
 
 }  // namespace pba

@@ -414,17 +414,11 @@ __global__ __launch_bounds__(1024) void k_sum_stats(int O, const T *__restrict__
 
 // ------------------------------------------------------------ depth update
 
-__device__ __forceinline__ void atomic_max_nonneg(double *addr, double v) {
-    // non-negative doubles order like their bit patterns as unsigned integers
-    atomicMax(reinterpret_cast<unsigned long long *>(addr), (unsigned long long)__double_as_longlong(v));
-}
-
 // Back-substitution of the depths, dd_n = -(g_d,n + h_n^T dtheta) / H_dd,n, the
 // depth update (IC: d_{k+1} = d_k (d0 - dd) / d0, Sec. 3.6; FC: d + dd), and
 // the largest level-0 displacement of any observation's point centre. A block
-// holds 32 points with 8 observation slots each. With conv_px >= 0 the last
-// block to finish applies the convergence test (Sec. 4.1): it counts the
-// iteration and closes the gate once the displacement is below conv_px.
+// holds 32 points with 8 observation slots each and writes its maxima to
+// part[block] (reduced by k_conv).
 constexpr int DU_PTS = 32, DU_SLOTS = 8;
 
 template <typename T>
@@ -433,33 +427,32 @@ __global__ __launch_bounds__(256) void k_depth_update(
     const int *__restrict__ host_frame, const float *__restrict__ host_uv, const double *__restrict__ K0,
     const int *__restrict__ pair_target, const T *__restrict__ rec, const double *__restrict__ Hdd,
     const double *__restrict__ dth_rel, const double *__restrict__ geo_old, const double *__restrict__ geo_new,
-    double *__restrict__ depth, const double *__restrict__ depth0, double *__restrict__ stat, int *__restrict__ gate,
-    const int *__restrict__ flag, unsigned *__restrict__ done, int *__restrict__ count, double conv_px) {
-    __shared__ double part[DU_PTS][DU_SLOTS];
+    double *__restrict__ depth, const double *__restrict__ depth0, double *__restrict__ part,
+    const int *__restrict__ gate, const int *__restrict__ flag) {
+    __shared__ double sp[DU_PTS][DU_SLOTS][2];
     __shared__ double dnew[DU_PTS], dold[DU_PTS];
     __shared__ double red[2][4];
-    __shared__ int last;
     if (*gate == 0 || *flag) return;
     const int q = threadIdx.x / DU_SLOTS, slot = threadIdx.x % DU_SLOTS;
     const int n = blockIdx.x * DU_PTS + q;
     const bool has = n < N;
     const int o0 = has ? obs_ptr[n] : 0, o1 = has ? obs_ptr[n + 1] : 0;
-    // g_d,n + h_n^T dtheta, slot-parallel over the point's observations
-    double s = 0.0;
+    // g_d,n and h_n^T dtheta, slot-parallel over the point's observations
+    double s = 0.0, g = 0.0;
     for (int o = o0 + slot; o < o1; o += DU_SLOTS) {
         const T *r = rec + (size_t)o * REC_STRIDE;
         const double *dr = dth_rel + 6 * obs_pair[o];
+        g += (double)r[REC_GD];
         for (int k = 0; k < 6; ++k) s += (double)r[REC_h + k] * dr[k];
     }
-    part[q][slot] = s;
+    sp[q][slot][0] = g;
+    sp[q][slot][1] = s;
     __syncthreads();
     double mstep = 0.0;
     if (slot == 0 && has) {
-        // g_d,n in observation order, as every other consumer sums it
-        double g = 0.0;
-        for (int o = o0; o < o1; ++o) g += (double)rec[(size_t)o * REC_STRIDE + REC_GD];
-        double t = g;
-        for (int k = 0; k < DU_SLOTS; ++k) t += part[q][k];
+        double t = 0.0;
+        for (int k = 0; k < DU_SLOTS; ++k) t += sp[q][k][0];
+        for (int k = 0; k < DU_SLOTS; ++k) t += sp[q][k][1];
         const double dd = -t / Hdd[n];
         const double d_old = depth[n];
         const double d_new = ic ? d_old * (depth0[n] - dd) / depth0[n] : d_old + dd;
@@ -480,11 +473,11 @@ __global__ __launch_bounds__(256) void k_depth_update(
             double qq[2][2];
             bool ok = true;
             for (int s2 = 0; s2 < 2; ++s2) {
-                const double *g = s2 ? geo_new + GEO_STRIDE * p : geo_old + GEO_STRIDE * p;
+                const double *gm = s2 ? geo_new + GEO_STRIDE * p : geo_old + GEO_STRIDE * p;
                 const double d = s2 ? dnew[q] : dold[q];
-                const double vx = g[0] * x + g[1] * y + g[2] + d * g[9];
-                const double vy = g[3] * x + g[4] * y + g[5] + d * g[10];
-                const double vz = g[6] * x + g[7] * y + g[8] + d * g[11];
+                const double vx = gm[0] * x + gm[1] * y + gm[2] + d * gm[9];
+                const double vy = gm[3] * x + gm[4] * y + gm[5] + d * gm[10];
+                const double vz = gm[6] * x + gm[7] * y + gm[8] + d * gm[11];
                 ok = ok && vz > 0.0;
                 const double vzs = vz > 0.0 ? vz : 1.0;
                 qq[s2][0] = Kt[0] * vx / vzs + Kt[2];
@@ -507,21 +500,8 @@ __global__ __launch_bounds__(256) void k_depth_update(
             mdisp = fmax(mdisp, red[0][k]);
             mstep = fmax(mstep, red[1][k]);
         }
-        atomic_max_nonneg(stat + ST_DISP, mdisp);
-        atomic_max_nonneg(stat + ST_STEP_D, mstep);
-        last = 0;
-        if (conv_px >= 0.0) {
-            __threadfence();
-            last = atomicAdd(done, 1u) == gridDim.x - 1;
-        }
-    }
-    __syncthreads();
-    if (last && threadIdx.x == 0) {
-        __threadfence();
-        const unsigned long long bits = atomicAdd(reinterpret_cast<unsigned long long *>(stat + ST_DISP), 0ull);
-        const double disp = __longlong_as_double((long long)bits);
-        *count += 1;
-        if (disp < conv_px) *gate = 0;
+        part[2 * blockIdx.x] = mdisp;
+        part[2 * blockIdx.x + 1] = mstep;
     }
 }
 
@@ -659,33 +639,58 @@ void Launch<T>::pair_reduce_y(hipStream_t s, Ctx &c) {
 template <typename T>
 void Launch<T>::depth_update(hipStream_t s, Ctx &c, const double *geo_old, const double *geo_new, double *stat,
                              double conv_px) {
-    if (c.N == 0) {
-        if (conv_px >= 0.0) launch_conv(s, c, stat, conv_px);
-        return;
-    }
-    k_depth_update<T><<<nblk(c.N, DU_PTS), 256, 0, s>>>(
-        c.N, c.cfg.mode == PBA_IC_PROXY ? 1 : 0, c.d_obs_ptr, c.d_obs_pair, c.d_host_frame, c.d_host_uv, c.d_K0,
-        c.d_pair_target, (const T *)c.d_rec, c.d_Hdd, c.d_dth_rel, geo_old, geo_new, c.d_depth, c.d_depth0, stat,
-        c.d_gate, c.d_flag, c.d_done, c.d_count, conv_px);
+    const int nb = (int)nblk(c.N, DU_PTS);
+    if (c.N > 0)
+        k_depth_update<T><<<nb, 256, 0, s>>>(c.N, c.cfg.mode == PBA_IC_PROXY ? 1 : 0, c.d_obs_ptr, c.d_obs_pair,
+                                             c.d_host_frame, c.d_host_uv, c.d_K0, c.d_pair_target,
+                                             (const T *)c.d_rec, c.d_Hdd, c.d_dth_rel, geo_old, geo_new, c.d_depth,
+                                             c.d_depth0, c.d_du_part, c.d_gate, c.d_flag);
     CHECK_LAUNCH();
+    launch_conv(s, c, stat, conv_px, c.N > 0 ? nb : 0);
 }
 
-// Convergence test of the coarse-to-fine solve (Sec. 4.1): after an iteration
-// that ran, count it and close the gate once the largest point-centre
-// displacement is below conv_px; later iterations of the level are skipped.
-__global__ void k_conv(const double *__restrict__ stat, double conv_px, int *__restrict__ gate,
-                       int *__restrict__ count, const int *__restrict__ flag) {
+// Maxima of the depth update's block partials into the iteration's statistics
+// and, with conv_px >= 0, the convergence test of the coarse-to-fine solve
+// (Sec. 4.1): count the iteration and close the gate once the largest
+// point-centre displacement is below conv_px.
+__global__ __launch_bounds__(256) void k_conv(const double *__restrict__ part, int nparts, double *__restrict__ stat,
+                                              double conv_px, int *__restrict__ gate, int *__restrict__ count,
+                                              const int *__restrict__ flag) {
+    __shared__ double red[2][4];
     if (*gate == 0) return;
+    double md = 0.0, ms = 0.0;
+    for (int i = threadIdx.x; i < nparts; i += blockDim.x) {
+        md = fmax(md, part[2 * i]);
+        ms = fmax(ms, part[2 * i + 1]);
+    }
+    for (int k = 32; k >= 1; k >>= 1) {
+        md = fmax(md, __shfl_xor(md, k, 64));
+        ms = fmax(ms, __shfl_xor(ms, k, 64));
+    }
+    if ((threadIdx.x & 63) == 0) {
+        red[0][threadIdx.x >> 6] = md;
+        red[1][threadIdx.x >> 6] = ms;
+    }
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    for (int k = 1; k < 4; ++k) {
+        md = fmax(md, red[0][k]);
+        ms = fmax(ms, red[1][k]);
+    }
     if (*flag) {
         *gate = 0;
         return;
     }
-    *count += 1;
-    if (stat[ST_DISP] < conv_px) *gate = 0;
+    stat[ST_DISP] = md;
+    stat[ST_STEP_D] = ms;
+    if (conv_px >= 0.0) {
+        *count += 1;
+        if (md < conv_px) *gate = 0;
+    }
 }
 
-void launch_conv(hipStream_t s, Ctx &c, const double *stat, double conv_px) {
-    k_conv<<<1, 1, 0, s>>>(stat, conv_px, c.d_gate, c.d_count, c.d_flag);
+void launch_conv(hipStream_t s, Ctx &c, double *stat, double conv_px, int nparts) {
+    k_conv<<<1, 256, 0, s>>>(c.d_du_part, nparts, stat, conv_px, c.d_gate, c.d_count, c.d_flag);
     CHECK_LAUNCH();
 }
 

@@ -4,6 +4,8 @@
 #include "pba_device.hpp"
 #include "pba_internal.hpp"
 
+#include <algorithm>
+
 namespace pba {
 
 constexpr int SOLVE_THREADS = 1024;
@@ -419,6 +421,25 @@ __device__ __forceinline__ bool chol_blocked(double *A, int n, double *panel, do
     return true;
 }
 
+// Block-wide L L^T x = b with the reciprocal diagonal given.
+template <class M>
+__device__ void block_chol_solve_d(M L, const double *invd, int n, double *b) {
+    for (int k = 0; k < n; ++k) {
+        const double yk = b[k] * invd[k];
+        __syncthreads();
+        if (threadIdx.x == 0) b[k] = yk;
+        for (int i = k + 1 + threadIdx.x; i < n; i += blockDim.x) b[i] -= L(i, k) * yk;
+        __syncthreads();
+    }
+    for (int k = n - 1; k >= 0; --k) {
+        const double xk = b[k] * invd[k];
+        __syncthreads();
+        if (threadIdx.x == 0) b[k] = xk;
+        for (int i = threadIdx.x; i < k; i += blockDim.x) b[i] -= L(k, i) * xk;
+        __syncthreads();
+    }
+}
+
 // IC setup: Cholesky factorization of S, once per level (the paper's "H need
 // only be inverted once"); every iteration then runs two triangular solves.
 // The factor is stored packed (lower, row-major) followed by 1 / L(k, k).
@@ -455,6 +476,49 @@ __global__ __launch_bounds__(SOLVE_THREADS) void k_ic_factor(int n, double *__re
     }
 }
 
+// IC setup: S^{-1} = L^{-T} L^{-1} from the packed factor, one column per
+// wavefront over ceil(n / 16) workgroups (each holds the factor in LDS). With
+// S^{-1} stored, every iteration's step is one matrix-vector product.
+__global__ __launch_bounds__(SOLVE_THREADS) void k_ic_inverse(int n, const double *__restrict__ Lfac,
+                                                              double *__restrict__ Sinv,
+                                                              const int *__restrict__ flag,
+                                                              const int *__restrict__ gate) {
+    __shared__ double lds[LDS_DOUBLES];
+    if (*gate == 0 || *flag) return;
+    const int np = n * (n + 1) / 2;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    if (n <= LDS_MAX_N) {
+        for (int e = threadIdx.x; e < np + n; e += blockDim.x) lds[e] = Lfac[e];
+        __syncthreads();
+        const int c = blockIdx.x * (SOLVE_THREADS / 64) + wv;
+        if (c >= n) return;
+        double x[WNS];
+#pragma unroll
+        for (int q = 0; q < WNS; ++q) x[q] = (lane + 64 * q == c) ? 1.0 : 0.0;
+        wave_chol_solve(PackedLds{lds}, lds + np, n, x, c);
+#pragma unroll
+        for (int q = 0; q < WNS; ++q) {
+            const int i = lane + 64 * q;
+            if (i < n) Sinv[(size_t)c * n + i] = x[q];
+        }
+    } else {
+        // one column per workgroup, block-wide solves on the factor in global memory
+        PackedGlobal L{Lfac};
+        for (int c = blockIdx.x; c < n; c += gridDim.x) {
+            double *x = Sinv + (size_t)c * n;
+            for (int i = threadIdx.x; i < n; i += blockDim.x) x[i] = (i == c) ? 1.0 : 0.0;
+            __syncthreads();
+            block_chol_solve_d(L, Lfac + np, n, x);
+        }
+    }
+}
+
+void launch_ic_inverse(hipStream_t s, Ctx &c) {
+    const int n = 6 * c.F;
+    const int grid = n <= LDS_MAX_N ? (n + SOLVE_THREADS / 64 - 1) / (SOLVE_THREADS / 64) : std::min(n, 512);
+    k_ic_inverse<<<grid, SOLVE_THREADS, 0, s>>>(n, c.d_Lfac, c.d_Sinv, c.d_flag, c.d_gate);
+}
+
 // One solve per iteration (single workgroup):
 //  0. pair sums of the reduced gradient from their chunk partials;
 //  1. reduced right-hand side b_f = sum over the frame's pairs of A^T y (target) or
@@ -472,15 +536,15 @@ __global__ __launch_bounds__(SOLVE_THREADS) void k_solve(
     double *__restrict__ S, const double *__restrict__ Sinv, double *__restrict__ poses,
     const double *__restrict__ poses0, double *__restrict__ b_out, double *__restrict__ dth_out,
     double *__restrict__ dth_rel, double *__restrict__ geo_next, T *__restrict__ rel_next, double *__restrict__ stat,
-    int *__restrict__ flag, int *__restrict__ gate, unsigned *__restrict__ done) {
+    int *__restrict__ flag, int *__restrict__ gate) {
     __shared__ double lds[LDS_DOUBLES];
     __shared__ double red[64 + 2 * LDS_MAX_N + 2];
     if (*gate == 0 || *flag) return;
     const int n = 6 * F;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
     const bool packed = n <= LDS_MAX_N;
-    // rhs / solution in LDS, after the packed factor (and the FC panel scratch)
-    double *bx = lds + (packed ? n * (n + 1) / 2 : 0);
+    // rhs / solution in LDS (FC: after the packed factor; the panel scratch follows)
+    double *bx = lds + ((packed && !ic) ? n * (n + 1) / 2 : 0);
     for (int e = threadIdx.x; e < Pn * 9; e += blockDim.x) {
         const int p = e / 9, k = e % 9;
         double s = 0.0;
@@ -503,7 +567,6 @@ __global__ __launch_bounds__(SOLVE_THREADS) void k_solve(
             stat[ST_CNT] = v3[2];
             stat[ST_DISP] = 0.0;
             stat[ST_STEP_D] = 0.0;
-            *done = 0u;
         }
     }
     for (int e = threadIdx.x; e < n; e += blockDim.x) {
@@ -525,15 +588,20 @@ __global__ __launch_bounds__(SOLVE_THREADS) void k_solve(
         bx[e] = s;
     }
     __syncthreads();
-    if (packed) {
-        // IC: the factor of S at p(0); FC: factor the S assembled this iteration
+    if (ic) {
+        // dtheta = -S^{-1} b, one wavefront per row of the inverse formed at p(0)
+        for (int i = wv; i < n; i += nw) {
+            const double *row = Sinv + (size_t)i * n;
+            double s = 0.0;
+            for (int j = lane; j < n; j += 64) s += row[j] * bx[j];
+            for (int k = 32; k >= 1; k >>= 1) s += __shfl_xor(s, k, 64);
+            if (lane == 0) dth_out[i] = -s;
+        }
+    } else if (packed) {
+        // FC: factor the S assembled this iteration
         const int np = n * (n + 1) / 2;
         double *invd = red + 64;
-        if (ic) {
-            for (int e = threadIdx.x; e < np; e += blockDim.x) lds[e] = Sinv[e];
-            for (int e = threadIdx.x; e < n; e += blockDim.x) invd[e] = Sinv[np + e];
-            __syncthreads();
-        } else {
+        {
             for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
                 const int i = e / n, j = e % n;
                 if (j <= i) lds[pidx(i, j)] = S[e];
@@ -561,10 +629,6 @@ __global__ __launch_bounds__(SOLVE_THREADS) void k_solve(
                 if (i < n) dth_out[i] = -x[q];
             }
         }
-    } else if (ic) {
-        PackedGlobal L{Sinv};
-        block_chol_solve(L, n, bx);
-        for (int i = threadIdx.x; i < n; i += blockDim.x) dth_out[i] = -bx[i];
     } else {
         FullGlobal A{S, n};
         if (!chol_inplace(A, n)) {
@@ -681,7 +745,7 @@ void launch_assemble_s(hipStream_t s, Ctx &c, const double *geo) {
 }
 
 void launch_ic_factor(hipStream_t s, Ctx &c) {
-    k_ic_factor<<<1, SOLVE_THREADS, 0, s>>>(6 * c.F, c.d_S, c.d_Sinv, c.d_flag, c.d_gate);
+    k_ic_factor<<<1, SOLVE_THREADS, 0, s>>>(6 * c.F, c.d_S, c.d_Lfac, c.d_flag, c.d_gate);
 }
 
 void launch_solve(hipStream_t s, Ctx &c, const double *geo_lin, double *geo_next, void *rel_next, bool rel_double,
@@ -691,12 +755,12 @@ void launch_solve(hipStream_t s, Ctx &c, const double *geo_lin, double *geo_next
         k_solve<double><<<1, SOLVE_THREADS, 0, s>>>(
             ic, c.F, c.st.n_pairs, c.cfg.pinned_frame, c.d_frame_pair_ptr, c.d_frame_pair_item, c.d_pair_host,
             c.d_pair_target, c.d_pair_chunk_ptr, c.d_partY, c.d_pairY, geo_lin, c.d_S, c.d_Sinv, c.d_poses,
-            c.d_poses0, c.d_b, c.d_dtheta, c.d_dth_rel, geo_next, (double *)rel_next, stat, c.d_flag, c.d_gate, c.d_done);
+            c.d_poses0, c.d_b, c.d_dtheta, c.d_dth_rel, geo_next, (double *)rel_next, stat, c.d_flag, c.d_gate);
     else
         k_solve<float><<<1, SOLVE_THREADS, 0, s>>>(
             ic, c.F, c.st.n_pairs, c.cfg.pinned_frame, c.d_frame_pair_ptr, c.d_frame_pair_item, c.d_pair_host,
             c.d_pair_target, c.d_pair_chunk_ptr, c.d_partY, c.d_pairY, geo_lin, c.d_S, c.d_Sinv, c.d_poses,
-            c.d_poses0, c.d_b, c.d_dtheta, c.d_dth_rel, geo_next, (float *)rel_next, stat, c.d_flag, c.d_gate, c.d_done);
+            c.d_poses0, c.d_b, c.d_dtheta, c.d_dth_rel, geo_next, (float *)rel_next, stat, c.d_flag, c.d_gate);
 }
 
 }  // namespace pba
