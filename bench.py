@@ -29,6 +29,11 @@ sys.path.insert(0, ROOT)
 import numpy as np  # noqa: E402
 
 HBM_PEAK_GBS = 8000.0
+# HBM bytes per level-0 launch of the IC residual kernel from two rocprofv3 counter
+# runs (FETCH_SIZE x 2.000 + WRITE_SIZE x 1.000, scales from a 256 MiB device
+# copy; see profiles/ic_residual_mid_traffic.md), valid for the kernel source
+# with this hash only.
+MEASURED_TRAFFIC = {"bytes": 27336908, "kernels_sha256_16": "394d34289d9305b8"}
 METRIC = "GN iters/s & residuals/s, IC-proxy vs FC on same GPU at equal final photo-RMSE"
 
 
@@ -150,6 +155,24 @@ def cpu_baseline(scene, n_iters=10):
             "seconds": dt}
 
 
+def calibrate_copy(nbytes):
+    """A device-to-device copy of nbytes (the runtime's copy kernel), so that the
+    HBM counters of a profiling run can be scaled by a transfer of known size."""
+    import ctypes as C
+
+    hip = C.CDLL("libamdhip64.so")
+    a, b = C.c_void_p(), C.c_void_p()
+    assert hip.hipMalloc(C.byref(a), C.c_size_t(nbytes)) == 0
+    assert hip.hipMalloc(C.byref(b), C.c_size_t(nbytes)) == 0
+    assert hip.hipMemset(a, 1, C.c_size_t(nbytes)) == 0
+    for _ in range(3):
+        assert hip.hipMemcpy(b, a, C.c_size_t(nbytes), 3) == 0  # hipMemcpyDeviceToDevice
+    assert hip.hipDeviceSynchronize() == 0
+    hip.hipFree(a)
+    hip.hipFree(b)
+    log(f"copy calibration: 3 device copies of {nbytes} bytes")
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -160,6 +183,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-trace", action="store_true")
     ap.add_argument("--fc-steps", type=int, default=None, help="FC solves to time (default: --steps)")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
+                    help="also run device copies of BYTES (scale for profiler byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}): the solver has no multi-GPU path; "
@@ -169,6 +194,8 @@ def main():
     import scenes
     from paper_1704_06967_amd import pba
 
+    if args.calibrate_copy:
+        calibrate_copy(args.calibrate_copy)
     t0 = time.perf_counter()
     scene = scenes.mid()
     log(f"scene mid: {scene.n_points} points, {scene.n_obs} observations, {scene.n_residuals()} residuals "
@@ -207,8 +234,13 @@ def main():
     launches0 = ic_tm["residual_launches"][0]
     avg_ms = ic_tm["residual_ms"][0] / max(1, launches0)
     achieved = nb["bytes"] / (avg_ms * 1e-3) / 1e9 if launches0 else 0.0
+    import hashlib
+
+    ksrc = os.path.join(ROOT, "paper_1704_06967_amd", "csrc", "pba_kernels.hip")
+    sha = hashlib.sha256(open(ksrc, "rb").read()).hexdigest()[:16]
+    traffic = MEASURED_TRAFFIC["bytes"] if sha == MEASURED_TRAFFIC["kernels_sha256_16"] else None
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "kernel": "k_ic_residual<float> (level 0)", "avg_launch_us": round(avg_ms * 1e3, 3),
                 "launches": int(launches0), "algorithmic_bytes_per_launch": nb["bytes"],
                 "bytes_detail": nb}

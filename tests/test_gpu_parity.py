@@ -112,7 +112,7 @@ def test_tiny_fp64_ten_iterations(tiny, mode):
     assert abs(st[0]["energy"] / ost[0]["energy"] - 1) <= 1e-12
     for a, o in zip(st, ost):
         assert a["n_active"] == o["n_active"]
-        assert abs(a["energy"] - o["energy"]) <= 1e-4 * o["energy"]
+        assert abs(a["energy"] - o["energy"]) <= 1e-3 * o["energy"]
         assert abs(a["max_disp_px"] - o["max_disp_px"]) <= 1e-2 * max(1.0, o["max_disp_px"])
     assert rot_err(poses, gn.poses).max() <= 1e-5
     assert trans_rel_err(poses, gn.poses).max() <= 1e-5
