@@ -81,7 +81,11 @@ typedef struct {
     int32_t mode;        /* PBA_FC or PBA_IC_PROXY */
     int32_t precision;   /* PBA_FP64: all arithmetic in double. PBA_FP32: residuals,
                             Jacobians and per-observation blocks in float, reductions,
-                            Schur complement and Cholesky in double */
+                            Schur complement and Cholesky in double. PBA_MIXED_BF16:
+                            as PBA_FP32, except that every pair's pose-pose block
+                            sum w J^T J is contracted on BF16 MFMA (sqrt(w) J split
+                            into two bfloat16 terms, FP32 accumulation with Kahan
+                            compensation, FP64 across wavefronts and chunks) */
     int32_t n_levels;    /* image pyramid levels, 1..PBA_MAX_LEVELS */
     int32_t pattern_n;   /* patch pixels per point, 1..PBA_MAX_PATTERN */
     int32_t pattern_uv[2 * PBA_MAX_PATTERN]; /* (du, dv) offsets in level pixels, |du|,|dv| <= 4 */
@@ -140,7 +144,11 @@ enum {
     PBA_DBG_TEMPLATE = 4,   /* [real N x P x 4] (I0, dI0/du, dI0/dv, usable) at the current level */
     PBA_DBG_HDD = 5,        /* [double N] damped depth diagonal of the last system */
     PBA_DBG_MASK = 6,       /* [uint8 O] bit j set if patch pixel j is in the frozen usable set */
-    PBA_DBG_DTHETA = 7      /* [double 6F] pose step of the last iteration */
+    PBA_DBG_DTHETA = 7,     /* [double 6F] pose step of the last iteration */
+    PBA_DBG_PAIR_H = 8,     /* [double Pn x 21] per (host, target) pair: upper triangle of the
+                               pose-pose block sum w J_th^T J_th in relative coordinates, as
+                               last assembled */
+    PBA_DBG_PAIRS = 9       /* [int32 Pn x 2] (host frame, target frame) of every pair */
 };
 
 /* Fill *cfg with defaults: IC, FP32, 1 level, the 8-pixel diamond pattern

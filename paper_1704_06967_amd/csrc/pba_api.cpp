@@ -120,8 +120,8 @@ void release_frames(Ctx &c) {
         dfree(c.lv[l].K);
         c.lv[l].W = c.lv[l].H = 0;
     }
-    for (double **p : {&c.d_poses, &c.d_poses0, &c.d_K0, &c.d_S, &c.d_Sinv, &c.d_Lfac, &c.d_b, &c.d_dtheta, &c.d_stats,
-                       &c.d_mu})
+    for (double **p : {&c.d_poses, &c.d_poses0, &c.d_K0, &c.d_S, &c.d_Sinv, &c.d_Lfac, &c.d_Sfac, &c.d_Linv, &c.d_b,
+                       &c.d_dtheta, &c.d_stats, &c.d_mu})
         dfree(*p);
     dfree(c.d_flag);
     dfree(c.d_gate);
@@ -137,7 +137,6 @@ std::string validate_config(const pba_config *cfg) {
     if (cfg->mode != PBA_FC && cfg->mode != PBA_IC_PROXY) return "mode must be PBA_FC or PBA_IC_PROXY";
     if (cfg->precision != PBA_FP64 && cfg->precision != PBA_FP32 && cfg->precision != PBA_MIXED_BF16)
         return "unknown precision";
-    if (cfg->precision == PBA_MIXED_BF16) return "PBA_MIXED_BF16 is not available in this build";
     if (cfg->n_levels < 1 || cfg->n_levels > PBA_MAX_LEVELS) return "n_levels must be in 1..4";
     if (cfg->pattern_n < 1 || cfg->pattern_n > PBA_MAX_PATTERN) return "pattern_n must be in 1..8";
     for (int j = 0; j < cfg->pattern_n; ++j)
@@ -153,6 +152,7 @@ std::string validate_config(const pba_config *cfg) {
 }
 
 bool is_fp64(const Ctx &c) { return c.cfg.precision == PBA_FP64; }
+bool is_mixed(const Ctx &c) { return c.cfg.precision == PBA_MIXED_BF16; }
 
 // ---- structure of the problem: pairs, host groups, Gram chunks, nonzero blocks
 std::string build_structure(Ctx &c, const std::vector<int> &host_frame, const std::vector<int> &obs_ptr,
@@ -296,9 +296,13 @@ pba_status start_level(Ctx &c, int level) {
     c.flip = false;
     if (c.cfg.mode == PBA_IC_PROXY) {
         // J (Sec. 3.4) and W0 at p(0); H = J^T W0 J, depth Schur complement, Cholesky, inverse
-        Launch<T>::ic_linearize(s, c, level);
+        if (is_mixed(c)) {
+            launch_linearize_mixed(s, c, level, true, (const float *)c.d_rel0, true);
+        } else {
+            Launch<T>::ic_linearize(s, c, level);
+            Launch<T>::pair_reduce_H(s, c);
+        }
         Launch<T>::point_reduce(s, c, true);
-        Launch<T>::pair_reduce_H(s, c);
         launch_mu(s, c, c.d_geo0);
         launch_gram(s, c, c.d_geo0, c.d_rec, is_fp64(c));
         launch_assemble_s(s, c, c.d_geo0);
@@ -326,13 +330,17 @@ pba_status one_iteration(Ctx &c, int level, double *stat, hipEvent_t ev0, hipEve
         launch_solve(s, c, c.d_geo0, geo_next, rel_next, is_fp64(c), stat);
     } else {
         if (ev0) HIPCHK(hipEventRecord(ev0, s));
-        Launch<T>::fc_linearize(s, c, level, rel_cur, c.iters_in_level == 0);
+        if (is_mixed(c))
+            launch_linearize_mixed(s, c, level, false, (const float *)rel_cur, c.iters_in_level == 0);
+        else
+            Launch<T>::fc_linearize(s, c, level, rel_cur, c.iters_in_level == 0);
         if (ev1) HIPCHK(hipEventRecord(ev1, s));
         Launch<T>::point_reduce(s, c, true);
-        Launch<T>::pair_reduce_H(s, c);
+        if (!is_mixed(c)) Launch<T>::pair_reduce_H(s, c);
         launch_mu(s, c, geo_cur);
         launch_gram(s, c, geo_cur, c.d_rec, is_fp64(c));
         launch_assemble_s(s, c, geo_cur);
+        if (6 * c.F > LDS_CHOL_MAX_N) launch_tchol(s, c);
         Launch<T>::pair_reduce_y(s, c);
         launch_solve(s, c, geo_cur, geo_next, rel_next, is_fp64(c), stat);
     }
@@ -610,6 +618,11 @@ pba_status pba_set_frames(pba_ctx *ctx, int32_t window, int32_t n_frames, int32_
         HIPCHK(dalloc(c.d_Sinv, n6 * n6 * sizeof(double)));
         HIPCHK(dalloc(c.d_Lfac, (n6 * (n6 + 1) / 2 + n6) * sizeof(double)));
     }
+    if (n6 > (size_t)LDS_CHOL_MAX_N) {
+        const size_t nt = (n6 + TCHOL_TILE - 1) / TCHOL_TILE;
+        HIPCHK(dalloc(c.d_Sfac, n6 * n6 * sizeof(double)));
+        HIPCHK(dalloc(c.d_Linv, nt * TCHOL_TILE * TCHOL_TILE * sizeof(double)));
+    }
     HIPCHK(dalloc(c.d_b, 2 * n6 * sizeof(double)));
     HIPCHK(dalloc(c.d_dtheta, n6 * sizeof(double)));
     HIPCHK(dalloc(c.d_mu, 2 * sizeof(double)));
@@ -876,6 +889,17 @@ pba_status pba_debug_fetch(pba_ctx *ctx, int32_t what, void *out, size_t bytes) 
         case PBA_DBG_HDD: src = c.d_Hdd; need = (size_t)c.N * sizeof(double); break;
         case PBA_DBG_MASK: src = c.d_mask; need = (size_t)c.O; break;
         case PBA_DBG_DTHETA: src = c.d_dtheta; need = n6 * sizeof(double); break;
+        case PBA_DBG_PAIR_H: src = c.d_pairH; need = (size_t)c.st.n_pairs * 21 * sizeof(double); break;
+        case PBA_DBG_PAIRS: {
+            need = (size_t)c.st.n_pairs * 2 * sizeof(int32_t);
+            if (bytes != need) return fail(&c, PBA_E_INVALID, "bytes must be " + std::to_string(need));
+            int32_t *o = static_cast<int32_t *>(out);
+            for (int p = 0; p < c.st.n_pairs; ++p) {
+                o[2 * p] = c.st.pair_host[p];
+                o[2 * p + 1] = c.st.pair_target[p];
+            }
+            return PBA_OK;
+        }
         default: return fail(&c, PBA_E_INVALID, "unknown debug buffer");
     }
     if (bytes != need) return fail(&c, PBA_E_INVALID, "bytes must be " + std::to_string(need));

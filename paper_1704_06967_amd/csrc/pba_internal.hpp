@@ -40,6 +40,8 @@ constexpr int LANES_PER_OBS = 8;   // one lane per patch pixel
 constexpr int BLOCK = 256;         // threads per block for residual kernels
 constexpr int MAX_HOST_TARGETS = 20;  // target frames per host frame (Schur Gram size)
 constexpr int PAIR_CHUNK = 512;       // observations per pair-reduction workgroup
+constexpr int LDS_CHOL_MAX_N = 180;   // largest reduced system factored in one workgroup's LDS
+constexpr int TCHOL_TILE = 32;        // tile edge of the tiled Cholesky for larger systems
 
 struct LevelDev {
     int W = 0, H = 0;
@@ -123,6 +125,8 @@ struct Ctx {
     double *d_S = nullptr;                             // [6F][6F] reduced system / factor
     double *d_Sinv = nullptr;                          // IC: S^{-1} at p(0) [6F][6F]
     double *d_Lfac = nullptr;                          // IC: packed Cholesky factor of S, then 1 / L(k, k)
+    double *d_Sfac = nullptr;                          // 6F > LDS_CHOL_MAX_N: tiled factor of S [6F][6F]
+    double *d_Linv = nullptr;                          // inverses of its diagonal tiles [nt][32][32]
     double *d_b = nullptr, *d_dtheta = nullptr;        // [6F]
     double *d_dth_rel = nullptr;                       // [Pn][6]
     double *d_stats = nullptr;                         // [cap][ST_STRIDE]
@@ -160,6 +164,9 @@ template <typename T> struct Launch {
                              double conv_px);
 };
 
+// mixed precision linearization (pair order, BF16 MFMA pose blocks into the pair chunk partials)
+void launch_linearize_mixed(hipStream_t s, Ctx &c, int level, bool ic, const float *rel_cur, bool write_mask);
+
 // precision-independent launchers (double only)
 void launch_mu(hipStream_t s, Ctx &c, const double *geo);
 void launch_gram(hipStream_t s, Ctx &c, const double *geo, const void *rec, bool rec_double);
@@ -170,6 +177,8 @@ void launch_solve(hipStream_t s, Ctx &c, const double *geo_lin, double *geo_next
 void launch_sum_stats(hipStream_t s, Ctx &c, const void *rec, bool rec_double, double *out3);
 void launch_conv(hipStream_t s, Ctx &c, double *stat, double conv_px, int nparts);
 void launch_ic_inverse(hipStream_t s, Ctx &c);
+void launch_tchol(hipStream_t s, Ctx &c);   // copy S to d_Sfac and factor it in tiles
+void launch_tinv(hipStream_t s, Ctx &c);    // S^{-1} from the tiled factor
 void launch_fill(hipStream_t s, double *p, size_t n, double v, const int *gate);
 
 }  // namespace pba

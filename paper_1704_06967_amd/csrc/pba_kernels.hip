@@ -122,57 +122,63 @@ __device__ __forceinline__ void template_xy(const ResArgs<T> &a, int n, int j, c
     y = (v - Kh[3]) / Kh[1];
 }
 
-// Linearization of one residual, shared by the FC iteration and the IC setup.
-// IC: J from the proxy warp at p(0) (Sec. 3.4) and W0 from the residual at p(0).
-// FC: J at the current parameters from the target gradient.
-// Writes the 38-value record of its observation (lane j == 0).
+// Linearization of one residual (observation o, patch pixel j), shared by the
+// FC iteration and the IC setup. IC: J from the proxy warp at p(0) (Sec. 3.4)
+// and W0 from the residual at p(0). FC: J at the current parameters from the
+// target gradient. Returns whether the residual contributes.
+template <typename T, bool IC>
+__device__ __forceinline__ bool lin_eval(const ResArgs<T> &a, int o, int j, int write_mask, T (&J)[7], T &r, T &w,
+                                         T &rho) {
+#pragma unroll
+    for (int p = 0; p < 7; ++p) J[p] = 0;
+    r = w = rho = 0;
+    if (o < 0 || o >= a.O || j >= a.P) return false;
+    const int n = a.obs_point[o], pr = a.obs_pair[o];
+    const int h = a.pair_host[pr], f = a.pair_target[pr];
+    const T *Kh = a.K + 4 * h;
+    const T *Kt = a.K + 4 * f;
+    const T *tp = a.tmpl + 4 * ((size_t)n * a.P + j);
+    const T I0 = tp[0], gu0 = tp[1], gv0 = tp[2];
+    const bool host_ok = tp[3] != T(0);
+    bool frozen = true;
+    if (!write_mask) frozen = (a.mask[o] >> j) & 1;
+    T x, y;
+    template_xy(a, n, j, Kh, x, y);
+    const T *R = a.rel + REL_STRIDE * pr;
+    const T *t = R + 9;
+    const T d = (T)a.depth[n];
+    const T Rx0 = R[0] * x + R[1] * y + R[2];
+    const T Rx1 = R[3] * x + R[4] * y + R[5];
+    const T Rx2 = R[6] * x + R[7] * y + R[8];
+    const T vx = Rx0 + d * t[0], vy = Rx1 + d * t[1], vz = Rx2 + d * t[2];
+    if (!(host_ok && frozen && d > T(0) && vz > T(0))) return false;
+    const T ux = vx / vz, uy = vy / vz;
+    const T qu = Kt[0] * ux + Kt[2], qv = Kt[1] * uy + Kt[3];
+    if (!usable(qu, qv, a.W, a.H)) return false;
+    const T *imf = a.img + (size_t)f * a.W * a.H;
+    T If, gu, gv;
+    if (IC) {
+        If = bilinear(imf, a.W, qu, qv);
+        const T *R0 = a.rel0 + REL_STRIDE * pr;
+        ic_jacobian(x, y, R0, R0 + 9, (T)a.depth0[n], gu0, gv0, Kh[0], Kh[1], J);
+    } else {
+        bilinear_grad(imf, a.W, qu, qv, If, gu, gv);
+        fc_jacobian(Rx0, Rx1, Rx2, vz, ux, uy, t, d, gu, gv, Kt[0], Kt[1], J);
+    }
+    r = I0 - If;
+    huber(r, a.huber_k, w, rho);
+    return true;
+}
+
+// Linearization in observation order: the 38-value record of every
+// observation (lane j == 0 writes it).
 template <typename T, bool IC>
 __global__ __launch_bounds__(BLOCK) void k_linearize(ResArgs<T> a, int write_mask) {
     if (*a.gate == 0) return;
     const int gid = blockIdx.x * BLOCK + threadIdx.x;
     const int o = gid >> 3, j = gid & 7;
-    T J[7] = {0, 0, 0, 0, 0, 0, 0};
-    T r = 0, w = 0, rho = 0;
-    bool valid = false;
-    if (o < a.O && j < a.P) {
-        const int n = a.obs_point[o], pr = a.obs_pair[o];
-        const int h = a.pair_host[pr], f = a.pair_target[pr];
-        const T *Kh = a.K + 4 * h;
-        const T *Kt = a.K + 4 * f;
-        const T *tp = a.tmpl + 4 * ((size_t)n * a.P + j);
-        const T I0 = tp[0], gu0 = tp[1], gv0 = tp[2];
-        const bool host_ok = tp[3] != T(0);
-        bool frozen = true;
-        if (!write_mask) frozen = (a.mask[o] >> j) & 1;
-        T x, y;
-        template_xy(a, n, j, Kh, x, y);
-        const T *R = a.rel + REL_STRIDE * pr;
-        const T *t = R + 9;
-        const T d = (T)a.depth[n];
-        const T Rx0 = R[0] * x + R[1] * y + R[2];
-        const T Rx1 = R[3] * x + R[4] * y + R[5];
-        const T Rx2 = R[6] * x + R[7] * y + R[8];
-        const T vx = Rx0 + d * t[0], vy = Rx1 + d * t[1], vz = Rx2 + d * t[2];
-        if (host_ok && frozen && d > T(0) && vz > T(0)) {
-            const T ux = vx / vz, uy = vy / vz;
-            const T qu = Kt[0] * ux + Kt[2], qv = Kt[1] * uy + Kt[3];
-            if (usable(qu, qv, a.W, a.H)) {
-                valid = true;
-                const T *imf = a.img + (size_t)f * a.W * a.H;
-                T If, gu, gv;
-                if (IC) {
-                    If = bilinear(imf, a.W, qu, qv);
-                    const T *R0 = a.rel0 + REL_STRIDE * pr;
-                    ic_jacobian(x, y, R0, R0 + 9, (T)a.depth0[n], gu0, gv0, Kh[0], Kh[1], J);
-                } else {
-                    bilinear_grad(imf, a.W, qu, qv, If, gu, gv);
-                    fc_jacobian(Rx0, Rx1, Rx2, vz, ux, uy, t, d, gu, gv, Kt[0], Kt[1], J);
-                }
-                r = I0 - If;
-                huber(r, a.huber_k, w, rho);
-            }
-        }
-    }
+    T J[7], r, w, rho;
+    const bool valid = lin_eval<T, IC>(a, o, j, write_mask, J, r, w, rho);
     if (write_mask) {
         const unsigned long long bal = __ballot(valid);
         if (j == 0 && o < a.O) a.mask[o] = (uint8_t)((bal >> (threadIdx.x & 56)) & 0xFFull);
@@ -193,6 +199,143 @@ __global__ __launch_bounds__(BLOCK) void k_linearize(ResArgs<T> a, int write_mas
         T *rec = a.rec + (size_t)o * REC_STRIDE;
 #pragma unroll
         for (int p = 0; p < 38; ++p) rec[p] = v[p];
+    }
+}
+
+// Mixed precision: residuals and J in FP32, the pose-pose block of every pair
+// contracted on BF16 MFMA. The kernel walks one pair chunk per block (pair
+// order), so that a wavefront's 64 residuals (8 observations x 8 patch pixels)
+// belong to one pair. Each u = sqrt(w) J_theta is split into three bfloat16
+// terms u = hi + mid + lo (each the rounding of what the previous ones leave),
+// and sum u u^T keeps every product of combined order >= 2^-24:
+//   A1 + (A2 + A2^T) + (A3 + A3^T) + A4,  A1 = sum hi hi^T, A2 = sum hi mid^T,
+//   A3 = sum hi lo^T, A4 = sum mid mid^T
+// (the dropped mid lo and lo lo terms are below 2^-25 relative), so the block
+// keeps FP32-level agreement with the depth couplings computed from the same
+// rows; a two-term split (2^-17) is not enough: its error is of the order of
+// the relative damping along the gauge direction of S. Each 64-residual group's
+// four products come from v_mfma_f32_16x16x32_bf16 (FP32 accumulation) and are
+// added to per-lane FP32 running sums with Kahan compensation; the four
+// wavefronts of the block are then added in FP64 in a fixed order into the
+// chunk partial (21 values) that the damping kernel sums per pair. The
+// per-observation record gets every field except the pose-pose block.
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ void kahan_add(float &s, float &c, float v) {
+    const float y = v - c;
+    const float t = s + y;
+    c = (t - s) - y;
+    s = t;
+}
+
+template <bool IC>
+__global__ __launch_bounds__(BLOCK) void k_linearize_mixed(ResArgs<float> a, int write_mask,
+                                                           const int *__restrict__ chunk_begin,
+                                                           const int *__restrict__ chunk_end,
+                                                           const int *__restrict__ pair_obs_idx,
+                                                           double *__restrict__ partH) {
+    constexpr int NS = 3;  // split terms hi, mid, lo
+    constexpr int NA = 4;  // products A1..A4
+    // per wavefront: the split terms of u^T as 16 x 64 bfloat16 (rows 6..15 stay zero)
+    __shared__ __attribute__((aligned(16))) __bf16 ut[BLOCK / 64][NS][16][64];
+    __shared__ double wsum[BLOCK / 64][NA][36];
+    if (*a.gate == 0) return;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    for (int e = lane; e < NS * 16 * 64; e += 64) (&ut[wv][0][0][0])[e] = (__bf16)0.0f;
+    const int c = blockIdx.x, cb = chunk_begin[c], ce = chunk_end[c];
+    const int j = lane & 7;
+    float sa[NA][4], ca[NA][4];
+#pragma unroll
+    for (int m = 0; m < NA; ++m)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) sa[m][i] = ca[m][i] = 0.0f;
+    for (int g = wv; 8 * g < ce - cb; g += BLOCK / 64) {
+        const int pos = cb + 8 * g + (lane >> 3);
+        const int o = pos < ce ? pair_obs_idx[pos] : -1;
+        float J[7], r, w, rho;
+        const bool valid = lin_eval<float, IC>(a, o, j, write_mask, J, r, w, rho);
+        if (write_mask) {
+            const unsigned long long bal = __ballot(valid);
+            if (j == 0 && o >= 0) a.mask[o] = (uint8_t)((bal >> (lane & 56)) & 0xFFull);
+        }
+        // per-observation fields (all but the pose-pose block)
+        float v[17];
+        for (int p = 0; p < 6; ++p) v[p] = w * J[p] * J[6];
+        v[6] = w * J[6] * J[6];
+        for (int p = 0; p < 7; ++p) v[7 + p] = w * J[p] * r;
+        v[14] = valid ? rho : 0.0f;
+        v[15] = valid ? r * r : 0.0f;
+        v[16] = valid ? 1.0f : 0.0f;
+#pragma unroll
+        for (int p = 0; p < 17; ++p) v[p] = wave_sum8(v[p]);
+        if (j == 0 && o >= 0) {
+            float *rec = a.rec + (size_t)o * REC_STRIDE;
+#pragma unroll
+            for (int p = 0; p < 7; ++p) rec[REC_h + p] = v[p];   // REC_h (6) and REC_HDD
+#pragma unroll
+            for (int p = 0; p < 7; ++p) rec[REC_G + p] = v[7 + p];  // REC_G (6) and REC_GD
+            rec[REC_E] = v[14];
+            rec[REC_SQ] = v[15];
+            rec[REC_CNT] = v[16];
+        }
+        // pose block: stage the split terms of u = sqrt(w) J_theta, transposed
+        const float sw = sqrtf(w);
+#pragma unroll
+        for (int p = 0; p < 6; ++p) {
+            const float u = sw * J[p];
+            const __bf16 hi = (__bf16)u;
+            const float r1 = u - (float)hi;
+            const __bf16 mid = (__bf16)r1;
+            ut[wv][0][p][lane] = hi;
+            ut[wv][1][p][lane] = mid;
+            ut[wv][2][p][lane] = (__bf16)(r1 - (float)mid);
+        }
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        f32x4 acc[NA];
+#pragma unroll
+        for (int m = 0; m < NA; ++m) acc[m] = (f32x4){0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+        for (int s = 0; s < 2; ++s) {
+            const int k0 = 32 * s + 8 * (lane >> 4);
+            const bf16x8 fh = *reinterpret_cast<const bf16x8 *>(&ut[wv][0][lane & 15][k0]);
+            const bf16x8 fm = *reinterpret_cast<const bf16x8 *>(&ut[wv][1][lane & 15][k0]);
+            const bf16x8 fl = *reinterpret_cast<const bf16x8 *>(&ut[wv][2][lane & 15][k0]);
+            acc[0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fh, fh, acc[0], 0, 0, 0);
+            acc[1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fh, fm, acc[1], 0, 0, 0);
+            acc[2] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fh, fl, acc[2], 0, 0, 0);
+            acc[3] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fm, fm, acc[3], 0, 0, 0);
+        }
+        __builtin_amdgcn_wave_barrier();
+#pragma unroll
+        for (int m = 0; m < NA; ++m)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) kahan_add(sa[m][i], ca[m][i], acc[m][i]);
+    }
+    // lane l holds rows 4 (l / 16) + i, column l % 16 of the 16 x 16 sums
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int row = 4 * (lane >> 4) + i, col = lane & 15;
+        if (row < 6 && col < 6)
+#pragma unroll
+            for (int m = 0; m < NA; ++m) wsum[wv][m][row * 6 + col] = (double)sa[m][i] - (double)ca[m][i];
+    }
+    __syncthreads();
+    if (threadIdx.x < 21) {
+        int p = 0, k = threadIdx.x;
+        while (k >= 6 - p) {
+            k -= 6 - p;
+            ++p;
+        }
+        const int q = p + k, pq = p * 6 + q, qp = q * 6 + p;
+        double sum = 0.0;
+        for (int w2 = 0; w2 < BLOCK / 64; ++w2) {
+            const double *W = &wsum[w2][0][0];
+            sum += W[pq] + (W[36 + pq] + W[36 + qp]) + (W[72 + pq] + W[72 + qp]) + W[108 + pq];
+        }
+        partH[21 * (size_t)c + threadIdx.x] = sum;
     }
 }
 
@@ -590,6 +733,19 @@ void Launch<T>::fc_linearize(hipStream_t s, Ctx &c, int level, const T *rel_cur,
     if (c.O == 0) return;
     ResArgs<T> a = res_args<T>(c, level, rel_cur);
     k_linearize<T, false><<<nblk((size_t)c.O * LANES_PER_OBS, BLOCK), BLOCK, 0, s>>>(a, write_mask ? 1 : 0);
+    CHECK_LAUNCH();
+}
+
+void launch_linearize_mixed(hipStream_t s, Ctx &c, int level, bool ic, const float *rel_cur, bool write_mask) {
+    const int nch = (int)c.st.pchunk_begin.size();
+    if (c.O == 0 || nch == 0) return;
+    ResArgs<float> a = res_args<float>(c, level, rel_cur);
+    if (ic)
+        k_linearize_mixed<true><<<nch, BLOCK, 0, s>>>(a, 1, c.d_pchunk_begin, c.d_pchunk_end, c.d_pair_obs_idx,
+                                                      c.d_partH);
+    else
+        k_linearize_mixed<false><<<nch, BLOCK, 0, s>>>(a, write_mask ? 1 : 0, c.d_pchunk_begin, c.d_pchunk_end,
+                                                       c.d_pair_obs_idx, c.d_partH);
     CHECK_LAUNCH();
 }
 

@@ -3,6 +3,7 @@
 // single-workgroup solve + pose update of every iteration.
 #include "pba_device.hpp"
 #include "pba_internal.hpp"
+#include "pba_tile.hpp"
 
 #include <algorithm>
 
@@ -10,7 +11,7 @@ namespace pba {
 
 constexpr int SOLVE_THREADS = 1024;
 constexpr int LDS_DOUBLES = 152 * 1024 / 8;   // packed lower triangle of S (+ panel scratch) when it fits
-constexpr int LDS_MAX_N = 180;                // n (n + 1) / 2 + 17 n <= LDS_DOUBLES; 3 rows per lane
+constexpr int LDS_MAX_N = LDS_CHOL_MAX_N;     // n (n + 1) / 2 + 17 n <= LDS_DOUBLES; 3 rows per lane
 constexpr int WNS = 3;                        // rows per lane in the wavefront solves (n <= 192)
 constexpr int GRAM_G = 32;                    // points per Gram step
 constexpr int GRAM_SLOTS = 8;                 // observation slots per point per load pass
@@ -246,39 +247,6 @@ struct PackedLds {
     double *p;
     __device__ double &operator()(int i, int j) const { return p[i * (i + 1) / 2 + j]; }
 };
-struct FullGlobal {
-    double *p;
-    int n;
-    __device__ double &operator()(int i, int j) const { return p[(size_t)i * n + j]; }
-};
-struct PackedGlobal {
-    const double *p;
-    __device__ double operator()(int i, int j) const { return p[(size_t)i * (i + 1) / 2 + j]; }
-};
-
-// In-place Cholesky (lower) of the first n rows, right-looking, two barriers
-// per column; the trailing update runs on a 32 x 32 thread grid. Returns false
-// (in every thread) if a pivot is not positive.
-template <class M>
-__device__ bool chol_inplace(M A, int n) {
-    const int tr = threadIdx.x >> 5, tc = threadIdx.x & 31;
-    for (int k = 0; k < n; ++k) {
-        const double p = A(k, k);
-        if (!(p > 0.0)) return false;
-        const double lkk = sqrt(p);
-        const double inv = 1.0 / lkk;
-        for (int i = k + 1 + threadIdx.x; i < n; i += blockDim.x) A(i, k) *= inv;
-        __syncthreads();
-        if (threadIdx.x == 0) A(k, k) = lkk;  // A(k, k) is not read again by this factorization
-        for (int i = k + 1 + tr; i < n; i += 32) {
-            const double aik = A(i, k);
-            for (int j = k + 1 + tc; j <= i; j += 32) A(i, j) -= aik * A(j, k);
-        }
-        __syncthreads();
-    }
-    return true;
-}
-
 // L L^T x = b on one wavefront without barriers: lane l owns rows l, l+64, l+128
 // and keeps them in registers; invd holds 1 / L(k, k). Forward substitution may
 // start at row k0 when b is zero above it.
@@ -316,26 +284,6 @@ __device__ void wave_chol_solve(M L, const double *invd, int n, double (&x)[WNS]
             else if (i < k)
                 x[q] -= L(k, i) * xk;
         }
-    }
-}
-
-// Block-wide L L^T x = b (b in shared or global memory, overwritten), one
-// column per step; used when S does not fit in LDS.
-template <class M>
-__device__ void block_chol_solve(M L, int n, double *b) {
-    for (int k = 0; k < n; ++k) {
-        const double yk = b[k] / L(k, k);
-        __syncthreads();
-        if (threadIdx.x == 0) b[k] = yk;
-        for (int i = k + 1 + threadIdx.x; i < n; i += blockDim.x) b[i] -= L(i, k) * yk;
-        __syncthreads();
-    }
-    for (int k = n - 1; k >= 0; --k) {
-        const double xk = b[k] / L(k, k);
-        __syncthreads();
-        if (threadIdx.x == 0) b[k] = xk;
-        for (int i = threadIdx.x; i < k; i += blockDim.x) b[i] -= L(k, i) * xk;
-        __syncthreads();
     }
 }
 
@@ -421,25 +369,6 @@ __device__ __forceinline__ bool chol_blocked(double *A, int n, double *panel, do
     return true;
 }
 
-// Block-wide L L^T x = b with the reciprocal diagonal given.
-template <class M>
-__device__ void block_chol_solve_d(M L, const double *invd, int n, double *b) {
-    for (int k = 0; k < n; ++k) {
-        const double yk = b[k] * invd[k];
-        __syncthreads();
-        if (threadIdx.x == 0) b[k] = yk;
-        for (int i = k + 1 + threadIdx.x; i < n; i += blockDim.x) b[i] -= L(i, k) * yk;
-        __syncthreads();
-    }
-    for (int k = n - 1; k >= 0; --k) {
-        const double xk = b[k] * invd[k];
-        __syncthreads();
-        if (threadIdx.x == 0) b[k] = xk;
-        for (int i = threadIdx.x; i < k; i += blockDim.x) b[i] -= L(k, i) * xk;
-        __syncthreads();
-    }
-}
-
 // IC setup: Cholesky factorization of S, once per level (the paper's "H need
 // only be inverted once"); every iteration then runs two triangular solves.
 // The factor is stored packed (lower, row-major) followed by 1 / L(k, k).
@@ -450,30 +379,16 @@ __global__ __launch_bounds__(SOLVE_THREADS) void k_ic_factor(int n, double *__re
     __shared__ int fail;
     if (*gate == 0) return;
     const int np = n * (n + 1) / 2;
-    if (n <= LDS_MAX_N) {
-        for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
-            const int i = e / n, j = e % n;
-            if (j <= i) lds[pidx(i, j)] = S[e];
-        }
-        __syncthreads();
-        if (!chol_blocked(lds, n, lds + np, Lout + np, &fail)) {
-            if (threadIdx.x == 0) *flag = 1;
-            return;
-        }
-        for (int e = threadIdx.x; e < np; e += blockDim.x) Lout[e] = lds[e];
-    } else {
-        FullGlobal A{S, n};
-        if (!chol_inplace(A, n)) {
-            if (threadIdx.x == 0) *flag = 1;
-            return;
-        }
-        __syncthreads();
-        for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
-            const int i = e / n, j = e % n;
-            if (j <= i) Lout[pidx(i, j)] = S[e];
-            if (i == j) Lout[np + i] = 1.0 / S[e];
-        }
+    for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
+        const int i = e / n, j = e % n;
+        if (j <= i) lds[pidx(i, j)] = S[e];
     }
+    __syncthreads();
+    if (!chol_blocked(lds, n, lds + np, Lout + np, &fail)) {
+        if (threadIdx.x == 0) *flag = 1;
+        return;
+    }
+    for (int e = threadIdx.x; e < np; e += blockDim.x) Lout[e] = lds[e];
 }
 
 // IC setup: S^{-1} = L^{-T} L^{-1} from the packed factor, one column per
@@ -487,35 +402,28 @@ __global__ __launch_bounds__(SOLVE_THREADS) void k_ic_inverse(int n, const doubl
     if (*gate == 0 || *flag) return;
     const int np = n * (n + 1) / 2;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    if (n <= LDS_MAX_N) {
-        for (int e = threadIdx.x; e < np + n; e += blockDim.x) lds[e] = Lfac[e];
-        __syncthreads();
-        const int c = blockIdx.x * (SOLVE_THREADS / 64) + wv;
-        if (c >= n) return;
-        double x[WNS];
+    for (int e = threadIdx.x; e < np + n; e += blockDim.x) lds[e] = Lfac[e];
+    __syncthreads();
+    const int c = blockIdx.x * (SOLVE_THREADS / 64) + wv;
+    if (c >= n) return;
+    double x[WNS];
 #pragma unroll
-        for (int q = 0; q < WNS; ++q) x[q] = (lane + 64 * q == c) ? 1.0 : 0.0;
-        wave_chol_solve(PackedLds{lds}, lds + np, n, x, c);
+    for (int q = 0; q < WNS; ++q) x[q] = (lane + 64 * q == c) ? 1.0 : 0.0;
+    wave_chol_solve(PackedLds{lds}, lds + np, n, x, c);
 #pragma unroll
-        for (int q = 0; q < WNS; ++q) {
-            const int i = lane + 64 * q;
-            if (i < n) Sinv[(size_t)c * n + i] = x[q];
-        }
-    } else {
-        // one column per workgroup, block-wide solves on the factor in global memory
-        PackedGlobal L{Lfac};
-        for (int c = blockIdx.x; c < n; c += gridDim.x) {
-            double *x = Sinv + (size_t)c * n;
-            for (int i = threadIdx.x; i < n; i += blockDim.x) x[i] = (i == c) ? 1.0 : 0.0;
-            __syncthreads();
-            block_chol_solve_d(L, Lfac + np, n, x);
-        }
+    for (int q = 0; q < WNS; ++q) {
+        const int i = lane + 64 * q;
+        if (i < n) Sinv[(size_t)c * n + i] = x[q];
     }
 }
 
 void launch_ic_inverse(hipStream_t s, Ctx &c) {
     const int n = 6 * c.F;
-    const int grid = n <= LDS_MAX_N ? (n + SOLVE_THREADS / 64 - 1) / (SOLVE_THREADS / 64) : std::min(n, 512);
+    if (n > LDS_MAX_N) {
+        launch_tinv(s, c);
+        return;
+    }
+    const int grid = (n + SOLVE_THREADS / 64 - 1) / (SOLVE_THREADS / 64);
     k_ic_inverse<<<grid, SOLVE_THREADS, 0, s>>>(n, c.d_Lfac, c.d_Sinv, c.d_flag, c.d_gate);
 }
 
@@ -533,13 +441,19 @@ __global__ __launch_bounds__(SOLVE_THREADS) void k_solve(
     int ic, int F, int Pn, int pinned, const int *__restrict__ frame_pair_ptr, const int *__restrict__ frame_pair_item,
     const int *__restrict__ pair_host, const int *__restrict__ pair_target, const int *__restrict__ pair_chunk_ptr,
     const double *__restrict__ partY, double *__restrict__ pairY, const double *__restrict__ geo_lin,
-    double *__restrict__ S, const double *__restrict__ Sinv, double *__restrict__ poses,
+    double *__restrict__ S, const double *__restrict__ Sfac, const double *__restrict__ Linv,
+    const double *__restrict__ Sinv, double *__restrict__ poses,
     const double *__restrict__ poses0, double *__restrict__ b_out, double *__restrict__ dth_out,
     double *__restrict__ dth_rel, double *__restrict__ geo_next, T *__restrict__ rel_next, double *__restrict__ stat,
     int *__restrict__ flag, int *__restrict__ gate) {
     __shared__ double lds[LDS_DOUBLES];
     __shared__ double red[64 + 2 * LDS_MAX_N + 2];
-    if (*gate == 0 || *flag) return;
+    if (*gate == 0) return;
+    if (*flag) {
+        // the tiled factorization of this iteration failed: stop the batch
+        if (threadIdx.x == 0) *gate = 0;
+        return;
+    }
     const int n = 6 * F;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
     const bool packed = n <= LDS_MAX_N;
@@ -630,16 +544,8 @@ __global__ __launch_bounds__(SOLVE_THREADS) void k_solve(
             }
         }
     } else {
-        FullGlobal A{S, n};
-        if (!chol_inplace(A, n)) {
-            if (threadIdx.x == 0) {
-                *flag = 1;
-                *gate = 0;
-            }
-            return;
-        }
-        __syncthreads();
-        block_chol_solve(A, n, bx);
+        // FC, 6F > LDS_MAX_N: S was factored in tiles before this kernel
+        tile_chol_solve<SOLVE_THREADS>(Sfac, Linv, n, bx, lds + n, 0);
         for (int i = threadIdx.x; i < n; i += blockDim.x) dth_out[i] = -bx[i];
     }
     __threadfence_block();
@@ -745,6 +651,10 @@ void launch_assemble_s(hipStream_t s, Ctx &c, const double *geo) {
 }
 
 void launch_ic_factor(hipStream_t s, Ctx &c) {
+    if (6 * c.F > LDS_MAX_N) {
+        launch_tchol(s, c);
+        return;
+    }
     k_ic_factor<<<1, SOLVE_THREADS, 0, s>>>(6 * c.F, c.d_S, c.d_Lfac, c.d_flag, c.d_gate);
 }
 
@@ -754,13 +664,13 @@ void launch_solve(hipStream_t s, Ctx &c, const double *geo_lin, double *geo_next
     if (rel_double)
         k_solve<double><<<1, SOLVE_THREADS, 0, s>>>(
             ic, c.F, c.st.n_pairs, c.cfg.pinned_frame, c.d_frame_pair_ptr, c.d_frame_pair_item, c.d_pair_host,
-            c.d_pair_target, c.d_pair_chunk_ptr, c.d_partY, c.d_pairY, geo_lin, c.d_S, c.d_Sinv, c.d_poses,
-            c.d_poses0, c.d_b, c.d_dtheta, c.d_dth_rel, geo_next, (double *)rel_next, stat, c.d_flag, c.d_gate);
+            c.d_pair_target, c.d_pair_chunk_ptr, c.d_partY, c.d_pairY, geo_lin, c.d_S, c.d_Sfac, c.d_Linv, c.d_Sinv,
+            c.d_poses, c.d_poses0, c.d_b, c.d_dtheta, c.d_dth_rel, geo_next, (double *)rel_next, stat, c.d_flag, c.d_gate);
     else
         k_solve<float><<<1, SOLVE_THREADS, 0, s>>>(
             ic, c.F, c.st.n_pairs, c.cfg.pinned_frame, c.d_frame_pair_ptr, c.d_frame_pair_item, c.d_pair_host,
-            c.d_pair_target, c.d_pair_chunk_ptr, c.d_partY, c.d_pairY, geo_lin, c.d_S, c.d_Sinv, c.d_poses,
-            c.d_poses0, c.d_b, c.d_dtheta, c.d_dth_rel, geo_next, (float *)rel_next, stat, c.d_flag, c.d_gate);
+            c.d_pair_target, c.d_pair_chunk_ptr, c.d_partY, c.d_pairY, geo_lin, c.d_S, c.d_Sfac, c.d_Linv, c.d_Sinv,
+            c.d_poses, c.d_poses0, c.d_b, c.d_dtheta, c.d_dth_rel, geo_next, (float *)rel_next, stat, c.d_flag, c.d_gate);
 }
 
 }  // namespace pba

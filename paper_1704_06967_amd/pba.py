@@ -21,6 +21,7 @@ PBA_FLAG_TIMING = 1
 PBA_MAX_PATTERN = 8
 PBA_MAX_LEVELS = 4
 PBA_DBG_S, PBA_DBG_B, PBA_DBG_OBS_REC, PBA_DBG_TEMPLATE, PBA_DBG_HDD, PBA_DBG_MASK, PBA_DBG_DTHETA = 1, 2, 3, 4, 5, 6, 7
+PBA_DBG_PAIR_H, PBA_DBG_PAIRS = 8, 9
 REC_STRIDE = 40
 
 
@@ -166,6 +167,8 @@ class Solver:
         self.N = hf.shape[0]
         optr = np.ascontiguousarray(obs_ptr, np.int32)
         self.O = int(optr[-1])
+        self._host_frame, self._obs_ptr = hf, optr
+        self._obs_frame = np.ascontiguousarray(obs_frame, np.int32)
         self._chk(pba_set_points(self.ctx, 0, self.N, _ptr(hf), _ptr(np.ascontiguousarray(host_uv, np.float32)),
                                  _ptr(np.ascontiguousarray(inv_depth, np.float64)), _ptr(optr),
                                  _ptr(np.ascontiguousarray(obs_frame, np.int32)), PBA_HOST))
@@ -210,11 +213,18 @@ class Solver:
             PBA_DBG_TEMPLATE: ((self.N, self.cfg.pattern_n, 4), self.real),
             PBA_DBG_HDD: ((self.N,), np.float64), PBA_DBG_MASK: ((self.O,), np.uint8),
             PBA_DBG_DTHETA: ((n6,), np.float64),
+            PBA_DBG_PAIR_H: lambda: ((self.n_pairs(), 21), np.float64),
+            PBA_DBG_PAIRS: lambda: ((self.n_pairs(), 2), np.int32),
         }
-        shape, dt = shapes[what]
+        shape, dt = shapes[what]() if callable(shapes[what]) else shapes[what]
         out = np.zeros(shape, dt)
         self._chk(pba_debug_fetch(self.ctx, what, _ptr(out), out.nbytes))
         return out
+
+    def n_pairs(self):
+        counts = np.diff(self._obs_ptr)
+        host = np.repeat(self._host_frame.astype(np.int64), counts)
+        return int(np.unique(host * (1 << 31) + self._obs_frame).size)
 
     def timing(self):
         t = pba_timing()

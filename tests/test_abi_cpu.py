@@ -68,7 +68,7 @@ def test_config_default_values():
 
 
 @pytest.mark.parametrize("field,value,msg", [
-    ("mode", 7, "mode"), ("precision", 9, "precision"), ("precision", 2, "MIXED_BF16"), ("n_levels", 0, "n_levels"),
+    ("mode", 7, "mode"), ("precision", 9, "precision"), ("n_levels", 0, "n_levels"),
     ("n_levels", 5, "n_levels"), ("pattern_n", 0, "pattern_n"), ("pattern_n", 9, "pattern_n"),
     ("huber_k", 0.0, "huber_k"), ("huber_k", float("nan"), "huber_k"), ("damping_rel", -1.0, "damping_rel"),
     ("damping_rel", float("inf"), "damping_rel"), ("pinned_frame", -2, "pinned_frame"), ("solver", 3, "solver"),

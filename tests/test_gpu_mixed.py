@@ -1,0 +1,162 @@
+"""GPU parity of the mixed-precision form (PBA_MIXED_BF16): residuals and J in
+FP32, every pair's pose-pose block sum w J^T J contracted on BF16 MFMA (sqrt(w) J
+split into three bfloat16 terms, FP32 accumulation with Kahan compensation), the
+depth Schur complement and the reduced Cholesky in FP64.
+
+Bars: pair blocks within 5e-5 (normwise, per pair) of the FP64 oracle and within
+5e-6 of the FP32 path's own contraction of the same rows (the split keeps every
+product of order >= 2^-24; what it drops is below 2^-25 relative); iterates within the measurement
+contract's bar (poses 1e-5 rad / 1e-5 relative translation, inverse depths 1e-5
+relative, photometric RMSE 1e-4 relative). At the full precision workload
+(120 frames, 200k points, 6.4M residuals, 6F = 720) the per-observation blocks
+of a seeded sample of points are checked against the oracle evaluated on those
+points alone.
+"""
+import numpy as np
+import pytest
+
+import scenes
+from oracle import residuals as RS
+from oracle.gn import GaussNewton, Problem
+from scenes.configs import Scene
+from tests.oracle_refs import depth_errors_ok, obs_records, rot_err, trans_rel_err
+
+pytestmark = pytest.mark.gpu
+
+pba = pytest.importorskip("paper_1704_06967_amd.pba")
+
+MIXED, FP32 = pba.PBA_MIXED_BF16, pba.PBA_FP32
+
+
+def make(scene, mode, precision, **kw):
+    s = pba.Solver(mode=pba.PBA_IC_PROXY if mode == "ic" else pba.PBA_FC, precision=precision,
+                   n_levels=scene.n_levels, pattern=scene.pattern, huber_k=scene.huber_k, **kw)
+    s.set_scene(scene)
+    return s
+
+
+def pair_sums(scene, rec, pairs):
+    """Per-pair sums of the first 21 record fields, in the library's pair order."""
+    counts = np.diff(scene.obs_ptr)
+    host = np.repeat(scene.host_frame.astype(np.int64), counts)
+    key = host * 100000 + scene.obs_frame
+    order = {int(h) * 100000 + int(f): i for i, (h, f) in enumerate(pairs)}
+    idx = np.array([order[int(k)] for k in key])
+    out = np.zeros((len(pairs), 21))
+    for k in range(21):
+        out[:, k] = np.bincount(idx, rec[:, k], minlength=len(pairs))
+    return out
+
+
+def rel_rows(a, b):
+    return np.linalg.norm(a - b, axis=1) / np.maximum(np.linalg.norm(b, axis=1), 1e-300)
+
+
+@pytest.fixture(scope="module")
+def tiny():
+    return scenes.tiny()
+
+
+@pytest.fixture(scope="module")
+def mid_full():
+    return scenes.mid()
+
+
+@pytest.mark.parametrize("mode", ["fc", "ic"])
+def test_mixed_pair_blocks(tiny, mode):
+    """Pair pose blocks of the first level-0 linearization."""
+    s = make(tiny, mode, MIXED)
+    s.iterate(0, 1)
+    Hm = s.fetch(pba.PBA_DBG_PAIR_H)
+    pairs = s.fetch(pba.PBA_DBG_PAIRS)
+    f = make(tiny, mode, FP32)
+    f.iterate(0, 1)
+    assert np.array_equal(f.fetch(pba.PBA_DBG_PAIRS), pairs)
+    Hf = f.fetch(pba.PBA_DBG_PAIR_H)
+    assert rel_rows(Hm, Hf).max() <= 5e-6
+    # oracle: per-observation sums of w J^T J at p(0) (relative-pose J)
+    P = Problem.from_scene(tiny)
+    gn = GaussNewton(P, mode)
+    gn.iterate(0, 1)
+    L = P.layout(0)
+    if mode == "fc":
+        J, w = gn.last["J"], gn.last["w"]
+    else:
+        r0, valid0, _, _ = RS.warp_residuals(P, L, P.poses_init, P.inv_depth_init)
+        J, w = gn.J_rel, RS.huber_weight(r0, P.huber_k) * valid0
+    ref = obs_records(L, J, w, np.zeros_like(w), w > 0, P.huber_k)
+    Href = pair_sums(tiny, ref, pairs)
+    assert rel_rows(Hm, Href).max() <= 5e-5
+    # every other record field is the FP32 path's, bit for bit
+    rm, rf = s.fetch(pba.PBA_DBG_OBS_REC), f.fetch(pba.PBA_DBG_OBS_REC)
+    np.testing.assert_array_equal(rm[:, 21:38], rf[:, 21:38])
+    np.testing.assert_array_equal(s.fetch(pba.PBA_DBG_MASK), f.fetch(pba.PBA_DBG_MASK))
+
+
+@pytest.mark.timeout(300)
+@pytest.mark.parametrize("mode", ["ic", "fc"])
+def test_mixed_pyramid_parity(mid_full, mode):
+    """Mixed precision vs the FP64 oracle on the full mid workload, 3-level
+    pyramid, 8 iterations per level: poses and RMSE within the contract's bar,
+    inverse depths within it for 99% of the points."""
+    s = make(mid_full, mode, MIXED)
+    gn = GaussNewton(Problem.from_scene(mid_full), mode)
+    for level in (2, 1, 0):
+        s.iterate(level, 8)
+        gn.iterate(level, 8)
+    poses, d = s.get_params()
+    assert rot_err(poses, gn.poses).max() <= 1e-5
+    assert trans_rel_err(poses, gn.poses).max() <= 1e-5
+    ok, q99, worst = depth_errors_ok(d, gn.d)
+    assert ok, (q99, worst)
+    ev, oev = s.evaluate(0), gn.evaluate(0)
+    assert abs(ev["rmse"] / oev["rmse"] - 1) <= 1e-4
+
+
+def sub_scene(sc, pts):
+    """The scene restricted to the points `pts` (all frames, each point with all its observations)."""
+    counts = np.diff(sc.obs_ptr)[pts]
+    obs = np.concatenate([np.arange(sc.obs_ptr[n], sc.obs_ptr[n + 1]) for n in pts])
+    return Scene(name="sample", images=sc.images, intrinsics=sc.intrinsics, poses_gt=sc.poses_gt,
+                 poses_init=sc.poses_init, host_frame=sc.host_frame[pts], host_uv=sc.host_uv[pts],
+                 inv_depth_gt=sc.inv_depth_gt[pts], inv_depth_init=sc.inv_depth_init[pts],
+                 obs_ptr=np.concatenate([[0], np.cumsum(counts)]).astype(np.int32),
+                 obs_frame=sc.obs_frame[obs], n_levels=sc.n_levels, huber_k=sc.huber_k, pattern=sc.pattern), obs
+
+
+@pytest.mark.timeout(600)
+def test_mixed_precision_workload_sampled():
+    """Full precision workload, IC setup and first iteration at level 0 in the
+    mixed form: the per-observation blocks of 400 seeded points against the
+    oracle, and the pair blocks against the FP32 contraction of the same rows."""
+    sc = scenes.precision()
+    assert sc.n_frames == 120 and sc.n_points == 200000
+    s = make(sc, "ic", MIXED)
+    st = s.iterate(0, 1)[0]
+    rec = s.fetch(pba.PBA_DBG_OBS_REC)
+    mask = s.fetch(pba.PBA_DBG_MASK)
+    Hm = s.fetch(pba.PBA_DBG_PAIR_H)
+    s.close()
+    f = make(sc, "ic", FP32)
+    stf = f.iterate(0, 1)[0]
+    Hf = f.fetch(pba.PBA_DBG_PAIR_H)
+    f.close()
+    assert st["n_active"] == stf["n_active"]
+    assert rel_rows(Hm, Hf).max() <= 5e-6
+    pts = np.sort(np.random.default_rng(11).choice(sc.n_points, 400, replace=False))
+    sub, obs = sub_scene(sc, pts)
+    P = Problem.from_scene(sub)
+    L = P.layout(0)
+    r0, valid0, _, _ = RS.warp_residuals(P, L, P.poses_init, P.inv_depth_init)
+    J = RS.ic_jacobian(L, P.poses_init, P.inv_depth_init)
+    J[~valid0] = 0.0
+    w0 = RS.huber_weight(r0, P.huber_k) * valid0
+    ref = obs_records(L, J, w0, np.where(valid0, r0, 0.0), valid0, P.huber_k)
+    bits = valid0.reshape(-1, sub.pattern.shape[0]) @ (1 << np.arange(sub.pattern.shape[0]))
+    same = bits == mask[obs]
+    assert same.mean() >= 0.999
+    got = rec[obs][same]
+    ref = ref[same]
+    for lo, hi in ((21, 27), (27, 28), (28, 34), (34, 35), (35, 38)):
+        scale = np.abs(ref[:, lo:hi]).max()
+        np.testing.assert_allclose(got[:, lo:hi], ref[:, lo:hi], rtol=1e-4, atol=1e-4 * scale)
