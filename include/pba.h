@@ -72,10 +72,11 @@ enum { PBA_FC = 0, PBA_IC_PROXY = 1 };                        /* pba_config.mode
 enum { PBA_FP64 = 0, PBA_FP32 = 1, PBA_MIXED_BF16 = 2 };      /* pba_config.precision */
 enum { PBA_SOLVER_CHOL = 0 };                                 /* pba_config.solver */
 enum { PBA_HOST = 0, PBA_DEVICE = 1 };                        /* memory of input pointers */
-enum { PBA_FLAG_TIMING = 1 };                                 /* pba_config.flags */
+enum { PBA_FLAG_TIMING = 1, PBA_FLAG_GRAPH = 2 };             /* pba_config.flags */
 
 #define PBA_MAX_PATTERN 8
 #define PBA_MAX_LEVELS 4
+#define PBA_MAX_WINDOWS 4096
 
 typedef struct {
     int32_t mode;        /* PBA_FC or PBA_IC_PROXY */

@@ -19,8 +19,25 @@
 
 using namespace pba;
 
+// Inputs of one window of a batched context, held on the host until every
+// window is set (the global arrays are assembled at the first call that needs
+// them).
+struct WinStage {
+    bool have_frames = false, have_points = false;
+    int F = 0;
+    std::vector<float> img;          // [F][H][W]
+    std::vector<double> K, P;        // [F][4], [F][12]
+    int N = 0;
+    std::vector<int> hf, optr, ofr;  // window-local frame indices
+    std::vector<float> uv;
+    std::vector<double> d;
+};
+
 struct pba_ctx {
     Ctx c;
+    std::vector<WinStage> stage;     // n_windows > 1 only
+    bool dirty = false;              // staged inputs not yet assembled
+    int stage_W = 0, stage_H = 0;
 };
 
 namespace {
@@ -85,7 +102,10 @@ hipError_t upload(Ctx &c, V *&dptr, const std::vector<V> &v) {
     return hipMemcpyAsync(dptr, v.data(), v.size() * sizeof(V), hipMemcpyHostToDevice, c.stream);
 }
 
+void drop_graph(Ctx &c);
+
 void release_points(Ctx &c) {
+    drop_graph(c);
     for (int **p : {&c.d_host_frame, &c.d_obs_ptr, &c.d_obs_frame, &c.d_obs_point, &c.d_obs_pair, &c.d_pair_host,
                     &c.d_pair_target, &c.d_pair_obs_ptr, &c.d_pair_obs_idx, &c.d_frame_pair_ptr,
                     &c.d_frame_pair_item, &c.d_pair_local, &c.d_pair_hidx, &c.d_host_m, &c.d_host_frames,
@@ -93,13 +113,14 @@ void release_points(Ctx &c) {
                     &c.d_host_chunk_ptr, &c.d_blk_fa, &c.d_blk_fb, &c.d_blk_pp_ptr, &c.d_blk_pp_item,
                     &c.d_blk_g_ptr, &c.d_blk_g_item, &c.d_pchunk_begin, &c.d_pchunk_end, &c.d_pair_chunk_ptr})
         dfree(*p);
+    for (int **p : {&c.d_win_pair_off, &c.d_win_point_off, &c.d_point_win}) dfree(*p);
     dfree(c.d_host_uv);
     dfree(c.d_mask);
     dfree(c.d_rec);
     dfree(c.d_depth);
     dfree(c.d_depth0);
     for (double **p : {&c.d_geo0, &c.d_geo_a, &c.d_geo_b, &c.d_pairH, &c.d_pairY, &c.d_Hdd, &c.d_gd,
-                       &c.d_hdd_part, &c.d_gram, &c.d_dth_rel, &c.d_partH, &c.d_partY, &c.d_obsmap})
+                       &c.d_gram, &c.d_dth_rel, &c.d_partH, &c.d_partY, &c.d_obsmap})
         dfree(*p);
     dfree(c.d_rel0);
     dfree(c.d_rel_a);
@@ -127,6 +148,8 @@ void release_frames(Ctx &c) {
     dfree(c.d_gate);
     dfree(c.d_count);
     dfree(c.d_du_part);
+    for (int **p : {&c.d_win_frame_off, &c.d_win_S_off, &c.d_win_L_off, &c.d_frame_win}) dfree(*p);
+    dfree(c.d_wstat);
     c.stats_cap = 0;
     c.have_frames = false;
     c.F = 0;
@@ -146,8 +169,8 @@ std::string validate_config(const pba_config *cfg) {
     if (!(cfg->damping_rel >= 0.0) || !std::isfinite(cfg->damping_rel)) return "damping_rel must be finite and >= 0";
     if (cfg->pinned_frame < -1) return "pinned_frame must be >= -1";
     if (cfg->solver != PBA_SOLVER_CHOL) return "solver must be PBA_SOLVER_CHOL";
-    if (cfg->n_windows != 1) return "n_windows must be 1";
-    if (cfg->flags & ~PBA_FLAG_TIMING) return "unknown flag bits";
+    if (cfg->n_windows < 1 || cfg->n_windows > PBA_MAX_WINDOWS) return "n_windows must be in 1..PBA_MAX_WINDOWS";
+    if (cfg->flags & ~(PBA_FLAG_TIMING | PBA_FLAG_GRAPH)) return "unknown flag bits";
     return "";
 }
 
@@ -287,10 +310,8 @@ pba_status start_level(Ctx &c, int level) {
         Launch<T>::make_template(s, c, level);
         c.lv[level].tmpl_valid = true;
     }
-    const size_t F12 = (size_t)c.F * 12 * sizeof(double);
-    HIPCHK(hipMemcpyAsync(c.d_poses0, c.d_poses, F12, hipMemcpyDeviceToDevice, s));
-    HIPCHK(hipMemcpyAsync(c.d_depth0, c.d_depth, std::max<size_t>(1, c.N) * sizeof(double),
-                          hipMemcpyDeviceToDevice, s));
+    launch_copy_d(s, c.d_poses, c.d_poses0, (size_t)c.F * 12);
+    launch_copy_d(s, c.d_depth, c.d_depth0, (size_t)c.N);
     Launch<T>::relpose(s, c, c.d_poses0, c.d_geo0, (T *)c.d_rel0);
     Launch<T>::relpose(s, c, c.d_poses0, c.d_geo_a, (T *)c.d_rel_a);
     c.flip = false;
@@ -340,21 +361,14 @@ pba_status one_iteration(Ctx &c, int level, double *stat, hipEvent_t ev0, hipEve
         launch_mu(s, c, geo_cur);
         launch_gram(s, c, geo_cur, c.d_rec, is_fp64(c));
         launch_assemble_s(s, c, geo_cur);
-        if (6 * c.F > LDS_CHOL_MAX_N) launch_tchol(s, c);
+        if (c.nwin == 1 && 6 * c.F > LDS_CHOL_MAX_N) launch_tchol(s, c);
         Launch<T>::pair_reduce_y(s, c);
         launch_solve(s, c, geo_cur, geo_next, rel_next, is_fp64(c), stat);
     }
-    Launch<T>::depth_update(s, c, geo_cur, geo_next, stat, conv_px);
+    Launch<T>::depth_update(s, c, geo_cur, geo_next, stat, conv_px, level);
     HIPCHK(hipGetLastError());
     c.flip = !c.flip;
     c.iters_in_level++;
-    return PBA_OK;
-}
-
-pba_status open_gate(Ctx &c) {
-    const int one = 1;
-    HIPCHK(hipMemcpyAsync(c.d_gate, &one, sizeof(int), hipMemcpyHostToDevice, c.stream));
-    HIPCHK(hipMemsetAsync(c.d_count, 0, sizeof(int), c.stream));
     return PBA_OK;
 }
 
@@ -375,6 +389,28 @@ pba_status ensure_events(Ctx &c, size_t n) {
     return PBA_OK;
 }
 
+void drop_graph(Ctx &c) {
+    if (c.solve_graph) (void)hipGraphExecDestroy(c.solve_graph);
+    c.solve_graph = nullptr;
+    c.graph_iters = -1;
+}
+
+void fill_stats(const double *h, int level, int it0, int n, pba_iter_stats *out) {
+    for (int k = 0; k < n; ++k) {
+        const double *x = h + (size_t)k * ST_STRIDE;
+        pba_iter_stats &o = out[k];
+        o.level = level;
+        o.iter = it0 + k;
+        o.n_active = (int64_t)std::llround(x[ST_CNT]);
+        o.energy = x[ST_E];
+        o.sq = x[ST_SQ];
+        o.rmse = o.n_active > 0 ? std::sqrt(x[ST_SQ] / (double)o.n_active) : 0.0;
+        o.max_disp_px = x[ST_DISP];
+        o.max_step_pose = x[ST_STEP_P];
+        o.max_step_depth = x[ST_STEP_D];
+    }
+}
+
 // Enqueue n_iters iterations without host synchronization. With conv_px >= 0
 // the device closes the gate after the first iteration whose largest
 // point-centre displacement is below conv_px and the remaining launches return
@@ -385,8 +421,7 @@ pba_status run_iterations(Ctx &c, int level, int n_iters, pba_iter_stats *out, d
     if ((st = ensure_stats(c, n_iters)) != PBA_OK) return st;
     const bool timing = (c.cfg.flags & PBA_FLAG_TIMING) != 0;
     if (timing && (st = ensure_events(c, 2 * (size_t)n_iters)) != PBA_OK) return st;
-    HIPCHK(hipMemsetAsync(c.d_flag, 0, sizeof(int), c.stream));
-    if ((st = open_gate(c)) != PBA_OK) return st;
+    launch_open(c.stream, c, level, true);
     const int it0 = c.iters_in_level;
     const bool flip0 = c.flip;
     for (int k = 0; k < n_iters; ++k) {
@@ -397,11 +432,11 @@ pba_status run_iterations(Ctx &c, int level, int n_iters, pba_iter_stats *out, d
         if (st != PBA_OK) return st;
     }
     std::vector<double> hs((size_t)n_iters * ST_STRIDE);
-    int flag = 0, count = n_iters;
+    int flag = 0, count = 0;
     if (n_iters > 0)
         HIPCHK(hipMemcpyAsync(hs.data(), c.d_stats, hs.size() * sizeof(double), hipMemcpyDeviceToHost, c.stream));
     HIPCHK(hipMemcpyAsync(&flag, c.d_flag, sizeof(int), hipMemcpyDeviceToHost, c.stream));
-    if (conv_px >= 0.0) HIPCHK(hipMemcpyAsync(&count, c.d_count, sizeof(int), hipMemcpyDeviceToHost, c.stream));
+    HIPCHK(hipMemcpyAsync(&count, c.d_count + level, sizeof(int), hipMemcpyDeviceToHost, c.stream));
     HIPCHK(hipStreamSynchronize(c.stream));
     HIPCHK(hipGetLastError());
     // host view of the double buffers follows the iterations that actually ran
@@ -418,29 +453,13 @@ pba_status run_iterations(Ctx &c, int level, int n_iters, pba_iter_stats *out, d
             c.t_res[level] += (int64_t)c.O * LANES_PER_OBS;
         }
     }
-    if (out) {
-        for (int k = 0; k < n_iters; ++k) {
-            const double *h = hs.data() + (size_t)k * ST_STRIDE;
-            pba_iter_stats &o = out[k];
-            o.level = level;
-            o.iter = it0 + k;
-            o.n_active = (int64_t)std::llround(h[ST_CNT]);
-            o.energy = h[ST_E];
-            o.sq = h[ST_SQ];
-            o.rmse = o.n_active > 0 ? std::sqrt(h[ST_SQ] / (double)o.n_active) : 0.0;
-            o.max_disp_px = h[ST_DISP];
-            o.max_step_pose = h[ST_STEP_P];
-            o.max_step_depth = h[ST_STEP_D];
-        }
-    }
+    if (out) fill_stats(hs.data(), level, it0, n_iters, out);
     if (flag) return fail(&c, PBA_E_NUMERIC, "reduced pose system is not positive definite");
     return PBA_OK;
 }
 
 pba_status do_start_level(Ctx &c, int level) {
-    HIPCHK(hipMemsetAsync(c.d_flag, 0, sizeof(int), c.stream));
-    pba_status st0 = open_gate(c);
-    if (st0 != PBA_OK) return st0;
+    launch_open(c.stream, c, level, true);
     pba_status st = is_fp64(c) ? start_level<double>(c, level) : start_level<float>(c, level);
     if (st != PBA_OK) return st;
     if (c.cfg.mode == PBA_IC_PROXY) {
@@ -452,6 +471,335 @@ pba_status do_start_level(Ctx &c, int level) {
             return fail(&c, PBA_E_NUMERIC, "reduced pose system at p(0) is not positive definite");
         }
     }
+    return PBA_OK;
+}
+
+// The whole coarse-to-fine solve (every level's start and max_iters iterations,
+// each with the device convergence gate) enqueued without host synchronization;
+// with PBA_FLAG_GRAPH it is captured once as a HIP graph and replayed. Level l's
+// statistics go to d_stats[(n_levels - 1 - l) * max_iters + k].
+pba_status enqueue_solve(Ctx &c, int max_iters, double conv_px) {
+    for (int level = c.cfg.n_levels - 1; level >= 0; --level) {
+        // a failure at a coarser level keeps the gate closed for the rest
+        launch_open(c.stream, c, level, level == c.cfg.n_levels - 1);
+        pba_status st = is_fp64(c) ? start_level<double>(c, level) : start_level<float>(c, level);
+        if (st != PBA_OK) return st;
+        const int slot = c.cfg.n_levels - 1 - level;
+        for (int k = 0; k < max_iters; ++k) {
+            double *stat = c.d_stats + ((size_t)slot * max_iters + k) * ST_STRIDE;
+            st = is_fp64(c) ? one_iteration<double>(c, level, stat, nullptr, nullptr, conv_px)
+                            : one_iteration<float>(c, level, stat, nullptr, nullptr, conv_px);
+            if (st != PBA_OK) return st;
+        }
+    }
+    return PBA_OK;
+}
+
+pba_status solve_batch(Ctx &c, int max_iters, double conv_px, pba_result &res) {
+    pba_status st;
+    const int L = c.cfg.n_levels;
+    if ((st = ensure_stats(c, L * max_iters)) != PBA_OK) return st;
+    // templates of every level first (they depend on the points only)
+    for (int level = 0; level < L; ++level)
+        if (!c.lv[level].tmpl_valid) {
+            if (is_fp64(c))
+                Launch<double>::make_template(c.stream, c, level);
+            else
+                Launch<float>::make_template(c.stream, c, level);
+            c.lv[level].tmpl_valid = true;
+        }
+    if (c.cfg.flags & PBA_FLAG_GRAPH) {
+        if (!c.solve_graph || c.graph_iters != max_iters || c.graph_conv != conv_px) {
+            drop_graph(c);
+            hipGraph_t g = nullptr;
+            HIPCHK(hipStreamBeginCapture(c.stream, hipStreamCaptureModeThreadLocal));
+            st = enqueue_solve(c, max_iters, conv_px);
+            hipError_t e = hipStreamEndCapture(c.stream, &g);
+            if (st != PBA_OK) {
+                if (g) (void)hipGraphDestroy(g);
+                return st;
+            }
+            HIPCHK(e);
+            e = hipGraphInstantiate(&c.solve_graph, g, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(g);
+            HIPCHK(e);
+            c.graph_iters = max_iters;
+            c.graph_conv = conv_px;
+        }
+        HIPCHK(hipGraphLaunch(c.solve_graph, c.stream));
+    } else if ((st = enqueue_solve(c, max_iters, conv_px)) != PBA_OK) {
+        return st;
+    }
+    std::vector<double> hs((size_t)L * max_iters * ST_STRIDE);
+    int flag = 0, counts[PBA_MAX_LEVELS] = {0, 0, 0, 0};
+    HIPCHK(hipMemcpyAsync(hs.data(), c.d_stats, hs.size() * sizeof(double), hipMemcpyDeviceToHost, c.stream));
+    HIPCHK(hipMemcpyAsync(&flag, c.d_flag, sizeof(int), hipMemcpyDeviceToHost, c.stream));
+    HIPCHK(hipMemcpyAsync(counts, c.d_count, sizeof(counts), hipMemcpyDeviceToHost, c.stream));
+    HIPCHK(hipStreamSynchronize(c.stream));
+    HIPCHK(hipGetLastError());
+    std::vector<pba_iter_stats> its(max_iters);
+    for (int level = L - 1; level >= 0; --level) {
+        const int k = counts[level];
+        fill_stats(hs.data() + (size_t)(L - 1 - level) * max_iters * ST_STRIDE, level, 0, k, its.data());
+        for (int i = 0; i < k; ++i) res.active_residuals += its[i].n_active;
+        res.iters[level] = k;
+        res.total_iters += k;
+        if (level == 0) res.converged = (k > 0 && its[k - 1].max_disp_px < conv_px) ? 1 : 0;
+    }
+    // host view of the level-0 double buffers
+    c.cur_level = 0;
+    c.iters_in_level = counts[0];
+    c.flip = counts[0] % 2 == 1;
+    if (flag) {
+        c.cur_level = -1;
+        return fail(&c, PBA_E_NUMERIC, "reduced pose system is not positive definite");
+    }
+    return PBA_OK;
+}
+
+// ---- device state from host arrays (one window, or the assembled windows)
+
+// Frames: images (host or device float32 [F][H][W]), level-0 intrinsics and
+// poses, and the window partition of the frames.
+pba_status load_frames(Ctx &c, int n_frames, int width, int height, const float *images, int mem,
+                       const std::vector<double> &K, const std::vector<double> &Pz, const std::vector<int> &frame_off) {
+    HIPCHK(hipStreamSynchronize(c.stream));
+    release_frames(c);
+    c.F = n_frames;
+    c.W = width;
+    c.H = height;
+    c.K0 = K;
+    c.nwin = (int)frame_off.size() - 1;
+    c.win_frame_off = frame_off;
+    const size_t npx = (size_t)n_frames * width * height;
+    const size_t rs = c.real_size;
+    int W = width, H = height;
+    for (int l = 0; l < c.cfg.n_levels; ++l) {
+        c.lv[l].W = W;
+        c.lv[l].H = H;
+        HIPCHK(dalloc(c.lv[l].img, (size_t)n_frames * W * H * rs));
+        HIPCHK(dalloc(c.lv[l].K, (size_t)n_frames * 4 * rs));
+        W /= 2;
+        H /= 2;
+    }
+    float *staging = nullptr;
+    const float *src = images;
+    if (mem == PBA_HOST) {
+        HIPCHK(dalloc(staging, npx * sizeof(float)));
+        HIPCHK(hipMemcpyAsync(staging, images, npx * sizeof(float), hipMemcpyHostToDevice, c.stream));
+        src = staging;
+    }
+    HIPCHK(dalloc(c.d_K0, K.size() * sizeof(double)));
+    HIPCHK(hipMemcpyAsync(c.d_K0, K.data(), K.size() * sizeof(double), hipMemcpyHostToDevice, c.stream));
+    if (is_fp64(c)) {
+        Launch<double>::convert_images(c.stream, src, (double *)c.lv[0].img, npx);
+        for (int l = 1; l < c.cfg.n_levels; ++l)
+            Launch<double>::downsample(c.stream, (double *)c.lv[l - 1].img, (double *)c.lv[l].img, n_frames,
+                                       c.lv[l - 1].W, c.lv[l - 1].H, c.lv[l].W, c.lv[l].H);
+        for (int l = 0; l < c.cfg.n_levels; ++l) Launch<double>::level_K(c.stream, c.d_K0, (double *)c.lv[l].K, n_frames, l);
+    } else {
+        Launch<float>::convert_images(c.stream, src, (float *)c.lv[0].img, npx);
+        for (int l = 1; l < c.cfg.n_levels; ++l)
+            Launch<float>::downsample(c.stream, (float *)c.lv[l - 1].img, (float *)c.lv[l].img, n_frames,
+                                      c.lv[l - 1].W, c.lv[l - 1].H, c.lv[l].W, c.lv[l].H);
+        for (int l = 0; l < c.cfg.n_levels; ++l) Launch<float>::level_K(c.stream, c.d_K0, (float *)c.lv[l].K, n_frames, l);
+    }
+    // per-window blocks of the reduced system
+    std::vector<int> frame_win(n_frames);
+    c.win_S_off.assign(c.nwin + 1, 0);
+    c.win_L_off.assign(c.nwin + 1, 0);
+    for (int w = 0; w < c.nwin; ++w) {
+        const long long nw = 6LL * (frame_off[w + 1] - frame_off[w]);
+        for (int f = frame_off[w]; f < frame_off[w + 1]; ++f) frame_win[f] = w;
+        if (c.win_S_off[w] + nw * nw > INT32_MAX) return fail(&c, PBA_E_INVALID, "reduced system too large");
+        c.win_S_off[w + 1] = (int)(c.win_S_off[w] + nw * nw);
+        c.win_L_off[w + 1] = (int)(c.win_L_off[w] + nw * (nw + 1) / 2 + nw);
+    }
+    HIPCHK(upload(c, c.d_win_frame_off, c.win_frame_off));
+    HIPCHK(upload(c, c.d_frame_win, frame_win));
+    HIPCHK(upload(c, c.d_win_S_off, c.win_S_off));
+    HIPCHK(upload(c, c.d_win_L_off, c.win_L_off));
+    const size_t n6 = 6 * (size_t)n_frames;
+    const size_t nS = (size_t)c.win_S_off[c.nwin], nL = (size_t)c.win_L_off[c.nwin];
+    HIPCHK(dalloc(c.d_poses, Pz.size() * sizeof(double)));
+    HIPCHK(dalloc(c.d_poses0, Pz.size() * sizeof(double)));
+    HIPCHK(hipMemcpyAsync(c.d_poses, Pz.data(), Pz.size() * sizeof(double), hipMemcpyHostToDevice, c.stream));
+    HIPCHK(dalloc(c.d_S, nS * sizeof(double)));
+    if (c.cfg.mode == PBA_IC_PROXY) {
+        HIPCHK(dalloc(c.d_Sinv, nS * sizeof(double)));
+        HIPCHK(dalloc(c.d_Lfac, nL * sizeof(double)));
+    }
+    if (c.nwin == 1 && n6 > (size_t)LDS_CHOL_MAX_N) {
+        const size_t nt = (n6 + TCHOL_TILE - 1) / TCHOL_TILE;
+        HIPCHK(dalloc(c.d_Sfac, n6 * n6 * sizeof(double)));
+        HIPCHK(dalloc(c.d_Linv, nt * TCHOL_TILE * TCHOL_TILE * sizeof(double)));
+    }
+    HIPCHK(dalloc(c.d_b, 2 * n6 * sizeof(double)));
+    HIPCHK(dalloc(c.d_dtheta, n6 * sizeof(double)));
+    HIPCHK(dalloc(c.d_mu, 2 * (size_t)c.nwin * sizeof(double)));
+    HIPCHK(dalloc(c.d_wstat, 4 * (size_t)c.nwin * sizeof(double)));
+    HIPCHK(dalloc(c.d_flag, sizeof(int)));
+    HIPCHK(dalloc(c.d_gate, sizeof(int)));
+    HIPCHK(dalloc(c.d_count, PBA_MAX_LEVELS * sizeof(int)));
+    HIPCHK(hipMemsetAsync(c.d_flag, 0, sizeof(int), c.stream));
+    HIPCHK(hipMemsetAsync(c.d_count, 0, PBA_MAX_LEVELS * sizeof(int), c.stream));
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(c.stream));
+    dfree(staging);
+    c.have_frames = true;
+    c.cur_level = -1;
+    return PBA_OK;
+}
+
+// Points and observations (global frame indices) and their window partition.
+pba_status load_points(Ctx &c, int n_points, const std::vector<int> &hf, const std::vector<float> &uv,
+                       const std::vector<double> &d, const std::vector<int> &optr, const std::vector<int> &ofr,
+                       const std::vector<int> &point_off) {
+    const long long O = optr[n_points];
+    HIPCHK(hipStreamSynchronize(c.stream));
+    release_points(c);
+    c.N = n_points;
+    c.O = (int)O;
+    const std::string e = build_structure(c, hf, optr, ofr);
+    if (!e.empty()) {
+        c.N = c.O = 0;
+        return fail(&c, PBA_E_INVALID, e);
+    }
+    const Structure &s = c.st;
+    // window partition of points and pairs (pairs are sorted by host frame)
+    c.win_point_off = point_off;
+    std::vector<int> point_win(n_points), frame_win(c.F);
+    for (int w = 0; w < c.nwin; ++w) {
+        for (int n = point_off[w]; n < point_off[w + 1]; ++n) point_win[n] = w;
+        for (int f = c.win_frame_off[w]; f < c.win_frame_off[w + 1]; ++f) frame_win[f] = w;
+    }
+    c.win_pair_off.assign(c.nwin + 1, 0);
+    for (int p = 0; p < s.n_pairs; ++p) c.win_pair_off[frame_win[s.pair_host[p]] + 1]++;
+    for (int w = 0; w < c.nwin; ++w) c.win_pair_off[w + 1] += c.win_pair_off[w];
+    HIPCHK(upload(c, c.d_win_point_off, c.win_point_off));
+    HIPCHK(upload(c, c.d_win_pair_off, c.win_pair_off));
+    HIPCHK(upload(c, c.d_point_win, point_win));
+    HIPCHK(upload(c, c.d_host_frame, hf));
+    HIPCHK(upload(c, c.d_obs_ptr, optr));
+    HIPCHK(upload(c, c.d_obs_frame, ofr));
+    HIPCHK(upload(c, c.d_host_uv, uv));
+    HIPCHK(upload(c, c.d_obs_point, s.obs_point));
+    HIPCHK(upload(c, c.d_obs_pair, s.obs_pair));
+    HIPCHK(upload(c, c.d_pair_host, s.pair_host));
+    HIPCHK(upload(c, c.d_pair_target, s.pair_target));
+    HIPCHK(upload(c, c.d_pair_obs_ptr, s.pair_obs_ptr));
+    HIPCHK(upload(c, c.d_pair_obs_idx, s.pair_obs_idx));
+    HIPCHK(upload(c, c.d_frame_pair_ptr, s.frame_pair_ptr));
+    HIPCHK(upload(c, c.d_frame_pair_item, s.frame_pair_item));
+    HIPCHK(upload(c, c.d_pair_local, s.pair_local));
+    HIPCHK(upload(c, c.d_pair_hidx, s.pair_hidx));
+    HIPCHK(upload(c, c.d_host_m, s.host_m));
+    HIPCHK(upload(c, c.d_host_frames, s.hosts));
+    HIPCHK(upload(c, c.d_host_pts, s.host_pts));
+    HIPCHK(upload(c, c.d_chunk_host, s.chunk_host));
+    HIPCHK(upload(c, c.d_chunk_begin, s.chunk_begin));
+    HIPCHK(upload(c, c.d_chunk_end, s.chunk_end));
+    HIPCHK(upload(c, c.d_chunk_off, s.chunk_off));
+    HIPCHK(upload(c, c.d_host_chunk_ptr, s.host_chunk_ptr));
+    HIPCHK(upload(c, c.d_blk_fa, s.blk_fa));
+    HIPCHK(upload(c, c.d_blk_fb, s.blk_fb));
+    HIPCHK(upload(c, c.d_blk_pp_ptr, s.blk_pp_ptr));
+    HIPCHK(upload(c, c.d_blk_pp_item, s.blk_pp_item));
+    HIPCHK(upload(c, c.d_blk_g_ptr, s.blk_g_ptr));
+    HIPCHK(upload(c, c.d_blk_g_item, s.blk_g_item));
+    HIPCHK(upload(c, c.d_pchunk_begin, s.pchunk_begin));
+    HIPCHK(upload(c, c.d_pchunk_end, s.pchunk_end));
+    HIPCHK(upload(c, c.d_pair_chunk_ptr, s.pair_chunk_ptr));
+    HIPCHK(upload(c, c.d_depth, d));
+    HIPCHK(dalloc(c.d_depth0, std::max<size_t>(1, n_points) * sizeof(double)));
+    const size_t rs = c.real_size;
+    const int Pn = s.n_pairs;
+    HIPCHK(dalloc(c.d_mask, std::max<size_t>(1, O)));
+    HIPCHK(dalloc(c.d_rec, (size_t)O * REC_STRIDE * rs));
+    HIPCHK(dalloc(c.d_geo0, (size_t)Pn * GEO_STRIDE * sizeof(double)));
+    HIPCHK(dalloc(c.d_geo_a, (size_t)Pn * GEO_STRIDE * sizeof(double)));
+    HIPCHK(dalloc(c.d_geo_b, (size_t)Pn * GEO_STRIDE * sizeof(double)));
+    HIPCHK(dalloc(c.d_rel0, (size_t)Pn * REL_STRIDE * rs));
+    HIPCHK(dalloc(c.d_rel_a, (size_t)Pn * REL_STRIDE * rs));
+    HIPCHK(dalloc(c.d_rel_b, (size_t)Pn * REL_STRIDE * rs));
+    HIPCHK(dalloc(c.d_pairH, (size_t)Pn * 21 * sizeof(double)));
+    HIPCHK(dalloc(c.d_pairY, (size_t)Pn * 9 * sizeof(double)));
+    HIPCHK(dalloc(c.d_partH, s.pchunk_begin.size() * 21 * sizeof(double)));
+    HIPCHK(dalloc(c.d_partY, s.pchunk_begin.size() * 9 * sizeof(double)));
+    HIPCHK(dalloc(c.d_obsmap, (size_t)O * 12 * sizeof(double)));
+    HIPCHK(dalloc(c.d_Hdd, (size_t)n_points * sizeof(double)));
+    HIPCHK(dalloc(c.d_gd, (size_t)n_points * sizeof(double)));
+    HIPCHK(dalloc(c.d_gram, s.gram_floats * sizeof(double)));
+    HIPCHK(dalloc(c.d_dth_rel, (size_t)Pn * 6 * sizeof(double)));
+    HIPCHK(dalloc(c.d_du_part, 2 * (size_t)std::max(1, (n_points + 31) / 32) * sizeof(double)));
+    for (int l = 0; l < c.cfg.n_levels; ++l) {
+        HIPCHK(dalloc(c.lv[l].tmpl, (size_t)n_points * c.P * 4 * rs));
+        c.lv[l].tmpl_valid = false;
+    }
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(c.stream));
+    c.have_points = true;
+    c.cur_level = -1;
+    return PBA_OK;
+}
+
+// Batched context: assemble the staged windows into the global problem (frames
+// and points of window w follow those of windows < w).
+pba_status assemble_windows(pba_ctx *ctx) {
+    Ctx &c = ctx->c;
+    const int nw = c.cfg.n_windows;
+    std::vector<int> frame_off(nw + 1, 0), point_off(nw + 1, 0);
+    for (int w = 0; w < nw; ++w) {
+        const WinStage &st = ctx->stage[w];
+        if (!st.have_frames || !st.have_points)
+            return fail(&c, PBA_E_STATE, "window " + std::to_string(w) + " has no frames or points");
+        frame_off[w + 1] = frame_off[w] + st.F;
+        point_off[w + 1] = point_off[w] + st.N;
+    }
+    const int F = frame_off[nw], N = point_off[nw];
+    const int W = ctx->stage_W, H = ctx->stage_H;
+    const size_t fpx = (size_t)W * H;
+    // images straight into one device buffer, window by window
+    HIPCHK(hipStreamSynchronize(c.stream));
+    release_frames(c);
+    float *dimg = nullptr;
+    HIPCHK(dalloc(dimg, (size_t)F * fpx * sizeof(float)));
+    std::vector<double> K, Pz;
+    for (int w = 0; w < nw; ++w) {
+        const WinStage &st = ctx->stage[w];
+        HIPCHK(hipMemcpyAsync(dimg + (size_t)frame_off[w] * fpx, st.img.data(), st.img.size() * sizeof(float),
+                              hipMemcpyHostToDevice, c.stream));
+        K.insert(K.end(), st.K.begin(), st.K.end());
+        Pz.insert(Pz.end(), st.P.begin(), st.P.end());
+    }
+    pba_status r = load_frames(c, F, W, H, dimg, PBA_DEVICE, K, Pz, frame_off);
+    dfree(dimg);
+    if (r != PBA_OK) return r;
+    std::vector<int> hf, optr{0}, ofr;
+    std::vector<float> uv;
+    std::vector<double> d;
+    hf.reserve(N);
+    for (int w = 0; w < nw; ++w) {
+        const WinStage &st = ctx->stage[w];
+        for (int n = 0; n < st.N; ++n) {
+            hf.push_back(st.hf[n] + frame_off[w]);
+            for (int o = st.optr[n]; o < st.optr[n + 1]; ++o) ofr.push_back(st.ofr[o] + frame_off[w]);
+            optr.push_back((int)ofr.size());
+        }
+        uv.insert(uv.end(), st.uv.begin(), st.uv.end());
+        d.insert(d.end(), st.d.begin(), st.d.end());
+    }
+    r = load_points(c, N, hf, uv, d, optr, ofr, point_off);
+    if (r != PBA_OK) return r;
+    ctx->dirty = false;
+    return PBA_OK;
+}
+
+// Device state current (assembles a batched context's staged windows).
+pba_status ready(pba_ctx *ctx) {
+    Ctx &c = ctx->c;
+    if (c.cfg.n_windows > 1 && ctx->dirty) return assemble_windows(ctx);
+    if (!c.have_points) return fail(&c, PBA_E_STATE, "pba_set_frames and pba_set_points must be called first");
     return PBA_OK;
 }
 
@@ -514,6 +862,7 @@ pba_status pba_create(const pba_config *cfg, pba_ctx **out) {
     c.device = dev;
     c.P = cfg->pattern_n;
     c.real_size = cfg->precision == PBA_FP64 ? sizeof(double) : sizeof(float);
+    if (cfg->n_windows > 1) ctx->stage.resize(cfg->n_windows);
     if (cfg->stream) {
         c.stream = (hipStream_t)cfg->stream;
         c.own_stream = false;
@@ -533,6 +882,7 @@ void pba_destroy(pba_ctx *ctx) {
     Ctx &c = ctx->c;
     if (c.stream) (void)hipStreamSynchronize(c.stream);
     release_frames(c);
+    dfree(c.d_eval);
     for (hipEvent_t e : c.ev_pool) (void)hipEventDestroy(e);
     if (c.own_stream && c.stream) (void)hipStreamDestroy(c.stream);
     delete ctx;
@@ -542,7 +892,8 @@ pba_status pba_set_frames(pba_ctx *ctx, int32_t window, int32_t n_frames, int32_
                           const float *images, const double *intrinsics, const double *poses, int32_t mem) {
     if (!ctx) return fail(nullptr, PBA_E_INVALID, "ctx is NULL");
     Ctx &c = ctx->c;
-    if (window != 0) return fail(&c, PBA_E_INVALID, "window must be 0");
+    if (window < 0 || window >= c.cfg.n_windows)
+        return fail(&c, PBA_E_INVALID, "window must be in 0..n_windows-1");
     if (mem != PBA_HOST && mem != PBA_DEVICE) return fail(&c, PBA_E_INVALID, "mem must be PBA_HOST or PBA_DEVICE");
     if (n_frames < 1) return fail(&c, PBA_E_INVALID, "n_frames must be >= 1");
     const int minsz = 8 << (c.cfg.n_levels - 1);
@@ -551,6 +902,14 @@ pba_status pba_set_frames(pba_ctx *ctx, int32_t window, int32_t n_frames, int32_
     if ((long long)n_frames * width * height > (1LL << 34)) return fail(&c, PBA_E_INVALID, "images too large");
     if (!images || !intrinsics || !poses) return fail(&c, PBA_E_INVALID, "NULL input array");
     if (c.cfg.pinned_frame >= n_frames) return fail(&c, PBA_E_INVALID, "pinned_frame >= n_frames");
+    if (c.cfg.n_windows > 1) {
+        if (6 * n_frames > LDS_CHOL_MAX_N)
+            return fail(&c, PBA_E_INVALID, "a window of a batched context holds at most " +
+                                               std::to_string(LDS_CHOL_MAX_N / 6) + " frames");
+        for (int w = 0; w < c.cfg.n_windows; ++w)
+            if (w != window && ctx->stage[w].have_frames && (width != ctx->stage_W || height != ctx->stage_H))
+                return fail(&c, PBA_E_INVALID, "every window of a batched context must have the same image size");
+    }
     std::vector<double> K, Pz;
     HIPCHK(fetch(K, intrinsics, (size_t)n_frames * 4, mem));
     HIPCHK(fetch(Pz, poses, (size_t)n_frames * 12, mem));
@@ -573,70 +932,20 @@ pba_status pba_set_frames(pba_ctx *ctx, int32_t window, int32_t n_frames, int32_
         for (size_t i = 0; i < npx; ++i)
             if (!std::isfinite(images[i])) return fail(&c, PBA_E_INVALID, "images contain non-finite values");
     }
-    // (re)allocate
-    HIPCHK(hipStreamSynchronize(c.stream));
-    release_frames(c);
-    c.F = n_frames;
-    c.W = width;
-    c.H = height;
-    c.K0 = K;
-    const size_t rs = c.real_size;
-    int W = width, H = height;
-    for (int l = 0; l < c.cfg.n_levels; ++l) {
-        c.lv[l].W = W;
-        c.lv[l].H = H;
-        HIPCHK(dalloc(c.lv[l].img, (size_t)n_frames * W * H * rs));
-        HIPCHK(dalloc(c.lv[l].K, (size_t)n_frames * 4 * rs));
-        W /= 2;
-        H /= 2;
+    if (c.cfg.n_windows > 1) {
+        WinStage &st = ctx->stage[window];
+        HIPCHK(fetch(st.img, images, npx, mem));
+        st.F = n_frames;
+        st.K = K;
+        st.P = Pz;
+        st.have_frames = true;
+        st.have_points = false;  // as for one window: the points follow the frames
+        ctx->stage_W = width;
+        ctx->stage_H = height;
+        ctx->dirty = true;
+        return PBA_OK;
     }
-    float *staging = nullptr;
-    HIPCHK(dalloc(staging, npx * sizeof(float)));
-    HIPCHK(hipMemcpyAsync(staging, images, npx * sizeof(float),
-                          mem == PBA_HOST ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice, c.stream));
-    HIPCHK(dalloc(c.d_K0, K.size() * sizeof(double)));
-    HIPCHK(hipMemcpyAsync(c.d_K0, K.data(), K.size() * sizeof(double), hipMemcpyHostToDevice, c.stream));
-    if (is_fp64(c)) {
-        Launch<double>::convert_images(c.stream, staging, (double *)c.lv[0].img, npx);
-        for (int l = 1; l < c.cfg.n_levels; ++l)
-            Launch<double>::downsample(c.stream, (double *)c.lv[l - 1].img, (double *)c.lv[l].img, n_frames,
-                                       c.lv[l - 1].W, c.lv[l - 1].H, c.lv[l].W, c.lv[l].H);
-        for (int l = 0; l < c.cfg.n_levels; ++l) Launch<double>::level_K(c.stream, c.d_K0, (double *)c.lv[l].K, n_frames, l);
-    } else {
-        Launch<float>::convert_images(c.stream, staging, (float *)c.lv[0].img, npx);
-        for (int l = 1; l < c.cfg.n_levels; ++l)
-            Launch<float>::downsample(c.stream, (float *)c.lv[l - 1].img, (float *)c.lv[l].img, n_frames,
-                                      c.lv[l - 1].W, c.lv[l - 1].H, c.lv[l].W, c.lv[l].H);
-        for (int l = 0; l < c.cfg.n_levels; ++l) Launch<float>::level_K(c.stream, c.d_K0, (float *)c.lv[l].K, n_frames, l);
-    }
-    const size_t n6 = 6 * (size_t)n_frames;
-    HIPCHK(dalloc(c.d_poses, Pz.size() * sizeof(double)));
-    HIPCHK(dalloc(c.d_poses0, Pz.size() * sizeof(double)));
-    HIPCHK(hipMemcpyAsync(c.d_poses, Pz.data(), Pz.size() * sizeof(double), hipMemcpyHostToDevice, c.stream));
-    HIPCHK(dalloc(c.d_S, n6 * n6 * sizeof(double)));
-    if (c.cfg.mode == PBA_IC_PROXY) {
-        HIPCHK(dalloc(c.d_Sinv, n6 * n6 * sizeof(double)));
-        HIPCHK(dalloc(c.d_Lfac, (n6 * (n6 + 1) / 2 + n6) * sizeof(double)));
-    }
-    if (n6 > (size_t)LDS_CHOL_MAX_N) {
-        const size_t nt = (n6 + TCHOL_TILE - 1) / TCHOL_TILE;
-        HIPCHK(dalloc(c.d_Sfac, n6 * n6 * sizeof(double)));
-        HIPCHK(dalloc(c.d_Linv, nt * TCHOL_TILE * TCHOL_TILE * sizeof(double)));
-    }
-    HIPCHK(dalloc(c.d_b, 2 * n6 * sizeof(double)));
-    HIPCHK(dalloc(c.d_dtheta, n6 * sizeof(double)));
-    HIPCHK(dalloc(c.d_mu, 2 * sizeof(double)));
-    HIPCHK(dalloc(c.d_flag, sizeof(int)));
-    HIPCHK(dalloc(c.d_gate, sizeof(int)));
-    HIPCHK(dalloc(c.d_count, sizeof(int)));
-
-    HIPCHK(hipMemsetAsync(c.d_flag, 0, sizeof(int), c.stream));
-    HIPCHK(hipGetLastError());
-    HIPCHK(hipStreamSynchronize(c.stream));
-    dfree(staging);
-    c.have_frames = true;
-    c.cur_level = -1;
-    return PBA_OK;
+    return load_frames(c, n_frames, width, height, images, mem, K, Pz, {0, n_frames});
 }
 
 pba_status pba_set_points(pba_ctx *ctx, int32_t window, int32_t n_points, const int32_t *host_frame,
@@ -644,13 +953,18 @@ pba_status pba_set_points(pba_ctx *ctx, int32_t window, int32_t n_points, const 
                           const int32_t *obs_frame, int32_t mem) {
     if (!ctx) return fail(nullptr, PBA_E_INVALID, "ctx is NULL");
     Ctx &c = ctx->c;
-    if (!c.have_frames) return fail(&c, PBA_E_STATE, "pba_set_frames must be called first");
-    if (window != 0) return fail(&c, PBA_E_INVALID, "window must be 0");
+    if (window < 0 || window >= c.cfg.n_windows)
+        return fail(&c, PBA_E_INVALID, "window must be in 0..n_windows-1");
+    const bool batched = c.cfg.n_windows > 1;
+    if (batched ? !ctx->stage[window].have_frames : !c.have_frames)
+        return fail(&c, PBA_E_STATE, "pba_set_frames must be called first");
     if (mem != PBA_HOST && mem != PBA_DEVICE) return fail(&c, PBA_E_INVALID, "mem must be PBA_HOST or PBA_DEVICE");
     if (n_points < 0) return fail(&c, PBA_E_INVALID, "n_points must be >= 0");
     if (n_points > 0 && (!host_frame || !host_uv || !inv_depth || !obs_ptr))
         return fail(&c, PBA_E_INVALID, "NULL input array");
     if (!obs_ptr) return fail(&c, PBA_E_INVALID, "obs_ptr is NULL");
+    const int F = batched ? ctx->stage[window].F : c.F;
+    const int W = batched ? ctx->stage_W : c.W, H = batched ? ctx->stage_H : c.H;
     std::vector<int> hf, optr, ofr;
     std::vector<float> uv;
     std::vector<double> d;
@@ -666,103 +980,41 @@ pba_status pba_set_points(pba_ctx *ctx, int32_t window, int32_t n_points, const 
     HIPCHK(fetch(d, inv_depth, (size_t)n_points, mem));
     HIPCHK(fetch(ofr, obs_frame, (size_t)O, mem));
     for (int n = 0; n < n_points; ++n) {
-        if (hf[n] < 0 || hf[n] >= c.F) return fail(&c, PBA_E_INVALID, "host_frame out of range at point " + std::to_string(n));
+        if (hf[n] < 0 || hf[n] >= F) return fail(&c, PBA_E_INVALID, "host_frame out of range at point " + std::to_string(n));
         if (!std::isfinite(d[n]) || !(d[n] > 0.0))
             return fail(&c, PBA_E_INVALID, "inv_depth must be finite and > 0 at point " + std::to_string(n));
-        if (!std::isfinite(uv[2 * n]) || !std::isfinite(uv[2 * n + 1]) || uv[2 * n] < 0 || uv[2 * n] > c.W - 1 ||
-            uv[2 * n + 1] < 0 || uv[2 * n + 1] > c.H - 1)
+        if (!std::isfinite(uv[2 * n]) || !std::isfinite(uv[2 * n + 1]) || uv[2 * n] < 0 || uv[2 * n] > W - 1 ||
+            uv[2 * n + 1] < 0 || uv[2 * n + 1] > H - 1)
             return fail(&c, PBA_E_INVALID, "host_uv outside the image at point " + std::to_string(n));
         for (int o = optr[n]; o < optr[n + 1]; ++o) {
-            if (ofr[o] < 0 || ofr[o] >= c.F) return fail(&c, PBA_E_INVALID, "obs_frame out of range");
+            if (ofr[o] < 0 || ofr[o] >= F) return fail(&c, PBA_E_INVALID, "obs_frame out of range");
             if (ofr[o] == hf[n]) return fail(&c, PBA_E_INVALID, "a point cannot observe its own host frame");
             if (o > optr[n] && ofr[o] <= ofr[o - 1])
                 return fail(&c, PBA_E_INVALID, "obs_frame must be strictly increasing within a point");
         }
     }
-    HIPCHK(hipStreamSynchronize(c.stream));
-    release_points(c);
-    c.N = n_points;
-    c.O = (int)O;
-    const std::string e = build_structure(c, hf, optr, ofr);
-    if (!e.empty()) {
-        c.N = c.O = 0;
-        return fail(&c, PBA_E_INVALID, e);
+    if (batched) {
+        WinStage &st = ctx->stage[window];
+        st.N = n_points;
+        st.hf = std::move(hf);
+        st.optr = std::move(optr);
+        st.ofr = std::move(ofr);
+        st.uv = std::move(uv);
+        st.d = std::move(d);
+        st.have_points = true;
+        ctx->dirty = true;
+        return PBA_OK;
     }
-    const Structure &s = c.st;
-    HIPCHK(upload(c, c.d_host_frame, hf));
-    HIPCHK(upload(c, c.d_obs_ptr, optr));
-    HIPCHK(upload(c, c.d_obs_frame, ofr));
-    HIPCHK(upload(c, c.d_host_uv, uv));
-    HIPCHK(upload(c, c.d_obs_point, s.obs_point));
-    HIPCHK(upload(c, c.d_obs_pair, s.obs_pair));
-    HIPCHK(upload(c, c.d_pair_host, s.pair_host));
-    HIPCHK(upload(c, c.d_pair_target, s.pair_target));
-    HIPCHK(upload(c, c.d_pair_obs_ptr, s.pair_obs_ptr));
-    HIPCHK(upload(c, c.d_pair_obs_idx, s.pair_obs_idx));
-    HIPCHK(upload(c, c.d_frame_pair_ptr, s.frame_pair_ptr));
-    HIPCHK(upload(c, c.d_frame_pair_item, s.frame_pair_item));
-    HIPCHK(upload(c, c.d_pair_local, s.pair_local));
-    HIPCHK(upload(c, c.d_pair_hidx, s.pair_hidx));
-    HIPCHK(upload(c, c.d_host_m, s.host_m));
-    HIPCHK(upload(c, c.d_host_frames, s.hosts));
-    HIPCHK(upload(c, c.d_host_pts, s.host_pts));
-    HIPCHK(upload(c, c.d_chunk_host, s.chunk_host));
-    HIPCHK(upload(c, c.d_chunk_begin, s.chunk_begin));
-    HIPCHK(upload(c, c.d_chunk_end, s.chunk_end));
-    HIPCHK(upload(c, c.d_chunk_off, s.chunk_off));
-    HIPCHK(upload(c, c.d_host_chunk_ptr, s.host_chunk_ptr));
-    HIPCHK(upload(c, c.d_blk_fa, s.blk_fa));
-    HIPCHK(upload(c, c.d_blk_fb, s.blk_fb));
-    HIPCHK(upload(c, c.d_blk_pp_ptr, s.blk_pp_ptr));
-    HIPCHK(upload(c, c.d_blk_pp_item, s.blk_pp_item));
-    HIPCHK(upload(c, c.d_blk_g_ptr, s.blk_g_ptr));
-    HIPCHK(upload(c, c.d_blk_g_item, s.blk_g_item));
-    HIPCHK(upload(c, c.d_pchunk_begin, s.pchunk_begin));
-    HIPCHK(upload(c, c.d_pchunk_end, s.pchunk_end));
-    HIPCHK(upload(c, c.d_pair_chunk_ptr, s.pair_chunk_ptr));
-    HIPCHK(upload(c, c.d_depth, d));
-    HIPCHK(dalloc(c.d_depth0, std::max<size_t>(1, n_points) * sizeof(double)));
-    const size_t rs = c.real_size;
-    const int Pn = s.n_pairs;
-    HIPCHK(dalloc(c.d_mask, std::max<size_t>(1, O)));
-    HIPCHK(dalloc(c.d_rec, (size_t)O * REC_STRIDE * rs));
-    HIPCHK(dalloc(c.d_geo0, (size_t)Pn * GEO_STRIDE * sizeof(double)));
-    HIPCHK(dalloc(c.d_geo_a, (size_t)Pn * GEO_STRIDE * sizeof(double)));
-    HIPCHK(dalloc(c.d_geo_b, (size_t)Pn * GEO_STRIDE * sizeof(double)));
-    HIPCHK(dalloc(c.d_rel0, (size_t)Pn * REL_STRIDE * rs));
-    HIPCHK(dalloc(c.d_rel_a, (size_t)Pn * REL_STRIDE * rs));
-    HIPCHK(dalloc(c.d_rel_b, (size_t)Pn * REL_STRIDE * rs));
-    HIPCHK(dalloc(c.d_pairH, (size_t)Pn * 21 * sizeof(double)));
-    HIPCHK(dalloc(c.d_pairY, (size_t)Pn * 9 * sizeof(double)));
-    HIPCHK(dalloc(c.d_partH, s.pchunk_begin.size() * 21 * sizeof(double)));
-    HIPCHK(dalloc(c.d_partY, s.pchunk_begin.size() * 9 * sizeof(double)));
-    HIPCHK(dalloc(c.d_obsmap, (size_t)O * 12 * sizeof(double)));
-    HIPCHK(dalloc(c.d_Hdd, (size_t)n_points * sizeof(double)));
-    HIPCHK(dalloc(c.d_gd, (size_t)n_points * sizeof(double)));
-    c.hdd_blocks = (n_points + 255) / 256;
-    HIPCHK(dalloc(c.d_hdd_part, (size_t)std::max(1, c.hdd_blocks) * sizeof(double)));
-    HIPCHK(dalloc(c.d_gram, s.gram_floats * sizeof(double)));
-    HIPCHK(dalloc(c.d_dth_rel, (size_t)Pn * 6 * sizeof(double)));
-    HIPCHK(dalloc(c.d_du_part, 2 * (size_t)std::max(1, (n_points + 31) / 32) * sizeof(double)));
-    for (int l = 0; l < c.cfg.n_levels; ++l) {
-        HIPCHK(dalloc(c.lv[l].tmpl, (size_t)n_points * c.P * 4 * rs));
-        c.lv[l].tmpl_valid = false;
-    }
-    if (c.hdd_blocks == 0) launch_fill(c.stream, c.d_hdd_part, 1, 0.0, nullptr);
-    HIPCHK(hipGetLastError());
-    HIPCHK(hipStreamSynchronize(c.stream));
-    c.have_points = true;
-    c.cur_level = -1;
-    return PBA_OK;
+    return load_points(c, n_points, hf, uv, d, optr, ofr, {0, n_points});
 }
 
 pba_status pba_iterate(pba_ctx *ctx, int32_t level, int32_t n_iters, pba_iter_stats *stats) {
     if (!ctx) return fail(nullptr, PBA_E_INVALID, "ctx is NULL");
     Ctx &c = ctx->c;
-    if (!c.have_points) return fail(&c, PBA_E_STATE, "pba_set_frames and pba_set_points must be called first");
     if (level < 0 || level >= c.cfg.n_levels) return fail(&c, PBA_E_INVALID, "level out of range");
     if (n_iters < 0) return fail(&c, PBA_E_INVALID, "n_iters must be >= 0");
     pba_status st;
+    if ((st = ready(ctx)) != PBA_OK) return st;
     if (c.cur_level != level && (st = do_start_level(c, level)) != PBA_OK) return st;
     return run_iterations(c, level, n_iters, stats);
 }
@@ -770,14 +1022,14 @@ pba_status pba_iterate(pba_ctx *ctx, int32_t level, int32_t n_iters, pba_iter_st
 pba_status pba_evaluate(pba_ctx *ctx, int32_t level, pba_iter_stats *out) {
     if (!ctx) return fail(nullptr, PBA_E_INVALID, "ctx is NULL");
     Ctx &c = ctx->c;
-    if (!c.have_points) return fail(&c, PBA_E_STATE, "pba_set_frames and pba_set_points must be called first");
     if (level < 0 || level >= c.cfg.n_levels) return fail(&c, PBA_E_INVALID, "level out of range");
     if (!out) return fail(&c, PBA_E_INVALID, "out is NULL");
+    pba_status st;
+    if ((st = ready(ctx)) != PBA_OK) return st;
     hipStream_t s = c.stream;
     // relative poses at the current parameters go to the buffer the next iteration reads
     double *geo = c.flip ? c.d_geo_b : c.d_geo_a;
-    double *tot = nullptr;
-    HIPCHK(dalloc(tot, 3 * sizeof(double)));
+    if (!c.d_eval) HIPCHK(dalloc(c.d_eval, 3 * sizeof(double)));
     if (is_fp64(c)) {
         if (!c.lv[level].tmpl_valid) Launch<double>::make_template(s, c, level);
         Launch<double>::relpose(s, c, c.d_poses, geo, (double *)(c.flip ? c.d_rel_b : c.d_rel_a));
@@ -789,13 +1041,12 @@ pba_status pba_evaluate(pba_ctx *ctx, int32_t level, pba_iter_stats *out) {
     }
     c.lv[level].tmpl_valid = true;
     if (c.O > 0)
-        launch_sum_stats(s, c, c.d_rec, is_fp64(c), tot);
+        launch_sum_stats(s, c, c.d_rec, is_fp64(c), c.d_eval);
     else
-        launch_fill(s, tot, 3, 0.0, nullptr);
+        launch_fill(s, c.d_eval, 3, 0.0, nullptr);
     double h[3];
-    HIPCHK(hipMemcpyAsync(h, tot, sizeof(h), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(h, c.d_eval, sizeof(h), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
-    dfree(tot);
     std::memset(out, 0, sizeof(*out));
     out->level = level;
     out->n_active = (int64_t)std::llround(h[2]);
@@ -808,23 +1059,13 @@ pba_status pba_evaluate(pba_ctx *ctx, int32_t level, pba_iter_stats *out) {
 pba_status pba_solve(pba_ctx *ctx, int32_t max_iters_per_level, double conv_px, pba_result *out) {
     if (!ctx) return fail(nullptr, PBA_E_INVALID, "ctx is NULL");
     Ctx &c = ctx->c;
-    if (!c.have_points) return fail(&c, PBA_E_STATE, "pba_set_frames and pba_set_points must be called first");
     if (max_iters_per_level < 1) return fail(&c, PBA_E_INVALID, "max_iters_per_level must be >= 1");
     if (!(conv_px >= 0.0)) return fail(&c, PBA_E_INVALID, "conv_px must be >= 0");
+    pba_status st;
+    if ((st = ready(ctx)) != PBA_OK) return st;
     pba_result res;
     std::memset(&res, 0, sizeof(res));
-    pba_status st;
-    for (int level = c.cfg.n_levels - 1; level >= 0; --level) {
-        if ((st = do_start_level(c, level)) != PBA_OK) return st;
-        std::vector<pba_iter_stats> its(max_iters_per_level);
-        int k = 0;
-        if ((st = run_iterations(c, level, max_iters_per_level, its.data(), conv_px, &k)) != PBA_OK) return st;
-        const bool conv = k > 0 && its[k - 1].max_disp_px < conv_px;
-        for (int i = 0; i < k; ++i) res.active_residuals += its[i].n_active;
-        res.iters[level] = k;
-        res.total_iters += k;
-        if (level == 0) res.converged = conv ? 1 : 0;
-    }
+    if ((st = solve_batch(c, max_iters_per_level, conv_px, res)) != PBA_OK) return st;
     pba_iter_stats ev;
     if ((st = pba_evaluate(ctx, 0, &ev)) != PBA_OK) return st;
     res.final_energy = ev.energy;
@@ -838,12 +1079,22 @@ pba_status pba_solve(pba_ctx *ctx, int32_t max_iters_per_level, double conv_px, 
 pba_status pba_get_params(pba_ctx *ctx, int32_t window, double *poses, double *inv_depth) {
     if (!ctx) return fail(nullptr, PBA_E_INVALID, "ctx is NULL");
     Ctx &c = ctx->c;
-    if (window != 0) return fail(&c, PBA_E_INVALID, "window must be 0");
+    if (window < 0 || window >= c.cfg.n_windows) return fail(&c, PBA_E_INVALID, "window must be in 0..n_windows-1");
+    if (c.cfg.n_windows > 1) {
+        pba_status st;
+        if ((st = ready(ctx)) != PBA_OK) return st;
+    }
     if (!c.have_frames) return fail(&c, PBA_E_STATE, "no frames set");
+    const int f0 = c.win_frame_off[window], f1 = c.win_frame_off[window + 1];
     if (poses)
-        HIPCHK(hipMemcpyAsync(poses, c.d_poses, (size_t)c.F * 12 * sizeof(double), hipMemcpyDeviceToHost, c.stream));
-    if (inv_depth && c.have_points && c.N > 0)
-        HIPCHK(hipMemcpyAsync(inv_depth, c.d_depth, (size_t)c.N * sizeof(double), hipMemcpyDeviceToHost, c.stream));
+        HIPCHK(hipMemcpyAsync(poses, c.d_poses + 12 * (size_t)f0, (size_t)(f1 - f0) * 12 * sizeof(double),
+                              hipMemcpyDeviceToHost, c.stream));
+    if (inv_depth && c.have_points) {
+        const int n0 = c.win_point_off[window], n1 = c.win_point_off[window + 1];
+        if (n1 > n0)
+            HIPCHK(hipMemcpyAsync(inv_depth, c.d_depth + n0, (size_t)(n1 - n0) * sizeof(double), hipMemcpyDeviceToHost,
+                                  c.stream));
+    }
     HIPCHK(hipStreamSynchronize(c.stream));
     return PBA_OK;
 }
@@ -851,18 +1102,23 @@ pba_status pba_get_params(pba_ctx *ctx, int32_t window, double *poses, double *i
 pba_status pba_set_params(pba_ctx *ctx, int32_t window, const double *poses, const double *inv_depth) {
     if (!ctx) return fail(nullptr, PBA_E_INVALID, "ctx is NULL");
     Ctx &c = ctx->c;
-    if (window != 0) return fail(&c, PBA_E_INVALID, "window must be 0");
-    if (!c.have_points) return fail(&c, PBA_E_STATE, "pba_set_frames and pba_set_points must be called first");
-    if (poses && !finite_all(poses, (size_t)c.F * 12)) return fail(&c, PBA_E_INVALID, "poses not finite");
+    if (window < 0 || window >= c.cfg.n_windows) return fail(&c, PBA_E_INVALID, "window must be in 0..n_windows-1");
+    pba_status st;
+    if ((st = ready(ctx)) != PBA_OK) return st;
+    const int f0 = c.win_frame_off[window], f1 = c.win_frame_off[window + 1];
+    const int n0 = c.win_point_off[window], n1 = c.win_point_off[window + 1];
+    if (poses && !finite_all(poses, (size_t)(f1 - f0) * 12)) return fail(&c, PBA_E_INVALID, "poses not finite");
     if (inv_depth) {
-        for (int n = 0; n < c.N; ++n)
+        for (int n = 0; n < n1 - n0; ++n)
             if (!std::isfinite(inv_depth[n]) || !(inv_depth[n] > 0.0))
                 return fail(&c, PBA_E_INVALID, "inv_depth must be finite and > 0");
     }
     if (poses)
-        HIPCHK(hipMemcpyAsync(c.d_poses, poses, (size_t)c.F * 12 * sizeof(double), hipMemcpyHostToDevice, c.stream));
-    if (inv_depth && c.N > 0)
-        HIPCHK(hipMemcpyAsync(c.d_depth, inv_depth, (size_t)c.N * sizeof(double), hipMemcpyHostToDevice, c.stream));
+        HIPCHK(hipMemcpyAsync(c.d_poses + 12 * (size_t)f0, poses, (size_t)(f1 - f0) * 12 * sizeof(double),
+                              hipMemcpyHostToDevice, c.stream));
+    if (inv_depth && n1 > n0)
+        HIPCHK(hipMemcpyAsync(c.d_depth + n0, inv_depth, (size_t)(n1 - n0) * sizeof(double), hipMemcpyHostToDevice,
+                              c.stream));
     HIPCHK(hipStreamSynchronize(c.stream));
     c.cur_level = -1;
     return PBA_OK;
@@ -872,12 +1128,13 @@ pba_status pba_debug_fetch(pba_ctx *ctx, int32_t what, void *out, size_t bytes) 
     if (!ctx) return fail(nullptr, PBA_E_INVALID, "ctx is NULL");
     Ctx &c = ctx->c;
     if (!out) return fail(&c, PBA_E_INVALID, "out is NULL");
-    if (!c.have_points) return fail(&c, PBA_E_STATE, "no problem set");
+    pba_status st0;
+    if ((st0 = ready(ctx)) != PBA_OK) return st0;
     const size_t n6 = 6 * (size_t)c.F;
     const void *src = nullptr;
     size_t need = 0;
     switch (what) {
-        case PBA_DBG_S: src = c.d_S; need = n6 * n6 * sizeof(double); break;
+        case PBA_DBG_S: src = c.d_S; need = (size_t)c.win_S_off[c.nwin] * sizeof(double); break;
         case PBA_DBG_B: src = c.d_b; need = n6 * sizeof(double); break;
         case PBA_DBG_OBS_REC: src = c.d_rec; need = (size_t)c.O * REC_STRIDE * c.real_size; break;
         case PBA_DBG_TEMPLATE: {

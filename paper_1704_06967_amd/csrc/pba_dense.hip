@@ -199,9 +199,14 @@ __global__ __launch_bounds__(256) void k_tinv_columns(int n, const double *__res
 
 __global__ void k_copy_d(const double *__restrict__ src, double *__restrict__ dst, size_t n,
                          const int *__restrict__ gate) {
-    if (*gate == 0) return;
+    if (gate && *gate == 0) return;
     const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) dst[i] = src[i];
+}
+
+void launch_copy_d(hipStream_t s, const double *src, double *dst, size_t n) {
+    if (n == 0) return;
+    k_copy_d<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(src, dst, n, nullptr);
 }
 
 void launch_tchol(hipStream_t s, Ctx &c) {

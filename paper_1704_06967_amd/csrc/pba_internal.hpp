@@ -43,6 +43,17 @@ constexpr int PAIR_CHUNK = 512;       // observations per pair-reduction workgro
 constexpr int LDS_CHOL_MAX_N = 180;   // largest reduced system factored in one workgroup's LDS
 constexpr int TCHOL_TILE = 32;        // tile edge of the tiled Cholesky for larger systems
 
+// Independent problems (windows) held by one context: frames, points and pairs
+// of window w are the contiguous ranges [off[w], off[w + 1]) of the global
+// arrays; the reduced system is block diagonal, window w's block (6 F_w square)
+// starting at S_off[w] doubles (its packed factor at L_off[w]). One window is
+// the single-problem case.
+struct WinArgs {
+    int nwin;
+    const int *frame_off, *pair_off, *point_off, *S_off, *L_off;  // [nwin + 1]
+    const int *frame_win, *point_win;                             // [F], [N]
+};
+
 struct LevelDev {
     int W = 0, H = 0;
     void *img = nullptr;      // T [F][H][W]
@@ -97,6 +108,17 @@ struct Ctx {
     int N = 0, O = 0, P = 0;
     Structure st;
 
+    // windows (host copies of the offsets; see WinArgs)
+    int nwin = 1;
+    std::vector<int> win_frame_off, win_point_off, win_pair_off, win_S_off, win_L_off;
+    int *d_win_frame_off = nullptr, *d_win_pair_off = nullptr, *d_win_point_off = nullptr, *d_win_S_off = nullptr,
+        *d_win_L_off = nullptr, *d_frame_win = nullptr, *d_point_win = nullptr;
+    double *d_wstat = nullptr;                         // [nwin][4] per-window E, SQ, CNT, max pose step
+    WinArgs win() const {
+        return WinArgs{nwin, d_win_frame_off, d_win_pair_off, d_win_point_off, d_win_S_off, d_win_L_off,
+                       d_frame_win, d_point_win};
+    }
+
     // device buffers (generic pointers; element type per precision)
     double *d_poses = nullptr, *d_poses0 = nullptr;   // [F][12]
     double *d_K0 = nullptr;                           // [F][4] level-0 intrinsics
@@ -119,8 +141,7 @@ struct Ctx {
     double *d_partH = nullptr, *d_partY = nullptr;     // per pair chunk partials [nch][21], [nch][9]
     double *d_obsmap = nullptr;                        // [O][12] observation couplings for the Gram
     double *d_Hdd = nullptr, *d_gd = nullptr;          // [N] (Hdd damped after assembly)
-    double *d_hdd_part = nullptr;                      // partial sums for the depth damping
-    double *d_mu = nullptr;                            // [2] mu_p, mu_d
+    double *d_mu = nullptr;                            // [nwin][2] mu_p, mu_d
     double *d_gram = nullptr;                          // chunk partials
     double *d_S = nullptr;                             // [6F][6F] reduced system / factor
     double *d_Sinv = nullptr;                          // IC: S^{-1} at p(0) [6F][6F]
@@ -133,12 +154,17 @@ struct Ctx {
     int stats_cap = 0;
     int *d_flag = nullptr;                             // device error flag (non-SPD)
     int *d_gate = nullptr;                             // 1 while the current solve level runs
-    int *d_count = nullptr;                            // iterations run in the current level
+    int *d_count = nullptr;                            // iterations run per level [PBA_MAX_LEVELS]
     double *d_du_part = nullptr;                       // depth-update block maxima [blocks][2]
-    int hdd_blocks = 0;
 
     // current double-buffer orientation
     bool flip = false;
+
+    // a whole coarse-to-fine solve captured as one HIP graph (PBA_FLAG_GRAPH)
+    hipGraphExec_t solve_graph = nullptr;
+    int graph_iters = -1;
+    double graph_conv = -1.0;
+    double *d_eval = nullptr;                          // [3] sums of the evaluation kernel
 
     // timing
     std::vector<hipEvent_t> ev_pool;
@@ -161,7 +187,7 @@ template <typename T> struct Launch {
     static void pair_reduce_H(hipStream_t s, Ctx &c);
     static void pair_reduce_y(hipStream_t s, Ctx &c);
     static void depth_update(hipStream_t s, Ctx &c, const double *geo_old, const double *geo_new, double *stat,
-                             double conv_px);
+                             double conv_px, int level);
 };
 
 // mixed precision linearization (pair order, BF16 MFMA pose blocks into the pair chunk partials)
@@ -175,10 +201,13 @@ void launch_ic_factor(hipStream_t s, Ctx &c);
 void launch_solve(hipStream_t s, Ctx &c, const double *geo_lin, double *geo_next, void *rel_next,
                   bool rel_double, double *stat);
 void launch_sum_stats(hipStream_t s, Ctx &c, const void *rec, bool rec_double, double *out3);
-void launch_conv(hipStream_t s, Ctx &c, double *stat, double conv_px, int nparts);
+void launch_conv(hipStream_t s, Ctx &c, double *stat, double conv_px, int nparts, int level);
+// count[level] = 0, optionally flag = 0, then gate = (flag == 0)
+void launch_open(hipStream_t s, Ctx &c, int level, bool clear_flag);
 void launch_ic_inverse(hipStream_t s, Ctx &c);
 void launch_tchol(hipStream_t s, Ctx &c);   // copy S to d_Sfac and factor it in tiles
 void launch_tinv(hipStream_t s, Ctx &c);    // S^{-1} from the tiled factor
+void launch_copy_d(hipStream_t s, const double *src, double *dst, size_t n);  // device copy as a kernel
 void launch_fill(hipStream_t s, double *p, size_t n, double v, const int *gate);
 
 }  // namespace pba

@@ -457,14 +457,12 @@ __device__ __forceinline__ void block_sum(double v[NV], double *lds /* [NV * 16]
     __syncthreads();
 }
 
-// Per point: sum of the depth blocks over the point's observations; block
-// partial sums of H_dd for the depth damping.
+// Per point: sum of the depth blocks over the point's observations.
 template <typename T>
 __global__ __launch_bounds__(256) void k_point_reduce(int N, const int *__restrict__ obs_ptr,
                                                       const T *__restrict__ rec, double *__restrict__ Hdd,
-                                                      double *__restrict__ gd, double *__restrict__ part,
-                                                      int with_hdd, const int *__restrict__ gate) {
-    __shared__ double lds[16];
+                                                      double *__restrict__ gd, int with_hdd,
+                                                      const int *__restrict__ gate) {
     if (*gate == 0) return;
     const int n = blockIdx.x * blockDim.x + threadIdx.x;
     double hs = 0.0, gs = 0.0;
@@ -476,11 +474,6 @@ __global__ __launch_bounds__(256) void k_point_reduce(int N, const int *__restri
         }
         gd[n] = gs;
         if (with_hdd) Hdd[n] = hs;
-    }
-    if (with_hdd) {
-        double v[1] = {hs};
-        block_sum<1>(v, lds);
-        if (threadIdx.x == 0) part[blockIdx.x] = v[0];
     }
 }
 
@@ -769,8 +762,8 @@ void Launch<T>::evaluate(hipStream_t s, Ctx &c, int level) {
 template <typename T>
 void Launch<T>::point_reduce(hipStream_t s, Ctx &c, bool with_hdd) {
     if (c.N == 0) return;
-    k_point_reduce<T><<<c.hdd_blocks, 256, 0, s>>>(c.N, c.d_obs_ptr, (const T *)c.d_rec, c.d_Hdd, c.d_gd,
-                                                   c.d_hdd_part, with_hdd ? 1 : 0, c.d_gate);
+    k_point_reduce<T><<<nblk(c.N, 256), 256, 0, s>>>(c.N, c.d_obs_ptr, (const T *)c.d_rec, c.d_Hdd, c.d_gd,
+                                                     with_hdd ? 1 : 0, c.d_gate);
     CHECK_LAUNCH();
 }
 
@@ -794,7 +787,7 @@ void Launch<T>::pair_reduce_y(hipStream_t s, Ctx &c) {
 
 template <typename T>
 void Launch<T>::depth_update(hipStream_t s, Ctx &c, const double *geo_old, const double *geo_new, double *stat,
-                             double conv_px) {
+                             double conv_px, int level) {
     const int nb = (int)nblk(c.N, DU_PTS);
     if (c.N > 0)
         k_depth_update<T><<<nb, 256, 0, s>>>(c.N, c.cfg.mode == PBA_IC_PROXY ? 1 : 0, c.d_obs_ptr, c.d_obs_pair,
@@ -802,14 +795,16 @@ void Launch<T>::depth_update(hipStream_t s, Ctx &c, const double *geo_old, const
                                              (const T *)c.d_rec, c.d_Hdd, c.d_dth_rel, geo_old, geo_new, c.d_depth,
                                              c.d_depth0, c.d_du_part, c.d_gate, c.d_flag);
     CHECK_LAUNCH();
-    launch_conv(s, c, stat, conv_px, c.N > 0 ? nb : 0);
+    launch_conv(s, c, stat, conv_px, c.N > 0 ? nb : 0, level);
 }
 
-// Maxima of the depth update's block partials into the iteration's statistics
-// and, with conv_px >= 0, the convergence test of the coarse-to-fine solve
-// (Sec. 4.1): count the iteration and close the gate once the largest
-// point-centre displacement is below conv_px.
-__global__ __launch_bounds__(256) void k_conv(const double *__restrict__ part, int nparts, double *__restrict__ stat,
+// End of an iteration (single block): the window statistics of the solve
+// kernel added over the windows in order, the largest point-centre
+// displacement and depth step from the depth-update block maxima, and the
+// convergence gate: with conv_px >= 0 the iteration is counted and the gate
+// closes once the displacement is below conv_px.
+__global__ __launch_bounds__(256) void k_conv(const double *__restrict__ part, int nparts,
+                                              const double *__restrict__ wstat, int nwin, double *__restrict__ stat,
                                               double conv_px, int *__restrict__ gate, int *__restrict__ count,
                                               const int *__restrict__ flag) {
     __shared__ double red[2][4];
@@ -837,16 +832,42 @@ __global__ __launch_bounds__(256) void k_conv(const double *__restrict__ part, i
         *gate = 0;
         return;
     }
+    double e = 0.0, sq = 0.0, cnt = 0.0, sp = 0.0;
+    for (int w = 0; w < nwin; ++w) {
+        e += wstat[4 * w];
+        sq += wstat[4 * w + 1];
+        cnt += wstat[4 * w + 2];
+        sp = fmax(sp, wstat[4 * w + 3]);
+    }
+    stat[ST_E] = e;
+    stat[ST_SQ] = sq;
+    stat[ST_CNT] = cnt;
+    stat[ST_STEP_P] = sp;
     stat[ST_DISP] = md;
     stat[ST_STEP_D] = ms;
-    if (conv_px >= 0.0) {
-        *count += 1;
-        if (md < conv_px) *gate = 0;
+    *count += 1;
+    if (conv_px >= 0.0 && md < conv_px) *gate = 0;
+}
+
+// Start of a batch of iterations: clear the level's iteration count and
+// (clear_flag) the failure flag, and open the gate unless a failure is flagged
+// (a kernel, so that it can be captured in a graph).
+__global__ void k_open(int *__restrict__ gate, int *__restrict__ flag, int *__restrict__ count, int clear_flag) {
+    if (threadIdx.x == 0) {
+        if (clear_flag) *flag = 0;
+        *gate = *flag == 0 ? 1 : 0;
+        *count = 0;
     }
 }
 
-void launch_conv(hipStream_t s, Ctx &c, double *stat, double conv_px, int nparts) {
-    k_conv<<<1, 256, 0, s>>>(c.d_du_part, nparts, stat, conv_px, c.d_gate, c.d_count, c.d_flag);
+void launch_conv(hipStream_t s, Ctx &c, double *stat, double conv_px, int nparts, int level) {
+    k_conv<<<1, 256, 0, s>>>(c.d_du_part, nparts, c.d_wstat, c.nwin, stat, conv_px, c.d_gate, c.d_count + level,
+                             c.d_flag);
+    CHECK_LAUNCH();
+}
+
+void launch_open(hipStream_t s, Ctx &c, int level, bool clear_flag) {
+    k_open<<<1, 64, 0, s>>>(c.d_gate, c.d_flag, c.d_count + level, clear_flag ? 1 : 0);
     CHECK_LAUNCH();
 }
 

@@ -65,47 +65,49 @@ __global__ void k_fill(double *__restrict__ p, size_t n, double v, const int *__
     if (i < n) p[i] = v;
 }
 
-// Pair sums of the pose-pose blocks (chunk partials added in order) and the
-// damping of the pose and depth diagonals: mu = damping_rel x mean diagonal of
-// the undamped blocks (damping_rel when that mean is zero).
-__global__ __launch_bounds__(256) void k_mu(int Pn, int F, int N, int hdd_blocks, double damping,
-                                            const int *__restrict__ pair_chunk_ptr, const double *__restrict__ partH,
-                                            double *__restrict__ pairH, const double *__restrict__ geo,
-                                            const double *__restrict__ hdd_part, double *__restrict__ mu,
-                                            const int *__restrict__ gate) {
-    __shared__ double lds[16];
+// Per window (one block each): pair sums of the pose-pose blocks (chunk
+// partials added in order) and the damping of the pose and depth diagonals:
+// mu = damping_rel x mean diagonal of the window's undamped blocks (damping_rel
+// when that mean is zero).
+__global__ __launch_bounds__(1024) void k_mu(WinArgs wa, double damping, const int *__restrict__ pair_chunk_ptr,
+                                             const double *__restrict__ partH, double *__restrict__ pairH,
+                                             const double *__restrict__ geo, const double *__restrict__ Hdd,
+                                             double *__restrict__ mu, const int *__restrict__ gate) {
+    __shared__ double lds[2 * 16];
     if (*gate == 0) return;
-    for (int e = threadIdx.x; e < Pn * 21; e += blockDim.x) {
-        const int p = e / 21, k = e % 21;
+    const int w = blockIdx.x;
+    const int p0 = wa.pair_off[w], p1 = wa.pair_off[w + 1];
+    for (int e = threadIdx.x; e < (p1 - p0) * 21; e += blockDim.x) {
+        const int p = p0 + e / 21, k = e % 21;
         double s = 0.0;
         for (int c = pair_chunk_ptr[p]; c < pair_chunk_ptr[p + 1]; ++c) s += partH[21 * c + k];
-        pairH[e] = s;
+        pairH[21 * p + k] = s;
     }
     __threadfence_block();
     __syncthreads();
-    double s = 0.0;
-    for (int e = threadIdx.x; e < Pn * 6; e += blockDim.x) {
-        const int p = e / 6, r = e % 6;
+    double v[2] = {0.0, 0.0};
+    for (int e = threadIdx.x; e < (p1 - p0) * 6; e += blockDim.x) {
+        const int p = p0 + e / 6, r = e % 6;
         double A[36], B[36];
         abs_maps(geo + GEO_STRIDE * p, A, B);
-        s += xthy(A, pairH + 21 * p, A, r, r) + xthy(B, pairH + 21 * p, B, r, r);
+        v[0] += xthy(A, pairH + 21 * p, A, r, r) + xthy(B, pairH + 21 * p, B, r, r);
     }
-    double v[1] = {s};
-    block_sum_d<1>(v, lds);
+    const int n0 = wa.point_off[w], n1 = wa.point_off[w + 1];
+    for (int n = n0 + threadIdx.x; n < n1; n += blockDim.x) v[1] += Hdd[n];
+    block_sum_d<2>(v, lds);
     if (threadIdx.x == 0) {
-        double hs = 0.0;
-        for (int k = 0; k < hdd_blocks; ++k) hs += hdd_part[k];
-        const double mp = v[0] / (6.0 * F), md = N > 0 ? hs / N : 0.0;
-        mu[0] = mp > 0.0 ? damping * mp : damping;
-        mu[1] = md > 0.0 ? damping * md : damping;
+        const int Fw = wa.frame_off[w + 1] - wa.frame_off[w], Nw = n1 - n0;
+        const double mp = Fw > 0 ? v[0] / (6.0 * Fw) : 0.0, md = Nw > 0 ? v[1] / Nw : 0.0;
+        mu[2 * w] = mp > 0.0 ? damping * mp : damping;
+        mu[2 * w + 1] = md > 0.0 ? damping * md : damping;
     }
 }
 
 __global__ void k_damp_hdd(int N, double *__restrict__ Hdd, const double *__restrict__ mu,
-                           const int *__restrict__ gate) {
+                           const int *__restrict__ point_win, const int *__restrict__ gate) {
     if (*gate == 0) return;
     int n = blockIdx.x * blockDim.x + threadIdx.x;
-    if (n < N) Hdd[n] += mu[1];
+    if (n < N) Hdd[n] += mu[2 * point_win[n] + 1];
 }
 
 // Coupling of every observation to its target and host poses in absolute
@@ -203,8 +205,9 @@ __global__ __launch_bounds__(256) void k_gram(const int *__restrict__ chunk_host
 
 // Reduced pose system S = H_pp + mu_p I - sum_n h_n h_n^T / H_dd,n, one nonzero
 // 6x6 block per workgroup: mapped pair blocks (A^T H A, B^T H B, A^T H B, B^T H A)
-// minus the host Gram blocks, then the gauge pin (identity rows / columns).
-__global__ __launch_bounds__(64) void k_assemble_s(int n6, int pinned, const int *__restrict__ blk_fa,
+// minus the host Gram blocks, then the gauge pin (identity rows / columns) of
+// the window's pinned frame; written into the window's diagonal block of S.
+__global__ __launch_bounds__(64) void k_assemble_s(WinArgs wa, int pinned, const int *__restrict__ blk_fa,
                                                    const int *__restrict__ blk_fb, const int *__restrict__ pp_ptr,
                                                    const int *__restrict__ pp_item, const int *__restrict__ g_ptr,
                                                    const int *__restrict__ g_item, const int *__restrict__ host_m,
@@ -218,6 +221,8 @@ __global__ __launch_bounds__(64) void k_assemble_s(int n6, int pinned, const int
     if (threadIdx.x >= 36) return;
     const int r = threadIdx.x / 6, c = threadIdx.x % 6;
     const int fa = blk_fa[b], fb = blk_fb[b];
+    const int w = wa.frame_win[fa], f0 = wa.frame_off[w], nw = 6 * (wa.frame_off[w + 1] - f0);
+    const int la = fa - f0, lb = fb - f0;
     double val = 0.0;
     for (int i = pp_ptr[b]; i < pp_ptr[b + 1]; ++i) {
         const int p = pp_item[i] >> 2, kind = pp_item[i] & 3;
@@ -234,9 +239,9 @@ __global__ __launch_bounds__(64) void k_assemble_s(int n6, int pinned, const int
         const size_t idx = (size_t)(6 * a + r) * E + 6 * bb + c;
         for (int ch = host_chunk_ptr[hi]; ch < host_chunk_ptr[hi + 1]; ++ch) val -= gram[(size_t)chunk_off[ch] + idx];
     }
-    if (fa == fb && r == c) val += mu[0];
-    if (pinned >= 0 && (fa == pinned || fb == pinned)) val = (fa == fb && r == c) ? 1.0 : 0.0;
-    S[(size_t)(6 * fa + r) * n6 + 6 * fb + c] = val;
+    if (fa == fb && r == c) val += mu[2 * w];
+    if (pinned >= 0 && (la == pinned || lb == pinned)) val = (fa == fb && r == c) ? 1.0 : 0.0;
+    S[(size_t)wa.S_off[w] + (size_t)(6 * la + r) * nw + 6 * lb + c] = val;
 }
 
 // ---- dense SPD helpers for one workgroup of SOLVE_THREADS threads (packed
@@ -370,14 +375,18 @@ __device__ __forceinline__ bool chol_blocked(double *A, int n, double *panel, do
 }
 
 // IC setup: Cholesky factorization of S, once per level (the paper's "H need
-// only be inverted once"); every iteration then runs two triangular solves.
-// The factor is stored packed (lower, row-major) followed by 1 / L(k, k).
-__global__ __launch_bounds__(SOLVE_THREADS) void k_ic_factor(int n, double *__restrict__ S,
-                                                             double *__restrict__ Lout, int *__restrict__ flag,
+// only be inverted once"), one window per workgroup. The factor is stored
+// packed (lower, row-major) followed by 1 / L(k, k).
+__global__ __launch_bounds__(SOLVE_THREADS) void k_ic_factor(WinArgs wa, double *__restrict__ S_all,
+                                                             double *__restrict__ L_all, int *__restrict__ flag,
                                                              const int *__restrict__ gate) {
     __shared__ double lds[LDS_DOUBLES];
     __shared__ int fail;
     if (*gate == 0) return;
+    const int w = blockIdx.x;
+    const int n = 6 * (wa.frame_off[w + 1] - wa.frame_off[w]);
+    const double *S = S_all + wa.S_off[w];
+    double *Lout = L_all + wa.L_off[w];
     const int np = n * (n + 1) / 2;
     for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
         const int i = e / n, j = e % n;
@@ -392,14 +401,19 @@ __global__ __launch_bounds__(SOLVE_THREADS) void k_ic_factor(int n, double *__re
 }
 
 // IC setup: S^{-1} = L^{-T} L^{-1} from the packed factor, one column per
-// wavefront over ceil(n / 16) workgroups (each holds the factor in LDS). With
-// S^{-1} stored, every iteration's step is one matrix-vector product.
-__global__ __launch_bounds__(SOLVE_THREADS) void k_ic_inverse(int n, const double *__restrict__ Lfac,
-                                                              double *__restrict__ Sinv,
+// wavefront over ceil(n / 16) workgroups per window (each holds the factor in
+// LDS). With S^{-1} stored, every iteration's step is one matrix-vector product.
+__global__ __launch_bounds__(SOLVE_THREADS) void k_ic_inverse(WinArgs wa, const double *__restrict__ L_all,
+                                                              double *__restrict__ Sinv_all,
                                                               const int *__restrict__ flag,
                                                               const int *__restrict__ gate) {
     __shared__ double lds[LDS_DOUBLES];
     if (*gate == 0 || *flag) return;
+    const int w = blockIdx.y;
+    const int n = 6 * (wa.frame_off[w + 1] - wa.frame_off[w]);
+    if ((int)blockIdx.x * (SOLVE_THREADS / 64) >= n) return;
+    const double *Lfac = L_all + wa.L_off[w];
+    double *Sinv = Sinv_all + wa.S_off[w];
     const int np = n * (n + 1) / 2;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     for (int e = threadIdx.x; e < np + n; e += blockDim.x) lds[e] = Lfac[e];
@@ -418,75 +432,83 @@ __global__ __launch_bounds__(SOLVE_THREADS) void k_ic_inverse(int n, const doubl
 }
 
 void launch_ic_inverse(hipStream_t s, Ctx &c) {
-    const int n = 6 * c.F;
-    if (n > LDS_MAX_N) {
+    if (c.nwin == 1 && 6 * c.F > LDS_MAX_N) {
         launch_tinv(s, c);
         return;
     }
-    const int grid = (n + SOLVE_THREADS / 64 - 1) / (SOLVE_THREADS / 64);
-    k_ic_inverse<<<grid, SOLVE_THREADS, 0, s>>>(n, c.d_Lfac, c.d_Sinv, c.d_flag, c.d_gate);
+    int nmax = 0;
+    for (int w = 0; w < c.nwin; ++w) nmax = std::max(nmax, 6 * (c.win_frame_off[w + 1] - c.win_frame_off[w]));
+    const dim3 grid((nmax + SOLVE_THREADS / 64 - 1) / (SOLVE_THREADS / 64), c.nwin);
+    k_ic_inverse<<<grid, SOLVE_THREADS, 0, s>>>(c.win(), c.d_Lfac, c.d_Sinv, c.d_flag, c.d_gate);
 }
 
-// One solve per iteration (single workgroup):
+// One solve per iteration and window (one workgroup each):
 //  0. pair sums of the reduced gradient from their chunk partials;
 //  1. reduced right-hand side b_f = sum over the frame's pairs of A^T y (target) or
-//     B^T y (host), zero on the pinned frame;
+//     B^T y (host), zero on the window's pinned frame;
 //  2. dtheta = -S^{-1} b (IC: product with the stored inverse, one wavefront per
 //     row; FC: Cholesky of the freshly assembled S and two triangular solves);
 //  3. pose update: IC R <- R_k R0^T exp(dw)^T R0, t <- t_k - R_k R0^T dt (Sec. 3.6);
 //     FC R <- exp(dw) R, t <- t + dt;
 //  4. the next relative poses of every pair and the relative steps A dth_f + B dth_h.
+// Window statistics (energy, squared residuals, count, largest pose step) go
+// to wstat[w]; the convergence kernel adds them over the windows.
 template <typename T>
 __global__ __launch_bounds__(SOLVE_THREADS) void k_solve(
-    int ic, int F, int Pn, int pinned, const int *__restrict__ frame_pair_ptr, const int *__restrict__ frame_pair_item,
+    WinArgs wa, int ic, int pinned, const int *__restrict__ frame_pair_ptr, const int *__restrict__ frame_pair_item,
     const int *__restrict__ pair_host, const int *__restrict__ pair_target, const int *__restrict__ pair_chunk_ptr,
     const double *__restrict__ partY, double *__restrict__ pairY, const double *__restrict__ geo_lin,
-    double *__restrict__ S, const double *__restrict__ Sfac, const double *__restrict__ Linv,
-    const double *__restrict__ Sinv, double *__restrict__ poses,
-    const double *__restrict__ poses0, double *__restrict__ b_out, double *__restrict__ dth_out,
-    double *__restrict__ dth_rel, double *__restrict__ geo_next, T *__restrict__ rel_next, double *__restrict__ stat,
-    int *__restrict__ flag, int *__restrict__ gate) {
+    const double *__restrict__ S_all, const double *__restrict__ Sfac, const double *__restrict__ Linv,
+    const double *__restrict__ Sinv_all, double *__restrict__ poses, const double *__restrict__ poses0,
+    double *__restrict__ b_all, double *__restrict__ dth_all, double *__restrict__ dth_rel,
+    double *__restrict__ geo_next, T *__restrict__ rel_next, double *__restrict__ wstat, int *__restrict__ flag,
+    int *__restrict__ gate) {
     __shared__ double lds[LDS_DOUBLES];
     __shared__ double red[64 + 2 * LDS_MAX_N + 2];
     if (*gate == 0) return;
     if (*flag) {
-        // the tiled factorization of this iteration failed: stop the batch
+        // a factorization of this iteration failed: stop the batch
         if (threadIdx.x == 0) *gate = 0;
         return;
     }
+    const int w = blockIdx.x;
+    const int f0 = wa.frame_off[w], F = wa.frame_off[w + 1] - f0;
+    const int p0 = wa.pair_off[w], p1 = wa.pair_off[w + 1];
     const int n = 6 * F;
+    const double *S = S_all + wa.S_off[w];
+    const double *Sinv = Sinv_all + wa.S_off[w];
+    double *b_out = b_all + 6 * f0;
+    double *dth_out = dth_all + 6 * f0;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
     const bool packed = n <= LDS_MAX_N;
     // rhs / solution in LDS (FC: after the packed factor; the panel scratch follows)
     double *bx = lds + ((packed && !ic) ? n * (n + 1) / 2 : 0);
-    for (int e = threadIdx.x; e < Pn * 9; e += blockDim.x) {
-        const int p = e / 9, k = e % 9;
+    for (int e = threadIdx.x; e < (p1 - p0) * 9; e += blockDim.x) {
+        const int p = p0 + e / 9, k = e % 9;
         double s = 0.0;
         for (int c = pair_chunk_ptr[p]; c < pair_chunk_ptr[p + 1]; ++c) s += partY[9 * c + k];
-        pairY[e] = s;
+        pairY[9 * p + k] = s;
     }
     __threadfence_block();
     __syncthreads();
     {
         double v3[3] = {0.0, 0.0, 0.0};
-        for (int p = threadIdx.x; p < Pn; p += blockDim.x) {
+        for (int p = p0 + threadIdx.x; p < p1; p += blockDim.x) {
             v3[0] += pairY[9 * p + 6];
             v3[1] += pairY[9 * p + 7];
             v3[2] += pairY[9 * p + 8];
         }
         block_sum_d<3>(v3, red);
         if (threadIdx.x == 0) {
-            stat[ST_E] = v3[0];
-            stat[ST_SQ] = v3[1];
-            stat[ST_CNT] = v3[2];
-            stat[ST_DISP] = 0.0;
-            stat[ST_STEP_D] = 0.0;
+            wstat[4 * w + 0] = v3[0];
+            wstat[4 * w + 1] = v3[1];
+            wstat[4 * w + 2] = v3[2];
         }
     }
     for (int e = threadIdx.x; e < n; e += blockDim.x) {
-        const int f = e / 6, r = e % 6;
+        const int lf = e / 6, r = e % 6, f = f0 + lf;
         double s = 0.0;
-        if (f != pinned) {
+        if (lf != pinned) {
             for (int i = frame_pair_ptr[f]; i < frame_pair_ptr[f + 1]; ++i) {
                 const int p = frame_pair_item[i] >> 1, is_host = frame_pair_item[i] & 1;
                 double yv[6], out[6];
@@ -544,7 +566,7 @@ __global__ __launch_bounds__(SOLVE_THREADS) void k_solve(
             }
         }
     } else {
-        // FC, 6F > LDS_MAX_N: S was factored in tiles before this kernel
+        // FC, one window with 6F > LDS_MAX_N: S was factored in tiles before this kernel
         tile_chol_solve<SOLVE_THREADS>(Sfac, Linv, n, bx, lds + n, 0);
         for (int i = threadIdx.x; i < n; i += blockDim.x) dth_out[i] = -bx[i];
     }
@@ -556,13 +578,13 @@ __global__ __launch_bounds__(SOLVE_THREADS) void k_solve(
     for (int k = 32; k >= 1; k >>= 1) mx = fmax(mx, __shfl_xor(mx, k, 64));
     if (lane == 0) red[wv] = mx;
     // pose update
-    for (int f = threadIdx.x; f < F; f += blockDim.x) {
-        const double *x = dth_out + 6 * f;
+    for (int lf = threadIdx.x; lf < F; lf += blockDim.x) {
+        const double *x = dth_out + 6 * lf;
         double dR[9], Rn[9], tn[3];
         so3_exp(x, dR);
-        double *P = poses + 12 * f;
+        double *P = poses + 12 * (f0 + lf);
         if (ic) {
-            const double *P0 = poses0 + 12 * f;
+            const double *P0 = poses0 + 12 * (f0 + lf);
             double A[9], Q[9];
             mat3_mul_bt(P, P0, Q);  // R_k R0^T
             mat3_mul_bt(Q, dR, A);  // R_k R0^T dR^T
@@ -580,10 +602,10 @@ __global__ __launch_bounds__(SOLVE_THREADS) void k_solve(
     if (threadIdx.x == 0) {
         double m2 = 0.0;
         for (int k = 0; k < nw; ++k) m2 = fmax(m2, red[k]);
-        stat[ST_STEP_P] = m2;
+        wstat[4 * w + 3] = m2;
     }
     // next relative poses and relative steps per pair
-    for (int p = threadIdx.x; p < Pn; p += blockDim.x) {
+    for (int p = p0 + threadIdx.x; p < p1; p += blockDim.x) {
         const double *Ph = poses + 12 * pair_host[p];
         const double *Pf = poses + 12 * pair_target[p];
         double R[9];
@@ -603,8 +625,8 @@ __global__ __launch_bounds__(SOLVE_THREADS) void k_solve(
         g[15] = 0.0;
         double xf[6], xh[6], af[6], bh[6];
         for (int a = 0; a < 6; ++a) {
-            xf[a] = dth_out[6 * pair_target[p] + a];
-            xh[a] = dth_out[6 * pair_host[p] + a];
+            xf[a] = dth_all[6 * pair_target[p] + a];
+            xh[a] = dth_all[6 * pair_host[p] + a];
         }
         apply_A(geo_lin + GEO_STRIDE * p, xf, af);
         apply_B(geo_lin + GEO_STRIDE * p, xh, bh);
@@ -622,9 +644,9 @@ void launch_fill(hipStream_t s, double *p, size_t n, double v, const int *gate) 
 }
 
 void launch_mu(hipStream_t s, Ctx &c, const double *geo) {
-    k_mu<<<1, 256, 0, s>>>(c.st.n_pairs, c.F, c.N, c.hdd_blocks, c.cfg.damping_rel, c.d_pair_chunk_ptr, c.d_partH,
-                           c.d_pairH, geo, c.d_hdd_part, c.d_mu, c.d_gate);
-    if (c.N) k_damp_hdd<<<nb(c.N, 256), 256, 0, s>>>(c.N, c.d_Hdd, c.d_mu, c.d_gate);
+    k_mu<<<c.nwin, 1024, 0, s>>>(c.win(), c.cfg.damping_rel, c.d_pair_chunk_ptr, c.d_partH, c.d_pairH, geo, c.d_Hdd,
+                                 c.d_mu, c.d_gate);
+    if (c.N) k_damp_hdd<<<nb(c.N, 256), 256, 0, s>>>(c.N, c.d_Hdd, c.d_mu, c.d_point_win, c.d_gate);
 }
 
 void launch_gram(hipStream_t s, Ctx &c, const double *geo, const void *rec, bool rec_double) {
@@ -642,35 +664,35 @@ void launch_gram(hipStream_t s, Ctx &c, const double *geo, const void *rec, bool
 }
 
 void launch_assemble_s(hipStream_t s, Ctx &c, const double *geo) {
-    const size_t n6 = 6 * (size_t)c.F;
-    launch_fill(s, c.d_S, n6 * n6, 0.0, c.d_gate);
+    launch_fill(s, c.d_S, (size_t)c.win_S_off[c.nwin], 0.0, c.d_gate);
     const int nbk = (int)c.st.blk_fa.size();
-    k_assemble_s<<<nbk, 64, 0, s>>>((int)n6, c.cfg.pinned_frame, c.d_blk_fa, c.d_blk_fb, c.d_blk_pp_ptr,
+    k_assemble_s<<<nbk, 64, 0, s>>>(c.win(), c.cfg.pinned_frame, c.d_blk_fa, c.d_blk_fb, c.d_blk_pp_ptr,
                                     c.d_blk_pp_item, c.d_blk_g_ptr, c.d_blk_g_item, c.d_host_m, c.d_host_chunk_ptr,
                                     c.d_chunk_off, c.d_pairH, geo, c.d_gram, c.d_mu, c.d_S, c.d_gate);
 }
 
 void launch_ic_factor(hipStream_t s, Ctx &c) {
-    if (6 * c.F > LDS_MAX_N) {
+    if (c.nwin == 1 && 6 * c.F > LDS_MAX_N) {
         launch_tchol(s, c);
         return;
     }
-    k_ic_factor<<<1, SOLVE_THREADS, 0, s>>>(6 * c.F, c.d_S, c.d_Lfac, c.d_flag, c.d_gate);
+    k_ic_factor<<<c.nwin, SOLVE_THREADS, 0, s>>>(c.win(), c.d_S, c.d_Lfac, c.d_flag, c.d_gate);
 }
 
 void launch_solve(hipStream_t s, Ctx &c, const double *geo_lin, double *geo_next, void *rel_next, bool rel_double,
                   double *stat) {
+    (void)stat;
     const int ic = c.cfg.mode == PBA_IC_PROXY ? 1 : 0;
     if (rel_double)
-        k_solve<double><<<1, SOLVE_THREADS, 0, s>>>(
-            ic, c.F, c.st.n_pairs, c.cfg.pinned_frame, c.d_frame_pair_ptr, c.d_frame_pair_item, c.d_pair_host,
-            c.d_pair_target, c.d_pair_chunk_ptr, c.d_partY, c.d_pairY, geo_lin, c.d_S, c.d_Sfac, c.d_Linv, c.d_Sinv,
-            c.d_poses, c.d_poses0, c.d_b, c.d_dtheta, c.d_dth_rel, geo_next, (double *)rel_next, stat, c.d_flag, c.d_gate);
+        k_solve<double><<<c.nwin, SOLVE_THREADS, 0, s>>>(
+            c.win(), ic, c.cfg.pinned_frame, c.d_frame_pair_ptr, c.d_frame_pair_item, c.d_pair_host, c.d_pair_target,
+            c.d_pair_chunk_ptr, c.d_partY, c.d_pairY, geo_lin, c.d_S, c.d_Sfac, c.d_Linv, c.d_Sinv, c.d_poses,
+            c.d_poses0, c.d_b, c.d_dtheta, c.d_dth_rel, geo_next, (double *)rel_next, c.d_wstat, c.d_flag, c.d_gate);
     else
-        k_solve<float><<<1, SOLVE_THREADS, 0, s>>>(
-            ic, c.F, c.st.n_pairs, c.cfg.pinned_frame, c.d_frame_pair_ptr, c.d_frame_pair_item, c.d_pair_host,
-            c.d_pair_target, c.d_pair_chunk_ptr, c.d_partY, c.d_pairY, geo_lin, c.d_S, c.d_Sfac, c.d_Linv, c.d_Sinv,
-            c.d_poses, c.d_poses0, c.d_b, c.d_dtheta, c.d_dth_rel, geo_next, (float *)rel_next, stat, c.d_flag, c.d_gate);
+        k_solve<float><<<c.nwin, SOLVE_THREADS, 0, s>>>(
+            c.win(), ic, c.cfg.pinned_frame, c.d_frame_pair_ptr, c.d_frame_pair_item, c.d_pair_host, c.d_pair_target,
+            c.d_pair_chunk_ptr, c.d_partY, c.d_pairY, geo_lin, c.d_S, c.d_Sfac, c.d_Linv, c.d_Sinv, c.d_poses,
+            c.d_poses0, c.d_b, c.d_dtheta, c.d_dth_rel, geo_next, (float *)rel_next, c.d_wstat, c.d_flag, c.d_gate);
 }
 
 }  // namespace pba

@@ -17,9 +17,10 @@ PBA_FC, PBA_IC_PROXY = 0, 1
 PBA_FP64, PBA_FP32, PBA_MIXED_BF16 = 0, 1, 2
 PBA_SOLVER_CHOL = 0
 PBA_HOST, PBA_DEVICE = 0, 1
-PBA_FLAG_TIMING = 1
+PBA_FLAG_TIMING, PBA_FLAG_GRAPH = 1, 2
 PBA_MAX_PATTERN = 8
 PBA_MAX_LEVELS = 4
+PBA_MAX_WINDOWS = 4096
 PBA_DBG_S, PBA_DBG_B, PBA_DBG_OBS_REC, PBA_DBG_TEMPLATE, PBA_DBG_HDD, PBA_DBG_MASK, PBA_DBG_DTHETA = 1, 2, 3, 4, 5, 6, 7
 PBA_DBG_PAIR_H, PBA_DBG_PAIRS = 8, 9
 REC_STRIDE = 40
@@ -140,6 +141,9 @@ class Solver:
         check(pba_create(C.byref(self.cfg), C.byref(h)))
         self.ctx = h
         self.real = np.float64 if self.cfg.precision == PBA_FP64 else np.float32
+        nw = self.cfg.n_windows
+        self.Fw, self.Nw, self.Ow = [0] * nw, [0] * nw, [0] * nw
+        self._win = [dict() for _ in range(nw)]
 
     def close(self):
         if self.ctx:
@@ -155,28 +159,42 @@ class Solver:
     def _chk(self, s):
         return check(s, self.ctx)
 
-    def set_frames(self, images, intrinsics, poses):
+    @property
+    def F(self):
+        return sum(self.Fw)
+
+    @property
+    def N(self):
+        return sum(self.Nw)
+
+    @property
+    def O(self):
+        return sum(self.Ow)
+
+    def set_frames(self, images, intrinsics, poses, window=0):
         images = np.ascontiguousarray(images, np.float32)
-        self.F, self.H, self.W = images.shape
-        self._chk(pba_set_frames(self.ctx, 0, self.F, self.W, self.H, _ptr(images),
+        F, H, W = images.shape
+        self._chk(pba_set_frames(self.ctx, window, F, W, H, _ptr(images),
                                  _ptr(np.ascontiguousarray(intrinsics, np.float64)),
                                  _ptr(np.ascontiguousarray(poses, np.float64)), PBA_HOST))
+        self.H, self.W = H, W
+        self.Fw[window] = F
+        self.Nw[window] = self.Ow[window] = 0
 
-    def set_points(self, host_frame, host_uv, inv_depth, obs_ptr, obs_frame):
+    def set_points(self, host_frame, host_uv, inv_depth, obs_ptr, obs_frame, window=0):
         hf = np.ascontiguousarray(host_frame, np.int32)
-        self.N = hf.shape[0]
         optr = np.ascontiguousarray(obs_ptr, np.int32)
-        self.O = int(optr[-1])
-        self._host_frame, self._obs_ptr = hf, optr
-        self._obs_frame = np.ascontiguousarray(obs_frame, np.int32)
-        self._chk(pba_set_points(self.ctx, 0, self.N, _ptr(hf), _ptr(np.ascontiguousarray(host_uv, np.float32)),
-                                 _ptr(np.ascontiguousarray(inv_depth, np.float64)), _ptr(optr),
-                                 _ptr(np.ascontiguousarray(obs_frame, np.int32)), PBA_HOST))
+        ofr = np.ascontiguousarray(obs_frame, np.int32)
+        self._chk(pba_set_points(self.ctx, window, hf.shape[0], _ptr(hf),
+                                 _ptr(np.ascontiguousarray(host_uv, np.float32)),
+                                 _ptr(np.ascontiguousarray(inv_depth, np.float64)), _ptr(optr), _ptr(ofr), PBA_HOST))
+        self.Nw[window], self.Ow[window] = hf.shape[0], int(optr[-1])
+        self._win[window] = dict(host_frame=hf, obs_ptr=optr, obs_frame=ofr)
 
-    def set_scene(self, scene, poses=None, inv_depth=None):
-        self.set_frames(scene.images, scene.intrinsics, scene.poses_init if poses is None else poses)
+    def set_scene(self, scene, poses=None, inv_depth=None, window=0):
+        self.set_frames(scene.images, scene.intrinsics, scene.poses_init if poses is None else poses, window)
         self.set_points(scene.host_frame, scene.host_uv, scene.inv_depth_init if inv_depth is None else inv_depth,
-                        scene.obs_ptr, scene.obs_frame)
+                        scene.obs_ptr, scene.obs_frame, window)
 
     def iterate(self, level, n_iters):
         st = (pba_iter_stats * max(1, n_iters))()
@@ -195,20 +213,21 @@ class Solver:
         self._chk(pba_evaluate(self.ctx, level, C.byref(st)))
         return st.as_dict()
 
-    def get_params(self):
-        poses = np.zeros((self.F, 12))
-        d = np.zeros(self.N)
-        self._chk(pba_get_params(self.ctx, 0, _ptr(poses), _ptr(d)))
+    def get_params(self, window=0):
+        poses = np.zeros((self.Fw[window], 12))
+        d = np.zeros(self.Nw[window])
+        self._chk(pba_get_params(self.ctx, window, _ptr(poses), _ptr(d)))
         return poses, d
 
-    def set_params(self, poses, inv_depth):
-        self._chk(pba_set_params(self.ctx, 0, _ptr(np.ascontiguousarray(poses, np.float64)),
+    def set_params(self, poses, inv_depth, window=0):
+        self._chk(pba_set_params(self.ctx, window, _ptr(np.ascontiguousarray(poses, np.float64)),
                                  _ptr(np.ascontiguousarray(inv_depth, np.float64))))
 
     def fetch(self, what):
         n6 = 6 * self.F
+        s_shape = (n6, n6) if len(self.Fw) == 1 else (sum(36 * f * f for f in self.Fw),)
         shapes = {
-            PBA_DBG_S: ((n6, n6), np.float64), PBA_DBG_B: ((n6,), np.float64),
+            PBA_DBG_S: (s_shape, np.float64), PBA_DBG_B: ((n6,), np.float64),
             PBA_DBG_OBS_REC: ((self.O, REC_STRIDE), self.real),
             PBA_DBG_TEMPLATE: ((self.N, self.cfg.pattern_n, 4), self.real),
             PBA_DBG_HDD: ((self.N,), np.float64), PBA_DBG_MASK: ((self.O,), np.uint8),
@@ -222,9 +241,13 @@ class Solver:
         return out
 
     def n_pairs(self):
-        counts = np.diff(self._obs_ptr)
-        host = np.repeat(self._host_frame.astype(np.int64), counts)
-        return int(np.unique(host * (1 << 31) + self._obs_frame).size)
+        total = 0
+        for w in self._win:
+            if not w:
+                continue
+            host = np.repeat(w["host_frame"].astype(np.int64), np.diff(w["obs_ptr"]))
+            total += int(np.unique(host * (1 << 31) + w["obs_frame"]).size)
+        return total
 
     def timing(self):
         t = pba_timing()

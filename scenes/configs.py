@@ -308,10 +308,12 @@ def learned(seed=5, n_per_host=30000, width=640, height=480, n_frames=300):
     return _build("learned", objs, poses, width, height, hosts, n_per_host, targets, 3, 2.0 / 255.0, seed)
 
 
-def window(seed, n_kf=None, pts_per_host=None, width=1280, height=720):
+def window(seed, n_kf=None, pts_per_host=None, width=1280, height=720, n_levels=1):
     """One sliding window of the batched workload: a seeded arc of 5-9
     keyframes over textured planes and spheres; every keyframe hosts
-    1000-3000 points; targets are the other keyframes where visible."""
+    1000-3000 points; targets are the other keyframes where visible; one
+    pyramid level by default (the windows run a fixed number of iterations from
+    the small perturbation of the paper's protocol)."""
     rng = np.random.default_rng(10_000 + seed)
     n_kf = int(rng.integers(5, 10)) if n_kf is None else n_kf
     pts = int(rng.integers(1000, 3001)) if pts_per_host is None else pts_per_host
@@ -326,7 +328,7 @@ def window(seed, n_kf=None, pts_per_host=None, width=1280, height=720):
     def targets(h, n):
         return [f for f in range(n_kf) if f != h]
 
-    return _build(f"window{seed}", objs, poses, width, height, list(range(n_kf)), pts, targets, 3,
+    return _build(f"window{seed}", objs, poses, width, height, list(range(n_kf)), pts, targets, n_levels,
                   2.0 / 255.0, seed)
 
 

@@ -72,7 +72,7 @@ def test_config_default_values():
     ("n_levels", 5, "n_levels"), ("pattern_n", 0, "pattern_n"), ("pattern_n", 9, "pattern_n"),
     ("huber_k", 0.0, "huber_k"), ("huber_k", float("nan"), "huber_k"), ("damping_rel", -1.0, "damping_rel"),
     ("damping_rel", float("inf"), "damping_rel"), ("pinned_frame", -2, "pinned_frame"), ("solver", 3, "solver"),
-    ("n_windows", 2, "n_windows"), ("flags", 8, "flag"),
+    ("n_windows", 0, "n_windows"), ("n_windows", 5000, "n_windows"), ("flags", 8, "flag"),
 ])
 def test_create_rejects_invalid_config(field, value, msg):
     cfg = pba.default_config()

@@ -1,0 +1,128 @@
+"""GPU parity of the batched form: independent windows held by one context
+(n_windows > 1) run through the same kernels in one launch per step, with a
+block-diagonal reduced system (one gauge pin and one damping per window), and
+the whole solve captured as one HIP graph (PBA_FLAG_GRAPH).
+
+Every window of the batch must equal the same window solved alone by the
+library (FP64: to rounding) and by the FP64 oracle; the captured graph must
+reproduce the uncaptured launches, replay after replay."""
+import numpy as np
+import pytest
+
+import scenes
+from oracle.gn import GaussNewton, Problem
+from tests.oracle_refs import depth_errors_ok, rot_err, trans_rel_err
+
+pytestmark = pytest.mark.gpu
+
+pba = pytest.importorskip("paper_1704_06967_amd.pba")
+
+
+@pytest.fixture(scope="module")
+def wins():
+    # uneven windows: 5, 7 and 6 keyframes, 150-250 points per keyframe, 640x360
+    return [scenes.window(s, n_kf=k, pts_per_host=p, width=640, height=360)
+            for s, k, p in ((1, 5, 150), (2, 7, 250), (3, 6, 200))]
+
+
+def make(n_windows, mode, precision, flags=0, **kw):
+    return pba.Solver(mode=pba.PBA_IC_PROXY if mode == "ic" else pba.PBA_FC, precision=precision,
+                      n_levels=1, n_windows=n_windows, flags=flags, **kw)
+
+
+def load(s, wins):
+    for w, sc in enumerate(wins):
+        s.set_scene(sc, window=w)
+
+
+@pytest.mark.parametrize("mode", ["ic", "fc"])
+def test_batched_equals_single_fp64(wins, mode):
+    b = make(len(wins), mode, pba.PBA_FP64)
+    load(b, wins)
+    st = b.iterate(0, 5)
+    assert len(st) == 5
+    for w, sc in enumerate(wins):
+        s = make(1, mode, pba.PBA_FP64)
+        s.set_scene(sc)
+        s.iterate(0, 5)
+        p1, d1 = s.get_params()
+        pb, db = b.get_params(w)
+        assert rot_err(pb, p1).max() <= 1e-12
+        assert trans_rel_err(pb, p1).max() <= 1e-12
+        np.testing.assert_allclose(db, d1, rtol=1e-12)
+        gn = GaussNewton(Problem.from_scene(sc), mode)
+        gn.iterate(0, 5)
+        assert rot_err(pb, gn.poses).max() <= 1e-8
+        assert trans_rel_err(pb, gn.poses).max() <= 1e-8
+        assert np.abs(db / gn.d - 1).max() <= 1e-8
+    # statistics are sums over the windows
+    tot = sum(GaussNewton(Problem.from_scene(sc), mode).iterate(0, 1)[0]["n_active"] for sc in wins)
+    assert st[0]["n_active"] == tot
+
+
+@pytest.mark.parametrize("mode", ["ic", "fc"])
+def test_batched_fp32_vs_oracle(wins, mode):
+    b = make(len(wins), mode, pba.PBA_FP32)
+    load(b, wins)
+    b.iterate(0, 5)
+    for w, sc in enumerate(wins):
+        gn = GaussNewton(Problem.from_scene(sc), mode)
+        gn.iterate(0, 5)
+        pb, db = b.get_params(w)
+        assert rot_err(pb, gn.poses).max() <= 1e-5
+        assert trans_rel_err(pb, gn.poses).max() <= 1e-5
+        ok, q99, worst = depth_errors_ok(db, gn.d)
+        assert ok, (w, q99, worst)
+
+
+@pytest.mark.parametrize("precision", [pba.PBA_FP64, pba.PBA_FP32])
+def test_graph_replays_match_launches(wins, precision):
+    """The solve captured once and replayed three times (with eager calls in
+    between) gives the uncaptured solve's result every time."""
+    ref = make(len(wins), "ic", precision)
+    load(ref, wins)
+    r_ref, _ = ref.solve(5, 0.0)
+    p_ref = [ref.get_params(w) for w in range(len(wins))]
+    g = make(len(wins), "ic", precision, flags=pba.PBA_FLAG_GRAPH)
+    load(g, wins)
+    for rep in range(3):
+        for w, sc in enumerate(wins):
+            g.set_params(sc.poses_init, sc.inv_depth_init, window=w)
+        r, _ = g.solve(5, 0.0)
+        assert list(r.iters) == list(r_ref.iters)
+        assert r.final_rmse == r_ref.final_rmse
+        for w in range(len(wins)):
+            pg, dg = g.get_params(w)
+            np.testing.assert_array_equal(pg, p_ref[w][0])
+            np.testing.assert_array_equal(dg, p_ref[w][1])
+        g.evaluate(0)  # eager work between replays
+
+
+def test_graph_single_problem_pyramid():
+    """One problem, 3 levels with the convergence gate: the captured solve equals
+    the launched one (iteration counts and parameters)."""
+    sc = scenes.mid(n_per_host=300)
+    kw = dict(mode=pba.PBA_IC_PROXY, precision=pba.PBA_FP32, n_levels=3, pattern=sc.pattern, huber_k=sc.huber_k)
+    a = pba.Solver(**kw)
+    a.set_scene(sc)
+    ra, _ = a.solve(10, 5e-3)
+    g = pba.Solver(flags=pba.PBA_FLAG_GRAPH, **kw)
+    g.set_scene(sc)
+    for _ in range(2):
+        g.set_params(sc.poses_init, sc.inv_depth_init)
+        rg, _ = g.solve(10, 5e-3)
+        assert list(rg.iters) == list(ra.iters)
+        np.testing.assert_array_equal(g.get_params()[0], a.get_params()[0])
+        np.testing.assert_array_equal(g.get_params()[1], a.get_params()[1])
+
+
+def test_batched_invalid_usage(wins):
+    b = make(2, "ic", pba.PBA_FP32)
+    b.set_scene(wins[0], window=0)
+    with pytest.raises(pba.PbaError) as e:
+        b.iterate(0, 1)  # window 1 not set
+    assert e.value.status == pba.PBA_E_STATE
+    with pytest.raises(pba.PbaError):
+        b.set_frames(wins[1].images[:, :100, :100], wins[1].intrinsics, wins[1].poses_init, window=1)
+    with pytest.raises(pba.PbaError):
+        b.set_scene(wins[1], window=2)
