@@ -155,6 +155,138 @@ def cpu_baseline(scene, n_iters=10):
             "seconds": dt}
 
 
+def param_errors(poses, d, ref_poses, ref_d):
+    """Per-result error of (poses, inverse depths) against a reference."""
+    R = poses[:, :9].reshape(-1, 3, 3)
+    Rr = ref_poses[:, :9].reshape(-1, 3, 3)
+    rot = 2.0 * np.arcsin(np.clip(np.linalg.norm((R - Rr).reshape(len(R), -1), axis=1) / (2.0 * np.sqrt(2.0)), 0, 1))
+    tn = np.linalg.norm(ref_poses[:, 9:], axis=1).max()
+    tr = np.linalg.norm(poses[:, 9:] - ref_poses[:, 9:], axis=1) / max(tn, 1e-12)
+    rel = np.abs(d / ref_d - 1.0)
+    return {"rot_max_rad": float(rot.max()), "trans_rel_max": float(tr.max()),
+            "inv_depth_rel_p50": float(np.median(rel)), "inv_depth_rel_p99": float(np.quantile(rel, 0.99)),
+            "inv_depth_rel_max": float(rel.max())}
+
+
+def precision_section(pba, steps, max_iters, conv_px):
+    """The precision workload (120 frames 640x480 around a value-noise torus,
+    10 hosts x 20000 points, 6.4M residuals per level-0 iteration, 6F = 720):
+    IC in the mixed form (BF16 MFMA pose blocks) timed per solve, and its result
+    against the FP64 path's (which matches the FP64 oracle to rounding in the
+    parity tests); FC in the mixed form for comparison."""
+    import scenes
+
+    t0 = time.perf_counter()
+    sc = scenes.precision()
+    log(f"scene precision: {sc.n_points} points, {sc.n_obs} observations ({time.perf_counter() - t0:.1f} s)")
+    kw = dict(n_levels=sc.n_levels, pattern=sc.pattern, huber_k=sc.huber_k, flags=pba.PBA_FLAG_TIMING)
+    out = {"workload": "precision: 120 frames 640x480 f32, value-noise torus, 3-level pyramid, 10 hosts x 20000 "
+                       "points (4 targets each), 8-px patches; 6F = 720",
+           "points": sc.n_points, "observations": sc.n_obs, "residuals_per_iter": sc.n_residuals(),
+           "reduced_system": 6 * sc.n_frames}
+    p0, d0 = sc.poses_init, sc.inv_depth_init
+    results = {}
+    for name, mode, prec, n in (("ic_mixed", pba.PBA_IC_PROXY, pba.PBA_MIXED_BF16, steps),
+                                ("ic_fp64", pba.PBA_IC_PROXY, pba.PBA_FP64, 1),
+                                ("fc_mixed", pba.PBA_FC, pba.PBA_MIXED_BF16, max(1, steps // 2))):
+        s = pba.Solver(mode=mode, precision=prec, **kw)
+        s.set_scene(sc)
+        s.set_params(p0, d0)
+        s.solve(max_iters, conv_px)  # warm-up
+        s.timing()
+        t, iters, active, res = run_steps(s, p0, d0, n, max_iters, conv_px)
+        tm = s.timing()
+        poses, d = s.get_params()
+        results[name] = (poses, d)
+        out[name] = {"ms_per_solve": round(float(np.mean(t)) * 1e3, 3), "iters_per_solve": res[-1]["iters"],
+                     "gn_iters_per_s": round(iters / float(np.sum(t)), 2),
+                     "residuals_per_s": round(active / float(np.sum(t)), 1), "final_rmse": res[-1]["final_rmse"],
+                     "residual_kernel_avg_us_level0": round(tm["residual_ms"][0] / max(1, tm["residual_launches"][0])
+                                                            * 1e3, 3)}
+        s.close()
+        log(f"precision {name}: {out[name]['ms_per_solve']} ms per solve")
+    out["ic_mixed_vs_fp64"] = param_errors(*results["ic_mixed"], *results["ic_fp64"])
+    out["ic_mixed_rmse_rel_vs_fp64"] = abs(out["ic_mixed"]["final_rmse"] / out["ic_fp64"]["final_rmse"] - 1)
+    out["note"] = ("errors of the mixed-form IC solve against the FP64 IC solve of the same problem (same "
+                   "iteration counts); the FP64 path equals the FP64 oracle to rounding in the parity tests")
+    return out
+
+
+def make_windows(n, workers):
+    """The batched workload's windows (seeds 0..n-1), built in worker processes
+    before this process touches the GPU."""
+    import concurrent.futures as cf
+    import multiprocessing as mp
+
+    import scenes
+
+    if workers <= 1:
+        return [scenes.window(i) for i in range(n)]
+    with cf.ProcessPoolExecutor(max_workers=workers, mp_context=mp.get_context("fork")) as ex:
+        return list(ex.map(scenes.window, range(n)))
+
+
+def batched_section(pba, wins, steps, iters):
+    """The batched workload: len(wins) independent windows (5-9 keyframes,
+    1000-3000 points per keyframe, 1280x720) in one context, IC in the mixed
+    form, `iters` Gauss-Newton iterations each; the whole solve is one HIP graph
+    launch, the residual kernel's launch shape autotuned on the batch. Window
+    latency is the time from a batch's launch to its completion (every window of
+    a batch completes with it)."""
+    nw = len(wins)
+    out = {"workload": f"batched: {nw} windows, 5-9 keyframes 1280x720 f32 (textured planes + spheres), 1000-3000 "
+                       f"points per keyframe, 8-px patches, {iters} IC iterations each, one graph launch",
+           "windows": nw, "keyframes": [w.n_frames for w in wins], "points": int(sum(w.n_points for w in wins)),
+           "observations": int(sum(w.n_obs for w in wins)),
+           "residuals_per_iter": int(sum(w.n_residuals() for w in wins))}
+    kw = dict(mode=pba.PBA_IC_PROXY, precision=pba.PBA_MIXED_BF16, n_levels=1)
+    b = pba.Solver(n_windows=nw, flags=pba.PBA_FLAG_GRAPH, **kw)
+    for i, w in enumerate(wins):
+        b.set_scene(w, window=i)
+    t0 = time.perf_counter()
+    out["autotune"] = b.autotune(0, 20)
+    out["autotune_s"] = round(time.perf_counter() - t0, 3)
+
+    def reset():
+        for i, w in enumerate(wins):
+            b.set_params(w.poses_init, w.inv_depth_init, window=i)
+
+    reset()
+    b.solve(iters, 0.0)  # capture + first replay
+    lat = []
+    for _ in range(steps):
+        reset()
+        t1 = time.perf_counter()
+        res, _ = b.solve(iters, 0.0)
+        lat.append(time.perf_counter() - t1)
+    lat = np.array(lat)
+    out.update({"ms_per_batch": round(float(lat.mean()) * 1e3, 3), "windows_per_s": round(nw / float(lat.mean()), 1),
+                "window_latency_ms_p50": round(float(np.percentile(lat, 50)) * 1e3, 3),
+                "window_latency_ms_p99": round(float(np.percentile(lat, 99)) * 1e3, 3),
+                "gn_iters_per_s": round(nw * iters / float(lat.mean()), 1),
+                "residuals_per_s": round(res.active_residuals / float(lat.mean()), 1)})
+    pb = [b.get_params(i) for i in range(nw)]
+    b.close()
+    # the same windows one context at a time (each its own graph), for the batching gain
+    one = []
+    err = 0.0
+    for i, w in enumerate(wins[: min(nw, 16)]):
+        s = pba.Solver(flags=pba.PBA_FLAG_GRAPH, **kw)
+        s.set_scene(w)
+        s.solve(iters, 0.0)
+        s.set_params(w.poses_init, w.inv_depth_init)
+        t1 = time.perf_counter()
+        s.solve(iters, 0.0)
+        one.append(time.perf_counter() - t1)
+        p1, d1 = s.get_params()
+        err = max(err, float(np.abs(p1 - pb[i][0]).max()), float(np.abs(d1 / pb[i][1] - 1).max()))
+        s.close()
+    out["one_window_per_context"] = {"windows": len(one), "ms_per_window": round(float(np.mean(one)) * 1e3, 3),
+                                     "windows_per_s": round(1.0 / float(np.mean(one)), 1)}
+    out["batched_vs_single_max_abs_diff"] = err
+    return out
+
+
 def calibrate_copy(nbytes):
     """A device-to-device copy of nbytes (the runtime's copy kernel), so that the
     HBM counters of a profiling run can be scaled by a transfer of known size."""
@@ -183,6 +315,11 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-trace", action="store_true")
     ap.add_argument("--fc-steps", type=int, default=None, help="FC solves to time (default: --steps)")
+    ap.add_argument("--no-precision", action="store_true", help="skip the precision-workload section")
+    ap.add_argument("--no-batched", action="store_true", help="skip the batched-windows section")
+    ap.add_argument("--windows", type=int, default=64, help="windows of the batched section")
+    ap.add_argument("--workers", type=int, default=min(16, os.cpu_count() or 1),
+                    help="processes that build the batched windows")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
                     help="also run device copies of BYTES (scale for profiler byte counters)")
     args = ap.parse_args()
@@ -192,6 +329,12 @@ def main():
         sys.exit(2)
 
     import scenes
+
+    wins = None
+    if not args.no_batched:
+        t0 = time.perf_counter()
+        wins = make_windows(args.windows, args.workers)
+        log(f"{len(wins)} windows built ({time.perf_counter() - t0:.1f} s)")
     from paper_1704_06967_amd import pba
 
     if args.calibrate_copy:
@@ -284,6 +427,11 @@ def main():
         line["equal_rmse"] = {"r_star": r_star, "ic_ms": round(t_ic * 1e3, 3), "fc_ms": round(t_fc * 1e3, 3),
                               "ic_speedup": round(t_fc / t_ic, 3) if t_ic > 0 and math.isfinite(t_fc) else None,
                               "note": "per-iteration synchronous calls; level-0 RMSE after each iteration"}
+    if not args.no_precision:
+        line["precision_form"] = precision_section(pba, max(1, min(args.steps, 5)), args.max_iters, args.conv_px)
+    if wins is not None:
+        line["batched_form"] = batched_section(pba, wins, max(3, min(args.steps, 20)), 5)
+        log(f"batched: {line['batched_form']['ms_per_batch']} ms per batch of {len(wins)} windows")
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
         line["cpu_baseline"] = cpu_baseline(scene)

@@ -197,6 +197,27 @@ pba_status pba_get_params(pba_ctx *ctx, int32_t window, double *poses, double *i
 /* Overwrite the current parameters (host memory); the next iterate restarts the level. */
 pba_status pba_set_params(pba_ctx *ctx, int32_t window, const double *poses, const double *inv_depth);
 
+/* Result of pba_autotune: the launch shapes tried for the per-iteration
+ * residual kernel (IC: the residual / J^T W r kernel; FC: the linearization
+ * kernel) and their measured mean launch time. */
+#define PBA_TUNE_MAX 16
+typedef struct {
+    int32_t n_candidates;
+    int32_t block[PBA_TUNE_MAX];     /* threads per workgroup (tiles of block / 8 observations) */
+    int32_t grid_mult[PBA_TUNE_MAX]; /* 0: one tile per workgroup; m > 0: persistent grid of m
+                                        workgroups per compute unit striding over the tiles */
+    double us[PBA_TUNE_MAX];         /* mean time per launch (microseconds, HIP events) */
+    int32_t chosen;                  /* index of the fastest, now used by the context */
+} pba_tune_report;
+
+/* Project autotuner: (re)starts `level` at the current parameters, times every
+ * candidate launch shape of the per-iteration residual kernel over `reps`
+ * launches on the context's own data, and keeps the fastest for all later
+ * iterations (a captured solve graph is rebuilt). The timed launches only
+ * rewrite per-observation sums that the next iteration recomputes. `out` may
+ * be NULL. PBA_MIXED_BF16 in FC mode has a fixed shape (n_candidates = 0). */
+pba_status pba_autotune(pba_ctx *ctx, int32_t level, int32_t reps, pba_tune_report *out);
+
 /* Copy an internal buffer (PBA_DBG_*) to host memory; bytes must match its size exactly. */
 pba_status pba_debug_fetch(pba_ctx *ctx, int32_t what, void *out, size_t bytes);
 

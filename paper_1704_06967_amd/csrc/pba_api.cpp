@@ -862,6 +862,11 @@ pba_status pba_create(const pba_config *cfg, pba_ctx **out) {
     c.device = dev;
     c.P = cfg->pattern_n;
     c.real_size = cfg->precision == PBA_FP64 ? sizeof(double) : sizeof(float);
+    {
+        int ncu = 0;
+        if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && ncu > 0)
+            c.n_cu = ncu;
+    }
     if (cfg->n_windows > 1) ctx->stage.resize(cfg->n_windows);
     if (cfg->stream) {
         c.stream = (hipStream_t)cfg->stream;
@@ -1162,6 +1167,69 @@ pba_status pba_debug_fetch(pba_ctx *ctx, int32_t what, void *out, size_t bytes) 
     if (bytes != need) return fail(&c, PBA_E_INVALID, "bytes must be " + std::to_string(need));
     if (need) HIPCHK(hipMemcpyAsync(out, src, need, hipMemcpyDeviceToHost, c.stream));
     HIPCHK(hipStreamSynchronize(c.stream));
+    return PBA_OK;
+}
+
+pba_status pba_autotune(pba_ctx *ctx, int32_t level, int32_t reps, pba_tune_report *out) {
+    if (!ctx) return fail(nullptr, PBA_E_INVALID, "ctx is NULL");
+    Ctx &c = ctx->c;
+    if (level < 0 || level >= c.cfg.n_levels) return fail(&c, PBA_E_INVALID, "level out of range");
+    if (reps < 1 || reps > 10000) return fail(&c, PBA_E_INVALID, "reps must be in 1..10000");
+    pba_status st;
+    if ((st = ready(ctx)) != PBA_OK) return st;
+    if ((st = do_start_level(c, level)) != PBA_OK) return st;
+    pba_tune_report rep;
+    std::memset(&rep, 0, sizeof(rep));
+    const bool ic = c.cfg.mode == PBA_IC_PROXY;
+    if (!ic && is_mixed(c)) {
+        if (out) *out = rep;
+        return PBA_OK;
+    }
+    std::vector<LaunchShape> cand = {{64, 0}, {128, 0}, {256, 0}, {512, 0}, {256, 2}, {256, 4}, {256, 8}, {512, 2},
+                                      {512, 4}};
+    if (ic) cand.push_back({1024, 0});
+    if ((st = ensure_events(c, 2)) != PBA_OK) return st;
+    hipEvent_t e0 = c.ev_pool[0], e1 = c.ev_pool[1];
+    const void *rel = c.flip ? c.d_rel_b : c.d_rel_a;
+    auto launch = [&](LaunchShape sh) {
+        if (ic) {
+            if (is_fp64(c))
+                Launch<double>::ic_residual_shape(c.stream, c, level, (const double *)rel, sh);
+            else
+                Launch<float>::ic_residual_shape(c.stream, c, level, (const float *)rel, sh);
+        } else {
+            if (is_fp64(c))
+                Launch<double>::fc_linearize_shape(c.stream, c, level, (const double *)rel, sh);
+            else
+                Launch<float>::fc_linearize_shape(c.stream, c, level, (const float *)rel, sh);
+        }
+    };
+    launch_open(c.stream, c, level, true);
+    int best = 0;
+    for (size_t k = 0; k < cand.size(); ++k) {
+        for (int w = 0; w < 2; ++w) launch(cand[k]);
+        HIPCHK(hipEventRecord(e0, c.stream));
+        for (int r = 0; r < reps; ++r) launch(cand[k]);
+        HIPCHK(hipEventRecord(e1, c.stream));
+        HIPCHK(hipEventSynchronize(e1));
+        HIPCHK(hipGetLastError());
+        float ms = 0.f;
+        HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+        rep.block[k] = cand[k].block;
+        rep.grid_mult[k] = cand[k].grid_mult;
+        rep.us[k] = 1e3 * ms / reps;
+        if (rep.us[k] < rep.us[best]) best = (int)k;
+    }
+    rep.n_candidates = (int)cand.size();
+    rep.chosen = best;
+    if (ic)
+        c.tune_res = cand[best];
+    else
+        c.tune_lin = cand[best];
+    drop_graph(c);
+    // the level restarts at the next iteration (the FC frozen set is rewritten by it)
+    c.cur_level = -1;
+    if (out) *out = rep;
     return PBA_OK;
 }
 

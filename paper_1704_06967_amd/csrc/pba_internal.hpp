@@ -54,6 +54,14 @@ struct WinArgs {
     const int *frame_win, *point_win;                             // [F], [N]
 };
 
+// Launch shape of a residual kernel: threads per workgroup (tiles of block / 8
+// observations) and, when grid_mult > 0, a persistent grid of grid_mult
+// workgroups per compute unit striding over the tiles.
+struct LaunchShape {
+    int block = 256;
+    int grid_mult = 0;
+};
+
 struct LevelDev {
     int W = 0, H = 0;
     void *img = nullptr;      // T [F][H][W]
@@ -160,6 +168,10 @@ struct Ctx {
     // current double-buffer orientation
     bool flip = false;
 
+    // launch shapes of the per-iteration residual kernels (autotuned)
+    int n_cu = 256;
+    LaunchShape tune_res, tune_lin;
+
     // a whole coarse-to-fine solve captured as one HIP graph (PBA_FLAG_GRAPH)
     hipGraphExec_t solve_graph = nullptr;
     int graph_iters = -1;
@@ -181,6 +193,8 @@ template <typename T> struct Launch {
     static void relpose(hipStream_t s, Ctx &c, const double *poses, double *geo, T *rel);
     static void ic_linearize(hipStream_t s, Ctx &c, int level);
     static void ic_residual(hipStream_t s, Ctx &c, int level, const T *rel_cur);
+    static void ic_residual_shape(hipStream_t s, Ctx &c, int level, const T *rel_cur, LaunchShape sh);
+    static void fc_linearize_shape(hipStream_t s, Ctx &c, int level, const T *rel_cur, LaunchShape sh);
     static void fc_linearize(hipStream_t s, Ctx &c, int level, const T *rel_cur, bool write_mask);
     static void evaluate(hipStream_t s, Ctx &c, int level);
     static void point_reduce(hipStream_t s, Ctx &c, bool with_hdd);

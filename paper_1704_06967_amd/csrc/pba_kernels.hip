@@ -9,6 +9,8 @@
 #include "pba_device.hpp"
 #include "pba_internal.hpp"
 
+#include <algorithm>
+
 namespace pba {
 
 #define CHECK_LAUNCH() (void)hipGetLastError()
@@ -171,34 +173,39 @@ __device__ __forceinline__ bool lin_eval(const ResArgs<T> &a, int o, int j, int 
 }
 
 // Linearization in observation order: the 38-value record of every
-// observation (lane j == 0 writes it).
-template <typename T, bool IC>
-__global__ __launch_bounds__(BLOCK) void k_linearize(ResArgs<T> a, int write_mask) {
+// observation (lane j == 0 writes it). NB threads per workgroup (NB / 8
+// observations per tile); the grid strides over the tiles, so that it can be
+// launched one tile per workgroup or as a persistent grid.
+template <typename T, bool IC, int NB>
+__global__ __launch_bounds__(NB) void k_linearize(ResArgs<T> a, int write_mask) {
     if (*a.gate == 0) return;
-    const int gid = blockIdx.x * BLOCK + threadIdx.x;
-    const int o = gid >> 3, j = gid & 7;
-    T J[7], r, w, rho;
-    const bool valid = lin_eval<T, IC>(a, o, j, write_mask, J, r, w, rho);
-    if (write_mask) {
-        const unsigned long long bal = __ballot(valid);
-        if (j == 0 && o < a.O) a.mask[o] = (uint8_t)((bal >> (threadIdx.x & 56)) & 0xFFull);
-    }
-    T v[38];
-    int k = 0;
-    for (int p = 0; p < 6; ++p)
-        for (int q = p; q < 6; ++q) v[k++] = w * J[p] * J[q];
-    for (int p = 0; p < 6; ++p) v[21 + p] = w * J[p] * J[6];
-    v[27] = w * J[6] * J[6];
-    for (int p = 0; p < 7; ++p) v[28 + p] = w * J[p] * r;
-    v[35] = valid ? rho : T(0);
-    v[36] = valid ? r * r : T(0);
-    v[37] = valid ? T(1) : T(0);
+    const int ntiles = (a.O + NB / 8 - 1) / (NB / 8);
+    for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        const int gid = tile * NB + threadIdx.x;
+        const int o = gid >> 3, j = gid & 7;
+        T J[7], r, w, rho;
+        const bool valid = lin_eval<T, IC>(a, o, j, write_mask, J, r, w, rho);
+        if (write_mask) {
+            const unsigned long long bal = __ballot(valid);
+            if (j == 0 && o < a.O) a.mask[o] = (uint8_t)((bal >> (threadIdx.x & 56)) & 0xFFull);
+        }
+        T v[38];
+        int k = 0;
+        for (int p = 0; p < 6; ++p)
+            for (int q = p; q < 6; ++q) v[k++] = w * J[p] * J[q];
+        for (int p = 0; p < 6; ++p) v[21 + p] = w * J[p] * J[6];
+        v[27] = w * J[6] * J[6];
+        for (int p = 0; p < 7; ++p) v[28 + p] = w * J[p] * r;
+        v[35] = valid ? rho : T(0);
+        v[36] = valid ? r * r : T(0);
+        v[37] = valid ? T(1) : T(0);
 #pragma unroll
-    for (int p = 0; p < 38; ++p) v[p] = wave_sum8(v[p]);
-    if (j == 0 && o < a.O) {
-        T *rec = a.rec + (size_t)o * REC_STRIDE;
+        for (int p = 0; p < 38; ++p) v[p] = wave_sum8(v[p]);
+        if (j == 0 && o < a.O) {
+            T *rec = a.rec + (size_t)o * REC_STRIDE;
 #pragma unroll
-        for (int p = 0; p < 38; ++p) rec[p] = v[p];
+            for (int p = 0; p < 38; ++p) rec[p] = v[p];
+        }
     }
 }
 
@@ -340,55 +347,59 @@ __global__ __launch_bounds__(BLOCK) void k_linearize_mixed(ResArgs<float> a, int
 }
 
 // IC iteration: residuals at the current parameters, Huber weights, and
-// g = J^T W r with the constant proxy Jacobian (Sec. 3.5 steps 1-2).
-template <typename T>
-__global__ __launch_bounds__(BLOCK) void k_ic_residual(ResArgs<T> a) {
+// g = J^T W r with the constant proxy Jacobian (Sec. 3.5 steps 1-2). NB threads
+// per workgroup, tiles of NB / 8 observations, grid-stride over the tiles.
+template <typename T, int NB>
+__global__ __launch_bounds__(NB) void k_ic_residual(ResArgs<T> a) {
     if (*a.gate == 0) return;
-    const int gid = blockIdx.x * BLOCK + threadIdx.x;
-    const int o = gid >> 3, j = gid & 7;
-    T c[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
-    if (o < a.O && j < a.P && ((a.mask[o] >> j) & 1)) {
-        const int n = a.obs_point[o], pr = a.obs_pair[o];
-        const int h = a.pair_host[pr], f = a.pair_target[pr];
-        const T *Kh = a.K + 4 * h;
-        const T *Kt = a.K + 4 * f;
-        T x, y;
-        template_xy(a, n, j, Kh, x, y);
-        const T *R = a.rel + REL_STRIDE * pr;
-        const T *t = R + 9;
-        const T d = (T)a.depth[n];
-        const T vz = R[6] * x + R[7] * y + R[8] + d * t[2];
-        if (d > T(0) && vz > T(0)) {
-            const T vx = R[0] * x + R[1] * y + R[2] + d * t[0];
-            const T vy = R[3] * x + R[4] * y + R[5] + d * t[1];
-            const T qu = Kt[0] * (vx / vz) + Kt[2], qv = Kt[1] * (vy / vz) + Kt[3];
-            if (usable(qu, qv, a.W, a.H)) {
-                const T *tp = a.tmpl + 4 * ((size_t)n * a.P + j);
-                const T If = bilinear(a.img + (size_t)f * a.W * a.H, a.W, qu, qv);
-                const T r = tp[0] - If;
-                T w, rho;
-                huber(r, a.huber_k, w, rho);
-                T J[7];
-                const T *R0 = a.rel0 + REL_STRIDE * pr;
-                ic_jacobian(x, y, R0, R0 + 9, (T)a.depth0[n], tp[1], tp[2], Kh[0], Kh[1], J);
-                const T wr = w * r;
+    const int ntiles = (a.O + NB / 8 - 1) / (NB / 8);
+    for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        const int gid = tile * NB + threadIdx.x;
+        const int o = gid >> 3, j = gid & 7;
+        T c[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+        if (o < a.O && j < a.P && ((a.mask[o] >> j) & 1)) {
+            const int n = a.obs_point[o], pr = a.obs_pair[o];
+            const int h = a.pair_host[pr], f = a.pair_target[pr];
+            const T *Kh = a.K + 4 * h;
+            const T *Kt = a.K + 4 * f;
+            T x, y;
+            template_xy(a, n, j, Kh, x, y);
+            const T *R = a.rel + REL_STRIDE * pr;
+            const T *t = R + 9;
+            const T d = (T)a.depth[n];
+            const T vz = R[6] * x + R[7] * y + R[8] + d * t[2];
+            if (d > T(0) && vz > T(0)) {
+                const T vx = R[0] * x + R[1] * y + R[2] + d * t[0];
+                const T vy = R[3] * x + R[4] * y + R[5] + d * t[1];
+                const T qu = Kt[0] * (vx / vz) + Kt[2], qv = Kt[1] * (vy / vz) + Kt[3];
+                if (usable(qu, qv, a.W, a.H)) {
+                    const T *tp = a.tmpl + 4 * ((size_t)n * a.P + j);
+                    const T If = bilinear(a.img + (size_t)f * a.W * a.H, a.W, qu, qv);
+                    const T r = tp[0] - If;
+                    T w, rho;
+                    huber(r, a.huber_k, w, rho);
+                    T J[7];
+                    const T *R0 = a.rel0 + REL_STRIDE * pr;
+                    ic_jacobian(x, y, R0, R0 + 9, (T)a.depth0[n], tp[1], tp[2], Kh[0], Kh[1], J);
+                    const T wr = w * r;
 #pragma unroll
-                for (int p = 0; p < 7; ++p) c[p] = wr * J[p];
-                c[7] = rho;
-                c[8] = r * r;
-                c[9] = T(1);
+                    for (int p = 0; p < 7; ++p) c[p] = wr * J[p];
+                    c[7] = rho;
+                    c[8] = r * r;
+                    c[9] = T(1);
+                }
             }
         }
-    }
 #pragma unroll
-    for (int p = 0; p < 10; ++p) c[p] = wave_sum8(c[p]);
-    if (j == 0 && o < a.O) {
-        T *rec = a.rec + (size_t)o * REC_STRIDE;
+        for (int p = 0; p < 10; ++p) c[p] = wave_sum8(c[p]);
+        if (j == 0 && o < a.O) {
+            T *rec = a.rec + (size_t)o * REC_STRIDE;
 #pragma unroll
-        for (int p = 0; p < 7; ++p) rec[REC_G + p] = c[p];
-        rec[REC_E] = c[7];
-        rec[REC_SQ] = c[8];
-        rec[REC_CNT] = c[9];
+            for (int p = 0; p < 7; ++p) rec[REC_G + p] = c[p];
+            rec[REC_E] = c[7];
+            rec[REC_SQ] = c[8];
+            rec[REC_CNT] = c[9];
+        }
     }
 }
 
@@ -713,11 +724,30 @@ void Launch<T>::relpose(hipStream_t s, Ctx &c, const double *poses, double *geo,
     CHECK_LAUNCH();
 }
 
+// Grid of a launch shape: one tile of nb / 8 observations per workgroup, or a
+// persistent grid of grid_mult workgroups per compute unit striding over them.
+static unsigned shape_grid(const Ctx &c, LaunchShape sh) {
+    const size_t tiles = ((size_t)c.O * LANES_PER_OBS + sh.block - 1) / sh.block;
+    if (sh.grid_mult <= 0) return (unsigned)tiles;
+    return (unsigned)std::min<size_t>(tiles, (size_t)sh.grid_mult * c.n_cu);
+}
+
+template <typename T, bool IC>
+static void launch_linearize_shape(hipStream_t s, const Ctx &c, const ResArgs<T> &a, int write_mask, LaunchShape sh) {
+    const unsigned g = shape_grid(c, sh);
+    switch (sh.block) {
+        case 64: k_linearize<T, IC, 64><<<g, 64, 0, s>>>(a, write_mask); break;
+        case 128: k_linearize<T, IC, 128><<<g, 128, 0, s>>>(a, write_mask); break;
+        case 512: k_linearize<T, IC, 512><<<g, 512, 0, s>>>(a, write_mask); break;
+        default: k_linearize<T, IC, 256><<<g, 256, 0, s>>>(a, write_mask); break;
+    }
+}
+
 template <typename T>
 void Launch<T>::ic_linearize(hipStream_t s, Ctx &c, int level) {
     if (c.O == 0) return;
     ResArgs<T> a = res_args<T>(c, level, (const T *)c.d_rel0);
-    k_linearize<T, true><<<nblk((size_t)c.O * LANES_PER_OBS, BLOCK), BLOCK, 0, s>>>(a, 1);
+    launch_linearize_shape<T, true>(s, c, a, 1, LaunchShape{});
     CHECK_LAUNCH();
 }
 
@@ -725,7 +755,7 @@ template <typename T>
 void Launch<T>::fc_linearize(hipStream_t s, Ctx &c, int level, const T *rel_cur, bool write_mask) {
     if (c.O == 0) return;
     ResArgs<T> a = res_args<T>(c, level, rel_cur);
-    k_linearize<T, false><<<nblk((size_t)c.O * LANES_PER_OBS, BLOCK), BLOCK, 0, s>>>(a, write_mask ? 1 : 0);
+    launch_linearize_shape<T, false>(s, c, a, write_mask ? 1 : 0, c.tune_lin);
     CHECK_LAUNCH();
 }
 
@@ -744,9 +774,29 @@ void launch_linearize_mixed(hipStream_t s, Ctx &c, int level, bool ic, const flo
 
 template <typename T>
 void Launch<T>::ic_residual(hipStream_t s, Ctx &c, int level, const T *rel_cur) {
+    ic_residual_shape(s, c, level, rel_cur, c.tune_res);
+}
+
+template <typename T>
+void Launch<T>::ic_residual_shape(hipStream_t s, Ctx &c, int level, const T *rel_cur, LaunchShape sh) {
     if (c.O == 0) return;
     ResArgs<T> a = res_args<T>(c, level, rel_cur);
-    k_ic_residual<T><<<nblk((size_t)c.O * LANES_PER_OBS, BLOCK), BLOCK, 0, s>>>(a);
+    const unsigned g = shape_grid(c, sh);
+    switch (sh.block) {
+        case 64: k_ic_residual<T, 64><<<g, 64, 0, s>>>(a); break;
+        case 128: k_ic_residual<T, 128><<<g, 128, 0, s>>>(a); break;
+        case 512: k_ic_residual<T, 512><<<g, 512, 0, s>>>(a); break;
+        case 1024: k_ic_residual<T, 1024><<<g, 1024, 0, s>>>(a); break;
+        default: k_ic_residual<T, 256><<<g, 256, 0, s>>>(a); break;
+    }
+    CHECK_LAUNCH();
+}
+
+template <typename T>
+void Launch<T>::fc_linearize_shape(hipStream_t s, Ctx &c, int level, const T *rel_cur, LaunchShape sh) {
+    if (c.O == 0) return;
+    ResArgs<T> a = res_args<T>(c, level, rel_cur);
+    launch_linearize_shape<T, false>(s, c, a, 1, sh);
     CHECK_LAUNCH();
 }
 

@@ -64,6 +64,21 @@ class pba_timing(C.Structure):
                 ("residuals_processed", C.c_int64 * PBA_MAX_LEVELS)]
 
 
+PBA_TUNE_MAX = 16
+
+
+class pba_tune_report(C.Structure):
+    _fields_ = [("n_candidates", C.c_int32), ("block", C.c_int32 * PBA_TUNE_MAX),
+                ("grid_mult", C.c_int32 * PBA_TUNE_MAX), ("us", C.c_double * PBA_TUNE_MAX), ("chosen", C.c_int32)]
+
+    def as_dict(self):
+        n = self.n_candidates
+        return {"candidates": [{"block": self.block[i], "grid_mult": self.grid_mult[i], "us": self.us[i]}
+                               for i in range(n)],
+                "chosen": {"block": self.block[self.chosen], "grid_mult": self.grid_mult[self.chosen],
+                           "us": self.us[self.chosen]} if n else None}
+
+
 class PbaError(RuntimeError):
     def __init__(self, status, msg):
         super().__init__(f"{status_string(status)}: {msg}")
@@ -87,6 +102,7 @@ _sig = {
     "pba_set_params": (C.c_int, [_P, C.c_int32, _P, _P]),
     "pba_debug_fetch": (C.c_int, [_P, C.c_int32, _P, C.c_size_t]),
     "pba_get_timing": (C.c_int, [_P, C.POINTER(pba_timing)]),
+    "pba_autotune": (C.c_int, [_P, C.c_int32, C.c_int32, C.POINTER(pba_tune_report)]),
     "pba_destroy": (None, [_P]),
     "pba_last_error": (C.c_char_p, [_P]),
     "pba_status_string": (C.c_char_p, [C.c_int]),
@@ -248,6 +264,11 @@ class Solver:
             host = np.repeat(w["host_frame"].astype(np.int64), np.diff(w["obs_ptr"]))
             total += int(np.unique(host * (1 << 31) + w["obs_frame"]).size)
         return total
+
+    def autotune(self, level=0, reps=20):
+        rep = pba_tune_report()
+        self._chk(pba_autotune(self.ctx, level, reps, C.byref(rep)))
+        return rep.as_dict()
 
     def timing(self):
         t = pba_timing()

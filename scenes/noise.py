@@ -15,6 +15,10 @@ class ValueNoise3:
         self.mask = table - 1
         self.perm = rng.permutation(table).astype(np.int64)
         self.vals = rng.random(table)
+        # lattice value reached through the last hash step, and int32 copies
+        # (exact integer arithmetic: the same values as _lattice, fewer gathers)
+        self._p32 = self.perm.astype(np.int32)
+        self._vp = self.vals[self.perm]
 
     def _lattice(self, i, j, k):
         p, m = self.perm, self.mask
@@ -28,15 +32,20 @@ class ValueNoise3:
     def single(self, x, y, z):
         xi, yi, zi = np.floor(x), np.floor(y), np.floor(z)
         fx, fy, fz = self._fade(x - xi), self._fade(y - yi), self._fade(z - zi)
-        i, j, k = xi.astype(np.int64), yi.astype(np.int64), zi.astype(np.int64)
+        m, p = self.mask, self._p32
+        # the table size is a power of two, so masking the low bits of the int32
+        # lattice indices gives the same hash as masking int64 ones
+        i, j, k = xi.astype(np.int32), yi.astype(np.int32), zi.astype(np.int32)
         out = 0.0
         for di in (0, 1):
             wx = fx if di else 1.0 - fx
+            hi = p[(i + di) & m]
             for dj in (0, 1):
                 wy = fy if dj else 1.0 - fy
+                hij = p[(hi + j + dj) & m]
                 for dk in (0, 1):
                     wz = fz if dk else 1.0 - fz
-                    out = out + wx * wy * wz * self._lattice(i + di, j + dj, k + dk)
+                    out = out + wx * wy * wz * self._vp[(hij + k + dk) & m]
         return out
 
     def fractal(self, pts, base_freq=4.0, octaves=3):

@@ -126,3 +126,23 @@ def test_batched_invalid_usage(wins):
         b.set_frames(wins[1].images[:, :100, :100], wins[1].intrinsics, wins[1].poses_init, window=1)
     with pytest.raises(pba.PbaError):
         b.set_scene(wins[1], window=2)
+
+
+@pytest.mark.parametrize("mode", ["ic", "fc"])
+def test_autotune_keeps_results(wins, mode):
+    """The autotuner only changes launch shapes: iterates after tuning equal the
+    untuned ones bit for bit."""
+    a = make(len(wins), mode, pba.PBA_FP32)
+    load(a, wins)
+    a.iterate(0, 3)
+    b = make(len(wins), mode, pba.PBA_FP32)
+    load(b, wins)
+    rep = b.autotune(0, 3)
+    assert len(rep["candidates"]) >= 9 and rep["chosen"] in rep["candidates"]
+    assert all(c["us"] > 0 for c in rep["candidates"])
+    b.iterate(0, 3)
+    for w in range(len(wins)):
+        pa, da = a.get_params(w)
+        pb, db = b.get_params(w)
+        np.testing.assert_array_equal(pa, pb)
+        np.testing.assert_array_equal(da, db)
