@@ -70,7 +70,7 @@ typedef enum {
 
 enum { PBA_FC = 0, PBA_IC_PROXY = 1 };                        /* pba_config.mode */
 enum { PBA_FP64 = 0, PBA_FP32 = 1, PBA_MIXED_BF16 = 2 };      /* pba_config.precision */
-enum { PBA_SOLVER_CHOL = 0 };                                 /* pba_config.solver */
+enum { PBA_SOLVER_CHOL = 0, PBA_SOLVER_PCG_JACOBI = 1, PBA_SOLVER_PCG_LEARNED = 2 }; /* reduced solvers */
 enum { PBA_HOST = 0, PBA_DEVICE = 1 };                        /* memory of input pointers */
 enum { PBA_FLAG_TIMING = 1, PBA_FLAG_GRAPH = 2 };             /* pba_config.flags */
 
@@ -93,7 +93,7 @@ typedef struct {
     double huber_k;      /* Huber threshold in intensity units (> 0; +inf = least squares) */
     double damping_rel;  /* diagonal damping relative to the mean diagonal (>= 0) */
     int32_t pinned_frame;/* frame whose pose is held fixed (gauge), or -1 */
-    int32_t solver;      /* PBA_SOLVER_CHOL */
+    int32_t solver;      /* PBA_SOLVER_CHOL (the Gauss-Newton iterations factor or invert S) */
     int32_t n_windows;   /* independent problems held by the context; must be 1 */
     int32_t flags;       /* PBA_FLAG_TIMING: time the residual kernel with HIP events */
     void *stream;        /* hipStream_t to run on, or NULL for a library-owned stream */
@@ -217,6 +217,69 @@ typedef struct {
  * rewrite per-observation sums that the next iteration recomputes. `out` may
  * be NULL. PBA_MIXED_BF16 in FC mode has a fixed shape (n_candidates = 0). */
 pba_status pba_autotune(pba_ctx *ctx, int32_t level, int32_t reps, pba_tune_report *out);
+
+/* ---- Learned block preconditioner for PCG on the reduced pose system (project-defined: the
+ * paper inverts or factorizes the reduced system). Block whitening: S_ii = C_i C_i^T,
+ * S^_ij = C_i^{-1} S_ij C_j^{-T}, coupling G_i = sum_{j != i} S^_ij S^_ij^T (6x6, stored as its
+ * upper triangle, row-major, 21 floats). Features of block i: upper(G_i) / (1 + tr G_i) and
+ * log(1 + tr G_i). Network 22 -> 256 -> 256 -> 21 (ReLU), weights packed as W1 [256][22], b1,
+ * W2 [256][256], b2, W3 [21][256], b3 (PBA_PC_N_PARAMS floats). Output y: lower factor L of
+ * a 6x6 (row-major lower triangle, exp on the diagonal); block of M^{-1}:
+ * C_i^{-T} L L^T C_i^{-1} (y = 0: block Jacobi). Training loss of a block:
+ * tr(P A P) - 2 tr(P) + 6 with P = L L^T, A = I + G_i (mean over a batch). Inference runs in
+ * FP16 on MFMA, training in FP32 with Adam, PCG in FP64. One window only (n_windows = 1). */
+#define PBA_PC_N_PARAMS 77077
+
+typedef struct {
+    int32_t steps;                /* optimizer steps */
+    int32_t batch;                /* blocks per step, 1..65536 */
+    float lr, beta1, beta2, eps;  /* Adam */
+    uint64_t seed;                /* order of the samples (reshuffled every pass) */
+} pba_train_config;
+
+typedef struct {
+    int32_t steps;
+    int64_t samples;
+    double first_loss, final_loss; /* mean block loss of the first and the last batch */
+    double jacobi_loss;            /* mean loss of block Jacobi (y = 0) over all samples: mean tr G */
+    double trained_loss;           /* mean loss of the trained network (FP32) over all samples */
+    double ms;                     /* GPU time of the optimizer steps */
+} pba_train_report;
+
+typedef struct {
+    int32_t solver;        /* PBA_SOLVER_* used */
+    int32_t iters;         /* PCG iterations (0 for Cholesky) */
+    int32_t converged;     /* PCG reached tol */
+    int32_t fallback;      /* PCG did not reach tol in max_iters: x is the Cholesky solution */
+    double rel_residual;   /* ||S x + b|| / ||b|| of the returned x */
+    double ms;             /* GPU time of the whole solve */
+    double ms_setup;       /* of which preconditioner set-up (whitening, network, blocks) or
+                              factorization (Cholesky) */
+} pba_reduced_report;
+
+/* Weights: He-initialized hidden layers and a zero output layer (block Jacobi) from `seed`. */
+pba_status pba_pc_init(pba_ctx *ctx, uint64_t seed);
+/* Copy n == PBA_PC_N_PARAMS weights in / out (host memory). */
+pba_status pba_pc_set_weights(pba_ctx *ctx, const float *w, size_t n);
+pba_status pba_pc_get_weights(pba_ctx *ctx, float *w, size_t n);
+/* Couplings G_i of the context's current reduced system (the last one assembled: IC at the
+ * level start, FC in the last iteration) into G_out [6F / 6][21] (n_floats must be >= 21 F);
+ * *n_blocks receives F. Training samples are gathered this way from any contexts. */
+pba_status pba_pc_harvest(pba_ctx *ctx, float *G_out, size_t n_floats, int32_t *n_blocks);
+/* Train the network on the GPU on n_samples couplings G [n_samples][21] (host memory). */
+pba_status pba_pc_train(pba_ctx *ctx, int64_t n_samples, const float *G, const pba_train_config *cfg,
+                        pba_train_report *rep);
+/* One FP32 forward and backward pass on n_samples couplings: mean loss and its gradient
+ * (PBA_PC_N_PARAMS floats, packed like the weights). */
+pba_status pba_pc_gradient(pba_ctx *ctx, int32_t n_samples, const float *G, double *loss, float *grad);
+/* FP16 network outputs y [n_samples][21] for the given couplings. */
+pba_status pba_pc_infer(pba_ctx *ctx, int32_t n_samples, const float *G, float *Y);
+/* Solve S x = -b for the context's current reduced system and right-hand side (those of the
+ * last iteration) with PBA_SOLVER_CHOL (tiled Cholesky), PBA_SOLVER_PCG_JACOBI or
+ * PBA_SOLVER_PCG_LEARNED (relative residual tol, at most max_iters iterations, Cholesky as
+ * the fallback). x_out: host [6F] or NULL. */
+pba_status pba_solve_reduced(pba_ctx *ctx, int32_t solver, double tol, int32_t max_iters, double *x_out,
+                             pba_reduced_report *rep);
 
 /* Copy an internal buffer (PBA_DBG_*) to host memory; bytes must match its size exactly. */
 pba_status pba_debug_fetch(pba_ctx *ctx, int32_t what, void *out, size_t bytes);

@@ -12,6 +12,7 @@
 #include <cstring>
 #include <map>
 #include <numeric>
+#include <random>
 #include <string>
 #include <vector>
 
@@ -106,6 +107,7 @@ void drop_graph(Ctx &c);
 
 void release_points(Ctx &c) {
     drop_graph(c);
+    c.s_valid = false;
     for (int **p : {&c.d_host_frame, &c.d_obs_ptr, &c.d_obs_frame, &c.d_obs_point, &c.d_obs_pair, &c.d_pair_host,
                     &c.d_pair_target, &c.d_pair_obs_ptr, &c.d_pair_obs_idx, &c.d_frame_pair_ptr,
                     &c.d_frame_pair_item, &c.d_pair_local, &c.d_pair_hidx, &c.d_host_m, &c.d_host_frames,
@@ -168,7 +170,7 @@ std::string validate_config(const pba_config *cfg) {
     if (!(cfg->huber_k > 0.0)) return "huber_k must be > 0";
     if (!(cfg->damping_rel >= 0.0) || !std::isfinite(cfg->damping_rel)) return "damping_rel must be finite and >= 0";
     if (cfg->pinned_frame < -1) return "pinned_frame must be >= -1";
-    if (cfg->solver != PBA_SOLVER_CHOL) return "solver must be PBA_SOLVER_CHOL";
+    if (cfg->solver != PBA_SOLVER_CHOL) return "solver must be PBA_SOLVER_CHOL (PCG: pba_solve_reduced)";
     if (cfg->n_windows < 1 || cfg->n_windows > PBA_MAX_WINDOWS) return "n_windows must be in 1..PBA_MAX_WINDOWS";
     if (cfg->flags & ~(PBA_FLAG_TIMING | PBA_FLAG_GRAPH)) return "unknown flag bits";
     return "";
@@ -329,6 +331,9 @@ pba_status start_level(Ctx &c, int level) {
         launch_assemble_s(s, c, c.d_geo0);
         launch_ic_factor(s, c);
         launch_ic_inverse(s, c);
+        c.s_valid = true;
+    } else {
+        c.s_valid = false;
     }
     HIPCHK(hipGetLastError());
     c.cur_level = level;
@@ -367,6 +372,7 @@ pba_status one_iteration(Ctx &c, int level, double *stat, hipEvent_t ev0, hipEve
     }
     Launch<T>::depth_update(s, c, geo_cur, geo_next, stat, conv_px, level);
     HIPCHK(hipGetLastError());
+    c.s_valid = true;
     c.flip = !c.flip;
     c.iters_in_level++;
     return PBA_OK;
@@ -803,6 +809,82 @@ pba_status ready(pba_ctx *ctx) {
     return PBA_OK;
 }
 
+// ---- learned preconditioner buffers
+
+void release_pc(Ctx &c) {
+    PcState &p = c.pc;
+    for (float **q : {&p.w, &p.m, &p.v, &p.grad, &p.X, &p.Y, &p.Z1, &p.H1, &p.Z2, &p.H2, &p.Yt, &p.dY, &p.D1, &p.D2,
+                      &p.lossv, &p.Xb, &p.Gb, &p.Gs, &p.Xs})
+        dfree(*q);
+    for (double **q : {&p.Ci, &p.G, &p.P, &p.x, &p.r, &p.z, &p.p, &p.q, &p.part, &p.sc, &p.lsum}) dfree(*q);
+    dfree(p.wh);
+    dfree(p.flag);
+    dfree(p.st);
+    dfree(p.idx);
+    p = PcState();
+}
+
+pba_status pc_ensure_weights(Ctx &c) {
+    PcState &p = c.pc;
+    if (p.w) return PBA_OK;
+    HIPCHK(dalloc(p.w, PC_N_PARAMS * sizeof(float)));
+    HIPCHK(dalloc(p.m, PC_N_PARAMS * sizeof(float)));
+    HIPCHK(dalloc(p.v, PC_N_PARAMS * sizeof(float)));
+    HIPCHK(dalloc(p.grad, PC_N_PARAMS * sizeof(float)));
+    HIPCHK(dalloc(p.wh, (size_t)(256 * 32 + 256 * 256 + 32 * 256) * sizeof(_Float16)));
+    HIPCHK(dalloc(p.lsum, sizeof(double)));
+    HIPCHK(dalloc(p.flag, sizeof(int)));
+    HIPCHK(dalloc(p.st, 2 * sizeof(int)));
+    return PBA_OK;
+}
+
+pba_status pc_ensure_system(Ctx &c, int nb) {
+    PcState &p = c.pc;
+    if (nb <= p.nb_cap) return PBA_OK;
+    const size_t n = 6 * (size_t)nb, parts = (n + 7) / 8 + 1;
+    HIPCHK(dalloc(p.Ci, (size_t)nb * 36 * sizeof(double)));
+    HIPCHK(dalloc(p.G, (size_t)nb * 21 * sizeof(double)));
+    HIPCHK(dalloc(p.P, (size_t)nb * 36 * sizeof(double)));
+    HIPCHK(dalloc(p.X, (size_t)nb * PC_IN * sizeof(float)));
+    HIPCHK(dalloc(p.Y, (size_t)nb * PC_OUT * sizeof(float)));
+    for (double **q : {&p.x, &p.r, &p.z, &p.p, &p.q}) HIPCHK(dalloc(*q, n * sizeof(double)));
+    HIPCHK(dalloc(p.part, parts * sizeof(double)));
+    HIPCHK(dalloc(p.sc, 4 * sizeof(double)));
+    p.nb_cap = nb;
+    return PBA_OK;
+}
+
+pba_status pc_ensure_batch(Ctx &c, int B) {
+    PcState &p = c.pc;
+    if (B <= p.b_cap) return PBA_OK;
+    for (float **q : {&p.Z1, &p.H1, &p.Z2, &p.H2, &p.D1, &p.D2}) HIPCHK(dalloc(*q, (size_t)B * 256 * sizeof(float)));
+    HIPCHK(dalloc(p.Yt, (size_t)B * PC_OUT * sizeof(float)));
+    HIPCHK(dalloc(p.dY, (size_t)B * PC_OUT * sizeof(float)));
+    HIPCHK(dalloc(p.lossv, (size_t)B * sizeof(float)));
+    HIPCHK(dalloc(p.Xb, (size_t)B * PC_IN * sizeof(float)));
+    HIPCHK(dalloc(p.Gb, (size_t)B * 21 * sizeof(float)));
+    HIPCHK(dalloc(p.idx, (size_t)B * sizeof(int)));
+    p.b_cap = B;
+    return PBA_OK;
+}
+
+// Samples G [m][21] to the device (Gb) and their features (Xb).
+pba_status pc_upload_samples(Ctx &c, int m, const float *G) {
+    pba_status st;
+    if ((st = pc_ensure_batch(c, m)) != PBA_OK) return st;
+    for (int i = 0; i < m * 21; ++i)
+        if (!std::isfinite(G[i])) return fail(&c, PBA_E_INVALID, "couplings must be finite");
+    HIPCHK(hipMemcpyAsync(c.pc.Gb, G, (size_t)m * 21 * sizeof(float), hipMemcpyHostToDevice, c.stream));
+    pc_features(c.stream, m, c.pc.Gb, c.pc.Xb);
+    return PBA_OK;
+}
+
+std::string pc_system_check(Ctx &c) {
+    if (c.nwin != 1) return "the reduced-system solvers take one window (n_windows = 1)";
+    if (!c.s_valid) return "no reduced system assembled yet (run an iteration first)";
+    return "";
+}
+
 }  // namespace
 
 // ================================================================ C ABI
@@ -888,6 +970,7 @@ void pba_destroy(pba_ctx *ctx) {
     if (c.stream) (void)hipStreamSynchronize(c.stream);
     release_frames(c);
     dfree(c.d_eval);
+    release_pc(c);
     for (hipEvent_t e : c.ev_pool) (void)hipEventDestroy(e);
     if (c.own_stream && c.stream) (void)hipStreamDestroy(c.stream);
     delete ctx;
@@ -1230,6 +1313,292 @@ pba_status pba_autotune(pba_ctx *ctx, int32_t level, int32_t reps, pba_tune_repo
     // the level restarts at the next iteration (the FC frozen set is rewritten by it)
     c.cur_level = -1;
     if (out) *out = rep;
+    return PBA_OK;
+}
+
+
+pba_status pba_pc_init(pba_ctx *ctx, uint64_t seed) {
+    if (!ctx) return fail(nullptr, PBA_E_INVALID, "ctx is NULL");
+    Ctx &c = ctx->c;
+    pba_status st;
+    if ((st = pc_ensure_weights(c)) != PBA_OK) return st;
+    std::mt19937_64 rng(seed);
+    std::normal_distribution<double> nd(0.0, 1.0);
+    std::vector<float> w(PC_N_PARAMS, 0.0f);
+    const double s1 = std::sqrt(2.0 / PC_IN), s2 = std::sqrt(2.0 / PC_HID);
+    for (int i = 0; i < PC_HID * PC_IN; ++i) w[i] = (float)(s1 * nd(rng));
+    for (int i = 0; i < PC_HID * PC_HID; ++i) w[PC_OFF_W2 + i] = (float)(s2 * nd(rng));
+    return pba_pc_set_weights(ctx, w.data(), w.size());
+}
+
+pba_status pba_pc_set_weights(pba_ctx *ctx, const float *w, size_t n) {
+    if (!ctx) return fail(nullptr, PBA_E_INVALID, "ctx is NULL");
+    Ctx &c = ctx->c;
+    if (!w || n != (size_t)PC_N_PARAMS) return fail(&c, PBA_E_INVALID, "need PBA_PC_N_PARAMS weights");
+    for (size_t i = 0; i < n; ++i)
+        if (!std::isfinite(w[i])) return fail(&c, PBA_E_INVALID, "weights must be finite");
+    pba_status st;
+    if ((st = pc_ensure_weights(c)) != PBA_OK) return st;
+    HIPCHK(hipMemcpyAsync(c.pc.w, w, n * sizeof(float), hipMemcpyHostToDevice, c.stream));
+    HIPCHK(hipMemsetAsync(c.pc.m, 0, n * sizeof(float), c.stream));
+    HIPCHK(hipMemsetAsync(c.pc.v, 0, n * sizeof(float), c.stream));
+    pc_to_half(c.stream, c);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(c.stream));
+    c.pc.adam_step = 0;
+    c.pc.have_w = true;
+    return PBA_OK;
+}
+
+pba_status pba_pc_get_weights(pba_ctx *ctx, float *w, size_t n) {
+    if (!ctx) return fail(nullptr, PBA_E_INVALID, "ctx is NULL");
+    Ctx &c = ctx->c;
+    if (!w || n != (size_t)PC_N_PARAMS) return fail(&c, PBA_E_INVALID, "need PBA_PC_N_PARAMS weights");
+    if (!c.pc.have_w) return fail(&c, PBA_E_STATE, "no weights (pba_pc_init or pba_pc_set_weights)");
+    HIPCHK(hipMemcpyAsync(w, c.pc.w, n * sizeof(float), hipMemcpyDeviceToHost, c.stream));
+    HIPCHK(hipStreamSynchronize(c.stream));
+    return PBA_OK;
+}
+
+pba_status pba_pc_harvest(pba_ctx *ctx, float *G_out, size_t n_floats, int32_t *n_blocks) {
+    if (!ctx) return fail(nullptr, PBA_E_INVALID, "ctx is NULL");
+    Ctx &c = ctx->c;
+    pba_status st;
+    if ((st = ready(ctx)) != PBA_OK) return st;
+    const std::string e = pc_system_check(c);
+    if (!e.empty()) return fail(&c, PBA_E_STATE, e);
+    const int nb = c.F;
+    if (!G_out || n_floats < (size_t)nb * 21) return fail(&c, PBA_E_INVALID, "G_out needs 21 F floats");
+    if ((st = pc_ensure_weights(c)) != PBA_OK) return st;
+    if ((st = pc_ensure_system(c, nb)) != PBA_OK) return st;
+    HIPCHK(hipMemsetAsync(c.pc.flag, 0, sizeof(int), c.stream));
+    pc_whiten(c.stream, c, nb);
+    std::vector<double> G((size_t)nb * 21);
+    int flag = 0;
+    HIPCHK(hipMemcpyAsync(G.data(), c.pc.G, G.size() * sizeof(double), hipMemcpyDeviceToHost, c.stream));
+    HIPCHK(hipMemcpyAsync(&flag, c.pc.flag, sizeof(int), hipMemcpyDeviceToHost, c.stream));
+    HIPCHK(hipStreamSynchronize(c.stream));
+    if (flag) return fail(&c, PBA_E_NUMERIC, "a diagonal block of S is not positive definite");
+    for (size_t i = 0; i < G.size(); ++i) G_out[i] = (float)G[i];
+    if (n_blocks) *n_blocks = nb;
+    return PBA_OK;
+}
+
+pba_status pba_pc_gradient(pba_ctx *ctx, int32_t n_samples, const float *G, double *loss, float *grad) {
+    if (!ctx) return fail(nullptr, PBA_E_INVALID, "ctx is NULL");
+    Ctx &c = ctx->c;
+    if (n_samples < 1 || n_samples > 65536 || !G) return fail(&c, PBA_E_INVALID, "need 1..65536 samples");
+    if (!c.pc.have_w) return fail(&c, PBA_E_STATE, "no weights (pba_pc_init or pba_pc_set_weights)");
+    pba_status st;
+    if ((st = pc_upload_samples(c, n_samples, G)) != PBA_OK) return st;
+    pc_forward_backward(c.stream, c, n_samples, c.pc.Xb, c.pc.Gb, c.pc.grad, c.pc.lossv);
+    pc_sum(c.stream, n_samples, c.pc.lossv, c.pc.lsum);
+    double ls = 0.0;
+    HIPCHK(hipMemcpyAsync(&ls, c.pc.lsum, sizeof(double), hipMemcpyDeviceToHost, c.stream));
+    if (grad) HIPCHK(hipMemcpyAsync(grad, c.pc.grad, PC_N_PARAMS * sizeof(float), hipMemcpyDeviceToHost, c.stream));
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(c.stream));
+    if (loss) *loss = ls / n_samples;
+    return PBA_OK;
+}
+
+pba_status pba_pc_infer(pba_ctx *ctx, int32_t n_samples, const float *G, float *Y) {
+    if (!ctx) return fail(nullptr, PBA_E_INVALID, "ctx is NULL");
+    Ctx &c = ctx->c;
+    if (n_samples < 1 || n_samples > 65536 || !G || !Y) return fail(&c, PBA_E_INVALID, "need 1..65536 samples");
+    if (!c.pc.have_w) return fail(&c, PBA_E_STATE, "no weights (pba_pc_init or pba_pc_set_weights)");
+    pba_status st;
+    if ((st = pc_upload_samples(c, n_samples, G)) != PBA_OK) return st;
+    pc_infer(c.stream, c, n_samples, c.pc.Xb, c.pc.Yt);
+    HIPCHK(hipMemcpyAsync(Y, c.pc.Yt, (size_t)n_samples * PC_OUT * sizeof(float), hipMemcpyDeviceToHost, c.stream));
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(c.stream));
+    return PBA_OK;
+}
+
+pba_status pba_pc_train(pba_ctx *ctx, int64_t n_samples, const float *G, const pba_train_config *cfg,
+                        pba_train_report *rep) {
+    if (!ctx) return fail(nullptr, PBA_E_INVALID, "ctx is NULL");
+    Ctx &c = ctx->c;
+    if (!cfg || !G || n_samples < 1 || n_samples > (1LL << 26)) return fail(&c, PBA_E_INVALID, "bad training input");
+    if (cfg->steps < 0 || cfg->batch < 1 || cfg->batch > 65536 || !(cfg->lr > 0.0f) || !(cfg->beta1 >= 0.0f) ||
+        !(cfg->beta1 < 1.0f) || !(cfg->beta2 >= 0.0f) || !(cfg->beta2 < 1.0f) || !(cfg->eps > 0.0f))
+        return fail(&c, PBA_E_INVALID, "bad training configuration");
+    if (!c.pc.have_w) return fail(&c, PBA_E_STATE, "no weights (pba_pc_init or pba_pc_set_weights)");
+    for (int64_t i = 0; i < n_samples * 21; ++i)
+        if (!std::isfinite(G[i])) return fail(&c, PBA_E_INVALID, "couplings must be finite");
+    PcState &p = c.pc;
+    pba_status st;
+    const int B = (int)std::min<int64_t>(cfg->batch, n_samples);
+    if ((st = pc_ensure_batch(c, B)) != PBA_OK) return st;
+    // samples and their features on the device
+    dfree(p.Gs);
+    dfree(p.Xs);
+    HIPCHK(dalloc(p.Gs, (size_t)n_samples * 21 * sizeof(float)));
+    HIPCHK(dalloc(p.Xs, (size_t)n_samples * PC_IN * sizeof(float)));
+    HIPCHK(hipMemcpyAsync(p.Gs, G, (size_t)n_samples * 21 * sizeof(float), hipMemcpyHostToDevice, c.stream));
+    pc_features(c.stream, (int)n_samples, p.Gs, p.Xs);
+    p.ns = n_samples;
+    int *didx = nullptr;
+    HIPCHK(dalloc(didx, (size_t)n_samples * sizeof(int)));
+    std::mt19937_64 rng(cfg->seed);
+    std::vector<int> perm(n_samples);
+    std::iota(perm.begin(), perm.end(), 0);
+    pba_train_report r;
+    std::memset(&r, 0, sizeof(r));
+    r.samples = n_samples;
+    double jl = 0.0;
+    for (int64_t i = 0; i < n_samples; ++i)
+        for (int k = 0; k < 6; ++k) jl += (double)G[21 * i + k * 6 - k * (k - 1) / 2];
+    r.jacobi_loss = jl / n_samples;
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    int64_t pos = n_samples;  // reshuffle at the first step
+    HIPCHK(hipEventRecord(e0, c.stream));
+    for (int step = 0; step < cfg->steps; ++step) {
+        if (pos + B > n_samples) {
+            std::shuffle(perm.begin(), perm.end(), rng);
+            HIPCHK(hipMemcpyAsync(didx, perm.data(), perm.size() * sizeof(int), hipMemcpyHostToDevice, c.stream));
+            HIPCHK(hipStreamSynchronize(c.stream));  // perm is reused by the next reshuffle
+            pos = 0;
+        }
+        pc_gather(c.stream, B, didx + pos, p.Xs, PC_IN, p.Xb);
+        pc_gather(c.stream, B, didx + pos, p.Gs, 21, p.Gb);
+        pos += B;
+        pc_forward_backward(c.stream, c, B, p.Xb, p.Gb, p.grad, p.lossv);
+        if (step == 0 || step == cfg->steps - 1) {
+            pc_sum(c.stream, B, p.lossv, p.lsum);
+            double ls = 0.0;
+            HIPCHK(hipMemcpyAsync(&ls, p.lsum, sizeof(double), hipMemcpyDeviceToHost, c.stream));
+            HIPCHK(hipStreamSynchronize(c.stream));
+            (step == 0 ? r.first_loss : r.final_loss) = ls / B;
+        }
+        pc_adam(c.stream, c, cfg->lr, cfg->beta1, cfg->beta2, cfg->eps, ++p.adam_step);
+    }
+    HIPCHK(hipEventRecord(e1, c.stream));
+    HIPCHK(hipEventSynchronize(e1));
+    float ms = 0.f;
+    HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    r.ms = ms;
+    r.steps = cfg->steps;
+    // mean loss of the trained network over all samples (FP32 forward, chunks of B)
+    double tot = 0.0;
+    for (int64_t i0 = 0; i0 < n_samples; i0 += B) {
+        const int m = (int)std::min<int64_t>(B, n_samples - i0);
+        pc_forward_backward(c.stream, c, m, p.Xs + i0 * PC_IN, p.Gs + i0 * 21, p.grad, p.lossv);
+        pc_sum(c.stream, m, p.lossv, p.lsum);
+        double ls = 0.0;
+        HIPCHK(hipMemcpyAsync(&ls, p.lsum, sizeof(double), hipMemcpyDeviceToHost, c.stream));
+        HIPCHK(hipStreamSynchronize(c.stream));
+        tot += ls;
+    }
+    r.trained_loss = tot / n_samples;
+    pc_to_half(c.stream, c);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(c.stream));
+    dfree(didx);
+    if (rep) *rep = r;
+    return PBA_OK;
+}
+
+pba_status pba_solve_reduced(pba_ctx *ctx, int32_t solver, double tol, int32_t max_iters, double *x_out,
+                             pba_reduced_report *rep) {
+    if (!ctx) return fail(nullptr, PBA_E_INVALID, "ctx is NULL");
+    Ctx &c = ctx->c;
+    if (solver != PBA_SOLVER_CHOL && solver != PBA_SOLVER_PCG_JACOBI && solver != PBA_SOLVER_PCG_LEARNED)
+        return fail(&c, PBA_E_INVALID, "unknown solver");
+    if (!(tol > 0.0) || max_iters < 1) return fail(&c, PBA_E_INVALID, "tol must be > 0 and max_iters >= 1");
+    pba_status st;
+    if ((st = ready(ctx)) != PBA_OK) return st;
+    const std::string e = pc_system_check(c);
+    if (!e.empty()) return fail(&c, PBA_E_STATE, e);
+    if (solver == PBA_SOLVER_PCG_LEARNED && !c.pc.have_w)
+        return fail(&c, PBA_E_STATE, "no weights (pba_pc_init, pba_pc_set_weights or pba_pc_train)");
+    const int nb = c.F, n = 6 * c.F;
+    if ((st = pc_ensure_weights(c)) != PBA_OK) return st;
+    if ((st = pc_ensure_system(c, nb)) != PBA_OK) return st;
+    if (!c.d_Sfac) {
+        const size_t nt = (n + TCHOL_TILE - 1) / TCHOL_TILE;
+        HIPCHK(dalloc(c.d_Sfac, (size_t)n * n * sizeof(double)));
+        HIPCHK(dalloc(c.d_Linv, nt * TCHOL_TILE * TCHOL_TILE * sizeof(double)));
+    }
+    if ((st = ensure_events(c, 3)) != PBA_OK) return st;
+    hipEvent_t e0 = c.ev_pool[0], e1 = c.ev_pool[1], e2 = c.ev_pool[2];
+    hipStream_t s = c.stream;
+    pba_reduced_report r;
+    std::memset(&r, 0, sizeof(r));
+    r.solver = solver;
+    const double *xdev = c.pc.x;
+    auto cholesky = [&](bool timed_setup) -> pba_status {
+        launch_open(s, c, 0, true);  // gate open, flag clear
+        launch_tchol(s, c);
+        if (timed_setup) HIPCHK(hipEventRecord(e1, s));
+        launch_tsolve(s, c, c.d_b, c.pc.x);
+        return PBA_OK;
+    };
+    HIPCHK(hipEventRecord(e0, s));
+    if (solver == PBA_SOLVER_CHOL) {
+        if ((st = cholesky(true)) != PBA_OK) return st;
+    } else {
+        HIPCHK(hipMemsetAsync(c.pc.flag, 0, sizeof(int), s));
+        pc_whiten(s, c, nb);
+        if (solver == PBA_SOLVER_PCG_LEARNED) {
+            pc_infer(s, c, nb, c.pc.X, c.pc.Y);
+            pc_blocks(s, c, nb, c.pc.Y);
+        } else {
+            pc_blocks(s, c, nb, nullptr);
+        }
+        HIPCHK(hipEventRecord(e1, s));
+        pcg_init(s, c, n);
+        int hst[2] = {0, 0};
+        const int chunk = 16;
+        int done_iters = 0;
+        while (done_iters < max_iters) {
+            const int k = std::min(chunk, max_iters - done_iters);
+            pcg_iterations(s, c, n, k, tol);
+            done_iters += k;
+            HIPCHK(hipMemcpyAsync(hst, c.pc.st, sizeof(hst), hipMemcpyDeviceToHost, s));
+            HIPCHK(hipStreamSynchronize(s));
+            if (hst[0]) break;
+        }
+        int pflag = 0;
+        HIPCHK(hipMemcpyAsync(&pflag, c.pc.flag, sizeof(int), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        if (pflag) return fail(&c, PBA_E_NUMERIC, "a diagonal block of S is not positive definite");
+        r.iters = hst[1];
+        r.converged = hst[0] && hst[1] <= max_iters ? 1 : 0;
+        if (!r.converged) {
+            r.fallback = 1;
+            if ((st = cholesky(false)) != PBA_OK) return st;
+        }
+    }
+    HIPCHK(hipEventRecord(e2, s));
+    // relative residual of the returned x
+    const int parts = (n + 7) / 8;
+    pc_resid(s, c, n, xdev, c.pc.part);
+    std::vector<double> hp(parts), hb(n);
+    int cflag = 0;
+    HIPCHK(hipMemcpyAsync(hp.data(), c.pc.part, parts * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(hb.data(), c.d_b, n * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(&cflag, c.d_flag, sizeof(int), hipMemcpyDeviceToHost, s));
+    if (x_out) HIPCHK(hipMemcpyAsync(x_out, xdev, n * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(s));
+    if ((solver == PBA_SOLVER_CHOL || r.fallback) && cflag)
+        return fail(&c, PBA_E_NUMERIC, "reduced pose system is not positive definite");
+    double rr = 0.0, bb = 0.0;
+    for (double v : hp) rr += v;
+    for (double v : hb) bb += v * v;
+    r.rel_residual = bb > 0.0 ? std::sqrt(rr / bb) : std::sqrt(rr);
+    float ms = 0.f, ms1 = 0.f;
+    HIPCHK(hipEventElapsedTime(&ms, e0, e2));
+    HIPCHK(hipEventElapsedTime(&ms1, e0, e1));
+    r.ms = ms;
+    r.ms_setup = ms1;
+    if (rep) *rep = r;
     return PBA_OK;
 }
 

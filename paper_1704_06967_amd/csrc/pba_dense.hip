@@ -209,6 +209,25 @@ void launch_copy_d(hipStream_t s, const double *src, double *dst, size_t n) {
     k_copy_d<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(src, dst, n, nullptr);
 }
 
+// x = -(L L^T)^{-1} b with the tiled factor (one workgroup).
+__global__ __launch_bounds__(1024) void k_tsolve(int n, const double *__restrict__ L, const double *__restrict__ Linv,
+                                                 const double *__restrict__ b, double *__restrict__ x,
+                                                 const int *__restrict__ flag) {
+    extern __shared__ double dyn[];
+    if (*flag) return;
+    double *v = dyn, *tmp = dyn + n;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) v[i] = -b[i];
+    __syncthreads();
+    tile_chol_solve<1024>(L, Linv, n, v, tmp, 0);
+    for (int i = threadIdx.x; i < n; i += blockDim.x) x[i] = v[i];
+}
+
+void launch_tsolve(hipStream_t s, Ctx &c, const double *b, double *x) {
+    const int n = 6 * c.F;
+    const size_t lds = ((size_t)n + TB * (1024 / TB) + TB) * sizeof(double);
+    k_tsolve<<<1, 1024, lds, s>>>(n, c.d_Sfac, c.d_Linv, b, x, c.d_flag);
+}
+
 void launch_tchol(hipStream_t s, Ctx &c) {
     const int n = 6 * c.F, nt = (n + TB - 1) / TB;
     const size_t nn = (size_t)n * n;

@@ -62,6 +62,32 @@ struct LaunchShape {
     int grid_mult = 0;
 };
 
+// Learned block preconditioner (network 22 -> 256 -> 256 -> 21) and PCG state.
+constexpr int PC_IN = 22, PC_HID = 256, PC_OUT = 21;
+constexpr int PC_OFF_B1 = PC_HID * PC_IN, PC_OFF_W2 = PC_OFF_B1 + PC_HID, PC_OFF_B2 = PC_OFF_W2 + PC_HID * PC_HID,
+              PC_OFF_W3 = PC_OFF_B2 + PC_HID, PC_OFF_B3 = PC_OFF_W3 + PC_OUT * PC_HID,
+              PC_N_PARAMS = PC_OFF_B3 + PC_OUT;
+struct PcState {
+    float *w = nullptr, *m = nullptr, *v = nullptr, *grad = nullptr;  // FP32 weights, Adam moments, gradient
+    _Float16 *wh = nullptr;                                           // padded FP16 copy for inference
+    bool have_w = false;
+    int adam_step = 0;
+    int nb_cap = 0;                                                   // blocks of the current system
+    double *Ci = nullptr, *G = nullptr, *P = nullptr;
+    float *X = nullptr, *Y = nullptr;
+    int *flag = nullptr;
+    int n_cap = 0;                                                    // PCG vectors
+    double *x = nullptr, *r = nullptr, *z = nullptr, *p = nullptr, *q = nullptr, *part = nullptr, *sc = nullptr;
+    int *st = nullptr;
+    int b_cap = 0;                                                    // training batch scratch
+    float *Z1 = nullptr, *H1 = nullptr, *Z2 = nullptr, *H2 = nullptr, *Yt = nullptr, *dY = nullptr, *D1 = nullptr,
+          *D2 = nullptr, *lossv = nullptr, *Xb = nullptr, *Gb = nullptr;
+    int *idx = nullptr;
+    double *lsum = nullptr;
+    int64_t ns = 0, ns_cap = 0;                                       // training samples
+    float *Gs = nullptr, *Xs = nullptr;
+};
+
 struct LevelDev {
     int W = 0, H = 0;
     void *img = nullptr;      // T [F][H][W]
@@ -168,6 +194,10 @@ struct Ctx {
     // current double-buffer orientation
     bool flip = false;
 
+    // learned preconditioner and PCG
+    PcState pc;
+    bool s_valid = false;                              // d_S / d_b hold an assembled system
+
     // launch shapes of the per-iteration residual kernels (autotuned)
     int n_cu = 256;
     LaunchShape tune_res, tune_lin;
@@ -203,6 +233,21 @@ template <typename T> struct Launch {
     static void depth_update(hipStream_t s, Ctx &c, const double *geo_old, const double *geo_new, double *stat,
                              double conv_px, int level);
 };
+
+// learned preconditioner and PCG (pba_learned.hip)
+void pc_whiten(hipStream_t s, Ctx &c, int nb);                      // C_i^{-1}, G_i, features of S
+void pc_infer(hipStream_t s, Ctx &c, int m, const float *X, float *Y);
+void pc_blocks(hipStream_t s, Ctx &c, int nb, const float *Y);      // Y = nullptr: block Jacobi
+void pc_to_half(hipStream_t s, Ctx &c);
+void pc_features(hipStream_t s, int m, const float *G, float *X);
+void pc_gather(hipStream_t s, int m, const int *idx, const float *src, int width, float *dst);
+void pc_forward_backward(hipStream_t s, Ctx &c, int m, const float *X, const float *G, float *grad, float *lossv);
+void pc_adam(hipStream_t s, Ctx &c, float lr, float b1, float b2, float eps, int step);
+void pc_sum(hipStream_t s, int n, const float *v, double *out);
+void pcg_init(hipStream_t s, Ctx &c, int n);
+void pcg_iterations(hipStream_t s, Ctx &c, int n, int k, double tol);
+void pc_resid(hipStream_t s, Ctx &c, int n, const double *x, double *part);   // (S x + b)^2 row-group sums
+void launch_tsolve(hipStream_t s, Ctx &c, const double *b, double *x);        // x = -S^{-1} b, tiled factor
 
 // mixed precision linearization (pair order, BF16 MFMA pose blocks into the pair chunk partials)
 void launch_linearize_mixed(hipStream_t s, Ctx &c, int level, bool ic, const float *rel_cur, bool write_mask);

@@ -15,7 +15,8 @@ LIB_PATH = os.path.join(_HERE, "libpba.so")
 PBA_OK, PBA_E_INVALID, PBA_E_STATE, PBA_E_OOM, PBA_E_DEVICE, PBA_E_NUMERIC, PBA_E_NOT_CONVERGED = 0, -1, -2, -3, -4, -5, -6
 PBA_FC, PBA_IC_PROXY = 0, 1
 PBA_FP64, PBA_FP32, PBA_MIXED_BF16 = 0, 1, 2
-PBA_SOLVER_CHOL = 0
+PBA_SOLVER_CHOL, PBA_SOLVER_PCG_JACOBI, PBA_SOLVER_PCG_LEARNED = 0, 1, 2
+PBA_PC_N_PARAMS = 77077
 PBA_HOST, PBA_DEVICE = 0, 1
 PBA_FLAG_TIMING, PBA_FLAG_GRAPH = 1, 2
 PBA_MAX_PATTERN = 8
@@ -79,6 +80,27 @@ class pba_tune_report(C.Structure):
                            "us": self.us[self.chosen]} if n else None}
 
 
+class pba_train_config(C.Structure):
+    _fields_ = [("steps", C.c_int32), ("batch", C.c_int32), ("lr", C.c_float), ("beta1", C.c_float),
+                ("beta2", C.c_float), ("eps", C.c_float), ("seed", C.c_uint64)]
+
+
+class pba_train_report(C.Structure):
+    _fields_ = [("steps", C.c_int32), ("samples", C.c_int64), ("first_loss", C.c_double), ("final_loss", C.c_double),
+                ("jacobi_loss", C.c_double), ("trained_loss", C.c_double), ("ms", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class pba_reduced_report(C.Structure):
+    _fields_ = [("solver", C.c_int32), ("iters", C.c_int32), ("converged", C.c_int32), ("fallback", C.c_int32),
+                ("rel_residual", C.c_double), ("ms", C.c_double), ("ms_setup", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 class PbaError(RuntimeError):
     def __init__(self, status, msg):
         super().__init__(f"{status_string(status)}: {msg}")
@@ -103,6 +125,14 @@ _sig = {
     "pba_debug_fetch": (C.c_int, [_P, C.c_int32, _P, C.c_size_t]),
     "pba_get_timing": (C.c_int, [_P, C.POINTER(pba_timing)]),
     "pba_autotune": (C.c_int, [_P, C.c_int32, C.c_int32, C.POINTER(pba_tune_report)]),
+    "pba_pc_init": (C.c_int, [_P, C.c_uint64]),
+    "pba_pc_set_weights": (C.c_int, [_P, _P, C.c_size_t]),
+    "pba_pc_get_weights": (C.c_int, [_P, _P, C.c_size_t]),
+    "pba_pc_harvest": (C.c_int, [_P, _P, C.c_size_t, C.POINTER(C.c_int32)]),
+    "pba_pc_train": (C.c_int, [_P, C.c_int64, _P, C.POINTER(pba_train_config), C.POINTER(pba_train_report)]),
+    "pba_pc_gradient": (C.c_int, [_P, C.c_int32, _P, C.POINTER(C.c_double), _P]),
+    "pba_pc_infer": (C.c_int, [_P, C.c_int32, _P, _P]),
+    "pba_solve_reduced": (C.c_int, [_P, C.c_int32, C.c_double, C.c_int32, _P, C.POINTER(pba_reduced_report)]),
     "pba_destroy": (None, [_P]),
     "pba_last_error": (C.c_char_p, [_P]),
     "pba_status_string": (C.c_char_p, [C.c_int]),
@@ -269,6 +299,51 @@ class Solver:
         rep = pba_tune_report()
         self._chk(pba_autotune(self.ctx, level, reps, C.byref(rep)))
         return rep.as_dict()
+
+    # ---- learned preconditioner and reduced-system solvers
+    def pc_init(self, seed=0):
+        self._chk(pba_pc_init(self.ctx, seed))
+
+    def pc_set_weights(self, w):
+        w = np.ascontiguousarray(w, np.float32)
+        self._chk(pba_pc_set_weights(self.ctx, _ptr(w), w.size))
+
+    def pc_get_weights(self):
+        w = np.zeros(PBA_PC_N_PARAMS, np.float32)
+        self._chk(pba_pc_get_weights(self.ctx, _ptr(w), w.size))
+        return w
+
+    def pc_harvest(self):
+        G = np.zeros((self.F, 21), np.float32)
+        nb = C.c_int32()
+        self._chk(pba_pc_harvest(self.ctx, _ptr(G), G.size, C.byref(nb)))
+        return G[:nb.value]
+
+    def pc_train(self, G, steps=2000, batch=1024, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, seed=0):
+        G = np.ascontiguousarray(G, np.float32).reshape(-1, 21)
+        cfg = pba_train_config(steps, batch, lr, beta1, beta2, eps, seed)
+        rep = pba_train_report()
+        self._chk(pba_pc_train(self.ctx, G.shape[0], _ptr(G), C.byref(cfg), C.byref(rep)))
+        return rep.as_dict()
+
+    def pc_gradient(self, G):
+        G = np.ascontiguousarray(G, np.float32).reshape(-1, 21)
+        loss = C.c_double()
+        grad = np.zeros(PBA_PC_N_PARAMS, np.float32)
+        self._chk(pba_pc_gradient(self.ctx, G.shape[0], _ptr(G), C.byref(loss), _ptr(grad)))
+        return loss.value, grad
+
+    def pc_infer(self, G):
+        G = np.ascontiguousarray(G, np.float32).reshape(-1, 21)
+        Y = np.zeros((G.shape[0], 21), np.float32)
+        self._chk(pba_pc_infer(self.ctx, G.shape[0], _ptr(G), _ptr(Y)))
+        return Y
+
+    def solve_reduced(self, solver, tol=1e-8, max_iters=5000, want_x=True):
+        x = np.zeros(6 * self.F) if want_x else None
+        rep = pba_reduced_report()
+        self._chk(pba_solve_reduced(self.ctx, solver, tol, max_iters, _ptr(x), C.byref(rep)))
+        return rep.as_dict(), x
 
     def timing(self):
         t = pba_timing()

@@ -1,0 +1,178 @@
+"""GPU parity of the learned block preconditioner and PCG on the reduced pose
+system against the FP64 oracle (oracle/learned.py):
+
+* the FP32 training kernels' gradient of the block loss (forward and backward
+  through the 22-256-256-21 network) against the oracle's FP64 gradient;
+* FP16 MFMA inference against the oracle's forward pass;
+* the block couplings, PCG with block Jacobi and with the learned blocks, and
+  the tiled Cholesky solve of S x = -b against the oracle's PCG and dense solve;
+* training on couplings harvested from the method's own reduced systems lowers
+  the block loss below block Jacobi's, and the trained preconditioner's PCG
+  iterations are reported against block Jacobi on a held-out system.
+"""
+import numpy as np
+import pytest
+
+import scenes
+from oracle import learned as LP
+from oracle.gn import GaussNewton, Problem
+
+pytestmark = pytest.mark.gpu
+
+pba = pytest.importorskip("paper_1704_06967_amd.pba")
+
+
+def random_couplings(m, seed, scale=0.5):
+    rng = np.random.default_rng(seed)
+    A = rng.normal(size=(m, 6, 6)) * scale
+    G = A @ np.swapaxes(A, 1, 2)
+    return G
+
+
+def upper(G):
+    return np.stack([G[:, r, c] for r, c in LP.UPPER], axis=1)
+
+
+def full(U):
+    G = np.zeros((U.shape[0], 6, 6))
+    for k, (r, c) in enumerate(LP.UPPER):
+        G[:, r, c] = G[:, c, r] = U[:, k]
+    return G
+
+
+def random_params(seed):
+    rng = np.random.default_rng(seed)
+    p = LP.init_params(seed)
+    p["W3"] = 0.05 * rng.normal(size=p["W3"].shape)
+    p["b3"] = 0.05 * rng.normal(size=21)
+    p["b1"] = 0.05 * rng.normal(size=256)
+    p["b2"] = 0.05 * rng.normal(size=256)
+    return p
+
+
+def solver(**kw):
+    return pba.Solver(mode=pba.PBA_FC, precision=pba.PBA_FP64, **kw)
+
+
+def test_gradient_matches_oracle():
+    p = random_params(1)
+    s = solver()
+    s.pc_set_weights(LP.pack(p).astype(np.float32))
+    pf = LP.unpack(LP.pack(p).astype(np.float32).astype(float))  # the weights as the GPU holds them
+    Gu = upper(random_couplings(512, 2)).astype(np.float32)
+    G = full(Gu.astype(float))
+    loss, grad = s.pc_gradient(Gu)
+    ref_loss, ref = LP.loss_and_grads(pf, LP.features(G), G)
+    assert loss == pytest.approx(ref_loss, rel=1e-5)
+    ref_v = LP.pack(ref)
+    o = 0
+    for name, shape in LP.PARAM_SHAPES:
+        m = int(np.prod(shape))
+        a, b = grad[o:o + m].astype(float), ref_v[o:o + m]
+        assert np.linalg.norm(a - b) <= 1e-4 * np.linalg.norm(b) + 1e-9, name
+        o += m
+
+
+def test_fp16_inference_matches_oracle_forward():
+    p = random_params(3)
+    s = solver()
+    s.pc_set_weights(LP.pack(p).astype(np.float32))
+    Gu = upper(random_couplings(300, 4)).astype(np.float32)
+    Y = s.pc_infer(Gu)
+    ref, _ = LP.mlp_forward(p, LP.features(full(Gu.astype(float))))
+    assert np.linalg.norm(Y - ref) <= 1e-2 * np.linalg.norm(ref)
+
+
+@pytest.fixture(scope="module")
+def mid_system():
+    """FC at level 0 of the mid orbit with 40 frames (6F = 240), FP64: the
+    library's S and b after one iteration, and the oracle's."""
+    sc = scenes.mid(n_per_host=1000, n_frames=40)
+    s = pba.Solver(mode=pba.PBA_FC, precision=pba.PBA_FP64, n_levels=sc.n_levels, pattern=sc.pattern,
+                   huber_k=sc.huber_k)
+    s.set_scene(sc)
+    s.iterate(0, 1)
+    gn = GaussNewton(Problem.from_scene(sc), "fc")
+    gn.iterate(0, 1)
+    return sc, s, gn.last["S"], gn.last["b"]
+
+
+def test_couplings_match_oracle(mid_system):
+    _, s, S, _ = mid_system
+    G = s.pc_harvest()
+    _, _, Gref = LP.block_whitening(S)
+    Ur = upper(Gref)
+    assert np.linalg.norm(G - Ur) <= 1e-5 * np.linalg.norm(Ur)
+
+
+def test_reduced_solvers_match_oracle(mid_system):
+    _, s, S, b = mid_system
+    x_ref = np.linalg.solve(S, -b)
+    rc, xc = s.solve_reduced(pba.PBA_SOLVER_CHOL)
+    assert rc["rel_residual"] <= 1e-10
+    assert np.linalg.norm(xc - x_ref) <= 1e-7 * np.linalg.norm(x_ref)
+    rj, xj = s.solve_reduced(pba.PBA_SOLVER_PCG_JACOBI, tol=1e-8, max_iters=5000)
+    x_o, k_o, _ = LP.pcg(S, -b, LP.jacobi_blocks(S), tol=1e-8)
+    assert rj["converged"] == 1 and rj["fallback"] == 0
+    assert rj["rel_residual"] <= 1e-8
+    assert abs(rj["iters"] - k_o) <= max(2, k_o // 50)
+    # both PCG solutions are within the tolerance's reach of the exact one
+    cond_tol = 1e-8 * np.linalg.cond(S)
+    assert np.linalg.norm(xj - x_ref) <= max(cond_tol, 1e-6) * np.linalg.norm(x_ref)
+    # a learned preconditioner with a zero output layer is block Jacobi: same iterations
+    s.pc_init(5)
+    rl, xl = s.solve_reduced(pba.PBA_SOLVER_PCG_LEARNED, tol=1e-8, max_iters=5000)
+    assert rl["iters"] == rj["iters"]
+    np.testing.assert_allclose(xl, xj, rtol=1e-12, atol=1e-14 * np.abs(xj).max())
+    # learned blocks from given weights: the same iterations as the oracle's PCG with them
+    p = random_params(6)
+    p["W3"] *= 0.2
+    p["b3"] *= 0.2
+    s.pc_set_weights(LP.pack(p).astype(np.float32))
+    rl2, xl2 = s.solve_reduced(pba.PBA_SOLVER_PCG_LEARNED, tol=1e-8, max_iters=5000)
+    _, k_l, _ = LP.pcg(S, -b, LP.learned_blocks(LP.unpack(LP.pack(p).astype(np.float32).astype(float)), S),
+                      tol=1e-8)
+    assert rl2["converged"] == 1 and rl2["rel_residual"] <= 1e-8
+    assert abs(rl2["iters"] - k_l) <= max(3, k_l // 20)   # FP16 inference vs FP64 forward
+    # too few iterations: Cholesky fallback, still the exact solution
+    rf, xf = s.solve_reduced(pba.PBA_SOLVER_PCG_JACOBI, tol=1e-8, max_iters=3)
+    assert rf["fallback"] == 1 and rf["rel_residual"] <= 1e-10
+
+
+@pytest.mark.timeout(600)
+def test_training_gains_over_block_jacobi():
+    """Couplings harvested from FC iterations of the method (mid orbit, several
+    starts) train the network on the GPU; its loss falls below block Jacobi's on
+    the training set and on a held-out system, and its PCG iterations there are
+    reported against block Jacobi's."""
+    sc = scenes.mid(n_per_host=600, n_frames=40)
+    s = pba.Solver(mode=pba.PBA_FC, precision=pba.PBA_FP32, n_levels=sc.n_levels, pattern=sc.pattern,
+                   huber_k=sc.huber_k)
+    s.set_scene(sc)
+    rng = np.random.default_rng(7)
+    Gs = []
+    for start in range(6):
+        P = sc.poses_init.copy()
+        P[1:, 9:] += 1e-3 * rng.normal(size=P[1:, 9:].shape)
+        s.set_params(P, sc.inv_depth_init)
+        for level in (2, 1, 0):
+            for _ in range(3):
+                s.iterate(level, 1)
+                Gs.append(s.pc_harvest())
+    G = np.concatenate(Gs)
+    held = Gs[-1]
+    s.pc_init(11)
+    rep = s.pc_train(np.concatenate(Gs[:-1]), steps=400, batch=512, lr=1e-3, seed=3)
+    assert rep["trained_loss"] < rep["jacobi_loss"]
+    assert rep["final_loss"] < rep["first_loss"]
+    # held-out system: the last harvested one
+    w = s.pc_get_weights().astype(float)
+    Y, _ = LP.mlp_forward(LP.unpack(w), LP.features(full(held.astype(float))))
+    l_net, _ = LP.block_loss(Y, full(held.astype(float)))
+    assert l_net.mean() < np.trace(full(held.astype(float)), axis1=1, axis2=2).mean()
+    rj, _ = s.solve_reduced(pba.PBA_SOLVER_PCG_JACOBI, tol=1e-8, max_iters=5000)
+    rl, _ = s.solve_reduced(pba.PBA_SOLVER_PCG_LEARNED, tol=1e-8, max_iters=5000)
+    assert rj["converged"] == 1 and rl["converged"] == 1
+    print(f"\nheld-out PCG iterations: block Jacobi {rj['iters']}, learned {rl['iters']}; "
+          f"loss {rep['jacobi_loss']:.4g} -> {rep['trained_loss']:.4g} on {G.shape[0]} blocks")
+    assert rl["iters"] <= rj["iters"] * 1.1
