@@ -209,7 +209,7 @@ def precision_section(pba, steps, max_iters, conv_px):
     out["ic_mixed_rmse_rel_vs_fp64"] = abs(out["ic_mixed"]["final_rmse"] / out["ic_fp64"]["final_rmse"] - 1)
     out["note"] = ("errors of the mixed-form IC solve against the FP64 IC solve of the same problem (same "
                    "iteration counts); the FP64 path equals the FP64 oracle to rounding in the parity tests")
-    return out
+    return out, sc
 
 
 def make_windows(n, workers):
@@ -287,6 +287,77 @@ def batched_section(pba, wins, steps, iters):
     return out
 
 
+def learned_section(pba, train_scenes, sc, n_systems, steps):
+    """The learned form: the network is trained on the GPU on block couplings
+    of n_systems reduced systems produced by FC iterations of the method on
+    the tiny, mid and precision workloads (restarted from seeded perturbations
+    of their starts), then PCG with the learned blocks, PCG with block Jacobi
+    and the tiled Cholesky solve the 1800 x 1800 reduced system of the learned
+    workload (300 frames, 30 hosts x 30000 points) to a relative residual of
+    1e-8. The three solutions agree to that residual, so a Gauss-Newton step
+    taken with any of them (and the photometric RMSE it reaches) is the same."""
+    out = {"workload": "learned: 300 frames 640x480 f32, 3 spheres + box, 30 hosts x 30000 points, 3-level "
+                       "pyramid; reduced system 1800 x 1800 FP64 at the start of level 0 (FC linearization)",
+           "points": sc.n_points, "observations": sc.n_obs, "reduced_system": 6 * sc.n_frames}
+    rng = np.random.default_rng(5)
+    Gs, sizes = [], []
+    t0 = time.perf_counter()
+    per = [max(1, n_systems // 10), (n_systems * 7) // 10, n_systems - max(1, n_systems // 10) - (n_systems * 7) // 10]
+    for tsc, count in zip(train_scenes, per):
+        s = pba.Solver(mode=pba.PBA_FC, precision=pba.PBA_FP32, n_levels=tsc.n_levels, pattern=tsc.pattern,
+                       huber_k=tsc.huber_k)
+        s.set_scene(tsc)
+        got = 0
+        while got < count:
+            P = tsc.poses_init.copy()
+            P[1:, 9:] += 2e-3 * np.abs(tsc.poses_init[1:, 9:]).mean() * rng.normal(size=P[1:, 9:].shape)
+            s.set_params(P, tsc.inv_depth_init * (1.0 + 1e-3 * rng.normal(size=tsc.n_points)))
+            try:
+                for level in reversed(range(tsc.n_levels)):
+                    for _ in range(4):
+                        if got >= count:
+                            break
+                        s.iterate(level, 1)
+                        Gs.append(s.pc_harvest())
+                        got += 1
+            except pba.PbaError:  # a start whose reduced system lost definiteness: take the next start
+                continue
+        sizes.append(got)
+        s.close()
+    G = np.concatenate(Gs)
+    out["training"] = {"systems": int(sum(sizes)), "systems_per_workload": {"tiny": sizes[0], "mid": sizes[1],
+                                                                               "precision": sizes[2]},
+                       "blocks": int(G.shape[0]), "harvest_s": round(time.perf_counter() - t0, 2)}
+    kw = dict(mode=pba.PBA_FC, precision=pba.PBA_FP64, n_levels=sc.n_levels, pattern=sc.pattern, huber_k=sc.huber_k)
+    s = pba.Solver(**kw)
+    s.set_scene(sc)
+    s.pc_init(1)
+    rep = s.pc_train(G, steps=steps, batch=1024, lr=1e-3, seed=2)
+    out["training"].update({k: rep[k] for k in ("steps", "samples", "first_loss", "final_loss", "jacobi_loss",
+                                                 "trained_loss", "ms")})
+    s.iterate(0, 1)  # assembles S and b at level 0 (FC linearization at the start)
+    res = {}
+    xs = {}
+    for name, solver in (("cholesky", pba.PBA_SOLVER_CHOL), ("pcg_block_jacobi", pba.PBA_SOLVER_PCG_JACOBI),
+                         ("pcg_learned", pba.PBA_SOLVER_PCG_LEARNED)):
+        s.solve_reduced(solver, 1e-8, 20000, want_x=False)  # warm-up
+        reps = [s.solve_reduced(solver, 1e-8, 20000, want_x=True) for _ in range(3)]
+        r, x = reps[-1]
+        res[name] = {"iters": r["iters"], "rel_residual": r["rel_residual"], "fallback": r["fallback"],
+                     "ms": round(float(np.median([q[0]["ms"] for q in reps])), 4),
+                     "ms_setup": round(float(np.median([q[0]["ms_setup"] for q in reps])), 4)}
+        xs[name] = x
+    xc = xs["cholesky"]
+    for name in ("pcg_block_jacobi", "pcg_learned"):
+        res[name]["rel_error_vs_cholesky"] = float(np.linalg.norm(xs[name] - xc) / np.linalg.norm(xc))
+    out["solvers"] = res
+    out["learned_vs_block_jacobi_iters"] = round(res["pcg_block_jacobi"]["iters"] / max(1, res["pcg_learned"]["iters"]),
+                                                 3)
+    out["learned_pcg_vs_cholesky_time"] = round(res["cholesky"]["ms"] / res["pcg_learned"]["ms"], 3)
+    s.close()
+    return out
+
+
 def calibrate_copy(nbytes):
     """A device-to-device copy of nbytes (the runtime's copy kernel), so that the
     HBM counters of a profiling run can be scaled by a transfer of known size."""
@@ -318,6 +389,9 @@ def main():
     ap.add_argument("--no-precision", action="store_true", help="skip the precision-workload section")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-windows section")
     ap.add_argument("--windows", type=int, default=64, help="windows of the batched section")
+    ap.add_argument("--no-learned", action="store_true", help="skip the learned-preconditioner section")
+    ap.add_argument("--train-systems", type=int, default=2000, help="reduced systems harvested for training")
+    ap.add_argument("--train-steps", type=int, default=2000, help="optimizer steps of the network")
     ap.add_argument("--workers", type=int, default=min(16, os.cpu_count() or 1),
                     help="processes that build the batched windows")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
@@ -335,6 +409,11 @@ def main():
         t0 = time.perf_counter()
         wins = make_windows(args.windows, args.workers)
         log(f"{len(wins)} windows built ({time.perf_counter() - t0:.1f} s)")
+    learned_scene = None
+    if not args.no_learned:
+        t0 = time.perf_counter()
+        learned_scene = scenes.learned()
+        log(f"scene learned: {learned_scene.n_points} points ({time.perf_counter() - t0:.1f} s)")
     from paper_1704_06967_amd import pba
 
     if args.calibrate_copy:
@@ -427,8 +506,15 @@ def main():
         line["equal_rmse"] = {"r_star": r_star, "ic_ms": round(t_ic * 1e3, 3), "fc_ms": round(t_fc * 1e3, 3),
                               "ic_speedup": round(t_fc / t_ic, 3) if t_ic > 0 and math.isfinite(t_fc) else None,
                               "note": "per-iteration synchronous calls; level-0 RMSE after each iteration"}
+    precision_scene = None
     if not args.no_precision:
-        line["precision_form"] = precision_section(pba, max(1, min(args.steps, 5)), args.max_iters, args.conv_px)
+        line["precision_form"], precision_scene = precision_section(pba, max(1, min(args.steps, 5)), args.max_iters,
+                                                                    args.conv_px)
+    if learned_scene is not None:
+        t0 = time.perf_counter()
+        train = [scenes.tiny(), scene, scenes.precision() if args.no_precision else precision_scene]
+        line["learned_form"] = learned_section(pba, train, learned_scene, args.train_systems, args.train_steps)
+        log(f"learned: {time.perf_counter() - t0:.1f} s")
     if wins is not None:
         line["batched_form"] = batched_section(pba, wins, max(3, min(args.steps, 20)), 5)
         log(f"batched: {line['batched_form']['ms_per_batch']} ms per batch of {len(wins)} windows")
