@@ -212,9 +212,15 @@ def precision_section(pba, steps, max_iters, conv_px):
     return out, sc
 
 
+def _one_thread():
+    from threadpoolctl import threadpool_limits
+
+    threadpool_limits(1)
+
+
 def make_windows(n, workers):
     """The batched workload's windows (seeds 0..n-1), built in worker processes
-    before this process touches the GPU."""
+    (one BLAS thread each) before this process touches the GPU."""
     import concurrent.futures as cf
     import multiprocessing as mp
 
@@ -222,7 +228,8 @@ def make_windows(n, workers):
 
     if workers <= 1:
         return [scenes.window(i) for i in range(n)]
-    with cf.ProcessPoolExecutor(max_workers=workers, mp_context=mp.get_context("fork")) as ex:
+    with cf.ProcessPoolExecutor(max_workers=workers, mp_context=mp.get_context("fork"),
+                                initializer=_one_thread) as ex:
         return list(ex.map(scenes.window, range(n)))
 
 
@@ -392,7 +399,7 @@ def main():
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-preconditioner section")
     ap.add_argument("--train-systems", type=int, default=2000, help="reduced systems harvested for training")
     ap.add_argument("--train-steps", type=int, default=2000, help="optimizer steps of the network")
-    ap.add_argument("--workers", type=int, default=min(16, os.cpu_count() or 1),
+    ap.add_argument("--workers", type=int, default=min(16, len(os.sched_getaffinity(0))),
                     help="processes that build the batched windows")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
                     help="also run device copies of BYTES (scale for profiler byte counters)")
@@ -422,29 +429,34 @@ def main():
     scene = scenes.mid()
     log(f"scene mid: {scene.n_points} points, {scene.n_obs} observations, {scene.n_residuals()} residuals "
         f"({time.perf_counter() - t0:.1f} s)")
-    kw = dict(precision=pba.PBA_FP32, n_levels=scene.n_levels, pattern=scene.pattern, huber_k=scene.huber_k,
-              flags=pba.PBA_FLAG_TIMING)
-    ic = pba.Solver(mode=pba.PBA_IC_PROXY, **kw)
-    fc = pba.Solver(mode=pba.PBA_FC, **kw)
-    ic.set_scene(scene)
-    fc.set_scene(scene)
+    kw = dict(precision=pba.PBA_FP32, n_levels=scene.n_levels, pattern=scene.pattern, huber_k=scene.huber_k)
+    # the timed solves run as captured graphs (one launch per solve); twin
+    # contexts without graphs time the residual kernels with HIP events
+    ic = pba.Solver(mode=pba.PBA_IC_PROXY, flags=pba.PBA_FLAG_GRAPH, **kw)
+    fc = pba.Solver(mode=pba.PBA_FC, flags=pba.PBA_FLAG_GRAPH, **kw)
+    ic_ev = pba.Solver(mode=pba.PBA_IC_PROXY, flags=pba.PBA_FLAG_TIMING, **kw)
+    fc_ev = pba.Solver(mode=pba.PBA_FC, flags=pba.PBA_FLAG_TIMING, **kw)
+    for s in (ic, fc, ic_ev, fc_ev):
+        s.set_scene(scene)
     p0, d0 = scene.poses_init, scene.inv_depth_init
 
     for _ in range(args.warmup):
-        for s in (ic, fc):
+        for s in (ic, fc, ic_ev, fc_ev):
             s.set_params(p0, d0)
             s.solve(args.max_iters, args.conv_px)
-    ic.timing()
-    fc.timing()
+    ic_ev.timing()
+    fc_ev.timing()
     log("warmup done")
 
     ic_t, ic_iters, ic_active, ic_res = run_steps(ic, p0, d0, args.steps, args.max_iters, args.conv_px)
-    ic_tm = ic.timing()
     log(f"IC: {args.steps} solves, {np.mean(ic_t) * 1e3:.3f} ms each")
     fc_steps = args.fc_steps or args.steps
     fc_t, fc_iters, fc_active, fc_res = run_steps(fc, p0, d0, fc_steps, args.max_iters, args.conv_px)
-    fc_tm = fc.timing()
     log(f"FC: {fc_steps} solves, {np.mean(fc_t) * 1e3:.3f} ms each")
+    run_steps(ic_ev, p0, d0, args.steps, args.max_iters, args.conv_px)
+    ic_tm = ic_ev.timing()
+    run_steps(fc_ev, p0, d0, fc_steps, args.max_iters, args.conv_px)
+    fc_tm = fc_ev.timing()
 
     total = float(np.sum(ic_t))
     value = ic_iters / total
@@ -521,8 +533,8 @@ def main():
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
         line["cpu_baseline"] = cpu_baseline(scene)
-    ic.close()
-    fc.close()
+    for s in (ic, fc, ic_ev, fc_ev):
+        s.close()
     print(json.dumps(line), flush=True)
 
 

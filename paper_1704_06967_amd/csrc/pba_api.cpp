@@ -484,7 +484,7 @@ pba_status do_start_level(Ctx &c, int level) {
 // each with the device convergence gate) enqueued without host synchronization;
 // with PBA_FLAG_GRAPH it is captured once as a HIP graph and replayed. Level l's
 // statistics go to d_stats[(n_levels - 1 - l) * max_iters + k].
-pba_status enqueue_solve(Ctx &c, int max_iters, double conv_px) {
+pba_status enqueue_solve(Ctx &c, int max_iters, double conv_px, bool events) {
     for (int level = c.cfg.n_levels - 1; level >= 0; --level) {
         // a failure at a coarser level keeps the gate closed for the rest
         launch_open(c.stream, c, level, level == c.cfg.n_levels - 1);
@@ -492,9 +492,11 @@ pba_status enqueue_solve(Ctx &c, int max_iters, double conv_px) {
         if (st != PBA_OK) return st;
         const int slot = c.cfg.n_levels - 1 - level;
         for (int k = 0; k < max_iters; ++k) {
-            double *stat = c.d_stats + ((size_t)slot * max_iters + k) * ST_STRIDE;
-            st = is_fp64(c) ? one_iteration<double>(c, level, stat, nullptr, nullptr, conv_px)
-                            : one_iteration<float>(c, level, stat, nullptr, nullptr, conv_px);
+            const size_t idx = (size_t)slot * max_iters + k;
+            double *stat = c.d_stats + idx * ST_STRIDE;
+            hipEvent_t e0 = events ? c.ev_pool[2 * idx] : nullptr, e1 = events ? c.ev_pool[2 * idx + 1] : nullptr;
+            st = is_fp64(c) ? one_iteration<double>(c, level, stat, e0, e1, conv_px)
+                            : one_iteration<float>(c, level, stat, e0, e1, conv_px);
             if (st != PBA_OK) return st;
         }
     }
@@ -505,6 +507,9 @@ pba_status solve_batch(Ctx &c, int max_iters, double conv_px, pba_result &res) {
     pba_status st;
     const int L = c.cfg.n_levels;
     if ((st = ensure_stats(c, L * max_iters)) != PBA_OK) return st;
+    // residual-kernel timing with HIP events (not inside a captured graph)
+    const bool timing = (c.cfg.flags & PBA_FLAG_TIMING) && !(c.cfg.flags & PBA_FLAG_GRAPH);
+    if (timing && (st = ensure_events(c, 2 * (size_t)L * max_iters)) != PBA_OK) return st;
     // templates of every level first (they depend on the points only)
     for (int level = 0; level < L; ++level)
         if (!c.lv[level].tmpl_valid) {
@@ -519,7 +524,7 @@ pba_status solve_batch(Ctx &c, int max_iters, double conv_px, pba_result &res) {
             drop_graph(c);
             hipGraph_t g = nullptr;
             HIPCHK(hipStreamBeginCapture(c.stream, hipStreamCaptureModeThreadLocal));
-            st = enqueue_solve(c, max_iters, conv_px);
+            st = enqueue_solve(c, max_iters, conv_px, false);
             hipError_t e = hipStreamEndCapture(c.stream, &g);
             if (st != PBA_OK) {
                 if (g) (void)hipGraphDestroy(g);
@@ -533,7 +538,7 @@ pba_status solve_batch(Ctx &c, int max_iters, double conv_px, pba_result &res) {
             c.graph_conv = conv_px;
         }
         HIPCHK(hipGraphLaunch(c.solve_graph, c.stream));
-    } else if ((st = enqueue_solve(c, max_iters, conv_px)) != PBA_OK) {
+    } else if ((st = enqueue_solve(c, max_iters, conv_px, timing)) != PBA_OK) {
         return st;
     }
     std::vector<double> hs((size_t)L * max_iters * ST_STRIDE);
@@ -544,6 +549,17 @@ pba_status solve_batch(Ctx &c, int max_iters, double conv_px, pba_result &res) {
     HIPCHK(hipStreamSynchronize(c.stream));
     HIPCHK(hipGetLastError());
     std::vector<pba_iter_stats> its(max_iters);
+    if (timing) {
+        for (int level = L - 1; level >= 0; --level)
+            for (int k = 0; k < counts[level]; ++k) {
+                const size_t idx = (size_t)(L - 1 - level) * max_iters + k;
+                float ms = 0.f;
+                HIPCHK(hipEventElapsedTime(&ms, c.ev_pool[2 * idx], c.ev_pool[2 * idx + 1]));
+                c.t_ms[level] += ms;
+                c.t_launches[level]++;
+                c.t_res[level] += (int64_t)c.O * LANES_PER_OBS;
+            }
+    }
     for (int level = L - 1; level >= 0; --level) {
         const int k = counts[level];
         fill_stats(hs.data() + (size_t)(L - 1 - level) * max_iters * ST_STRIDE, level, 0, k, its.data());
