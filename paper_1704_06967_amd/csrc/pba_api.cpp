@@ -366,7 +366,7 @@ pba_status one_iteration(Ctx &c, int level, double *stat, hipEvent_t ev0, hipEve
         launch_mu(s, c, geo_cur);
         launch_gram(s, c, geo_cur, c.d_rec, is_fp64(c));
         launch_assemble_s(s, c, geo_cur);
-        if (c.nwin == 1 && 6 * c.F > LDS_CHOL_MAX_N) launch_tchol(s, c);
+        if (c.tiled()) launch_tchol(s, c);
         Launch<T>::pair_reduce_y(s, c);
         launch_solve(s, c, geo_cur, geo_next, rel_next, is_fp64(c), stat);
     }
@@ -651,7 +651,7 @@ pba_status load_frames(Ctx &c, int n_frames, int width, int height, const float 
         HIPCHK(dalloc(c.d_Sinv, nS * sizeof(double)));
         HIPCHK(dalloc(c.d_Lfac, nL * sizeof(double)));
     }
-    if (c.nwin == 1 && n6 > (size_t)LDS_CHOL_MAX_N) {
+    if (c.tiled()) {
         const size_t nt = (n6 + TCHOL_TILE - 1) / TCHOL_TILE;
         HIPCHK(dalloc(c.d_Sfac, n6 * n6 * sizeof(double)));
         HIPCHK(dalloc(c.d_Linv, nt * TCHOL_TILE * TCHOL_TILE * sizeof(double)));
@@ -1133,7 +1133,10 @@ pba_status pba_evaluate(pba_ctx *ctx, int32_t level, pba_iter_stats *out) {
     hipStream_t s = c.stream;
     // relative poses at the current parameters go to the buffer the next iteration reads
     double *geo = c.flip ? c.d_geo_b : c.d_geo_a;
-    if (!c.d_eval) HIPCHK(dalloc(c.d_eval, 3 * sizeof(double)));
+    if (c.eval_cap < sum_stats_doubles(c)) {
+        HIPCHK(dalloc(c.d_eval, sum_stats_doubles(c) * sizeof(double)));
+        c.eval_cap = sum_stats_doubles(c);
+    }
     if (is_fp64(c)) {
         if (!c.lv[level].tmpl_valid) Launch<double>::make_template(s, c, level);
         Launch<double>::relpose(s, c, c.d_poses, geo, (double *)(c.flip ? c.d_rel_b : c.d_rel_a));

@@ -46,59 +46,80 @@ __device__ __forceinline__ f64x4 quad_xyT(const double *X, const double *Y, int 
     return acc;
 }
 
+// Value of v in lane l (uniform l), as a scalar read of the register.
+__device__ __forceinline__ double readlane_d(double v, int l) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)b, l);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
 // Factor the LDS tile t = L L^T in place (rows and columns >= nb are made the
 // identity first), and write L^{-1} (identity on the padding) to Linv_g.
-// Called by a whole 256-thread block; wavefront 0 does the sequential work.
-// Returns false in every thread when a pivot is not positive.
-__device__ bool tile_potrf_inv(double *t, int nb, double *__restrict__ Linv_g, double *invd, int *fail) {
+// Called by a whole 256-thread block; wavefront 0 does the work with the tile
+// in registers (lane r holds row r): each column step reads the pivot and the
+// column's entries of the other rows with scalar lane reads, so the 32 steps
+// need no LDS round trips or barriers. Lane c then forms column c of L^{-1} by
+// forward substitution. Returns false in every thread when a pivot is not
+// positive.
+__device__ __forceinline__ bool tile_potrf_inv(double *t, int nb, double *__restrict__ Linv_g, double *invd, int *fail) {
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    for (int e = threadIdx.x; e < TB * TB; e += blockDim.x) {
-        const int r = e / TB, c = e % TB;
-        if (r >= nb || c >= nb) tl(t, r, c) = (r == c) ? 1.0 : 0.0;
-    }
     if (threadIdx.x == 0) *fail = 0;
     __syncthreads();
     if (wv == 0) {
+        double row[TB];
+#pragma unroll
+        for (int c = 0; c < TB; ++c) {
+            double v = 0.0;
+            if (lane < TB) v = (lane < nb && c < nb) ? tl(t, lane, c) : (lane == c ? 1.0 : 0.0);
+            row[c] = v;
+        }
+        bool ok = true;
+#pragma unroll
         for (int j = 0; j < TB; ++j) {
-            const double p = tl(t, j, j);
-            if (!(p > 0.0)) {
-                if (lane == 0) *fail = 1;
-                break;
+            const double p = readlane_d(row[j], j);
+            ok = ok && p > 0.0;
+            const double l = sqrt(p > 0.0 ? p : 1.0), inv = 1.0 / l;
+            const double a = lane > j ? row[j] * inv : (lane == j ? l : row[j]);
+            row[j] = a;
+#pragma unroll
+            for (int c = j + 1; c < TB; ++c) {
+                const double ac = readlane_d(a, c);
+                if (lane >= c && lane < TB) row[c] -= a * ac;
             }
-            const double l = sqrt(p), inv = 1.0 / l;
-            double a = 0.0;
-            if (lane > j && lane < TB) {
-                a = tl(t, lane, j) * inv;
-                tl(t, lane, j) = a;
-            }
-            if (lane == j) {
-                tl(t, j, j) = l;
-                invd[j] = inv;
+        }
+        if (!ok) {
+            if (lane == 0) *fail = 1;
+        } else {
+            if (lane < TB) {
+#pragma unroll
+                for (int c = 0; c < TB; ++c) tl(t, lane, c) = c <= lane ? row[c] : 0.0;
             }
             __builtin_amdgcn_wave_barrier();
-            if (lane > j && lane < TB)
-                for (int c = j + 1; c <= lane; ++c) tl(t, lane, c) -= a * tl(t, c, j);
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            if (lane < TB) invd[lane] = 1.0 / tl(t, lane, lane);
             __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            // column `lane` of L^{-1}: x[i] = (delta_i,lane - sum_k<i L(i, k) x[k]) / L(i, i)
+            // (every lane reads the same L(i, k): LDS broadcasts)
+            double x[TB];
+#pragma unroll
+            for (int i = 0; i < TB; ++i) {
+                double s = (i == lane) ? 1.0 : 0.0;
+#pragma unroll
+                for (int k = 0; k < i; ++k) s -= tl(t, i, k) * x[k];
+                x[i] = (i >= lane) ? s * invd[i] : 0.0;
+            }
+            if (lane < TB) {
+#pragma unroll
+                for (int i = 0; i < TB; ++i) Linv_g[i * TB + lane] = x[i];
+            }
         }
     }
     __syncthreads();
-    if (*fail) return false;
-    if (wv == 0 && lane < TB) {
-        // column `lane` of L^{-1} by forward substitution (x[i] = 0 above the diagonal)
-        const int c = lane;
-        double x[TB];
-#pragma unroll
-        for (int i = 0; i < TB; ++i) {
-            double s = (i == c) ? 1.0 : 0.0;
-#pragma unroll
-            for (int k = 0; k < i; ++k) s -= tl(t, i, k) * x[k];
-            x[i] = (i >= c) ? s * invd[i] : 0.0;
-        }
-#pragma unroll
-        for (int i = 0; i < TB; ++i) Linv_g[i * TB + c] = x[i];
-    }
-    __syncthreads();
-    return true;
+    return *fail == 0;
 }
 
 __device__ __forceinline__ void chol_fail(int *flag, int *gate) {

@@ -41,6 +41,7 @@ constexpr int BLOCK = 256;         // threads per block for residual kernels
 constexpr int MAX_HOST_TARGETS = 20;  // target frames per host frame (Schur Gram size)
 constexpr int PAIR_CHUNK = 512;       // observations per pair-reduction workgroup
 constexpr int LDS_CHOL_MAX_N = 180;   // largest reduced system factored in one workgroup's LDS
+constexpr int TILED_MIN_N = 96;       // one-window systems from this size on use the tiled multi-workgroup path
 constexpr int TCHOL_TILE = 32;        // tile edge of the tiled Cholesky for larger systems
 
 // Independent problems (windows) held by one context: frames, points and pairs
@@ -180,7 +181,7 @@ struct Ctx {
     double *d_S = nullptr;                             // [6F][6F] reduced system / factor
     double *d_Sinv = nullptr;                          // IC: S^{-1} at p(0) [6F][6F]
     double *d_Lfac = nullptr;                          // IC: packed Cholesky factor of S, then 1 / L(k, k)
-    double *d_Sfac = nullptr;                          // 6F > LDS_CHOL_MAX_N: tiled factor of S [6F][6F]
+    double *d_Sfac = nullptr;                          // tiled path: factor of S [6F][6F]
     double *d_Linv = nullptr;                          // inverses of its diagonal tiles [nt][32][32]
     double *d_b = nullptr, *d_dtheta = nullptr;        // [6F]
     double *d_dth_rel = nullptr;                       // [Pn][6]
@@ -197,6 +198,7 @@ struct Ctx {
     // learned preconditioner and PCG
     PcState pc;
     bool s_valid = false;                              // d_S / d_b hold an assembled system
+    bool tiled() const { return nwin == 1 && 6 * F >= TILED_MIN_N; }  // tiled Cholesky path (else one-workgroup LDS)
 
     // launch shapes of the per-iteration residual kernels (autotuned)
     int n_cu = 256;
@@ -206,7 +208,8 @@ struct Ctx {
     hipGraphExec_t solve_graph = nullptr;
     int graph_iters = -1;
     double graph_conv = -1.0;
-    double *d_eval = nullptr;                          // [3] sums of the evaluation kernel
+    double *d_eval = nullptr;                          // sums of the evaluation kernel and their block partials
+    size_t eval_cap = 0;
 
     // timing
     std::vector<hipEvent_t> ev_pool;
@@ -260,6 +263,7 @@ void launch_ic_factor(hipStream_t s, Ctx &c);
 void launch_solve(hipStream_t s, Ctx &c, const double *geo_lin, double *geo_next, void *rel_next,
                   bool rel_double, double *stat);
 void launch_sum_stats(hipStream_t s, Ctx &c, const void *rec, bool rec_double, double *out3);
+size_t sum_stats_doubles(const Ctx &c);  // size of out3 (the sums and the block partials)
 void launch_conv(hipStream_t s, Ctx &c, double *stat, double conv_px, int nparts, int level);
 // count[level] = 0, optionally flag = 0, then gate = (flag == 0)
 void launch_open(hipStream_t s, Ctx &c, int level, bool clear_flag);

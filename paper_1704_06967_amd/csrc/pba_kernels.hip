@@ -543,12 +543,16 @@ __global__ __launch_bounds__(256) void k_pair_chunk_y(const int *__restrict__ ch
         for (int k = 0; k < 9; ++k) partY[9 * c + k] = v[k];
 }
 
-// Sum of the record statistics over all observations (single block).
+// Sums of the record statistics (energy, squared residuals, count): block
+// partials over SUM_OBS observations each, then one block adds them in order.
+constexpr int SUM_OBS = 2048;
+
 template <typename T>
-__global__ __launch_bounds__(1024) void k_sum_stats(int O, const T *__restrict__ rec, double *__restrict__ out) {
+__global__ __launch_bounds__(256) void k_sum_stats(int O, const T *__restrict__ rec, double *__restrict__ part) {
     __shared__ double lds[3 * 16];
     double v[3] = {0.0, 0.0, 0.0};
-    for (int o = threadIdx.x; o < O; o += blockDim.x) {
+    const int o1 = min(O, (blockIdx.x + 1) * SUM_OBS);
+    for (int o = blockIdx.x * SUM_OBS + threadIdx.x; o < o1; o += blockDim.x) {
         const T *r = rec + (size_t)o * REC_STRIDE;
         v[0] += (double)r[REC_E];
         v[1] += (double)r[REC_SQ];
@@ -556,16 +560,16 @@ __global__ __launch_bounds__(1024) void k_sum_stats(int O, const T *__restrict__
     }
     block_sum<3>(v, lds);
     if (threadIdx.x == 0)
-        for (int k = 0; k < 3; ++k) out[k] = v[k];
+        for (int k = 0; k < 3; ++k) part[3 * blockIdx.x + k] = v[k];
 }
 
-// ------------------------------------------------------------ depth update
+__global__ void k_sum_parts3(int np, const double *__restrict__ part, double *__restrict__ out) {
+    if (threadIdx.x >= 3) return;
+    double s = 0.0;
+    for (int b = 0; b < np; ++b) s += part[3 * b + threadIdx.x];
+    out[threadIdx.x] = s;
+}
 
-// Back-substitution of the depths, dd_n = -(g_d,n + h_n^T dtheta) / H_dd,n, the
-// depth update (IC: d_{k+1} = d_k (d0 - dd) / d0, Sec. 3.6; FC: d + dd), and
-// the largest level-0 displacement of any observation's point centre. A block
-// holds 32 points with 8 observation slots each and writes its maxima to
-// part[block] (reduced by k_conv).
 constexpr int DU_PTS = 32, DU_SLOTS = 8;
 
 template <typename T>
@@ -922,12 +926,17 @@ void launch_open(hipStream_t s, Ctx &c, int level, bool clear_flag) {
 }
 
 void launch_sum_stats(hipStream_t s, Ctx &c, const void *rec, bool rec_double, double *out3) {
+    // out3 has room for the block partials after the three sums (see sum_stats_doubles)
+    const int np = (c.O + SUM_OBS - 1) / SUM_OBS;
     if (rec_double)
-        k_sum_stats<double><<<1, 1024, 0, s>>>(c.O, (const double *)rec, out3);
+        k_sum_stats<double><<<np, 256, 0, s>>>(c.O, (const double *)rec, out3 + 3);
     else
-        k_sum_stats<float><<<1, 1024, 0, s>>>(c.O, (const float *)rec, out3);
+        k_sum_stats<float><<<np, 256, 0, s>>>(c.O, (const float *)rec, out3 + 3);
+    k_sum_parts3<<<1, 64, 0, s>>>(np, out3 + 3, out3);
     CHECK_LAUNCH();
 }
+
+size_t sum_stats_doubles(const Ctx &c) { return 3 + 3 * (size_t)((c.O + SUM_OBS - 1) / SUM_OBS); }
 
 template struct Launch<float>;
 template struct Launch<double>;

@@ -432,7 +432,7 @@ __global__ __launch_bounds__(SOLVE_THREADS) void k_ic_inverse(WinArgs wa, const 
 }
 
 void launch_ic_inverse(hipStream_t s, Ctx &c) {
-    if (c.nwin == 1 && 6 * c.F > LDS_MAX_N) {
+    if (c.tiled()) {
         launch_tinv(s, c);
         return;
     }
@@ -455,7 +455,7 @@ void launch_ic_inverse(hipStream_t s, Ctx &c) {
 // to wstat[w]; the convergence kernel adds them over the windows.
 template <typename T>
 __global__ __launch_bounds__(SOLVE_THREADS) void k_solve(
-    WinArgs wa, int ic, int pinned, const int *__restrict__ frame_pair_ptr, const int *__restrict__ frame_pair_item,
+    WinArgs wa, int ic, int tiled, int pinned, const int *__restrict__ frame_pair_ptr, const int *__restrict__ frame_pair_item,
     const int *__restrict__ pair_host, const int *__restrict__ pair_target, const int *__restrict__ pair_chunk_ptr,
     const double *__restrict__ partY, double *__restrict__ pairY, const double *__restrict__ geo_lin,
     const double *__restrict__ S_all, const double *__restrict__ Sfac, const double *__restrict__ Linv,
@@ -480,7 +480,7 @@ __global__ __launch_bounds__(SOLVE_THREADS) void k_solve(
     double *b_out = b_all + 6 * f0;
     double *dth_out = dth_all + 6 * f0;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
-    const bool packed = n <= LDS_MAX_N;
+    const bool packed = !tiled;
     // rhs / solution in LDS (FC: after the packed factor; the panel scratch follows)
     double *bx = lds + ((packed && !ic) ? n * (n + 1) / 2 : 0);
     for (int e = threadIdx.x; e < (p1 - p0) * 9; e += blockDim.x) {
@@ -566,7 +566,7 @@ __global__ __launch_bounds__(SOLVE_THREADS) void k_solve(
             }
         }
     } else {
-        // FC, one window with 6F > LDS_MAX_N: S was factored in tiles before this kernel
+        // FC, one window on the tiled path: S was factored in tiles before this kernel
         tile_chol_solve<SOLVE_THREADS>(Sfac, Linv, n, bx, lds + n, 0);
         for (int i = threadIdx.x; i < n; i += blockDim.x) dth_out[i] = -bx[i];
     }
@@ -672,7 +672,7 @@ void launch_assemble_s(hipStream_t s, Ctx &c, const double *geo) {
 }
 
 void launch_ic_factor(hipStream_t s, Ctx &c) {
-    if (c.nwin == 1 && 6 * c.F > LDS_MAX_N) {
+    if (c.tiled()) {
         launch_tchol(s, c);
         return;
     }
@@ -685,12 +685,12 @@ void launch_solve(hipStream_t s, Ctx &c, const double *geo_lin, double *geo_next
     const int ic = c.cfg.mode == PBA_IC_PROXY ? 1 : 0;
     if (rel_double)
         k_solve<double><<<c.nwin, SOLVE_THREADS, 0, s>>>(
-            c.win(), ic, c.cfg.pinned_frame, c.d_frame_pair_ptr, c.d_frame_pair_item, c.d_pair_host, c.d_pair_target,
+            c.win(), ic, c.tiled() ? 1 : 0, c.cfg.pinned_frame, c.d_frame_pair_ptr, c.d_frame_pair_item, c.d_pair_host, c.d_pair_target,
             c.d_pair_chunk_ptr, c.d_partY, c.d_pairY, geo_lin, c.d_S, c.d_Sfac, c.d_Linv, c.d_Sinv, c.d_poses,
             c.d_poses0, c.d_b, c.d_dtheta, c.d_dth_rel, geo_next, (double *)rel_next, c.d_wstat, c.d_flag, c.d_gate);
     else
         k_solve<float><<<c.nwin, SOLVE_THREADS, 0, s>>>(
-            c.win(), ic, c.cfg.pinned_frame, c.d_frame_pair_ptr, c.d_frame_pair_item, c.d_pair_host, c.d_pair_target,
+            c.win(), ic, c.tiled() ? 1 : 0, c.cfg.pinned_frame, c.d_frame_pair_ptr, c.d_frame_pair_item, c.d_pair_host, c.d_pair_target,
             c.d_pair_chunk_ptr, c.d_partY, c.d_pairY, geo_lin, c.d_S, c.d_Sfac, c.d_Linv, c.d_Sinv, c.d_poses,
             c.d_poses0, c.d_b, c.d_dtheta, c.d_dth_rel, geo_next, (float *)rel_next, c.d_wstat, c.d_flag, c.d_gate);
 }
