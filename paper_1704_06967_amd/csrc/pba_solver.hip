@@ -525,13 +525,36 @@ __global__ __launch_bounds__(SOLVE_THREADS) void k_solve(
     }
     __syncthreads();
     if (ic) {
-        // dtheta = -S^{-1} b, one wavefront per row of the inverse formed at p(0)
-        for (int i = wv; i < n; i += nw) {
-            const double *row = Sinv + (size_t)i * n;
-            double s = 0.0;
-            for (int j = lane; j < n; j += 64) s += row[j] * bx[j];
-            for (int k = 32; k >= 1; k >>= 1) s += __shfl_xor(s, k, 64);
-            if (lane == 0) dth_out[i] = -s;
+        // dtheta = -S^{-1} b with the inverse formed at p(0). Up to 256 rows: G
+        // consecutive threads per row, each with four independent partial sums
+        // (all of a thread's loads are in flight at once); larger systems: one
+        // wavefront per row.
+        if (n <= 256) {
+            const int G = n <= 128 ? 8 : 4;
+            const int i = threadIdx.x / G, q = threadIdx.x % G;
+            double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+            if (i < n) {
+                const double *row = Sinv + (size_t)i * n;
+                int j = q;
+                for (; j + 3 * G < n; j += 4 * G) {
+                    s0 += row[j] * bx[j];
+                    s1 += row[j + G] * bx[j + G];
+                    s2 += row[j + 2 * G] * bx[j + 2 * G];
+                    s3 += row[j + 3 * G] * bx[j + 3 * G];
+                }
+                for (; j < n; j += G) s0 += row[j] * bx[j];
+            }
+            double s = (s0 + s1) + (s2 + s3);
+            for (int k = G / 2; k >= 1; k >>= 1) s += __shfl_xor(s, k, 64);
+            if (i < n && q == 0) dth_out[i] = -s;
+        } else {
+            for (int i = wv; i < n; i += nw) {
+                const double *row = Sinv + (size_t)i * n;
+                double s = 0.0;
+                for (int j = lane; j < n; j += 64) s += row[j] * bx[j];
+                for (int k = 32; k >= 1; k >>= 1) s += __shfl_xor(s, k, 64);
+                if (lane == 0) dth_out[i] = -s;
+            }
         }
     } else if (packed) {
         // FC: factor the S assembled this iteration
