@@ -141,7 +141,9 @@ enum {
     PBA_DBG_OBS_REC = 3,    /* [real O x 40] per-observation blocks: 0-20 upper triangle of
                                sum w J_th^T J_th (row-major), 21-26 sum w J_th J_d, 27 sum w J_d^2,
                                28-33 sum w J_th r, 34 sum w J_d r, 35 energy, 36 sum r^2,
-                               37 active count (relative-pose coordinates) */
+                               37 active count (relative-pose coordinates). IC: the linearization
+                               at p(0) (the iterations keep g, g_d and the statistics in a
+                               compact buffer of their own) */
     PBA_DBG_TEMPLATE = 4,   /* [real N x P x 4] (I0, dI0/du, dI0/dv, usable) at the current level */
     PBA_DBG_HDD = 5,        /* [double N] damped depth diagonal of the last system */
     PBA_DBG_MASK = 6,       /* [uint8 O] bit j set if patch pixel j is in the frozen usable set */

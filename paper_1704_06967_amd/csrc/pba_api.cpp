@@ -127,8 +127,10 @@ void release_points(Ctx &c) {
     dfree(c.d_rel0);
     dfree(c.d_rel_a);
     dfree(c.d_rel_b);
+    dfree(c.d_icr);
     for (int l = 0; l < PBA_MAX_LEVELS; ++l) {
         dfree(c.lv[l].tmpl);
+        dfree(c.lv[l].pcam);
         c.lv[l].tmpl_valid = false;
     }
     c.have_points = false;
@@ -150,6 +152,8 @@ void release_frames(Ctx &c) {
     dfree(c.d_gate);
     dfree(c.d_count);
     dfree(c.d_du_part);
+    dfree(c.d_pairK0);
+    dfree(c.d_obs_prange);
     for (int **p : {&c.d_win_frame_off, &c.d_win_S_off, &c.d_win_L_off, &c.d_frame_win}) dfree(*p);
     dfree(c.d_wstat);
     c.stats_cap = 0;
@@ -754,8 +758,25 @@ pba_status load_points(Ctx &c, int n_points, const std::vector<int> &hf, const s
     HIPCHK(dalloc(c.d_gram, s.gram_floats * sizeof(double)));
     HIPCHK(dalloc(c.d_dth_rel, (size_t)Pn * 6 * sizeof(double)));
     HIPCHK(dalloc(c.d_du_part, 2 * (size_t)std::max(1, (n_points + 31) / 32) * sizeof(double)));
+    {
+        std::vector<double> pk((size_t)Pn * 8);
+        for (int p = 0; p < Pn; ++p)
+            for (int k = 0; k < 4; ++k) {
+                pk[8 * (size_t)p + k] = c.K0[4 * (size_t)s.pair_host[p] + k];
+                pk[8 * (size_t)p + 4 + k] = c.K0[4 * (size_t)s.pair_target[p] + k];
+            }
+        HIPCHK(upload(c, c.d_pairK0, pk));
+        std::vector<int> pr(2 * (size_t)O);
+        for (int o = 0; o < O; ++o) {
+            pr[2 * (size_t)o] = optr[s.obs_point[o]];
+            pr[2 * (size_t)o + 1] = optr[s.obs_point[o] + 1];
+        }
+        HIPCHK(upload(c, c.d_obs_prange, pr));
+    }
+    HIPCHK(dalloc(c.d_icr, (size_t)O * IC_REC * rs));
     for (int l = 0; l < c.cfg.n_levels; ++l) {
         HIPCHK(dalloc(c.lv[l].tmpl, (size_t)n_points * c.P * 4 * rs));
+        HIPCHK(dalloc(c.lv[l].pcam, (size_t)std::max(1, Pn) * 8 * rs));
         c.lv[l].tmpl_valid = false;
     }
     HIPCHK(hipGetLastError());

@@ -103,14 +103,20 @@ __device__ __forceinline__ bool tile_potrf_inv(double *t, int nb, double *__rest
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
             // column `lane` of L^{-1}: x[i] = (delta_i,lane - sum_k<i L(i, k) x[k]) / L(i, i)
-            // (every lane reads the same L(i, k): LDS broadcasts)
+            // (every lane reads the same L(i, k): LDS broadcasts; four partial
+            // sums shorten the dependent chains)
             double x[TB];
 #pragma unroll
             for (int i = 0; i < TB; ++i) {
-                double s = (i == lane) ? 1.0 : 0.0;
+                double s0 = (i == lane) ? 1.0 : 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
 #pragma unroll
-                for (int k = 0; k < i; ++k) s -= tl(t, i, k) * x[k];
-                x[i] = (i >= lane) ? s * invd[i] : 0.0;
+                for (int k = 0; k < i; k += 4) {
+                    s0 -= tl(t, i, k) * x[k];
+                    if (k + 1 < i) s1 -= tl(t, i, k + 1) * x[k + 1];
+                    if (k + 2 < i) s2 -= tl(t, i, k + 2) * x[k + 2];
+                    if (k + 3 < i) s3 -= tl(t, i, k + 3) * x[k + 3];
+                }
+                x[i] = (i >= lane) ? ((s0 + s1) + (s2 + s3)) * invd[i] : 0.0;
             }
             if (lane < TB) {
 #pragma unroll
@@ -245,7 +251,7 @@ __global__ __launch_bounds__(1024) void k_tsolve(int n, const double *__restrict
 
 void launch_tsolve(hipStream_t s, Ctx &c, const double *b, double *x) {
     const int n = 6 * c.F;
-    const size_t lds = ((size_t)n + TB * (1024 / TB) + TB) * sizeof(double);
+    const size_t lds = ((size_t)n + tile_solve_tmp(1024)) * sizeof(double);
     k_tsolve<<<1, 1024, lds, s>>>(n, c.d_Sfac, c.d_Linv, b, x, c.d_flag);
 }
 
@@ -263,7 +269,7 @@ void launch_tchol(hipStream_t s, Ctx &c) {
 
 void launch_tinv(hipStream_t s, Ctx &c) {
     const int n = 6 * c.F;
-    const size_t lds = ((size_t)n + TB * (256 / TB) + TB) * sizeof(double);
+    const size_t lds = ((size_t)n + tile_solve_tmp(256)) * sizeof(double);
     k_tinv_columns<<<std::min(n, 2048), 256, lds, s>>>(n, c.d_Sfac, c.d_Linv, c.d_Sinv, c.d_flag, c.d_gate);
 }
 

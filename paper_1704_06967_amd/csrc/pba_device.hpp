@@ -240,6 +240,13 @@ __device__ __forceinline__ void mat3_mul_bt(const double *A, const double *B, do
         }
 }
 
+// An empty asm statement that takes v in a vector register and may change it:
+// the value must exist at this point, so a load feeding it is not moved past it.
+template <typename T>
+__device__ __forceinline__ void pin_reg(T &v) {
+    asm volatile("" : "+v"(v));
+}
+
 template <typename T>
 __device__ __forceinline__ T wave_sum8(T v) {
     v += __shfl_xor(v, 1, 64);

@@ -25,6 +25,17 @@ enum RecField : int {
     REC_CNT = 37,     // 1: number of contributing residuals
     REC_STRIDE = 40
 };
+// Gradient record: g (6), g_d, energy, sum r^2, count. In the full record these
+// are the fields REC_G .. REC_CNT; the IC iterations keep them in a compact
+// record of IC_REC values per observation.
+enum {
+    GR_G = 0,
+    GR_GD = 6,
+    GR_E = 7,
+    GR_SQ = 8,
+    GR_CNT = 9,
+    IC_REC = 10
+};
 
 // Per-pair geometry in double: R_fh (9), t_fh (3), t_h (3), pad.
 constexpr int GEO_STRIDE = 16;
@@ -94,6 +105,7 @@ struct LevelDev {
     void *img = nullptr;      // T [F][H][W]
     void *K = nullptr;        // T [F][4] level intrinsics
     void *tmpl = nullptr;     // T [N][P][4] (I0, gu, gv, usable) at the host patch pixels
+    void *pcam = nullptr;     // T [Pn][8] host and target intrinsics of every pair
     bool tmpl_valid = false;
 };
 
@@ -169,6 +181,7 @@ struct Ctx {
     float *d_host_uv = nullptr;                        // [N][2]
     uint8_t *d_mask = nullptr;                         // [O]
     void *d_rec = nullptr;                             // T [O][REC_STRIDE]
+    void *d_icr = nullptr;                             // T [O][IC_REC] gradient records of the IC iterations
     double *d_geo0 = nullptr, *d_geo_a = nullptr, *d_geo_b = nullptr;   // [Pn][GEO_STRIDE]
     void *d_rel0 = nullptr, *d_rel_a = nullptr, *d_rel_b = nullptr;      // T [Pn][REL_STRIDE]
     double *d_pairH = nullptr;                         // [Pn][21]
@@ -191,6 +204,8 @@ struct Ctx {
     int *d_gate = nullptr;                             // 1 while the current solve level runs
     int *d_count = nullptr;                            // iterations run per level [PBA_MAX_LEVELS]
     double *d_du_part = nullptr;                       // depth-update block maxima [blocks][2]
+    double *d_pairK0 = nullptr;                        // [Pn][8] level-0 intrinsics of host and target
+    int *d_obs_prange = nullptr;                       // [O][2] observation range of each observation's point
 
     // current double-buffer orientation
     bool flip = false;

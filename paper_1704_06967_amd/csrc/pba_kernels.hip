@@ -48,6 +48,18 @@ __global__ void k_level_K(const double *__restrict__ K0, T *__restrict__ K, int 
     K[4 * f + 3] = (T)((K0[4 * f + 3] + 0.5) * s - 0.5);
 }
 
+// Level intrinsics of every pair's host and target frames, side by side, so
+// that a residual reads its camera data with its pair index alone.
+template <typename T>
+__global__ void k_pair_cam(int Pn, const int *__restrict__ pair_host, const int *__restrict__ pair_target,
+                           const T *__restrict__ K, T *__restrict__ pcam) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= Pn * 8) return;
+    const int p = e >> 3, k = e & 7;
+    const int f = k < 4 ? pair_host[p] : pair_target[p];
+    pcam[e] = K[4 * f + (k & 3)];
+}
+
 // Template data at every host patch pixel: I0, the interpolated central-difference
 // gradient, and whether the pixel is usable at this level.
 template <typename T>
@@ -112,6 +124,8 @@ struct ResArgs {
     const double *depth, *depth0;
     uint8_t *mask;
     T *rec;
+    const T *pcam;       // per pair: host and target level intrinsics (fx, fy, cx, cy) x 2
+    T *icr;              // IC iterations: per observation g (6), g_d, energy, sum r^2, count
     const int *gate;     // device flag: 0 = the solve has converged, skip the work
 };
 
@@ -349,38 +363,79 @@ __global__ __launch_bounds__(BLOCK) void k_linearize_mixed(ResArgs<float> a, int
 // IC iteration: residuals at the current parameters, Huber weights, and
 // g = J^T W r with the constant proxy Jacobian (Sec. 3.5 steps 1-2). NB threads
 // per workgroup, tiles of NB / 8 observations, grid-stride over the tiles.
+// Three dependent memory steps per residual: the observation (with the gate),
+// then the point, pair pose and pair camera data, then the target texels. The
+// ten sums of an observation go out as one contiguous record (two stores per
+// wavefront).
 template <typename T, int NB>
 __global__ __launch_bounds__(NB) void k_ic_residual(ResArgs<T> a) {
-    if (*a.gate == 0) return;
     const int ntiles = (a.O + NB / 8 - 1) / (NB / 8);
     for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
         const int gid = tile * NB + threadIdx.x;
         const int o = gid >> 3, j = gid & 7;
+        const bool in = o < a.O;
+        const int n = in ? a.obs_point[o] : 0, pr = in ? a.obs_pair[o] : 0;
+        const unsigned m = in ? (unsigned)a.mask[o] : 0u;
+        // the gate as a vector load, in flight together with the observation's
+        const int gv = __hip_atomic_load(a.gate, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (__builtin_amdgcn_readfirstlane(gv) == 0) return;
         T c[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
-        if (o < a.O && j < a.P && ((a.mask[o] >> j) & 1)) {
-            const int n = a.obs_point[o], pr = a.obs_pair[o];
-            const int h = a.pair_host[pr], f = a.pair_target[pr];
-            const T *Kh = a.K + 4 * h;
-            const T *Kt = a.K + 4 * f;
-            T x, y;
-            template_xy(a, n, j, Kh, x, y);
-            const T *R = a.rel + REL_STRIDE * pr;
+        if (in && j < a.P && ((m >> j) & 1)) {
+            // second step: every load that depends only on (n, pr, j), issued
+            // before any branch
+            const double dd = a.depth[n], dd0 = a.depth0[n];
+            T cam[8], R[12], R0[12], tp[4];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) cam[k] = a.pcam[8 * pr + k];   // host, target (fx, fy, cx, cy)
+#pragma unroll
+            for (int k = 0; k < 12; ++k) R[k] = a.rel[REL_STRIDE * pr + k];
+#pragma unroll
+            for (int k = 0; k < 12; ++k) R0[k] = a.rel0[REL_STRIDE * pr + k];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) tp[k] = a.tmpl[4 * ((size_t)n * a.P + j) + k];
+            int f = a.pair_target[pr];
+            T hu = (T)a.host_uv[2 * n], hv = (T)a.host_uv[2 * n + 1];
+            T d = (T)dd, d0 = (T)dd0;
+            // keep the compiler from sinking these loads into the branches below
+            // (the pins follow every load, so that all of them are in flight)
+            pin_reg(f);
+            pin_reg(hu);
+            pin_reg(hv);
+            pin_reg(d);
+            pin_reg(d0);
+#pragma unroll
+            for (int k = 0; k < 8; ++k) pin_reg(cam[k]);
+#pragma unroll
+            for (int k = 0; k < 12; ++k) {
+                pin_reg(R[k]);
+                pin_reg(R0[k]);
+            }
+#pragma unroll
+            for (int k = 0; k < 4; ++k) pin_reg(tp[k]);
+            // pattern offset of lane j by selects (no lane-indexed argument loads)
+            float du = a.pat.du[0], dv = a.pat.dv[0];
+#pragma unroll
+            for (int k = 1; k < 8; ++k) {
+                du = j == k ? a.pat.du[k] : du;
+                dv = j == k ? a.pat.dv[k] : dv;
+            }
+            const T u = (hu + T(0.5)) * a.scale - T(0.5) + (T)du;
+            const T v = (hv + T(0.5)) * a.scale - T(0.5) + (T)dv;
+            const T x = (u - cam[2]) / cam[0], y = (v - cam[3]) / cam[1];
             const T *t = R + 9;
-            const T d = (T)a.depth[n];
             const T vz = R[6] * x + R[7] * y + R[8] + d * t[2];
+            const T vx = R[0] * x + R[1] * y + R[2] + d * t[0];
+            const T vy = R[3] * x + R[4] * y + R[5] + d * t[1];
             if (d > T(0) && vz > T(0)) {
-                const T vx = R[0] * x + R[1] * y + R[2] + d * t[0];
-                const T vy = R[3] * x + R[4] * y + R[5] + d * t[1];
-                const T qu = Kt[0] * (vx / vz) + Kt[2], qv = Kt[1] * (vy / vz) + Kt[3];
+                const T qu = cam[4] * (vx / vz) + cam[6], qv = cam[5] * (vy / vz) + cam[7];
                 if (usable(qu, qv, a.W, a.H)) {
-                    const T *tp = a.tmpl + 4 * ((size_t)n * a.P + j);
+                    // third step: the target texels
                     const T If = bilinear(a.img + (size_t)f * a.W * a.H, a.W, qu, qv);
                     const T r = tp[0] - If;
                     T w, rho;
                     huber(r, a.huber_k, w, rho);
                     T J[7];
-                    const T *R0 = a.rel0 + REL_STRIDE * pr;
-                    ic_jacobian(x, y, R0, R0 + 9, (T)a.depth0[n], tp[1], tp[2], Kh[0], Kh[1], J);
+                    ic_jacobian(x, y, R0, R0 + 9, d0, tp[1], tp[2], cam[0], cam[1], J);
                     const T wr = w * r;
 #pragma unroll
                     for (int p = 0; p < 7; ++p) c[p] = wr * J[p];
@@ -392,13 +447,16 @@ __global__ __launch_bounds__(NB) void k_ic_residual(ResArgs<T> a) {
         }
 #pragma unroll
         for (int p = 0; p < 10; ++p) c[p] = wave_sum8(c[p]);
-        if (j == 0 && o < a.O) {
-            T *rec = a.rec + (size_t)o * REC_STRIDE;
+        // every lane of the observation holds the sums: lane j stores field j
+        // (and lanes 0, 1 fields 8, 9)
+        T v0 = c[0];
 #pragma unroll
-            for (int p = 0; p < 7; ++p) rec[REC_G + p] = c[p];
-            rec[REC_E] = c[7];
-            rec[REC_SQ] = c[8];
-            rec[REC_CNT] = c[9];
+        for (int p = 1; p < 8; ++p) v0 = j == p ? c[p] : v0;
+        const T v1 = j == 0 ? c[8] : c[9];
+        if (in) {
+            T *rec = a.icr + (size_t)o * IC_REC;
+            rec[j] = v0;
+            if (j < 2) rec[8 + j] = v1;
         }
     }
 }
@@ -488,11 +546,11 @@ __global__ __launch_bounds__(256) void k_point_reduce(int N, const int *__restri
     }
 }
 
-// Per chunk of one pair's observations (at most PAIR_CHUNK, two per thread):
+// Per chunk of one pair's observations (at most PAIR_CHUNK, one per thread):
 // sum of the pose-pose block (21 values). Chunk partials are added per pair in
 // chunk order by the consumer.
 template <typename T>
-__global__ __launch_bounds__(256) void k_pair_chunk_H(const int *__restrict__ chunk_begin,
+__global__ __launch_bounds__(PAIR_CHUNK) void k_pair_chunk_H(const int *__restrict__ chunk_begin,
                                                       const int *__restrict__ chunk_end,
                                                       const int *__restrict__ pair_obs_idx, const T *__restrict__ rec,
                                                       double *__restrict__ partH, const int *__restrict__ gate) {
@@ -510,17 +568,20 @@ __global__ __launch_bounds__(256) void k_pair_chunk_H(const int *__restrict__ ch
         for (int k = 0; k < 21; ++k) partH[21 * c + k] = v[k];
 }
 
-// Per chunk of one pair's observations: reduced right-hand side contribution
-// sum_o (g_o - h_o g_d,n / H_dd,n) (depth elimination of the gradient) and the
-// energy statistics.
+// Per chunk of one pair's observations (at most PAIR_CHUNK, one per thread):
+// reduced right-hand side contribution sum_o (g_o - h_o g_d,n / H_dd,n) (depth
+// elimination of the gradient) and the energy statistics. gr / gs: gradient
+// records (GR_* fields) and their stride; h_o from the full record; prange: the
+// observation range of each observation's point.
 template <typename T>
-__global__ __launch_bounds__(256) void k_pair_chunk_y(const int *__restrict__ chunk_begin,
-                                                      const int *__restrict__ chunk_end,
-                                                      const int *__restrict__ pair_obs_idx,
-                                                      const int *__restrict__ obs_point,
-                                                      const int *__restrict__ obs_ptr, const T *__restrict__ rec,
-                                                      const double *__restrict__ Hdd, double *__restrict__ partY,
-                                                      const int *__restrict__ gate) {
+__global__ __launch_bounds__(PAIR_CHUNK) void k_pair_chunk_y(const int *__restrict__ chunk_begin,
+                                                             const int *__restrict__ chunk_end,
+                                                             const int *__restrict__ pair_obs_idx,
+                                                             const int *__restrict__ obs_point,
+                                                             const int *__restrict__ prange, const T *__restrict__ rec,
+                                                             const T *__restrict__ gr, int gs,
+                                                             const double *__restrict__ Hdd,
+                                                             double *__restrict__ partY, const int *__restrict__ gate) {
     __shared__ double lds[9 * 16];
     if (*gate == 0) return;
     const int c = blockIdx.x;
@@ -529,14 +590,17 @@ __global__ __launch_bounds__(256) void k_pair_chunk_y(const int *__restrict__ ch
     for (int i = chunk_begin[c] + threadIdx.x; i < chunk_end[c]; i += blockDim.x) {
         const int o = pair_obs_idx[i];
         const T *r = rec + (size_t)o * REC_STRIDE;
+        const T *g = gr + (size_t)o * gs;
         const int n = obs_point[o];
+        const int q0 = prange[2 * o], q1 = prange[2 * o + 1];
         double gdn = 0.0;  // g_d,n: the point's records in order (bitwise the per-point sum)
-        for (int q = obs_ptr[n]; q < obs_ptr[n + 1]; ++q) gdn += (double)rec[(size_t)q * REC_STRIDE + REC_GD];
+#pragma unroll 4
+        for (int q = q0; q < q1; ++q) gdn += (double)gr[(size_t)q * gs + GR_GD];
         const double s = gdn / Hdd[n];
-        for (int k = 0; k < 6; ++k) v[k] += (double)r[REC_G + k] - (double)r[REC_h + k] * s;
-        v[6] += (double)r[REC_E];
-        v[7] += (double)r[REC_SQ];
-        v[8] += (double)r[REC_CNT];
+        for (int k = 0; k < 6; ++k) v[k] += (double)g[GR_G + k] - (double)r[REC_h + k] * s;
+        v[6] += (double)g[GR_E];
+        v[7] += (double)g[GR_SQ];
+        v[8] += (double)g[GR_CNT];
     }
     block_sum<9>(v, lds);
     if (threadIdx.x == 0)
@@ -572,28 +636,99 @@ __global__ void k_sum_parts3(int np, const double *__restrict__ part, double *__
 
 constexpr int DU_PTS = 32, DU_SLOTS = 8;
 
+// End-of-iteration statistics and the convergence gate (see k_conv).
+struct ConvArgs {
+    const double *wstat;
+    int nwin;
+    double *stat;
+    double conv_px;
+    int *gate, *count;
+    const int *flag;
+};
+
+// Statistics of an iteration from the block maxima (largest point-centre
+// displacement, largest depth step) and the per-window statistics of the solve,
+// added over the windows in order; closes the gate once the displacement is
+// below conv_px (conv_px >= 0). One block; md / ms are its thread-0 maxima.
+__device__ void conv_finish(const ConvArgs &cv, double md, double ms) {
+    if (*cv.flag) {
+        *cv.gate = 0;
+        return;
+    }
+    double e = 0.0, sq = 0.0, cnt = 0.0, sp = 0.0;
+    for (int w = 0; w < cv.nwin; ++w) {
+        e += cv.wstat[4 * w];
+        sq += cv.wstat[4 * w + 1];
+        cnt += cv.wstat[4 * w + 2];
+        sp = fmax(sp, cv.wstat[4 * w + 3]);
+    }
+    cv.stat[ST_E] = e;
+    cv.stat[ST_SQ] = sq;
+    cv.stat[ST_CNT] = cnt;
+    cv.stat[ST_STEP_P] = sp;
+    cv.stat[ST_DISP] = md;
+    cv.stat[ST_STEP_D] = ms;
+    *cv.count += 1;
+    if (cv.conv_px >= 0.0 && md < cv.conv_px) *cv.gate = 0;
+}
+
+// Block maxima of the pairs (part[2 i], part[2 i + 1]), i < nparts; valid in thread 0.
+__device__ void block_max2(const double *part, int nparts, double &md, double &ms, double (*red)[16]) {
+    md = 0.0;
+    ms = 0.0;
+    for (int i = threadIdx.x; i < nparts; i += blockDim.x) {
+        md = fmax(md, part[2 * i]);
+        ms = fmax(ms, part[2 * i + 1]);
+    }
+    for (int k = 32; k >= 1; k >>= 1) {
+        md = fmax(md, __shfl_xor(md, k, 64));
+        ms = fmax(ms, __shfl_xor(ms, k, 64));
+    }
+    if ((threadIdx.x & 63) == 0) {
+        red[0][threadIdx.x >> 6] = md;
+        red[1][threadIdx.x >> 6] = ms;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0)
+        for (int k = 1; k < (int)(blockDim.x >> 6); ++k) {
+            md = fmax(md, red[0][k]);
+            ms = fmax(ms, red[1][k]);
+        }
+}
+
+// Depth step of every point after the pose step (depth back-substitution,
+// Sec. 3.5 step 4 for IC, the Schur back-substitution for FC) and the block
+// maxima of the point-centre displacement it causes and of the depth step
+// (k_conv finishes the iteration from them). DU_PTS points per block,
+// DU_SLOTS threads per point over its observations. Loads that depend only on
+// the point are issued first; the target intrinsics come per pair (level 0).
 template <typename T>
 __global__ __launch_bounds__(256) void k_depth_update(
     int N, int ic, const int *__restrict__ obs_ptr, const int *__restrict__ obs_pair,
-    const int *__restrict__ host_frame, const float *__restrict__ host_uv, const double *__restrict__ K0,
-    const int *__restrict__ pair_target, const T *__restrict__ rec, const double *__restrict__ Hdd,
-    const double *__restrict__ dth_rel, const double *__restrict__ geo_old, const double *__restrict__ geo_new,
-    double *__restrict__ depth, const double *__restrict__ depth0, double *__restrict__ part,
-    const int *__restrict__ gate, const int *__restrict__ flag) {
+    const float *__restrict__ host_uv, const double *__restrict__ pairK0, const T *__restrict__ rec,
+    const T *__restrict__ gr, int gs, const double *__restrict__ Hdd, const double *__restrict__ dth_rel,
+    const double *__restrict__ geo_old, const double *__restrict__ geo_new, double *__restrict__ depth,
+    const double *__restrict__ depth0, double *__restrict__ part, const int *__restrict__ gate,
+    const int *__restrict__ flag) {
     __shared__ double sp[DU_PTS][DU_SLOTS][2];
     __shared__ double dnew[DU_PTS], dold[DU_PTS];
     __shared__ double red[2][4];
-    if (*gate == 0 || *flag) return;
     const int q = threadIdx.x / DU_SLOTS, slot = threadIdx.x % DU_SLOTS;
     const int n = blockIdx.x * DU_PTS + q;
     const bool has = n < N;
+    // first step: the point's data and the gate
     const int o0 = has ? obs_ptr[n] : 0, o1 = has ? obs_ptr[n + 1] : 0;
+    const double hu = has ? (double)host_uv[2 * n] : 0.0, hv = has ? (double)host_uv[2 * n + 1] : 0.0;
+    const double Hn = has ? Hdd[n] : 1.0, d_old = has ? depth[n] : 0.0, d0 = has ? depth0[n] : 1.0;
+    const int gv = __hip_atomic_load(gate, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const int fv = __hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (__builtin_amdgcn_readfirstlane(gv) == 0 || __builtin_amdgcn_readfirstlane(fv) != 0) return;
     // g_d,n and h_n^T dtheta, slot-parallel over the point's observations
     double s = 0.0, g = 0.0;
     for (int o = o0 + slot; o < o1; o += DU_SLOTS) {
         const T *r = rec + (size_t)o * REC_STRIDE;
         const double *dr = dth_rel + 6 * obs_pair[o];
-        g += (double)r[REC_GD];
+        g += (double)gr[(size_t)o * gs + GR_GD];
         for (int k = 0; k < 6; ++k) s += (double)r[REC_h + k] * dr[k];
     }
     sp[q][slot][0] = g;
@@ -604,9 +739,8 @@ __global__ __launch_bounds__(256) void k_depth_update(
         double t = 0.0;
         for (int k = 0; k < DU_SLOTS; ++k) t += sp[q][k][0];
         for (int k = 0; k < DU_SLOTS; ++k) t += sp[q][k][1];
-        const double dd = -t / Hdd[n];
-        const double d_old = depth[n];
-        const double d_new = ic ? d_old * (depth0[n] - dd) / depth0[n] : d_old + dd;
+        const double dd = -t / Hn;
+        const double d_new = ic ? d_old * (d0 - dd) / d0 : d_old + dd;
         depth[n] = d_new;
         dold[q] = d_old;
         dnew[q] = d_new;
@@ -614,28 +748,24 @@ __global__ __launch_bounds__(256) void k_depth_update(
     }
     __syncthreads();
     double mdisp = 0.0;
-    if (has) {
-        const int h = host_frame[n];
-        const double x = ((double)host_uv[2 * n] - K0[4 * h + 2]) / K0[4 * h + 0];
-        const double y = ((double)host_uv[2 * n + 1] - K0[4 * h + 3]) / K0[4 * h + 1];
-        for (int o = o0 + slot; o < o1; o += DU_SLOTS) {
-            const int p = obs_pair[o];
-            const double *Kt = K0 + 4 * pair_target[p];
-            double qq[2][2];
-            bool ok = true;
-            for (int s2 = 0; s2 < 2; ++s2) {
-                const double *gm = s2 ? geo_new + GEO_STRIDE * p : geo_old + GEO_STRIDE * p;
-                const double d = s2 ? dnew[q] : dold[q];
-                const double vx = gm[0] * x + gm[1] * y + gm[2] + d * gm[9];
-                const double vy = gm[3] * x + gm[4] * y + gm[5] + d * gm[10];
-                const double vz = gm[6] * x + gm[7] * y + gm[8] + d * gm[11];
-                ok = ok && vz > 0.0;
-                const double vzs = vz > 0.0 ? vz : 1.0;
-                qq[s2][0] = Kt[0] * vx / vzs + Kt[2];
-                qq[s2][1] = Kt[1] * vy / vzs + Kt[3];
-            }
-            if (ok) mdisp = fmax(mdisp, hypot(qq[1][0] - qq[0][0], qq[1][1] - qq[0][1]));
+    for (int o = o0 + slot; o < o1; o += DU_SLOTS) {
+        const int p = obs_pair[o];
+        const double *Kp = pairK0 + 8 * p;   // host (fx, fy, cx, cy), target (fx, fy, cx, cy)
+        const double x = (hu - Kp[2]) / Kp[0], y = (hv - Kp[3]) / Kp[1];
+        double qq[2][2];
+        bool ok = true;
+        for (int s2 = 0; s2 < 2; ++s2) {
+            const double *gm = s2 ? geo_new + GEO_STRIDE * p : geo_old + GEO_STRIDE * p;
+            const double d = s2 ? dnew[q] : dold[q];
+            const double vx = gm[0] * x + gm[1] * y + gm[2] + d * gm[9];
+            const double vy = gm[3] * x + gm[4] * y + gm[5] + d * gm[10];
+            const double vz = gm[6] * x + gm[7] * y + gm[8] + d * gm[11];
+            ok = ok && vz > 0.0;
+            const double vzs = vz > 0.0 ? vz : 1.0;
+            qq[s2][0] = Kp[4] * vx / vzs + Kp[6];
+            qq[s2][1] = Kp[5] * vy / vzs + Kp[7];
         }
+        if (ok) mdisp = fmax(mdisp, hypot(qq[1][0] - qq[0][0], qq[1][1] - qq[0][1]));
     }
     for (int k = 32; k >= 1; k >>= 1) {
         mdisp = fmax(mdisp, __shfl_xor(mdisp, k, 64));
@@ -688,8 +818,23 @@ static ResArgs<T> res_args(Ctx &c, int level, const T *rel_cur) {
     a.depth0 = c.d_depth0;
     a.mask = c.d_mask;
     a.rec = (T *)c.d_rec;
+    a.pcam = (const T *)c.lv[level].pcam;
+    a.icr = (T *)c.d_icr;
     a.gate = c.d_gate;
     return a;
+}
+
+// Gradient records of the current iteration: the compact IC records or the
+// G .. CNT fields of the full record (FC).
+template <typename T>
+static void grad_records(const Ctx &c, const T *&gr, int &gs) {
+    if (c.cfg.mode == PBA_IC_PROXY) {
+        gr = (const T *)c.d_icr;
+        gs = IC_REC;
+    } else {
+        gr = (const T *)c.d_rec + REC_G;
+        gs = REC_STRIDE;
+    }
 }
 
 template <typename T>
@@ -718,6 +863,11 @@ void Launch<T>::make_template(hipStream_t s, Ctx &c, int level) {
     k_template<T><<<nblk(n, 256), 256, 0, s>>>(c.N, c.P, a.pat, c.d_host_uv, c.d_host_frame, a.img, a.W, a.H,
                                                a.scale, (T *)c.lv[level].tmpl);
     CHECK_LAUNCH();
+    if (c.st.n_pairs > 0) {
+        k_pair_cam<T><<<nblk((size_t)c.st.n_pairs * 8, 256), 256, 0, s>>>(
+            c.st.n_pairs, c.d_pair_host, c.d_pair_target, a.K, (T *)c.lv[level].pcam);
+        CHECK_LAUNCH();
+    }
 }
 
 template <typename T>
@@ -825,7 +975,7 @@ template <typename T>
 void Launch<T>::pair_reduce_H(hipStream_t s, Ctx &c) {
     const int nch = (int)c.st.pchunk_begin.size();
     if (nch == 0) return;
-    k_pair_chunk_H<T><<<nch, 256, 0, s>>>(c.d_pchunk_begin, c.d_pchunk_end, c.d_pair_obs_idx, (const T *)c.d_rec,
+    k_pair_chunk_H<T><<<nch, PAIR_CHUNK, 0, s>>>(c.d_pchunk_begin, c.d_pchunk_end, c.d_pair_obs_idx, (const T *)c.d_rec,
                                           c.d_partH, c.d_gate);
     CHECK_LAUNCH();
 }
@@ -834,73 +984,43 @@ template <typename T>
 void Launch<T>::pair_reduce_y(hipStream_t s, Ctx &c) {
     const int nch = (int)c.st.pchunk_begin.size();
     if (nch == 0) return;
-    k_pair_chunk_y<T><<<nch, 256, 0, s>>>(c.d_pchunk_begin, c.d_pchunk_end, c.d_pair_obs_idx, c.d_obs_point,
-                                          c.d_obs_ptr, (const T *)c.d_rec, c.d_Hdd, c.d_partY, c.d_gate);
+    const T *gr;
+    int gs;
+    grad_records<T>(c, gr, gs);
+    k_pair_chunk_y<T><<<nch, PAIR_CHUNK, 0, s>>>(c.d_pchunk_begin, c.d_pchunk_end, c.d_pair_obs_idx,
+                                                 c.d_obs_point, c.d_obs_prange, (const T *)c.d_rec, gr, gs, c.d_Hdd,
+                                                 c.d_partY, c.d_gate);
     CHECK_LAUNCH();
+}
+
+static ConvArgs conv_args(Ctx &c, double *stat, double conv_px, int level) {
+    return ConvArgs{c.d_wstat, c.nwin, stat, conv_px, c.d_gate, c.d_count + level, c.d_flag};
 }
 
 template <typename T>
 void Launch<T>::depth_update(hipStream_t s, Ctx &c, const double *geo_old, const double *geo_new, double *stat,
                              double conv_px, int level) {
     const int nb = (int)nblk(c.N, DU_PTS);
+    const T *gr;
+    int gs;
+    grad_records<T>(c, gr, gs);
     if (c.N > 0)
         k_depth_update<T><<<nb, 256, 0, s>>>(c.N, c.cfg.mode == PBA_IC_PROXY ? 1 : 0, c.d_obs_ptr, c.d_obs_pair,
-                                             c.d_host_frame, c.d_host_uv, c.d_K0, c.d_pair_target,
-                                             (const T *)c.d_rec, c.d_Hdd, c.d_dth_rel, geo_old, geo_new, c.d_depth,
-                                             c.d_depth0, c.d_du_part, c.d_gate, c.d_flag);
+                                             c.d_host_uv, c.d_pairK0, (const T *)c.d_rec, gr, gs, c.d_Hdd,
+                                             c.d_dth_rel, geo_old, geo_new, c.d_depth, c.d_depth0, c.d_du_part,
+                                             c.d_gate, c.d_flag);
     CHECK_LAUNCH();
     launch_conv(s, c, stat, conv_px, c.N > 0 ? nb : 0, level);
 }
 
-// End of an iteration (single block): the window statistics of the solve
-// kernel added over the windows in order, the largest point-centre
-// displacement and depth step from the depth-update block maxima, and the
-// convergence gate: with conv_px >= 0 the iteration is counted and the gate
-// closes once the displacement is below conv_px.
-__global__ __launch_bounds__(256) void k_conv(const double *__restrict__ part, int nparts,
-                                              const double *__restrict__ wstat, int nwin, double *__restrict__ stat,
-                                              double conv_px, int *__restrict__ gate, int *__restrict__ count,
-                                              const int *__restrict__ flag) {
-    __shared__ double red[2][4];
-    if (*gate == 0) return;
-    double md = 0.0, ms = 0.0;
-    for (int i = threadIdx.x; i < nparts; i += blockDim.x) {
-        md = fmax(md, part[2 * i]);
-        ms = fmax(ms, part[2 * i + 1]);
-    }
-    for (int k = 32; k >= 1; k >>= 1) {
-        md = fmax(md, __shfl_xor(md, k, 64));
-        ms = fmax(ms, __shfl_xor(ms, k, 64));
-    }
-    if ((threadIdx.x & 63) == 0) {
-        red[0][threadIdx.x >> 6] = md;
-        red[1][threadIdx.x >> 6] = ms;
-    }
-    __syncthreads();
-    if (threadIdx.x != 0) return;
-    for (int k = 1; k < 4; ++k) {
-        md = fmax(md, red[0][k]);
-        ms = fmax(ms, red[1][k]);
-    }
-    if (*flag) {
-        *gate = 0;
-        return;
-    }
-    double e = 0.0, sq = 0.0, cnt = 0.0, sp = 0.0;
-    for (int w = 0; w < nwin; ++w) {
-        e += wstat[4 * w];
-        sq += wstat[4 * w + 1];
-        cnt += wstat[4 * w + 2];
-        sp = fmax(sp, wstat[4 * w + 3]);
-    }
-    stat[ST_E] = e;
-    stat[ST_SQ] = sq;
-    stat[ST_CNT] = cnt;
-    stat[ST_STEP_P] = sp;
-    stat[ST_DISP] = md;
-    stat[ST_STEP_D] = ms;
-    *count += 1;
-    if (conv_px >= 0.0 && md < conv_px) *gate = 0;
+// End of an iteration without points (single block): the iteration
+// statistics and the convergence gate from nparts block maxima.
+__global__ __launch_bounds__(256) void k_conv(const double *__restrict__ part, int nparts, ConvArgs cv) {
+    __shared__ double red[2][16];
+    if (*cv.gate == 0) return;
+    double md, ms;
+    block_max2(part, nparts, md, ms, red);
+    if (threadIdx.x == 0) conv_finish(cv, md, ms);
 }
 
 // Start of a batch of iterations: clear the level's iteration count and
@@ -915,8 +1035,7 @@ __global__ void k_open(int *__restrict__ gate, int *__restrict__ flag, int *__re
 }
 
 void launch_conv(hipStream_t s, Ctx &c, double *stat, double conv_px, int nparts, int level) {
-    k_conv<<<1, 256, 0, s>>>(c.d_du_part, nparts, c.d_wstat, c.nwin, stat, conv_px, c.d_gate, c.d_count + level,
-                             c.d_flag);
+    k_conv<<<1, 256, 0, s>>>(c.d_du_part, nparts, conv_args(c, stat, conv_px, level));
     CHECK_LAUNCH();
 }
 

@@ -12,6 +12,7 @@ namespace pba {
 constexpr int SOLVE_THREADS = 1024;
 constexpr int LDS_DOUBLES = 152 * 1024 / 8;   // packed lower triangle of S (+ panel scratch) when it fits
 constexpr int LDS_MAX_N = LDS_CHOL_MAX_N;     // n (n + 1) / 2 + 17 n <= LDS_DOUBLES; 3 rows per lane
+constexpr int IC_SPLIT_N = 256;               // IC systems above this size: multi-workgroup S^{-1} b
 constexpr int WNS = 3;                        // rows per lane in the wavefront solves (n <= 192)
 constexpr int GRAM_G = 32;                    // points per Gram step
 constexpr int GRAM_SLOTS = 8;                 // observation slots per point per load pass
@@ -455,7 +456,7 @@ void launch_ic_inverse(hipStream_t s, Ctx &c) {
 // to wstat[w]; the convergence kernel adds them over the windows.
 template <typename T>
 __global__ __launch_bounds__(SOLVE_THREADS) void k_solve(
-    WinArgs wa, int ic, int tiled, int pinned, const int *__restrict__ frame_pair_ptr, const int *__restrict__ frame_pair_item,
+    WinArgs wa, int ic, int tiled, int pinned, int stage, const int *__restrict__ frame_pair_ptr, const int *__restrict__ frame_pair_item,
     const int *__restrict__ pair_host, const int *__restrict__ pair_target, const int *__restrict__ pair_chunk_ptr,
     const double *__restrict__ partY, double *__restrict__ pairY, const double *__restrict__ geo_lin,
     const double *__restrict__ S_all, const double *__restrict__ Sfac, const double *__restrict__ Linv,
@@ -483,21 +484,24 @@ __global__ __launch_bounds__(SOLVE_THREADS) void k_solve(
     const bool packed = !tiled;
     // rhs / solution in LDS (FC: after the packed factor; the panel scratch follows)
     double *bx = lds + ((packed && !ic) ? n * (n + 1) / 2 : 0);
-    for (int e = threadIdx.x; e < (p1 - p0) * 9; e += blockDim.x) {
-        const int p = p0 + e / 9, k = e % 9;
-        double s = 0.0;
-        for (int c = pair_chunk_ptr[p]; c < pair_chunk_ptr[p + 1]; ++c) s += partY[9 * c + k];
-        pairY[9 * p + k] = s;
-    }
-    __threadfence_block();
-    __syncthreads();
+    // stage 0: the whole step; stage 1: up to the right-hand side b; stage 2:
+    // from dtheta (formed between the stages by k_ic_matvec) to the pose update
+    if (stage != 2) {
     {
+        // pair sums of the chunk partials (chunks in order; loads unrolled so
+        // that a pair's chunks are fetched together), and the window's energy
+        // statistics as a fixed-order block sum of the pair sums
         double v3[3] = {0.0, 0.0, 0.0};
-        for (int p = p0 + threadIdx.x; p < p1; p += blockDim.x) {
-            v3[0] += pairY[9 * p + 6];
-            v3[1] += pairY[9 * p + 7];
-            v3[2] += pairY[9 * p + 8];
+        for (int e = threadIdx.x; e < (p1 - p0) * 9; e += blockDim.x) {
+            const int p = p0 + e / 9, k = e % 9;
+            const int c0 = pair_chunk_ptr[p], c1 = pair_chunk_ptr[p + 1];
+            double s = 0.0;
+#pragma unroll 8
+            for (int c = c0; c < c1; ++c) s += partY[9 * c + k];
+            pairY[9 * p + k] = s;
+            if (k >= 6) v3[k - 6] += s;
         }
+        __threadfence_block();
         block_sum_d<3>(v3, red);
         if (threadIdx.x == 0) {
             wstat[4 * w + 0] = v3[0];
@@ -505,11 +509,18 @@ __global__ __launch_bounds__(SOLVE_THREADS) void k_solve(
             wstat[4 * w + 2] = v3[2];
         }
     }
-    for (int e = threadIdx.x; e < n; e += blockDim.x) {
-        const int lf = e / 6, r = e % 6, f = f0 + lf;
-        double s = 0.0;
-        if (lf != pinned) {
-            for (int i = frame_pair_ptr[f]; i < frame_pair_ptr[f + 1]; ++i) {
+    // b = sum over the frame's pair items of A_p^T y_p (target) or B_p^T y_p (host),
+    // items added in list order. The item maps are formed in parallel into LDS
+    // (in chunks of what fits beside the rhs), then every row adds its frame's
+    // items of the chunk; rows of the pinned frame stay zero.
+    {
+        double *cb = bx + ((n + 1) & ~1);
+        const int cap_items = (int)((lds + LDS_DOUBLES - cb) / 6);
+        const int i0 = frame_pair_ptr[f0], i1 = frame_pair_ptr[f0 + F];
+        for (int e = threadIdx.x; e < n; e += blockDim.x) bx[e] = 0.0;
+        for (int c0 = i0; c0 < i1; c0 += cap_items) {
+            const int c1 = min(i1, c0 + cap_items);
+            for (int i = c0 + threadIdx.x; i < c1; i += blockDim.x) {
                 const int p = frame_pair_item[i] >> 1, is_host = frame_pair_item[i] & 1;
                 double yv[6], out[6];
                 for (int a = 0; a < 6; ++a) yv[a] = pairY[9 * p + a];
@@ -517,40 +528,69 @@ __global__ __launch_bounds__(SOLVE_THREADS) void k_solve(
                     apply_Bt(geo_lin + GEO_STRIDE * p, yv, out);
                 else
                     apply_At(geo_lin + GEO_STRIDE * p, yv, out);
-                s += out[r];
+                double *o = cb + 6 * (i - c0);
+                for (int a = 0; a < 6; ++a) o[a] = out[a];
             }
+            __syncthreads();
+            for (int e = threadIdx.x; e < n; e += blockDim.x) {
+                const int lf = e / 6, r = e % 6, f = f0 + lf;
+                if (lf == pinned) continue;
+                const int a0 = max(c0, frame_pair_ptr[f]), a1 = min(c1, frame_pair_ptr[f + 1]);
+                double s = bx[e];
+                for (int i = a0; i < a1; ++i) s += cb[6 * (i - c0) + r];
+                bx[e] = s;
+            }
+            __syncthreads();
         }
-        b_out[e] = s;
-        bx[e] = s;
+        for (int e = threadIdx.x; e < n; e += blockDim.x) b_out[e] = bx[e];
     }
     __syncthreads();
-    if (ic) {
-        // dtheta = -S^{-1} b with the inverse formed at p(0). Up to 256 rows: G
-        // consecutive threads per row, each with four independent partial sums
-        // (all of a thread's loads are in flight at once); larger systems: one
-        // wavefront per row.
+    }
+    if (stage == 1) return;
+    if (stage == 2) {
+        // dtheta is in global memory
+    } else if (ic) {
+        // dtheta = -S^{-1} b with the inverse formed at p(0) (stored by
+        // columns; S^{-1} is symmetric). Up to 256 unknowns: NG groups of
+        // threads, each thread one column j and every NG-th row i, so that a
+        // wavefront reads 64 consecutive entries of a row; loads issued in
+        // batches of 12, group partials added in group order.
         if (n <= 256) {
-            const int G = n <= 128 ? 8 : 4;
-            const int i = threadIdx.x / G, q = threadIdx.x % G;
-            double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
-            if (i < n) {
-                const double *row = Sinv + (size_t)i * n;
-                int j = q;
-                for (; j + 3 * G < n; j += 4 * G) {
-                    s0 += row[j] * bx[j];
-                    s1 += row[j + G] * bx[j + G];
-                    s2 += row[j + 2 * G] * bx[j + 2 * G];
-                    s3 += row[j + 3 * G] * bx[j + 3 * G];
+            const int ncw = (n + 63) & ~63;
+            const int NG = blockDim.x / ncw;
+            const int g = threadIdx.x / ncw, j = threadIdx.x % ncw;
+            double *part = bx + ((n + 1) & ~1);
+            double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+            if (g < NG && j < n) {
+                constexpr int U = 12;
+                for (int i0 = g; i0 < n; i0 += U * NG) {
+                    double v[U];
+#pragma unroll
+                    for (int u = 0; u < U; ++u) {
+                        const int i = i0 + u * NG;
+                        v[u] = i < n ? Sinv[(size_t)i * n + j] : 0.0;
+                    }
+#pragma unroll
+                    for (int u = 0; u < U; u += 3) {
+                        const int i = i0 + u * NG;
+                        s0 += v[u] * (i < n ? bx[i] : 0.0);
+                        s1 += v[u + 1] * (i + NG < n ? bx[i + NG] : 0.0);
+                        s2 += v[u + 2] * (i + 2 * NG < n ? bx[i + 2 * NG] : 0.0);
+                    }
                 }
-                for (; j < n; j += G) s0 += row[j] * bx[j];
             }
-            double s = (s0 + s1) + (s2 + s3);
-            for (int k = G / 2; k >= 1; k >>= 1) s += __shfl_xor(s, k, 64);
-            if (i < n && q == 0) dth_out[i] = -s;
+            if (g < NG) part[g * ncw + j] = (s0 + s1) + s2;
+            __syncthreads();
+            if (threadIdx.x < n) {
+                double s = 0.0;
+                for (int q = 0; q < NG; ++q) s += part[q * ncw + threadIdx.x];
+                dth_out[threadIdx.x] = -s;
+            }
         } else {
             for (int i = wv; i < n; i += nw) {
                 const double *row = Sinv + (size_t)i * n;
                 double s = 0.0;
+#pragma unroll 8
                 for (int j = lane; j < n; j += 64) s += row[j] * bx[j];
                 for (int k = 32; k >= 1; k >>= 1) s += __shfl_xor(s, k, 64);
                 if (lane == 0) dth_out[i] = -s;
@@ -657,6 +697,23 @@ __global__ __launch_bounds__(SOLVE_THREADS) void k_solve(
     }
 }
 
+// dtheta = -S^{-1} b of one large window (IC between the two solve stages):
+// one wavefront per row, lane loads unrolled so that several are in flight.
+__global__ __launch_bounds__(256) void k_ic_matvec(int n, const double *__restrict__ Sinv, const double *__restrict__ b,
+                                                   double *__restrict__ dth, const int *__restrict__ flag,
+                                                   const int *__restrict__ gate) {
+    if (*gate == 0 || *flag) return;
+    const int lane = threadIdx.x & 63;
+    const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (i >= n) return;
+    const double *row = Sinv + (size_t)i * n;
+    double s = 0.0;
+#pragma unroll 8
+    for (int j = lane; j < n; j += 64) s += row[j] * b[j];
+    for (int k = 32; k >= 1; k >>= 1) s += __shfl_xor(s, k, 64);
+    if (lane == 0) dth[i] = -s;
+}
+
 // ------------------------------------------------------------ launchers
 
 static inline unsigned nb(size_t n, unsigned b) { return (unsigned)((n + b - 1) / b); }
@@ -706,16 +763,30 @@ void launch_solve(hipStream_t s, Ctx &c, const double *geo_lin, double *geo_next
                   double *stat) {
     (void)stat;
     const int ic = c.cfg.mode == PBA_IC_PROXY ? 1 : 0;
-    if (rel_double)
-        k_solve<double><<<c.nwin, SOLVE_THREADS, 0, s>>>(
-            c.win(), ic, c.tiled() ? 1 : 0, c.cfg.pinned_frame, c.d_frame_pair_ptr, c.d_frame_pair_item, c.d_pair_host, c.d_pair_target,
-            c.d_pair_chunk_ptr, c.d_partY, c.d_pairY, geo_lin, c.d_S, c.d_Sfac, c.d_Linv, c.d_Sinv, c.d_poses,
-            c.d_poses0, c.d_b, c.d_dtheta, c.d_dth_rel, geo_next, (double *)rel_next, c.d_wstat, c.d_flag, c.d_gate);
-    else
-        k_solve<float><<<c.nwin, SOLVE_THREADS, 0, s>>>(
-            c.win(), ic, c.tiled() ? 1 : 0, c.cfg.pinned_frame, c.d_frame_pair_ptr, c.d_frame_pair_item, c.d_pair_host, c.d_pair_target,
-            c.d_pair_chunk_ptr, c.d_partY, c.d_pairY, geo_lin, c.d_S, c.d_Sfac, c.d_Linv, c.d_Sinv, c.d_poses,
-            c.d_poses0, c.d_b, c.d_dtheta, c.d_dth_rel, geo_next, (float *)rel_next, c.d_wstat, c.d_flag, c.d_gate);
+    const int n = 6 * c.F;
+    // IC on one large window: the product with S^{-1} spread over many workgroups
+    const bool split = ic && c.nwin == 1 && n > IC_SPLIT_N;
+    auto solve = [&](int stage) {
+        if (rel_double)
+            k_solve<double><<<c.nwin, SOLVE_THREADS, 0, s>>>(
+                c.win(), ic, c.tiled() ? 1 : 0, c.cfg.pinned_frame, stage, c.d_frame_pair_ptr, c.d_frame_pair_item,
+                c.d_pair_host, c.d_pair_target, c.d_pair_chunk_ptr, c.d_partY, c.d_pairY, geo_lin, c.d_S, c.d_Sfac,
+                c.d_Linv, c.d_Sinv, c.d_poses, c.d_poses0, c.d_b, c.d_dtheta, c.d_dth_rel, geo_next,
+                (double *)rel_next, c.d_wstat, c.d_flag, c.d_gate);
+        else
+            k_solve<float><<<c.nwin, SOLVE_THREADS, 0, s>>>(
+                c.win(), ic, c.tiled() ? 1 : 0, c.cfg.pinned_frame, stage, c.d_frame_pair_ptr, c.d_frame_pair_item,
+                c.d_pair_host, c.d_pair_target, c.d_pair_chunk_ptr, c.d_partY, c.d_pairY, geo_lin, c.d_S, c.d_Sfac,
+                c.d_Linv, c.d_Sinv, c.d_poses, c.d_poses0, c.d_b, c.d_dtheta, c.d_dth_rel, geo_next,
+                (float *)rel_next, c.d_wstat, c.d_flag, c.d_gate);
+    };
+    if (!split) {
+        solve(0);
+        return;
+    }
+    solve(1);
+    k_ic_matvec<<<nb(n, 4), 256, 0, s>>>(n, c.d_Sinv, c.d_b, c.d_dtheta, c.d_flag, c.d_gate);
+    solve(2);
 }
 
 }  // namespace pba
