@@ -179,32 +179,48 @@ def precision_section(pba, steps, max_iters, conv_px):
     t0 = time.perf_counter()
     sc = scenes.precision()
     log(f"scene precision: {sc.n_points} points, {sc.n_obs} observations ({time.perf_counter() - t0:.1f} s)")
-    kw = dict(n_levels=sc.n_levels, pattern=sc.pattern, huber_k=sc.huber_k, flags=pba.PBA_FLAG_TIMING)
+    kw = dict(n_levels=sc.n_levels, pattern=sc.pattern, huber_k=sc.huber_k)
     out = {"workload": "precision: 120 frames 640x480 f32, value-noise torus, 3-level pyramid, 10 hosts x 20000 "
                        "points (4 targets each), 8-px patches; 6F = 720",
            "points": sc.n_points, "observations": sc.n_obs, "residuals_per_iter": sc.n_residuals(),
            "reduced_system": 6 * sc.n_frames}
     p0, d0 = sc.poses_init, sc.inv_depth_init
+    nb = ic_residual_bytes(sc, 0, 4)
     results = {}
     for name, mode, prec, n in (("ic_mixed", pba.PBA_IC_PROXY, pba.PBA_MIXED_BF16, steps),
                                 ("ic_fp64", pba.PBA_IC_PROXY, pba.PBA_FP64, 1),
                                 ("fc_mixed", pba.PBA_FC, pba.PBA_MIXED_BF16, max(1, steps // 2))):
-        s = pba.Solver(mode=mode, precision=prec, **kw)
+        # solves replayed as captured graphs; the residual kernel timed with
+        # events in a second context (events are not captured)
+        s = pba.Solver(mode=mode, precision=prec, flags=pba.PBA_FLAG_GRAPH, **kw)
         s.set_scene(sc)
         s.set_params(p0, d0)
-        s.solve(max_iters, conv_px)  # warm-up
-        s.timing()
+        s.solve(max_iters, conv_px)  # warm-up (captures the graph)
         t, iters, active, res = run_steps(s, p0, d0, n, max_iters, conv_px)
-        tm = s.timing()
         poses, d = s.get_params()
         results[name] = (poses, d)
+        s.close()
+        e = pba.Solver(mode=mode, precision=prec, flags=pba.PBA_FLAG_TIMING, **kw)
+        e.set_scene(sc)
+        e.set_params(p0, d0)
+        e.solve(max_iters, conv_px)
+        e.timing()
+        e.set_params(p0, d0)
+        e.solve(max_iters, conv_px)
+        tm = e.timing()
+        e.close()
+        avg_us = tm["residual_ms"][0] / max(1, tm["residual_launches"][0]) * 1e3
         out[name] = {"ms_per_solve": round(float(np.mean(t)) * 1e3, 3), "iters_per_solve": res[-1]["iters"],
                      "gn_iters_per_s": round(iters / float(np.sum(t)), 2),
                      "residuals_per_s": round(active / float(np.sum(t)), 1), "final_rmse": res[-1]["final_rmse"],
-                     "residual_kernel_avg_us_level0": round(tm["residual_ms"][0] / max(1, tm["residual_launches"][0])
-                                                            * 1e3, 3)}
-        s.close()
-        log(f"precision {name}: {out[name]['ms_per_solve']} ms per solve")
+                     "residual_kernel_avg_us_level0": round(avg_us, 3)}
+        if mode == pba.PBA_IC_PROXY and prec == pba.PBA_MIXED_BF16 and avg_us > 0:
+            gbs = nb["bytes"] / (avg_us * 1e-6) / 1e9
+            out["residual_roofline"] = {"kernel": "k_ic_residual<float> (level 0)", "bound": "hbm",
+                                        "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                        "frac": round(gbs / HBM_PEAK_GBS, 4), "avg_launch_us": round(avg_us, 3),
+                                        "algorithmic_bytes_per_launch": nb["bytes"], "bytes_detail": nb}
+        log(f"precision {name}: {out[name]['ms_per_solve']} ms per solve, residual kernel {avg_us:.1f} us")
     out["ic_mixed_vs_fp64"] = param_errors(*results["ic_mixed"], *results["ic_fp64"])
     out["ic_mixed_rmse_rel_vs_fp64"] = abs(out["ic_mixed"]["final_rmse"] / out["ic_fp64"]["final_rmse"] - 1)
     out["note"] = ("errors of the mixed-form IC solve against the FP64 IC solve of the same problem (same "

@@ -54,74 +54,159 @@ __device__ __forceinline__ double readlane_d(double v, int l) {
     return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+constexpr int SP = 17;   // LDS pitch of the 16 x 16 scratch blocks
+
 // Factor the LDS tile t = L L^T in place (rows and columns >= nb are made the
 // identity first), and write L^{-1} (identity on the padding) to Linv_g.
-// Called by a whole 256-thread block; wavefront 0 does the work with the tile
-// in registers (lane r holds row r): each column step reads the pivot and the
-// column's entries of the other rows with scalar lane reads, so the 32 steps
-// need no LDS round trips or barriers. Lane c then forms column c of L^{-1} by
-// forward substitution. Returns false in every thread when a pivot is not
-// positive.
-__device__ __forceinline__ bool tile_potrf_inv(double *t, int nb, double *__restrict__ Linv_g, double *invd, int *fail) {
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+// Called by a whole 256-thread block; wavefront 0 does the work, blocked 2 x 2
+// in 16-wide panels. Panel 1 (columns 0-15 of all 32 rows) and, after the
+// update A22 -= L21 L21^T on FP64 MFMA, panel 2 (A22) are factored with the
+// rows in registers (lane r holds row r): each column step reads the pivot and
+// the column's entries with scalar lane reads, without LDS round trips. The
+// inverse is [X11 0; X21 X22] with X11 = L11^{-1} and X22 = L22^{-1} formed
+// at once by forward substitution (lane c of each half one column) and
+// X21 = -X22 (L21 X11) as two MFMA products. s1, s2: LDS scratch of 16 x SP
+// doubles each. Returns false in every thread when a pivot is not positive.
+__device__ __forceinline__ bool tile_potrf_inv(double *t, int nb, double *__restrict__ Linv_g, double *invd,
+                                               double *s1, double *s2, int *fail) {
+    const int l = threadIdx.x & 63, wv = threadIdx.x >> 6;
     if (threadIdx.x == 0) *fail = 0;
     __syncthreads();
     if (wv == 0) {
-        double row[TB];
+        if (nb < TB && l < TB) {
 #pragma unroll
-        for (int c = 0; c < TB; ++c) {
-            double v = 0.0;
-            if (lane < TB) v = (lane < nb && c < nb) ? tl(t, lane, c) : (lane == c ? 1.0 : 0.0);
-            row[c] = v;
+            for (int c = 0; c < TB; ++c)
+                if (l >= nb || c >= nb) tl(t, l, c) = (l == c) ? 1.0 : 0.0;
         }
+        wave_sync();
         bool ok = true;
+        double row[16];
+        // panel 1: columns 0..15 of rows 0..31 (L11 and L21)
 #pragma unroll
-        for (int j = 0; j < TB; ++j) {
+        for (int c = 0; c < 16; ++c) row[c] = l < TB ? tl(t, l, c) : 0.0;
+#pragma unroll
+        for (int j = 0; j < 16; ++j) {
             const double p = readlane_d(row[j], j);
             ok = ok && p > 0.0;
-            const double l = sqrt(p > 0.0 ? p : 1.0), inv = 1.0 / l;
-            const double a = lane > j ? row[j] * inv : (lane == j ? l : row[j]);
+            const double lj = sqrt(p > 0.0 ? p : 1.0), inv = 1.0 / lj;
+            const double a = l > j ? row[j] * inv : (l == j ? lj : row[j]);
             row[j] = a;
 #pragma unroll
-            for (int c = j + 1; c < TB; ++c) {
+            for (int c = j + 1; c < 16; ++c) {
                 const double ac = readlane_d(a, c);
-                if (lane >= c && lane < TB) row[c] -= a * ac;
+                if (l >= c && l < TB) row[c] -= a * ac;
+            }
+        }
+        if (l < TB) {
+#pragma unroll
+            for (int c = 0; c < 16; ++c) tl(t, l, c) = c <= l ? row[c] : 0.0;
+        }
+        wave_sync();
+        // A22 -= L21 L21^T (element i of lane l: row 16 + l / 16 + 4 i, column 16 + l % 16)
+        {
+            f64x4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+            for (int s = 0; s < 4; ++s) {
+                const double av = tl(t, 16 + (l & 15), 4 * s + (l >> 4));
+                acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, av, acc, 0, 0, 0);
+            }
+#pragma unroll
+            for (int i = 0; i < 4; ++i) tl(t, 16 + (l >> 4) + 4 * i, 16 + (l & 15)) -= acc[i];
+        }
+        wave_sync();
+        // panel 2: A22 on lanes 16..31
+#pragma unroll
+        for (int c = 0; c < 16; ++c) row[c] = (l >= 16 && l < TB) ? tl(t, l, 16 + c) : 0.0;
+#pragma unroll
+        for (int j = 0; j < 16; ++j) {
+            const double p = readlane_d(row[j], 16 + j);
+            ok = ok && p > 0.0;
+            const double lj = sqrt(p > 0.0 ? p : 1.0), inv = 1.0 / lj;
+            const double a = l > 16 + j ? row[j] * inv : (l == 16 + j ? lj : row[j]);
+            row[j] = a;
+#pragma unroll
+            for (int c = j + 1; c < 16; ++c) {
+                const double ac = readlane_d(a, 16 + c);
+                if (l >= 16 + c && l < TB) row[c] -= a * ac;
             }
         }
         if (!ok) {
-            if (lane == 0) *fail = 1;
+            if (l == 0) *fail = 1;
         } else {
-            if (lane < TB) {
+            if (l >= 16 && l < TB) {
 #pragma unroll
-                for (int c = 0; c < TB; ++c) tl(t, lane, c) = c <= lane ? row[c] : 0.0;
+                for (int c = 0; c < 16; ++c) tl(t, l, 16 + c) = 16 + c <= l ? row[c] : 0.0;
             }
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-            if (lane < TB) invd[lane] = 1.0 / tl(t, lane, lane);
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-            // column `lane` of L^{-1}: x[i] = (delta_i,lane - sum_k<i L(i, k) x[k]) / L(i, i)
-            // (every lane reads the same L(i, k): LDS broadcasts; four partial
-            // sums shorten the dependent chains)
-            double x[TB];
+            if (l < 16) {
 #pragma unroll
-            for (int i = 0; i < TB; ++i) {
-                double s0 = (i == lane) ? 1.0 : 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+                for (int c = 0; c < 16; ++c) tl(t, l, 16 + c) = 0.0;
+            }
+            wave_sync();
+            if (l < TB) invd[l] = 1.0 / tl(t, l, l);
+            wave_sync();
+            // X11 (lanes 0..15, column l) and X22 (lanes 16..31, column l - 16):
+            // x[i] = (delta_i,c - sum_k<i L(i, k) x[k]) / L(i, i) within the half,
+            // four partial sums to shorten the dependent chains
+            const int base = l < 16 ? 0 : 16, cc = l & 15;
+            double x[16];
+#pragma unroll
+            for (int i = 0; i < 16; ++i) {
+                double q0 = (i == cc) ? 1.0 : 0.0, q1 = 0.0, q2 = 0.0, q3 = 0.0;
 #pragma unroll
                 for (int k = 0; k < i; k += 4) {
-                    s0 -= tl(t, i, k) * x[k];
-                    if (k + 1 < i) s1 -= tl(t, i, k + 1) * x[k + 1];
-                    if (k + 2 < i) s2 -= tl(t, i, k + 2) * x[k + 2];
-                    if (k + 3 < i) s3 -= tl(t, i, k + 3) * x[k + 3];
+                    q0 -= tl(t, base + i, base + k) * x[k];
+                    if (k + 1 < i) q1 -= tl(t, base + i, base + k + 1) * x[k + 1];
+                    if (k + 2 < i) q2 -= tl(t, base + i, base + k + 2) * x[k + 2];
+                    if (k + 3 < i) q3 -= tl(t, base + i, base + k + 3) * x[k + 3];
                 }
-                x[i] = (i >= lane) ? ((s0 + s1) + (s2 + s3)) * invd[i] : 0.0;
+                x[i] = (i >= cc) ? ((q0 + q1) + (q2 + q3)) * invd[base + i] : 0.0;
             }
-            if (lane < TB) {
+            // s1 = X11^T, s2 = X22^T (row c holds column c)
+            if (l < TB) {
+                double *sx = l < 16 ? s1 : s2;
 #pragma unroll
-                for (int i = 0; i < TB; ++i) Linv_g[i * TB + lane] = x[i];
+                for (int i = 0; i < 16; ++i) sx[cc * SP + i] = x[i];
             }
+            wave_sync();
+            // P = L21 X11 (rows of L21 against rows of X11^T)
+            f64x4 pacc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+            for (int s = 0; s < 4; ++s) {
+                const double av = tl(t, 16 + (l & 15), 4 * s + (l >> 4));
+                const double bv = s1[(l & 15) * SP + 4 * s + (l >> 4)];
+                pacc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, pacc, 0, 0, 0);
+            }
+            wave_sync();
+            // P row-major into s1 (X11 stays in the registers of lanes 0..15)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) s1[((l >> 4) + 4 * i) * SP + (l & 15)] = pacc[i];
+            wave_sync();
+            // X21 = -X22 P (rows of X22 = columns of s2 against rows of P^T = columns of s1)
+            f64x4 xacc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+            for (int s = 0; s < 4; ++s) {
+                const double av = s2[(4 * s + (l >> 4)) * SP + (l & 15)];
+                const double bv = s1[(4 * s + (l >> 4)) * SP + (l & 15)];
+                xacc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, xacc, 0, 0, 0);
+            }
+            if (l < 16) {
+#pragma unroll
+                for (int i = 0; i < 16; ++i) {
+                    Linv_g[i * TB + l] = x[i];
+                    Linv_g[i * TB + 16 + l] = 0.0;
+                }
+            } else if (l < TB) {
+#pragma unroll
+                for (int i = 0; i < 16; ++i) Linv_g[(16 + i) * TB + l] = x[i];
+            }
+#pragma unroll
+            for (int i = 0; i < 4; ++i) Linv_g[(16 + (l >> 4) + 4 * i) * TB + (l & 15)] = -xacc[i];
         }
     }
     __syncthreads();
@@ -139,12 +224,13 @@ __device__ __forceinline__ void chol_fail(int *flag, int *gate) {
 __global__ __launch_bounds__(256) void k_tchol_first(int n, double *__restrict__ A, double *__restrict__ Linv,
                                                      int *__restrict__ flag, int *__restrict__ gate) {
     __shared__ double t[TB * TP];
+    __shared__ double s1[16 * SP], s2[16 * SP];
     __shared__ double invd[TB];
     __shared__ int fail;
     if (*gate == 0 || *flag) return;
     load_tile(A, n, 0, 0, t);
     __syncthreads();
-    if (!tile_potrf_inv(t, min(TB, n), Linv, invd, &fail)) {
+    if (!tile_potrf_inv(t, min(TB, n), Linv, invd, s1, s2, &fail)) {
         chol_fail(flag, gate);
         return;
     }
@@ -198,7 +284,8 @@ __global__ __launch_bounds__(256) void k_tchol_update(int n, int kt, double *__r
     for (int q = 0; q < 4; ++q) tl(tc, 16 * qr + (l >> 4) + 4 * q, 16 * qc + (l & 15)) -= acc[q];
     __syncthreads();
     if (I == kt + 1 && J == kt + 1) {
-        if (!tile_potrf_inv(tc, min(TB, n - TB * I), Linv + (size_t)I * TB * TB, invd, &fail)) {
+        // ti and tj are free once the update is in tc: scratch of the factor
+        if (!tile_potrf_inv(tc, min(TB, n - TB * I), Linv + (size_t)I * TB * TB, invd, ti, tj, &fail)) {
             chol_fail(flag, gate);
             return;
         }

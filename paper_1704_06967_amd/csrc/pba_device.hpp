@@ -146,6 +146,51 @@ __device__ __forceinline__ void abs_maps(const double *geo, double A[36], double
         }
 }
 
+// Entry (i, j) of [v]_x for v given by a callable component getter.
+__device__ __forceinline__ double cross_entry(double v0, double v1, double v2, int i, int j) {
+    if (i == j) return 0.0;
+    const int m = 3 - i - j;
+    const double vm = m == 0 ? v0 : (m == 1 ? v1 : v2);
+    return ((j - i + 3) % 3 == 1) ? -vm : vm;
+}
+
+// Column r of A and of B (the maps formed by abs_maps), computed entry by entry
+// into registers (no indexed private arrays): a[k] = A(k, r), b[k] = B(k, r).
+__device__ __forceinline__ void abs_map_columns(const double *geo, int r, double a[6], double b[6]) {
+    const double *R = geo, *th = geo + 12;
+    const double Rt0 = R[0] * th[0] + R[1] * th[1] + R[2] * th[2];
+    const double Rt1 = R[3] * th[0] + R[4] * th[1] + R[5] * th[2];
+    const double Rt2 = R[6] * th[0] + R[7] * th[1] + R[8] * th[2];
+    const bool rw = r < 3;           // rotation column
+    const int rr = rw ? r : r - 3;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        // rows 0-2: A = [I 0], B = [-R 0]
+        a[k] = (k == r) ? 1.0 : 0.0;
+        b[k] = rw ? -R[3 * k + rr] : 0.0;
+        // rows 3-5: A = [[R t_h]_x I], B = [-R [t_h]_x  -R]
+        double rth = 0.0;
+#pragma unroll
+        for (int q = 0; q < 3; ++q) rth += R[3 * k + q] * cross_entry(th[0], th[1], th[2], q, rr);
+        a[3 + k] = rw ? cross_entry(Rt0, Rt1, Rt2, k, rr) : ((3 + k == r) ? 1.0 : 0.0);
+        b[3 + k] = rw ? -rth : -R[3 * k + rr];
+    }
+}
+
+// x^T H y for 6-vectors and H given by its upper triangle (row-major).
+__device__ __forceinline__ double quad6(const double x[6], const double *H21, const double y[6]) {
+    double s = 0.0;
+    int e = 0;
+#pragma unroll
+    for (int a = 0; a < 6; ++a) {
+        s += x[a] * H21[e] * y[a];
+        ++e;
+#pragma unroll
+        for (int b = a + 1; b < 6; ++b, ++e) s += H21[e] * (x[a] * y[b] + x[b] * y[a]);
+    }
+    return s;
+}
+
 // The same maps applied to 6-vectors without forming them (geo = R_fh, t_fh, t_h):
 //   A x   = (x_w, (R t_h) x x_w + x_t)            A^T y = (y_w - (R t_h) x y_t, y_t)
 //   B x   = (-R x_w, -R (t_h x x_w + x_t))        B^T y = (-R^T y_w + t_h x (R^T y_t), -R^T y_t)

@@ -17,7 +17,6 @@ constexpr int WNS = 3;                        // rows per lane in the wavefront 
 constexpr int GRAM_G = 32;                    // points per Gram step
 constexpr int GRAM_SLOTS = 8;                 // observation slots per point per load pass
 constexpr int GRAM_EMAX = 6 * (MAX_HOST_TARGETS + 1);
-constexpr int GRAM_KMAX = (GRAM_EMAX * GRAM_EMAX + 255) / 256;
 
 __device__ __forceinline__ double sym21(const double *u, int a, int b) {
     // upper triangle (row-major) of a symmetric 6x6
@@ -89,9 +88,9 @@ __global__ __launch_bounds__(1024) void k_mu(WinArgs wa, double damping, const i
     double v[2] = {0.0, 0.0};
     for (int e = threadIdx.x; e < (p1 - p0) * 6; e += blockDim.x) {
         const int p = p0 + e / 6, r = e % 6;
-        double A[36], B[36];
-        abs_maps(geo + GEO_STRIDE * p, A, B);
-        v[0] += xthy(A, pairH + 21 * p, A, r, r) + xthy(B, pairH + 21 * p, B, r, r);
+        double a[6], bcol[6];
+        abs_map_columns(geo + GEO_STRIDE * p, r, a, bcol);
+        v[0] += quad6(a, pairH + 21 * p, a) + quad6(bcol, pairH + 21 * p, bcol);
     }
     const int n0 = wa.point_off[w], n1 = wa.point_off[w + 1];
     for (int n = n0 + threadIdx.x; n < n1; n += blockDim.x) v[1] += Hdd[n];
@@ -136,32 +135,43 @@ __global__ __launch_bounds__(256) void k_obs_map(int O, const int *__restrict__ 
 }
 
 // Depth Schur complement, one chunk of one host frame's points per block:
-// T += u_n u_n^T with u_n = [A_1^T h_1, ..., A_m^T h_m, sum_o B_o^T h_o] / sqrt(H_dd,n),
+// T += U^T U with row n of U = [A_1^T h_1, ..., A_m^T h_m, sum_o B_o^T h_o] / sqrt(H_dd,n),
 // the coupling of point n to each of the host's target frames and to the host,
-// in absolute coordinates. T is (6(m+1))^2, every entry owned by one thread.
+// in absolute coordinates. T is E x E, E = 6 (m + 1). Every step stages U^T for
+// GRAM_G points in LDS (E padded to a multiple of 16) and adds U^T U on FP64
+// MFMA (v_mfma_f64_16x16x4, K = GRAM_G): each wavefront owns a fixed set of
+// 16 x 16 output tiles whose accumulators stay in registers across the steps.
+typedef double gram_f64x4 __attribute__((ext_vector_type(4)));
+constexpr int GRAM_EP = (GRAM_EMAX + 15) / 16 * 16;   // padded E
+constexpr int GRAM_TP = GRAM_G + 1;                   // LDS pitch of U^T rows
+constexpr int GRAM_TILES = (GRAM_EP / 16) * (GRAM_EP / 16);
+constexpr int GRAM_TPW = (GRAM_TILES + 3) / 4;        // output tiles per wavefront (4 wavefronts)
+
 __global__ __launch_bounds__(256) void k_gram(const int *__restrict__ chunk_host, const int *__restrict__ chunk_begin,
                                               const int *__restrict__ chunk_end, const int *__restrict__ chunk_off,
                                               const int *__restrict__ host_m, const int *__restrict__ host_pts,
                                               const int *__restrict__ obs_ptr, const int *__restrict__ obs_pair,
                                               const int *__restrict__ pair_local, const double *__restrict__ map,
                                               double *__restrict__ gram, const int *__restrict__ gate) {
-    __shared__ double u[GRAM_G][GRAM_EMAX];
+    static_assert(GRAM_G % 4 == 0, "MFMA K steps of 4 points");
+    __shared__ double ut[GRAM_EP * GRAM_TP];
     __shared__ double ub[GRAM_G][GRAM_SLOTS][6];
     if (*gate == 0) return;
     const int c = blockIdx.x;
     const int m = host_m[chunk_host[c]];
     const int E = 6 * (m + 1);
-    const int EE = E * E;
-    double acc[GRAM_KMAX];
+    const int nt = (E + 15) / 16;
+    const int l = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    gram_f64x4 acc[GRAM_TPW];
 #pragma unroll
-    for (int k = 0; k < GRAM_KMAX; ++k) acc[k] = 0.0;
+    for (int k = 0; k < GRAM_TPW; ++k) acc[k] = gram_f64x4{0.0, 0.0, 0.0, 0.0};
     for (int base = chunk_begin[c]; base < chunk_end[c]; base += GRAM_G) {
         const int G = min(GRAM_G, chunk_end[c] - base);
-        for (int e = threadIdx.x; e < GRAM_G * GRAM_EMAX; e += blockDim.x) (&u[0][0])[e] = 0.0;
+        for (int e = threadIdx.x; e < 16 * nt * GRAM_TP; e += blockDim.x) ut[e] = 0.0;
         __syncthreads();
         {
-            // one observation slot per thread: its target block goes straight to u,
-            // its host block is summed over the point's observations below
+            // one observation slot per thread: its target block goes straight to
+            // U^T, its host block is summed over the point's observations below
             const int q = threadIdx.x / GRAM_SLOTS, slot = threadIdx.x % GRAM_SLOTS;
             double hb[6] = {0, 0, 0, 0, 0, 0};
             if (q < G) {
@@ -170,7 +180,7 @@ __global__ __launch_bounds__(256) void k_gram(const int *__restrict__ chunk_host
                     const double *mo = map + 12 * (size_t)o;
                     const int i6 = 6 * pair_local[obs_pair[o]];
                     for (int r = 0; r < 6; ++r) {
-                        u[q][i6 + r] = mo[r];
+                        ut[(i6 + r) * GRAM_TP + q] = mo[r];
                         hb[r] += mo[6 + r];
                     }
                 }
@@ -182,25 +192,40 @@ __global__ __launch_bounds__(256) void k_gram(const int *__restrict__ chunk_host
             const int q = threadIdx.x / 6, r = threadIdx.x % 6;
             double s = 0.0;
             for (int k = 0; k < GRAM_SLOTS; ++k) s += ub[q][k][r];
-            u[q][6 * m + r] = s;
+            ut[(6 * m + r) * GRAM_TP + q] = s;
         }
         __syncthreads();
+        // tile t = (I, J) of U^T U: rows 16 I .., columns 16 J .. of T
 #pragma unroll
-        for (int k = 0; k < GRAM_KMAX; ++k) {
-            const int e = threadIdx.x + 256 * k;
-            if (e < EE) {
-                const int a = e / E, b = e % E;
-                double s = 0.0;
-                for (int q = 0; q < G; ++q) s += u[q][a] * u[q][b];
-                acc[k] += s;
+        for (int k = 0; k < GRAM_TPW; ++k) {
+            const int t = wv + 4 * k;
+            if (t < nt * nt) {
+                const int I = t / nt, J = t % nt;
+                gram_f64x4 a4 = acc[k];
+#pragma unroll
+                for (int s = 0; s < GRAM_G / 4; ++s) {
+                    const double av = ut[(16 * I + (l & 15)) * GRAM_TP + 4 * s + (l >> 4)];
+                    const double bv = ut[(16 * J + (l & 15)) * GRAM_TP + 4 * s + (l >> 4)];
+                    a4 = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, a4, 0, 0, 0);
+                }
+                acc[k] = a4;
             }
         }
         __syncthreads();
     }
+    // element i of lane l: row 16 I + l / 16 + 4 i, column 16 J + l % 16
 #pragma unroll
-    for (int k = 0; k < GRAM_KMAX; ++k) {
-        const int e = threadIdx.x + 256 * k;
-        if (e < EE) gram[(size_t)chunk_off[c] + e] = acc[k];
+    for (int k = 0; k < GRAM_TPW; ++k) {
+        const int t = wv + 4 * k;
+        if (t < nt * nt) {
+            const int I = t / nt, J = t % nt;
+            const int col = 16 * J + (l & 15);
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int row = 16 * I + (l >> 4) + 4 * i;
+                if (row < E && col < E) gram[(size_t)chunk_off[c] + (size_t)row * E + col] = acc[k][i];
+            }
+        }
     }
 }
 
@@ -227,18 +252,24 @@ __global__ __launch_bounds__(64) void k_assemble_s(WinArgs wa, int pinned, const
     double val = 0.0;
     for (int i = pp_ptr[b]; i < pp_ptr[b + 1]; ++i) {
         const int p = pp_item[i] >> 2, kind = pp_item[i] & 3;
-        double A[36], B[36];
-        abs_maps(geo + GEO_STRIDE * p, A, B);
-        const double *X = (kind == 0 || kind == 2) ? A : B;
-        const double *Y = (kind == 0 || kind == 3) ? A : B;
-        val += xthy(X, pairH + 21 * p, Y, r, c);
+        double ar[6], br[6], ac[6], bc[6], x[6], y[6];
+        abs_map_columns(geo + GEO_STRIDE * p, r, ar, br);
+        abs_map_columns(geo + GEO_STRIDE * p, c, ac, bc);
+#pragma unroll
+        for (int k = 0; k < 6; ++k) {
+            x[k] = (kind == 0 || kind == 2) ? ar[k] : br[k];
+            y[k] = (kind == 0 || kind == 3) ? ac[k] : bc[k];
+        }
+        val += quad6(x, pairH + 21 * p, y);
     }
     for (int i = g_ptr[b]; i < g_ptr[b + 1]; ++i) {
         const int it = g_item[i];
         const int hi = it >> 12, a = (it >> 6) & 63, bb = it & 63;
         const int E = 6 * (host_m[hi] + 1);
         const size_t idx = (size_t)(6 * a + r) * E + 6 * bb + c;
-        for (int ch = host_chunk_ptr[hi]; ch < host_chunk_ptr[hi + 1]; ++ch) val -= gram[(size_t)chunk_off[ch] + idx];
+        const int ch0 = host_chunk_ptr[hi], ch1 = host_chunk_ptr[hi + 1];
+#pragma unroll 8
+        for (int ch = ch0; ch < ch1; ++ch) val -= gram[(size_t)chunk_off[ch] + idx];
     }
     if (fa == fb && r == c) val += mu[2 * w];
     if (pinned >= 0 && (la == pinned || lb == pinned)) val = (fa == fb && r == c) ? 1.0 : 0.0;

@@ -22,23 +22,36 @@ __device__ void tile_chol_solve(const double *__restrict__ L, const double *__re
                                 double *tmp, int k0) {
     const int nt = (n + TB - 1) / TB;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    constexpr int NW = NT / 64, Q = NT / TB, RP = NT / TB;
+    constexpr int NW = NT / 64, Q = NT / TB, RP = NT / TB, RPW = TB / NW;
     static_assert(Q <= TB, "partials per column exceed a 32-lane sum");
     double *t = tmp + TB * Q;
     double *lv = t + TB;                                   // [TB][TB + 1]
     const int kk = threadIdx.x & (TB - 1), rr = threadIdx.x / TB;
     for (int K = k0; K < nt; ++K) {
         const int r0 = TB * K;
-        // t_r = x_r - sum_{c < r0} L(r0 + r, c) x_c: one wavefront per row, lanes over columns
-        for (int r = wv; r < TB; r += NW) {
-            double s = 0.0;
-            if (r0 + r < n) {
-                const double *Lr = L + (size_t)(r0 + r) * n;
-#pragma unroll 8
-                for (int c = TB * k0 + lane; c < r0; c += 64) s += Lr[c] * x[c];
+        // t_r = x_r - sum_{c < r0} L(r0 + r, c) x_c: wavefront wv owns rows
+        // wv + NW u, lanes over columns; the rows' loads are interleaved so that
+        // all of them are in flight together
+        {
+            double s[RPW];
+#pragma unroll
+            for (int u = 0; u < RPW; ++u) s[u] = 0.0;
+#pragma unroll 2
+            for (int c = TB * k0 + lane; c < r0; c += 64) {
+                const double xc = x[c];
+#pragma unroll
+                for (int u = 0; u < RPW; ++u) {
+                    const int r = wv + NW * u;
+                    if (r0 + r < n) s[u] += L[(size_t)(r0 + r) * n + c] * xc;
+                }
             }
-            for (int o = 32; o >= 1; o >>= 1) s += __shfl_xor(s, o, 64);
-            if (lane == 0) t[r] = (r0 + r < n) ? x[r0 + r] - s : 0.0;
+#pragma unroll
+            for (int u = 0; u < RPW; ++u) {
+                const int r = wv + NW * u;
+                double v = s[u];
+                for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+                if (lane == 0) t[r] = (r0 + r < n) ? x[r0 + r] - v : 0.0;
+            }
         }
         {
             const double *Lk = Linv + (size_t)K * TB * TB;
