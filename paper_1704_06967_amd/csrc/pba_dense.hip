@@ -294,7 +294,30 @@ __global__ __launch_bounds__(256) void k_tchol_update(int n, int kt, double *__r
 }
 
 // S^{-1} column by column from the tiled factor (one column per block; by
-// symmetry it is stored as a row).
+// symmetry it is stored as a row). Up to TINV_LDS_N unknowns every block first
+// copies the packed factor into LDS, so that the tile steps read only LDS.
+constexpr int TINV_LDS_DOUBLES = 18688;   // packed factor, column and solve scratch (146 KB)
+constexpr int TINV_LDS_THREADS = 1024;
+constexpr int tinv_lds_need(int n) { return n * (n + 1) / 2 + n + TILE_PACKED_TMP; }
+
+__global__ __launch_bounds__(TINV_LDS_THREADS) void k_tinv_columns_lds(int n, const double *__restrict__ L,
+                                                                      const double *__restrict__ Linv,
+                                                                      double *__restrict__ Sinv,
+                                                                      const int *__restrict__ flag,
+                                                                      const int *__restrict__ gate) {
+    __shared__ double lds[TINV_LDS_DOUBLES];
+    if (*gate == 0 || *flag) return;
+    double *Lp = lds, *x = Lp + n * (n + 1) / 2, *tmp = x + n;
+    load_packed_lower<TINV_LDS_THREADS>(L, n, Lp);
+    for (int col = blockIdx.x; col < n; col += gridDim.x) {
+        for (int i = threadIdx.x; i < n; i += blockDim.x) x[i] = (i == col) ? 1.0 : 0.0;
+        __syncthreads();
+        tile_chol_solve_packed<TINV_LDS_THREADS>(Lp, Linv, n, x, tmp, col / TB);
+        for (int i = threadIdx.x; i < n; i += blockDim.x) Sinv[(size_t)col * n + i] = x[i];
+        __syncthreads();
+    }
+}
+
 __global__ __launch_bounds__(256) void k_tinv_columns(int n, const double *__restrict__ L,
                                                       const double *__restrict__ Linv, double *__restrict__ Sinv,
                                                       const int *__restrict__ flag, const int *__restrict__ gate) {
@@ -356,8 +379,12 @@ void launch_tchol(hipStream_t s, Ctx &c) {
 
 void launch_tinv(hipStream_t s, Ctx &c) {
     const int n = 6 * c.F;
-    const size_t lds = ((size_t)n + tile_solve_tmp(256)) * sizeof(double);
-    k_tinv_columns<<<std::min(n, 2048), 256, lds, s>>>(n, c.d_Sfac, c.d_Linv, c.d_Sinv, c.d_flag, c.d_gate);
+    if (tinv_lds_need(n) <= TINV_LDS_DOUBLES) {
+        k_tinv_columns_lds<<<std::min(n, 2048), TINV_LDS_THREADS, 0, s>>>(n, c.d_Sfac, c.d_Linv, c.d_Sinv, c.d_flag, c.d_gate);
+    } else {
+        const size_t lds = ((size_t)n + tile_solve_tmp(256)) * sizeof(double);
+        k_tinv_columns<<<std::min(n, 2048), 256, lds, s>>>(n, c.d_Sfac, c.d_Linv, c.d_Sinv, c.d_flag, c.d_gate);
+    }
 }
 
 }  // namespace pba
