@@ -353,18 +353,14 @@ pba_status one_iteration(Ctx &c, int level, double *stat, hipEvent_t ev0, hipEve
     T *rel_cur = (T *)(c.flip ? c.d_rel_b : c.d_rel_a);
     T *rel_next = (T *)(c.flip ? c.d_rel_a : c.d_rel_b);
     if (c.cfg.mode == PBA_IC_PROXY) {
-        if (ev0) HIPCHK(hipEventRecord(ev0, s));
-        Launch<T>::ic_residual(s, c, level, rel_cur);
-        if (ev1) HIPCHK(hipEventRecord(ev1, s));
+        Launch<T>::ic_residual(s, c, level, rel_cur, ev0, ev1);
         Launch<T>::pair_reduce_y(s, c);
         launch_solve(s, c, c.d_geo0, geo_next, rel_next, is_fp64(c), stat);
     } else {
-        if (ev0) HIPCHK(hipEventRecord(ev0, s));
         if (is_mixed(c))
-            launch_linearize_mixed(s, c, level, false, (const float *)rel_cur, c.iters_in_level == 0);
+            launch_linearize_mixed(s, c, level, false, (const float *)rel_cur, c.iters_in_level == 0, ev0, ev1);
         else
-            Launch<T>::fc_linearize(s, c, level, rel_cur, c.iters_in_level == 0);
-        if (ev1) HIPCHK(hipEventRecord(ev1, s));
+            Launch<T>::fc_linearize(s, c, level, rel_cur, c.iters_in_level == 0, ev0, ev1);
         Launch<T>::point_reduce(s, c, true);
         if (!is_mixed(c)) Launch<T>::pair_reduce_H(s, c);
         launch_mu(s, c, geo_cur);

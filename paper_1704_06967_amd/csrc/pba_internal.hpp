@@ -240,10 +240,14 @@ template <typename T> struct Launch {
     static void make_template(hipStream_t s, Ctx &c, int level);
     static void relpose(hipStream_t s, Ctx &c, const double *poses, double *geo, T *rel);
     static void ic_linearize(hipStream_t s, Ctx &c, int level);
-    static void ic_residual(hipStream_t s, Ctx &c, int level, const T *rel_cur);
-    static void ic_residual_shape(hipStream_t s, Ctx &c, int level, const T *rel_cur, LaunchShape sh);
+    // e0 / e1 (optional): events recorded by the dispatch itself at the kernel's start and end
+    static void ic_residual(hipStream_t s, Ctx &c, int level, const T *rel_cur, hipEvent_t e0 = nullptr,
+                            hipEvent_t e1 = nullptr);
+    static void ic_residual_shape(hipStream_t s, Ctx &c, int level, const T *rel_cur, LaunchShape sh,
+                                  hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
     static void fc_linearize_shape(hipStream_t s, Ctx &c, int level, const T *rel_cur, LaunchShape sh);
-    static void fc_linearize(hipStream_t s, Ctx &c, int level, const T *rel_cur, bool write_mask);
+    static void fc_linearize(hipStream_t s, Ctx &c, int level, const T *rel_cur, bool write_mask,
+                             hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
     static void evaluate(hipStream_t s, Ctx &c, int level);
     static void point_reduce(hipStream_t s, Ctx &c, bool with_hdd);
     static void pair_reduce_H(hipStream_t s, Ctx &c);
@@ -268,7 +272,8 @@ void pc_resid(hipStream_t s, Ctx &c, int n, const double *x, double *part);   //
 void launch_tsolve(hipStream_t s, Ctx &c, const double *b, double *x);        // x = -S^{-1} b, tiled factor
 
 // mixed precision linearization (pair order, BF16 MFMA pose blocks into the pair chunk partials)
-void launch_linearize_mixed(hipStream_t s, Ctx &c, int level, bool ic, const float *rel_cur, bool write_mask);
+void launch_linearize_mixed(hipStream_t s, Ctx &c, int level, bool ic, const float *rel_cur, bool write_mask,
+                            hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 
 // precision-independent launchers (double only)
 void launch_mu(hipStream_t s, Ctx &c, const double *geo);

@@ -6,6 +6,8 @@
 // record of Gauss-Newton blocks in relative-pose coordinates. Every later
 // reduction (per point, per pair, per frame) runs in a fixed order in FP64, so
 // results are bitwise reproducible run to run (no floating-point atomics).
+#include <hip/hip_ext.h>
+
 #include "pba_device.hpp"
 #include "pba_internal.hpp"
 
@@ -878,6 +880,16 @@ void Launch<T>::relpose(hipStream_t s, Ctx &c, const double *poses, double *geo,
     CHECK_LAUNCH();
 }
 
+// Launch, with the start and end of the kernel recorded into e0 / e1 by the
+// dispatch itself when they are given (timing of the kernel alone).
+template <typename K, typename... A>
+static void launch_ev(K kernel, unsigned g, unsigned b, hipStream_t s, hipEvent_t e0, hipEvent_t e1, A... args) {
+    if (e0 || e1)
+        hipExtLaunchKernelGGL(kernel, dim3(g), dim3(b), 0, s, e0, e1, 0, args...);
+    else
+        hipLaunchKernelGGL(kernel, dim3(g), dim3(b), 0, s, args...);
+}
+
 // Grid of a launch shape: one tile of nb / 8 observations per workgroup, or a
 // persistent grid of grid_mult workgroups per compute unit striding over them.
 static unsigned shape_grid(const Ctx &c, LaunchShape sh) {
@@ -887,13 +899,14 @@ static unsigned shape_grid(const Ctx &c, LaunchShape sh) {
 }
 
 template <typename T, bool IC>
-static void launch_linearize_shape(hipStream_t s, const Ctx &c, const ResArgs<T> &a, int write_mask, LaunchShape sh) {
+static void launch_linearize_shape(hipStream_t s, const Ctx &c, const ResArgs<T> &a, int write_mask, LaunchShape sh,
+                                   hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr) {
     const unsigned g = shape_grid(c, sh);
     switch (sh.block) {
-        case 64: k_linearize<T, IC, 64><<<g, 64, 0, s>>>(a, write_mask); break;
-        case 128: k_linearize<T, IC, 128><<<g, 128, 0, s>>>(a, write_mask); break;
-        case 512: k_linearize<T, IC, 512><<<g, 512, 0, s>>>(a, write_mask); break;
-        default: k_linearize<T, IC, 256><<<g, 256, 0, s>>>(a, write_mask); break;
+        case 64: launch_ev(k_linearize<T, IC, 64>, g, 64, s, e0, e1, a, write_mask); break;
+        case 128: launch_ev(k_linearize<T, IC, 128>, g, 128, s, e0, e1, a, write_mask); break;
+        case 512: launch_ev(k_linearize<T, IC, 512>, g, 512, s, e0, e1, a, write_mask); break;
+        default: launch_ev(k_linearize<T, IC, 256>, g, 256, s, e0, e1, a, write_mask); break;
     }
 }
 
@@ -906,42 +919,46 @@ void Launch<T>::ic_linearize(hipStream_t s, Ctx &c, int level) {
 }
 
 template <typename T>
-void Launch<T>::fc_linearize(hipStream_t s, Ctx &c, int level, const T *rel_cur, bool write_mask) {
+void Launch<T>::fc_linearize(hipStream_t s, Ctx &c, int level, const T *rel_cur, bool write_mask, hipEvent_t e0,
+                             hipEvent_t e1) {
     if (c.O == 0) return;
     ResArgs<T> a = res_args<T>(c, level, rel_cur);
-    launch_linearize_shape<T, false>(s, c, a, write_mask ? 1 : 0, c.tune_lin);
+    launch_linearize_shape<T, false>(s, c, a, write_mask ? 1 : 0, c.tune_lin, e0, e1);
     CHECK_LAUNCH();
 }
 
-void launch_linearize_mixed(hipStream_t s, Ctx &c, int level, bool ic, const float *rel_cur, bool write_mask) {
+void launch_linearize_mixed(hipStream_t s, Ctx &c, int level, bool ic, const float *rel_cur, bool write_mask,
+                            hipEvent_t e0, hipEvent_t e1) {
     const int nch = (int)c.st.pchunk_begin.size();
     if (c.O == 0 || nch == 0) return;
     ResArgs<float> a = res_args<float>(c, level, rel_cur);
     if (ic)
-        k_linearize_mixed<true><<<nch, BLOCK, 0, s>>>(a, 1, c.d_pchunk_begin, c.d_pchunk_end, c.d_pair_obs_idx,
-                                                      c.d_partH);
+        launch_ev(k_linearize_mixed<true>, nch, BLOCK, s, e0, e1, a, 1, (const int *)c.d_pchunk_begin,
+                  (const int *)c.d_pchunk_end, (const int *)c.d_pair_obs_idx, c.d_partH);
     else
-        k_linearize_mixed<false><<<nch, BLOCK, 0, s>>>(a, write_mask ? 1 : 0, c.d_pchunk_begin, c.d_pchunk_end,
-                                                       c.d_pair_obs_idx, c.d_partH);
+        launch_ev(k_linearize_mixed<false>, nch, BLOCK, s, e0, e1, a, write_mask ? 1 : 0,
+                  (const int *)c.d_pchunk_begin, (const int *)c.d_pchunk_end, (const int *)c.d_pair_obs_idx,
+                  c.d_partH);
     CHECK_LAUNCH();
 }
 
 template <typename T>
-void Launch<T>::ic_residual(hipStream_t s, Ctx &c, int level, const T *rel_cur) {
-    ic_residual_shape(s, c, level, rel_cur, c.tune_res);
+void Launch<T>::ic_residual(hipStream_t s, Ctx &c, int level, const T *rel_cur, hipEvent_t e0, hipEvent_t e1) {
+    ic_residual_shape(s, c, level, rel_cur, c.tune_res, e0, e1);
 }
 
 template <typename T>
-void Launch<T>::ic_residual_shape(hipStream_t s, Ctx &c, int level, const T *rel_cur, LaunchShape sh) {
+void Launch<T>::ic_residual_shape(hipStream_t s, Ctx &c, int level, const T *rel_cur, LaunchShape sh, hipEvent_t e0,
+                                  hipEvent_t e1) {
     if (c.O == 0) return;
     ResArgs<T> a = res_args<T>(c, level, rel_cur);
     const unsigned g = shape_grid(c, sh);
     switch (sh.block) {
-        case 64: k_ic_residual<T, 64><<<g, 64, 0, s>>>(a); break;
-        case 128: k_ic_residual<T, 128><<<g, 128, 0, s>>>(a); break;
-        case 512: k_ic_residual<T, 512><<<g, 512, 0, s>>>(a); break;
-        case 1024: k_ic_residual<T, 1024><<<g, 1024, 0, s>>>(a); break;
-        default: k_ic_residual<T, 256><<<g, 256, 0, s>>>(a); break;
+        case 64: launch_ev(k_ic_residual<T, 64>, g, 64, s, e0, e1, a); break;
+        case 128: launch_ev(k_ic_residual<T, 128>, g, 128, s, e0, e1, a); break;
+        case 512: launch_ev(k_ic_residual<T, 512>, g, 512, s, e0, e1, a); break;
+        case 1024: launch_ev(k_ic_residual<T, 1024>, g, 1024, s, e0, e1, a); break;
+        default: launch_ev(k_ic_residual<T, 256>, g, 256, s, e0, e1, a); break;
     }
     CHECK_LAUNCH();
 }
