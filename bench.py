@@ -17,6 +17,7 @@ stream, so wall-clock time around them brackets the device work.
 Prints one JSON line.
 """
 import argparse
+import hashlib
 import json
 import math
 import os
@@ -29,11 +30,17 @@ sys.path.insert(0, ROOT)
 import numpy as np  # noqa: E402
 
 HBM_PEAK_GBS = 8000.0
-# HBM bytes per level-0 launch of the IC residual kernel from two rocprofv3 counter
-# runs (FETCH_SIZE x 2.000 + WRITE_SIZE x 1.000, scales from a 256 MiB device
-# copy; see profiles/ic_residual_mid_traffic.md), valid for the kernel source
-# with this hash only.
-MEASURED_TRAFFIC = {"bytes": 27336908, "kernels_sha256_16": "394d34289d9305b8"}
+# HBM bytes per level-0 launch of k_ic_residual<float> from two rocprofv3 counter
+# runs (FETCH_SIZE x 2.000 + WRITE_SIZE x 1.000, scales from a 256 MiB device copy;
+# profiles/k_ic_residual_traffic_mid_precision.md), valid for the kernel source with
+# this hash only
+MEASURED_TRAFFIC = {"mid": 24462274, "precision": 202050943, "kernels_sha256_16": "57b25de35012ff61"}
+
+
+def measured_traffic(workload):
+    ksrc = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_1704_06967_amd", "csrc", "pba_kernels.hip")
+    sha = hashlib.sha256(open(ksrc, "rb").read()).hexdigest()[:16]
+    return MEASURED_TRAFFIC[workload] if sha == MEASURED_TRAFFIC["kernels_sha256_16"] else None
 METRIC = "GN iters/s & residuals/s, IC-proxy vs FC on same GPU at equal final photo-RMSE"
 
 
@@ -218,7 +225,8 @@ def precision_section(pba, steps, max_iters, conv_px):
             gbs = nb["bytes"] / (avg_us * 1e-6) / 1e9
             out["residual_roofline"] = {"kernel": "k_ic_residual<float> (level 0)", "bound": "hbm",
                                         "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                                        "frac": round(gbs / HBM_PEAK_GBS, 4), "avg_launch_us": round(avg_us, 3),
+                                        "frac": round(gbs / HBM_PEAK_GBS, 4),
+                                        "traffic": measured_traffic("precision"), "avg_launch_us": round(avg_us, 3),
                                         "algorithmic_bytes_per_launch": nb["bytes"], "bytes_detail": nb}
         log(f"precision {name}: {out[name]['ms_per_solve']} ms per solve, residual kernel {avg_us:.1f} us")
     out["ic_mixed_vs_fp64"] = param_errors(*results["ic_mixed"], *results["ic_fp64"])
@@ -484,11 +492,7 @@ def main():
     launches0 = ic_tm["residual_launches"][0]
     avg_ms = ic_tm["residual_ms"][0] / max(1, launches0)
     achieved = nb["bytes"] / (avg_ms * 1e-3) / 1e9 if launches0 else 0.0
-    import hashlib
-
-    ksrc = os.path.join(ROOT, "paper_1704_06967_amd", "csrc", "pba_kernels.hip")
-    sha = hashlib.sha256(open(ksrc, "rb").read()).hexdigest()[:16]
-    traffic = MEASURED_TRAFFIC["bytes"] if sha == MEASURED_TRAFFIC["kernels_sha256_16"] else None
+    traffic = measured_traffic("mid")
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "kernel": "k_ic_residual<float> (level 0)", "avg_launch_us": round(avg_ms * 1e3, 3),

@@ -276,9 +276,13 @@ std::string build_structure(Ctx &c, const std::vector<int> &host_frame, const st
     s.gram_floats = off;
     if (off > (size_t)INT32_MAX) return "too many points for the Schur Gram buffers";
     // nonzero blocks of S
+    // every 6 x 6 block of each window's S (structurally zero ones written as
+    // zeros by the assembly, so that S needs no clearing pass)
     std::map<long long, std::pair<std::vector<int>, std::vector<int>>> blk;
     auto key = [F](int a, int b) { return (long long)a * F + b; };
-    for (int f = 0; f < F; ++f) blk[key(f, f)];
+    for (int w = 0; w + 1 < (int)c.win_frame_off.size(); ++w)
+        for (int a = c.win_frame_off[w]; a < c.win_frame_off[w + 1]; ++a)
+            for (int b = c.win_frame_off[w]; b < c.win_frame_off[w + 1]; ++b) blk[key(a, b)];
     for (int p = 0; p < Pn; ++p) {
         const int t = s.pair_target[p], h = s.pair_host[p];
         blk[key(t, t)].first.push_back(p * 4 + 0);
@@ -309,17 +313,16 @@ std::string build_structure(Ctx &c, const std::vector<int> &host_frame, const st
 }
 
 // ---- level start and iterations, per element type
+// Opens the level's gate (clear_flag: also clears the failure flag) and sets up
+// the level.
 template <typename T>
-pba_status start_level(Ctx &c, int level) {
+pba_status start_level(Ctx &c, int level, bool clear_flag) {
     hipStream_t s = c.stream;
     if (!c.lv[level].tmpl_valid) {
         Launch<T>::make_template(s, c, level);
         c.lv[level].tmpl_valid = true;
     }
-    launch_copy_d(s, c.d_poses, c.d_poses0, (size_t)c.F * 12);
-    launch_copy_d(s, c.d_depth, c.d_depth0, (size_t)c.N);
-    Launch<T>::relpose(s, c, c.d_poses0, c.d_geo0, (T *)c.d_rel0);
-    Launch<T>::relpose(s, c, c.d_poses0, c.d_geo_a, (T *)c.d_rel_a);
+    Launch<T>::level_begin(s, c, level, clear_flag);
     c.flip = false;
     if (c.cfg.mode == PBA_IC_PROXY) {
         // J (Sec. 3.4) and W0 at p(0); H = J^T W0 J, depth Schur complement, Cholesky, inverse
@@ -366,7 +369,7 @@ pba_status one_iteration(Ctx &c, int level, double *stat, hipEvent_t ev0, hipEve
         launch_mu(s, c, geo_cur);
         launch_gram(s, c, geo_cur, c.d_rec, is_fp64(c));
         launch_assemble_s(s, c, geo_cur);
-        if (c.tiled()) launch_tchol(s, c);
+        if (c.tiled()) launch_tchol(s, c, false);   // the assembly wrote S into the factor buffer too
         Launch<T>::pair_reduce_y(s, c);
         launch_solve(s, c, geo_cur, geo_next, rel_next, is_fp64(c), stat);
     }
@@ -465,8 +468,7 @@ pba_status run_iterations(Ctx &c, int level, int n_iters, pba_iter_stats *out, d
 }
 
 pba_status do_start_level(Ctx &c, int level) {
-    launch_open(c.stream, c, level, true);
-    pba_status st = is_fp64(c) ? start_level<double>(c, level) : start_level<float>(c, level);
+    pba_status st = is_fp64(c) ? start_level<double>(c, level, true) : start_level<float>(c, level, true);
     if (st != PBA_OK) return st;
     if (c.cfg.mode == PBA_IC_PROXY) {
         int flag = 0;
@@ -487,8 +489,8 @@ pba_status do_start_level(Ctx &c, int level) {
 pba_status enqueue_solve(Ctx &c, int max_iters, double conv_px, bool events) {
     for (int level = c.cfg.n_levels - 1; level >= 0; --level) {
         // a failure at a coarser level keeps the gate closed for the rest
-        launch_open(c.stream, c, level, level == c.cfg.n_levels - 1);
-        pba_status st = is_fp64(c) ? start_level<double>(c, level) : start_level<float>(c, level);
+        const bool clear = level == c.cfg.n_levels - 1;
+        pba_status st = is_fp64(c) ? start_level<double>(c, level, clear) : start_level<float>(c, level, clear);
         if (st != PBA_OK) return st;
         const int slot = c.cfg.n_levels - 1 - level;
         for (int k = 0; k < max_iters; ++k) {

@@ -365,10 +365,10 @@ void launch_tsolve(hipStream_t s, Ctx &c, const double *b, double *x) {
     k_tsolve<<<1, 1024, lds, s>>>(n, c.d_Sfac, c.d_Linv, b, x, c.d_flag);
 }
 
-void launch_tchol(hipStream_t s, Ctx &c) {
+void launch_tchol(hipStream_t s, Ctx &c, bool copy) {
     const int n = 6 * c.F, nt = (n + TB - 1) / TB;
     const size_t nn = (size_t)n * n;
-    k_copy_d<<<(unsigned)((nn + 255) / 256), 256, 0, s>>>(c.d_S, c.d_Sfac, nn, c.d_gate);
+    if (copy) k_copy_d<<<(unsigned)((nn + 255) / 256), 256, 0, s>>>(c.d_S, c.d_Sfac, nn, c.d_gate);
     k_tchol_first<<<1, 256, 0, s>>>(n, c.d_Sfac, c.d_Linv, c.d_flag, c.d_gate);
     for (int kt = 0; kt + 1 < nt; ++kt) {
         const int m = nt - kt - 1;

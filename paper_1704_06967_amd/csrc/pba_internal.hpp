@@ -241,6 +241,8 @@ template <typename T> struct Launch {
     static void relpose(hipStream_t s, Ctx &c, const double *poses, double *geo, T *rel);
     static void ic_linearize(hipStream_t s, Ctx &c, int level);
     // e0 / e1 (optional): events recorded by the dispatch itself at the kernel's start and end
+    // level start: gate / flag / count, p(0) copies, relative poses at p(0) (one launch)
+    static void level_begin(hipStream_t s, Ctx &c, int level, bool clear_flag);
     static void ic_residual(hipStream_t s, Ctx &c, int level, const T *rel_cur, hipEvent_t e0 = nullptr,
                             hipEvent_t e1 = nullptr);
     static void ic_residual_shape(hipStream_t s, Ctx &c, int level, const T *rel_cur, LaunchShape sh,
@@ -288,7 +290,7 @@ void launch_conv(hipStream_t s, Ctx &c, double *stat, double conv_px, int nparts
 // count[level] = 0, optionally flag = 0, then gate = (flag == 0)
 void launch_open(hipStream_t s, Ctx &c, int level, bool clear_flag);
 void launch_ic_inverse(hipStream_t s, Ctx &c);
-void launch_tchol(hipStream_t s, Ctx &c);   // copy S to d_Sfac and factor it in tiles
+void launch_tchol(hipStream_t s, Ctx &c, bool copy = true);   // (copy S to d_Sfac and) factor d_Sfac in tiles
 void launch_tinv(hipStream_t s, Ctx &c);    // S^{-1} from the tiled factor
 void launch_copy_d(hipStream_t s, const double *src, double *dst, size_t n);  // device copy as a kernel
 void launch_fill(hipStream_t s, double *p, size_t n, double v, const int *gate);

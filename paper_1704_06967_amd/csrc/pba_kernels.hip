@@ -108,6 +108,47 @@ __global__ void k_relpose(int Pn, const int *__restrict__ pair_host, const int *
     for (int i = 0; i < 3; ++i) r[9 + i] = (T)t[i];
 }
 
+// Start of a level, one launch: the level's gate, failure flag (cleared with
+// clear_flag) and iteration count; p(0) copies of the poses and inverse depths;
+// the relative poses of every pair at p(0), kept as the IC linearization point
+// (geo0, rel0) and as the current iterate (geo_a, rel_a).
+template <typename T>
+__global__ void k_level_begin(int F, int N, int Pn, const double *__restrict__ poses, double *__restrict__ poses0,
+                              const double *__restrict__ depth, double *__restrict__ depth0,
+                              const int *__restrict__ pair_host, const int *__restrict__ pair_target,
+                              double *__restrict__ geo0, T *__restrict__ rel0, double *__restrict__ geo_a,
+                              T *__restrict__ rel_a, int *__restrict__ gate, int *__restrict__ flag,
+                              int *__restrict__ count, int clear_flag) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i == 0) {
+        if (clear_flag) *flag = 0;
+        *gate = *flag == 0 ? 1 : 0;
+        *count = 0;
+    }
+    if (i < 12 * F) poses0[i] = poses[i];
+    if (i < N) depth0[i] = depth[i];
+    if (i < Pn) {
+        const double *Ph = poses + 12 * pair_host[i];
+        const double *Pf = poses + 12 * pair_target[i];
+        double R[9];
+        mat3_mul_bt(Pf, Ph, R);
+        double t[3];
+        for (int k = 0; k < 3; ++k) t[k] = Pf[9 + k] - (R[k * 3] * Ph[9] + R[k * 3 + 1] * Ph[10] + R[k * 3 + 2] * Ph[11]);
+        double *g0 = geo0 + GEO_STRIDE * i, *ga = geo_a + GEO_STRIDE * i;
+        T *r0 = rel0 + REL_STRIDE * i, *ra = rel_a + REL_STRIDE * i;
+        for (int k = 0; k < 9; ++k) {
+            g0[k] = ga[k] = R[k];
+            r0[k] = ra[k] = (T)R[k];
+        }
+        for (int k = 0; k < 3; ++k) {
+            g0[9 + k] = ga[9 + k] = t[k];
+            r0[9 + k] = ra[9 + k] = (T)t[k];
+            g0[12 + k] = ga[12 + k] = Ph[9 + k];
+        }
+        g0[15] = ga[15] = 0.0;
+    }
+}
+
 // ------------------------------------------------------------ residual kernels
 
 template <typename T>
@@ -870,6 +911,16 @@ void Launch<T>::make_template(hipStream_t s, Ctx &c, int level) {
             c.st.n_pairs, c.d_pair_host, c.d_pair_target, a.K, (T *)c.lv[level].pcam);
         CHECK_LAUNCH();
     }
+}
+
+template <typename T>
+void Launch<T>::level_begin(hipStream_t s, Ctx &c, int level, bool clear_flag) {
+    const int m = std::max(std::max(12 * c.F, c.N), std::max(c.st.n_pairs, 1));
+    k_level_begin<T><<<nblk(m, 256), 256, 0, s>>>(c.F, c.N, c.st.n_pairs, c.d_poses, c.d_poses0, c.d_depth,
+                                                  c.d_depth0, c.d_pair_host, c.d_pair_target, c.d_geo0,
+                                                  (T *)c.d_rel0, c.d_geo_a, (T *)c.d_rel_a, c.d_gate, c.d_flag,
+                                                  c.d_count + level, clear_flag ? 1 : 0);
+    CHECK_LAUNCH();
 }
 
 template <typename T>

@@ -241,7 +241,7 @@ __global__ __launch_bounds__(64) void k_assemble_s(WinArgs wa, int pinned, const
                                                    const int *__restrict__ chunk_off, const double *__restrict__ pairH,
                                                    const double *__restrict__ geo, const double *__restrict__ gram,
                                                    const double *__restrict__ mu, double *__restrict__ S,
-                                                   const int *__restrict__ gate) {
+                                                   double *__restrict__ Sfac, const int *__restrict__ gate) {
     if (*gate == 0) return;
     const int b = blockIdx.x;
     if (threadIdx.x >= 36) return;
@@ -273,7 +273,9 @@ __global__ __launch_bounds__(64) void k_assemble_s(WinArgs wa, int pinned, const
     }
     if (fa == fb && r == c) val += mu[2 * w];
     if (pinned >= 0 && (la == pinned || lb == pinned)) val = (fa == fb && r == c) ? 1.0 : 0.0;
-    S[(size_t)wa.S_off[w] + (size_t)(6 * la + r) * nw + 6 * lb + c] = val;
+    const size_t at = (size_t)wa.S_off[w] + (size_t)(6 * la + r) * nw + 6 * lb + c;
+    S[at] = val;
+    if (Sfac) Sfac[at] = val;   // one tiled window: the factorization's working copy
 }
 
 // ---- dense SPD helpers for one workgroup of SOLVE_THREADS threads (packed
@@ -775,16 +777,18 @@ void launch_gram(hipStream_t s, Ctx &c, const double *geo, const void *rec, bool
 }
 
 void launch_assemble_s(hipStream_t s, Ctx &c, const double *geo) {
-    launch_fill(s, c.d_S, (size_t)c.win_S_off[c.nwin], 0.0, c.d_gate);
+    // every block of every window's S is written (zeros where no pair or Gram
+    // item contributes), so S needs no clearing pass
     const int nbk = (int)c.st.blk_fa.size();
     k_assemble_s<<<nbk, 64, 0, s>>>(c.win(), c.cfg.pinned_frame, c.d_blk_fa, c.d_blk_fb, c.d_blk_pp_ptr,
                                     c.d_blk_pp_item, c.d_blk_g_ptr, c.d_blk_g_item, c.d_host_m, c.d_host_chunk_ptr,
-                                    c.d_chunk_off, c.d_pairH, geo, c.d_gram, c.d_mu, c.d_S, c.d_gate);
+                                    c.d_chunk_off, c.d_pairH, geo, c.d_gram, c.d_mu, c.d_S,
+                                    c.tiled() ? c.d_Sfac : nullptr, c.d_gate);
 }
 
 void launch_ic_factor(hipStream_t s, Ctx &c) {
     if (c.tiled()) {
-        launch_tchol(s, c);
+        launch_tchol(s, c, false);   // the assembly wrote S into the factor buffer too
         return;
     }
     k_ic_factor<<<c.nwin, SOLVE_THREADS, 0, s>>>(c.win(), c.d_S, c.d_Lfac, c.d_flag, c.d_gate);
