@@ -349,7 +349,11 @@ pba_status start_level(Ctx &c, int level, bool clear_flag) {
 }
 
 template <typename T>
-pba_status one_iteration(Ctx &c, int level, double *stat, hipEvent_t ev0, hipEvent_t ev1, double conv_px) {
+// prev_stat (IC, not the first iteration of a batch): the previous iteration's
+// statistics slot, finished by this iteration's pair sums; last: the final
+// iteration of the batch, whose end runs as a kernel of its own.
+pba_status one_iteration(Ctx &c, int level, double *stat, hipEvent_t ev0, hipEvent_t ev1, double conv_px,
+                         double *prev_stat, bool last) {
     hipStream_t s = c.stream;
     double *geo_cur = c.flip ? c.d_geo_b : c.d_geo_a;
     double *geo_next = c.flip ? c.d_geo_a : c.d_geo_b;
@@ -357,7 +361,7 @@ pba_status one_iteration(Ctx &c, int level, double *stat, hipEvent_t ev0, hipEve
     T *rel_next = (T *)(c.flip ? c.d_rel_a : c.d_rel_b);
     if (c.cfg.mode == PBA_IC_PROXY) {
         Launch<T>::ic_residual(s, c, level, rel_cur, ev0, ev1);
-        Launch<T>::pair_reduce_y(s, c);
+        Launch<T>::pair_reduce_y(s, c, prev_stat, conv_px, level);
         launch_solve(s, c, c.d_geo0, geo_next, rel_next, is_fp64(c), stat);
     } else {
         if (is_mixed(c))
@@ -373,7 +377,10 @@ pba_status one_iteration(Ctx &c, int level, double *stat, hipEvent_t ev0, hipEve
         Launch<T>::pair_reduce_y(s, c);
         launch_solve(s, c, geo_cur, geo_next, rel_next, is_fp64(c), stat);
     }
-    Launch<T>::depth_update(s, c, geo_cur, geo_next, stat, conv_px, level);
+    // IC: the end of the iteration (statistics, convergence gate) is taken by the
+    // next iteration's pair sums, or by a kernel of its own after the last one
+    const bool finish = c.cfg.mode != PBA_IC_PROXY || last;
+    Launch<T>::depth_update(s, c, geo_cur, geo_next, stat, conv_px, level, finish);
     HIPCHK(hipGetLastError());
     c.s_valid = true;
     c.flip = !c.flip;
@@ -436,8 +443,10 @@ pba_status run_iterations(Ctx &c, int level, int n_iters, pba_iter_stats *out, d
     for (int k = 0; k < n_iters; ++k) {
         hipEvent_t e0 = timing ? c.ev_pool[2 * k] : nullptr, e1 = timing ? c.ev_pool[2 * k + 1] : nullptr;
         double *stat = c.d_stats + (size_t)k * ST_STRIDE;
-        st = is_fp64(c) ? one_iteration<double>(c, level, stat, e0, e1, conv_px)
-                        : one_iteration<float>(c, level, stat, e0, e1, conv_px);
+        double *prev = k > 0 ? stat - ST_STRIDE : nullptr;
+        const bool last = k == n_iters - 1;
+        st = is_fp64(c) ? one_iteration<double>(c, level, stat, e0, e1, conv_px, prev, last)
+                        : one_iteration<float>(c, level, stat, e0, e1, conv_px, prev, last);
         if (st != PBA_OK) return st;
     }
     std::vector<double> hs((size_t)n_iters * ST_STRIDE);
@@ -497,8 +506,10 @@ pba_status enqueue_solve(Ctx &c, int max_iters, double conv_px, bool events) {
             const size_t idx = (size_t)slot * max_iters + k;
             double *stat = c.d_stats + idx * ST_STRIDE;
             hipEvent_t e0 = events ? c.ev_pool[2 * idx] : nullptr, e1 = events ? c.ev_pool[2 * idx + 1] : nullptr;
-            st = is_fp64(c) ? one_iteration<double>(c, level, stat, e0, e1, conv_px)
-                            : one_iteration<float>(c, level, stat, e0, e1, conv_px);
+            double *prev = k > 0 ? stat - ST_STRIDE : nullptr;
+            const bool last = k == max_iters - 1;
+            st = is_fp64(c) ? one_iteration<double>(c, level, stat, e0, e1, conv_px, prev, last)
+                            : one_iteration<float>(c, level, stat, e0, e1, conv_px, prev, last);
             if (st != PBA_OK) return st;
         }
     }

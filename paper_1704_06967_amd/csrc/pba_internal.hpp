@@ -253,9 +253,12 @@ template <typename T> struct Launch {
     static void evaluate(hipStream_t s, Ctx &c, int level);
     static void point_reduce(hipStream_t s, Ctx &c, bool with_hdd);
     static void pair_reduce_H(hipStream_t s, Ctx &c);
-    static void pair_reduce_y(hipStream_t s, Ctx &c);
+    // prev_stat (IC): the previous iteration's statistics slot; its end (statistics,
+    // count, convergence gate) is taken by this kernel from the depth update's maxima
+    static void pair_reduce_y(hipStream_t s, Ctx &c, double *prev_stat = nullptr, double conv_px = -1.0,
+                              int level = 0);
     static void depth_update(hipStream_t s, Ctx &c, const double *geo_old, const double *geo_new, double *stat,
-                             double conv_px, int level);
+                             double conv_px, int level, bool finish = true);
 };
 
 // learned preconditioner and PCG (pba_learned.hip)

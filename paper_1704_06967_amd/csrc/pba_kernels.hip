@@ -546,6 +546,66 @@ __global__ __launch_bounds__(BLOCK) void k_evaluate(ResArgs<T> a) {
     }
 }
 
+// End-of-iteration statistics and the convergence gate (see k_conv).
+struct ConvArgs {
+    const double *wstat;
+    int nwin;
+    double *stat;
+    double conv_px;
+    int *gate, *count;
+    const int *flag;
+};
+
+// Statistics of an iteration from the block maxima (largest point-centre
+// displacement, largest depth step) and the per-window statistics of the solve,
+// added over the windows in order; closes the gate once the displacement is
+// below conv_px (conv_px >= 0). One block; md / ms are its thread-0 maxima.
+__device__ void conv_finish(const ConvArgs &cv, double md, double ms) {
+    if (*cv.flag) {
+        *cv.gate = 0;
+        return;
+    }
+    double e = 0.0, sq = 0.0, cnt = 0.0, sp = 0.0;
+    for (int w = 0; w < cv.nwin; ++w) {
+        e += cv.wstat[4 * w];
+        sq += cv.wstat[4 * w + 1];
+        cnt += cv.wstat[4 * w + 2];
+        sp = fmax(sp, cv.wstat[4 * w + 3]);
+    }
+    cv.stat[ST_E] = e;
+    cv.stat[ST_SQ] = sq;
+    cv.stat[ST_CNT] = cnt;
+    cv.stat[ST_STEP_P] = sp;
+    cv.stat[ST_DISP] = md;
+    cv.stat[ST_STEP_D] = ms;
+    *cv.count += 1;
+    if (cv.conv_px >= 0.0 && md < cv.conv_px) *cv.gate = 0;
+}
+
+// Block maxima of the pairs (part[2 i], part[2 i + 1]), i < nparts; valid in thread 0.
+__device__ void block_max2(const double *part, int nparts, double &md, double &ms, double (*red)[16]) {
+    md = 0.0;
+    ms = 0.0;
+    for (int i = threadIdx.x; i < nparts; i += blockDim.x) {
+        md = fmax(md, part[2 * i]);
+        ms = fmax(ms, part[2 * i + 1]);
+    }
+    for (int k = 32; k >= 1; k >>= 1) {
+        md = fmax(md, __shfl_xor(md, k, 64));
+        ms = fmax(ms, __shfl_xor(ms, k, 64));
+    }
+    if ((threadIdx.x & 63) == 0) {
+        red[0][threadIdx.x >> 6] = md;
+        red[1][threadIdx.x >> 6] = ms;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0)
+        for (int k = 1; k < (int)(blockDim.x >> 6); ++k) {
+            md = fmax(md, red[0][k]);
+            ms = fmax(ms, red[1][k]);
+        }
+}
+
 // ------------------------------------------------------------ reductions
 
 // Block-wide sum of NV doubles per thread in a fixed order (wave shuffles, then
@@ -624,9 +684,23 @@ __global__ __launch_bounds__(PAIR_CHUNK) void k_pair_chunk_y(const int *__restri
                                                              const int *__restrict__ prange, const T *__restrict__ rec,
                                                              const T *__restrict__ gr, int gs,
                                                              const double *__restrict__ Hdd,
-                                                             double *__restrict__ partY, const int *__restrict__ gate) {
+                                                             double *__restrict__ partY, const int *__restrict__ gate,
+                                                             const double *__restrict__ du_part, int du_nparts,
+                                                             ConvArgs cv) {
     __shared__ double lds[9 * 16];
+    __shared__ double red[2][16];
     if (*gate == 0) return;
+    // block 0 also ends the previous iteration (IC): the depth update's block
+    // maxima (loaded now, reduced after the pair sums) give its largest
+    // displacement and depth step, its statistics and the convergence gate. If
+    // that closes the gate, this iteration's sums are simply not used.
+    const bool finish_prev = du_part != nullptr && blockIdx.x == 0;
+    double pmd = 0.0, pms = 0.0;
+    if (finish_prev)
+        for (int i = threadIdx.x; i < du_nparts; i += blockDim.x) {
+            pmd = fmax(pmd, du_part[2 * i]);
+            pms = fmax(pms, du_part[2 * i + 1]);
+        }
     const int c = blockIdx.x;
     double v[9];
     for (int k = 0; k < 9; ++k) v[k] = 0.0;
@@ -648,6 +722,24 @@ __global__ __launch_bounds__(PAIR_CHUNK) void k_pair_chunk_y(const int *__restri
     block_sum<9>(v, lds);
     if (threadIdx.x == 0)
         for (int k = 0; k < 9; ++k) partY[9 * c + k] = v[k];
+    if (finish_prev) {
+        for (int k = 32; k >= 1; k >>= 1) {
+            pmd = fmax(pmd, __shfl_xor(pmd, k, 64));
+            pms = fmax(pms, __shfl_xor(pms, k, 64));
+        }
+        if ((threadIdx.x & 63) == 0) {
+            red[0][threadIdx.x >> 6] = pmd;
+            red[1][threadIdx.x >> 6] = pms;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            for (int k = 1; k < (int)(blockDim.x >> 6); ++k) {
+                pmd = fmax(pmd, red[0][k]);
+                pms = fmax(pms, red[1][k]);
+            }
+            conv_finish(cv, pmd, pms);
+        }
+    }
 }
 
 // Sums of the record statistics (energy, squared residuals, count): block
@@ -679,65 +771,6 @@ __global__ void k_sum_parts3(int np, const double *__restrict__ part, double *__
 
 constexpr int DU_PTS = 32, DU_SLOTS = 8;
 
-// End-of-iteration statistics and the convergence gate (see k_conv).
-struct ConvArgs {
-    const double *wstat;
-    int nwin;
-    double *stat;
-    double conv_px;
-    int *gate, *count;
-    const int *flag;
-};
-
-// Statistics of an iteration from the block maxima (largest point-centre
-// displacement, largest depth step) and the per-window statistics of the solve,
-// added over the windows in order; closes the gate once the displacement is
-// below conv_px (conv_px >= 0). One block; md / ms are its thread-0 maxima.
-__device__ void conv_finish(const ConvArgs &cv, double md, double ms) {
-    if (*cv.flag) {
-        *cv.gate = 0;
-        return;
-    }
-    double e = 0.0, sq = 0.0, cnt = 0.0, sp = 0.0;
-    for (int w = 0; w < cv.nwin; ++w) {
-        e += cv.wstat[4 * w];
-        sq += cv.wstat[4 * w + 1];
-        cnt += cv.wstat[4 * w + 2];
-        sp = fmax(sp, cv.wstat[4 * w + 3]);
-    }
-    cv.stat[ST_E] = e;
-    cv.stat[ST_SQ] = sq;
-    cv.stat[ST_CNT] = cnt;
-    cv.stat[ST_STEP_P] = sp;
-    cv.stat[ST_DISP] = md;
-    cv.stat[ST_STEP_D] = ms;
-    *cv.count += 1;
-    if (cv.conv_px >= 0.0 && md < cv.conv_px) *cv.gate = 0;
-}
-
-// Block maxima of the pairs (part[2 i], part[2 i + 1]), i < nparts; valid in thread 0.
-__device__ void block_max2(const double *part, int nparts, double &md, double &ms, double (*red)[16]) {
-    md = 0.0;
-    ms = 0.0;
-    for (int i = threadIdx.x; i < nparts; i += blockDim.x) {
-        md = fmax(md, part[2 * i]);
-        ms = fmax(ms, part[2 * i + 1]);
-    }
-    for (int k = 32; k >= 1; k >>= 1) {
-        md = fmax(md, __shfl_xor(md, k, 64));
-        ms = fmax(ms, __shfl_xor(ms, k, 64));
-    }
-    if ((threadIdx.x & 63) == 0) {
-        red[0][threadIdx.x >> 6] = md;
-        red[1][threadIdx.x >> 6] = ms;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0)
-        for (int k = 1; k < (int)(blockDim.x >> 6); ++k) {
-            md = fmax(md, red[0][k]);
-            ms = fmax(ms, red[1][k]);
-        }
-}
 
 // Depth step of every point after the pose step (depth back-substitution,
 // Sec. 3.5 step 4 for IC, the Schur back-substitution for FC) and the block
@@ -865,6 +898,10 @@ static ResArgs<T> res_args(Ctx &c, int level, const T *rel_cur) {
     a.icr = (T *)c.d_icr;
     a.gate = c.d_gate;
     return a;
+}
+
+static ConvArgs conv_args(Ctx &c, double *stat, double conv_px, int level) {
+    return ConvArgs{c.d_wstat, c.nwin, stat, conv_px, c.d_gate, c.d_count + level, c.d_flag};
 }
 
 // Gradient records of the current iteration: the compact IC records or the
@@ -1049,25 +1086,27 @@ void Launch<T>::pair_reduce_H(hipStream_t s, Ctx &c) {
 }
 
 template <typename T>
-void Launch<T>::pair_reduce_y(hipStream_t s, Ctx &c) {
+void Launch<T>::pair_reduce_y(hipStream_t s, Ctx &c, double *prev_stat, double conv_px, int level) {
     const int nch = (int)c.st.pchunk_begin.size();
-    if (nch == 0) return;
+    if (nch == 0) {
+        // no pair chunks to carry the previous iteration's end: its own kernel
+        if (prev_stat) launch_conv(s, c, prev_stat, conv_px, c.N > 0 ? (int)nblk(c.N, DU_PTS) : 0, level);
+        return;
+    }
     const T *gr;
     int gs;
     grad_records<T>(c, gr, gs);
     k_pair_chunk_y<T><<<nch, PAIR_CHUNK, 0, s>>>(c.d_pchunk_begin, c.d_pchunk_end, c.d_pair_obs_idx,
                                                  c.d_obs_point, c.d_obs_prange, (const T *)c.d_rec, gr, gs, c.d_Hdd,
-                                                 c.d_partY, c.d_gate);
+                                                 c.d_partY, c.d_gate, prev_stat ? c.d_du_part : nullptr,
+                                                 c.N > 0 ? (int)nblk(c.N, DU_PTS) : 0, conv_args(c, prev_stat, conv_px, level));
     CHECK_LAUNCH();
 }
 
-static ConvArgs conv_args(Ctx &c, double *stat, double conv_px, int level) {
-    return ConvArgs{c.d_wstat, c.nwin, stat, conv_px, c.d_gate, c.d_count + level, c.d_flag};
-}
 
 template <typename T>
 void Launch<T>::depth_update(hipStream_t s, Ctx &c, const double *geo_old, const double *geo_new, double *stat,
-                             double conv_px, int level) {
+                             double conv_px, int level, bool finish) {
     const int nb = (int)nblk(c.N, DU_PTS);
     const T *gr;
     int gs;
@@ -1078,7 +1117,7 @@ void Launch<T>::depth_update(hipStream_t s, Ctx &c, const double *geo_old, const
                                              c.d_dth_rel, geo_old, geo_new, c.d_depth, c.d_depth0, c.d_du_part,
                                              c.d_gate, c.d_flag);
     CHECK_LAUNCH();
-    launch_conv(s, c, stat, conv_px, c.N > 0 ? nb : 0, level);
+    if (finish) launch_conv(s, c, stat, conv_px, c.N > 0 ? nb : 0, level);
 }
 
 // End of an iteration without points (single block): the iteration

@@ -286,13 +286,27 @@ __global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, const float *
     }
 }
 
-// Column sums (bias gradients): out[n] = sum_m A[m][n], fixed order.
-__global__ void k_colsum(int M, int N, const float *__restrict__ A, float *__restrict__ out) {
-    const int n = blockIdx.x * blockDim.x + threadIdx.x;
-    if (n >= N) return;
+// Column sums (bias gradients): out[n] = sum_m A[m][n], in a fixed order:
+// COLSUM_COLS columns per 1024-thread block, 16 row groups (rows g, g + 16, ...,
+// loads unrolled) whose partials are added in group order.
+constexpr int COLSUM_COLS = 64, COLSUM_GROUPS = 16;
+
+__global__ __launch_bounds__(1024) void k_colsum(int M, int N, const float *__restrict__ A, float *__restrict__ out) {
+    __shared__ float part[COLSUM_GROUPS][COLSUM_COLS];
+    const int c = threadIdx.x % COLSUM_COLS, g = threadIdx.x / COLSUM_COLS;
+    const int n = blockIdx.x * COLSUM_COLS + c;
     float s = 0.0f;
-    for (int m = 0; m < M; ++m) s += A[(size_t)m * N + n];
-    out[n] = s;
+    if (n < N) {
+#pragma unroll 8
+        for (int m = g; m < M; m += COLSUM_GROUPS) s += A[(size_t)m * N + n];
+    }
+    part[g][c] = s;
+    __syncthreads();
+    if (g == 0 && n < N) {
+        float t = 0.0f;
+        for (int k = 0; k < COLSUM_GROUPS; ++k) t += part[k][c];
+        out[n] = t;
+    }
 }
 
 // Block loss l = tr(P A P) - 2 tr(P) + 6 (A = I + G, P = L L^T) of every
@@ -580,17 +594,17 @@ void pc_forward_backward(hipStream_t s, Ctx &c, int m, const float *X, const flo
     // backward
     k_gemm<true, false, 0><<<grid(PC_OUT, 256), t, 0, s>>>(PC_OUT, 256, m, p.dY, PC_OUT, p.H2, 256, grad + PC_OFF_W3,
                                                            256, nullptr, nullptr, 0);
-    k_colsum<<<1, 64, 0, s>>>(m, PC_OUT, p.dY, grad + PC_OFF_B3);
+    k_colsum<<<nbk(PC_OUT, COLSUM_COLS), 1024, 0, s>>>(m, PC_OUT, p.dY, grad + PC_OFF_B3);
     k_gemm<false, false, 3><<<grid(m, 256), t, 0, s>>>(m, 256, PC_OUT, p.dY, PC_OUT, w + PC_OFF_W3, 256, p.D2, 256,
                                                        nullptr, p.Z2, 256);
     k_gemm<true, false, 0><<<grid(256, 256), t, 0, s>>>(256, 256, m, p.D2, 256, p.H1, 256, grad + PC_OFF_W2, 256,
                                                         nullptr, nullptr, 0);
-    k_colsum<<<1, 256, 0, s>>>(m, 256, p.D2, grad + PC_OFF_B2);
+    k_colsum<<<nbk(256, COLSUM_COLS), 1024, 0, s>>>(m, 256, p.D2, grad + PC_OFF_B2);
     k_gemm<false, false, 3><<<grid(m, 256), t, 0, s>>>(m, 256, 256, p.D2, 256, w + PC_OFF_W2, 256, p.D1, 256, nullptr,
                                                        p.Z1, 256);
     k_gemm<true, false, 0><<<grid(256, PC_IN), t, 0, s>>>(256, PC_IN, m, p.D1, 256, X, PC_IN, grad, PC_IN, nullptr,
                                                           nullptr, 0);
-    k_colsum<<<1, 256, 0, s>>>(m, 256, p.D1, grad + PC_OFF_B1);
+    k_colsum<<<nbk(256, COLSUM_COLS), 1024, 0, s>>>(m, 256, p.D1, grad + PC_OFF_B1);
 }
 
 void pc_adam(hipStream_t s, Ctx &c, float lr, float b1, float b2, float eps, int step) {

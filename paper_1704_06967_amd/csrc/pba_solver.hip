@@ -505,6 +505,7 @@ __global__ __launch_bounds__(SOLVE_THREADS) void k_solve(
         if (threadIdx.x == 0) *gate = 0;
         return;
     }
+
     const int w = blockIdx.x;
     const int f0 = wa.frame_off[w], F = wa.frame_off[w + 1] - f0;
     const int p0 = wa.pair_off[w], p1 = wa.pair_off[w + 1];
