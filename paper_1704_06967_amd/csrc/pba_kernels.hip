@@ -639,7 +639,9 @@ __global__ __launch_bounds__(256) void k_point_reduce(int N, const int *__restri
     const int n = blockIdx.x * blockDim.x + threadIdx.x;
     double hs = 0.0, gs = 0.0;
     if (n < N) {
-        for (int o = obs_ptr[n]; o < obs_ptr[n + 1]; ++o) {
+        const int o0 = obs_ptr[n], o1 = obs_ptr[n + 1];
+#pragma unroll 4
+        for (int o = o0; o < o1; ++o) {
             const T *r = rec + (size_t)o * REC_STRIDE;
             hs += (double)r[REC_HDD];
             gs += (double)r[REC_GD];

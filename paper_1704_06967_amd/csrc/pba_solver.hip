@@ -79,8 +79,10 @@ __global__ __launch_bounds__(1024) void k_mu(WinArgs wa, double damping, const i
     const int p0 = wa.pair_off[w], p1 = wa.pair_off[w + 1];
     for (int e = threadIdx.x; e < (p1 - p0) * 21; e += blockDim.x) {
         const int p = p0 + e / 21, k = e % 21;
+        const int c0 = pair_chunk_ptr[p], c1 = pair_chunk_ptr[p + 1];
         double s = 0.0;
-        for (int c = pair_chunk_ptr[p]; c < pair_chunk_ptr[p + 1]; ++c) s += partH[21 * c + k];
+#pragma unroll 8
+        for (int c = c0; c < c1; ++c) s += partH[21 * c + k];
         pairH[21 * p + k] = s;
     }
     __threadfence_block();
@@ -93,6 +95,7 @@ __global__ __launch_bounds__(1024) void k_mu(WinArgs wa, double damping, const i
         v[0] += quad6(a, pairH + 21 * p, a) + quad6(bcol, pairH + 21 * p, bcol);
     }
     const int n0 = wa.point_off[w], n1 = wa.point_off[w + 1];
+#pragma unroll 8
     for (int n = n0 + threadIdx.x; n < n1; n += blockDim.x) v[1] += Hdd[n];
     block_sum_d<2>(v, lds);
     if (threadIdx.x == 0) {
@@ -250,7 +253,9 @@ __global__ __launch_bounds__(64) void k_assemble_s(WinArgs wa, int pinned, const
     const int w = wa.frame_win[fa], f0 = wa.frame_off[w], nw = 6 * (wa.frame_off[w + 1] - f0);
     const int la = fa - f0, lb = fb - f0;
     double val = 0.0;
-    for (int i = pp_ptr[b]; i < pp_ptr[b + 1]; ++i) {
+    const int i0 = pp_ptr[b], i1 = pp_ptr[b + 1];
+#pragma unroll 2
+    for (int i = i0; i < i1; ++i) {
         const int p = pp_item[i] >> 2, kind = pp_item[i] & 3;
         double ar[6], br[6], ac[6], bc[6], x[6], y[6];
         abs_map_columns(geo + GEO_STRIDE * p, r, ar, br);
