@@ -292,12 +292,93 @@ __device__ __forceinline__ void pin_reg(T &v) {
     asm volatile("" : "+v"(v));
 }
 
+// Cross-lane exchanges by DPP inside rows of 16 lanes (a few cycles, where a
+// shuffle takes an LDS round trip): lane i reads lane i ^ 1 or i ^ 2 (quad
+// permutes) and i ^ 4 or i ^ 8 (a row shift left or right by 4 or 8, chosen by
+// the lane's bit). The reductions below add in the order of an xor butterfly
+// over 1, 2, 4, 8 (then 16, 32 through lane reads), so they match it to the
+// bit. Every lane of the groups they reduce must be active.
+enum { DPP_XOR1 = 0xb1, DPP_XOR2 = 0x4e, DPP_ROW_SHL = 0x100, DPP_ROW_SHR = 0x110 };
+
+template <int CTRL>
+__device__ __forceinline__ float dpp_mov(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xf, 0xf, false));
+}
+
+template <int CTRL>
+__device__ __forceinline__ double dpp_mov(double v) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xf, 0xf, false);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// Lane i ^ M for M = 4 or 8: lanes with bit M clear read M lanes up, the others
+// M lanes down (both inside the row).
+template <int M, typename T>
+__device__ __forceinline__ T dpp_xor(T v) {
+    static_assert(M == 4 || M == 8, "row shifts serve the exchanges over 4 and 8");
+    const T up = dpp_mov<DPP_ROW_SHL + M>(v), down = dpp_mov<DPP_ROW_SHR + M>(v);
+    return (threadIdx.x & M) ? down : up;
+}
+
+__device__ __forceinline__ float lane_value(float v, int l) {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
+}
+
+__device__ __forceinline__ double lane_value(double v, int l) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)b, l), hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// Sum over each group of 8 lanes; every lane gets its group's sum.
 template <typename T>
 __device__ __forceinline__ T wave_sum8(T v) {
-    v += __shfl_xor(v, 1, 64);
-    v += __shfl_xor(v, 2, 64);
-    v += __shfl_xor(v, 4, 64);
+    v += dpp_mov<DPP_XOR1>(v);
+    v += dpp_mov<DPP_XOR2>(v);
+    v += dpp_xor<4>(v);
     return v;
+}
+
+// Sum over each row of 16 lanes; every lane gets its row's sum.
+template <typename T>
+__device__ __forceinline__ T row_sum16(T v) {
+    v = wave_sum8(v);
+    return v + dpp_xor<8>(v);
+}
+
+// Maximum over each row of 16 lanes; every lane gets its row's maximum.
+template <typename T>
+__device__ __forceinline__ T row_max16(T v) {
+    v = fmax(v, dpp_mov<DPP_XOR1>(v));
+    v = fmax(v, dpp_mov<DPP_XOR2>(v));
+    v = fmax(v, dpp_xor<4>(v));
+    return fmax(v, dpp_xor<8>(v));
+}
+
+// Sum over the 64 lanes (lane 0's butterfly result: the row sums added as
+// (r0 + r1) + (r2 + r3)); every lane gets it.
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v) {
+    v = row_sum16(v);
+    return (lane_value(v, 0) + lane_value(v, 16)) + (lane_value(v, 32) + lane_value(v, 48));
+}
+
+// Maximum over the 64 lanes; every lane gets it.
+template <typename T>
+__device__ __forceinline__ T wave_max(T v) {
+    v = row_max16(v);
+    return fmax(fmax(lane_value(v, 0), lane_value(v, 16)), fmax(lane_value(v, 32), lane_value(v, 48)));
+}
+
+// Sum over each half of 32 lanes (lanes 0 and 32's butterfly results); lanes
+// 0-31 get the first half's, 32-63 the second half's.
+template <typename T>
+__device__ __forceinline__ T half_sum32(T v) {
+    v = row_sum16(v);
+    const T a = lane_value(v, 0) + lane_value(v, 16), b = lane_value(v, 32) + lane_value(v, 48);
+    return (threadIdx.x & 32) ? b : a;
 }
 
 }  // namespace pba

@@ -2,7 +2,7 @@
 //
 // Residual-level kernels put one observation (point n seen in frame f) on 8
 // consecutive lanes, one lane per patch pixel, 8 observations per wavefront.
-// Each observation reduces its lanes with cross-lane shuffles and writes one
+// Each observation reduces its lanes with cross-lane DPP moves and writes one
 // record of Gauss-Newton blocks in relative-pose coordinates. Every later
 // reduction (per point, per pair, per frame) runs in a fixed order in FP64, so
 // results are bitwise reproducible run to run (no floating-point atomics).
@@ -590,41 +590,37 @@ __device__ void block_max2(const double *part, int nparts, double &md, double &m
         md = fmax(md, part[2 * i]);
         ms = fmax(ms, part[2 * i + 1]);
     }
-    for (int k = 32; k >= 1; k >>= 1) {
-        md = fmax(md, __shfl_xor(md, k, 64));
-        ms = fmax(ms, __shfl_xor(ms, k, 64));
-    }
+    md = wave_max(md);
+    ms = wave_max(ms);
     if ((threadIdx.x & 63) == 0) {
         red[0][threadIdx.x >> 6] = md;
         red[1][threadIdx.x >> 6] = ms;
     }
     __syncthreads();
-    if (threadIdx.x == 0)
-        for (int k = 1; k < (int)(blockDim.x >> 6); ++k) {
-            md = fmax(md, red[0][k]);
-            ms = fmax(ms, red[1][k]);
-        }
+    if (threadIdx.x < 64) {
+        // the (non-negative) wavefront maxima over the lanes of row 0
+        const int l = threadIdx.x, nw = blockDim.x >> 6;
+        md = row_max16(l < nw ? red[0][l] : 0.0);
+        ms = row_max16(l < nw ? red[1][l] : 0.0);
+    }
 }
 
 // ------------------------------------------------------------ reductions
 
-// Block-wide sum of NV doubles per thread in a fixed order (wave shuffles, then
-// the waves in index order). Result valid in thread 0.
+// Block-wide sum of NV doubles per thread (up to 16 wavefronts) in a fixed
+// order: a butterfly in every wavefront, then one over the wavefront partials
+// in wavefront 0. Result valid in thread 0.
 template <int NV>
 __device__ __forceinline__ void block_sum(double v[NV], double *lds /* [NV * 16] */) {
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     for (int p = 0; p < NV; ++p)
-        for (int s = 32; s >= 1; s >>= 1) v[p] += __shfl_xor(v[p], s, 64);
+        v[p] = wave_sum(v[p]);
     if (lane == 0)
         for (int p = 0; p < NV; ++p) lds[wv * NV + p] = v[p];
     __syncthreads();
-    if (threadIdx.x == 0) {
+    if (wv == 0) {
         const int nw = (blockDim.x + 63) >> 6;
-        for (int p = 0; p < NV; ++p) {
-            double s = 0.0;
-            for (int k = 0; k < nw; ++k) s += lds[k * NV + p];
-            v[p] = s;
-        }
+        for (int p = 0; p < NV; ++p) v[p] = row_sum16(lane < nw ? lds[lane * NV + p] : 0.0);
     }
     __syncthreads();
 }
@@ -725,21 +721,18 @@ __global__ __launch_bounds__(PAIR_CHUNK) void k_pair_chunk_y(const int *__restri
     if (threadIdx.x == 0)
         for (int k = 0; k < 9; ++k) partY[9 * c + k] = v[k];
     if (finish_prev) {
-        for (int k = 32; k >= 1; k >>= 1) {
-            pmd = fmax(pmd, __shfl_xor(pmd, k, 64));
-            pms = fmax(pms, __shfl_xor(pms, k, 64));
-        }
+        pmd = wave_max(pmd);
+        pms = wave_max(pms);
         if ((threadIdx.x & 63) == 0) {
             red[0][threadIdx.x >> 6] = pmd;
             red[1][threadIdx.x >> 6] = pms;
         }
         __syncthreads();
-        if (threadIdx.x == 0) {
-            for (int k = 1; k < (int)(blockDim.x >> 6); ++k) {
-                pmd = fmax(pmd, red[0][k]);
-                pms = fmax(pms, red[1][k]);
-            }
-            conv_finish(cv, pmd, pms);
+        if (threadIdx.x < 64) {
+            const int l = threadIdx.x, nw = blockDim.x >> 6;
+            pmd = row_max16(l < nw ? red[0][l] : 0.0);
+            pms = row_max16(l < nw ? red[1][l] : 0.0);
+            if (l == 0) conv_finish(cv, pmd, pms);
         }
     }
 }
@@ -845,22 +838,21 @@ __global__ __launch_bounds__(256) void k_depth_update(
         }
         if (ok) mdisp = fmax(mdisp, hypot(qq[1][0] - qq[0][0], qq[1][1] - qq[0][1]));
     }
-    for (int k = 32; k >= 1; k >>= 1) {
-        mdisp = fmax(mdisp, __shfl_xor(mdisp, k, 64));
-        mstep = fmax(mstep, __shfl_xor(mstep, k, 64));
-    }
+    mdisp = wave_max(mdisp);
+    mstep = wave_max(mstep);
     if ((threadIdx.x & 63) == 0) {
         red[0][threadIdx.x >> 6] = mdisp;
         red[1][threadIdx.x >> 6] = mstep;
     }
     __syncthreads();
-    if (threadIdx.x == 0) {
-        for (int k = 1; k < 4; ++k) {
-            mdisp = fmax(mdisp, red[0][k]);
-            mstep = fmax(mstep, red[1][k]);
+    if (threadIdx.x < 64) {
+        const int l = threadIdx.x;
+        mdisp = row_max16(l < 4 ? red[0][l] : 0.0);
+        mstep = row_max16(l < 4 ? red[1][l] : 0.0);
+        if (l == 0) {
+            part[2 * blockIdx.x] = mdisp;
+            part[2 * blockIdx.x + 1] = mstep;
         }
-        part[2 * blockIdx.x] = mdisp;
-        part[2 * blockIdx.x + 1] = mstep;
     }
 }
 

@@ -39,22 +39,20 @@ __device__ __forceinline__ double xthy(const double *X, const double *H21, const
     return s;
 }
 
-// Fixed-order block sum of NV doubles per thread; result valid in thread 0.
+// Fixed-order block sum of NV doubles per thread (up to 16 wavefronts): a
+// butterfly in every wavefront, then one over the wavefront partials in
+// wavefront 0; result valid in thread 0.
 template <int NV>
 __device__ __forceinline__ void block_sum_d(double v[NV], double *lds /* [NV * 16] */) {
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     for (int p = 0; p < NV; ++p)
-        for (int s = 32; s >= 1; s >>= 1) v[p] += __shfl_xor(v[p], s, 64);
+        v[p] = wave_sum(v[p]);
     if (lane == 0)
         for (int p = 0; p < NV; ++p) lds[wv * NV + p] = v[p];
     __syncthreads();
-    if (threadIdx.x == 0) {
+    if (wv == 0) {
         const int nw = (blockDim.x + 63) >> 6;
-        for (int p = 0; p < NV; ++p) {
-            double s = 0.0;
-            for (int k = 0; k < nw; ++k) s += lds[k * NV + p];
-            v[p] = s;
-        }
+        for (int p = 0; p < NV; ++p) v[p] = row_sum16(lane < nw ? lds[lane * NV + p] : 0.0);
     }
     __syncthreads();
 }
@@ -481,68 +479,234 @@ void launch_ic_inverse(hipStream_t s, Ctx &c) {
     k_ic_inverse<<<grid, SOLVE_THREADS, 0, s>>>(c.win(), c.d_Lfac, c.d_Sinv, c.d_flag, c.d_gate);
 }
 
+// Paths of the per-iteration solve, one kernel instance each (so that each
+// gets a register allocation of its own).
+enum SolvePath { SOLVE_IC = 0, SOLVE_FC_PACKED = 1, SOLVE_FC_TILED = 2 };
+
+// IC window cache at the top of the solve's LDS. Doubles: current poses [12 F],
+// p(0) poses [12 F], pair geometry at the linearization [GEO_STRIDE P], dtheta
+// [n rounded up to even], pair sums [9 P]; then ints: window-local host
+// and target frame of every pair [2 P], the frames' item pointers [F + 1], the
+// pairs' chunk pointers [P + 1] and the frames' items [2 P] (a window's items
+// are its pairs' host and target entries, so they start at 2 p0).
+__host__ __device__ inline int solve_cache_doubles(int F, int P) {
+    const int nq = (6 * F + 1) & ~1;
+    const int ints = 2 * P + (F + 1) + (P + 1) + 2 * P;
+    return 24 * F + GEO_STRIDE * P + nq + 9 * P + (ints + 1) / 2;
+}
+
+// Batched copy of the concatenation of NS global segments (segment s starts
+// at src[s] and ends at the cumulative length end[s]) into LDS, K elements per
+// thread per batch: fetch() issues the first batch into registers, store()
+// writes it and copies any further batches. Elements past the end read the
+// valid element *dummy; the first nsub elements are stored less sub.
+template <int NS, int K, typename V>
+struct LdsGather {
+    const V *src[NS];
+    int end[NS];
+    const V *dummy;
+    V v[K];
+    __device__ __forceinline__ void fetch(int b) {
+#pragma unroll
+        for (int u = 0; u < K; ++u) {
+            const int e = b + (int)threadIdx.x + u * SOLVE_THREADS;
+            const V *p = dummy;
+#pragma unroll
+            for (int s = 0; s < NS; ++s) {
+                const int beg = s ? end[s - 1] : 0;
+                p = (e >= beg && e < end[s]) ? src[s] + (e - beg) : p;
+            }
+            v[u] = *p;
+        }
+    }
+    __device__ __forceinline__ void put(V *dst, int b, V sub, int nsub) {
+#pragma unroll
+        for (int u = 0; u < K; ++u) {
+            const int e = b + (int)threadIdx.x + u * SOLVE_THREADS;
+            if (e < end[NS - 1]) dst[e] = e < nsub ? v[u] - sub : v[u];
+        }
+    }
+    __device__ __forceinline__ void store(V *dst, V sub, int nsub) {
+        put(dst, 0, sub, nsub);
+        for (int b = K * SOLVE_THREADS; b < end[NS - 1]; b += K * SOLVE_THREADS) {
+            fetch(b);
+            put(dst, b, sub, nsub);
+        }
+    }
+};
+
+// Keeps a wave-uniform value's load ahead of this point (so that the loads of
+// one batch are not split by a later branch).
+template <typename V>
+__device__ __forceinline__ void pin_sreg(V v) {
+    asm volatile("" ::"s"(v));
+}
+
+// S^{-1} entries that every thread of the IC product (up to IC_SPLIT_N
+// unknowns) prefetches at the start: SV_REG rows in registers, up to SV_LDS
+// more in a thread-private LDS area.
+constexpr int SV_REG = 21, SV_LDS = 15;
+
 // One solve per iteration and window (one workgroup each):
 //  0. pair sums of the reduced gradient from their chunk partials;
 //  1. reduced right-hand side b_f = sum over the frame's pairs of A^T y (target) or
 //     B^T y (host), zero on the window's pinned frame;
-//  2. dtheta = -S^{-1} b (IC: product with the stored inverse, one wavefront per
-//     row; FC: Cholesky of the freshly assembled S and two triangular solves);
+//  2. dtheta = -S^{-1} b (IC: product with the stored inverse; FC: Cholesky of
+//     the freshly assembled S and two triangular solves);
 //  3. pose update: IC R <- R_k R0^T exp(dw)^T R0, t <- t_k - R_k R0^T dt (Sec. 3.6);
 //     FC R <- exp(dw) R, t <- t + dt;
 //  4. the next relative poses of every pair and the relative steps A dth_f + B dth_h.
 // Window statistics (energy, squared residuals, count, largest pose step) go
 // to wstat[w]; the convergence kernel adds them over the windows.
-template <typename T>
+// With CACHE (IC), one batch of loads at the start brings every input that no
+// other load feeds (poses, pair geometry, the index lists and, up to
+// IC_SPLIT_N unknowns, S^{-1}) into LDS and registers, so that the only
+// dependent global loads left are the chunk partials. A single window's ranges
+// come as arguments (one_F >= 0: frames and pairs from 0), others' are loaded.
+template <typename T, int PATH, bool CACHE>
 __global__ __launch_bounds__(SOLVE_THREADS) void k_solve(
-    WinArgs wa, int ic, int tiled, int pinned, int stage, const int *__restrict__ frame_pair_ptr, const int *__restrict__ frame_pair_item,
-    const int *__restrict__ pair_host, const int *__restrict__ pair_target, const int *__restrict__ pair_chunk_ptr,
-    const double *__restrict__ partY, double *__restrict__ pairY, const double *__restrict__ geo_lin,
-    const double *__restrict__ S_all, const double *__restrict__ Sfac, const double *__restrict__ Linv,
-    const double *__restrict__ Sinv_all, double *__restrict__ poses, const double *__restrict__ poses0,
-    double *__restrict__ b_all, double *__restrict__ dth_all, double *__restrict__ dth_rel,
-    double *__restrict__ geo_next, T *__restrict__ rel_next, double *__restrict__ wstat, int *__restrict__ flag,
-    int *__restrict__ gate) {
+    WinArgs wa, int one_F, int one_P, int pinned, int stage, const int *__restrict__ frame_pair_ptr,
+    const int *__restrict__ frame_pair_item, const int *__restrict__ pair_host, const int *__restrict__ pair_target,
+    const int *__restrict__ pair_chunk_ptr, const double *__restrict__ partY, double *__restrict__ pairY,
+    const double *__restrict__ geo_lin, const double *__restrict__ S_all, const double *__restrict__ Sfac,
+    const double *__restrict__ Linv, const double *__restrict__ Sinv_all, double *__restrict__ poses,
+    const double *__restrict__ poses0, double *__restrict__ b_all, double *__restrict__ dth_all,
+    double *__restrict__ dth_rel, double *__restrict__ geo_next, T *__restrict__ rel_next,
+    double *__restrict__ wstat, int *__restrict__ flag, int *__restrict__ gate) {
+    constexpr bool ic = PATH == SOLVE_IC, tiled = PATH == SOLVE_FC_TILED, packed = PATH == SOLVE_FC_PACKED;
+    static_assert(ic || !CACHE, "the LDS cache serves the IC path");
     __shared__ double lds[LDS_DOUBLES];
     __shared__ double red[64 + 2 * LDS_MAX_N + 2];
-    if (*gate == 0) return;
-    if (*flag) {
-        // a factorization of this iteration failed: stop the batch
-        if (threadIdx.x == 0) *gate = 0;
-        return;
+
+    // the gate, the failure flag and the window's ranges
+    const int w = blockIdx.x;
+    const int gv = *gate, fv = *flag;
+    int f0 = 0, fe = one_F, p0 = 0, p1 = one_P, soff = 0;
+    if (one_F < 0) {
+        f0 = wa.frame_off[w];
+        fe = wa.frame_off[w + 1];
+        p0 = wa.pair_off[w];
+        p1 = wa.pair_off[w + 1];
+        soff = wa.S_off[w];
+        pin_sreg(f0);
+        pin_sreg(fe);
+        pin_sreg(p0);
+        pin_sreg(p1);
+        pin_sreg(soff);
     }
 
-    const int w = blockIdx.x;
-    const int f0 = wa.frame_off[w], F = wa.frame_off[w + 1] - f0;
-    const int p0 = wa.pair_off[w], p1 = wa.pair_off[w + 1];
-    const int n = 6 * F;
-    const double *S = S_all + wa.S_off[w];
-    const double *Sinv = Sinv_all + wa.S_off[w];
+    const int F = fe - f0, P = p1 - p0;
+    const int n = 6 * F, nq = (n + 1) & ~1;
+    const double *S = S_all + soff;
+    const double *Sinv = Sinv_all + soff;
     double *b_out = b_all + 6 * f0;
     double *dth_out = dth_all + 6 * f0;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
-    const bool packed = !tiled;
-    // rhs / solution in LDS (FC: after the packed factor; the panel scratch follows)
-    double *bx = lds + ((packed && !ic) ? n * (n + 1) / 2 : 0);
+    // rhs / solution in LDS (FC packed: after the packed factor; the panel scratch follows)
+    double *bx = lds + (packed ? n * (n + 1) / 2 : 0);
+    // IC product layout up to IC_SPLIT_N unknowns: thread (g, j) takes column j
+    // and rows g + NG u; group partials after bx
+    const int ncw = (n + 63) & ~63;
+    const int NG = ncw ? SOLVE_THREADS / ncw : 1;
+    const int mg = threadIdx.x / max(ncw, 1), mj = threadIdx.x % max(ncw, 1);
+    double *const part = bx + nq;
+
+    // the cache (IC) and its end; scratch of the steps stays below it
+    double *const ctop = CACHE ? lds + LDS_DOUBLES - solve_cache_doubles(F, P) : lds + LDS_DOUBLES;
+    double *const c_pose = ctop, *const c_pose0 = c_pose + 12 * F, *const c_geo = c_pose0 + 12 * F;
+    double *const c_dth = c_geo + GEO_STRIDE * P, *const c_y = c_dth + nq;
+    int *const c_host = reinterpret_cast<int *>(c_y + 9 * P), *const c_target = c_host + P;
+    int *const c_fptr = c_target + P, *const c_cptr = c_fptr + F + 1, *const c_item = c_cptr + P + 1;
+    // S^{-1} prefetch (CACHE, up to IC_SPLIT_N unknowns): SV_REG rows per
+    // thread in registers, then ul more in LDS after the group partials (the
+    // right-hand side's item maps then stay below them); ul is a multiple of 3
+    const bool pre = CACHE && n <= IC_SPLIT_N;
+    double *const c_sinv = part + SOLVE_THREADS;
+    const int ul = pre ? min(SV_LDS, (int)((ctop - c_sinv) / SOLVE_THREADS)) / 3 * 3 : 0;
+    double sv[SV_REG];
+    if constexpr (CACHE) {
+        LdsGather<4, 2, double> gd{{poses + 12 * f0, poses0 + 12 * f0, geo_lin + GEO_STRIDE * p0, dth_out},
+                                   {12 * F, 24 * F, 24 * F + GEO_STRIDE * P, 24 * F + GEO_STRIDE * P + (stage == 2 ? n : 0)},
+                                   wstat + 4 * w};
+        LdsGather<5, 1, int> gi{{pair_host + p0, pair_target + p0, frame_pair_ptr + f0, pair_chunk_ptr + p0,
+                                 frame_pair_item + 2 * p0},
+                                {P, 2 * P, 2 * P + F + 1, 3 * P + F + 2, 5 * P + F + 2},
+                                gate};
+        gd.fetch(0);
+        gi.fetch(0);
+        const bool col = mg < NG && mj < n;
+        double sl[SV_LDS];
+#pragma unroll
+        for (int u = 0; u < SV_LDS; ++u) sl[u] = 0.0;
+#pragma unroll
+        for (int u = 0; u < SV_REG; ++u) sv[u] = 0.0;
+        if (pre) {
+#pragma unroll
+            for (int u = 0; u < SV_LDS; ++u) {
+                const int i = mg + NG * (SV_REG + u);
+                const bool ok = col && u < ul && i < n;
+                const double v = *(ok ? Sinv + (size_t)i * n + mj : wstat + 4 * w);
+                sl[u] = ok ? v : 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < SV_REG; ++u) {
+                const int i = mg + NG * u;
+                const bool ok = col && i < n;
+                const double v = *(ok ? Sinv + (size_t)i * n + mj : wstat + 4 * w);
+                sv[u] = ok ? v : 0.0;
+            }
+        }
+        if (gv == 0) return;
+        if (fv) {
+            if (threadIdx.x == 0) *gate = 0;
+            return;
+        }
+        gd.store(c_pose, 0.0, 0);
+        gi.store(c_host, f0, 2 * P);
+#pragma unroll
+        for (int u = 0; u < SV_LDS; ++u)
+            if (u < ul) c_sinv[u * SOLVE_THREADS + threadIdx.x] = sl[u];
+#pragma unroll
+        for (int u = 0; u < SV_REG; ++u) pin_reg(sv[u]);
+        __syncthreads();
+    } else {
+        if (gv == 0) return;
+        if (fv) {
+            // a factorization of this iteration failed: stop the batch
+            if (threadIdx.x == 0) *gate = 0;
+            return;
+        }
+    }
+    auto fptr = [&](int f) { return CACHE ? c_fptr[f - f0] : frame_pair_ptr[f]; };
+    auto geo_of = [&](int p) { return CACHE ? c_geo + GEO_STRIDE * (p - p0) : geo_lin + GEO_STRIDE * p; };
+
     // stage 0: the whole step; stage 1: up to the right-hand side b; stage 2:
     // from dtheta (formed between the stages by k_ic_matvec) to the pose update
+    // with the cache, every global store of the step waits for the end of the
+    // kernel (results stay in LDS and registers until then)
+    double v3[3] = {0.0, 0.0, 0.0};
     if (stage != 2) {
     {
         // pair sums of the chunk partials (chunks in order; loads unrolled so
         // that a pair's chunks are fetched together), and the window's energy
         // statistics as a fixed-order block sum of the pair sums
-        double v3[3] = {0.0, 0.0, 0.0};
-        for (int e = threadIdx.x; e < (p1 - p0) * 9; e += blockDim.x) {
-            const int p = p0 + e / 9, k = e % 9;
-            const int c0 = pair_chunk_ptr[p], c1 = pair_chunk_ptr[p + 1];
+        for (int e = threadIdx.x; e < P * 9; e += blockDim.x) {
+            const int pl = e / 9, k = e % 9;
+            const int c0 = CACHE ? c_cptr[pl] : pair_chunk_ptr[p0 + pl];
+            const int c1 = CACHE ? c_cptr[pl + 1] : pair_chunk_ptr[p0 + pl + 1];
             double s = 0.0;
 #pragma unroll 8
             for (int c = c0; c < c1; ++c) s += partY[9 * c + k];
-            pairY[9 * p + k] = s;
+            if (CACHE)
+                c_y[9 * pl + k] = s;
+            else
+                pairY[9 * (p0 + pl) + k] = s;
             if (k >= 6) v3[k - 6] += s;
         }
-        __threadfence_block();
+        // global pair sums are read back below only without the cache
+        if constexpr (!CACHE) __threadfence_block();
         block_sum_d<3>(v3, red);
-        if (threadIdx.x == 0) {
+        if (!CACHE && threadIdx.x == 0) {
             wstat[4 * w + 0] = v3[0];
             wstat[4 * w + 1] = v3[1];
             wstat[4 * w + 2] = v3[2];
@@ -553,20 +717,21 @@ __global__ __launch_bounds__(SOLVE_THREADS) void k_solve(
     // (in chunks of what fits beside the rhs), then every row adds its frame's
     // items of the chunk; rows of the pinned frame stay zero.
     {
-        double *cb = bx + ((n + 1) & ~1);
-        const int cap_items = (int)((lds + LDS_DOUBLES - cb) / 6);
-        const int i0 = frame_pair_ptr[f0], i1 = frame_pair_ptr[f0 + F];
+        double *cb = bx + nq;
+        const int cap_items = (int)(((pre ? c_sinv : ctop) - cb) / 6);
+        const int i0 = fptr(f0), i1 = fptr(f0 + F);
         for (int e = threadIdx.x; e < n; e += blockDim.x) bx[e] = 0.0;
         for (int c0 = i0; c0 < i1; c0 += cap_items) {
             const int c1 = min(i1, c0 + cap_items);
             for (int i = c0 + threadIdx.x; i < c1; i += blockDim.x) {
-                const int p = frame_pair_item[i] >> 1, is_host = frame_pair_item[i] & 1;
+                const int it = CACHE ? c_item[i - i0] : frame_pair_item[i];
+                const int p = it >> 1, is_host = it & 1;
                 double yv[6], out[6];
-                for (int a = 0; a < 6; ++a) yv[a] = pairY[9 * p + a];
+                for (int a = 0; a < 6; ++a) yv[a] = CACHE ? c_y[9 * (p - p0) + a] : pairY[9 * p + a];
                 if (is_host)
-                    apply_Bt(geo_lin + GEO_STRIDE * p, yv, out);
+                    apply_Bt(geo_of(p), yv, out);
                 else
-                    apply_At(geo_lin + GEO_STRIDE * p, yv, out);
+                    apply_At(geo_of(p), yv, out);
                 double *o = cb + 6 * (i - c0);
                 for (int a = 0; a < 6; ++a) o[a] = out[a];
             }
@@ -574,35 +739,65 @@ __global__ __launch_bounds__(SOLVE_THREADS) void k_solve(
             for (int e = threadIdx.x; e < n; e += blockDim.x) {
                 const int lf = e / 6, r = e % 6, f = f0 + lf;
                 if (lf == pinned) continue;
-                const int a0 = max(c0, frame_pair_ptr[f]), a1 = min(c1, frame_pair_ptr[f + 1]);
+                const int a0 = max(c0, fptr(f)), a1 = min(c1, fptr(f + 1));
                 double s = bx[e];
                 for (int i = a0; i < a1; ++i) s += cb[6 * (i - c0) + r];
                 bx[e] = s;
             }
             __syncthreads();
         }
-        for (int e = threadIdx.x; e < n; e += blockDim.x) b_out[e] = bx[e];
+        if (!CACHE)
+            for (int e = threadIdx.x; e < n; e += blockDim.x) b_out[e] = bx[e];
     }
     __syncthreads();
     }
-    if (stage == 1) return;
+    // pair sums, right-hand side and energy statistics to global memory
+    auto store_b = [&]() {
+        for (int e = threadIdx.x; e < 9 * P; e += blockDim.x) pairY[9 * p0 + e] = c_y[e];
+        for (int e = threadIdx.x; e < n; e += blockDim.x) b_out[e] = bx[e];
+        if (threadIdx.x == 0) {
+            wstat[4 * w + 0] = v3[0];
+            wstat[4 * w + 1] = v3[1];
+            wstat[4 * w + 2] = v3[2];
+        }
+    };
+    if (stage == 1) {
+        if (CACHE) store_b();
+        return;
+    }
     if (stage == 2) {
-        // dtheta is in global memory
-    } else if (ic) {
+        // dtheta is in global memory (and in the cache)
+    } else if constexpr (ic) {
         // dtheta = -S^{-1} b with the inverse formed at p(0) (stored by
-        // columns; S^{-1} is symmetric). Up to 256 unknowns: NG groups of
-        // threads, each thread one column j and every NG-th row i, so that a
-        // wavefront reads 64 consecutive entries of a row; loads issued in
-        // batches of 12, group partials added in group order.
-        if (n <= 256) {
-            const int ncw = (n + 63) & ~63;
-            const int NG = blockDim.x / ncw;
-            const int g = threadIdx.x / ncw, j = threadIdx.x % ncw;
-            double *part = bx + ((n + 1) & ~1);
+        // columns; S^{-1} is symmetric). Up to IC_SPLIT_N unknowns: NG groups
+        // of threads, each thread one column j and every NG-th row i, so that
+        // a wavefront reads 64 consecutive entries of a row; rows prefetched at
+        // the start first (registers, then LDS), the rest loaded in batches of
+        // 12; group partials added in group order.
+        if (n <= IC_SPLIT_N) {
+            const int g = mg, j = mj;
             double s0 = 0.0, s1 = 0.0, s2 = 0.0;
             if (g < NG && j < n) {
+                int u0 = 0;
+                if (pre) {
+#pragma unroll
+                    for (int u = 0; u < SV_REG; u += 3) {
+                        const int i = g + NG * u;
+                        s0 += sv[u] * bx[min(i, n - 1)];
+                        s1 += sv[u + 1] * bx[min(i + NG, n - 1)];
+                        s2 += sv[u + 2] * bx[min(i + 2 * NG, n - 1)];
+                    }
+                    for (int u = 0; u < ul; u += 3) {
+                        const int i = g + NG * (SV_REG + u);
+                        const double *q = c_sinv + u * SOLVE_THREADS + threadIdx.x;
+                        s0 += q[0] * bx[min(i, n - 1)];
+                        s1 += q[SOLVE_THREADS] * bx[min(i + NG, n - 1)];
+                        s2 += q[2 * SOLVE_THREADS] * bx[min(i + 2 * NG, n - 1)];
+                    }
+                    u0 = SV_REG + ul;
+                }
                 constexpr int U = 12;
-                for (int i0 = g; i0 < n; i0 += U * NG) {
+                for (int i0 = g + NG * u0; i0 < n; i0 += U * NG) {
                     double v[U];
 #pragma unroll
                     for (int u = 0; u < U; ++u) {
@@ -623,7 +818,10 @@ __global__ __launch_bounds__(SOLVE_THREADS) void k_solve(
             if (threadIdx.x < n) {
                 double s = 0.0;
                 for (int q = 0; q < NG; ++q) s += part[q * ncw + threadIdx.x];
-                dth_out[threadIdx.x] = -s;
+                if (CACHE)
+                    c_dth[threadIdx.x] = -s;
+                else
+                    dth_out[threadIdx.x] = -s;
             }
         } else {
             for (int i = wv; i < n; i += nw) {
@@ -631,11 +829,16 @@ __global__ __launch_bounds__(SOLVE_THREADS) void k_solve(
                 double s = 0.0;
 #pragma unroll 8
                 for (int j = lane; j < n; j += 64) s += row[j] * bx[j];
-                for (int k = 32; k >= 1; k >>= 1) s += __shfl_xor(s, k, 64);
-                if (lane == 0) dth_out[i] = -s;
+                s = wave_sum(s);
+                if (lane == 0) {
+                    if (CACHE)
+                        c_dth[i] = -s;
+                    else
+                        dth_out[i] = -s;
+                }
             }
         }
-    } else if (packed) {
+    } else if constexpr (packed) {
         // FC: factor the S assembled this iteration
         const int np = n * (n + 1) / 2;
         double *invd = red + 64;
@@ -672,21 +875,24 @@ __global__ __launch_bounds__(SOLVE_THREADS) void k_solve(
         tile_chol_solve<SOLVE_THREADS>(Sfac, Linv, n, bx, lds + n, 0);
         for (int i = threadIdx.x; i < n; i += blockDim.x) dth_out[i] = -bx[i];
     }
-    __threadfence_block();
+    // with the cache, no thread reads back what this kernel stored globally:
+    // a fence here would only wait for those stores
+    if constexpr (!CACHE) __threadfence_block();
     __syncthreads();
+    const double *dth = CACHE ? c_dth : dth_out;
     // largest pose step
     double mx = 0.0;
-    for (int i = threadIdx.x; i < n; i += blockDim.x) mx = fmax(mx, fabs(dth_out[i]));
-    for (int k = 32; k >= 1; k >>= 1) mx = fmax(mx, __shfl_xor(mx, k, 64));
+    for (int i = threadIdx.x; i < n; i += blockDim.x) mx = fmax(mx, fabs(dth[i]));
+    mx = wave_max(mx);
     if (lane == 0) red[wv] = mx;
     // pose update
     for (int lf = threadIdx.x; lf < F; lf += blockDim.x) {
-        const double *x = dth_out + 6 * lf;
+        const double *x = dth + 6 * lf;
+        const double *P = CACHE ? c_pose + 12 * lf : poses + 12 * (f0 + lf);
         double dR[9], Rn[9], tn[3];
         so3_exp(x, dR);
-        double *P = poses + 12 * (f0 + lf);
         if (ic) {
-            const double *P0 = poses0 + 12 * (f0 + lf);
+            const double *P0 = CACHE ? c_pose0 + 12 * lf : poses0 + 12 * (f0 + lf);
             double A[9], Q[9];
             mat3_mul_bt(P, P0, Q);  // R_k R0^T
             mat3_mul_bt(Q, dR, A);  // R_k R0^T dR^T
@@ -696,20 +902,23 @@ __global__ __launch_bounds__(SOLVE_THREADS) void k_solve(
             mat3_mul(dR, P, Rn);
             for (int i = 0; i < 3; ++i) tn[i] = P[9 + i] + x[3 + i];
         }
-        for (int i = 0; i < 9; ++i) P[i] = Rn[i];
-        for (int i = 0; i < 3; ++i) P[9 + i] = tn[i];
+        double *Pn = CACHE ? c_pose + 12 * lf : poses + 12 * (f0 + lf);
+        for (int i = 0; i < 9; ++i) Pn[i] = Rn[i];
+        for (int i = 0; i < 3; ++i) Pn[9 + i] = tn[i];
     }
-    __threadfence_block();
+    if constexpr (!CACHE) __threadfence_block();
     __syncthreads();
-    if (threadIdx.x == 0) {
-        double m2 = 0.0;
-        for (int k = 0; k < nw; ++k) m2 = fmax(m2, red[k]);
-        wstat[4 * w + 3] = m2;
+    if (wv == 0) {
+        const double m2 = row_max16(lane < nw ? red[lane] : 0.0);
+        if (lane == 0) wstat[4 * w + 3] = m2;
     }
-    // next relative poses and relative steps per pair
+    // next relative poses and relative steps per pair (frames window-local)
+    const double *pose_w = CACHE ? c_pose : poses + 12 * f0;
     for (int p = p0 + threadIdx.x; p < p1; p += blockDim.x) {
-        const double *Ph = poses + 12 * pair_host[p];
-        const double *Pf = poses + 12 * pair_target[p];
+        const int h = CACHE ? c_host[p - p0] : pair_host[p] - f0;
+        const int t = CACHE ? c_target[p - p0] : pair_target[p] - f0;
+        const double *Ph = pose_w + 12 * h;
+        const double *Pf = pose_w + 12 * t;
         double R[9];
         mat3_mul_bt(Pf, Ph, R);
         double *g = geo_next + GEO_STRIDE * p;
@@ -727,12 +936,19 @@ __global__ __launch_bounds__(SOLVE_THREADS) void k_solve(
         g[15] = 0.0;
         double xf[6], xh[6], af[6], bh[6];
         for (int a = 0; a < 6; ++a) {
-            xf[a] = dth_all[6 * pair_target[p] + a];
-            xh[a] = dth_all[6 * pair_host[p] + a];
+            xf[a] = dth[6 * t + a];
+            xh[a] = dth[6 * h + a];
         }
-        apply_A(geo_lin + GEO_STRIDE * p, xf, af);
-        apply_B(geo_lin + GEO_STRIDE * p, xh, bh);
+        apply_A(geo_of(p), xf, af);
+        apply_B(geo_of(p), xh, bh);
         for (int r = 0; r < 6; ++r) dth_rel[6 * p + r] = af[r] + bh[r];
+    }
+    if constexpr (CACHE) {
+        if (stage == 0) {
+            store_b();
+            for (int e = threadIdx.x; e < n; e += blockDim.x) dth_out[e] = c_dth[e];
+        }
+        for (int e = threadIdx.x; e < 12 * F; e += blockDim.x) poses[12 * f0 + e] = c_pose[e];
     }
 }
 
@@ -749,7 +965,7 @@ __global__ __launch_bounds__(256) void k_ic_matvec(int n, const double *__restri
     double s = 0.0;
 #pragma unroll 8
     for (int j = lane; j < n; j += 64) s += row[j] * b[j];
-    for (int k = 32; k >= 1; k >>= 1) s += __shfl_xor(s, k, 64);
+    s = wave_sum(s);
     if (lane == 0) dth[i] = -s;
 }
 
@@ -800,26 +1016,61 @@ void launch_ic_factor(hipStream_t s, Ctx &c) {
     k_ic_factor<<<c.nwin, SOLVE_THREADS, 0, s>>>(c.win(), c.d_S, c.d_Lfac, c.d_flag, c.d_gate);
 }
 
+// Whether every window's IC cache fits in LDS beside the step's scratch and
+// the windows' items start at twice their first pair.
+static bool solve_cache_fits(const Ctx &c) {
+    const std::vector<int> &fp = c.st.frame_pair_ptr;
+    if (c.win_frame_off.size() != (size_t)c.nwin + 1 || c.win_pair_off.size() != (size_t)c.nwin + 1) return false;
+    for (int w = 0; w < c.nwin; ++w) {
+        const int f0 = c.win_frame_off[w], f1 = c.win_frame_off[w + 1];
+        const int p0 = c.win_pair_off[w], p1 = c.win_pair_off[w + 1];
+        if ((size_t)f1 >= fp.size() || fp[f0] != 2 * p0 || fp[f1] != 2 * p1) return false;
+        const int nq = (6 * (f1 - f0) + 1) & ~1;
+        if (LDS_DOUBLES - solve_cache_doubles(f1 - f0, p1 - p0) < nq + std::max(SOLVE_THREADS, 6 * 64)) return false;
+    }
+    return true;
+}
+
+template <typename T, int PATH, bool CACHE>
+static void solve_kernel(hipStream_t s, Ctx &c, int stage, const double *geo_lin, double *geo_next, T *rel_next) {
+    // one window starting at frame, pair and S offset 0: its ranges as arguments
+    const bool one = c.nwin == 1 && c.win_frame_off.size() == 2 && c.win_pair_off.size() == 2 &&
+                     c.win_S_off.size() >= 1 && c.win_frame_off[0] == 0 && c.win_pair_off[0] == 0 &&
+                     c.win_S_off[0] == 0;
+    k_solve<T, PATH, CACHE><<<c.nwin, SOLVE_THREADS, 0, s>>>(
+        c.win(), one ? c.win_frame_off[1] : -1, one ? c.win_pair_off[1] : -1, c.cfg.pinned_frame, stage, c.d_frame_pair_ptr, c.d_frame_pair_item, c.d_pair_host, c.d_pair_target,
+        c.d_pair_chunk_ptr, c.d_partY, c.d_pairY, geo_lin, c.d_S, c.d_Sfac, c.d_Linv, c.d_Sinv, c.d_poses,
+        c.d_poses0, c.d_b, c.d_dtheta, c.d_dth_rel, geo_next, rel_next, c.d_wstat, c.d_flag, c.d_gate);
+}
+
+template <typename T>
+static void solve_path(hipStream_t s, Ctx &c, int stage, bool cache, const double *geo_lin, double *geo_next,
+                       T *rel_next) {
+    if (c.cfg.mode == PBA_IC_PROXY) {
+        if (cache)
+            solve_kernel<T, SOLVE_IC, true>(s, c, stage, geo_lin, geo_next, rel_next);
+        else
+            solve_kernel<T, SOLVE_IC, false>(s, c, stage, geo_lin, geo_next, rel_next);
+    } else if (c.tiled()) {
+        solve_kernel<T, SOLVE_FC_TILED, false>(s, c, stage, geo_lin, geo_next, rel_next);
+    } else {
+        solve_kernel<T, SOLVE_FC_PACKED, false>(s, c, stage, geo_lin, geo_next, rel_next);
+    }
+}
+
 void launch_solve(hipStream_t s, Ctx &c, const double *geo_lin, double *geo_next, void *rel_next, bool rel_double,
                   double *stat) {
     (void)stat;
-    const int ic = c.cfg.mode == PBA_IC_PROXY ? 1 : 0;
+    const bool ic = c.cfg.mode == PBA_IC_PROXY;
     const int n = 6 * c.F;
+    const bool cache = ic && solve_cache_fits(c);
     // IC on one large window: the product with S^{-1} spread over many workgroups
     const bool split = ic && c.nwin == 1 && n > IC_SPLIT_N;
     auto solve = [&](int stage) {
         if (rel_double)
-            k_solve<double><<<c.nwin, SOLVE_THREADS, 0, s>>>(
-                c.win(), ic, c.tiled() ? 1 : 0, c.cfg.pinned_frame, stage, c.d_frame_pair_ptr, c.d_frame_pair_item,
-                c.d_pair_host, c.d_pair_target, c.d_pair_chunk_ptr, c.d_partY, c.d_pairY, geo_lin, c.d_S, c.d_Sfac,
-                c.d_Linv, c.d_Sinv, c.d_poses, c.d_poses0, c.d_b, c.d_dtheta, c.d_dth_rel, geo_next,
-                (double *)rel_next, c.d_wstat, c.d_flag, c.d_gate);
+            solve_path<double>(s, c, stage, cache, geo_lin, geo_next, (double *)rel_next);
         else
-            k_solve<float><<<c.nwin, SOLVE_THREADS, 0, s>>>(
-                c.win(), ic, c.tiled() ? 1 : 0, c.cfg.pinned_frame, stage, c.d_frame_pair_ptr, c.d_frame_pair_item,
-                c.d_pair_host, c.d_pair_target, c.d_pair_chunk_ptr, c.d_partY, c.d_pairY, geo_lin, c.d_S, c.d_Sfac,
-                c.d_Linv, c.d_Sinv, c.d_poses, c.d_poses0, c.d_b, c.d_dtheta, c.d_dth_rel, geo_next,
-                (float *)rel_next, c.d_wstat, c.d_flag, c.d_gate);
+            solve_path<float>(s, c, stage, cache, geo_lin, geo_next, (float *)rel_next);
     };
     if (!split) {
         solve(0);

@@ -8,6 +8,7 @@
 namespace pba {
 
 constexpr int TB = TCHOL_TILE;   // tile edge
+static_assert(TB == 32, "the tile solves reduce over halves of a wavefront");
 
 // LDS scratch (doubles) that tile_chol_solve<NT> needs beside x.
 constexpr int tile_solve_tmp(int nt_threads) { return TB * (nt_threads / TB) + TB + TB * (TB + 1); }
@@ -16,7 +17,7 @@ constexpr int tile_solve_tmp(int nt_threads) { return TB * (nt_threads / TB) + T
 // threads. Forward substitution starts at tile k0 (b is zero above it). Every
 // tile step stages the inverse diagonal tile in LDS (one load per thread,
 // overlapped with the step's panel loads) and forms its product with 32-lane
-// shuffle sums. tmp: tile_solve_tmp(NT) doubles of LDS.
+// sums over half wavefronts. tmp: tile_solve_tmp(NT) doubles of LDS.
 template <int NT>
 __device__ void tile_chol_solve(const double *__restrict__ L, const double *__restrict__ Linv, int n, double *x,
                                 double *tmp, int k0) {
@@ -48,8 +49,7 @@ __device__ void tile_chol_solve(const double *__restrict__ L, const double *__re
 #pragma unroll
             for (int u = 0; u < RPW; ++u) {
                 const int r = wv + NW * u;
-                double v = s[u];
-                for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+                const double v = wave_sum(s[u]);
                 if (lane == 0) t[r] = (r0 + r < n) ? x[r0 + r] - v : 0.0;
             }
         }
@@ -60,8 +60,7 @@ __device__ void tile_chol_solve(const double *__restrict__ L, const double *__re
         __syncthreads();
         // x_r = sum_{k <= r} Linv_K(r, k) t_k
         for (int r = rr; r < TB; r += RP) {
-            double v = kk <= r ? lv[r * (TB + 1) + kk] * t[kk] : 0.0;
-            for (int o = TB / 2; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+            const double v = half_sum32(kk <= r ? lv[r * (TB + 1) + kk] * t[kk] : 0.0);
             if (kk == 0 && r0 + r < n) x[r0 + r] = v;
         }
         __syncthreads();
@@ -84,15 +83,13 @@ __device__ void tile_chol_solve(const double *__restrict__ L, const double *__re
         }
         __syncthreads();
         for (int r = rr; r < TB; r += RP) {
-            double v = kk < Q ? tmp[kk * TB + r] : 0.0;
-            for (int o = TB / 2; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+            const double v = half_sum32(kk < Q ? tmp[kk * TB + r] : 0.0);
             if (kk == 0) t[r] = (r0 + r < n) ? x[r0 + r] - v : 0.0;
         }
         __syncthreads();
         // x_r = sum_{k >= r} Linv_K(k, r) t_k
         for (int r = rr; r < TB; r += RP) {
-            double v = kk >= r ? lv[kk * (TB + 1) + r] * t[kk] : 0.0;
-            for (int o = TB / 2; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+            const double v = half_sum32(kk >= r ? lv[kk * (TB + 1) + r] * t[kk] : 0.0);
             if (kk == 0 && r0 + r < n) x[r0 + r] = v;
         }
         __syncthreads();

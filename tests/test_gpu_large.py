@@ -81,3 +81,23 @@ def test_tiled_iterations_fp32(mid40, mode):
     assert ok, (q99, worst)
     ev, oev = s.evaluate(0), gn.evaluate(0)
     assert abs(ev["rmse"] / oev["rmse"] - 1) <= 1e-4
+
+
+def test_ic_split_solve_iterations_fp64():
+    """IC with 6F = 288 > 256 unknowns on one window: the step's product with
+    S^{-1} runs between the two stages of the solve (many workgroups), and the
+    window's poses, pair geometry and index lists fit the solve's LDS cache, so
+    the second stage reads dtheta from there."""
+    sc = scenes.mid(n_per_host=400, n_frames=48)
+    s = make(sc, "ic", 0)
+    gn = GaussNewton(Problem.from_scene(sc), "ic")
+    for level in (2, 1, 0):
+        st = s.iterate(level, 3)
+        ost = gn.iterate(level, 3)
+        for a, o in zip(st, ost):
+            assert a["n_active"] == o["n_active"]
+            assert abs(a["energy"] / o["energy"] - 1) <= 1e-9
+    poses, d = s.get_params()
+    assert rot_err(poses, gn.poses).max() <= 1e-8
+    assert trans_rel_err(poses, gn.poses).max() <= 1e-8
+    assert np.abs(d / gn.d - 1).max() <= 1e-8
