@@ -145,7 +145,7 @@ void release_frames(Ctx &c) {
         dfree(c.lv[l].K);
         c.lv[l].W = c.lv[l].H = 0;
     }
-    for (double **p : {&c.d_poses, &c.d_poses0, &c.d_K0, &c.d_S, &c.d_Sinv, &c.d_Lfac, &c.d_Sfac, &c.d_Linv, &c.d_b,
+    for (double **p : {&c.d_poses, &c.d_poses0, &c.d_poses_alt, &c.d_K0, &c.d_S, &c.d_Sinv, &c.d_Lfac, &c.d_Sfac, &c.d_Linv, &c.d_b,
                        &c.d_dtheta, &c.d_stats, &c.d_mu})
         dfree(*p);
     dfree(c.d_flag);
@@ -154,6 +154,7 @@ void release_frames(Ctx &c) {
     dfree(c.d_du_part);
     dfree(c.d_pairK0);
     dfree(c.d_obs_prange);
+    dfree(c.d_step_sel);
     for (int **p : {&c.d_win_frame_off, &c.d_win_S_off, &c.d_win_L_off, &c.d_frame_win}) dfree(*p);
     dfree(c.d_wstat);
     c.stats_cap = 0;
@@ -359,10 +360,14 @@ pba_status one_iteration(Ctx &c, int level, double *stat, hipEvent_t ev0, hipEve
     double *geo_next = c.flip ? c.d_geo_a : c.d_geo_b;
     T *rel_cur = (T *)(c.flip ? c.d_rel_b : c.d_rel_a);
     T *rel_next = (T *)(c.flip ? c.d_rel_a : c.d_rel_b);
+    const bool fused = ic_fused(c);
     if (c.cfg.mode == PBA_IC_PROXY) {
         Launch<T>::ic_residual(s, c, level, rel_cur, ev0, ev1);
         Launch<T>::pair_reduce_y(s, c, prev_stat, conv_px, level);
-        launch_solve(s, c, c.d_geo0, geo_next, rel_next, is_fp64(c), stat);
+        if (fused)
+            launch_ic_step(s, c, c.d_geo0, geo_cur, geo_next, rel_next, is_fp64(c));
+        else
+            launch_solve(s, c, c.d_geo0, geo_next, rel_next, is_fp64(c), stat);
     } else {
         if (is_mixed(c))
             launch_linearize_mixed(s, c, level, false, (const float *)rel_cur, c.iters_in_level == 0, ev0, ev1);
@@ -380,7 +385,10 @@ pba_status one_iteration(Ctx &c, int level, double *stat, hipEvent_t ev0, hipEve
     // IC: the end of the iteration (statistics, convergence gate) is taken by the
     // next iteration's pair sums, or by a kernel of its own after the last one
     const bool finish = c.cfg.mode != PBA_IC_PROXY || last;
-    Launch<T>::depth_update(s, c, geo_cur, geo_next, stat, conv_px, level, finish);
+    if (!fused)
+        Launch<T>::depth_update(s, c, geo_cur, geo_next, stat, conv_px, level, finish);
+    else if (finish)
+        launch_conv(s, c, stat, conv_px, du_nparts(c), level, true);
     HIPCHK(hipGetLastError());
     c.s_valid = true;
     c.flip = !c.flip;
@@ -443,6 +451,7 @@ pba_status run_iterations(Ctx &c, int level, int n_iters, pba_iter_stats *out, d
     for (int k = 0; k < n_iters; ++k) {
         hipEvent_t e0 = timing ? c.ev_pool[2 * k] : nullptr, e1 = timing ? c.ev_pool[2 * k + 1] : nullptr;
         double *stat = c.d_stats + (size_t)k * ST_STRIDE;
+        c.batch_k = k;
         double *prev = k > 0 ? stat - ST_STRIDE : nullptr;
         const bool last = k == n_iters - 1;
         st = is_fp64(c) ? one_iteration<double>(c, level, stat, e0, e1, conv_px, prev, last)
@@ -508,6 +517,7 @@ pba_status enqueue_solve(Ctx &c, int max_iters, double conv_px, bool events) {
             hipEvent_t e0 = events ? c.ev_pool[2 * idx] : nullptr, e1 = events ? c.ev_pool[2 * idx + 1] : nullptr;
             double *prev = k > 0 ? stat - ST_STRIDE : nullptr;
             const bool last = k == max_iters - 1;
+            c.batch_k = k;
             st = is_fp64(c) ? one_iteration<double>(c, level, stat, e0, e1, conv_px, prev, last)
                             : one_iteration<float>(c, level, stat, e0, e1, conv_px, prev, last);
             if (st != PBA_OK) return st;
@@ -658,6 +668,7 @@ pba_status load_frames(Ctx &c, int n_frames, int width, int height, const float 
     const size_t nS = (size_t)c.win_S_off[c.nwin], nL = (size_t)c.win_L_off[c.nwin];
     HIPCHK(dalloc(c.d_poses, Pz.size() * sizeof(double)));
     HIPCHK(dalloc(c.d_poses0, Pz.size() * sizeof(double)));
+    HIPCHK(dalloc(c.d_poses_alt, Pz.size() * sizeof(double)));
     HIPCHK(hipMemcpyAsync(c.d_poses, Pz.data(), Pz.size() * sizeof(double), hipMemcpyHostToDevice, c.stream));
     HIPCHK(dalloc(c.d_S, nS * sizeof(double)));
     if (c.cfg.mode == PBA_IC_PROXY) {
@@ -781,6 +792,27 @@ pba_status load_points(Ctx &c, int n_points, const std::vector<int> &hf, const s
             pr[2 * (size_t)o + 1] = optr[s.obs_point[o] + 1];
         }
         HIPCHK(upload(c, c.d_obs_prange, pr));
+        // frames each depth workgroup of the fused IC step observes
+        dfree(c.d_step_sel);
+        c.step_sel_max = 0;
+        const int nbk = (n_points + IC_STEP_PTS - 1) / IC_STEP_PTS;
+        if (c.F <= STEP_SEL_STRIDE - 4 && nbk > 0) {
+            std::vector<unsigned long long> mask((size_t)nbk, 0ull);
+            for (int o = 0; o < O; ++o) {
+                const int p = s.obs_pair[o];
+                mask[(size_t)(s.obs_point[o] / IC_STEP_PTS)] |= (1ull << s.pair_host[p]) | (1ull << s.pair_target[p]);
+            }
+            std::vector<int> sel((size_t)nbk * STEP_SEL_STRIDE, 0);
+            for (int b = 0; b < nbk; ++b) {
+                int *e = sel.data() + (size_t)b * STEP_SEL_STRIDE;
+                for (int f = 0; f < c.F; ++f)
+                    if ((mask[(size_t)b] >> f) & 1ull) e[1 + e[0]++] = f;
+                e[STEP_SEL_STRIDE - 2] = (int)(unsigned)(mask[(size_t)b] & 0xffffffffull);
+                e[STEP_SEL_STRIDE - 1] = (int)(unsigned)(mask[(size_t)b] >> 32);
+                c.step_sel_max = std::max(c.step_sel_max, e[0]);
+            }
+            HIPCHK(upload(c, c.d_step_sel, sel));
+        }
     }
     HIPCHK(dalloc(c.d_icr, (size_t)O * IC_REC * rs));
     for (int l = 0; l < c.cfg.n_levels; ++l) {

@@ -67,8 +67,11 @@ constexpr int SP = 17;   // LDS pitch of the 16 x 16 scratch blocks
 // Called by a whole 256-thread block; wavefront 0 does the work, blocked 2 x 2
 // in 16-wide panels. Panel 1 (columns 0-15 of all 32 rows) and, after the
 // update A22 -= L21 L21^T on FP64 MFMA, panel 2 (A22) are factored with the
-// rows in registers (lane r holds row r): each column step reads the pivot and
-// the column's entries with scalar lane reads, without LDS round trips. The
+// rows in registers (lane r holds row r): each column step reads the pivot
+// with a scalar lane read and the column's multipliers with broadcast LDS
+// reads (one write and one read round trip per column); the rank-one update
+// runs on every lane (entries above the diagonal take values that are never
+// read and are zeroed when the panel is stored). The
 // inverse is [X11 0; X21 X22] with X11 = L11^{-1} and X22 = L22^{-1} formed
 // at once by forward substitution (lane c of each half one column) and
 // X21 = -X22 (L21 X11) as two MFMA products. s1, s2: LDS scratch of 16 x SP
@@ -90,6 +93,7 @@ __device__ __forceinline__ bool tile_potrf_inv(double *t, int nb, double *__rest
         // panel 1: columns 0..15 of rows 0..31 (L11 and L21)
 #pragma unroll
         for (int c = 0; c < 16; ++c) row[c] = l < TB ? tl(t, l, c) : 0.0;
+        double *bc = s1;   // the column's multipliers of rows j + 1 .. 15
 #pragma unroll
         for (int j = 0; j < 16; ++j) {
             const double p = readlane_d(row[j], j);
@@ -97,10 +101,12 @@ __device__ __forceinline__ bool tile_potrf_inv(double *t, int nb, double *__rest
             const double lj = sqrt(p > 0.0 ? p : 1.0), inv = 1.0 / lj;
             const double a = l > j ? row[j] * inv : (l == j ? lj : row[j]);
             row[j] = a;
+            if (j < 15) {
+                if (l > j && l < 16) bc[l] = a;
+                wave_sync();
 #pragma unroll
-            for (int c = j + 1; c < 16; ++c) {
-                const double ac = readlane_d(a, c);
-                if (l >= c && l < TB) row[c] -= a * ac;
+                for (int c = j + 1; c < 16; ++c) row[c] -= a * bc[c];
+                wave_sync();
             }
         }
         if (l < TB) {
@@ -130,10 +136,12 @@ __device__ __forceinline__ bool tile_potrf_inv(double *t, int nb, double *__rest
             const double lj = sqrt(p > 0.0 ? p : 1.0), inv = 1.0 / lj;
             const double a = l > 16 + j ? row[j] * inv : (l == 16 + j ? lj : row[j]);
             row[j] = a;
+            if (j < 15) {
+                if (l > 16 + j && l < TB) bc[l - 16] = a;
+                wave_sync();
 #pragma unroll
-            for (int c = j + 1; c < 16; ++c) {
-                const double ac = readlane_d(a, 16 + c);
-                if (l >= 16 + c && l < TB) row[c] -= a * ac;
+                for (int c = j + 1; c < 16; ++c) row[c] -= a * bc[c];
+                wave_sync();
             }
         }
         if (!ok) {

@@ -52,7 +52,9 @@ constexpr int BLOCK = 256;         // threads per block for residual kernels
 constexpr int MAX_HOST_TARGETS = 20;  // target frames per host frame (Schur Gram size)
 constexpr int PAIR_CHUNK = 512;       // observations per pair-reduction workgroup
 constexpr int LDS_CHOL_MAX_N = 180;   // largest reduced system factored in one workgroup's LDS
-constexpr int TILED_MIN_N = 96;       // one-window systems from this size on use the tiled multi-workgroup path
+constexpr int TILED_MIN_N = 96;
+constexpr int IC_STEP_PTS = 128;      // points per depth workgroup of the fused IC step (1024 threads / 8)
+constexpr int STEP_SEL_STRIDE = 64;   // ints per workgroup in the fused step's frame lists       // one-window systems from this size on use the tiled multi-workgroup path
 constexpr int TCHOL_TILE = 32;        // tile edge of the tiled Cholesky for larger systems
 
 // Independent problems (windows) held by one context: frames, points and pairs
@@ -168,6 +170,13 @@ struct Ctx {
 
     // device buffers (generic pointers; element type per precision)
     double *d_poses = nullptr, *d_poses0 = nullptr;   // [F][12]
+    double *d_poses_alt = nullptr;                    // [F][12] second pose buffer of the fused IC step
+    int batch_k = 0;                                  // index of the iteration being enqueued in its batch
+    // per depth workgroup of the fused IC step (IC_STEP_PTS points each): the
+    // frames its points observe, [count, frames ..., 64-bit mask] at stride
+    // STEP_SEL_STRIDE (empty when a window has more than 60 frames)
+    int *d_step_sel = nullptr;
+    int step_sel_max = 0;                             // most frames of one workgroup
     double *d_K0 = nullptr;                           // [F][4] level-0 intrinsics
     double *d_depth = nullptr, *d_depth0 = nullptr;   // [N]
     int *d_host_frame = nullptr, *d_obs_ptr = nullptr, *d_obs_frame = nullptr, *d_obs_point = nullptr,
@@ -289,7 +298,15 @@ void launch_solve(hipStream_t s, Ctx &c, const double *geo_lin, double *geo_next
                   bool rel_double, double *stat);
 void launch_sum_stats(hipStream_t s, Ctx &c, const void *rec, bool rec_double, double *out3);
 size_t sum_stats_doubles(const Ctx &c);  // size of out3 (the sums and the block partials)
-void launch_conv(hipStream_t s, Ctx &c, double *stat, double conv_px, int nparts, int level);
+// pose_sync (fused IC step, last iteration of a batch): after an odd number of
+// iterations the current poses are copied back from the second pose buffer.
+void launch_conv(hipStream_t s, Ctx &c, double *stat, double conv_px, int nparts, int level, bool pose_sync = false);
+// IC on one window whose step fits the solve's LDS cache: the solve and the
+// depth step of an iteration run as one kernel (launch_ic_step).
+bool ic_fused(const Ctx &c);
+void launch_ic_step(hipStream_t s, Ctx &c, const double *geo_lin, const double *geo_old, double *geo_next,
+                    void *rel_next, bool rel_double);
+int du_nparts(const Ctx &c);   // blocks of the depth step (parts of its convergence maxima)
 // count[level] = 0, optionally flag = 0, then gate = (flag == 0)
 void launch_open(hipStream_t s, Ctx &c, int level, bool clear_flag);
 void launch_ic_inverse(hipStream_t s, Ctx &c);

@@ -8,6 +8,7 @@
 // results are bitwise reproducible run to run (no floating-point atomics).
 #include <hip/hip_ext.h>
 
+#include "pba_depth.hpp"
 #include "pba_device.hpp"
 #include "pba_internal.hpp"
 
@@ -764,15 +765,9 @@ __global__ void k_sum_parts3(int np, const double *__restrict__ part, double *__
     out[threadIdx.x] = s;
 }
 
-constexpr int DU_PTS = 32, DU_SLOTS = 8;
-
-
-// Depth step of every point after the pose step (depth back-substitution,
-// Sec. 3.5 step 4 for IC, the Schur back-substitution for FC) and the block
-// maxima of the point-centre displacement it causes and of the depth step
-// (k_conv finishes the iteration from them). DU_PTS points per block,
-// DU_SLOTS threads per point over its observations. Loads that depend only on
-// the point are issued first; the target intrinsics come per pair (level 0).
+// Depth step of every point after the pose step and the block maxima of the
+// point-centre displacement and of the depth step (k_conv finishes the
+// iteration from them); DU_PTS points per block.
 template <typename T>
 __global__ __launch_bounds__(256) void k_depth_update(
     int N, int ic, const int *__restrict__ obs_ptr, const int *__restrict__ obs_pair,
@@ -781,78 +776,14 @@ __global__ __launch_bounds__(256) void k_depth_update(
     const double *__restrict__ geo_old, const double *__restrict__ geo_new, double *__restrict__ depth,
     const double *__restrict__ depth0, double *__restrict__ part, const int *__restrict__ gate,
     const int *__restrict__ flag) {
-    __shared__ double sp[DU_PTS][DU_SLOTS][2];
-    __shared__ double dnew[DU_PTS], dold[DU_PTS];
-    __shared__ double red[2][4];
-    const int q = threadIdx.x / DU_SLOTS, slot = threadIdx.x % DU_SLOTS;
-    const int n = blockIdx.x * DU_PTS + q;
-    const bool has = n < N;
-    // first step: the point's data and the gate
-    const int o0 = has ? obs_ptr[n] : 0, o1 = has ? obs_ptr[n + 1] : 0;
-    const double hu = has ? (double)host_uv[2 * n] : 0.0, hv = has ? (double)host_uv[2 * n + 1] : 0.0;
-    const double Hn = has ? Hdd[n] : 1.0, d_old = has ? depth[n] : 0.0, d0 = has ? depth0[n] : 1.0;
-    const int gv = __hip_atomic_load(gate, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    const int fv = __hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    if (__builtin_amdgcn_readfirstlane(gv) == 0 || __builtin_amdgcn_readfirstlane(fv) != 0) return;
-    // g_d,n and h_n^T dtheta, slot-parallel over the point's observations
-    double s = 0.0, g = 0.0;
-    for (int o = o0 + slot; o < o1; o += DU_SLOTS) {
-        const T *r = rec + (size_t)o * REC_STRIDE;
-        const double *dr = dth_rel + 6 * obs_pair[o];
-        g += (double)gr[(size_t)o * gs + GR_GD];
-        for (int k = 0; k < 6; ++k) s += (double)r[REC_h + k] * dr[k];
-    }
-    sp[q][slot][0] = g;
-    sp[q][slot][1] = s;
-    __syncthreads();
-    double mstep = 0.0;
-    if (slot == 0 && has) {
-        double t = 0.0;
-        for (int k = 0; k < DU_SLOTS; ++k) t += sp[q][k][0];
-        for (int k = 0; k < DU_SLOTS; ++k) t += sp[q][k][1];
-        const double dd = -t / Hn;
-        const double d_new = ic ? d_old * (d0 - dd) / d0 : d_old + dd;
-        depth[n] = d_new;
-        dold[q] = d_old;
-        dnew[q] = d_new;
-        mstep = fabs(dd);
-    }
-    __syncthreads();
-    double mdisp = 0.0;
-    for (int o = o0 + slot; o < o1; o += DU_SLOTS) {
-        const int p = obs_pair[o];
-        const double *Kp = pairK0 + 8 * p;   // host (fx, fy, cx, cy), target (fx, fy, cx, cy)
-        const double x = (hu - Kp[2]) / Kp[0], y = (hv - Kp[3]) / Kp[1];
-        double qq[2][2];
-        bool ok = true;
-        for (int s2 = 0; s2 < 2; ++s2) {
-            const double *gm = s2 ? geo_new + GEO_STRIDE * p : geo_old + GEO_STRIDE * p;
-            const double d = s2 ? dnew[q] : dold[q];
-            const double vx = gm[0] * x + gm[1] * y + gm[2] + d * gm[9];
-            const double vy = gm[3] * x + gm[4] * y + gm[5] + d * gm[10];
-            const double vz = gm[6] * x + gm[7] * y + gm[8] + d * gm[11];
-            ok = ok && vz > 0.0;
-            const double vzs = vz > 0.0 ? vz : 1.0;
-            qq[s2][0] = Kp[4] * vx / vzs + Kp[6];
-            qq[s2][1] = Kp[5] * vy / vzs + Kp[7];
-        }
-        if (ok) mdisp = fmax(mdisp, hypot(qq[1][0] - qq[0][0], qq[1][1] - qq[0][1]));
-    }
-    mdisp = wave_max(mdisp);
-    mstep = wave_max(mstep);
-    if ((threadIdx.x & 63) == 0) {
-        red[0][threadIdx.x >> 6] = mdisp;
-        red[1][threadIdx.x >> 6] = mstep;
-    }
-    __syncthreads();
-    if (threadIdx.x < 64) {
-        const int l = threadIdx.x;
-        mdisp = row_max16(l < 4 ? red[0][l] : 0.0);
-        mstep = row_max16(l < 4 ? red[1][l] : 0.0);
-        if (l == 0) {
-            part[2 * blockIdx.x] = mdisp;
-            part[2 * blockIdx.x + 1] = mstep;
-        }
+    __shared__ double lds[depth_lds_doubles(256)];
+    double md = 0.0, ms = 0.0;
+    if (!depth_points<T, 256>(N, blockIdx.x * DU_PTS, ic, obs_ptr, obs_pair, host_uv, pairK0, rec, gr, gs, Hdd,
+                              dth_rel, geo_old, geo_new, depth, depth0, gate, flag, lds, md, ms))
+        return;
+    if (threadIdx.x == 0) {
+        part[2 * blockIdx.x] = md;
+        part[2 * blockIdx.x + 1] = ms;
     }
 }
 
@@ -1084,7 +1015,7 @@ void Launch<T>::pair_reduce_y(hipStream_t s, Ctx &c, double *prev_stat, double c
     const int nch = (int)c.st.pchunk_begin.size();
     if (nch == 0) {
         // no pair chunks to carry the previous iteration's end: its own kernel
-        if (prev_stat) launch_conv(s, c, prev_stat, conv_px, c.N > 0 ? (int)nblk(c.N, DU_PTS) : 0, level);
+        if (prev_stat) launch_conv(s, c, prev_stat, conv_px, du_nparts(c), level);
         return;
     }
     const T *gr;
@@ -1093,7 +1024,7 @@ void Launch<T>::pair_reduce_y(hipStream_t s, Ctx &c, double *prev_stat, double c
     k_pair_chunk_y<T><<<nch, PAIR_CHUNK, 0, s>>>(c.d_pchunk_begin, c.d_pchunk_end, c.d_pair_obs_idx,
                                                  c.d_obs_point, c.d_obs_prange, (const T *)c.d_rec, gr, gs, c.d_Hdd,
                                                  c.d_partY, c.d_gate, prev_stat ? c.d_du_part : nullptr,
-                                                 c.N > 0 ? (int)nblk(c.N, DU_PTS) : 0, conv_args(c, prev_stat, conv_px, level));
+                                                 du_nparts(c), conv_args(c, prev_stat, conv_px, level));
     CHECK_LAUNCH();
 }
 
@@ -1111,17 +1042,31 @@ void Launch<T>::depth_update(hipStream_t s, Ctx &c, const double *geo_old, const
                                              c.d_dth_rel, geo_old, geo_new, c.d_depth, c.d_depth0, c.d_du_part,
                                              c.d_gate, c.d_flag);
     CHECK_LAUNCH();
-    if (finish) launch_conv(s, c, stat, conv_px, c.N > 0 ? nb : 0, level);
+    if (finish) launch_conv(s, c, stat, conv_px, du_nparts(c), level);
 }
 
 // End of an iteration without points (single block): the iteration
 // statistics and the convergence gate from nparts block maxima.
-__global__ __launch_bounds__(256) void k_conv(const double *__restrict__ part, int nparts, ConvArgs cv) {
+// With np > 0 (the fused IC step, which alternates two pose buffers: iteration
+// k of a batch reads buffer k mod 2), the poses are then copied back from
+// pose_alt when the batch ran an odd number of iterations; this runs whether or
+// not the gate is open.
+__global__ __launch_bounds__(256) void k_conv(const double *__restrict__ part, int nparts, ConvArgs cv,
+                                              const double *__restrict__ pose_alt, double *__restrict__ pose,
+                                              int np) {
     __shared__ double red[2][16];
-    if (*cv.gate == 0) return;
-    double md, ms;
-    block_max2(part, nparts, md, ms, red);
-    if (threadIdx.x == 0) conv_finish(cv, md, ms);
+    __shared__ int ran;
+    if (*cv.gate != 0) {
+        double md, ms;
+        block_max2(part, nparts, md, ms, red);
+        if (threadIdx.x == 0) conv_finish(cv, md, ms);
+    }
+    if (np == 0) return;
+    __syncthreads();
+    if (threadIdx.x == 0) ran = *cv.count;
+    __syncthreads();
+    if (ran & 1)
+        for (int e = threadIdx.x; e < np; e += blockDim.x) pose[e] = pose_alt[e];
 }
 
 // Start of a batch of iterations: clear the level's iteration count and
@@ -1135,8 +1080,9 @@ __global__ void k_open(int *__restrict__ gate, int *__restrict__ flag, int *__re
     }
 }
 
-void launch_conv(hipStream_t s, Ctx &c, double *stat, double conv_px, int nparts, int level) {
-    k_conv<<<1, 256, 0, s>>>(c.d_du_part, nparts, conv_args(c, stat, conv_px, level));
+void launch_conv(hipStream_t s, Ctx &c, double *stat, double conv_px, int nparts, int level, bool pose_sync) {
+    k_conv<<<1, 256, 0, s>>>(c.d_du_part, nparts, conv_args(c, stat, conv_px, level), c.d_poses_alt, c.d_poses,
+                             pose_sync ? 12 * c.F : 0);
     CHECK_LAUNCH();
 }
 

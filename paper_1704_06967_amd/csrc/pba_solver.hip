@@ -1,6 +1,7 @@
 // FP64 kernels of the reduced pose system: depth damping, the per-host Gram of
 // the depth Schur complement, assembly of S, Cholesky, the IC inverse, and the
 // single-workgroup solve + pose update of every iteration.
+#include "pba_depth.hpp"
 #include "pba_device.hpp"
 #include "pba_internal.hpp"
 #include "pba_tile.hpp"
@@ -489,17 +490,21 @@ enum SolvePath { SOLVE_IC = 0, SOLVE_FC_PACKED = 1, SOLVE_FC_TILED = 2 };
 // and target frame of every pair [2 P], the frames' item pointers [F + 1], the
 // pairs' chunk pointers [P + 1] and the frames' items [2 P] (a window's items
 // are its pairs' host and target entries, so they start at 2 p0).
-__host__ __device__ inline int solve_cache_doubles(int F, int P) {
+// With pair_out (the fused IC step), every pair's next geometry and relative
+// step [P][GEO_STRIDE + 6] sit above the cache, at the very top of LDS.
+__host__ __device__ inline int solve_out_doubles(int P, bool pair_out) { return pair_out ? (GEO_STRIDE + 6) * P : 0; }
+__host__ __device__ inline int solve_cache_doubles(int F, int P, bool pair_out = false) {
     const int nq = (6 * F + 1) & ~1;
     const int ints = 2 * P + (F + 1) + (P + 1) + 2 * P;
-    return 24 * F + GEO_STRIDE * P + nq + 9 * P + (ints + 1) / 2;
+    return 24 * F + GEO_STRIDE * P + nq + 9 * P + (ints + 1) / 2 + solve_out_doubles(P, pair_out);
 }
 
 // Batched copy of the concatenation of NS global segments (segment s starts
 // at src[s] and ends at the cumulative length end[s]) into LDS, K elements per
 // thread per batch: fetch() issues the first batch into registers, store()
-// writes it and copies any further batches. Elements past the end read the
-// valid element *dummy; the first nsub elements are stored less sub.
+// writes it and copies any further batches. Elements past the end are not
+// loaded (a load under an inactive mask moves no data); the first nsub
+// elements are stored less sub.
 template <int NS, int K, typename V>
 struct LdsGather {
     const V *src[NS];
@@ -516,7 +521,8 @@ struct LdsGather {
                 const int beg = s ? end[s - 1] : 0;
                 p = (e >= beg && e < end[s]) ? src[s] + (e - beg) : p;
             }
-            v[u] = *p;
+            v[u] = V(0);
+            if (e < end[NS - 1]) v[u] = *p;
         }
     }
     __device__ __forceinline__ void put(V *dst, int b, V sub, int nsub) {
@@ -564,19 +570,18 @@ constexpr int SV_REG = 21, SV_LDS = 15;
 // dependent global loads left are the chunk partials. A single window's ranges
 // come as arguments (one_F >= 0: frames and pairs from 0), others' are loaded.
 template <typename T, int PATH, bool CACHE>
-__global__ __launch_bounds__(SOLVE_THREADS) void k_solve(
-    WinArgs wa, int one_F, int one_P, int pinned, int stage, const int *__restrict__ frame_pair_ptr,
+__device__ __forceinline__ bool solve_window(
+    double *lds, double *red, bool writer, bool pair_out, WinArgs wa, int one_F, int one_P, int pinned, int stage, const int *__restrict__ frame_pair_ptr,
     const int *__restrict__ frame_pair_item, const int *__restrict__ pair_host, const int *__restrict__ pair_target,
     const int *__restrict__ pair_chunk_ptr, const double *__restrict__ partY, double *__restrict__ pairY,
     const double *__restrict__ geo_lin, const double *__restrict__ S_all, const double *__restrict__ Sfac,
-    const double *__restrict__ Linv, const double *__restrict__ Sinv_all, double *__restrict__ poses,
+    const double *__restrict__ Linv, const double *__restrict__ Sinv_all, double *poses,
     const double *__restrict__ poses0, double *__restrict__ b_all, double *__restrict__ dth_all,
     double *__restrict__ dth_rel, double *__restrict__ geo_next, T *__restrict__ rel_next,
-    double *__restrict__ wstat, int *__restrict__ flag, int *__restrict__ gate) {
+    double *__restrict__ wstat, int *__restrict__ flag, int *__restrict__ gate, double *poses_out,
+    const int *__restrict__ sel = nullptr, int sel_ncw = 0) {
     constexpr bool ic = PATH == SOLVE_IC, tiled = PATH == SOLVE_FC_TILED, packed = PATH == SOLVE_FC_PACKED;
     static_assert(ic || !CACHE, "the LDS cache serves the IC path");
-    __shared__ double lds[LDS_DOUBLES];
-    __shared__ double red[64 + 2 * LDS_MAX_N + 2];
 
     // the gate, the failure flag and the window's ranges
     const int w = blockIdx.x;
@@ -606,13 +611,28 @@ __global__ __launch_bounds__(SOLVE_THREADS) void k_solve(
     double *bx = lds + (packed ? n * (n + 1) / 2 : 0);
     // IC product layout up to IC_SPLIT_N unknowns: thread (g, j) takes column j
     // and rows g + NG u; group partials after bx
-    const int ncw = (n + 63) & ~63;
+    // and rows g + NG u; group partials after bx. With sel (IC cache path), only
+    // the columns of the listed frames: sel = [count, frames ..., mask (2 ints)]
+    // at stride STEP_SEL_STRIDE, column slot k of thread (g, k) the (k % 6)-th
+    // unknown of frame sel[1 + k / 6], sel_ncw slots per group
+    const bool subset = CACHE && sel != nullptr;
+    const int ncw = subset ? sel_ncw : (n + 63) & ~63;
     const int NG = ncw ? SOLVE_THREADS / ncw : 1;
-    const int mg = threadIdx.x / max(ncw, 1), mj = threadIdx.x % max(ncw, 1);
+    const int mg = threadIdx.x / max(ncw, 1), mk = threadIdx.x % max(ncw, 1);
+    int nsel = F, mj = mk;
+    unsigned long long fmask = ~0ull;
+    if (subset) {
+        nsel = sel[0];
+        fmask = (unsigned long long)(unsigned)sel[STEP_SEL_STRIDE - 2] |
+                ((unsigned long long)(unsigned)sel[STEP_SEL_STRIDE - 1] << 32);
+        mj = 6 * sel[1 + min(mk / 6, STEP_SEL_STRIDE - 4)] + mk % 6;   // slots past the list: frame 0, unused
+    }
+    const int ncols = 6 * nsel;   // product columns (n without sel)
     double *const part = bx + nq;
 
     // the cache (IC) and its end; scratch of the steps stays below it
-    double *const ctop = CACHE ? lds + LDS_DOUBLES - solve_cache_doubles(F, P) : lds + LDS_DOUBLES;
+    double *const ctop = CACHE ? lds + LDS_DOUBLES - solve_cache_doubles(F, P, pair_out) : lds + LDS_DOUBLES;
+    double *const c_out = lds + LDS_DOUBLES - solve_out_doubles(P, pair_out);   // [P][GEO_STRIDE], then [P][6]
     double *const c_pose = ctop, *const c_pose0 = c_pose + 12 * F, *const c_geo = c_pose0 + 12 * F;
     double *const c_dth = c_geo + GEO_STRIDE * P, *const c_y = c_dth + nq;
     int *const c_host = reinterpret_cast<int *>(c_y + 9 * P), *const c_target = c_host + P;
@@ -634,32 +654,30 @@ __global__ __launch_bounds__(SOLVE_THREADS) void k_solve(
                                 gate};
         gd.fetch(0);
         gi.fetch(0);
-        const bool col = mg < NG && mj < n;
+        const bool col = mg < NG && mk < ncols;
         double sl[SV_LDS];
 #pragma unroll
         for (int u = 0; u < SV_LDS; ++u) sl[u] = 0.0;
 #pragma unroll
         for (int u = 0; u < SV_REG; ++u) sv[u] = 0.0;
         if (pre) {
+            // entries outside the rows, columns or LDS rows are not loaded (the
+            // registers were zeroed first, so no load waits on another)
 #pragma unroll
             for (int u = 0; u < SV_LDS; ++u) {
                 const int i = mg + NG * (SV_REG + u);
-                const bool ok = col && u < ul && i < n;
-                const double v = *(ok ? Sinv + (size_t)i * n + mj : wstat + 4 * w);
-                sl[u] = ok ? v : 0.0;
+                if (col && u < ul && i < n) sl[u] = Sinv[(size_t)i * n + mj];
             }
 #pragma unroll
             for (int u = 0; u < SV_REG; ++u) {
                 const int i = mg + NG * u;
-                const bool ok = col && i < n;
-                const double v = *(ok ? Sinv + (size_t)i * n + mj : wstat + 4 * w);
-                sv[u] = ok ? v : 0.0;
+                if (col && i < n) sv[u] = Sinv[(size_t)i * n + mj];
             }
         }
-        if (gv == 0) return;
+        if (gv == 0) return false;
         if (fv) {
-            if (threadIdx.x == 0) *gate = 0;
-            return;
+            if (writer && threadIdx.x == 0) *gate = 0;
+            return false;
         }
         gd.store(c_pose, 0.0, 0);
         gi.store(c_host, f0, 2 * P);
@@ -670,11 +688,11 @@ __global__ __launch_bounds__(SOLVE_THREADS) void k_solve(
         for (int u = 0; u < SV_REG; ++u) pin_reg(sv[u]);
         __syncthreads();
     } else {
-        if (gv == 0) return;
+        if (gv == 0) return false;
         if (fv) {
             // a factorization of this iteration failed: stop the batch
             if (threadIdx.x == 0) *gate = 0;
-            return;
+            return false;
         }
     }
     auto fptr = [&](int f) { return CACHE ? c_fptr[f - f0] : frame_pair_ptr[f]; };
@@ -763,7 +781,7 @@ __global__ __launch_bounds__(SOLVE_THREADS) void k_solve(
     };
     if (stage == 1) {
         if (CACHE) store_b();
-        return;
+        return false;
     }
     if (stage == 2) {
         // dtheta is in global memory (and in the cache)
@@ -777,7 +795,7 @@ __global__ __launch_bounds__(SOLVE_THREADS) void k_solve(
         if (n <= IC_SPLIT_N) {
             const int g = mg, j = mj;
             double s0 = 0.0, s1 = 0.0, s2 = 0.0;
-            if (g < NG && j < n) {
+            if (g < NG && mk < ncols) {
                 int u0 = 0;
                 if (pre) {
 #pragma unroll
@@ -813,15 +831,16 @@ __global__ __launch_bounds__(SOLVE_THREADS) void k_solve(
                     }
                 }
             }
-            if (g < NG) part[g * ncw + j] = (s0 + s1) + s2;
+            if (g < NG) part[g * ncw + mk] = (s0 + s1) + s2;
             __syncthreads();
-            if (threadIdx.x < n) {
+            if (threadIdx.x < ncols) {
+                // thread (0, k): its column j
                 double s = 0.0;
                 for (int q = 0; q < NG; ++q) s += part[q * ncw + threadIdx.x];
                 if (CACHE)
-                    c_dth[threadIdx.x] = -s;
+                    c_dth[j] = -s;
                 else
-                    dth_out[threadIdx.x] = -s;
+                    dth_out[j] = -s;
             }
         } else {
             for (int i = wv; i < n; i += nw) {
@@ -853,7 +872,7 @@ __global__ __launch_bounds__(SOLVE_THREADS) void k_solve(
                     *flag = 1;
                     *gate = 0;
                 }
-                return;
+                return false;
             }
         }
         if (wv == 0) {
@@ -887,6 +906,7 @@ __global__ __launch_bounds__(SOLVE_THREADS) void k_solve(
     if (lane == 0) red[wv] = mx;
     // pose update
     for (int lf = threadIdx.x; lf < F; lf += blockDim.x) {
+        if (!((fmask >> (lf & 63)) & 1ull)) continue;   // (sel) a frame whose step was not formed
         const double *x = dth + 6 * lf;
         const double *P = CACHE ? c_pose + 12 * lf : poses + 12 * (f0 + lf);
         double dR[9], Rn[9], tn[3];
@@ -910,7 +930,7 @@ __global__ __launch_bounds__(SOLVE_THREADS) void k_solve(
     __syncthreads();
     if (wv == 0) {
         const double m2 = row_max16(lane < nw ? red[lane] : 0.0);
-        if (lane == 0) wstat[4 * w + 3] = m2;
+        if (writer && lane == 0) wstat[4 * w + 3] = m2;
     }
     // next relative poses and relative steps per pair (frames window-local)
     const double *pose_w = CACHE ? c_pose : poses + 12 * f0;
@@ -921,19 +941,29 @@ __global__ __launch_bounds__(SOLVE_THREADS) void k_solve(
         const double *Pf = pose_w + 12 * t;
         double R[9];
         mat3_mul_bt(Pf, Ph, R);
-        double *g = geo_next + GEO_STRIDE * p;
-        T *rl = rel_next + REL_STRIDE * p;
-        for (int i = 0; i < 9; ++i) {
-            g[i] = R[i];
-            rl[i] = (T)R[i];
+        double tr[3];
+#pragma unroll
+        for (int i = 0; i < 3; ++i) tr[i] = Pf[9 + i] - (R[3 * i] * Ph[9] + R[3 * i + 1] * Ph[10] + R[3 * i + 2] * Ph[11]);
+        // geometry [R, t, t_host, 0] of the pair at the new poses
+        auto put_geo = [&](double *g) {
+#pragma unroll
+            for (int i = 0; i < 9; ++i) g[i] = R[i];
+#pragma unroll
+            for (int i = 0; i < 3; ++i) {
+                g[9 + i] = tr[i];
+                g[12 + i] = Ph[9 + i];
+            }
+            g[15] = 0.0;
+        };
+        if (writer) {
+            put_geo(geo_next + GEO_STRIDE * p);
+            T *rl = rel_next + REL_STRIDE * p;
+#pragma unroll
+            for (int i = 0; i < 9; ++i) rl[i] = (T)R[i];
+#pragma unroll
+            for (int i = 0; i < 3; ++i) rl[9 + i] = (T)tr[i];
         }
-        for (int i = 0; i < 3; ++i) {
-            const double ti = Pf[9 + i] - (R[3 * i] * Ph[9] + R[3 * i + 1] * Ph[10] + R[3 * i + 2] * Ph[11]);
-            g[9 + i] = ti;
-            rl[9 + i] = (T)ti;
-            g[12 + i] = Ph[9 + i];
-        }
-        g[15] = 0.0;
+        if (pair_out) put_geo(c_out + GEO_STRIDE * (p - p0));
         double xf[6], xh[6], af[6], bh[6];
         for (int a = 0; a < 6; ++a) {
             xf[a] = dth[6 * t + a];
@@ -941,14 +971,87 @@ __global__ __launch_bounds__(SOLVE_THREADS) void k_solve(
         }
         apply_A(geo_of(p), xf, af);
         apply_B(geo_of(p), xh, bh);
-        for (int r = 0; r < 6; ++r) dth_rel[6 * p + r] = af[r] + bh[r];
+        if (writer)
+            for (int r = 0; r < 6; ++r) dth_rel[6 * p + r] = af[r] + bh[r];
+        if (pair_out)
+            for (int r = 0; r < 6; ++r) c_out[GEO_STRIDE * P + 6 * (p - p0) + r] = af[r] + bh[r];
     }
     if constexpr (CACHE) {
-        if (stage == 0) {
-            store_b();
-            for (int e = threadIdx.x; e < n; e += blockDim.x) dth_out[e] = c_dth[e];
+        if (writer) {
+            if (stage == 0) {
+                store_b();
+                for (int e = threadIdx.x; e < n; e += blockDim.x) dth_out[e] = c_dth[e];
+            }
+            for (int e = threadIdx.x; e < 12 * F; e += blockDim.x) poses_out[12 * f0 + e] = c_pose[e];
         }
-        for (int e = threadIdx.x; e < 12 * F; e += blockDim.x) poses[12 * f0 + e] = c_pose[e];
+    }
+    return true;
+}
+
+template <typename T, int PATH, bool CACHE>
+__global__ __launch_bounds__(SOLVE_THREADS) void k_solve(
+    WinArgs wa, int one_F, int one_P, int pinned, int stage, const int *__restrict__ frame_pair_ptr,
+    const int *__restrict__ frame_pair_item, const int *__restrict__ pair_host, const int *__restrict__ pair_target,
+    const int *__restrict__ pair_chunk_ptr, const double *__restrict__ partY, double *__restrict__ pairY,
+    const double *__restrict__ geo_lin, const double *__restrict__ S_all, const double *__restrict__ Sfac,
+    const double *__restrict__ Linv, const double *__restrict__ Sinv_all, double *__restrict__ poses,
+    const double *__restrict__ poses0, double *__restrict__ b_all, double *__restrict__ dth_all,
+    double *__restrict__ dth_rel, double *__restrict__ geo_next, T *__restrict__ rel_next,
+    double *__restrict__ wstat, int *__restrict__ flag, int *__restrict__ gate) {
+    __shared__ double lds[LDS_DOUBLES];
+    __shared__ double red[64 + 2 * LDS_MAX_N + 2];
+    solve_window<T, PATH, CACHE>(lds, red, true, false, wa, one_F, one_P, pinned, stage, frame_pair_ptr,
+                                 frame_pair_item, pair_host, pair_target, pair_chunk_ptr, partY, pairY, geo_lin, S_all,
+                                 Sfac, Linv, Sinv_all, poses, poses0, b_all, dth_all, dth_rel, geo_next, rel_next,
+                                 wstat, flag, gate, poses);
+}
+
+static_assert(IC_STEP_PTS == SOLVE_THREADS / DU_SLOTS, "one depth workgroup of the fused IC step: 8 lanes per point");
+
+// One IC iteration's solve and depth step in one launch (one window on the
+// cache path, so that no kernel boundary separates them): every workgroup
+// forms the step itself (the pair sums and S^{-1} b repeat cheaply from L2).
+// Workgroup 0 stores the solve's results (the updated poses into poses_out, a
+// buffer no workgroup of the launch reads) and has no points; workgroup
+// b > 0 then updates the depths of points [(b - 1) IC_STEP_PTS, b IC_STEP_PTS)
+// from the relative steps and poses of the pairs it holds in LDS, and part[b - 1]
+// receives its maxima of the displacement and of the depth step.
+template <typename T>
+__global__ __launch_bounds__(SOLVE_THREADS) void k_ic_step(
+    WinArgs wa, int one_F, int one_P, int pinned, const int *__restrict__ frame_pair_ptr,
+    const int *__restrict__ frame_pair_item, const int *__restrict__ pair_host, const int *__restrict__ pair_target,
+    const int *__restrict__ pair_chunk_ptr, const double *__restrict__ partY, double *__restrict__ pairY,
+    const double *__restrict__ geo_lin, const double *__restrict__ Sinv_all, const double *__restrict__ poses_in,
+    double *__restrict__ poses_out, const double *__restrict__ poses0, double *__restrict__ b_all,
+    double *__restrict__ dth_all, double *__restrict__ dth_rel, double *__restrict__ geo_next,
+    T *__restrict__ rel_next, double *__restrict__ wstat, int *__restrict__ flag, int *__restrict__ gate, int N,
+    const int *__restrict__ obs_ptr, const int *__restrict__ obs_pair, const float *__restrict__ host_uv,
+    const double *__restrict__ pairK0, const T *__restrict__ rec, const T *__restrict__ gr, int gs,
+    const double *__restrict__ Hdd, const double *__restrict__ geo_old, double *__restrict__ depth,
+    const double *__restrict__ depth0, double *__restrict__ part, const int *__restrict__ step_sel, int sel_ncw) {
+    __shared__ double lds[LDS_DOUBLES];
+    __shared__ double red[64 + 2 * LDS_MAX_N + 2];
+    const bool writer = blockIdx.x == 0;
+    // a depth workgroup forms the step of the frames its points observe only
+    const int *sel = (writer || sel_ncw == 0) ? nullptr : step_sel + (size_t)(blockIdx.x - 1) * STEP_SEL_STRIDE;
+    if (!solve_window<T, SOLVE_IC, true>(lds, red, writer, !writer, wa, one_F, one_P, pinned, 0,
+                                         frame_pair_ptr, frame_pair_item, pair_host, pair_target, pair_chunk_ptr,
+                                         partY, pairY, geo_lin, nullptr, nullptr, nullptr, Sinv_all,
+                                         const_cast<double *>(poses_in), poses0, b_all, dth_all, dth_rel, geo_next,
+                                         rel_next, wstat, flag, gate, poses_out, sel, sel_ncw))
+        return;
+    if (writer) return;
+    __syncthreads();
+    // the step's scratch is free now; the pairs' results stay at the top of LDS
+    const int P = one_P, b = blockIdx.x - 1;
+    const double *c_out = lds + LDS_DOUBLES - solve_out_doubles(P, true);
+    double md = 0.0, ms = 0.0;
+    depth_points<T, SOLVE_THREADS>(N, b * IC_STEP_PTS, 1, obs_ptr, obs_pair, host_uv, pairK0, rec, gr, gs, Hdd,
+                                   c_out + GEO_STRIDE * P, geo_old, c_out, depth, depth0, nullptr, nullptr, lds, md,
+                                   ms);
+    if (threadIdx.x == 0) {
+        part[2 * b] = md;
+        part[2 * b + 1] = ms;
     }
 }
 
@@ -1018,7 +1121,7 @@ void launch_ic_factor(hipStream_t s, Ctx &c) {
 
 // Whether every window's IC cache fits in LDS beside the step's scratch and
 // the windows' items start at twice their first pair.
-static bool solve_cache_fits(const Ctx &c) {
+static bool solve_cache_fits(const Ctx &c, bool pair_out = false) {
     const std::vector<int> &fp = c.st.frame_pair_ptr;
     if (c.win_frame_off.size() != (size_t)c.nwin + 1 || c.win_pair_off.size() != (size_t)c.nwin + 1) return false;
     for (int w = 0; w < c.nwin; ++w) {
@@ -1026,17 +1129,65 @@ static bool solve_cache_fits(const Ctx &c) {
         const int p0 = c.win_pair_off[w], p1 = c.win_pair_off[w + 1];
         if ((size_t)f1 >= fp.size() || fp[f0] != 2 * p0 || fp[f1] != 2 * p1) return false;
         const int nq = (6 * (f1 - f0) + 1) & ~1;
-        if (LDS_DOUBLES - solve_cache_doubles(f1 - f0, p1 - p0) < nq + std::max(SOLVE_THREADS, 6 * 64)) return false;
+        if (LDS_DOUBLES - solve_cache_doubles(f1 - f0, p1 - p0, pair_out) < nq + std::max(SOLVE_THREADS, 6 * 64))
+            return false;
     }
     return true;
 }
 
+// One window starting at frame, pair and S offset 0 (its ranges go as arguments).
+static bool one_window(const Ctx &c) {
+    return c.nwin == 1 && c.win_frame_off.size() == 2 && c.win_pair_off.size() == 2 && c.win_S_off.size() >= 1 &&
+           c.win_frame_off[0] == 0 && c.win_pair_off[0] == 0 && c.win_S_off[0] == 0;
+}
+
+// Column slots per group of a depth workgroup's product (0: every workgroup
+// forms the whole step): the listed frames' unknowns rounded up to 32, when
+// every thread's rows then fit its prefetch registers.
+static int step_sel_ncw(const Ctx &c) {
+    if (!c.d_step_sel || c.step_sel_max <= 0 || 6 * c.step_sel_max >= 6 * c.F) return 0;
+    const int ncw = (6 * c.step_sel_max + 31) & ~31;
+    const int ng = SOLVE_THREADS / ncw;
+    return (6 * c.F + ng - 1) / ng <= SV_REG ? ncw : 0;
+}
+
+bool ic_fused(const Ctx &c) {
+    return c.cfg.mode == PBA_IC_PROXY && one_window(c) && 6 * c.F <= IC_SPLIT_N && c.N > 0 &&
+           solve_cache_fits(c, true);
+}
+
+int du_nparts(const Ctx &c) {
+    if (c.N <= 0) return 0;
+    return (int)nb(c.N, ic_fused(c) ? IC_STEP_PTS : DU_PTS);
+}
+
+template <typename T>
+static void ic_step_kernel(hipStream_t s, Ctx &c, const double *geo_lin, const double *geo_old, double *geo_next,
+                           T *rel_next) {
+    const T *rec = (const T *)c.d_rec, *gr = (const T *)c.d_icr;
+    // iteration k of a batch reads pose buffer k mod 2 and writes the other
+    // (the convergence kernel at the batch's end copies back after odd counts)
+    const bool odd = (c.batch_k & 1) != 0;
+    double *p_in = odd ? c.d_poses_alt : c.d_poses, *p_out = odd ? c.d_poses : c.d_poses_alt;
+    k_ic_step<T><<<1 + nb(c.N, IC_STEP_PTS), SOLVE_THREADS, 0, s>>>(
+        c.win(), c.win_frame_off[1], c.win_pair_off[1], c.cfg.pinned_frame, c.d_frame_pair_ptr, c.d_frame_pair_item,
+        c.d_pair_host, c.d_pair_target, c.d_pair_chunk_ptr, c.d_partY, c.d_pairY, geo_lin, c.d_Sinv, p_in, p_out,
+        c.d_poses0, c.d_b, c.d_dtheta, c.d_dth_rel, geo_next, rel_next, c.d_wstat, c.d_flag, c.d_gate, c.N,
+        c.d_obs_ptr, c.d_obs_pair, c.d_host_uv, c.d_pairK0, rec, gr, IC_REC, c.d_Hdd, geo_old, c.d_depth,
+        c.d_depth0, c.d_du_part, c.d_step_sel, step_sel_ncw(c));
+}
+
+void launch_ic_step(hipStream_t s, Ctx &c, const double *geo_lin, const double *geo_old, double *geo_next,
+                    void *rel_next, bool rel_double) {
+    if (rel_double)
+        ic_step_kernel<double>(s, c, geo_lin, geo_old, geo_next, (double *)rel_next);
+    else
+        ic_step_kernel<float>(s, c, geo_lin, geo_old, geo_next, (float *)rel_next);
+}
+
 template <typename T, int PATH, bool CACHE>
 static void solve_kernel(hipStream_t s, Ctx &c, int stage, const double *geo_lin, double *geo_next, T *rel_next) {
-    // one window starting at frame, pair and S offset 0: its ranges as arguments
-    const bool one = c.nwin == 1 && c.win_frame_off.size() == 2 && c.win_pair_off.size() == 2 &&
-                     c.win_S_off.size() >= 1 && c.win_frame_off[0] == 0 && c.win_pair_off[0] == 0 &&
-                     c.win_S_off[0] == 0;
+    const bool one = one_window(c);
     k_solve<T, PATH, CACHE><<<c.nwin, SOLVE_THREADS, 0, s>>>(
         c.win(), one ? c.win_frame_off[1] : -1, one ? c.win_pair_off[1] : -1, c.cfg.pinned_frame, stage, c.d_frame_pair_ptr, c.d_frame_pair_item, c.d_pair_host, c.d_pair_target,
         c.d_pair_chunk_ptr, c.d_partY, c.d_pairY, geo_lin, c.d_S, c.d_Sfac, c.d_Linv, c.d_Sinv, c.d_poses,
