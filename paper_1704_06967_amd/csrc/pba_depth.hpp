@@ -14,22 +14,53 @@ constexpr int DU_PTS = 256 / DU_SLOTS;   // points per block of the depth-update
 // LDS doubles that depth_points<T, NT> takes.
 constexpr int depth_lds_doubles(int nt) { return (nt / DU_SLOTS) * (2 * DU_SLOTS + 2) + 2 * (nt / 64); }
 
+// The data of point n0 + threadIdx.x / DU_SLOTS that its depth step reads first.
+struct DepthPoint {
+    int o0, o1;
+    double hu, hv, Hn, d_old, d0;
+};
+
+// Loads that data (neutral values past N). EARLY: as relaxed atomic loads,
+// which the compiler keeps where they are, so that a caller can issue them
+// long before the depth step (the wait comes at their first use).
+template <bool EARLY>
+__device__ __forceinline__ DepthPoint depth_point(int N, int n0, const int *__restrict__ obs_ptr,
+                                                  const float *__restrict__ host_uv, const double *__restrict__ Hdd,
+                                                  const double *__restrict__ depth, const double *__restrict__ depth0) {
+    const int n = n0 + (int)threadIdx.x / DU_SLOTS;
+    auto ld = [](const auto *p) {
+        if constexpr (EARLY)
+            return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        else
+            return *p;
+    };
+    DepthPoint pt{0, 0, 0.0, 0.0, 1.0, 0.0, 1.0};
+    if (n < N) {
+        pt.o0 = ld(obs_ptr + n);
+        pt.o1 = ld(obs_ptr + n + 1);
+        pt.hu = (double)ld(host_uv + 2 * n);
+        pt.hv = (double)ld(host_uv + 2 * n + 1);
+        pt.Hn = ld(Hdd + n);
+        pt.d_old = ld(depth + n);
+        pt.d0 = ld(depth0 + n);
+    }
+    return pt;
+}
+
 // Depth step of the NT / DU_SLOTS points from n0 after the pose step (depth
 // back-substitution, Sec. 3.5 step 4 for IC, the Schur back-substitution for
 // FC): dd = -(g_d + h^T dtheta_rel) / H_dd per point; then the largest
 // point-centre displacement (old pose and depth against new, level-0 camera)
-// and depth step of the block, valid in thread 0. Loads that depend only on
-// the point are issued first; with gate / flag given, the gate is read in the
-// same batch and false comes back when it is closed (nothing written).
-// dth_rel [pair][6] and geo_new [pair][GEO_STRIDE] may live in LDS.
+// and depth step of the block, valid in thread 0. pt: the thread's point data
+// (depth_point); with gate / flag given, the gate is read right after it and
+// false comes back when it is closed (nothing written). dth_rel [pair][6] and
+// geo_new [pair][GEO_STRIDE] may live in LDS.
 template <typename T, int NT>
 __device__ __forceinline__ bool depth_points(
-    int N, int n0, int ic, const int *__restrict__ obs_ptr, const int *__restrict__ obs_pair,
-    const float *__restrict__ host_uv, const double *__restrict__ pairK0, const T *__restrict__ rec,
-    const T *__restrict__ gr, int gs, const double *__restrict__ Hdd, const double *dth_rel,
-    const double *__restrict__ geo_old, const double *geo_new, double *__restrict__ depth,
-    const double *__restrict__ depth0, const int *gate, const int *flag, double *lds, double &mdisp_out,
-    double &mstep_out) {
+    int N, int n0, int ic, const DepthPoint &pt, const int *__restrict__ obs_pair,
+    const double *__restrict__ pairK0, const T *__restrict__ rec, const T *__restrict__ gr, int gs,
+    const double *dth_rel, const double *__restrict__ geo_old, const double *geo_new, double *__restrict__ depth,
+    const int *gate, const int *flag, double *lds, double &mdisp_out, double &mstep_out) {
     constexpr int NPTS = NT / DU_SLOTS, NW = NT / 64;
     static_assert(NW <= 16, "the block maxima are taken over one row of 16 lanes");
     double(*sp)[DU_SLOTS][2] = reinterpret_cast<double(*)[DU_SLOTS][2]>(lds);
@@ -37,10 +68,8 @@ __device__ __forceinline__ bool depth_points(
     const int q = threadIdx.x / DU_SLOTS, slot = threadIdx.x % DU_SLOTS;
     const int n = n0 + q;
     const bool has = n < N;
-    // first step: the point's data (and the gate)
-    const int o0 = has ? obs_ptr[n] : 0, o1 = has ? obs_ptr[n + 1] : 0;
-    const double hu = has ? (double)host_uv[2 * n] : 0.0, hv = has ? (double)host_uv[2 * n + 1] : 0.0;
-    const double Hn = has ? Hdd[n] : 1.0, d_old = has ? depth[n] : 0.0, d0 = has ? depth0[n] : 1.0;
+    const int o0 = pt.o0, o1 = pt.o1;
+    const double hu = pt.hu, hv = pt.hv, Hn = pt.Hn, d_old = pt.d_old, d0 = pt.d0;
     if (gate) {
         const int gv = __hip_atomic_load(gate, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         const int fv = __hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);

@@ -778,8 +778,10 @@ __global__ __launch_bounds__(256) void k_depth_update(
     const int *__restrict__ flag) {
     __shared__ double lds[depth_lds_doubles(256)];
     double md = 0.0, ms = 0.0;
-    if (!depth_points<T, 256>(N, blockIdx.x * DU_PTS, ic, obs_ptr, obs_pair, host_uv, pairK0, rec, gr, gs, Hdd,
-                              dth_rel, geo_old, geo_new, depth, depth0, gate, flag, lds, md, ms))
+    const int n0 = blockIdx.x * DU_PTS;
+    const DepthPoint pt = depth_point<false>(N, n0, obs_ptr, host_uv, Hdd, depth, depth0);
+    if (!depth_points<T, 256>(N, n0, ic, pt, obs_pair, pairK0, rec, gr, gs, dth_rel, geo_old, geo_new, depth, gate,
+                              flag, lds, md, ms))
         return;
     if (threadIdx.x == 0) {
         part[2 * blockIdx.x] = md;

@@ -579,7 +579,7 @@ __device__ __forceinline__ bool solve_window(
     const double *__restrict__ poses0, double *__restrict__ b_all, double *__restrict__ dth_all,
     double *__restrict__ dth_rel, double *__restrict__ geo_next, T *__restrict__ rel_next,
     double *__restrict__ wstat, int *__restrict__ flag, int *__restrict__ gate, double *poses_out,
-    const int *__restrict__ sel = nullptr, int sel_ncw = 0) {
+    const int *__restrict__ sel = nullptr, int sel_ncw = 0, int one_nch = -1) {
     constexpr bool ic = PATH == SOLVE_IC, tiled = PATH == SOLVE_FC_TILED, packed = PATH == SOLVE_FC_PACKED;
     static_assert(ic || !CACHE, "the LDS cache serves the IC path");
 
@@ -642,7 +642,10 @@ __device__ __forceinline__ bool solve_window(
     // right-hand side's item maps then stay below them); ul is a multiple of 3
     const bool pre = CACHE && n <= IC_SPLIT_N;
     double *const c_sinv = part + SOLVE_THREADS;
-    const int ul = pre ? min(SV_LDS, (int)((ctop - c_sinv) / SOLVE_THREADS)) / 3 * 3 : 0;
+    // (with sel every row fits the registers: the LDS rows then hold the staged
+    // chunk partials instead)
+    const int ul = (pre && !subset) ? min(SV_LDS, (int)((ctop - c_sinv) / SOLVE_THREADS)) / 3 * 3 : 0;
+    const double *yl = nullptr;   // staged chunk partials
     double sv[SV_REG];
     if constexpr (CACHE) {
         LdsGather<4, 2, double> gd{{poses + 12 * f0, poses0 + 12 * f0, geo_lin + GEO_STRIDE * p0, dth_out},
@@ -654,6 +657,11 @@ __device__ __forceinline__ bool solve_window(
                                 gate};
         gd.fetch(0);
         gi.fetch(0);
+        // (sel, one window with one_nch chunks) the chunk partials of the pair
+        // sums too, into the LDS rows that a column subset leaves unused
+        const bool stage_y = subset && one_nch >= 0 && 9 * one_nch <= (int)(ctop - c_sinv);
+        LdsGather<1, 3, double> gy{{partY}, {stage_y ? 9 * one_nch : 0}, wstat + 4 * w};
+        if (stage_y) gy.fetch(0);
         const bool col = mg < NG && mk < ncols;
         double sl[SV_LDS];
 #pragma unroll
@@ -681,6 +689,10 @@ __device__ __forceinline__ bool solve_window(
         }
         gd.store(c_pose, 0.0, 0);
         gi.store(c_host, f0, 2 * P);
+        if (stage_y) {
+            gy.store(c_sinv, 0.0, 0);
+            yl = c_sinv;
+        }
 #pragma unroll
         for (int u = 0; u < SV_LDS; ++u)
             if (u < ul) c_sinv[u * SOLVE_THREADS + threadIdx.x] = sl[u];
@@ -713,8 +725,9 @@ __device__ __forceinline__ bool solve_window(
             const int c0 = CACHE ? c_cptr[pl] : pair_chunk_ptr[p0 + pl];
             const int c1 = CACHE ? c_cptr[pl + 1] : pair_chunk_ptr[p0 + pl + 1];
             double s = 0.0;
+            const double *py = yl ? yl : partY;
 #pragma unroll 8
-            for (int c = c0; c < c1; ++c) s += partY[9 * c + k];
+            for (int c = c0; c < c1; ++c) s += py[9 * c + k];
             if (CACHE)
                 c_y[9 * pl + k] = s;
             else
@@ -1028,27 +1041,31 @@ __global__ __launch_bounds__(SOLVE_THREADS) void k_ic_step(
     const int *__restrict__ obs_ptr, const int *__restrict__ obs_pair, const float *__restrict__ host_uv,
     const double *__restrict__ pairK0, const T *__restrict__ rec, const T *__restrict__ gr, int gs,
     const double *__restrict__ Hdd, const double *__restrict__ geo_old, double *__restrict__ depth,
-    const double *__restrict__ depth0, double *__restrict__ part, const int *__restrict__ step_sel, int sel_ncw) {
+    const double *__restrict__ depth0, double *__restrict__ part, const int *__restrict__ step_sel, int sel_ncw,
+    int nch) {
     __shared__ double lds[LDS_DOUBLES];
     __shared__ double red[64 + 2 * LDS_MAX_N + 2];
     const bool writer = blockIdx.x == 0;
+    // a depth workgroup's point data, issued before the step (used after it)
+    const int b = blockIdx.x - 1;
+    DepthPoint pt{0, 0, 0.0, 0.0, 1.0, 0.0, 1.0};
+    if (!writer) pt = depth_point<true>(N, b * IC_STEP_PTS, obs_ptr, host_uv, Hdd, depth, depth0);
     // a depth workgroup forms the step of the frames its points observe only
     const int *sel = (writer || sel_ncw == 0) ? nullptr : step_sel + (size_t)(blockIdx.x - 1) * STEP_SEL_STRIDE;
     if (!solve_window<T, SOLVE_IC, true>(lds, red, writer, !writer, wa, one_F, one_P, pinned, 0,
                                          frame_pair_ptr, frame_pair_item, pair_host, pair_target, pair_chunk_ptr,
                                          partY, pairY, geo_lin, nullptr, nullptr, nullptr, Sinv_all,
                                          const_cast<double *>(poses_in), poses0, b_all, dth_all, dth_rel, geo_next,
-                                         rel_next, wstat, flag, gate, poses_out, sel, sel_ncw))
+                                         rel_next, wstat, flag, gate, poses_out, sel, sel_ncw, nch))
         return;
     if (writer) return;
     __syncthreads();
     // the step's scratch is free now; the pairs' results stay at the top of LDS
-    const int P = one_P, b = blockIdx.x - 1;
+    const int P = one_P;
     const double *c_out = lds + LDS_DOUBLES - solve_out_doubles(P, true);
     double md = 0.0, ms = 0.0;
-    depth_points<T, SOLVE_THREADS>(N, b * IC_STEP_PTS, 1, obs_ptr, obs_pair, host_uv, pairK0, rec, gr, gs, Hdd,
-                                   c_out + GEO_STRIDE * P, geo_old, c_out, depth, depth0, nullptr, nullptr, lds, md,
-                                   ms);
+    depth_points<T, SOLVE_THREADS>(N, b * IC_STEP_PTS, 1, pt, obs_pair, pairK0, rec, gr, gs, c_out + GEO_STRIDE * P,
+                                   geo_old, c_out, depth, nullptr, nullptr, lds, md, ms);
     if (threadIdx.x == 0) {
         part[2 * b] = md;
         part[2 * b + 1] = ms;
@@ -1174,7 +1191,7 @@ static void ic_step_kernel(hipStream_t s, Ctx &c, const double *geo_lin, const d
         c.d_pair_host, c.d_pair_target, c.d_pair_chunk_ptr, c.d_partY, c.d_pairY, geo_lin, c.d_Sinv, p_in, p_out,
         c.d_poses0, c.d_b, c.d_dtheta, c.d_dth_rel, geo_next, rel_next, c.d_wstat, c.d_flag, c.d_gate, c.N,
         c.d_obs_ptr, c.d_obs_pair, c.d_host_uv, c.d_pairK0, rec, gr, IC_REC, c.d_Hdd, geo_old, c.d_depth,
-        c.d_depth0, c.d_du_part, c.d_step_sel, step_sel_ncw(c));
+        c.d_depth0, c.d_du_part, c.d_step_sel, step_sel_ncw(c), (int)c.st.pchunk_begin.size());
 }
 
 void launch_ic_step(hipStream_t s, Ctx &c, const double *geo_lin, const double *geo_old, double *geo_next,
