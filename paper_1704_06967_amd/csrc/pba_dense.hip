@@ -15,12 +15,37 @@ constexpr int TP = TB + 1;       // LDS row pitch (doubles)
 __device__ __forceinline__ double &tl(double *t, int r, int c) { return t[r * TP + c]; }
 __device__ __forceinline__ double tl(const double *t, int r, int c) { return t[r * TP + c]; }
 
-// Tile (I, J) of the row-major n x n matrix into LDS; entries outside the matrix are 0.
-__device__ __forceinline__ void load_tile(const double *__restrict__ A, int n, int I, int J, double *t) {
-    for (int e = threadIdx.x; e < TB * TB; e += blockDim.x) {
-        const int r = e / TB, c = e % TB, gr = TB * I + r, gc = TB * J + c;
-        tl(t, r, c) = (gr < n && gc < n) ? A[(size_t)gr * n + gc] : 0.0;
+// A thread's share of a tile for the 256-thread tile kernels: tile_fetch loads
+// it into registers, tile_put stores it into an LDS tile, so that the loads of
+// all the tiles a kernel needs are in flight together (entries outside the
+// matrix are 0 and are not loaded).
+constexpr int TILE_THREADS = 256, TILE_PER = TB * TB / TILE_THREADS;
+struct TileRegs {
+    double v[TILE_PER];
+};
+
+__device__ __forceinline__ void tile_fetch(const double *__restrict__ A, int n, int I, int J, TileRegs &r) {
+#pragma unroll
+    for (int u = 0; u < TILE_PER; ++u) {
+        const int e = threadIdx.x + TILE_THREADS * u, gr = TB * I + e / TB, gc = TB * J + e % TB;
+        r.v[u] = 0.0;
+        if (gr < n && gc < n) r.v[u] = A[(size_t)gr * n + gc];
     }
+}
+
+__device__ __forceinline__ void tile_put(double *t, const TileRegs &r) {
+#pragma unroll
+    for (int u = 0; u < TILE_PER; ++u) {
+        const int e = threadIdx.x + TILE_THREADS * u;
+        tl(t, e / TB, e % TB) = r.v[u];
+    }
+}
+
+// Tile (I, J) of the row-major n x n matrix into LDS (256 threads).
+__device__ __forceinline__ void load_tile(const double *__restrict__ A, int n, int I, int J, double *t) {
+    TileRegs r;
+    tile_fetch(A, n, I, J, r);
+    tile_put(t, r);
 }
 
 __device__ __forceinline__ void store_tile(double *__restrict__ A, int n, int I, int J, const double *t) {
@@ -252,9 +277,11 @@ __global__ __launch_bounds__(256) void k_tchol_panel(int n, int kt, double *__re
     __shared__ double ta[TB * TP], tv[TB * TP];
     if (*gate == 0 || *flag) return;
     const int I = kt + 1 + blockIdx.x;
-    load_tile(A, n, I, kt, ta);
-    const double *Lv = Linv + (size_t)kt * TB * TB;
-    for (int e = threadIdx.x; e < TB * TB; e += blockDim.x) tl(tv, e / TB, e % TB) = Lv[e];
+    TileRegs ra, rv;
+    tile_fetch(A, n, I, kt, ra);
+    tile_fetch(Linv + (size_t)kt * TB * TB, TB, 0, 0, rv);   // the inverse diagonal tile (TB x TB)
+    tile_put(ta, ra);
+    tile_put(tv, rv);
     __syncthreads();
     const int wv = threadIdx.x >> 6, l = threadIdx.x & 63, qr = wv >> 1, qc = wv & 1;
     const f64x4 acc = quad_xyT(ta, tv, qr, qc);
@@ -282,9 +309,15 @@ __global__ __launch_bounds__(256) void k_tchol_update(int n, int kt, double *__r
     while (i * (i + 1) / 2 > b) --i;
     const int j = b - i * (i + 1) / 2;
     const int I = kt + 1 + i, J = kt + 1 + j;
-    load_tile(A, n, I, kt, ti);
-    if (I != J) load_tile(A, n, J, kt, tj);
-    load_tile(A, n, I, J, tc);
+    {
+        TileRegs ri, rj, rc;
+        tile_fetch(A, n, I, kt, ri);
+        if (I != J) tile_fetch(A, n, J, kt, rj);
+        tile_fetch(A, n, I, J, rc);
+        tile_put(ti, ri);
+        if (I != J) tile_put(tj, rj);
+        tile_put(tc, rc);
+    }
     __syncthreads();
     const int wv = threadIdx.x >> 6, l = threadIdx.x & 63, qr = wv >> 1, qc = wv & 1;
     const f64x4 acc = quad_xyT(ti, I != J ? tj : ti, qr, qc);
@@ -297,6 +330,146 @@ __global__ __launch_bounds__(256) void k_tchol_update(int n, int kt, double *__r
             chol_fail(flag, gate);
             return;
         }
+    }
+    store_tile(A, n, I, J, tc);
+}
+
+// The chain for a few tiles (n <= TCHOL_FUSE_N): every panel is formed in the
+// kernel that factors its diagonal tile, so that one launch per step remains.
+// A panel block cannot read that tile from the factor (its own block rewrites
+// it in place), so it forms it itself: the tile of the unchanged S minus the
+// products of its row's factor tiles, in step order, which gives the same
+// values to the bit, and factors it.
+constexpr int TCHOL_FUSE_N = 8 * TB;
+
+// Diagonal tile J formed again: td holds S_JJ and tm[m] the factor tiles
+// L_Jm (m < J), all loaded by the caller; every wavefront subtracts the
+// products from its quadrant in step order, then the tile is factored and its
+// inverse left in LDS (tw, pitch TP). tv, ti, tj: scratch tiles. Whole block.
+__device__ __forceinline__ bool tile_diag_again(int n, int J, double *td, const double *tm, double *tv, double *ti,
+                                                double *tj, double *tw, double *invd, int *fail) {
+    const int wv = threadIdx.x >> 6, qr = wv >> 1, qc = wv & 1, l = threadIdx.x & 63;
+    for (int m = 0; m < J; ++m) {
+        const double *L = tm + (size_t)m * TB * TP;
+        const f64x4 acc = quad_xyT(L, L, qr, qc);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) tl(td, 16 * qr + (l >> 4) + 4 * q, 16 * qc + (l & 15)) -= acc[q];
+    }
+    __syncthreads();
+    // inverse written at pitch TB into tv, then copied at pitch TP into tw
+    if (!tile_potrf_inv(td, min(TB, n - TB * J), tv, invd, ti, tj, fail)) return false;
+    for (int e = threadIdx.x; e < TB * TB; e += blockDim.x) tl(tw, e / TB, e % TB) = tv[e];
+    __syncthreads();
+    return true;
+}
+
+// Panel tile (I, J): A_IJ (in ta) times the inverse's transpose (tw), written back.
+__device__ __forceinline__ void tile_panel(double *A, int n, int I, int J, double *ta, const double *tw) {
+    const int wv = threadIdx.x >> 6, l = threadIdx.x & 63, qr = wv >> 1, qc = wv & 1;
+    const f64x4 acc = quad_xyT(ta, tw, qr, qc);
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < 4; ++i) tl(ta, 16 * qr + (l >> 4) + 4 * i, 16 * qc + (l & 15)) = acc[i];
+    __syncthreads();
+    store_tile(A, n, I, J, ta);
+}
+
+// Step 0 of the short chain: block 0 factors tile (0, 0) (writing it and its
+// inverse); block I > 0 forms L_I0 = A_I0 L00^{-T}.
+__global__ __launch_bounds__(256) void k_tchol_first_panel(int n, const double *__restrict__ S, double *__restrict__ A,
+                                                           double *__restrict__ Linv, int *__restrict__ flag,
+                                                           int *__restrict__ gate) {
+    __shared__ double ta[TB * TP], td[TB * TP], tv[TB * TP], ti[TB * TP], tj[TB * TP], tw[TB * TP];
+    __shared__ double invd[TB];
+    __shared__ int fail;
+    if (*gate == 0 || *flag) return;
+    const int I = blockIdx.x;
+    if (I == 0) {
+        load_tile(A, n, 0, 0, ta);
+        __syncthreads();
+        if (!tile_potrf_inv(ta, min(TB, n), Linv, invd, ti, tj, &fail)) {
+            chol_fail(flag, gate);
+            return;
+        }
+        store_tile(A, n, 0, 0, ta);
+        return;
+    }
+    {
+        TileRegs ra, rd;
+        tile_fetch(A, n, I, 0, ra);
+        tile_fetch(S, n, 0, 0, rd);
+        tile_put(ta, ra);
+        tile_put(td, rd);
+    }
+    __syncthreads();
+    if (!tile_diag_again(n, 0, td, nullptr, tv, ti, tj, tw, invd, &fail)) {
+        chol_fail(flag, gate);
+        return;
+    }
+    tile_panel(A, n, I, 0, ta, tw);
+}
+
+// Step kt of the short chain: the trailing update A_IJ -= L_I,kt L_J,kt^T of
+// every tile kt < J <= I (one per block, lower-triangle order); the block of
+// tile (kt+1, kt+1) then factors it and writes its inverse, and the blocks of
+// column kt + 1 form their panel tiles.
+__global__ __launch_bounds__(256) void k_tchol_update_panel(int n, int kt, const double *__restrict__ S,
+                                                            double *__restrict__ A, double *__restrict__ Linv,
+                                                            int *__restrict__ flag, int *__restrict__ gate) {
+    __shared__ double ti[TB * TP], tj[TB * TP], tc[TB * TP], td[TB * TP], tw[TB * TP];
+    __shared__ double tm[(TCHOL_FUSE_N / TB - 1) * TB * TP];   // L_Jm, m < J (panel blocks)
+    __shared__ double invd[TB];
+    __shared__ int fail;
+    if (*gate == 0 || *flag) return;
+    const int b = blockIdx.x;
+    int i = (int)((sqrt(8.0 * b + 1.0) - 1.0) * 0.5);
+    while ((i + 1) * (i + 2) / 2 <= b) ++i;
+    while (i * (i + 1) / 2 > b) --i;
+    const int j = b - i * (i + 1) / 2;
+    const int I = kt + 1 + i, J = kt + 1 + j;
+    const bool panel = J == kt + 1 && I != J;
+    // every load of the block in one batch: the update's tiles and, for a panel
+    // block, S_JJ and the factor tiles L_Jm of the diagonal tile's row
+    {
+        constexpr int MM = TCHOL_FUSE_N / TB - 1;
+        TileRegs ri, rj, rc, rd, rm[MM];
+        tile_fetch(A, n, I, kt, ri);
+        if (I != J) tile_fetch(A, n, J, kt, rj);
+        tile_fetch(A, n, I, J, rc);
+        if (panel) {
+            tile_fetch(S, n, J, J, rd);
+#pragma unroll
+            for (int m = 0; m < MM; ++m)
+                if (m < J) tile_fetch(A, n, J, m, rm[m]);
+        }
+        tile_put(ti, ri);
+        if (I != J) tile_put(tj, rj);
+        tile_put(tc, rc);
+        if (panel) {
+            tile_put(td, rd);
+#pragma unroll
+            for (int m = 0; m < MM; ++m)
+                if (m < J) tile_put(tm + (size_t)m * TB * TP, rm[m]);
+        }
+    }
+    __syncthreads();
+    const int wv = threadIdx.x >> 6, l = threadIdx.x & 63, qr = wv >> 1, qc = wv & 1;
+    const f64x4 acc = quad_xyT(ti, I != J ? tj : ti, qr, qc);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) tl(tc, 16 * qr + (l >> 4) + 4 * q, 16 * qc + (l & 15)) -= acc[q];
+    __syncthreads();
+    if (I == kt + 1 && J == kt + 1) {
+        if (!tile_potrf_inv(tc, min(TB, n - TB * I), Linv + (size_t)I * TB * TB, invd, ti, tj, &fail)) {
+            chol_fail(flag, gate);
+            return;
+        }
+    } else if (panel) {
+        if (!tile_diag_again(n, J, td, tm, tm, ti, tj, tw, invd, &fail)) {
+            chol_fail(flag, gate);
+            return;
+        }
+        tile_panel(A, n, I, J, tc, tw);
+        return;
     }
     store_tile(A, n, I, J, tc);
 }
@@ -377,6 +550,16 @@ void launch_tchol(hipStream_t s, Ctx &c, bool copy) {
     const int n = 6 * c.F, nt = (n + TB - 1) / TB;
     const size_t nn = (size_t)n * n;
     if (copy) k_copy_d<<<(unsigned)((nn + 255) / 256), 256, 0, s>>>(c.d_S, c.d_Sfac, nn, c.d_gate);
+    if (n <= TCHOL_FUSE_N) {
+        // S (unchanged by the factorization) holds the diagonal tiles' values
+        k_tchol_first_panel<<<nt, 256, 0, s>>>(n, c.d_S, c.d_Sfac, c.d_Linv, c.d_flag, c.d_gate);
+        for (int kt = 0; kt + 1 < nt; ++kt) {
+            const int m = nt - kt - 1;
+            k_tchol_update_panel<<<m * (m + 1) / 2, 256, 0, s>>>(n, kt, c.d_S, c.d_Sfac, c.d_Linv, c.d_flag,
+                                                                  c.d_gate);
+        }
+        return;
+    }
     k_tchol_first<<<1, 256, 0, s>>>(n, c.d_Sfac, c.d_Linv, c.d_flag, c.d_gate);
     for (int kt = 0; kt + 1 < nt; ++kt) {
         const int m = nt - kt - 1;
