@@ -11,6 +11,7 @@
 namespace pba {
 
 constexpr int SOLVE_THREADS = 1024;
+constexpr int MU_LDS_PAIRS = 512;               // pair sums of the damping kernel kept in LDS up to this many pairs
 constexpr int LDS_DOUBLES = 152 * 1024 / 8;   // packed lower triangle of S (+ panel scratch) when it fits
 constexpr int LDS_MAX_N = LDS_CHOL_MAX_N;     // n (n + 1) / 2 + 17 n <= LDS_DOUBLES; 3 rows per lane
 constexpr int IC_SPLIT_N = 256;               // IC systems above this size: multi-workgroup S^{-1} b
@@ -73,9 +74,11 @@ __global__ __launch_bounds__(1024) void k_mu(WinArgs wa, double damping, const i
                                              const double *__restrict__ geo, const double *__restrict__ Hdd,
                                              double *__restrict__ mu, const int *__restrict__ gate) {
     __shared__ double lds[2 * 16];
+    __shared__ double hl[MU_LDS_PAIRS * 21];   // the pair sums, when the window's pairs fit
     if (*gate == 0) return;
     const int w = blockIdx.x;
     const int p0 = wa.pair_off[w], p1 = wa.pair_off[w + 1];
+    const bool in_lds = p1 - p0 <= MU_LDS_PAIRS;
     for (int e = threadIdx.x; e < (p1 - p0) * 21; e += blockDim.x) {
         const int p = p0 + e / 21, k = e % 21;
         const int c0 = pair_chunk_ptr[p], c1 = pair_chunk_ptr[p + 1];
@@ -83,15 +86,19 @@ __global__ __launch_bounds__(1024) void k_mu(WinArgs wa, double damping, const i
 #pragma unroll 8
         for (int c = c0; c < c1; ++c) s += partH[21 * c + k];
         pairH[21 * p + k] = s;
+        if (in_lds) hl[e] = s;
     }
-    __threadfence_block();
+    // the sums are read back from LDS (no wait for the global stores) unless
+    // the window has more pairs than that holds
+    if (!in_lds) __threadfence_block();
     __syncthreads();
     double v[2] = {0.0, 0.0};
     for (int e = threadIdx.x; e < (p1 - p0) * 6; e += blockDim.x) {
         const int p = p0 + e / 6, r = e % 6;
         double a[6], bcol[6];
         abs_map_columns(geo + GEO_STRIDE * p, r, a, bcol);
-        v[0] += quad6(a, pairH + 21 * p, a) + quad6(bcol, pairH + 21 * p, bcol);
+        const double *H = in_lds ? hl + 21 * (p - p0) : pairH + 21 * p;
+        v[0] += quad6(a, H, a) + quad6(bcol, H, bcol);
     }
     const int n0 = wa.point_off[w], n1 = wa.point_off[w + 1];
 #pragma unroll 8
