@@ -87,6 +87,44 @@ __device__ __forceinline__ void wave_sync() {
 
 constexpr int SP = 17;   // LDS pitch of the 16 x 16 scratch blocks
 
+// Factors a 16-column register panel in place (lane r holds row r; the
+// diagonal of column j sits in lane base + j; rows past the tile hold 0).
+// After column j's multipliers are formed, the next column is updated first,
+// with the pivot row's multiplier read from its lane, so that the next pivot's
+// square root and reciprocal are formed before the rest of column j's
+// rank-one update is broadcast through LDS (bc, 16 doubles) and applied; the
+// operations and operands are those of the plain column loop. The update runs
+// on every lane (entries above the diagonal take values that are never read).
+// Returns whether every pivot was positive.
+__device__ __forceinline__ bool panel_factor16(double (&row)[16], int base, double *bc) {
+    const int l = threadIdx.x & 63;
+    double p = readlane_d(row[0], base);
+    bool ok = p > 0.0;
+    double lj = sqrt(p > 0.0 ? p : 1.0), inv = 1.0 / lj;
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+        const double a = l > base + j ? row[j] * inv : (l == base + j ? lj : row[j]);
+        row[j] = a;
+        if (j < 15) {
+            const double an = readlane_d(a, base + j + 1);
+            row[j + 1] -= a * an;
+            const double pn = readlane_d(row[j + 1], base + j + 1);
+            ok = ok && pn > 0.0;
+            const double ljn = sqrt(pn > 0.0 ? pn : 1.0), invn = 1.0 / ljn;
+            if (j < 14) {
+                if (l > base + j + 1 && l < base + 16) bc[l - base] = a;
+                wave_sync();
+#pragma unroll
+                for (int c = j + 2; c < 16; ++c) row[c] -= a * bc[c];
+                wave_sync();
+            }
+            lj = ljn;
+            inv = invn;
+        }
+    }
+    return ok;
+}
+
 // Factor the LDS tile t = L L^T in place (rows and columns >= nb are made the
 // identity first), and write L^{-1} (identity on the padding) to Linv_g.
 // Called by a whole 256-thread block; wavefront 0 does the work, blocked 2 x 2
@@ -118,22 +156,7 @@ __device__ __forceinline__ bool tile_potrf_inv(double *t, int nb, double *__rest
         // panel 1: columns 0..15 of rows 0..31 (L11 and L21)
 #pragma unroll
         for (int c = 0; c < 16; ++c) row[c] = l < TB ? tl(t, l, c) : 0.0;
-        double *bc = s1;   // the column's multipliers of rows j + 1 .. 15
-#pragma unroll
-        for (int j = 0; j < 16; ++j) {
-            const double p = readlane_d(row[j], j);
-            ok = ok && p > 0.0;
-            const double lj = sqrt(p > 0.0 ? p : 1.0), inv = 1.0 / lj;
-            const double a = l > j ? row[j] * inv : (l == j ? lj : row[j]);
-            row[j] = a;
-            if (j < 15) {
-                if (l > j && l < 16) bc[l] = a;
-                wave_sync();
-#pragma unroll
-                for (int c = j + 1; c < 16; ++c) row[c] -= a * bc[c];
-                wave_sync();
-            }
-        }
+        ok = panel_factor16(row, 0, s1);
         if (l < TB) {
 #pragma unroll
             for (int c = 0; c < 16; ++c) tl(t, l, c) = c <= l ? row[c] : 0.0;
@@ -154,21 +177,8 @@ __device__ __forceinline__ bool tile_potrf_inv(double *t, int nb, double *__rest
         // panel 2: A22 on lanes 16..31
 #pragma unroll
         for (int c = 0; c < 16; ++c) row[c] = (l >= 16 && l < TB) ? tl(t, l, 16 + c) : 0.0;
-#pragma unroll
-        for (int j = 0; j < 16; ++j) {
-            const double p = readlane_d(row[j], 16 + j);
-            ok = ok && p > 0.0;
-            const double lj = sqrt(p > 0.0 ? p : 1.0), inv = 1.0 / lj;
-            const double a = l > 16 + j ? row[j] * inv : (l == 16 + j ? lj : row[j]);
-            row[j] = a;
-            if (j < 15) {
-                if (l > 16 + j && l < TB) bc[l - 16] = a;
-                wave_sync();
-#pragma unroll
-                for (int c = j + 1; c < 16; ++c) row[c] -= a * bc[c];
-                wave_sync();
-            }
-        }
+        const bool ok2 = panel_factor16(row, 16, s1);
+        ok = ok && ok2;
         if (!ok) {
             if (l == 0) *fail = 1;
         } else {
