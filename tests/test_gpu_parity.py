@@ -254,3 +254,18 @@ def test_invalid_arguments_leave_state():
     assert e.value.status == pba.PBA_E_INVALID
     st = s.iterate(0, 1)  # the previous points are still set
     assert st[0]["n_active"] > 0
+
+
+@pytest.mark.parametrize("split", [(1, 2), (2, 1)])
+def test_ic_iteration_batches_compose(mid_small, split):
+    """IC iterations enqueued in several calls give exactly the result of one
+    call: the fused solve + depth step alternates two pose buffers within a
+    batch and copies back after an odd count, so both parities are covered."""
+    out = []
+    for parts in (split, (sum(split),)):
+        s = make(mid_small, "ic", 0)
+        for k in parts:
+            s.iterate(0, k)
+        out.append(s.get_params())
+        s.close()
+    assert np.array_equal(out[0][0], out[1][0]) and np.array_equal(out[0][1], out[1][1])
