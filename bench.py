@@ -429,8 +429,9 @@ def main():
                     help="also run device copies of BYTES (scale for profiler byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}): the solver has no multi-GPU path; "
-              "see DESIGN.md for how it would shard.", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}): the solver has no multi-GPU path "
+              "(points would shard over GPUs with an all-reduce of the FP64 reduced pose system; not built).",
+              file=sys.stderr)
         sys.exit(2)
 
     import scenes
