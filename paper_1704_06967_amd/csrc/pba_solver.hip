@@ -1175,9 +1175,12 @@ static int step_sel_ncw(const Ctx &c) {
     return (6 * c.F + ng - 1) / ng <= SV_REG ? ncw : 0;
 }
 
+// Every workgroup of the fused step repeats the solve and holds a compute unit
+// (its LDS), so the step is fused only while its grid is one round on the
+// device: more points keep the solve and the depth step as separate kernels.
 bool ic_fused(const Ctx &c) {
     return c.cfg.mode == PBA_IC_PROXY && one_window(c) && 6 * c.F <= IC_SPLIT_N && c.N > 0 &&
-           solve_cache_fits(c, true);
+           1 + (int)nb(c.N, IC_STEP_PTS) <= c.n_cu && solve_cache_fits(c, true);
 }
 
 int du_nparts(const Ctx &c) {

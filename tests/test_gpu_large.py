@@ -101,3 +101,21 @@ def test_ic_split_solve_iterations_fp64():
     assert rot_err(poses, gn.poses).max() <= 1e-8
     assert trans_rel_err(poses, gn.poses).max() <= 1e-8
     assert np.abs(d / gn.d - 1).max() <= 1e-8
+
+
+def test_ic_many_points_separate_kernels_fp64():
+    """IC on one window with more points (36 000) than one round of the fused
+    solve + depth-step grid covers: the solve and the depth step run as
+    separate kernels. Level 2, three iterations against the oracle."""
+    sc = scenes.mid(n_per_host=7200)
+    s = make(sc, "ic", 0)
+    gn = GaussNewton(Problem.from_scene(sc), "ic")
+    st = s.iterate(2, 3)
+    ost = gn.iterate(2, 3)
+    for a, o in zip(st, ost):
+        assert a["n_active"] == o["n_active"]
+        assert abs(a["energy"] / o["energy"] - 1) <= 1e-9
+    poses, d = s.get_params()
+    assert rot_err(poses, gn.poses).max() <= 1e-8
+    assert trans_rel_err(poses, gn.poses).max() <= 1e-8
+    assert np.abs(d / gn.d - 1).max() <= 1e-8
