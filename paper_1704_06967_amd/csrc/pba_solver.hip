@@ -743,7 +743,11 @@ __device__ __forceinline__ bool solve_window(
         }
         // global pair sums are read back below only without the cache
         if constexpr (!CACHE) __threadfence_block();
-        block_sum_d<3>(v3, red);
+        // the statistics only where they are stored (the barrier either way)
+        if (writer)
+            block_sum_d<3>(v3, red);
+        else
+            __syncthreads();
         if (!CACHE && threadIdx.x == 0) {
             wstat[4 * w + 0] = v3[0];
             wstat[4 * w + 1] = v3[1];
@@ -919,11 +923,13 @@ __device__ __forceinline__ bool solve_window(
     if constexpr (!CACHE) __threadfence_block();
     __syncthreads();
     const double *dth = CACHE ? c_dth : dth_out;
-    // largest pose step
-    double mx = 0.0;
-    for (int i = threadIdx.x; i < n; i += blockDim.x) mx = fmax(mx, fabs(dth[i]));
-    mx = wave_max(mx);
-    if (lane == 0) red[wv] = mx;
+    // largest pose step (where it is stored)
+    if (writer) {
+        double mx = 0.0;
+        for (int i = threadIdx.x; i < n; i += blockDim.x) mx = fmax(mx, fabs(dth[i]));
+        mx = wave_max(mx);
+        if (lane == 0) red[wv] = mx;
+    }
     // pose update
     for (int lf = threadIdx.x; lf < F; lf += blockDim.x) {
         if (!((fmask >> (lf & 63)) & 1ull)) continue;   // (sel) a frame whose step was not formed
@@ -948,9 +954,9 @@ __device__ __forceinline__ bool solve_window(
     }
     if constexpr (!CACHE) __threadfence_block();
     __syncthreads();
-    if (wv == 0) {
+    if (writer && wv == 0) {
         const double m2 = row_max16(lane < nw ? red[lane] : 0.0);
-        if (writer && lane == 0) wstat[4 * w + 3] = m2;
+        if (lane == 0) wstat[4 * w + 3] = m2;
     }
     // next relative poses and relative steps per pair (frames window-local)
     const double *pose_w = CACHE ? c_pose : poses + 12 * f0;
