@@ -4,6 +4,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <utility>
+
 namespace pba {
 
 struct PatternArg {
@@ -379,6 +381,31 @@ __device__ __forceinline__ T half_sum32(T v) {
     v = row_sum16(v);
     const T a = lane_value(v, 0) + lane_value(v, 16), b = lane_value(v, 32) + lane_value(v, 48);
     return (threadIdx.x & 32) ? b : a;
+}
+
+// Lane S of each aligned group of 8 lanes, read by every lane of the group:
+// ds_swizzle in bit-mask mode (within each 32 lanes the source is
+// (lane & 0x18) | S). An inactive source lane reads as 0, so the whole group
+// must be active.
+template <int S>
+__device__ __forceinline__ float bcast8(float v) {
+    static_assert(S >= 0 && S < 8, "a lane of the group of 8");
+    return __int_as_float(__builtin_amdgcn_ds_swizzle(__float_as_int(v), 0x18 | (S << 5)));
+}
+template <int S>
+__device__ __forceinline__ double bcast8(double v) {
+    static_assert(S >= 0 && S < 8, "a lane of the group of 8");
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_ds_swizzle((int)b, 0x18 | (S << 5));
+    const int hi = __builtin_amdgcn_ds_swizzle((int)(b >> 32), 0x18 | (S << 5));
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// out[k] = component k % 4 of lane k / 4's slice, for k < 4 * 8 (every lane of
+// a group of 8 gets the group's 32 values).
+template <typename T, typename V, int... K>
+__device__ __forceinline__ void bcast8_slices(const V &sl, T *out, std::integer_sequence<int, K...>) {
+    ((out[K] = bcast8<K / 4>((T)sl[K % 4])), ...);
 }
 
 }  // namespace pba

@@ -424,38 +424,48 @@ __global__ __launch_bounds__(NB) void k_ic_residual(ResArgs<T> a) {
         const int gv = __hip_atomic_load(a.gate, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         if (__builtin_amdgcn_readfirstlane(gv) == 0) return;
         T c[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
-        if (in && j < a.P && ((m >> j) & 1)) {
-            // second step: every load that depends only on (n, pr, j), issued
-            // before any branch
-            const double dd = a.depth[n], dd0 = a.depth0[n];
-            T cam[8], R[12], R0[12], tp[4];
-#pragma unroll
-            for (int k = 0; k < 8; ++k) cam[k] = a.pcam[8 * pr + k];   // host, target (fx, fy, cx, cy)
-#pragma unroll
-            for (int k = 0; k < 12; ++k) R[k] = a.rel[REL_STRIDE * pr + k];
-#pragma unroll
-            for (int k = 0; k < 12; ++k) R0[k] = a.rel0[REL_STRIDE * pr + k];
+        // second step: every load that depends only on (n, pr, j), issued
+        // before any branch. The pair's intrinsics and both relative poses (32
+        // values) and the point's host pixel and inverse depths are loaded once
+        // per observation, a slice per lane (lane j: values 4j..4j+3 of
+        // pcam | rel | rel0; lanes 0-2: host_uv, depth, depth0), and read across
+        // the observation's 8 lanes: a lane's loads return 11 values instead of
+        // 43, and the per-CU return path is what bounds this step.
+        typedef T T4 __attribute__((ext_vector_type(4)));
+        const bool act = in && j < a.P && ((m >> j) & 1);
+        T4 sl = {0, 0, 0, 0};
+        double pt = 0.0;
+        if (in && m != 0u) {
+            const T *src = j < 2 ? a.pcam + 8 * pr + 4 * j
+                                 : (j < 5 ? a.rel + REL_STRIDE * pr + 4 * (j - 2)
+                                          : a.rel0 + REL_STRIDE * pr + 4 * (j - 5));
+            sl = *reinterpret_cast<const T4 *>(src);
+            if (j < 3)
+                pt = j == 0 ? *reinterpret_cast<const double *>(a.host_uv + 2 * n) : (j == 1 ? a.depth[n] : a.depth0[n]);
+        }
+        T tp[4] = {0, 0, 0, 0};
+        int f = 0;
+        if (act) {
 #pragma unroll
             for (int k = 0; k < 4; ++k) tp[k] = a.tmpl[4 * ((size_t)n * a.P + j) + k];
-            int f = a.pair_target[pr];
-            T hu = (T)a.host_uv[2 * n], hv = (T)a.host_uv[2 * n + 1];
-            T d = (T)dd, d0 = (T)dd0;
-            // keep the compiler from sinking these loads into the branches below
-            // (the pins follow every load, so that all of them are in flight)
-            pin_reg(f);
-            pin_reg(hu);
-            pin_reg(hv);
-            pin_reg(d);
-            pin_reg(d0);
+            f = a.pair_target[pr];
+        }
+        // keep the compiler from sinking these loads into the branches below
+        // (the pins follow every load, so that all of them are in flight)
+        pin_reg(sl);
+        pin_reg(pt);
+        pin_reg(f);
 #pragma unroll
-            for (int k = 0; k < 8; ++k) pin_reg(cam[k]);
-#pragma unroll
-            for (int k = 0; k < 12; ++k) {
-                pin_reg(R[k]);
-                pin_reg(R0[k]);
-            }
-#pragma unroll
-            for (int k = 0; k < 4; ++k) pin_reg(tp[k]);
+        for (int k = 0; k < 4; ++k) pin_reg(tp[k]);
+        // the group's values, read by the whole wavefront
+        T q[32];
+        bcast8_slices(sl, q, std::make_integer_sequence<int, 32>{});
+        const double uv = bcast8<0>(pt), dd = bcast8<1>(pt), dd0 = bcast8<2>(pt);
+        if (act) {
+            const T *cam = q, *R = q + 8, *R0 = q + 20;   // cam: host, target (fx, fy, cx, cy)
+            const long long uvb = __double_as_longlong(uv);
+            const T hu = (T)__int_as_float((int)uvb), hv = (T)__int_as_float((int)(uvb >> 32));
+            const T d = (T)dd, d0 = (T)dd0;
             // pattern offset of lane j by selects (no lane-indexed argument loads)
             float du = a.pat.du[0], dv = a.pat.dv[0];
 #pragma unroll
