@@ -153,7 +153,7 @@ void release_frames(Ctx &c) {
     dfree(c.d_count);
     dfree(c.d_du_part);
     dfree(c.d_pairK0);
-    dfree(c.d_obs_prange);
+    dfree(c.d_pc_slot);
     dfree(c.d_step_sel);
     for (int **p : {&c.d_win_frame_off, &c.d_win_S_off, &c.d_win_L_off, &c.d_frame_win}) dfree(*p);
     dfree(c.d_wstat);
@@ -786,12 +786,26 @@ pba_status load_points(Ctx &c, int n_points, const std::vector<int> &hf, const s
                 pk[8 * (size_t)p + 4 + k] = c.K0[4 * (size_t)s.pair_target[p] + k];
             }
         HIPCHK(upload(c, c.d_pairK0, pk));
-        std::vector<int> pr(2 * (size_t)O);
-        for (int o = 0; o < O; ++o) {
-            pr[2 * (size_t)o] = optr[s.obs_point[o]];
-            pr[2 * (size_t)o + 1] = optr[s.obs_point[o] + 1];
-        }
-        HIPCHK(upload(c, c.d_obs_prange, pr));
+        // per slot t of pair chunk k (slot k * PAIR_CHUNK + t): the observation,
+        // its point and the point's observation range; observation -1 past the
+        // chunk's end
+        const size_t nsl = s.pchunk_begin.size() * (size_t)PAIR_CHUNK;
+        std::vector<int> sl(4 * std::max<size_t>(nsl, 1), 0);
+        for (size_t k = 0; k < s.pchunk_begin.size(); ++k)
+            for (int t = 0; t < PAIR_CHUNK; ++t) {
+                int *e = &sl[4 * (k * PAIR_CHUNK + t)];
+                const int i = s.pchunk_begin[k] + t;
+                if (i >= s.pchunk_end[k]) {
+                    e[0] = -1;
+                    continue;
+                }
+                const int o = s.pair_obs_idx[i], n = s.obs_point[o];
+                e[0] = o;
+                e[1] = n;
+                e[2] = optr[n];
+                e[3] = optr[n + 1];
+            }
+        HIPCHK(upload(c, c.d_pc_slot, sl));
         // frames each depth workgroup of the fused IC step observes
         dfree(c.d_step_sel);
         c.step_sel_max = 0;

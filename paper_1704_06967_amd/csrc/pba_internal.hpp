@@ -214,7 +214,7 @@ struct Ctx {
     int *d_count = nullptr;                            // iterations run per level [PBA_MAX_LEVELS]
     double *d_du_part = nullptr;                       // depth-update block maxima [blocks][2]
     double *d_pairK0 = nullptr;                        // [Pn][8] level-0 intrinsics of host and target
-    int *d_obs_prange = nullptr;                       // [O][2] observation range of each observation's point
+    int *d_pc_slot = nullptr;  // [pair chunks][PAIR_CHUNK][4] observation (-1: none), point, point's range
 
     // current double-buffer orientation
     bool flip = false;

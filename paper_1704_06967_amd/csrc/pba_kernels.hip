@@ -660,19 +660,19 @@ __global__ __launch_bounds__(256) void k_point_reduce(int N, const int *__restri
 
 // Per chunk of one pair's observations (at most PAIR_CHUNK, one per thread):
 // sum of the pose-pose block (21 values). Chunk partials are added per pair in
-// chunk order by the consumer.
+// chunk order by the consumer. slot: per thread of each chunk (observation,
+// point, the point's observation range), observation -1 past the chunk's end.
 template <typename T>
-__global__ __launch_bounds__(PAIR_CHUNK) void k_pair_chunk_H(const int *__restrict__ chunk_begin,
-                                                      const int *__restrict__ chunk_end,
-                                                      const int *__restrict__ pair_obs_idx, const T *__restrict__ rec,
+__global__ __launch_bounds__(PAIR_CHUNK) void k_pair_chunk_H(const int4 *__restrict__ slot, const T *__restrict__ rec,
                                                       double *__restrict__ partH, const int *__restrict__ gate) {
     __shared__ double lds[21 * 16];
     if (*gate == 0) return;
     const int c = blockIdx.x;
+    const int o = slot[(size_t)c * PAIR_CHUNK + threadIdx.x].x;
     double v[21];
     for (int k = 0; k < 21; ++k) v[k] = 0.0;
-    for (int i = chunk_begin[c] + threadIdx.x; i < chunk_end[c]; i += blockDim.x) {
-        const T *r = rec + (size_t)pair_obs_idx[i] * REC_STRIDE;
+    if (o >= 0) {
+        const T *r = rec + (size_t)o * REC_STRIDE;
         for (int k = 0; k < 21; ++k) v[k] += (double)r[REC_H + k];
     }
     block_sum<21>(v, lds);
@@ -686,11 +686,7 @@ __global__ __launch_bounds__(PAIR_CHUNK) void k_pair_chunk_H(const int *__restri
 // records (GR_* fields) and their stride; h_o from the full record; prange: the
 // observation range of each observation's point.
 template <typename T>
-__global__ __launch_bounds__(PAIR_CHUNK) void k_pair_chunk_y(const int *__restrict__ chunk_begin,
-                                                             const int *__restrict__ chunk_end,
-                                                             const int *__restrict__ pair_obs_idx,
-                                                             const int *__restrict__ obs_point,
-                                                             const int *__restrict__ prange, const T *__restrict__ rec,
+__global__ __launch_bounds__(PAIR_CHUNK) void k_pair_chunk_y(const int4 *__restrict__ slot, const T *__restrict__ rec,
                                                              const T *__restrict__ gr, int gs,
                                                              const double *__restrict__ Hdd,
                                                              double *__restrict__ partY, const int *__restrict__ gate,
@@ -698,27 +694,31 @@ __global__ __launch_bounds__(PAIR_CHUNK) void k_pair_chunk_y(const int *__restri
                                                              ConvArgs cv) {
     __shared__ double lds[9 * 16];
     __shared__ double red[2][16];
-    if (*gate == 0) return;
+    const int c = blockIdx.x;
+    // the thread's slot and the gate (a vector load) in one memory step; a
+    // closed gate leaves every sum zero (the sums are then not used), so that
+    // all waves of the block reach its barriers
+    const int4 sd = slot[(size_t)c * PAIR_CHUNK + threadIdx.x];
+    const bool live = __builtin_amdgcn_readfirstlane(
+                          __hip_atomic_load(gate, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) != 0;
     // block 0 also ends the previous iteration (IC): the depth update's block
     // maxima (loaded now, reduced after the pair sums) give its largest
     // displacement and depth step, its statistics and the convergence gate. If
-    // that closes the gate, this iteration's sums are simply not used.
-    const bool finish_prev = du_part != nullptr && blockIdx.x == 0;
+    // that closes the gate, this iteration's sums are simply not used. Only
+    // block 0 writes the gate, after all its waves have read it.
+    const bool finish_prev = du_part != nullptr && blockIdx.x == 0 && live;
     double pmd = 0.0, pms = 0.0;
     if (finish_prev)
         for (int i = threadIdx.x; i < du_nparts; i += blockDim.x) {
             pmd = fmax(pmd, du_part[2 * i]);
             pms = fmax(pms, du_part[2 * i + 1]);
         }
-    const int c = blockIdx.x;
     double v[9];
     for (int k = 0; k < 9; ++k) v[k] = 0.0;
-    for (int i = chunk_begin[c] + threadIdx.x; i < chunk_end[c]; i += blockDim.x) {
-        const int o = pair_obs_idx[i];
+    if (live && sd.x >= 0) {
+        const int o = sd.x, n = sd.y, q0 = sd.z, q1 = sd.w;
         const T *r = rec + (size_t)o * REC_STRIDE;
         const T *g = gr + (size_t)o * gs;
-        const int n = obs_point[o];
-        const int q0 = prange[2 * o], q1 = prange[2 * o + 1];
         double gdn = 0.0;  // g_d,n: the point's records in order (bitwise the per-point sum)
 #pragma unroll 4
         for (int q = q0; q < q1; ++q) gdn += (double)gr[(size_t)q * gs + GR_GD];
@@ -729,7 +729,7 @@ __global__ __launch_bounds__(PAIR_CHUNK) void k_pair_chunk_y(const int *__restri
         v[8] += (double)g[GR_CNT];
     }
     block_sum<9>(v, lds);
-    if (threadIdx.x == 0)
+    if (threadIdx.x == 0 && live)
         for (int k = 0; k < 9; ++k) partY[9 * c + k] = v[k];
     if (finish_prev) {
         pmd = wave_max(pmd);
@@ -1017,8 +1017,7 @@ template <typename T>
 void Launch<T>::pair_reduce_H(hipStream_t s, Ctx &c) {
     const int nch = (int)c.st.pchunk_begin.size();
     if (nch == 0) return;
-    k_pair_chunk_H<T><<<nch, PAIR_CHUNK, 0, s>>>(c.d_pchunk_begin, c.d_pchunk_end, c.d_pair_obs_idx, (const T *)c.d_rec,
-                                          c.d_partH, c.d_gate);
+    k_pair_chunk_H<T><<<nch, PAIR_CHUNK, 0, s>>>((const int4 *)c.d_pc_slot, (const T *)c.d_rec, c.d_partH, c.d_gate);
     CHECK_LAUNCH();
 }
 
@@ -1033,8 +1032,7 @@ void Launch<T>::pair_reduce_y(hipStream_t s, Ctx &c, double *prev_stat, double c
     const T *gr;
     int gs;
     grad_records<T>(c, gr, gs);
-    k_pair_chunk_y<T><<<nch, PAIR_CHUNK, 0, s>>>(c.d_pchunk_begin, c.d_pchunk_end, c.d_pair_obs_idx,
-                                                 c.d_obs_point, c.d_obs_prange, (const T *)c.d_rec, gr, gs, c.d_Hdd,
+    k_pair_chunk_y<T><<<nch, PAIR_CHUNK, 0, s>>>((const int4 *)c.d_pc_slot, (const T *)c.d_rec, gr, gs, c.d_Hdd,
                                                  c.d_partY, c.d_gate, prev_stat ? c.d_du_part : nullptr,
                                                  du_nparts(c), conv_args(c, prev_stat, conv_px, level));
     CHECK_LAUNCH();
