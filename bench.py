@@ -34,7 +34,7 @@ HBM_PEAK_GBS = 8000.0
 # runs (FETCH_SIZE x 2.000 + WRITE_SIZE x 1.000, scales from a 256 MiB device copy;
 # profiles/k_ic_residual_traffic_mid_precision.md), valid for the kernel source with
 # this hash only
-MEASURED_TRAFFIC = {"mid": 24461198, "precision": 202066290, "kernels_sha256_16": "46aea7f173a83712"}
+MEASURED_TRAFFIC = {"mid": 24468431, "precision": 202061042, "kernels_sha256_16": "d907afdac7c1cd53"}
 
 
 def measured_traffic(workload):

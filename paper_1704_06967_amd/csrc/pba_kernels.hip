@@ -194,9 +194,9 @@ __device__ __forceinline__ bool lin_eval(const ResArgs<T> &a, int o, int j, int 
     r = w = rho = 0;
     if (o < 0 || o >= a.O || j >= a.P) return false;
     const int n = a.obs_point[o], pr = a.obs_pair[o];
-    const int h = a.pair_host[pr], f = a.pair_target[pr];
-    const T *Kh = a.K + 4 * h;
-    const T *Kt = a.K + 4 * f;
+    const int f = a.pair_target[pr];
+    const T *Kh = a.pcam + 8 * pr;   // the pair's host and target intrinsics (one load step fewer than K[frame])
+    const T *Kt = Kh + 4;
     const T *tp = a.tmpl + 4 * ((size_t)n * a.P + j);
     const T I0 = tp[0], gu0 = tp[1], gv0 = tp[2];
     const bool host_ok = tp[3] != T(0);
