@@ -41,6 +41,8 @@ def measured_traffic(workload):
     ksrc = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_1704_06967_amd", "csrc", "pba_kernels.hip")
     sha = hashlib.sha256(open(ksrc, "rb").read()).hexdigest()[:16]
     return MEASURED_TRAFFIC[workload] if sha == MEASURED_TRAFFIC["kernels_sha256_16"] else None
+
+
 METRIC = "GN iters/s & residuals/s, IC-proxy vs FC on same GPU at equal final photo-RMSE"
 
 
