@@ -85,8 +85,11 @@ typedef struct {
                             Schur complement and Cholesky in double. PBA_MIXED_BF16:
                             as PBA_FP32, except that every pair's pose-pose block
                             sum w J^T J is contracted on BF16 MFMA (sqrt(w) J split
-                            into two bfloat16 terms, FP32 accumulation with Kahan
-                            compensation, FP64 across wavefronts and chunks) */
+                            into three bfloat16 terms hi + mid + lo, every product
+                            of combined order >= 2^-24 kept, FP32 accumulation with
+                            Kahan compensation, FP64 across wavefronts and chunks).
+                            In every precision the target pixel of a residual (warp
+                            and projection) is computed in double */
     int32_t n_levels;    /* image pyramid levels, 1..PBA_MAX_LEVELS */
     int32_t pattern_n;   /* patch pixels per point, 1..PBA_MAX_PATTERN */
     int32_t pattern_uv[2 * PBA_MAX_PATTERN]; /* (du, dv) offsets in level pixels, |du|,|dv| <= 4 */
@@ -94,8 +97,24 @@ typedef struct {
     double damping_rel;  /* diagonal damping relative to the mean diagonal (>= 0) */
     int32_t pinned_frame;/* frame whose pose is held fixed (gauge), or -1 */
     int32_t solver;      /* PBA_SOLVER_CHOL (the Gauss-Newton iterations factor or invert S) */
-    int32_t n_windows;   /* independent problems held by the context; must be 1 */
-    int32_t flags;       /* PBA_FLAG_TIMING: time the residual kernel with HIP events */
+    int32_t n_windows;   /* independent problems (windows) held by the context,
+                            1..PBA_MAX_WINDOWS. With n_windows > 1 (batched form) every
+                            window has its own frames, points, pinned frame (the index
+                            pinned_frame within the window) and damping, all windows
+                            have the same image size and at most 30 frames each, and
+                            they are solved together: one launch per step over all
+                            windows, a block-diagonal reduced system */
+    int32_t flags;       /* PBA_FLAG_TIMING: time the per-iteration residual kernel
+                            with HIP events (read with pba_get_timing; not recorded
+                            while PBA_FLAG_GRAPH replays a graph).
+                            PBA_FLAG_GRAPH: pba_solve captures its whole coarse-to-fine
+                            solve (every level start and max_iters gated iterations)
+                            as one HIP graph on the context's stream at its first
+                            call and replays it on later calls with the same
+                            max_iters and conv_px; the graph is dropped (and captured
+                            again when needed) when points are set, when max_iters
+                            or conv_px change, and when pba_autotune picks a launch
+                            shape. pba_iterate never uses the graph */
     void *stream;        /* hipStream_t to run on, or NULL for a library-owned stream */
 } pba_config;
 
@@ -162,41 +181,60 @@ pba_status pba_config_default(pba_config *cfg);
 /* Create a context on the current HIP device (must be gfx950). Validates *cfg. */
 pba_status pba_create(const pba_config *cfg, pba_ctx **out);
 
-/* Define the frames: n_frames images of width x height pixels
- * (images [F][H][W] float32, row-major), intrinsics [F][4] (fx, fy, cx, cy,
- * level-0 pixels), poses [F][12] world->camera. window must be 0. Resets any
- * points previously set. Width and height must be >= 8 * 2^(n_levels-1). */
+/* Define the frames of window `window` (0..n_windows-1): n_frames images of
+ * width x height pixels (images [F][H][W] float32, row-major), intrinsics [F][4]
+ * (fx, fy, cx, cy, level-0 pixels), poses [F][12] world->camera (Sec. 1: the
+ * SE(3) pose of each frame; frame indices are local to the window). Resets any
+ * points previously set on that window. Width and height must be
+ * >= 8 * 2^(n_levels-1); in a batched context every window has the same size and
+ * at most 30 frames. A batched context assembles its windows on the first call
+ * that needs them. */
 pba_status pba_set_frames(pba_ctx *ctx, int32_t window, int32_t n_frames, int32_t width, int32_t height,
                           const float *images, const double *intrinsics, const double *poses, int32_t mem);
 
-/* Define the points: host_frame [N], host_uv [N][2] (level-0 pixel of the point
- * centre), inv_depth [N] (> 0), and the observing frames in CSR form
- * (obs_ptr [N+1], obs_frame [O]; per point strictly increasing, never the
- * host). These parameters become the starting point of the next level. */
+/* Define the points of window `window` (0..n_windows-1), Sec. 3 eq:energy: host_frame
+ * [N], host_uv [N][2] (level-0 pixel of the point centre), inv_depth [N] (> 0, one
+ * per point, shared by its patch pixels), and the observing frames in CSR form
+ * (obs_ptr [N+1], obs_frame [O]; per point strictly increasing, never the host).
+ * A host frame may have at most 20 distinct target frames. These parameters
+ * become the starting point of the next level. */
 pba_status pba_set_points(pba_ctx *ctx, int32_t window, int32_t n_points, const int32_t *host_frame,
                           const float *host_uv, const double *inv_depth, const int32_t *obs_ptr,
                           const int32_t *obs_frame, int32_t mem);
 
-/* Run exactly n_iters Gauss-Newton iterations on pyramid `level`. If the
- * context's current level differs (or parameters were set since), the level
- * starts over: p(0) := current parameters, usable set frozen, and in IC mode
- * the constant system is built and factorized. stats: n_iters entries or NULL. */
+/* Run exactly n_iters Gauss-Newton iterations on pyramid `level` (all windows).
+ * If the context's current level differs (or parameters were set since), the
+ * level starts over: p(0) := current parameters, usable set frozen, and in IC
+ * mode the constant system of Sec. 3.4-3.5 (proxy Jacobian, W0, H = J^T W0 J, the
+ * depth Schur complement and its factorization) is built once. Each IC iteration
+ * is Sec. 3.5 steps 1-4 (Huber weights at the current residuals, g = J^T W r,
+ * dp = -H^{-1} g) followed by the update equations of Sec. 3.6; each FC iteration
+ * rebuilds J and H at the current parameters and applies R <- exp(dw) R,
+ * t <- t + dt, d <- d + dd (Sec. 1-2). stats: n_iters entries or NULL (statistics
+ * summed over the windows). PBA_E_NUMERIC: the reduced system lost definiteness;
+ * the parameters stay at the last good iterate. */
 pba_status pba_iterate(pba_ctx *ctx, int32_t level, int32_t n_iters, pba_iter_stats *stats);
 
 /* Coarse-to-fine solve: for each level from n_levels-1 down to 0, start the
- * level and iterate until max_disp_px < conv_px (the paper uses 5e-3) or
- * max_iters_per_level iterations. Returns PBA_E_NOT_CONVERGED (with *out
- * filled and parameters updated) if level 0 did not converge. */
+ * level and iterate (as pba_iterate) until max_disp_px < conv_px or
+ * max_iters_per_level iterations. The test is the convergence criterion of
+ * Sec. 4.1 (largest level-0 pixel displacement of the reprojected point centres
+ * caused by one update; the paper uses 5e-3 px); conv_px < 0 runs every
+ * iteration. In a batched context the test applies to all windows together.
+ * Returns PBA_E_NOT_CONVERGED (with *out filled and parameters updated) if level
+ * 0 did not converge. */
 pba_status pba_solve(pba_ctx *ctx, int32_t max_iters_per_level, double conv_px, pba_result *out);
 
 /* Energy / RMSE at the current parameters on `level` over the residuals usable
  * at those parameters (not the frozen set). Fills level, n_active, energy, sq, rmse. */
 pba_status pba_evaluate(pba_ctx *ctx, int32_t level, pba_iter_stats *out);
 
-/* Copy the current parameters out (host memory): poses [F][12], inv_depth [N]. */
+/* Copy the current parameters of window `window` out (host memory): poses [F][12],
+ * inv_depth [N]. */
 pba_status pba_get_params(pba_ctx *ctx, int32_t window, double *poses, double *inv_depth);
 
-/* Overwrite the current parameters (host memory); the next iterate restarts the level. */
+/* Overwrite the current parameters of window `window` (host memory); the next
+ * iterate restarts the level. */
 pba_status pba_set_params(pba_ctx *ctx, int32_t window, const double *poses, const double *inv_depth);
 
 /* Result of pba_autotune: the launch shapes tried for the per-iteration

@@ -112,7 +112,7 @@ class GaussNewton:
             "n_active": n_act,
             "rmse": float(np.sqrt(np.sum(r * r) / max(n_act, 1))),
         }
-        q_old, ok_old = RS.centre_pixels(L, self.poses, self.d)
+        poses_before, d_before = self.poses.copy(), self.d.copy()
         if self.mode == "fc":
             J = RS.fc_jacobian(P, L, self.poses, self.d, q)
             J[~act] = 0.0
@@ -137,10 +137,7 @@ class GaussNewton:
             Rn, tn, dn = G.ic_update(R, t, self.d, R0, self.d0, dth6[:, :3], dth6[:, 3:], dd)
             self.poses = G.pack(Rn, tn)
             self.d = dn
-        q_new, ok_new = RS.centre_pixels(L, self.poses, self.d)
-        ok = ok_old & ok_new
-        disp = np.hypot(q_new[:, 0] - q_old[:, 0], q_new[:, 1] - q_old[:, 1])
-        st["max_disp_px"] = float(np.max(np.where(ok, disp, 0.0))) if ok.size else 0.0
+        st["max_disp_px"] = RS.max_centre_displacement(L, poses_before, d_before, self.poses, self.d)
         st["step_pose"] = float(np.max(np.abs(dth))) if dth.size else 0.0
         st["step_depth"] = float(np.max(np.abs(dd))) if dd.size else 0.0
         self.history.append(st)

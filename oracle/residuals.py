@@ -146,3 +146,15 @@ def centre_pixels(layout, poses, d):
     K = layout.obs_K0t
     q = np.stack([K[:, 0] * v[:, 0] / vzs + K[:, 2], K[:, 1] * v[:, 1] / vzs + K[:, 3]], -1)
     return q, ok
+
+
+def max_centre_displacement(layout, poses_a, d_a, poses_b, d_b):
+    """Convergence measure of Sec. 4.1: the largest change, in level-0 pixels,
+    of the reprojected point centres between parameters a and b, over every
+    observation whose centre lies in front of the target camera under both.
+    The measure does not depend on the pyramid level being iterated."""
+    qa, oka = centre_pixels(layout, poses_a, d_a)
+    qb, okb = centre_pixels(layout, poses_b, d_b)
+    ok = oka & okb
+    disp = np.hypot(qb[:, 0] - qa[:, 0], qb[:, 1] - qa[:, 1])
+    return float(np.max(np.where(ok, disp, 0.0))) if ok.size else 0.0

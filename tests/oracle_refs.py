@@ -47,19 +47,6 @@ def trans_rel_err(P1, P2):
     return np.linalg.norm(t1 - t2, axis=1) / scale
 
 
-def align_scale(P1, d1, P2):
-    """P1 (poses), d1 (inverse depths) rescaled by the single factor that best
-    aligns P1's translations with P2's: frame 0 is pinned, which fixes six of the
-    seven gauge freedoms of the problem; the global scale (all translations times
-    s, all inverse depths over s) is fixed only by the small damping, so results
-    computed with different rounding are compared modulo it."""
-    t1, t2 = P1[:, 9:], P2[:, 9:]
-    s = float(np.sum(t1 * t2) / max(np.sum(t1 * t1), 1e-300))
-    Q = P1.copy()
-    Q[:, 9:] *= s
-    return Q, d1 / s, s
-
-
 def depth_errors_ok(d, d_ref, q99=1e-5, worst=1e-3):
     """Relative inverse-depth agreement of a single-precision result with the
     FP64 oracle: the 99th percentile within q99, every point within `worst`.

@@ -112,3 +112,27 @@ def test_valid_config_without_gpu_reports_device_error():
     cfg = pba.default_config()
     h = C.c_void_p()
     assert pba.pba_create(C.byref(cfg), C.byref(h)) == pba.PBA_E_DEVICE
+
+
+def header_define(name):
+    m = re.search(rf"#define\s+{name}\s+(\d+)", open(HEADER).read())
+    return int(m.group(1))
+
+
+@pytest.mark.parametrize("field,value", [
+    ("n_windows", 1), ("n_windows", 2), ("n_windows", None), ("flags", 1), ("flags", 2), ("flags", 3),
+    ("n_levels", 4), ("pattern_n", 1), ("pinned_frame", -1), ("huber_k", float("inf")), ("damping_rel", 0.0),
+])
+def test_create_accepts_documented_limits(field, value):
+    """Every value the header documents as valid passes validation (without a GPU
+    the call then fails only for the missing device); one past the documented
+    window limit does not."""
+    if os.path.exists("/dev/kfd"):
+        pytest.skip("a GPU is present")
+    assert header_define("PBA_MAX_WINDOWS") == pba.PBA_MAX_WINDOWS
+    cfg = pba.default_config()
+    setattr(cfg, field, pba.PBA_MAX_WINDOWS if value is None else value)
+    h = C.c_void_p()
+    assert pba.pba_create(C.byref(cfg), C.byref(h)) == pba.PBA_E_DEVICE, pba.last_error()
+    cfg.n_windows = pba.PBA_MAX_WINDOWS + 1
+    assert pba.pba_create(C.byref(cfg), C.byref(h)) == pba.PBA_E_INVALID

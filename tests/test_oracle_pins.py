@@ -535,3 +535,108 @@ def test_ic_first_iteration_step_equals_fc_step_on_planar_problem():
     step = np.abs(out["fc"][0][:, 9:] - (sc.poses_gt[:, 9:] + pert)).max()
     diff = np.abs(out["fc"][0] - out["ic"][0]).max()
     assert step > 1e-5 and diff < 0.05 * step, (step, diff)
+
+
+# ---------------------------------------------------------------- convergence test (Sec. 4.1)
+
+
+def _world_point_pixels(scene, poses, d):
+    """Level-0 pixel of every observation's point centre, by another route than
+    the oracle's relative-pose warp: back-project the host pixel at depth 1/d
+    into world coordinates with the host's absolute pose, then project the world
+    point with the target's absolute pose."""
+    N = scene.n_points
+    obs_point = np.repeat(np.arange(N), np.diff(scene.obs_ptr))
+    K = scene.intrinsics
+    h, f = scene.host_frame[obs_point], scene.obs_frame
+    uv = scene.host_uv[obs_point].astype(float)
+    ray = np.stack([(uv[:, 0] - K[h, 2]) / K[h, 0], (uv[:, 1] - K[h, 3]) / K[h, 1], np.ones(len(h))], 1)
+    Xc = ray / d[obs_point][:, None]
+    R = poses[:, :9].reshape(-1, 3, 3)
+    t = poses[:, 9:]
+    Xw = np.einsum("oji,oj->oi", R[h], Xc - t[h])
+    Xf = np.einsum("oij,oj->oi", R[f], Xw) + t[f]
+    return np.stack([K[f, 0] * Xf[:, 0] / Xf[:, 2] + K[f, 2], K[f, 1] * Xf[:, 1] / Xf[:, 2] + K[f, 3]], 1)
+
+
+def _rolled_pattern(scene):
+    """The scene with its patch pattern rotated so that the first pattern pixel
+    is not the point centre (a test that reads a pattern pixel fails)."""
+    scene.pattern = np.roll(scene.pattern, -1, axis=0)
+    assert np.any(scene.pattern[0] != 0)
+    return scene
+
+
+def test_centre_pixels_equal_world_point_projection():
+    """Several hosts, rotated and translated cameras, 3 pyramid levels: the
+    centre pixel of every observation is the level-0 projection of the point's
+    world position, whatever level's layout computes it."""
+    sc = _rolled_pattern(scenes.mid(n_per_host=60))
+    P = Problem.from_scene(sc)
+    rng = np.random.default_rng(8)
+    d = sc.inv_depth_init * (1 + 0.02 * rng.normal(size=sc.n_points))
+    ref = _world_point_pixels(sc, sc.poses_init, d)
+    for level in range(3):
+        q, ok = RS.centre_pixels(P.layout(level), sc.poses_init, d)
+        assert ok.all()
+        np.testing.assert_allclose(q, ref, rtol=0, atol=1e-9)
+
+
+def test_centre_pixels_planar_closed_form():
+    """Planar problem: inverting the image generator's map (host pixel of a
+    target pixel on the plane Z = Z0 under a pure translation t) gives the
+    target pixel of a host pixel as c + ((u_h - c) Z0 + f t_x) / (Z0 + t_z)."""
+    sc = _rolled_pattern(planar(n_levels=3, n_points=30))
+    P = Problem.from_scene(sc)
+    z0 = 1.0 / sc.inv_depth_gt[0]
+    K = sc.intrinsics[0]
+    obs_point = np.repeat(np.arange(sc.n_points), np.diff(sc.obs_ptr))
+    t = sc.poses_gt[sc.obs_frame, 9:]
+    uh = sc.host_uv[obs_point].astype(float)
+    ref = np.stack([K[2] + ((uh[:, 0] - K[2]) * z0 + K[0] * t[:, 0]) / (z0 + t[:, 2]),
+                    K[3] + ((uh[:, 1] - K[3]) * z0 + K[1] * t[:, 1]) / (z0 + t[:, 2])], 1)
+    for level in range(3):
+        q, ok = RS.centre_pixels(P.layout(level), sc.poses_gt, sc.inv_depth_gt)
+        assert ok.all()
+        np.testing.assert_allclose(q, ref, rtol=0, atol=1e-10)
+
+
+def test_max_centre_displacement_of_known_translations():
+    """Planar problem: moving target k by delta_k along x shifts every centre it
+    observes by f delta_k / (Z0 + t_z,k) level-0 pixels (the closed form above
+    is linear in t_x); the measure is the largest of these, at every level."""
+    sc = planar(n_levels=3, n_frames=4, n_points=30)
+    P = Problem.from_scene(sc)
+    z0 = 1.0 / sc.inv_depth_gt[0]
+    f = sc.intrinsics[0, 0]
+    delta = np.array([0.0, 3e-4, -7e-4, 2e-4])
+    moved = sc.poses_gt.copy()
+    moved[:, 9] += delta
+    shift = np.abs(f * delta / (z0 + sc.poses_gt[:, 11]))
+    for level in range(3):
+        m = RS.max_centre_displacement(P.layout(level), sc.poses_gt, sc.inv_depth_gt, moved, sc.inv_depth_gt)
+        np.testing.assert_allclose(m, shift.max(), rtol=1e-9)
+    # a depth change alone moves centres along their epipolar lines: compare
+    # with the world-point route
+    d2 = sc.inv_depth_gt * (1 + 1e-3 * np.arange(sc.n_points) / sc.n_points)
+    ref = np.hypot(*(_world_point_pixels(sc, sc.poses_gt, d2) - _world_point_pixels(sc, sc.poses_gt,
+                                                                                     sc.inv_depth_gt)).T).max()
+    m = RS.max_centre_displacement(P.layout(2), sc.poses_gt, sc.inv_depth_gt, sc.poses_gt, d2)
+    np.testing.assert_allclose(m, ref, rtol=1e-7)
+
+
+@pytest.mark.parametrize("mode", ["fc", "ic"])
+def test_gn_reports_displacement_of_its_own_step(mode):
+    """Every Gauss-Newton iteration reports the largest level-0 displacement of
+    the point centres between the parameters it started from and those it
+    returns (world-point route), at every level of a 2-level solve."""
+    sc = _rolled_pattern(scenes.mid(n_per_host=40))
+    P = Problem.from_scene(sc, n_levels=2)
+    gn = GaussNewton(P, mode)
+    for level in (1, 0):
+        for _ in range(2):
+            before = (gn.poses.copy(), gn.d.copy())
+            st = gn.iterate(level, 1)[0]
+            ref = np.hypot(*(_world_point_pixels(sc, gn.poses, gn.d) - _world_point_pixels(sc, *before)).T).max()
+            assert ref > 1e-4
+            np.testing.assert_allclose(st["max_disp_px"], ref, rtol=1e-7)
