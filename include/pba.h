@@ -70,7 +70,9 @@ typedef enum {
 
 enum { PBA_FC = 0, PBA_IC_PROXY = 1 };                        /* pba_config.mode */
 enum { PBA_FP64 = 0, PBA_FP32 = 1, PBA_MIXED_BF16 = 2 };      /* pba_config.precision */
-enum { PBA_SOLVER_CHOL = 0, PBA_SOLVER_PCG_JACOBI = 1, PBA_SOLVER_PCG_LEARNED = 2 }; /* reduced solvers */
+/* reduced solvers; PBA_SOLVER_PCG_BLOCKOPT: PCG with the blocks that minimize the learned
+ * preconditioner's training loss exactly, P^_i = (I + G_i)^{-1} (the bound of any network) */
+enum { PBA_SOLVER_CHOL = 0, PBA_SOLVER_PCG_JACOBI = 1, PBA_SOLVER_PCG_LEARNED = 2, PBA_SOLVER_PCG_BLOCKOPT = 3 };
 enum { PBA_HOST = 0, PBA_DEVICE = 1 };                        /* memory of input pointers */
 enum { PBA_FLAG_TIMING = 1, PBA_FLAG_GRAPH = 2 };             /* pba_config.flags */
 
@@ -80,16 +82,18 @@ enum { PBA_FLAG_TIMING = 1, PBA_FLAG_GRAPH = 2 };             /* pba_config.flag
 
 typedef struct {
     int32_t mode;        /* PBA_FC or PBA_IC_PROXY */
-    int32_t precision;   /* PBA_FP64: all arithmetic in double. PBA_FP32: residuals,
-                            Jacobians and per-observation blocks in float, reductions,
-                            Schur complement and Cholesky in double. PBA_MIXED_BF16:
-                            as PBA_FP32, except that every pair's pose-pose block
-                            sum w J^T J is contracted on BF16 MFMA (sqrt(w) J split
-                            into three bfloat16 terms hi + mid + lo, every product
-                            of combined order >= 2^-24 kept, FP32 accumulation with
-                            Kahan compensation, FP64 across wavefronts and chunks).
-                            In every precision the target pixel of a residual (warp
-                            and projection) is computed in double */
+    int32_t precision;   /* PBA_FP64: all arithmetic in double. PBA_FP32: images,
+                            template, residuals r, Huber weights and Jacobians in
+                            float; the warp and projection of every patch pixel, the
+                            bilinear interpolant (r is rounded to float once), the
+                            per-observation sums of products (stored as double),
+                            reductions, Schur complement and Cholesky in double.
+                            PBA_MIXED_BF16: as PBA_FP32, except that every pair's
+                            pose-pose block sum w J^T J is contracted on BF16 MFMA:
+                            sqrt(w) J on a fixed-point grid per 64 residuals (three
+                            exact bfloat16 terms), FP32 accumulation that is exact
+                            on that grid, double sums across groups; h and H_dd are
+                            double sums over the same rows */
     int32_t n_levels;    /* image pyramid levels, 1..PBA_MAX_LEVELS */
     int32_t pattern_n;   /* patch pixels per point, 1..PBA_MAX_PATTERN */
     int32_t pattern_uv[2 * PBA_MAX_PATTERN]; /* (du, dv) offsets in level pixels, |du|,|dv| <= 4 */
@@ -148,6 +152,11 @@ typedef struct {
     double residual_ms[PBA_MAX_LEVELS];         /* their summed duration (HIP events on the
                                                    context's stream; needs PBA_FLAG_TIMING) */
     int64_t residuals_processed[PBA_MAX_LEVELS];/* residual slots those launches covered */
+    /* IC on one window with the fused step (solve and depth update in one launch per
+       iteration): launches of that step kernel that did work and their summed duration;
+       0 on the other paths */
+    int64_t step_launches[PBA_MAX_LEVELS];
+    double step_ms[PBA_MAX_LEVELS];
 } pba_timing;
 
 /* Debug / verification buffers for pba_debug_fetch (element type in brackets;
@@ -157,7 +166,7 @@ enum {
                                system assembled (row-major); for 6F > 192 the buffer holds
                                its Cholesky factor (lower triangle) once it has been factored */
     PBA_DBG_B = 2,          /* [double 6F] reduced right-hand side of the last iteration */
-    PBA_DBG_OBS_REC = 3,    /* [real O x 40] per-observation blocks: 0-20 upper triangle of
+    PBA_DBG_OBS_REC = 3,    /* [double O x 40] per-observation blocks: 0-20 upper triangle of
                                sum w J_th^T J_th (row-major), 21-26 sum w J_th J_d, 27 sum w J_d^2,
                                28-33 sum w J_th r, 34 sum w J_d r, 35 energy, 36 sum r^2,
                                37 active count (relative-pose coordinates). IC: the linearization
@@ -315,8 +324,8 @@ pba_status pba_pc_gradient(pba_ctx *ctx, int32_t n_samples, const float *G, doub
 /* FP16 network outputs y [n_samples][21] for the given couplings. */
 pba_status pba_pc_infer(pba_ctx *ctx, int32_t n_samples, const float *G, float *Y);
 /* Solve S x = -b for the context's current reduced system and right-hand side (those of the
- * last iteration) with PBA_SOLVER_CHOL (tiled Cholesky), PBA_SOLVER_PCG_JACOBI or
- * PBA_SOLVER_PCG_LEARNED (relative residual tol, at most max_iters iterations, Cholesky as
+ * last iteration) with PBA_SOLVER_CHOL (tiled Cholesky), PBA_SOLVER_PCG_JACOBI,
+ * PBA_SOLVER_PCG_LEARNED or PBA_SOLVER_PCG_BLOCKOPT (relative residual tol, at most max_iters iterations, Cholesky as
  * the fallback). x_out: host [6F] or NULL. */
 pba_status pba_solve_reduced(pba_ctx *ctx, int32_t solver, double tol, int32_t max_iters, double *x_out,
                              pba_reduced_report *rep);

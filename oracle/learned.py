@@ -142,6 +142,15 @@ def learned_blocks(p, S):
     return np.swapaxes(Ci, 1, 2) @ Ph @ Ci
 
 
+def optimal_blocks(S):
+    """Blocks P_i of M^{-1} at the minimizer of the training loss itself:
+    P^_i = (I + G_i)^{-1}, so P_i = C_i^{-T} (I + G_i)^{-1} C_i^{-1} (the
+    lowest block loss any network output can reach)."""
+    C, Ci, G = block_whitening(S)
+    Ph = np.linalg.inv(np.eye(6)[None] + G)
+    return np.swapaxes(Ci, 1, 2) @ Ph @ Ci
+
+
 def jacobi_blocks(S):
     nb = S.shape[0] // 6
     return np.stack([np.linalg.inv(S[6 * i:6 * i + 6, 6 * i:6 * i + 6]) for i in range(nb)])

@@ -328,14 +328,14 @@ pba_status start_level(Ctx &c, int level, bool clear_flag) {
     if (c.cfg.mode == PBA_IC_PROXY) {
         // J (Sec. 3.4) and W0 at p(0); H = J^T W0 J, depth Schur complement, Cholesky, inverse
         if (is_mixed(c)) {
-            launch_linearize_mixed(s, c, level, true, (const float *)c.d_rel0, true);
+            launch_linearize_mixed(s, c, level, true, c.d_geo0, true);
         } else {
             Launch<T>::ic_linearize(s, c, level);
             Launch<T>::pair_reduce_H(s, c);
         }
         Launch<T>::point_reduce(s, c, true);
         launch_mu(s, c, c.d_geo0);
-        launch_gram(s, c, c.d_geo0, c.d_rec, is_fp64(c));
+        launch_gram(s, c, c.d_geo0, c.d_rec, true);
         launch_assemble_s(s, c, c.d_geo0);
         launch_ic_factor(s, c);
         launch_ic_inverse(s, c);
@@ -354,7 +354,7 @@ template <typename T>
 // statistics slot, finished by this iteration's pair sums; last: the final
 // iteration of the batch, whose end runs as a kernel of its own.
 pba_status one_iteration(Ctx &c, int level, double *stat, hipEvent_t ev0, hipEvent_t ev1, double conv_px,
-                         double *prev_stat, bool last) {
+                         double *prev_stat, bool last, hipEvent_t ev2 = nullptr, hipEvent_t ev3 = nullptr) {
     hipStream_t s = c.stream;
     double *geo_cur = c.flip ? c.d_geo_b : c.d_geo_a;
     double *geo_next = c.flip ? c.d_geo_a : c.d_geo_b;
@@ -362,21 +362,21 @@ pba_status one_iteration(Ctx &c, int level, double *stat, hipEvent_t ev0, hipEve
     T *rel_next = (T *)(c.flip ? c.d_rel_a : c.d_rel_b);
     const bool fused = ic_fused(c);
     if (c.cfg.mode == PBA_IC_PROXY) {
-        Launch<T>::ic_residual(s, c, level, rel_cur, ev0, ev1);
+        Launch<T>::ic_residual(s, c, level, geo_cur, ev0, ev1);
         Launch<T>::pair_reduce_y(s, c, prev_stat, conv_px, level);
         if (fused)
-            launch_ic_step(s, c, c.d_geo0, geo_cur, geo_next, rel_next, is_fp64(c));
+            launch_ic_step(s, c, c.d_geo0, geo_cur, geo_next, rel_next, is_fp64(c), ev2, ev3);
         else
             launch_solve(s, c, c.d_geo0, geo_next, rel_next, is_fp64(c), stat);
     } else {
         if (is_mixed(c))
-            launch_linearize_mixed(s, c, level, false, (const float *)rel_cur, c.iters_in_level == 0, ev0, ev1);
+            launch_linearize_mixed(s, c, level, false, geo_cur, c.iters_in_level == 0, ev0, ev1);
         else
-            Launch<T>::fc_linearize(s, c, level, rel_cur, c.iters_in_level == 0, ev0, ev1);
+            Launch<T>::fc_linearize(s, c, level, geo_cur, c.iters_in_level == 0, ev0, ev1);
         Launch<T>::point_reduce(s, c, true);
         if (!is_mixed(c)) Launch<T>::pair_reduce_H(s, c);
         launch_mu(s, c, geo_cur);
-        launch_gram(s, c, geo_cur, c.d_rec, is_fp64(c));
+        launch_gram(s, c, geo_cur, c.d_rec, true);
         launch_assemble_s(s, c, geo_cur);
         if (c.tiled()) launch_tchol(s, c, false);   // the assembly wrote S into the factor buffer too
         Launch<T>::pair_reduce_y(s, c);
@@ -444,18 +444,19 @@ pba_status run_iterations(Ctx &c, int level, int n_iters, pba_iter_stats *out, d
     pba_status st;
     if ((st = ensure_stats(c, n_iters)) != PBA_OK) return st;
     const bool timing = (c.cfg.flags & PBA_FLAG_TIMING) != 0;
-    if (timing && (st = ensure_events(c, 2 * (size_t)n_iters)) != PBA_OK) return st;
+    if (timing && (st = ensure_events(c, 4 * (size_t)n_iters)) != PBA_OK) return st;
     launch_open(c.stream, c, level, true);
     const int it0 = c.iters_in_level;
     const bool flip0 = c.flip;
     for (int k = 0; k < n_iters; ++k) {
-        hipEvent_t e0 = timing ? c.ev_pool[2 * k] : nullptr, e1 = timing ? c.ev_pool[2 * k + 1] : nullptr;
+        hipEvent_t e0 = timing ? c.ev_pool[4 * k] : nullptr, e1 = timing ? c.ev_pool[4 * k + 1] : nullptr;
+        hipEvent_t e2 = timing ? c.ev_pool[4 * k + 2] : nullptr, e3 = timing ? c.ev_pool[4 * k + 3] : nullptr;
         double *stat = c.d_stats + (size_t)k * ST_STRIDE;
         c.batch_k = k;
         double *prev = k > 0 ? stat - ST_STRIDE : nullptr;
         const bool last = k == n_iters - 1;
-        st = is_fp64(c) ? one_iteration<double>(c, level, stat, e0, e1, conv_px, prev, last)
-                        : one_iteration<float>(c, level, stat, e0, e1, conv_px, prev, last);
+        st = is_fp64(c) ? one_iteration<double>(c, level, stat, e0, e1, conv_px, prev, last, e2, e3)
+                        : one_iteration<float>(c, level, stat, e0, e1, conv_px, prev, last, e2, e3);
         if (st != PBA_OK) return st;
     }
     std::vector<double> hs((size_t)n_iters * ST_STRIDE);
@@ -474,10 +475,15 @@ pba_status run_iterations(Ctx &c, int level, int n_iters, pba_iter_stats *out, d
     if (timing) {
         for (int k = 0; k < n_iters; ++k) {
             float ms = 0.f;
-            HIPCHK(hipEventElapsedTime(&ms, c.ev_pool[2 * k], c.ev_pool[2 * k + 1]));
+            HIPCHK(hipEventElapsedTime(&ms, c.ev_pool[4 * k], c.ev_pool[4 * k + 1]));
             c.t_ms[level] += ms;
             c.t_launches[level]++;
             c.t_res[level] += (int64_t)c.O * LANES_PER_OBS;
+            if (c.cfg.mode == PBA_IC_PROXY && ic_fused(c)) {
+                HIPCHK(hipEventElapsedTime(&ms, c.ev_pool[4 * k + 2], c.ev_pool[4 * k + 3]));
+                c.t_step_ms[level] += ms;
+                c.t_step_launches[level]++;
+            }
         }
     }
     if (out) fill_stats(hs.data(), level, it0, n_iters, out);
@@ -514,12 +520,13 @@ pba_status enqueue_solve(Ctx &c, int max_iters, double conv_px, bool events) {
         for (int k = 0; k < max_iters; ++k) {
             const size_t idx = (size_t)slot * max_iters + k;
             double *stat = c.d_stats + idx * ST_STRIDE;
-            hipEvent_t e0 = events ? c.ev_pool[2 * idx] : nullptr, e1 = events ? c.ev_pool[2 * idx + 1] : nullptr;
+            hipEvent_t e0 = events ? c.ev_pool[4 * idx] : nullptr, e1 = events ? c.ev_pool[4 * idx + 1] : nullptr;
+            hipEvent_t e2 = events ? c.ev_pool[4 * idx + 2] : nullptr, e3 = events ? c.ev_pool[4 * idx + 3] : nullptr;
             double *prev = k > 0 ? stat - ST_STRIDE : nullptr;
             const bool last = k == max_iters - 1;
             c.batch_k = k;
-            st = is_fp64(c) ? one_iteration<double>(c, level, stat, e0, e1, conv_px, prev, last)
-                            : one_iteration<float>(c, level, stat, e0, e1, conv_px, prev, last);
+            st = is_fp64(c) ? one_iteration<double>(c, level, stat, e0, e1, conv_px, prev, last, e2, e3)
+                            : one_iteration<float>(c, level, stat, e0, e1, conv_px, prev, last, e2, e3);
             if (st != PBA_OK) return st;
         }
     }
@@ -532,7 +539,7 @@ pba_status solve_batch(Ctx &c, int max_iters, double conv_px, pba_result &res) {
     if ((st = ensure_stats(c, L * max_iters)) != PBA_OK) return st;
     // residual-kernel timing with HIP events (not inside a captured graph)
     const bool timing = (c.cfg.flags & PBA_FLAG_TIMING) && !(c.cfg.flags & PBA_FLAG_GRAPH);
-    if (timing && (st = ensure_events(c, 2 * (size_t)L * max_iters)) != PBA_OK) return st;
+    if (timing && (st = ensure_events(c, 4 * (size_t)L * max_iters)) != PBA_OK) return st;
     // templates of every level first (they depend on the points only)
     for (int level = 0; level < L; ++level)
         if (!c.lv[level].tmpl_valid) {
@@ -577,10 +584,15 @@ pba_status solve_batch(Ctx &c, int max_iters, double conv_px, pba_result &res) {
             for (int k = 0; k < counts[level]; ++k) {
                 const size_t idx = (size_t)(L - 1 - level) * max_iters + k;
                 float ms = 0.f;
-                HIPCHK(hipEventElapsedTime(&ms, c.ev_pool[2 * idx], c.ev_pool[2 * idx + 1]));
+                HIPCHK(hipEventElapsedTime(&ms, c.ev_pool[4 * idx], c.ev_pool[4 * idx + 1]));
                 c.t_ms[level] += ms;
                 c.t_launches[level]++;
                 c.t_res[level] += (int64_t)c.O * LANES_PER_OBS;
+                if (c.cfg.mode == PBA_IC_PROXY && ic_fused(c)) {
+                    HIPCHK(hipEventElapsedTime(&ms, c.ev_pool[4 * idx + 2], c.ev_pool[4 * idx + 3]));
+                    c.t_step_ms[level] += ms;
+                    c.t_step_launches[level]++;
+                }
             }
     }
     for (int level = L - 1; level >= 0; --level) {
@@ -697,10 +709,72 @@ pba_status load_frames(Ctx &c, int n_frames, int width, int height, const float 
     return PBA_OK;
 }
 
-// Points and observations (global frame indices) and their window partition.
+// Bits of x and y interleaved (x in the even bits): the Z-order of a cell.
+uint64_t morton2(uint32_t x, uint32_t y) {
+    uint64_t m = 0;
+    for (int b = 0; b < 16; ++b) m |= ((uint64_t)((x >> b) & 1u) << (2 * b)) | ((uint64_t)((y >> b) & 1u) << (2 * b + 1));
+    return m;
+}
+
+// Internal order of the points of every window: by host frame, then by the
+// Z-order of the host pixel's 4 x 4-pixel cell (ties in the caller's order).
+// Neighbouring points of a host warp to neighbouring positions of each target,
+// so consecutive observations share texel lines and a contiguous range of
+// points (which the residual kernel maps to one XCD) stays in a compact image
+// region. Returns the caller's index of every internal point.
+std::vector<int> spatial_order(int n_points, const std::vector<int> &hf, const std::vector<float> &uv,
+                               const std::vector<int> &point_off) {
+    std::vector<int> perm(n_points);
+    std::vector<uint64_t> key(n_points);
+    for (int n = 0; n < n_points; ++n) {
+        perm[n] = n;
+        const uint32_t cx = (uint32_t)std::max(0.0f, uv[2 * (size_t)n]) >> 2;
+        const uint32_t cy = (uint32_t)std::max(0.0f, uv[2 * (size_t)n + 1]) >> 2;
+        key[n] = ((uint64_t)(uint32_t)hf[n] << 32) | morton2(cx & 0xffffu, cy & 0xffffu);
+    }
+    for (size_t w = 0; w + 1 < point_off.size(); ++w)
+        std::stable_sort(perm.begin() + point_off[w], perm.begin() + point_off[w + 1],
+                         [&](int a, int b) { return key[a] < key[b]; });
+    return perm;
+}
+
+pba_status load_points_ordered(Ctx &c, int n_points, const std::vector<int> &hf, const std::vector<float> &uv,
+                               const std::vector<double> &d, const std::vector<int> &optr,
+                               const std::vector<int> &ofr, const std::vector<int> &point_off);
+
+// Points and observations (global frame indices, the caller's order) and
+// their window partition: reordered (spatial_order) and loaded.
 pba_status load_points(Ctx &c, int n_points, const std::vector<int> &hf, const std::vector<float> &uv,
                        const std::vector<double> &d, const std::vector<int> &optr, const std::vector<int> &ofr,
                        const std::vector<int> &point_off) {
+    const std::vector<int> perm = spatial_order(n_points, hf, uv, point_off);
+    std::vector<int> hf2(n_points), optr2(n_points + 1, 0), ofr2(ofr.size()), obs_caller(ofr.size());
+    std::vector<float> uv2(2 * (size_t)n_points);
+    std::vector<double> d2(n_points);
+    for (int i = 0; i < n_points; ++i) {
+        const int n = perm[i];
+        hf2[i] = hf[n];
+        uv2[2 * (size_t)i] = uv[2 * (size_t)n];
+        uv2[2 * (size_t)i + 1] = uv[2 * (size_t)n + 1];
+        d2[i] = d[n];
+        int o2 = optr2[i];
+        for (int o = optr[n]; o < optr[n + 1]; ++o, ++o2) {
+            ofr2[o2] = ofr[o];
+            obs_caller[o2] = o;
+        }
+        optr2[i + 1] = o2;
+    }
+    const pba_status st = load_points_ordered(c, n_points, hf2, uv2, d2, optr2, ofr2, point_off);
+    if (st == PBA_OK) {
+        c.pt_caller = perm;
+        c.obs_caller = std::move(obs_caller);
+    }
+    return st;
+}
+
+pba_status load_points_ordered(Ctx &c, int n_points, const std::vector<int> &hf, const std::vector<float> &uv,
+                               const std::vector<double> &d, const std::vector<int> &optr,
+                               const std::vector<int> &ofr, const std::vector<int> &point_off) {
     const long long O = optr[n_points];
     HIPCHK(hipStreamSynchronize(c.stream));
     release_points(c);
@@ -761,7 +835,7 @@ pba_status load_points(Ctx &c, int n_points, const std::vector<int> &hf, const s
     const size_t rs = c.real_size;
     const int Pn = s.n_pairs;
     HIPCHK(dalloc(c.d_mask, std::max<size_t>(1, O)));
-    HIPCHK(dalloc(c.d_rec, (size_t)O * REC_STRIDE * rs));
+    HIPCHK(dalloc(c.d_rec, (size_t)O * REC_STRIDE * sizeof(double)));   // records: FP64 for every element type
     HIPCHK(dalloc(c.d_geo0, (size_t)Pn * GEO_STRIDE * sizeof(double)));
     HIPCHK(dalloc(c.d_geo_a, (size_t)Pn * GEO_STRIDE * sizeof(double)));
     HIPCHK(dalloc(c.d_geo_b, (size_t)Pn * GEO_STRIDE * sizeof(double)));
@@ -828,10 +902,10 @@ pba_status load_points(Ctx &c, int n_points, const std::vector<int> &hf, const s
             HIPCHK(upload(c, c.d_step_sel, sel));
         }
     }
-    HIPCHK(dalloc(c.d_icr, (size_t)O * IC_REC * rs));
+    HIPCHK(dalloc(c.d_icr, (size_t)O * IC_REC * sizeof(double)));
     for (int l = 0; l < c.cfg.n_levels; ++l) {
         HIPCHK(dalloc(c.lv[l].tmpl, (size_t)n_points * c.P * 4 * rs));
-        HIPCHK(dalloc(c.lv[l].pcam, (size_t)std::max(1, Pn) * 8 * rs));
+        HIPCHK(dalloc(c.lv[l].pcam, (size_t)std::max(1, Pn) * 8 * sizeof(double)));
         c.lv[l].tmpl_valid = false;
     }
     HIPCHK(hipGetLastError());
@@ -1224,7 +1298,7 @@ pba_status pba_evaluate(pba_ctx *ctx, int32_t level, pba_iter_stats *out) {
     }
     c.lv[level].tmpl_valid = true;
     if (c.O > 0)
-        launch_sum_stats(s, c, c.d_rec, is_fp64(c), c.d_eval);
+        launch_sum_stats(s, c, c.d_rec, true, c.d_eval);
     else
         launch_fill(s, c.d_eval, 3, 0.0, nullptr);
     double h[3];
@@ -1272,13 +1346,14 @@ pba_status pba_get_params(pba_ctx *ctx, int32_t window, double *poses, double *i
     if (poses)
         HIPCHK(hipMemcpyAsync(poses, c.d_poses + 12 * (size_t)f0, (size_t)(f1 - f0) * 12 * sizeof(double),
                               hipMemcpyDeviceToHost, c.stream));
-    if (inv_depth && c.have_points) {
-        const int n0 = c.win_point_off[window], n1 = c.win_point_off[window + 1];
-        if (n1 > n0)
-            HIPCHK(hipMemcpyAsync(inv_depth, c.d_depth + n0, (size_t)(n1 - n0) * sizeof(double), hipMemcpyDeviceToHost,
-                                  c.stream));
+    std::vector<double> dn;
+    const int n0 = c.have_points ? c.win_point_off[window] : 0, n1 = c.have_points ? c.win_point_off[window + 1] : 0;
+    if (inv_depth && n1 > n0) {
+        dn.resize((size_t)(n1 - n0));
+        HIPCHK(hipMemcpyAsync(dn.data(), c.d_depth + n0, dn.size() * sizeof(double), hipMemcpyDeviceToHost, c.stream));
     }
     HIPCHK(hipStreamSynchronize(c.stream));
+    for (int i = n0; i < n1 && inv_depth; ++i) inv_depth[c.pt_caller[i] - n0] = dn[(size_t)(i - n0)];
     return PBA_OK;
 }
 
@@ -1299,9 +1374,12 @@ pba_status pba_set_params(pba_ctx *ctx, int32_t window, const double *poses, con
     if (poses)
         HIPCHK(hipMemcpyAsync(c.d_poses + 12 * (size_t)f0, poses, (size_t)(f1 - f0) * 12 * sizeof(double),
                               hipMemcpyHostToDevice, c.stream));
-    if (inv_depth && n1 > n0)
-        HIPCHK(hipMemcpyAsync(c.d_depth + n0, inv_depth, (size_t)(n1 - n0) * sizeof(double), hipMemcpyHostToDevice,
-                              c.stream));
+    std::vector<double> dn;
+    if (inv_depth && n1 > n0) {
+        dn.resize((size_t)(n1 - n0));
+        for (int i = n0; i < n1; ++i) dn[(size_t)(i - n0)] = inv_depth[c.pt_caller[i] - n0];
+        HIPCHK(hipMemcpyAsync(c.d_depth + n0, dn.data(), dn.size() * sizeof(double), hipMemcpyHostToDevice, c.stream));
+    }
     HIPCHK(hipStreamSynchronize(c.stream));
     c.cur_level = -1;
     return PBA_OK;
@@ -1319,7 +1397,7 @@ pba_status pba_debug_fetch(pba_ctx *ctx, int32_t what, void *out, size_t bytes) 
     switch (what) {
         case PBA_DBG_S: src = c.d_S; need = (size_t)c.win_S_off[c.nwin] * sizeof(double); break;
         case PBA_DBG_B: src = c.d_b; need = n6 * sizeof(double); break;
-        case PBA_DBG_OBS_REC: src = c.d_rec; need = (size_t)c.O * REC_STRIDE * c.real_size; break;
+        case PBA_DBG_OBS_REC: src = c.d_rec; need = (size_t)c.O * REC_STRIDE * sizeof(double); break;
         case PBA_DBG_TEMPLATE: {
             const int l = c.cur_level < 0 ? 0 : c.cur_level;
             src = c.lv[l].tmpl;
@@ -1343,8 +1421,21 @@ pba_status pba_debug_fetch(pba_ctx *ctx, int32_t what, void *out, size_t bytes) 
         default: return fail(&c, PBA_E_INVALID, "unknown debug buffer");
     }
     if (bytes != need) return fail(&c, PBA_E_INVALID, "bytes must be " + std::to_string(need));
-    if (need) HIPCHK(hipMemcpyAsync(out, src, need, hipMemcpyDeviceToHost, c.stream));
+    // per-point and per-observation buffers go back to the caller's order
+    const std::vector<int> *rows = nullptr;
+    if (what == PBA_DBG_OBS_REC || what == PBA_DBG_MASK) rows = &c.obs_caller;
+    if (what == PBA_DBG_TEMPLATE || what == PBA_DBG_HDD) rows = &c.pt_caller;
+    if (!rows || need == 0) {
+        if (need) HIPCHK(hipMemcpyAsync(out, src, need, hipMemcpyDeviceToHost, c.stream));
+        HIPCHK(hipStreamSynchronize(c.stream));
+        return PBA_OK;
+    }
+    std::vector<char> tmp(need);
+    HIPCHK(hipMemcpyAsync(tmp.data(), src, need, hipMemcpyDeviceToHost, c.stream));
     HIPCHK(hipStreamSynchronize(c.stream));
+    const size_t row = need / rows->size();
+    char *o = static_cast<char *>(out);
+    for (size_t i = 0; i < rows->size(); ++i) std::memcpy(o + (size_t)(*rows)[i] * row, tmp.data() + i * row, row);
     return PBA_OK;
 }
 
@@ -1368,18 +1459,18 @@ pba_status pba_autotune(pba_ctx *ctx, int32_t level, int32_t reps, pba_tune_repo
     if (ic) cand.push_back({1024, 0});
     if ((st = ensure_events(c, 2)) != PBA_OK) return st;
     hipEvent_t e0 = c.ev_pool[0], e1 = c.ev_pool[1];
-    const void *rel = c.flip ? c.d_rel_b : c.d_rel_a;
+    const double *geo = c.flip ? c.d_geo_b : c.d_geo_a;
     auto launch = [&](LaunchShape sh) {
         if (ic) {
             if (is_fp64(c))
-                Launch<double>::ic_residual_shape(c.stream, c, level, (const double *)rel, sh);
+                Launch<double>::ic_residual_shape(c.stream, c, level, geo, sh);
             else
-                Launch<float>::ic_residual_shape(c.stream, c, level, (const float *)rel, sh);
+                Launch<float>::ic_residual_shape(c.stream, c, level, geo, sh);
         } else {
             if (is_fp64(c))
-                Launch<double>::fc_linearize_shape(c.stream, c, level, (const double *)rel, sh);
+                Launch<double>::fc_linearize_shape(c.stream, c, level, geo, sh);
             else
-                Launch<float>::fc_linearize_shape(c.stream, c, level, (const float *)rel, sh);
+                Launch<float>::fc_linearize_shape(c.stream, c, level, geo, sh);
         }
     };
     launch_open(c.stream, c, level, true);
@@ -1603,7 +1694,8 @@ pba_status pba_solve_reduced(pba_ctx *ctx, int32_t solver, double tol, int32_t m
                              pba_reduced_report *rep) {
     if (!ctx) return fail(nullptr, PBA_E_INVALID, "ctx is NULL");
     Ctx &c = ctx->c;
-    if (solver != PBA_SOLVER_CHOL && solver != PBA_SOLVER_PCG_JACOBI && solver != PBA_SOLVER_PCG_LEARNED)
+    if (solver != PBA_SOLVER_CHOL && solver != PBA_SOLVER_PCG_JACOBI && solver != PBA_SOLVER_PCG_LEARNED &&
+        solver != PBA_SOLVER_PCG_BLOCKOPT)
         return fail(&c, PBA_E_INVALID, "unknown solver");
     if (!(tol > 0.0) || max_iters < 1) return fail(&c, PBA_E_INVALID, "tol must be > 0 and max_iters >= 1");
     pba_status st;
@@ -1643,6 +1735,8 @@ pba_status pba_solve_reduced(pba_ctx *ctx, int32_t solver, double tol, int32_t m
         if (solver == PBA_SOLVER_PCG_LEARNED) {
             pc_infer(s, c, nb, c.pc.X, c.pc.Y);
             pc_blocks(s, c, nb, c.pc.Y);
+        } else if (solver == PBA_SOLVER_PCG_BLOCKOPT) {
+            pc_blocks_opt(s, c, nb);
         } else {
             pc_blocks(s, c, nb, nullptr);
         }
@@ -1705,9 +1799,13 @@ pba_status pba_get_timing(pba_ctx *ctx, pba_timing *out) {
         out->residual_launches[l] = c.t_launches[l];
         out->residual_ms[l] = c.t_ms[l];
         out->residuals_processed[l] = c.t_res[l];
+        out->step_launches[l] = c.t_step_launches[l];
+        out->step_ms[l] = c.t_step_ms[l];
         c.t_launches[l] = 0;
         c.t_ms[l] = 0.0;
         c.t_res[l] = 0;
+        c.t_step_launches[l] = 0;
+        c.t_step_ms[l] = 0.0;
     }
     return PBA_OK;
 }

@@ -58,7 +58,7 @@ __device__ __forceinline__ DepthPoint depth_point(int N, int n0, const int *__re
 template <typename T, int NT>
 __device__ __forceinline__ bool depth_points(
     int N, int n0, int ic, const DepthPoint &pt, const int *__restrict__ obs_pair,
-    const double *__restrict__ pairK0, const T *__restrict__ rec, const T *__restrict__ gr, int gs,
+    const double *__restrict__ pairK0, const double *__restrict__ rec, const double *__restrict__ gr, int gs,
     const double *dth_rel, const double *__restrict__ geo_old, const double *geo_new, double *__restrict__ depth,
     const int *gate, const int *flag, double *lds, double &mdisp_out, double &mstep_out) {
     constexpr int NPTS = NT / DU_SLOTS, NW = NT / 64;
@@ -78,7 +78,7 @@ __device__ __forceinline__ bool depth_points(
     // g_d,n and h_n^T dtheta, slot-parallel over the point's observations
     double s = 0.0, g = 0.0;
     for (int o = o0 + slot; o < o1; o += DU_SLOTS) {
-        const T *r = rec + (size_t)o * REC_STRIDE;
+        const double *r = rec + (size_t)o * REC_STRIDE;
         const double *dr = dth_rel + 6 * obs_pair[o];
         g += (double)gr[(size_t)o * gs + GR_GD];
         for (int k = 0; k < 6; ++k) s += (double)r[REC_h + k] * dr[k];

@@ -20,22 +20,31 @@ __device__ __forceinline__ bool usable(T u, T v, int W, int H) {
 }
 
 // Bilinear interpolation of a row-major image at (u, v) (Notation: image
-// functions are bilinear interpolants of the pixel grid).
-template <typename T>
-__device__ __forceinline__ T bilinear(const T *__restrict__ im, int W, T u, T v) {
+// functions are bilinear interpolants of the pixel grid), formed in FP64 from
+// the image's texels for every element type. The position comes in T or in
+// FP64 (P) and the cell is found in P. In FP64 the interpolant of FP32 texels
+// at an FP64 position is exact to rounding, so the single-precision paths
+// round the residual r = I0 - I once, at the end (to 1e-9 for |r| ~ 0.01),
+// where an FP32 interpolation would carry ~1e-7 of rounding, and an FP32
+// pixel coordinate near 600 another ~3e-5 px times the gradient.
+template <typename T, typename P>
+__device__ __forceinline__ double bilinear(const T *__restrict__ im, int W, P u, P v) {
     const int j0 = (int)floor(u), i0 = (int)floor(v);
-    const T a = u - T(j0), b = v - T(i0);
+    const double a = (double)u - (double)j0, b = (double)v - (double)i0;
     const T *r0 = im + (size_t)i0 * W + j0;
     const T *r1 = r0 + W;
-    return (T(1) - a) * (T(1) - b) * r0[0] + a * (T(1) - b) * r0[1] + (T(1) - a) * b * r1[0] + a * b * r1[1];
+    return (1.0 - a) * (1.0 - b) * (double)r0[0] + a * (1.0 - b) * (double)r0[1] + (1.0 - a) * b * (double)r1[0] +
+           a * b * (double)r1[1];
 }
 
 // Intensity and gradient at (u, v): the gradient is the central difference on
 // the grid, bilinearly interpolated between the four surrounding pixel centres.
-template <typename T>
-__device__ __forceinline__ void bilinear_grad(const T *__restrict__ im, int W, T u, T v, T &I, T &gu, T &gv) {
+// The intensity as in bilinear (FP64); the gradient in T (it enters J only).
+template <typename T, typename P>
+__device__ __forceinline__ void bilinear_grad(const T *__restrict__ im, int W, P u, P v, double &I, T &gu, T &gv) {
     const int j0 = (int)floor(u), i0 = (int)floor(v);
-    const T a = u - T(j0), b = v - T(i0);
+    const double ad = (double)u - (double)j0, bd = (double)v - (double)i0;
+    const T a = (T)ad, b = (T)bd;
     const T *rm = im + (size_t)(i0 - 1) * W + j0;  // row i0-1
     const T *r0 = rm + W;
     const T *r1 = r0 + W;
@@ -46,7 +55,8 @@ __device__ __forceinline__ void bilinear_grad(const T *__restrict__ im, int W, T
     const T gv00 = T(0.5) * (r1[0] - rm[0]), gv01 = T(0.5) * (r1[1] - rm[1]);
     const T gv10 = T(0.5) * (r2[0] - r0[0]), gv11 = T(0.5) * (r2[1] - r0[1]);
     const T w00 = (T(1) - a) * (T(1) - b), w01 = a * (T(1) - b), w10 = (T(1) - a) * b, w11 = a * b;
-    I = w00 * i00 + w01 * i01 + w10 * i10 + w11 * i11;
+    I = (1.0 - ad) * (1.0 - bd) * (double)i00 + ad * (1.0 - bd) * (double)i01 + (1.0 - ad) * bd * (double)i10 +
+        ad * bd * (double)i11;
     gu = w00 * gu00 + w01 * gu01 + w10 * gu10 + w11 * gu11;
     gv = w00 * gv00 + w01 * gv01 + w10 * gv10 + w11 * gv11;
 }
@@ -401,11 +411,29 @@ __device__ __forceinline__ double bcast8(double v) {
     return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
-// out[k] = component k % 4 of lane k / 4's slice, for k < 4 * 8 (every lane of
-// a group of 8 gets the group's 32 values).
-template <typename T, typename V, int... K>
-__device__ __forceinline__ void bcast8_slices(const V &sl, T *out, std::integer_sequence<int, K...>) {
-    ((out[K] = bcast8<K / 4>((T)sl[K % 4])), ...);
+// Words of 16-byte slices spread over a group of 8 lanes, read by every lane
+// of the group: lane l of the group holds slice l in s0 and slice l + 8 in s1;
+// out[k] = word k % 4 of slice k / 4 (ds_swizzle in bit-mask mode, as bcast8).
+template <typename V, int... K>
+__device__ __forceinline__ void bcast8_words(const V &s0, const V &s1, int *out, std::integer_sequence<int, K...>) {
+    ((out[K] = __builtin_amdgcn_ds_swizzle(K < 32 ? s0[K % 4] : s1[K % 4], 0x18 | (((K / 4) % 8) << 5))), ...);
+}
+
+// Words B + k of the same layout, into out[B + k].
+template <int B, typename V, int... K>
+__device__ __forceinline__ void bcast8_words_range(const V &s0, const V &s1, int *out,
+                                                   std::integer_sequence<int, K...>) {
+    ((out[B + K] = __builtin_amdgcn_ds_swizzle((B + K) < 32 ? s0[(B + K) % 4] : s1[(B + K) % 4],
+                                               0x18 | ((((B + K) / 4) % 8) << 5))),
+     ...);
+}
+
+// Words B + k of the same slice layout, all from s1 (slices 8 and up): out[k]
+// = word (B + k) % 4 of slice (B + k) / 4.
+template <int B, typename V, int... K>
+__device__ __forceinline__ void bcast8_words_from(const V &s1, int *out, std::integer_sequence<int, K...>) {
+    static_assert(B >= 32, "words of the second slice register");
+    ((out[K] = __builtin_amdgcn_ds_swizzle(s1[(B + K) % 4], 0x18 | ((((B + K) / 4) % 8) << 5))), ...);
 }
 
 }  // namespace pba

@@ -107,7 +107,7 @@ struct LevelDev {
     void *img = nullptr;      // T [F][H][W]
     void *K = nullptr;        // T [F][4] level intrinsics
     void *tmpl = nullptr;     // T [N][P][4] (I0, gu, gv, usable) at the host patch pixels
-    void *pcam = nullptr;     // T [Pn][8] host and target intrinsics of every pair
+    void *pcam = nullptr;     // double [Pn][8] host and target level intrinsics of every pair
     bool tmpl_valid = false;
 };
 
@@ -160,6 +160,10 @@ struct Ctx {
     // windows (host copies of the offsets; see WinArgs)
     int nwin = 1;
     std::vector<int> win_frame_off, win_point_off, win_pair_off, win_S_off, win_L_off;
+    // internal order of points and observations (see load_points): internal
+    // point i is the caller's point pt_caller[i] (global, windows after one
+    // another), internal observation o the caller's observation obs_caller[o]
+    std::vector<int> pt_caller, obs_caller;
     int *d_win_frame_off = nullptr, *d_win_pair_off = nullptr, *d_win_point_off = nullptr, *d_win_S_off = nullptr,
         *d_win_L_off = nullptr, *d_frame_win = nullptr, *d_point_win = nullptr;
     double *d_wstat = nullptr;                         // [nwin][4] per-window E, SQ, CNT, max pose step
@@ -189,8 +193,8 @@ struct Ctx {
         *d_pchunk_begin = nullptr, *d_pchunk_end = nullptr, *d_pair_chunk_ptr = nullptr;
     float *d_host_uv = nullptr;                        // [N][2]
     uint8_t *d_mask = nullptr;                         // [O]
-    void *d_rec = nullptr;                             // T [O][REC_STRIDE]
-    void *d_icr = nullptr;                             // T [O][IC_REC] gradient records of the IC iterations
+    void *d_rec = nullptr;                             // double [O][REC_STRIDE]
+    void *d_icr = nullptr;                             // double [O][IC_REC] gradient records of the IC iterations
     double *d_geo0 = nullptr, *d_geo_a = nullptr, *d_geo_b = nullptr;   // [Pn][GEO_STRIDE]
     void *d_rel0 = nullptr, *d_rel_a = nullptr, *d_rel_b = nullptr;      // T [Pn][REL_STRIDE]
     double *d_pairH = nullptr;                         // [Pn][21]
@@ -239,6 +243,8 @@ struct Ctx {
     std::vector<hipEvent_t> ev_pool;
     int64_t t_launches[PBA_MAX_LEVELS] = {0, 0, 0, 0}, t_res[PBA_MAX_LEVELS] = {0, 0, 0, 0};
     double t_ms[PBA_MAX_LEVELS] = {0.0, 0.0, 0.0, 0.0};
+    int64_t t_step_launches[PBA_MAX_LEVELS] = {0, 0, 0, 0};
+    double t_step_ms[PBA_MAX_LEVELS] = {0.0, 0.0, 0.0, 0.0};
 };
 
 // ---- kernel launchers (pba_kernels.hip); T selects float or double.
@@ -252,12 +258,12 @@ template <typename T> struct Launch {
     // e0 / e1 (optional): events recorded by the dispatch itself at the kernel's start and end
     // level start: gate / flag / count, p(0) copies, relative poses at p(0) (one launch)
     static void level_begin(hipStream_t s, Ctx &c, int level, bool clear_flag);
-    static void ic_residual(hipStream_t s, Ctx &c, int level, const T *rel_cur, hipEvent_t e0 = nullptr,
+    static void ic_residual(hipStream_t s, Ctx &c, int level, const double *geo_cur, hipEvent_t e0 = nullptr,
                             hipEvent_t e1 = nullptr);
-    static void ic_residual_shape(hipStream_t s, Ctx &c, int level, const T *rel_cur, LaunchShape sh,
+    static void ic_residual_shape(hipStream_t s, Ctx &c, int level, const double *geo_cur, LaunchShape sh,
                                   hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
-    static void fc_linearize_shape(hipStream_t s, Ctx &c, int level, const T *rel_cur, LaunchShape sh);
-    static void fc_linearize(hipStream_t s, Ctx &c, int level, const T *rel_cur, bool write_mask,
+    static void fc_linearize_shape(hipStream_t s, Ctx &c, int level, const double *geo_cur, LaunchShape sh);
+    static void fc_linearize(hipStream_t s, Ctx &c, int level, const double *geo_cur, bool write_mask,
                              hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
     static void evaluate(hipStream_t s, Ctx &c, int level);
     static void point_reduce(hipStream_t s, Ctx &c, bool with_hdd);
@@ -274,6 +280,7 @@ template <typename T> struct Launch {
 void pc_whiten(hipStream_t s, Ctx &c, int nb);                      // C_i^{-1}, G_i, features of S
 void pc_infer(hipStream_t s, Ctx &c, int m, const float *X, float *Y);
 void pc_blocks(hipStream_t s, Ctx &c, int nb, const float *Y);      // Y = nullptr: block Jacobi
+void pc_blocks_opt(hipStream_t s, Ctx &c, int nb);                 // P^ = (I + G_i)^{-1}
 void pc_to_half(hipStream_t s, Ctx &c);
 void pc_features(hipStream_t s, int m, const float *G, float *X);
 void pc_gather(hipStream_t s, int m, const int *idx, const float *src, int width, float *dst);
@@ -286,7 +293,7 @@ void pc_resid(hipStream_t s, Ctx &c, int n, const double *x, double *part);   //
 void launch_tsolve(hipStream_t s, Ctx &c, const double *b, double *x);        // x = -S^{-1} b, tiled factor
 
 // mixed precision linearization (pair order, BF16 MFMA pose blocks into the pair chunk partials)
-void launch_linearize_mixed(hipStream_t s, Ctx &c, int level, bool ic, const float *rel_cur, bool write_mask,
+void launch_linearize_mixed(hipStream_t s, Ctx &c, int level, bool ic, const double *geo_cur, bool write_mask,
                             hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 
 // precision-independent launchers (double only)
@@ -305,7 +312,7 @@ void launch_conv(hipStream_t s, Ctx &c, double *stat, double conv_px, int nparts
 // depth step of an iteration run as one kernel (launch_ic_step).
 bool ic_fused(const Ctx &c);
 void launch_ic_step(hipStream_t s, Ctx &c, const double *geo_lin, const double *geo_old, double *geo_next,
-                    void *rel_next, bool rel_double);
+                    void *rel_next, bool rel_double, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 int du_nparts(const Ctx &c);   // blocks of the depth step (parts of its convergence maxima)
 // count[level] = 0, optionally flag = 0, then gate = (flag == 0)
 void launch_open(hipStream_t s, Ctx &c, int level, bool clear_flag);

@@ -51,16 +51,17 @@ __global__ void k_level_K(const double *__restrict__ K0, T *__restrict__ K, int 
     K[4 * f + 3] = (T)((K0[4 * f + 3] + 0.5) * s - 0.5);
 }
 
-// Level intrinsics of every pair's host and target frames, side by side, so
-// that a residual reads its camera data with its pair index alone.
-template <typename T>
+// Level intrinsics (FP64, every element type) of every pair's host and target
+// frames, side by side, so that a residual reads its camera data with its pair
+// index alone: f / 2^l and (c + 0.5) / 2^l - 0.5 from the level-0 values.
 __global__ void k_pair_cam(int Pn, const int *__restrict__ pair_host, const int *__restrict__ pair_target,
-                           const T *__restrict__ K, T *__restrict__ pcam) {
+                           const double *__restrict__ K0, int level, double *__restrict__ pcam) {
     const int e = blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= Pn * 8) return;
     const int p = e >> 3, k = e & 7;
     const int f = k < 4 ? pair_host[p] : pair_target[p];
-    pcam[e] = K[4 * f + (k & 3)];
+    const double s = 1.0 / (double)(1 << level), k0 = K0[4 * f + (k & 3)];
+    pcam[e] = (k & 3) < 2 ? k0 * s : (k0 + 0.5) * s - 0.5;
 }
 
 // Template data at every host patch pixel: I0, the interpolated central-difference
@@ -76,7 +77,9 @@ __global__ void k_template(int N, int P, PatternArg pat, const float *__restrict
     const T v = ((T)host_uv[2 * n + 1] + T(0.5)) * scale - T(0.5) + (T)pat.dv[j];
     T I = 0, gu = 0, gv = 0, ok = 0;
     if (usable(u, v, W, H)) {
-        bilinear_grad(img + (size_t)host_frame[n] * W * H, W, u, v, I, gu, gv);
+        double Id;
+        bilinear_grad(img + (size_t)host_frame[n] * W * H, W, u, v, Id, gu, gv);
+        I = (T)Id;
         ok = 1;
     }
     tmpl[4 * idx + 0] = I;
@@ -156,28 +159,33 @@ template <typename T>
 struct ResArgs {
     int O, P, W, H;
     PatternArg pat;
-    T scale;             // 1 / 2^level
+    double scale;        // 1 / 2^level
     T huber_k;
     const int *obs_point, *obs_pair, *pair_host, *pair_target;
     const float *host_uv;
     const T *img;        // level image stack
-    const T *K;          // level intrinsics [F][4]
     const T *tmpl;       // [N][P][4]
-    const T *rel;        // current relative poses
-    const T *rel0;       // relative poses at p(0) (IC)
+    const double *geo;   // current pair geometry [Pn][GEO_STRIDE]: relative R, t; host t
+    const T *rel0;       // relative poses at p(0) (IC Jacobian)
     const double *depth, *depth0;
     uint8_t *mask;
-    T *rec;
-    const T *pcam;       // per pair: host and target level intrinsics (fx, fy, cx, cy) x 2
-    T *icr;              // IC iterations: per observation g (6), g_d, energy, sum r^2, count
+    double *rec;         // per-observation records (FP64 for every element type)
+    const double *pcam;  // per pair: host and target level intrinsics (fx, fy, cx, cy) x 2
+    double *icr;         // IC iterations: per observation g (6), g_d, energy, sum r^2, count (FP64)
     const int *gate;     // device flag: 0 = the solve has converged, skip the work
 };
 
-// Normalized template coordinates of patch pixel j of point n (host intrinsics).
+// Normalized template coordinates of patch pixel j of point n (host
+// intrinsics). The warp of every element type runs in FP64: single-precision
+// pixel coordinates near 600 carry 3e-5 px of rounding, which moves r by the
+// image gradient times that (and the inverse depths of weakly constrained
+// points by 1e-5 relative and more); only the sampled intensities, J and the
+// sums run in the element type.
 template <typename T>
-__device__ __forceinline__ void template_xy(const ResArgs<T> &a, int n, int j, const T *Kh, T &x, T &y) {
-    const T u = ((T)a.host_uv[2 * n] + T(0.5)) * a.scale - T(0.5) + (T)a.pat.du[j];
-    const T v = ((T)a.host_uv[2 * n + 1] + T(0.5)) * a.scale - T(0.5) + (T)a.pat.dv[j];
+__device__ __forceinline__ void template_xy(const ResArgs<T> &a, int n, int j, const double *Kh, double &x,
+                                            double &y) {
+    const double u = ((double)a.host_uv[2 * n] + 0.5) * a.scale - 0.5 + (double)a.pat.du[j];
+    const double v = ((double)a.host_uv[2 * n + 1] + 0.5) * a.scale - 0.5 + (double)a.pat.dv[j];
     x = (u - Kh[2]) / Kh[0];
     y = (v - Kh[3]) / Kh[1];
 }
@@ -195,50 +203,80 @@ __device__ __forceinline__ bool lin_eval(const ResArgs<T> &a, int o, int j, int 
     if (o < 0 || o >= a.O || j >= a.P) return false;
     const int n = a.obs_point[o], pr = a.obs_pair[o];
     const int f = a.pair_target[pr];
-    const T *Kh = a.pcam + 8 * pr;   // the pair's host and target intrinsics (one load step fewer than K[frame])
-    const T *Kt = Kh + 4;
+    const double *Kh = a.pcam + 8 * pr;   // the pair's host and target intrinsics (one load step fewer than K[frame])
+    const double *Kt = Kh + 4;
     const T *tp = a.tmpl + 4 * ((size_t)n * a.P + j);
     const T I0 = tp[0], gu0 = tp[1], gv0 = tp[2];
     const bool host_ok = tp[3] != T(0);
     bool frozen = true;
     if (!write_mask) frozen = (a.mask[o] >> j) & 1;
-    T x, y;
+    double x, y;
     template_xy(a, n, j, Kh, x, y);
-    const T *R = a.rel + REL_STRIDE * pr;
-    const T *t = R + 9;
-    const T d = (T)a.depth[n];
-    const T Rx0 = R[0] * x + R[1] * y + R[2];
-    const T Rx1 = R[3] * x + R[4] * y + R[5];
-    const T Rx2 = R[6] * x + R[7] * y + R[8];
-    const T vx = Rx0 + d * t[0], vy = Rx1 + d * t[1], vz = Rx2 + d * t[2];
-    if (!(host_ok && frozen && d > T(0) && vz > T(0))) return false;
-    const T ux = vx / vz, uy = vy / vz;
-    const T qu = Kt[0] * ux + Kt[2], qv = Kt[1] * uy + Kt[3];
+    const double *R = a.geo + GEO_STRIDE * pr;
+    const double *t = R + 9;
+    const double d = a.depth[n];
+    const double Rx0 = R[0] * x + R[1] * y + R[2];
+    const double Rx1 = R[3] * x + R[4] * y + R[5];
+    const double Rx2 = R[6] * x + R[7] * y + R[8];
+    const double vx = Rx0 + d * t[0], vy = Rx1 + d * t[1], vz = Rx2 + d * t[2];
+    if (!(host_ok && frozen && d > 0.0 && vz > 0.0)) return false;
+    const double ux = vx / vz, uy = vy / vz;
+    const double qu = Kt[0] * ux + Kt[2], qv = Kt[1] * uy + Kt[3];
     if (!usable(qu, qv, a.W, a.H)) return false;
     const T *imf = a.img + (size_t)f * a.W * a.H;
-    T If, gu, gv;
+    double If;
+    T gu, gv;
     if (IC) {
         If = bilinear(imf, a.W, qu, qv);
         const T *R0 = a.rel0 + REL_STRIDE * pr;
-        ic_jacobian(x, y, R0, R0 + 9, (T)a.depth0[n], gu0, gv0, Kh[0], Kh[1], J);
+        ic_jacobian((T)x, (T)y, R0, R0 + 9, (T)a.depth0[n], gu0, gv0, (T)Kh[0], (T)Kh[1], J);
     } else {
         bilinear_grad(imf, a.W, qu, qv, If, gu, gv);
-        fc_jacobian(Rx0, Rx1, Rx2, vz, ux, uy, t, d, gu, gv, Kt[0], Kt[1], J);
+        const T tt[3] = {(T)t[0], (T)t[1], (T)t[2]};
+        fc_jacobian((T)Rx0, (T)Rx1, (T)Rx2, (T)vz, (T)ux, (T)uy, tt, (T)d, gu, gv, (T)Kt[0], (T)Kt[1], J);
     }
-    r = I0 - If;
+    r = (T)((double)I0 - If);   // rounded once (bilinear)
     huber(r, a.huber_k, w, rho);
     return true;
 }
 
+// Tile of the i-th workgroup in an XCD-aware order. Workgroups are dispatched
+// to the 8 XCDs in turn (workgroup i to XCD i mod 8), and each XCD has its own
+// L2; this bijection of [0, ntiles) gives XCD x one contiguous range of tiles
+// (ntiles / 8 of them, one more for the first ntiles mod 8 XCDs), so that
+// neighbouring observations (points are stored in a spatial order) meet in
+// one L2.
+__device__ __forceinline__ int xcd_tile(int i, int ntiles) {
+    const int q = ntiles >> 3, r = ntiles & 7, x = i & 7;
+    return x * q + min(x, r) + (i >> 3);
+}
+
+// Sum over an observation's 8 lanes of a per-residual product, in FP64 for
+// every element type, into the field slot that lane j of the observation
+// stores (fields p with p % 8 == j, slot p / 8). Single-precision products and
+// sums would round the pose block, h and H_dd of an observation independently
+// (a few units in the last place of each), which breaks the consistency of the
+// depth Schur complement and moves the FP32 iterates by up to 1e-5 relative;
+// from FP64 sums the record is rounded to T once. The empty asm keeps the
+// compiler from fusing the product into the first addition, so that every
+// lane of the group ends with the same sum.
+template <int NS>
+__device__ __forceinline__ void obs_sum_field(double (&mine)[NS], int j, int p, double v) {
+    pin_reg(v);
+    v = wave_sum8(v);
+    mine[p >> 3] = (j == (p & 7)) ? v : mine[p >> 3];
+}
+
 // Linearization in observation order: the 38-value record of every
-// observation (lane j == 0 writes it). NB threads per workgroup (NB / 8
-// observations per tile); the grid strides over the tiles, so that it can be
-// launched one tile per workgroup or as a persistent grid.
+// observation (lane j stores fields j, j + 8, ...). NB threads per workgroup
+// (NB / 8 observations per tile); the grid strides over the tiles, so that it
+// can be launched one tile per workgroup or as a persistent grid.
 template <typename T, bool IC, int NB>
 __global__ __launch_bounds__(NB) void k_linearize(ResArgs<T> a, int write_mask) {
     if (*a.gate == 0) return;
     const int ntiles = (a.O + NB / 8 - 1) / (NB / 8);
-    for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    for (int it = blockIdx.x; it < ntiles; it += gridDim.x) {
+        const int tile = xcd_tile(it, ntiles);
         const int gid = tile * NB + threadIdx.x;
         const int o = gid >> 3, j = gid & 7;
         T J[7], r, w, rho;
@@ -247,22 +285,26 @@ __global__ __launch_bounds__(NB) void k_linearize(ResArgs<T> a, int write_mask) 
             const unsigned long long bal = __ballot(valid);
             if (j == 0 && o < a.O) a.mask[o] = (uint8_t)((bal >> (threadIdx.x & 56)) & 0xFFull);
         }
-        T v[38];
+        double mine[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+        const double wd = (double)w;
         int k = 0;
+#pragma unroll
         for (int p = 0; p < 6; ++p)
-            for (int q = p; q < 6; ++q) v[k++] = w * J[p] * J[q];
-        for (int p = 0; p < 6; ++p) v[21 + p] = w * J[p] * J[6];
-        v[27] = w * J[6] * J[6];
-        for (int p = 0; p < 7; ++p) v[28 + p] = w * J[p] * r;
-        v[35] = valid ? rho : T(0);
-        v[36] = valid ? r * r : T(0);
-        v[37] = valid ? T(1) : T(0);
 #pragma unroll
-        for (int p = 0; p < 38; ++p) v[p] = wave_sum8(v[p]);
-        if (j == 0 && o < a.O) {
-            T *rec = a.rec + (size_t)o * REC_STRIDE;
+            for (int q = p; q < 6; ++q) obs_sum_field(mine, j, k++, wd * J[p] * J[q]);
 #pragma unroll
-            for (int p = 0; p < 38; ++p) rec[p] = v[p];
+        for (int p = 0; p < 6; ++p) obs_sum_field(mine, j, REC_h + p, wd * J[p] * J[6]);
+        obs_sum_field(mine, j, REC_HDD, wd * J[6] * J[6]);
+#pragma unroll
+        for (int p = 0; p < 7; ++p) obs_sum_field(mine, j, REC_G + p, wd * J[p] * r);
+        obs_sum_field(mine, j, REC_E, valid ? (double)rho : 0.0);
+        obs_sum_field(mine, j, REC_SQ, valid ? (double)r * r : 0.0);
+        obs_sum_field(mine, j, REC_CNT, valid ? 1.0 : 0.0);
+        if (o < a.O) {
+            double *rec = a.rec + (size_t)o * REC_STRIDE;
+#pragma unroll
+            for (int i = 0; i < 5; ++i)
+                if (8 * i + j <= REC_CNT) rec[8 * i + j] = mine[i];
         }
     }
 }
@@ -270,29 +312,26 @@ __global__ __launch_bounds__(NB) void k_linearize(ResArgs<T> a, int write_mask) 
 // Mixed precision: residuals and J in FP32, the pose-pose block of every pair
 // contracted on BF16 MFMA. The kernel walks one pair chunk per block (pair
 // order), so that a wavefront's 64 residuals (8 observations x 8 patch pixels)
-// belong to one pair. Each u = sqrt(w) J_theta is split into three bfloat16
-// terms u = hi + mid + lo (each the rounding of what the previous ones leave),
-// and sum u u^T keeps every product of combined order >= 2^-24:
-//   A1 + (A2 + A2^T) + (A3 + A3^T) + A4,  A1 = sum hi hi^T, A2 = sum hi mid^T,
-//   A3 = sum hi lo^T, A4 = sum mid mid^T
-// (the dropped mid lo and lo lo terms are below 2^-25 relative), so the block
-// keeps FP32-level agreement with the depth couplings computed from the same
-// rows; a two-term split (2^-17) is not enough: its error is of the order of
-// the relative damping along the gauge direction of S. Each 64-residual group's
-// four products come from v_mfma_f32_16x16x32_bf16 (FP32 accumulation) and are
-// added to per-lane FP32 running sums with Kahan compensation; the four
-// wavefronts of the block are then added in FP64 in a fixed order into the
-// chunk partial (21 values) that the damping kernel sums per pair. The
-// per-observation record gets every field except the pose-pose block.
+// belong to one pair. The rows u = sqrt(w) J_theta of a 64-residual group are
+// put on a fixed-point grid per component p: with S_p the power of two at or
+// above the group's largest |u_p|, u_p / S_p = hi + mid + lo, each term an
+// integer (|k| <= 128) times 2^-7, 2^-15 and 2^-23, i.e. exactly a bfloat16
+// (the quantized row differs from u by at most 2^-24 S_p). Every product of
+// two such terms is an integer multiple of one unit per term pair, and 64 of
+// them (two 16x16x32 MFMAs) sum to below 2^21 units, so the FP32 accumulation
+// of v_mfma_f32_16x16x32_bf16 is exact whatever its internal order: the nine
+// term products are kept in five accumulators by unit (hi hi; hi mid + mid hi;
+// hi lo + mid mid + lo hi; mid lo + lo mid; lo lo) and added, scaled by
+// S_p S_q, in FP64. The pose block is thus the exact Gram of the quantized
+// rows, and h and H_dd of the record are FP64 sums over the same quantized
+// rows: the per-point blocks of the depth Schur complement stay consistent
+// (PSD as a Gram), which a rounded FP32 accumulation (~1e-7 relative, out of
+// step with FP64 h and H_dd) does not keep: that moved the iterates along the
+// weak directions of S by up to 1e-4 relative in inverse depth. The four
+// wavefronts' FP64 sums are added in a fixed order into the chunk partial (21
+// values) that the damping kernel sums per pair.
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
-
-__device__ __forceinline__ void kahan_add(float &s, float &c, float v) {
-    const float y = v - c;
-    const float t = s + y;
-    c = (t - s) - y;
-    s = t;
-}
 
 template <bool IC>
 __global__ __launch_bounds__(BLOCK) void k_linearize_mixed(ResArgs<float> a, int write_mask,
@@ -300,21 +339,19 @@ __global__ __launch_bounds__(BLOCK) void k_linearize_mixed(ResArgs<float> a, int
                                                            const int *__restrict__ chunk_end,
                                                            const int *__restrict__ pair_obs_idx,
                                                            double *__restrict__ partH) {
-    constexpr int NS = 3;  // split terms hi, mid, lo
-    constexpr int NA = 4;  // products A1..A4
-    // per wavefront: the split terms of u^T as 16 x 64 bfloat16 (rows 6..15 stay zero)
+    constexpr int NS = 3;  // fixed-point terms hi, mid, lo
+    constexpr int NU = 5;  // accumulators by unit: term index sum 0..4
+    // per wavefront: the terms of u^T as 16 x 64 bfloat16 (rows 6..15 stay zero)
     __shared__ __attribute__((aligned(16))) __bf16 ut[BLOCK / 64][NS][16][64];
-    __shared__ double wsum[BLOCK / 64][NA][36];
+    __shared__ double wsum[BLOCK / 64][36];
     if (*a.gate == 0) return;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     for (int e = lane; e < NS * 16 * 64; e += 64) (&ut[wv][0][0][0])[e] = (__bf16)0.0f;
     const int c = blockIdx.x, cb = chunk_begin[c], ce = chunk_end[c];
     const int j = lane & 7;
-    float sa[NA][4], ca[NA][4];
-#pragma unroll
-    for (int m = 0; m < NA; ++m)
-#pragma unroll
-        for (int i = 0; i < 4; ++i) sa[m][i] = ca[m][i] = 0.0f;
+    // this lane's elements of the 16 x 16 Gram: rows 4 (lane / 16) + i, column lane % 16
+    const int col = lane & 15, row0 = 4 * (lane >> 4);
+    double tot[4] = {0.0, 0.0, 0.0, 0.0};
     for (int g = wv; 8 * g < ce - cb; g += BLOCK / 64) {
         const int pos = cb + 8 * g + (lane >> 3);
         const int o = pos < ce ? pair_obs_idx[pos] : -1;
@@ -324,68 +361,86 @@ __global__ __launch_bounds__(BLOCK) void k_linearize_mixed(ResArgs<float> a, int
             const unsigned long long bal = __ballot(valid);
             if (j == 0 && o >= 0) a.mask[o] = (uint8_t)((bal >> (lane & 56)) & 0xFFull);
         }
-        // per-observation fields (all but the pose-pose block)
-        float v[17];
-        for (int p = 0; p < 6; ++p) v[p] = w * J[p] * J[6];
-        v[6] = w * J[6] * J[6];
-        for (int p = 0; p < 7; ++p) v[7 + p] = w * J[p] * r;
-        v[14] = valid ? rho : 0.0f;
-        v[15] = valid ? r * r : 0.0f;
-        v[16] = valid ? 1.0f : 0.0f;
-#pragma unroll
-        for (int p = 0; p < 17; ++p) v[p] = wave_sum8(v[p]);
-        if (j == 0 && o >= 0) {
-            float *rec = a.rec + (size_t)o * REC_STRIDE;
-#pragma unroll
-            for (int p = 0; p < 7; ++p) rec[REC_h + p] = v[p];   // REC_h (6) and REC_HDD
-#pragma unroll
-            for (int p = 0; p < 7; ++p) rec[REC_G + p] = v[7 + p];  // REC_G (6) and REC_GD
-            rec[REC_E] = v[14];
-            rec[REC_SQ] = v[15];
-            rec[REC_CNT] = v[16];
-        }
-        // pose block: stage the split terms of u = sqrt(w) J_theta, transposed
-        const float sw = sqrtf(w);
+        // rows u = sqrt(w) J on the group's fixed-point grid
+        const double sw = sqrt((double)w);
+        const double ud = sw * (double)J[6];
+        double uq[6], scale[6];
 #pragma unroll
         for (int p = 0; p < 6; ++p) {
-            const float u = sw * J[p];
-            const __bf16 hi = (__bf16)u;
-            const float r1 = u - (float)hi;
-            const __bf16 mid = (__bf16)r1;
-            ut[wv][0][p][lane] = hi;
-            ut[wv][1][p][lane] = mid;
-            ut[wv][2][p][lane] = (__bf16)(r1 - (float)mid);
+            const double u = sw * (double)J[p];
+            const double m = wave_max(fabs(u));
+            int ex = 0;
+            (void)frexp(m, &ex);                     // m < 2^ex (m = 0: ex = 0)
+            scale[p] = ldexp(1.0, ex);
+            const double v = u / scale[p];           // |v| < 1, exact (power-of-two scale)
+            const double hi = rint(v * 128.0) * (1.0 / 128.0);
+            const double r1 = v - hi;                // exact, |r1| <= 2^-8
+            const double mid = rint(r1 * 32768.0) * (1.0 / 32768.0);
+            const double r2 = r1 - mid;              // exact, |r2| <= 2^-16
+            const double lo = rint(r2 * 8388608.0) * (1.0 / 8388608.0);
+            uq[p] = scale[p] * ((hi + mid) + lo);    // exact
+            ut[wv][0][p][lane] = (__bf16)(float)hi;  // each term exactly a bfloat16
+            ut[wv][1][p][lane] = (__bf16)(float)mid;
+            ut[wv][2][p][lane] = (__bf16)(float)lo;
+        }
+        // per-observation fields (all but the pose-pose block: REC_h .. REC_CNT,
+        // which are contiguous), FP64 sums as in k_linearize, h and H_dd over
+        // the quantized rows; field REC_h + p goes to slot p / 8 of lane p % 8
+        double mine[3] = {0.0, 0.0, 0.0};
+        const double wd = (double)w;
+#pragma unroll
+        for (int p = 0; p < 6; ++p) obs_sum_field(mine, j, p, uq[p] * ud);
+        obs_sum_field(mine, j, REC_HDD - REC_h, ud * ud);
+#pragma unroll
+        for (int p = 0; p < 7; ++p) obs_sum_field(mine, j, REC_G - REC_h + p, wd * J[p] * r);
+        obs_sum_field(mine, j, REC_E - REC_h, valid ? (double)rho : 0.0);
+        obs_sum_field(mine, j, REC_SQ - REC_h, valid ? (double)r * r : 0.0);
+        obs_sum_field(mine, j, REC_CNT - REC_h, valid ? 1.0 : 0.0);
+        if (o >= 0) {
+            double *rec = a.rec + (size_t)o * REC_STRIDE + REC_h;
+#pragma unroll
+            for (int i = 0; i < 3; ++i)
+                if (8 * i + j <= REC_CNT - REC_h) rec[8 * i + j] = mine[i];
         }
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        f32x4 acc[NA];
+        f32x4 acc[NU];
 #pragma unroll
-        for (int m = 0; m < NA; ++m) acc[m] = (f32x4){0.0f, 0.0f, 0.0f, 0.0f};
+        for (int m = 0; m < NU; ++m) acc[m] = (f32x4){0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
         for (int s = 0; s < 2; ++s) {
             const int k0 = 32 * s + 8 * (lane >> 4);
-            const bf16x8 fh = *reinterpret_cast<const bf16x8 *>(&ut[wv][0][lane & 15][k0]);
-            const bf16x8 fm = *reinterpret_cast<const bf16x8 *>(&ut[wv][1][lane & 15][k0]);
-            const bf16x8 fl = *reinterpret_cast<const bf16x8 *>(&ut[wv][2][lane & 15][k0]);
-            acc[0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fh, fh, acc[0], 0, 0, 0);
-            acc[1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fh, fm, acc[1], 0, 0, 0);
-            acc[2] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fh, fl, acc[2], 0, 0, 0);
-            acc[3] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fm, fm, acc[3], 0, 0, 0);
+            bf16x8 f[NS];
+#pragma unroll
+            for (int t = 0; t < NS; ++t) f[t] = *reinterpret_cast<const bf16x8 *>(&ut[wv][t][lane & 15][k0]);
+#pragma unroll
+            for (int ta = 0; ta < NS; ++ta)
+#pragma unroll
+                for (int tb = 0; tb < NS; ++tb)
+                    acc[ta + tb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(f[ta], f[tb], acc[ta + tb], 0, 0, 0);
         }
         __builtin_amdgcn_wave_barrier();
+        // the exact FP32 sums (smallest unit first) in FP64, then S_p S_q
 #pragma unroll
-        for (int m = 0; m < NA; ++m)
+        for (int i = 0; i < 4; ++i) {
+            const int rw = row0 + i;
+            double t = (double)acc[NU - 1][i];
 #pragma unroll
-            for (int i = 0; i < 4; ++i) kahan_add(sa[m][i], ca[m][i], acc[m][i]);
+            for (int m = NU - 2; m >= 0; --m) t += (double)acc[m][i];
+            double sr = 0.0, sc = 0.0;   // S of the element's row and column (selects, no indexed registers)
+#pragma unroll
+            for (int p = 0; p < 6; ++p) {
+                sr = rw == p ? scale[p] : sr;
+                sc = col == p ? scale[p] : sc;
+            }
+            tot[i] += t * sr * sc;
+        }
     }
-    // lane l holds rows 4 (l / 16) + i, column l % 16 of the 16 x 16 sums
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-        const int row = 4 * (lane >> 4) + i, col = lane & 15;
-        if (row < 6 && col < 6)
-#pragma unroll
-            for (int m = 0; m < NA; ++m) wsum[wv][m][row * 6 + col] = (double)sa[m][i] - (double)ca[m][i];
+        const int rw = row0 + i;
+        if (rw < 6 && col < 6) wsum[wv][rw * 6 + col] = tot[i];
     }
     __syncthreads();
     if (threadIdx.x < 21) {
@@ -394,12 +449,9 @@ __global__ __launch_bounds__(BLOCK) void k_linearize_mixed(ResArgs<float> a, int
             k -= 6 - p;
             ++p;
         }
-        const int q = p + k, pq = p * 6 + q, qp = q * 6 + p;
+        const int pq = p * 6 + p + k;
         double sum = 0.0;
-        for (int w2 = 0; w2 < BLOCK / 64; ++w2) {
-            const double *W = &wsum[w2][0][0];
-            sum += W[pq] + (W[36 + pq] + W[36 + qp]) + (W[72 + pq] + W[72 + qp]) + W[108 + pq];
-        }
+        for (int w2 = 0; w2 < BLOCK / 64; ++w2) sum += wsum[w2][pq];
         partH[21 * (size_t)c + threadIdx.x] = sum;
     }
 }
@@ -414,7 +466,8 @@ __global__ __launch_bounds__(BLOCK) void k_linearize_mixed(ResArgs<float> a, int
 template <typename T, int NB>
 __global__ __launch_bounds__(NB) void k_ic_residual(ResArgs<T> a) {
     const int ntiles = (a.O + NB / 8 - 1) / (NB / 8);
-    for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    for (int it = blockIdx.x; it < ntiles; it += gridDim.x) {
+        const int tile = xcd_tile(it, ntiles);
         const int gid = tile * NB + threadIdx.x;
         const int o = gid >> 3, j = gid & 7;
         const bool in = o < a.O;
@@ -423,23 +476,28 @@ __global__ __launch_bounds__(NB) void k_ic_residual(ResArgs<T> a) {
         // the gate as a vector load, in flight together with the observation's
         const int gv = __hip_atomic_load(a.gate, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         if (__builtin_amdgcn_readfirstlane(gv) == 0) return;
-        T c[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+        double c[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};   // FP64 products and sums (see obs_sum_field)
         // second step: every load that depends only on (n, pr, j), issued
-        // before any branch. The pair's intrinsics and both relative poses (32
-        // values) and the point's host pixel and inverse depths are loaded once
-        // per observation, a slice per lane (lane j: values 4j..4j+3 of
-        // pcam | rel | rel0; lanes 0-2: host_uv, depth, depth0), and read across
-        // the observation's 8 lanes: a lane's loads return 11 values instead of
-        // 43, and the per-CU return path is what bounds this step.
-        typedef T T4 __attribute__((ext_vector_type(4)));
+        // before any branch. The pair's data (FP64 intrinsics of host and
+        // target, FP64 relative pose at the current iterate, the relative pose
+        // at p(0) in T for the Jacobian: 13 (FP32) or 16 (FP64) slices of 16
+        // bytes) and the point's host pixel and inverse depths are loaded once
+        // per observation, lane j taking slices j and j + 8 (lanes 0-2:
+        // host_uv, depth, depth0), and read across the observation's 8 lanes:
+        // the per-CU return path is what bounds this step.
+        constexpr int NSL = 10 + (12 * (int)sizeof(T)) / 16;
+        typedef int I4 __attribute__((ext_vector_type(4)));
         const bool act = in && j < a.P && ((m >> j) & 1);
-        T4 sl = {0, 0, 0, 0};
+        I4 sl0 = {0, 0, 0, 0}, sl1 = {0, 0, 0, 0};
         double pt = 0.0;
         if (in && m != 0u) {
-            const T *src = j < 2 ? a.pcam + 8 * pr + 4 * j
-                                 : (j < 5 ? a.rel + REL_STRIDE * pr + 4 * (j - 2)
-                                          : a.rel0 + REL_STRIDE * pr + 4 * (j - 5));
-            sl = *reinterpret_cast<const T4 *>(src);
+            auto slice = [&](int k) -> const I4 * {
+                if (k < 4) return reinterpret_cast<const I4 *>(a.pcam + 8 * pr + 2 * k);
+                if (k < 10) return reinterpret_cast<const I4 *>(a.geo + GEO_STRIDE * pr + 2 * (k - 4));
+                return reinterpret_cast<const I4 *>(a.rel0 + REL_STRIDE * pr) + (k - 10);
+            };
+            sl0 = *slice(j);
+            if (j + 8 < NSL) sl1 = *slice(j + 8);
             if (j < 3)
                 pt = j == 0 ? *reinterpret_cast<const double *>(a.host_uv + 2 * n) : (j == 1 ? a.depth[n] : a.depth0[n]);
         }
@@ -452,63 +510,85 @@ __global__ __launch_bounds__(NB) void k_ic_residual(ResArgs<T> a) {
         }
         // keep the compiler from sinking these loads into the branches below
         // (the pins follow every load, so that all of them are in flight)
-        pin_reg(sl);
+        pin_reg(sl0);
+        pin_reg(sl1);
         pin_reg(pt);
         pin_reg(f);
 #pragma unroll
         for (int k = 0; k < 4; ++k) pin_reg(tp[k]);
-        // the group's values, read by the whole wavefront
-        T q[32];
-        bcast8_slices(sl, q, std::make_integer_sequence<int, 32>{});
-        const double uv = bcast8<0>(pt), dd = bcast8<1>(pt), dd0 = bcast8<2>(pt);
-        if (act) {
-            const T *cam = q, *R = q + 8, *R0 = q + 20;   // cam: host, target (fx, fy, cx, cy)
-            const long long uvb = __double_as_longlong(uv);
-            const T hu = (T)__int_as_float((int)uvb), hv = (T)__int_as_float((int)(uvb >> 32));
-            const T d = (T)dd, d0 = (T)dd0;
-            // pattern offset of lane j by selects (no lane-indexed argument loads)
-            float du = a.pat.du[0], dv = a.pat.dv[0];
+        // the group's camera and current-pose words (slices 0-9), read by the
+        // whole wavefront; the warp runs on every lane (no memory access),
+        // then the texels are gathered where the residual is usable
+        int q[40];
+        bcast8_words(sl0, sl1, q, std::make_integer_sequence<int, 8>{});
+        auto word_d = [&](int k) { return __hiloint2double(q[2 * k + 1], q[2 * k]); };
+        const double uv = bcast8<0>(pt), d = bcast8<1>(pt);
+        const long long uvb = __double_as_longlong(uv);
+        const double hu = (double)__int_as_float((int)uvb), hv = (double)__int_as_float((int)(uvb >> 32));
+        // pattern offset of lane j by selects (no lane-indexed argument loads)
+        int du = a.pat.du[0], dv = a.pat.dv[0];
 #pragma unroll
-            for (int k = 1; k < 8; ++k) {
-                du = j == k ? a.pat.du[k] : du;
-                dv = j == k ? a.pat.dv[k] : dv;
-            }
-            const T u = (hu + T(0.5)) * a.scale - T(0.5) + (T)du;
-            const T v = (hv + T(0.5)) * a.scale - T(0.5) + (T)dv;
-            const T x = (u - cam[2]) / cam[0], y = (v - cam[3]) / cam[1];
-            const T *t = R + 9;
-            const T vz = R[6] * x + R[7] * y + R[8] + d * t[2];
-            const T vx = R[0] * x + R[1] * y + R[2] + d * t[0];
-            const T vy = R[3] * x + R[4] * y + R[5] + d * t[1];
-            if (d > T(0) && vz > T(0)) {
-                const T qu = cam[4] * (vx / vz) + cam[6], qv = cam[5] * (vy / vz) + cam[7];
-                if (usable(qu, qv, a.W, a.H)) {
-                    // third step: the target texels
-                    const T If = bilinear(a.img + (size_t)f * a.W * a.H, a.W, qu, qv);
-                    const T r = tp[0] - If;
-                    T w, rho;
-                    huber(r, a.huber_k, w, rho);
-                    T J[7];
-                    ic_jacobian(x, y, R0, R0 + 9, d0, tp[1], tp[2], cam[0], cam[1], J);
-                    const T wr = w * r;
+        for (int k = 1; k < 8; ++k) {
+            du = j == k ? a.pat.du[k] : du;
+            dv = j == k ? a.pat.dv[k] : dv;
+        }
+        // the warp in FP64 (as template_xy and lin_eval); cam: host, target
+        // (fx, fy, cx, cy) in words 0-15, R and t in words 16-39
+        const double u = (hu + 0.5) * a.scale - 0.5 + (double)du;
+        const double v = (hv + 0.5) * a.scale - 0.5 + (double)dv;
+        const double x = (u - word_d(2)) / word_d(0), y = (v - word_d(3)) / word_d(1);
+        // the rest of the words once x and y are formed
+        pin_reg(sl0);
+        bcast8_words_range<8>(sl0, sl1, q, std::make_integer_sequence<int, 32>{});
+        const double vz = word_d(14) * x + word_d(15) * y + word_d(16) + d * word_d(19);
+        const double vx = word_d(8) * x + word_d(9) * y + word_d(10) + d * word_d(17);
+        const double vy = word_d(11) * x + word_d(12) * y + word_d(13) + d * word_d(18);
+        const double qu = word_d(4) * (vx / vz) + word_d(6), qv = word_d(5) * (vy / vz) + word_d(7);
+        const bool ok = act && d > 0.0 && vz > 0.0 && usable(qu, qv, a.W, a.H);
+        double If = 0.0;
+        // third step: the target texels
+        if (ok) If = bilinear(a.img + (size_t)f * a.W * a.H, a.W, qu, qv);
+        // the p(0) pose words (slices 10 and up, all in sl1) only now, so that
+        // they are not held in registers across the warp
+        pin_reg(sl1);
+        constexpr int NR0 = 12 * (int)sizeof(T) / 4;
+        int q0[NR0];
+        bcast8_words_from<40>(sl1, q0, std::make_integer_sequence<int, NR0>{});
+        const double dd0 = bcast8<2>(pt);
+        if (ok) {
+            T R0[12];
 #pragma unroll
-                    for (int p = 0; p < 7; ++p) c[p] = wr * J[p];
-                    c[7] = rho;
-                    c[8] = r * r;
-                    c[9] = T(1);
-                }
+            for (int k = 0; k < 12; ++k) {
+                if constexpr (sizeof(T) == 8)
+                    R0[k] = (T)__hiloint2double(q0[2 * k + 1], q0[2 * k]);
+                else
+                    R0[k] = (T)__int_as_float(q0[k]);
             }
+            const T r = (T)((double)tp[0] - If);   // rounded once (bilinear)
+            T w, rho;
+            huber(r, a.huber_k, w, rho);
+            T J[7];
+            ic_jacobian((T)x, (T)y, R0, R0 + 9, (T)dd0, tp[1], tp[2], (T)word_d(0), (T)word_d(1), J);
+            const double wr = (double)w * r;
+#pragma unroll
+            for (int p = 0; p < 7; ++p) c[p] = wr * J[p];
+            c[7] = rho;
+            c[8] = (double)r * r;
+            c[9] = 1.0;
         }
 #pragma unroll
-        for (int p = 0; p < 10; ++p) c[p] = wave_sum8(c[p]);
+        for (int p = 0; p < 10; ++p) {
+            pin_reg(c[p]);
+            c[p] = wave_sum8(c[p]);
+        }
         // every lane of the observation holds the sums: lane j stores field j
-        // (and lanes 0, 1 fields 8, 9)
-        T v0 = c[0];
+        // (and lanes 0, 1 fields 8, 9), rounded to T once
+        double v0 = c[0];
 #pragma unroll
         for (int p = 1; p < 8; ++p) v0 = j == p ? c[p] : v0;
-        const T v1 = j == 0 ? c[8] : c[9];
+        const double v1 = j == 0 ? c[8] : c[9];
         if (in) {
-            T *rec = a.icr + (size_t)o * IC_REC;
+            double *rec = a.icr + (size_t)o * IC_REC;
             rec[j] = v0;
             if (j < 2) rec[8 + j] = v1;
         }
@@ -524,22 +604,21 @@ __global__ __launch_bounds__(BLOCK) void k_evaluate(ResArgs<T> a) {
     T c[3] = {0, 0, 0};
     if (o < a.O && j < a.P) {
         const int n = a.obs_point[o], pr = a.obs_pair[o];
-        const int h = a.pair_host[pr], f = a.pair_target[pr];
-        const T *Kh = a.K + 4 * h;
-        const T *Kt = a.K + 4 * f;
+        const int f = a.pair_target[pr];
+        const double *Kh = a.pcam + 8 * pr, *Kt = Kh + 4;
         const T *tp = a.tmpl + 4 * ((size_t)n * a.P + j);
-        T x, y;
+        double x, y;
         template_xy(a, n, j, Kh, x, y);
-        const T *R = a.rel + REL_STRIDE * pr;
-        const T *t = R + 9;
-        const T d = (T)a.depth[n];
-        const T vz = R[6] * x + R[7] * y + R[8] + d * t[2];
-        if (tp[3] != T(0) && d > T(0) && vz > T(0)) {
-            const T vx = R[0] * x + R[1] * y + R[2] + d * t[0];
-            const T vy = R[3] * x + R[4] * y + R[5] + d * t[1];
-            const T qu = Kt[0] * (vx / vz) + Kt[2], qv = Kt[1] * (vy / vz) + Kt[3];
+        const double *R = a.geo + GEO_STRIDE * pr;
+        const double *t = R + 9;
+        const double d = a.depth[n];
+        const double vz = R[6] * x + R[7] * y + R[8] + d * t[2];
+        if (tp[3] != T(0) && d > 0.0 && vz > 0.0) {
+            const double vx = R[0] * x + R[1] * y + R[2] + d * t[0];
+            const double vy = R[3] * x + R[4] * y + R[5] + d * t[1];
+            const double qu = Kt[0] * (vx / vz) + Kt[2], qv = Kt[1] * (vy / vz) + Kt[3];
             if (usable(qu, qv, a.W, a.H)) {
-                const T r = tp[0] - bilinear(a.img + (size_t)f * a.W * a.H, a.W, qu, qv);
+                const T r = (T)((double)tp[0] - bilinear(a.img + (size_t)f * a.W * a.H, a.W, qu, qv));
                 T w, rho;
                 huber(r, a.huber_k, w, rho);
                 c[0] = rho;
@@ -550,7 +629,7 @@ __global__ __launch_bounds__(BLOCK) void k_evaluate(ResArgs<T> a) {
     }
     for (int p = 0; p < 3; ++p) c[p] = wave_sum8(c[p]);
     if (j == 0 && o < a.O) {
-        T *rec = a.rec + (size_t)o * REC_STRIDE;
+        double *rec = a.rec + (size_t)o * REC_STRIDE;
         rec[REC_E] = c[0];
         rec[REC_SQ] = c[1];
         rec[REC_CNT] = c[2];
@@ -639,7 +718,7 @@ __device__ __forceinline__ void block_sum(double v[NV], double *lds /* [NV * 16]
 // Per point: sum of the depth blocks over the point's observations.
 template <typename T>
 __global__ __launch_bounds__(256) void k_point_reduce(int N, const int *__restrict__ obs_ptr,
-                                                      const T *__restrict__ rec, double *__restrict__ Hdd,
+                                                      const double *__restrict__ rec, double *__restrict__ Hdd,
                                                       double *__restrict__ gd, int with_hdd,
                                                       const int *__restrict__ gate) {
     if (*gate == 0) return;
@@ -649,8 +728,8 @@ __global__ __launch_bounds__(256) void k_point_reduce(int N, const int *__restri
         const int o0 = obs_ptr[n], o1 = obs_ptr[n + 1];
 #pragma unroll 4
         for (int o = o0; o < o1; ++o) {
-            const T *r = rec + (size_t)o * REC_STRIDE;
-            hs += (double)r[REC_HDD];
+            const double *r = rec + (size_t)o * REC_STRIDE;
+            hs += r[REC_HDD];
             gs += (double)r[REC_GD];
         }
         gd[n] = gs;
@@ -663,7 +742,7 @@ __global__ __launch_bounds__(256) void k_point_reduce(int N, const int *__restri
 // chunk order by the consumer. slot: per thread of each chunk (observation,
 // point, the point's observation range), observation -1 past the chunk's end.
 template <typename T>
-__global__ __launch_bounds__(PAIR_CHUNK) void k_pair_chunk_H(const int4 *__restrict__ slot, const T *__restrict__ rec,
+__global__ __launch_bounds__(PAIR_CHUNK) void k_pair_chunk_H(const int4 *__restrict__ slot, const double *__restrict__ rec,
                                                       double *__restrict__ partH, const int *__restrict__ gate) {
     __shared__ double lds[21 * 16];
     if (*gate == 0) return;
@@ -672,8 +751,8 @@ __global__ __launch_bounds__(PAIR_CHUNK) void k_pair_chunk_H(const int4 *__restr
     double v[21];
     for (int k = 0; k < 21; ++k) v[k] = 0.0;
     if (o >= 0) {
-        const T *r = rec + (size_t)o * REC_STRIDE;
-        for (int k = 0; k < 21; ++k) v[k] += (double)r[REC_H + k];
+        const double *r = rec + (size_t)o * REC_STRIDE;
+        for (int k = 0; k < 21; ++k) v[k] += r[REC_H + k];
     }
     block_sum<21>(v, lds);
     if (threadIdx.x == 0)
@@ -686,8 +765,8 @@ __global__ __launch_bounds__(PAIR_CHUNK) void k_pair_chunk_H(const int4 *__restr
 // records (GR_* fields) and their stride; h_o from the full record; prange: the
 // observation range of each observation's point.
 template <typename T>
-__global__ __launch_bounds__(PAIR_CHUNK) void k_pair_chunk_y(const int4 *__restrict__ slot, const T *__restrict__ rec,
-                                                             const T *__restrict__ gr, int gs,
+__global__ __launch_bounds__(PAIR_CHUNK) void k_pair_chunk_y(const int4 *__restrict__ slot, const double *__restrict__ rec,
+                                                             const double *__restrict__ gr, int gs,
                                                              const double *__restrict__ Hdd,
                                                              double *__restrict__ partY, const int *__restrict__ gate,
                                                              const double *__restrict__ du_part, int du_nparts,
@@ -717,8 +796,8 @@ __global__ __launch_bounds__(PAIR_CHUNK) void k_pair_chunk_y(const int4 *__restr
     for (int k = 0; k < 9; ++k) v[k] = 0.0;
     if (live && sd.x >= 0) {
         const int o = sd.x, n = sd.y, q0 = sd.z, q1 = sd.w;
-        const T *r = rec + (size_t)o * REC_STRIDE;
-        const T *g = gr + (size_t)o * gs;
+        const double *r = rec + (size_t)o * REC_STRIDE;
+        const double *g = gr + (size_t)o * gs;
         double gdn = 0.0;  // g_d,n: the point's records in order (bitwise the per-point sum)
 #pragma unroll 4
         for (int q = q0; q < q1; ++q) gdn += (double)gr[(size_t)q * gs + GR_GD];
@@ -781,8 +860,8 @@ __global__ void k_sum_parts3(int np, const double *__restrict__ part, double *__
 template <typename T>
 __global__ __launch_bounds__(256) void k_depth_update(
     int N, int ic, const int *__restrict__ obs_ptr, const int *__restrict__ obs_pair,
-    const float *__restrict__ host_uv, const double *__restrict__ pairK0, const T *__restrict__ rec,
-    const T *__restrict__ gr, int gs, const double *__restrict__ Hdd, const double *__restrict__ dth_rel,
+    const float *__restrict__ host_uv, const double *__restrict__ pairK0, const double *__restrict__ rec,
+    const double *__restrict__ gr, int gs, const double *__restrict__ Hdd, const double *__restrict__ dth_rel,
     const double *__restrict__ geo_old, const double *__restrict__ geo_new, double *__restrict__ depth,
     const double *__restrict__ depth0, double *__restrict__ part, const int *__restrict__ gate,
     const int *__restrict__ flag) {
@@ -804,7 +883,7 @@ __global__ __launch_bounds__(256) void k_depth_update(
 static inline unsigned nblk(size_t n, unsigned b) { return (unsigned)((n + b - 1) / b); }
 
 template <typename T>
-static ResArgs<T> res_args(Ctx &c, int level, const T *rel_cur) {
+static ResArgs<T> res_args(Ctx &c, int level, const double *geo_cur) {
     ResArgs<T> a{};
     a.O = c.O;
     a.P = c.P;
@@ -815,7 +894,7 @@ static ResArgs<T> res_args(Ctx &c, int level, const T *rel_cur) {
         a.pat.du[j] = j < c.cfg.pattern_n ? c.cfg.pattern_uv[2 * j] : 0;
         a.pat.dv[j] = j < c.cfg.pattern_n ? c.cfg.pattern_uv[2 * j + 1] : 0;
     }
-    a.scale = T(1) / T(1 << level);
+    a.scale = 1.0 / (double)(1 << level);
     a.huber_k = (T)c.cfg.huber_k;
     a.obs_point = c.d_obs_point;
     a.obs_pair = c.d_obs_pair;
@@ -823,16 +902,15 @@ static ResArgs<T> res_args(Ctx &c, int level, const T *rel_cur) {
     a.pair_target = c.d_pair_target;
     a.host_uv = c.d_host_uv;
     a.img = (const T *)c.lv[level].img;
-    a.K = (const T *)c.lv[level].K;
     a.tmpl = (const T *)c.lv[level].tmpl;
-    a.rel = rel_cur;
+    a.geo = geo_cur;
     a.rel0 = (const T *)c.d_rel0;
     a.depth = c.d_depth;
     a.depth0 = c.d_depth0;
     a.mask = c.d_mask;
-    a.rec = (T *)c.d_rec;
-    a.pcam = (const T *)c.lv[level].pcam;
-    a.icr = (T *)c.d_icr;
+    a.rec = (double *)c.d_rec;
+    a.pcam = (const double *)c.lv[level].pcam;
+    a.icr = (double *)c.d_icr;
     a.gate = c.d_gate;
     return a;
 }
@@ -844,12 +922,12 @@ static ConvArgs conv_args(Ctx &c, double *stat, double conv_px, int level) {
 // Gradient records of the current iteration: the compact IC records or the
 // G .. CNT fields of the full record (FC).
 template <typename T>
-static void grad_records(const Ctx &c, const T *&gr, int &gs) {
+static void grad_records(const Ctx &c, const double *&gr, int &gs) {
     if (c.cfg.mode == PBA_IC_PROXY) {
-        gr = (const T *)c.d_icr;
+        gr = (const double *)c.d_icr;
         gs = IC_REC;
     } else {
-        gr = (const T *)c.d_rec + REC_G;
+        gr = (const double *)c.d_rec + REC_G;
         gs = REC_STRIDE;
     }
 }
@@ -878,11 +956,12 @@ void Launch<T>::make_template(hipStream_t s, Ctx &c, int level) {
     const size_t n = (size_t)c.N * c.P;
     if (n == 0) return;
     k_template<T><<<nblk(n, 256), 256, 0, s>>>(c.N, c.P, a.pat, c.d_host_uv, c.d_host_frame, a.img, a.W, a.H,
-                                               a.scale, (T *)c.lv[level].tmpl);
+                                               (T)a.scale, (T *)c.lv[level].tmpl);
     CHECK_LAUNCH();
     if (c.st.n_pairs > 0) {
-        k_pair_cam<T><<<nblk((size_t)c.st.n_pairs * 8, 256), 256, 0, s>>>(
-            c.st.n_pairs, c.d_pair_host, c.d_pair_target, a.K, (T *)c.lv[level].pcam);
+        k_pair_cam<<<nblk((size_t)c.st.n_pairs * 8, 256), 256, 0, s>>>(c.st.n_pairs, c.d_pair_host,
+                                                                      c.d_pair_target, c.d_K0, level,
+                                                                      (double *)c.lv[level].pcam);
         CHECK_LAUNCH();
     }
 }
@@ -938,25 +1017,25 @@ static void launch_linearize_shape(hipStream_t s, const Ctx &c, const ResArgs<T>
 template <typename T>
 void Launch<T>::ic_linearize(hipStream_t s, Ctx &c, int level) {
     if (c.O == 0) return;
-    ResArgs<T> a = res_args<T>(c, level, (const T *)c.d_rel0);
+    ResArgs<T> a = res_args<T>(c, level, c.d_geo0);
     launch_linearize_shape<T, true>(s, c, a, 1, LaunchShape{});
     CHECK_LAUNCH();
 }
 
 template <typename T>
-void Launch<T>::fc_linearize(hipStream_t s, Ctx &c, int level, const T *rel_cur, bool write_mask, hipEvent_t e0,
-                             hipEvent_t e1) {
+void Launch<T>::fc_linearize(hipStream_t s, Ctx &c, int level, const double *geo_cur, bool write_mask,
+                             hipEvent_t e0, hipEvent_t e1) {
     if (c.O == 0) return;
-    ResArgs<T> a = res_args<T>(c, level, rel_cur);
+    ResArgs<T> a = res_args<T>(c, level, geo_cur);
     launch_linearize_shape<T, false>(s, c, a, write_mask ? 1 : 0, c.tune_lin, e0, e1);
     CHECK_LAUNCH();
 }
 
-void launch_linearize_mixed(hipStream_t s, Ctx &c, int level, bool ic, const float *rel_cur, bool write_mask,
+void launch_linearize_mixed(hipStream_t s, Ctx &c, int level, bool ic, const double *geo_cur, bool write_mask,
                             hipEvent_t e0, hipEvent_t e1) {
     const int nch = (int)c.st.pchunk_begin.size();
     if (c.O == 0 || nch == 0) return;
-    ResArgs<float> a = res_args<float>(c, level, rel_cur);
+    ResArgs<float> a = res_args<float>(c, level, geo_cur);
     if (ic)
         launch_ev(k_linearize_mixed<true>, nch, BLOCK, s, e0, e1, a, 1, (const int *)c.d_pchunk_begin,
                   (const int *)c.d_pchunk_end, (const int *)c.d_pair_obs_idx, c.d_partH);
@@ -968,15 +1047,15 @@ void launch_linearize_mixed(hipStream_t s, Ctx &c, int level, bool ic, const flo
 }
 
 template <typename T>
-void Launch<T>::ic_residual(hipStream_t s, Ctx &c, int level, const T *rel_cur, hipEvent_t e0, hipEvent_t e1) {
-    ic_residual_shape(s, c, level, rel_cur, c.tune_res, e0, e1);
+void Launch<T>::ic_residual(hipStream_t s, Ctx &c, int level, const double *geo_cur, hipEvent_t e0, hipEvent_t e1) {
+    ic_residual_shape(s, c, level, geo_cur, c.tune_res, e0, e1);
 }
 
 template <typename T>
-void Launch<T>::ic_residual_shape(hipStream_t s, Ctx &c, int level, const T *rel_cur, LaunchShape sh, hipEvent_t e0,
-                                  hipEvent_t e1) {
+void Launch<T>::ic_residual_shape(hipStream_t s, Ctx &c, int level, const double *geo_cur, LaunchShape sh,
+                                  hipEvent_t e0, hipEvent_t e1) {
     if (c.O == 0) return;
-    ResArgs<T> a = res_args<T>(c, level, rel_cur);
+    ResArgs<T> a = res_args<T>(c, level, geo_cur);
     const unsigned g = shape_grid(c, sh);
     switch (sh.block) {
         case 64: launch_ev(k_ic_residual<T, 64>, g, 64, s, e0, e1, a); break;
@@ -989,9 +1068,9 @@ void Launch<T>::ic_residual_shape(hipStream_t s, Ctx &c, int level, const T *rel
 }
 
 template <typename T>
-void Launch<T>::fc_linearize_shape(hipStream_t s, Ctx &c, int level, const T *rel_cur, LaunchShape sh) {
+void Launch<T>::fc_linearize_shape(hipStream_t s, Ctx &c, int level, const double *geo_cur, LaunchShape sh) {
     if (c.O == 0) return;
-    ResArgs<T> a = res_args<T>(c, level, rel_cur);
+    ResArgs<T> a = res_args<T>(c, level, geo_cur);
     launch_linearize_shape<T, false>(s, c, a, 1, sh);
     CHECK_LAUNCH();
 }
@@ -999,8 +1078,7 @@ void Launch<T>::fc_linearize_shape(hipStream_t s, Ctx &c, int level, const T *re
 template <typename T>
 void Launch<T>::evaluate(hipStream_t s, Ctx &c, int level) {
     if (c.O == 0) return;
-    const T *rel = (const T *)(c.flip ? c.d_rel_b : c.d_rel_a);
-    ResArgs<T> a = res_args<T>(c, level, rel);
+    ResArgs<T> a = res_args<T>(c, level, c.flip ? c.d_geo_b : c.d_geo_a);
     k_evaluate<T><<<nblk((size_t)c.O * LANES_PER_OBS, BLOCK), BLOCK, 0, s>>>(a);
     CHECK_LAUNCH();
 }
@@ -1008,7 +1086,7 @@ void Launch<T>::evaluate(hipStream_t s, Ctx &c, int level) {
 template <typename T>
 void Launch<T>::point_reduce(hipStream_t s, Ctx &c, bool with_hdd) {
     if (c.N == 0) return;
-    k_point_reduce<T><<<nblk(c.N, 256), 256, 0, s>>>(c.N, c.d_obs_ptr, (const T *)c.d_rec, c.d_Hdd, c.d_gd,
+    k_point_reduce<T><<<nblk(c.N, 256), 256, 0, s>>>(c.N, c.d_obs_ptr, (const double *)c.d_rec, c.d_Hdd, c.d_gd,
                                                      with_hdd ? 1 : 0, c.d_gate);
     CHECK_LAUNCH();
 }
@@ -1017,7 +1095,7 @@ template <typename T>
 void Launch<T>::pair_reduce_H(hipStream_t s, Ctx &c) {
     const int nch = (int)c.st.pchunk_begin.size();
     if (nch == 0) return;
-    k_pair_chunk_H<T><<<nch, PAIR_CHUNK, 0, s>>>((const int4 *)c.d_pc_slot, (const T *)c.d_rec, c.d_partH, c.d_gate);
+    k_pair_chunk_H<T><<<nch, PAIR_CHUNK, 0, s>>>((const int4 *)c.d_pc_slot, (const double *)c.d_rec, c.d_partH, c.d_gate);
     CHECK_LAUNCH();
 }
 
@@ -1029,10 +1107,10 @@ void Launch<T>::pair_reduce_y(hipStream_t s, Ctx &c, double *prev_stat, double c
         if (prev_stat) launch_conv(s, c, prev_stat, conv_px, du_nparts(c), level);
         return;
     }
-    const T *gr;
+    const double *gr;
     int gs;
     grad_records<T>(c, gr, gs);
-    k_pair_chunk_y<T><<<nch, PAIR_CHUNK, 0, s>>>((const int4 *)c.d_pc_slot, (const T *)c.d_rec, gr, gs, c.d_Hdd,
+    k_pair_chunk_y<T><<<nch, PAIR_CHUNK, 0, s>>>((const int4 *)c.d_pc_slot, (const double *)c.d_rec, gr, gs, c.d_Hdd,
                                                  c.d_partY, c.d_gate, prev_stat ? c.d_du_part : nullptr,
                                                  du_nparts(c), conv_args(c, prev_stat, conv_px, level));
     CHECK_LAUNCH();
@@ -1043,12 +1121,12 @@ template <typename T>
 void Launch<T>::depth_update(hipStream_t s, Ctx &c, const double *geo_old, const double *geo_new, double *stat,
                              double conv_px, int level, bool finish) {
     const int nb = (int)nblk(c.N, DU_PTS);
-    const T *gr;
+    const double *gr;
     int gs;
     grad_records<T>(c, gr, gs);
     if (c.N > 0)
         k_depth_update<T><<<nb, 256, 0, s>>>(c.N, c.cfg.mode == PBA_IC_PROXY ? 1 : 0, c.d_obs_ptr, c.d_obs_pair,
-                                             c.d_host_uv, c.d_pairK0, (const T *)c.d_rec, gr, gs, c.d_Hdd,
+                                             c.d_host_uv, c.d_pairK0, (const double *)c.d_rec, gr, gs, c.d_Hdd,
                                              c.d_dth_rel, geo_old, geo_new, c.d_depth, c.d_depth0, c.d_du_part,
                                              c.d_gate, c.d_flag);
     CHECK_LAUNCH();

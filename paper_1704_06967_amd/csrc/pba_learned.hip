@@ -247,6 +247,58 @@ __global__ void k_pc_blocks(int nb, const float *__restrict__ Y, const double *_
         }
 }
 
+// Blocks of M^{-1} at the minimizer of the block loss itself: tr(P A P) -
+// 2 tr P with A = I + G_i is smallest at P^ = A^{-1}, so P_i = C_i^{-T}
+// (I + G_i)^{-1} C_i^{-1} = (X C_i^{-1})^T (X C_i^{-1}) with X = R^{-1} and
+// A = R R^T (the bound a trained network approaches).
+__global__ void k_pc_blocks_opt(int nb, const double *__restrict__ G, const double *__restrict__ Ci,
+                                double *__restrict__ P, int *__restrict__ flag) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nb) return;
+    double A[6][6], R[6][6], X[6][6];
+    for (int r = 0; r < 6; ++r)
+        for (int c = 0; c < 6; ++c)
+            A[r][c] = (r == c ? 1.0 : 0.0) + G[21 * (size_t)i + (r <= c ? upper_idx(r, c) : upper_idx(c, r))];
+    for (int c = 0; c < 6; ++c) {
+        double d = A[c][c];
+        for (int q = 0; q < c; ++q) d -= R[c][q] * R[c][q];
+        if (!(d > 0.0)) {
+            *flag = 1;
+            return;
+        }
+        R[c][c] = sqrt(d);
+        for (int r = c + 1; r < 6; ++r) {
+            double v = A[r][c];
+            for (int q = 0; q < c; ++q) v -= R[r][q] * R[c][q];
+            R[r][c] = v / R[c][c];
+        }
+    }
+    for (int c = 0; c < 6; ++c)
+        for (int r = 0; r < 6; ++r) {
+            if (r < c) {
+                X[r][c] = 0.0;
+                continue;
+            }
+            double v = (r == c) ? 1.0 : 0.0;
+            for (int q = c; q < r; ++q) v -= R[r][q] * X[q][c];
+            X[r][c] = v / R[r][r];
+        }
+    const double *B = Ci + 36 * (size_t)i;
+    double W[6][6];   // X C_i^{-1} (both lower)
+    for (int r = 0; r < 6; ++r)
+        for (int c = 0; c < 6; ++c) {
+            double v = 0.0;
+            for (int q = c; q <= r; ++q) v += X[r][q] * B[6 * q + c];
+            W[r][c] = v;
+        }
+    for (int r = 0; r < 6; ++r)
+        for (int c = 0; c < 6; ++c) {
+            double v = 0.0;
+            for (int q = 0; q < 6; ++q) v += W[q][r] * W[q][c];
+            P[36 * (size_t)i + 6 * r + c] = v;
+        }
+}
+
 // ---------------------------------------------------------------- training (FP32)
 
 // C[M][N] = op(A) op(B) (+ epilogue), 16 x 16 output tile per 256-thread block,
@@ -563,6 +615,10 @@ void pc_infer(hipStream_t s, Ctx &c, int m, const float *X, float *Y) {
 
 void pc_blocks(hipStream_t s, Ctx &c, int nb, const float *Y) {
     k_pc_blocks<<<nbk(nb, 64), 64, 0, s>>>(nb, Y, c.pc.Ci, c.pc.P);
+}
+
+void pc_blocks_opt(hipStream_t s, Ctx &c, int nb) {
+    k_pc_blocks_opt<<<nbk(nb, 64), 64, 0, s>>>(nb, c.pc.G, c.pc.Ci, c.pc.P, c.pc.flag);
 }
 
 void pc_to_half(hipStream_t s, Ctx &c) { k_pc_to_half<<<nbk(256 * 256, 256), 256, 0, s>>>(c.pc.w, c.pc.wh); }

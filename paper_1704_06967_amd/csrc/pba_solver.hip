@@ -1,6 +1,8 @@
 // FP64 kernels of the reduced pose system: depth damping, the per-host Gram of
 // the depth Schur complement, assembly of S, Cholesky, the IC inverse, and the
 // single-workgroup solve + pose update of every iteration.
+#include <hip/hip_ext.h>
+
 #include "pba_depth.hpp"
 #include "pba_device.hpp"
 #include "pba_internal.hpp"
@@ -1052,7 +1054,7 @@ __global__ __launch_bounds__(SOLVE_THREADS) void k_ic_step(
     double *__restrict__ dth_all, double *__restrict__ dth_rel, double *__restrict__ geo_next,
     T *__restrict__ rel_next, double *__restrict__ wstat, int *__restrict__ flag, int *__restrict__ gate, int N,
     const int *__restrict__ obs_ptr, const int *__restrict__ obs_pair, const float *__restrict__ host_uv,
-    const double *__restrict__ pairK0, const T *__restrict__ rec, const T *__restrict__ gr, int gs,
+    const double *__restrict__ pairK0, const double *__restrict__ rec, const double *__restrict__ gr, int gs,
     const double *__restrict__ Hdd, const double *__restrict__ geo_old, double *__restrict__ depth,
     const double *__restrict__ depth0, double *__restrict__ part, const int *__restrict__ step_sel, int sel_ncw,
     int nch) {
@@ -1196,13 +1198,14 @@ int du_nparts(const Ctx &c) {
 
 template <typename T>
 static void ic_step_kernel(hipStream_t s, Ctx &c, const double *geo_lin, const double *geo_old, double *geo_next,
-                           T *rel_next) {
-    const T *rec = (const T *)c.d_rec, *gr = (const T *)c.d_icr;
+                           T *rel_next, hipEvent_t e0, hipEvent_t e1) {
+    const double *rec = (const double *)c.d_rec, *gr = (const double *)c.d_icr;
     // iteration k of a batch reads pose buffer k mod 2 and writes the other
     // (the convergence kernel at the batch's end copies back after odd counts)
     const bool odd = (c.batch_k & 1) != 0;
     double *p_in = odd ? c.d_poses_alt : c.d_poses, *p_out = odd ? c.d_poses : c.d_poses_alt;
-    k_ic_step<T><<<1 + nb(c.N, IC_STEP_PTS), SOLVE_THREADS, 0, s>>>(
+    // with events: recorded by the dispatch itself (the kernel's own duration)
+    hipExtLaunchKernelGGL(k_ic_step<T>, dim3(1 + nb(c.N, IC_STEP_PTS)), dim3(SOLVE_THREADS), 0, s, e0, e1, 0,
         c.win(), c.win_frame_off[1], c.win_pair_off[1], c.cfg.pinned_frame, c.d_frame_pair_ptr, c.d_frame_pair_item,
         c.d_pair_host, c.d_pair_target, c.d_pair_chunk_ptr, c.d_partY, c.d_pairY, geo_lin, c.d_Sinv, p_in, p_out,
         c.d_poses0, c.d_b, c.d_dtheta, c.d_dth_rel, geo_next, rel_next, c.d_wstat, c.d_flag, c.d_gate, c.N,
@@ -1211,11 +1214,11 @@ static void ic_step_kernel(hipStream_t s, Ctx &c, const double *geo_lin, const d
 }
 
 void launch_ic_step(hipStream_t s, Ctx &c, const double *geo_lin, const double *geo_old, double *geo_next,
-                    void *rel_next, bool rel_double) {
+                    void *rel_next, bool rel_double, hipEvent_t e0, hipEvent_t e1) {
     if (rel_double)
-        ic_step_kernel<double>(s, c, geo_lin, geo_old, geo_next, (double *)rel_next);
+        ic_step_kernel<double>(s, c, geo_lin, geo_old, geo_next, (double *)rel_next, e0, e1);
     else
-        ic_step_kernel<float>(s, c, geo_lin, geo_old, geo_next, (float *)rel_next);
+        ic_step_kernel<float>(s, c, geo_lin, geo_old, geo_next, (float *)rel_next, e0, e1);
 }
 
 template <typename T, int PATH, bool CACHE>

@@ -15,7 +15,7 @@ LIB_PATH = os.path.join(_HERE, "libpba.so")
 PBA_OK, PBA_E_INVALID, PBA_E_STATE, PBA_E_OOM, PBA_E_DEVICE, PBA_E_NUMERIC, PBA_E_NOT_CONVERGED = 0, -1, -2, -3, -4, -5, -6
 PBA_FC, PBA_IC_PROXY = 0, 1
 PBA_FP64, PBA_FP32, PBA_MIXED_BF16 = 0, 1, 2
-PBA_SOLVER_CHOL, PBA_SOLVER_PCG_JACOBI, PBA_SOLVER_PCG_LEARNED = 0, 1, 2
+PBA_SOLVER_CHOL, PBA_SOLVER_PCG_JACOBI, PBA_SOLVER_PCG_LEARNED, PBA_SOLVER_PCG_BLOCKOPT = 0, 1, 2, 3
 PBA_PC_N_PARAMS = 77077
 PBA_HOST, PBA_DEVICE = 0, 1
 PBA_FLAG_TIMING, PBA_FLAG_GRAPH = 1, 2
@@ -62,7 +62,8 @@ class pba_result(C.Structure):
 
 class pba_timing(C.Structure):
     _fields_ = [("residual_launches", C.c_int64 * PBA_MAX_LEVELS), ("residual_ms", C.c_double * PBA_MAX_LEVELS),
-                ("residuals_processed", C.c_int64 * PBA_MAX_LEVELS)]
+                ("residuals_processed", C.c_int64 * PBA_MAX_LEVELS), ("step_launches", C.c_int64 * PBA_MAX_LEVELS),
+                ("step_ms", C.c_double * PBA_MAX_LEVELS)]
 
 
 PBA_TUNE_MAX = 16
@@ -274,7 +275,7 @@ class Solver:
         s_shape = (n6, n6) if len(self.Fw) == 1 else (sum(36 * f * f for f in self.Fw),)
         shapes = {
             PBA_DBG_S: (s_shape, np.float64), PBA_DBG_B: ((n6,), np.float64),
-            PBA_DBG_OBS_REC: ((self.O, REC_STRIDE), self.real),
+            PBA_DBG_OBS_REC: ((self.O, REC_STRIDE), np.float64),
             PBA_DBG_TEMPLATE: ((self.N, self.cfg.pattern_n, 4), self.real),
             PBA_DBG_HDD: ((self.N,), np.float64), PBA_DBG_MASK: ((self.O,), np.uint8),
             PBA_DBG_DTHETA: ((n6,), np.float64),

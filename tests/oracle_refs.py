@@ -47,11 +47,11 @@ def trans_rel_err(P1, P2):
     return np.linalg.norm(t1 - t2, axis=1) / scale
 
 
-def depth_errors_ok(d, d_ref, q99=1e-5, worst=1e-3):
-    """Relative inverse-depth agreement of a single-precision result with the
-    FP64 oracle: the 99th percentile within q99, every point within `worst`.
-    A point whose depth is weakly determined (small H_dd: its texture gradient
-    nearly orthogonal to the epipolar lines) amplifies the FP32 rounding of its
-    residual sums by 1 / H_dd; such points set the maximum, not the bulk."""
+def depth_errors_ok(d, d_ref, bar=1e-5):
+    """Relative inverse-depth agreement of a result with the FP64 oracle,
+    gated on the worst point (the measurement contract's 1e-5 relative bar).
+    Returns (ok, 99th percentile, maximum); the statistics go into the
+    assertion message."""
     rel = np.abs(d / d_ref - 1.0)
-    return np.quantile(rel, 0.99) <= q99 and rel.max() <= worst, float(np.quantile(rel, 0.99)), float(rel.max())
+    worst = float(rel.max()) if rel.size else 0.0
+    return worst <= bar, float(np.quantile(rel, 0.99)) if rel.size else 0.0, worst

@@ -142,9 +142,8 @@ def test_tiny_fp64_ten_iterations(tiny, mode):
 @pytest.mark.parametrize("mode", ["ic", "fc"])
 def test_mid_fp32_pyramid_parity(mid_full, mode):
     """FP32 library vs FP64 oracle on the full mid workload (20000 points), 3-level
-    pyramid, 8 iterations per level: poses and RMSE within the contract's bar;
-    inverse depths within it for 99% of the points (weakly determined depths
-    amplify single-precision rounding, see depth_errors_ok)."""
+    pyramid, 8 iterations per level: poses, every inverse depth and the RMSE
+    within the contract's bar."""
     s = make(mid_full, mode, 1)
     gn = GaussNewton(Problem.from_scene(mid_full), mode)
     for level in (2, 1, 0):

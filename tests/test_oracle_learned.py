@@ -84,6 +84,36 @@ def test_loss_minimizer_and_identity():
                                rtol=1e-10)
 
 
+def test_optimal_blocks_are_the_loss_minimizer():
+    """optimal_blocks: on a block-diagonal system (G = 0) it is block Jacobi;
+    in general its whitened blocks are the stationary point of the block loss
+    (dense inverse of I + G, computed here from the densely whitened S^2), and
+    no perturbed output has a lower loss."""
+    S = random_spd(24, 9)
+    Sd = np.zeros_like(S)
+    for i in range(4):
+        Sd[6 * i:6 * i + 6, 6 * i:6 * i + 6] = S[6 * i:6 * i + 6, 6 * i:6 * i + 6]
+    np.testing.assert_allclose(LP.optimal_blocks(Sd), LP.jacobi_blocks(Sd), rtol=1e-10, atol=1e-14)
+    C, Ci, G = LP.block_whitening(S)
+    D = sl.block_diag(*Ci)
+    Sh = D @ S @ D.T
+    Sh2 = Sh @ Sh
+    P = LP.optimal_blocks(S)
+    for i in range(4):
+        want = np.linalg.inv(Sh2[6 * i:6 * i + 6, 6 * i:6 * i + 6])      # (I + G_i)^{-1} = ((S^ S^)_ii)^{-1}
+        np.testing.assert_allclose(C[i].T @ P[i] @ C[i], want, rtol=1e-9, atol=1e-12)
+    rng = np.random.default_rng(3)
+    Y = np.zeros((4, 21))
+    for i in range(4):
+        Lm = np.linalg.cholesky(C[i].T @ P[i] @ C[i])
+        for k, (r, c) in enumerate(LP.TRI):
+            Y[i, k] = np.log(Lm[r, c]) if r == c else Lm[r, c]
+    best, _ = LP.block_loss(Y, G)
+    for _ in range(20):
+        worse, _ = LP.block_loss(Y + 1e-3 * rng.normal(size=Y.shape), G)
+        assert np.all(worse >= best - 1e-12)
+
+
 def test_gradients_match_finite_differences():
     rng = np.random.default_rng(6)
     p = LP.init_params(7)
