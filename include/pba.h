@@ -330,6 +330,28 @@ pba_status pba_pc_infer(pba_ctx *ctx, int32_t n_samples, const float *G, float *
 pba_status pba_solve_reduced(pba_ctx *ctx, int32_t solver, double tol, int32_t max_iters, double *x_out,
                              pba_reduced_report *rep);
 
+/* ---- Cholesky solve without allocation
+ * For callers that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): the PBA_SOLVER_CHOL path of
+ * pba_solve_reduced (the tiled FP64-MFMA Cholesky and the tile-blocked triangular
+ * solves) applied to a caller's system, with no context and no allocation. The
+ * factor, the inverses of its diagonal tiles and a failure flag live in a static
+ * scratch array of the library (4.9 MB, one copy per GPU, held until the process ends).
+ *   n     unknowns, 1 .. PBA_NOALLOC_MAX_N; larger systems are rejected (PBA_E_INVALID)
+ *   S     device, double [n][n] row-major, symmetric positive definite (read only)
+ *   b     device, double [n];  x: device, double [n], receives x = -S^{-1} b
+ *   info  device int32 or NULL: 0 after a successful factorization, 1 if a pivot was
+ *         not positive (x is then not written)
+ *   stream  hipStream_t (NULL: the null stream)
+ * Asynchronous on `stream`: returns after enqueueing (PBA_OK), or before any device work
+ * on an invalid argument. Every call on one GPU shares its scratch array, which keeps the
+ * last call's contents (the call clears the flag itself): calls that overlap on one GPU
+ * (other streams, other host threads) race and must be serialized by the caller.
+ * The first call on a device looks up the array's device address (no allocation). */
+#define PBA_NOALLOC_MAX_N 768
+pba_status pba_solve_dense_noalloc(int32_t n, const double *S, const double *b, double *x, int32_t *info,
+                                   void *stream);
+
 /* Copy an internal buffer (PBA_DBG_*) to host memory; bytes must match its size exactly. */
 pba_status pba_debug_fetch(pba_ctx *ctx, int32_t what, void *out, size_t bytes);
 

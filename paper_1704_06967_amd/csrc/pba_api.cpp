@@ -1055,6 +1055,10 @@ std::string pc_system_check(Ctx &c) {
 
 // ================================================================ C ABI
 
+namespace pba {
+pba_status fail_global(pba_status s, const std::string &msg) { return fail(nullptr, s, msg); }
+}  // namespace pba
+
 extern "C" {
 
 const char *pba_status_string(pba_status s) {

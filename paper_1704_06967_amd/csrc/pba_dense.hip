@@ -6,6 +6,9 @@
 #include "pba_internal.hpp"
 #include "pba_tile.hpp"
 
+#include <mutex>
+#include <string>
+
 namespace pba {
 
 typedef double f64x4 __attribute__((ext_vector_type(4)));
@@ -550,32 +553,42 @@ __global__ __launch_bounds__(1024) void k_tsolve(int n, const double *__restrict
     for (int i = threadIdx.x; i < n; i += blockDim.x) x[i] = v[i];
 }
 
-void launch_tsolve(hipStream_t s, Ctx &c, const double *b, double *x) {
-    const int n = 6 * c.F;
+static void tsolve_ptrs(hipStream_t s, int n, const double *fac, const double *Linv, const double *b, double *x,
+                        const int *flag) {
     const size_t lds = ((size_t)n + tile_solve_tmp(1024)) * sizeof(double);
-    k_tsolve<<<1, 1024, lds, s>>>(n, c.d_Sfac, c.d_Linv, b, x, c.d_flag);
+    k_tsolve<<<1, 1024, lds, s>>>(n, fac, Linv, b, x, flag);
 }
 
-void launch_tchol(hipStream_t s, Ctx &c, bool copy) {
-    const int n = 6 * c.F, nt = (n + TB - 1) / TB;
-    const size_t nn = (size_t)n * n;
-    if (copy) k_copy_d<<<(unsigned)((nn + 255) / 256), 256, 0, s>>>(c.d_S, c.d_Sfac, nn, c.d_gate);
+void launch_tsolve(hipStream_t s, Ctx &c, const double *b, double *x) {
+    tsolve_ptrs(s, 6 * c.F, c.d_Sfac, c.d_Linv, b, x, c.d_flag);
+}
+
+// Tiled factorization of fac (which holds S on entry) in place; S itself is
+// read again for the diagonal tiles of the short chain.
+static void tchol_ptrs(hipStream_t s, int n, const double *S, double *fac, double *Linv, int *flag, int *gate) {
+    const int nt = (n + TB - 1) / TB;
     if (n <= TCHOL_FUSE_N) {
         // S (unchanged by the factorization) holds the diagonal tiles' values
-        k_tchol_first_panel<<<nt, 256, 0, s>>>(n, c.d_S, c.d_Sfac, c.d_Linv, c.d_flag, c.d_gate);
+        k_tchol_first_panel<<<nt, 256, 0, s>>>(n, S, fac, Linv, flag, gate);
         for (int kt = 0; kt + 1 < nt; ++kt) {
             const int m = nt - kt - 1;
-            k_tchol_update_panel<<<m * (m + 1) / 2, 256, 0, s>>>(n, kt, c.d_S, c.d_Sfac, c.d_Linv, c.d_flag,
-                                                                  c.d_gate);
+            k_tchol_update_panel<<<m * (m + 1) / 2, 256, 0, s>>>(n, kt, S, fac, Linv, flag, gate);
         }
         return;
     }
-    k_tchol_first<<<1, 256, 0, s>>>(n, c.d_Sfac, c.d_Linv, c.d_flag, c.d_gate);
+    k_tchol_first<<<1, 256, 0, s>>>(n, fac, Linv, flag, gate);
     for (int kt = 0; kt + 1 < nt; ++kt) {
         const int m = nt - kt - 1;
-        k_tchol_panel<<<m, 256, 0, s>>>(n, kt, c.d_Sfac, c.d_Linv, c.d_flag, c.d_gate);
-        k_tchol_update<<<m * (m + 1) / 2, 256, 0, s>>>(n, kt, c.d_Sfac, c.d_Linv, c.d_flag, c.d_gate);
+        k_tchol_panel<<<m, 256, 0, s>>>(n, kt, fac, Linv, flag, gate);
+        k_tchol_update<<<m * (m + 1) / 2, 256, 0, s>>>(n, kt, fac, Linv, flag, gate);
     }
+}
+
+void launch_tchol(hipStream_t s, Ctx &c, bool copy) {
+    const int n = 6 * c.F;
+    const size_t nn = (size_t)n * n;
+    if (copy) k_copy_d<<<(unsigned)((nn + 255) / 256), 256, 0, s>>>(c.d_S, c.d_Sfac, nn, c.d_gate);
+    tchol_ptrs(s, n, c.d_S, c.d_Sfac, c.d_Linv, c.d_flag, c.d_gate);
 }
 
 void launch_tinv(hipStream_t s, Ctx &c) {
@@ -588,4 +601,73 @@ void launch_tinv(hipStream_t s, Ctx &c) {
     }
 }
 
+// ------------------------------------------------------------ solve without allocation
+// Scratch of pba_solve_dense_noalloc: the factor (n x n), the inverses of its
+// diagonal tiles, a failure flag and a gate, for systems of at most
+// PBA_NOALLOC_MAX_N unknowns (4.9 MB). Each GPU the library runs on holds its
+// own copy until the process ends; every call on that GPU shares it. In host
+// code `scratch` names a host-side stand-in, never the device memory: kernels
+// get the address that hipGetSymbolAddress returns for the current device.
+constexpr int NOALLOC_NT = PBA_NOALLOC_MAX_N / TB;
+static_assert(PBA_NOALLOC_MAX_N % TB == 0, "whole tiles");
+constexpr size_t NOALLOC_FAC = (size_t)PBA_NOALLOC_MAX_N * PBA_NOALLOC_MAX_N;
+constexpr size_t NOALLOC_LINV = (size_t)NOALLOC_NT * TB * TB;
+constexpr size_t NOALLOC_DOUBLES = NOALLOC_FAC + NOALLOC_LINV + 2;   // + flag, gate (one int per double)
+static __device__ __align__(256) double scratch[NOALLOC_DOUBLES];
+
+constexpr int NOALLOC_MAX_DEVICES = 64;
+static std::mutex g_scratch_mu;
+static double *g_scratch_dev[NOALLOC_MAX_DEVICES];   // device address of `scratch` per device
+
+// Copy S into the factor buffer; clear the failure flag and open the gate.
+__global__ void k_noalloc_begin(int n, const double *__restrict__ S, double *__restrict__ fac,
+                                int *__restrict__ flag, int *__restrict__ gate) {
+    const size_t nn = (size_t)n * n;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < nn; i += (size_t)gridDim.x * blockDim.x)
+        fac[i] = S[i];
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        *flag = 0;
+        *gate = 1;
+    }
+}
+
+__global__ void k_noalloc_info(const int *__restrict__ flag, int *__restrict__ info) {
+    if (threadIdx.x == 0) *info = *flag ? 1 : 0;
+}
+
 }  // namespace pba
+
+extern "C" pba_status pba_solve_dense_noalloc(int32_t n, const double *S, const double *b, double *x,
+                                              int32_t *info, void *stream) {
+    using namespace pba;
+    if (n < 1 || n > PBA_NOALLOC_MAX_N)
+        return fail_global(PBA_E_INVALID, "n must be in 1..PBA_NOALLOC_MAX_N (768)");
+    if (!S || !b || !x) return fail_global(PBA_E_INVALID, "S, b and x must be device pointers (not NULL)");
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= NOALLOC_MAX_DEVICES)
+        return fail_global(PBA_E_DEVICE, "no usable current device");
+    double *base = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(g_scratch_mu);
+        if (!g_scratch_dev[dev]) {
+            void *p = nullptr;
+            const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+            if (e != hipSuccess || !p)
+                return fail_global(PBA_E_DEVICE, std::string("hipGetSymbolAddress: ") + hipGetErrorString(e));
+            g_scratch_dev[dev] = static_cast<double *>(p);
+        }
+        base = g_scratch_dev[dev];
+    }
+    double *fac = base, *Linv = base + NOALLOC_FAC;
+    int *flag = reinterpret_cast<int *>(base + NOALLOC_FAC + NOALLOC_LINV);
+    int *gate = reinterpret_cast<int *>(base + NOALLOC_FAC + NOALLOC_LINV + 1);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const size_t nn = (size_t)n * n;
+    k_noalloc_begin<<<(unsigned)std::min<size_t>(1024, (nn + 255) / 256), 256, 0, s>>>(n, S, fac, flag, gate);
+    tchol_ptrs(s, n, S, fac, Linv, flag, gate);
+    tsolve_ptrs(s, n, fac, Linv, b, x, flag);
+    if (info) k_noalloc_info<<<1, 64, 0, s>>>(flag, info);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail_global(PBA_E_DEVICE, std::string("launch: ") + hipGetErrorString(e));
+    return PBA_OK;
+}

@@ -319,6 +319,8 @@ void launch_open(hipStream_t s, Ctx &c, int level, bool clear_flag);
 void launch_ic_inverse(hipStream_t s, Ctx &c);
 void launch_tchol(hipStream_t s, Ctx &c, bool copy = true);   // (copy S to d_Sfac and) factor d_Sfac in tiles
 void launch_tinv(hipStream_t s, Ctx &c);    // S^{-1} from the tiled factor
+// Error of a call that has no context: recorded for pba_last_error(NULL).
+pba_status fail_global(pba_status s, const std::string &msg);
 void launch_copy_d(hipStream_t s, const double *src, double *dst, size_t n);  // device copy as a kernel
 void launch_fill(hipStream_t s, double *p, size_t n, double v, const int *gate);
 

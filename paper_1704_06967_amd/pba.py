@@ -18,6 +18,7 @@ PBA_FP64, PBA_FP32, PBA_MIXED_BF16 = 0, 1, 2
 PBA_SOLVER_CHOL, PBA_SOLVER_PCG_JACOBI, PBA_SOLVER_PCG_LEARNED, PBA_SOLVER_PCG_BLOCKOPT = 0, 1, 2, 3
 PBA_PC_N_PARAMS = 77077
 PBA_HOST, PBA_DEVICE = 0, 1
+PBA_NOALLOC_MAX_N = 768
 PBA_FLAG_TIMING, PBA_FLAG_GRAPH = 1, 2
 PBA_MAX_PATTERN = 8
 PBA_MAX_LEVELS = 4
@@ -134,6 +135,7 @@ _sig = {
     "pba_pc_gradient": (C.c_int, [_P, C.c_int32, _P, C.POINTER(C.c_double), _P]),
     "pba_pc_infer": (C.c_int, [_P, C.c_int32, _P, _P]),
     "pba_solve_reduced": (C.c_int, [_P, C.c_int32, C.c_double, C.c_int32, _P, C.POINTER(pba_reduced_report)]),
+    "pba_solve_dense_noalloc": (C.c_int, [C.c_int32, _P, _P, _P, _P, _P]),
     "pba_destroy": (None, [_P]),
     "pba_last_error": (C.c_char_p, [_P]),
     "pba_status_string": (C.c_char_p, [C.c_int]),

@@ -136,3 +136,14 @@ def test_create_accepts_documented_limits(field, value):
     assert pba.pba_create(C.byref(cfg), C.byref(h)) == pba.PBA_E_DEVICE, pba.last_error()
     cfg.n_windows = pba.PBA_MAX_WINDOWS + 1
     assert pba.pba_create(C.byref(cfg), C.byref(h)) == pba.PBA_E_INVALID
+
+
+def test_noalloc_solve_rejects_sizes_before_device_work():
+    """pba_solve_dense_noalloc validates n and its pointers before any HIP call
+    (no GPU here): sizes outside 1..PBA_NOALLOC_MAX_N and NULL buffers."""
+    import ctypes as C
+    for n in (0, -3, pba.PBA_NOALLOC_MAX_N + 1):
+        assert pba.pba_solve_dense_noalloc(n, C.c_void_p(8), C.c_void_p(8), C.c_void_p(8), None, None) == pba.PBA_E_INVALID
+        assert "768" in pba.last_error()
+    assert pba.pba_solve_dense_noalloc(16, None, C.c_void_p(8), C.c_void_p(8), None, None) == pba.PBA_E_INVALID
+
