@@ -120,6 +120,13 @@ typedef struct {
                             or conv_px change, and when pba_autotune picks a launch
                             shape. pba_iterate never uses the graph */
     void *stream;        /* hipStream_t to run on, or NULL for a library-owned stream */
+    int32_t recentre_every; /* proxy re-centring (Sec. 3.6: the proxy update holds near
+                            p(0)): with m > 0, IC re-linearizes after every m
+                            iterations of a level, with p(0) the current parameters (J,
+                            W0, H, S and S^-1 formed again, as at a level start); within
+                            pba_solve's device schedule, captured graphs included, and
+                            across pba_iterate calls. 0 (default): the paper's IC.
+                            0..1000; ignored by FC */
 } pba_config;
 
 typedef struct {

@@ -19,6 +19,13 @@ level's p(0) (a residual that later leaves the image, or whose point moves
 behind the camera, gets weight 0 for that iteration); p(0) is re-centred at
 the start of every pyramid level; the convergence test (Sec. 4.1) takes the
 largest level-0 pixel displacement of any observation's point centre.
+
+Proxy re-centring (hybrid schedule): the final update equations of Sec. 3.6
+rest on approximations that hold while the parameters stay near p(0) (the
+proxy depth taken as 1/d0 and d0/d taken as 1). With recentre_every = m > 0
+the IC iteration re-centres after every m iterations of a level: p(0) becomes
+the current parameters and the level's linearization (J, W0, H, S) is formed
+again there, exactly as at the level's start. m = 0 is the paper's IC.
 """
 import numpy as np
 
@@ -67,10 +74,13 @@ class Problem:
 
 
 class GaussNewton:
-    def __init__(self, prob, mode):
+    def __init__(self, prob, mode, recentre_every=0):
         assert mode in ("fc", "ic")
+        assert recentre_every >= 0
         self.prob = prob
         self.mode = mode
+        self.recentre_every = int(recentre_every) if mode == "ic" else 0
+        self.since = 0   # iterations since the last linearization of the level
         self.poses = prob.poses_init.copy()
         self.d = prob.inv_depth_init.copy()
         self.level = None
@@ -82,6 +92,7 @@ class GaussNewton:
         L = P.layout(level)
         self.level = level
         self.L = L
+        self.since = 0
         self.poses0 = self.poses.copy()
         self.d0 = self.d.copy()
         r0, valid0, _, _ = RS.warp_residuals(P, L, self.poses0, self.d0)
@@ -99,6 +110,9 @@ class GaussNewton:
 
     # ---- one Gauss-Newton iteration at the current level
     def step(self):
+        if self.recentre_every and self.since == self.recentre_every:
+            self.start_level(self.level)   # proxy re-centring: p(0) <- current parameters
+        self.since += 1
         P, L = self.prob, self.L
         r, valid, q, v = RS.warp_residuals(P, L, self.poses, self.d)
         act = self.frozen & valid

@@ -151,6 +151,7 @@ void release_frames(Ctx &c) {
     dfree(c.d_flag);
     dfree(c.d_gate);
     dfree(c.d_count);
+    dfree(c.d_count_base);
     dfree(c.d_du_part);
     dfree(c.d_pairK0);
     dfree(c.d_pc_slot);
@@ -178,6 +179,7 @@ std::string validate_config(const pba_config *cfg) {
     if (cfg->solver != PBA_SOLVER_CHOL) return "solver must be PBA_SOLVER_CHOL (PCG: pba_solve_reduced)";
     if (cfg->n_windows < 1 || cfg->n_windows > PBA_MAX_WINDOWS) return "n_windows must be in 1..PBA_MAX_WINDOWS";
     if (cfg->flags & ~(PBA_FLAG_TIMING | PBA_FLAG_GRAPH)) return "unknown flag bits";
+    if (cfg->recentre_every < 0 || cfg->recentre_every > 1000) return "recentre_every must be in 0..1000";
     return "";
 }
 
@@ -315,15 +317,17 @@ std::string build_structure(Ctx &c, const std::vector<int> &host_frame, const st
 
 // ---- level start and iterations, per element type
 // Opens the level's gate (clear_flag: also clears the failure flag) and sets up
-// the level.
+// the level. recentre: proxy re-centring inside the level (IC): the same set-up
+// at the current parameters, gated (no effect once the level's gate is closed),
+// keeping the level's iteration count.
 template <typename T>
-pba_status start_level(Ctx &c, int level, bool clear_flag) {
+pba_status start_level(Ctx &c, int level, bool clear_flag, bool recentre = false) {
     hipStream_t s = c.stream;
     if (!c.lv[level].tmpl_valid) {
         Launch<T>::make_template(s, c, level);
         c.lv[level].tmpl_valid = true;
     }
-    Launch<T>::level_begin(s, c, level, clear_flag);
+    Launch<T>::level_begin(s, c, level, clear_flag, recentre);
     c.flip = false;
     if (c.cfg.mode == PBA_IC_PROXY) {
         // J (Sec. 3.4) and W0 at p(0); H = J^T W0 J, depth Schur complement, Cholesky, inverse
@@ -345,8 +349,16 @@ pba_status start_level(Ctx &c, int level, bool clear_flag) {
     }
     HIPCHK(hipGetLastError());
     c.cur_level = level;
-    c.iters_in_level = 0;
+    if (!recentre) c.iters_in_level = 0;
+    c.since_lin = 0;
     return PBA_OK;
+}
+
+// Iterations between proxy re-centrings (0: none; FC: none).
+int recentre_every(const Ctx &c) { return c.cfg.mode == PBA_IC_PROXY ? c.cfg.recentre_every : 0; }
+
+pba_status recentre_level(Ctx &c, int level) {
+    return is_fp64(c) ? start_level<double>(c, level, false, true) : start_level<float>(c, level, false, true);
 }
 
 template <typename T>
@@ -448,13 +460,25 @@ pba_status run_iterations(Ctx &c, int level, int n_iters, pba_iter_stats *out, d
     launch_open(c.stream, c, level, true);
     const int it0 = c.iters_in_level;
     const bool flip0 = c.flip;
+    const int since0 = c.since_lin, m = recentre_every(c);
+    // segments between proxy re-centrings: each is a batch of its own (the
+    // pose buffers alternate within a batch and are synchronized at its end)
+    std::vector<int> seg_start{0};
+    int kb = 0;   // iteration within the current segment
     for (int k = 0; k < n_iters; ++k) {
+        if (m > 0 && c.since_lin == m) {
+            if ((st = recentre_level(c, level)) != PBA_OK) return st;
+            seg_start.push_back(k);
+            kb = 0;
+        }
         hipEvent_t e0 = timing ? c.ev_pool[4 * k] : nullptr, e1 = timing ? c.ev_pool[4 * k + 1] : nullptr;
         hipEvent_t e2 = timing ? c.ev_pool[4 * k + 2] : nullptr, e3 = timing ? c.ev_pool[4 * k + 3] : nullptr;
         double *stat = c.d_stats + (size_t)k * ST_STRIDE;
-        c.batch_k = k;
-        double *prev = k > 0 ? stat - ST_STRIDE : nullptr;
-        const bool last = k == n_iters - 1;
+        c.batch_k = kb;
+        double *prev = kb > 0 ? stat - ST_STRIDE : nullptr;
+        const bool last = k == n_iters - 1 || (m > 0 && c.since_lin + 1 == m);
+        ++kb;
+        c.since_lin++;
         st = is_fp64(c) ? one_iteration<double>(c, level, stat, e0, e1, conv_px, prev, last, e2, e3)
                         : one_iteration<float>(c, level, stat, e0, e1, conv_px, prev, last, e2, e3);
         if (st != PBA_OK) return st;
@@ -467,9 +491,17 @@ pba_status run_iterations(Ctx &c, int level, int n_iters, pba_iter_stats *out, d
     HIPCHK(hipMemcpyAsync(&count, c.d_count + level, sizeof(int), hipMemcpyDeviceToHost, c.stream));
     HIPCHK(hipStreamSynchronize(c.stream));
     HIPCHK(hipGetLastError());
-    // host view of the double buffers follows the iterations that actually ran
+    // host view of the double buffers follows the iterations that actually ran:
+    // those of the last segment that ran, from its start (flip0 and since0 for
+    // the segment that continues the previous call)
     c.iters_in_level = it0 + count;
-    c.flip = (count % 2 == 1) ? !flip0 : flip0;
+    {
+        size_t si = 0;
+        while (si + 1 < seg_start.size() && seg_start[si + 1] < count) ++si;
+        const int j = count - seg_start[si];
+        c.flip = (si == 0 ? flip0 : false) != (j % 2 == 1);
+        c.since_lin = (si == 0 ? since0 : 0) + j;
+    }
     n_iters = count;
     if (ran) *ran = count;
     if (timing) {
@@ -517,14 +549,19 @@ pba_status enqueue_solve(Ctx &c, int max_iters, double conv_px, bool events) {
         pba_status st = is_fp64(c) ? start_level<double>(c, level, clear) : start_level<float>(c, level, clear);
         if (st != PBA_OK) return st;
         const int slot = c.cfg.n_levels - 1 - level;
+        const int m = recentre_every(c);
         for (int k = 0; k < max_iters; ++k) {
+            // proxy re-centring every m iterations (gated: nothing once the level
+            // has converged); each segment is a batch of its own
+            const int kb = m > 0 ? k % m : k;
+            if (m > 0 && k > 0 && kb == 0 && (st = recentre_level(c, level)) != PBA_OK) return st;
             const size_t idx = (size_t)slot * max_iters + k;
             double *stat = c.d_stats + idx * ST_STRIDE;
             hipEvent_t e0 = events ? c.ev_pool[4 * idx] : nullptr, e1 = events ? c.ev_pool[4 * idx + 1] : nullptr;
             hipEvent_t e2 = events ? c.ev_pool[4 * idx + 2] : nullptr, e3 = events ? c.ev_pool[4 * idx + 3] : nullptr;
-            double *prev = k > 0 ? stat - ST_STRIDE : nullptr;
-            const bool last = k == max_iters - 1;
-            c.batch_k = k;
+            double *prev = kb > 0 ? stat - ST_STRIDE : nullptr;
+            const bool last = k == max_iters - 1 || (m > 0 && kb == m - 1);
+            c.batch_k = kb;
             st = is_fp64(c) ? one_iteration<double>(c, level, stat, e0, e1, conv_px, prev, last, e2, e3)
                             : one_iteration<float>(c, level, stat, e0, e1, conv_px, prev, last, e2, e3);
             if (st != PBA_OK) return st;
@@ -603,10 +640,16 @@ pba_status solve_batch(Ctx &c, int max_iters, double conv_px, pba_result &res) {
         res.total_iters += k;
         if (level == 0) res.converged = (k > 0 && its[k - 1].max_disp_px < conv_px) ? 1 : 0;
     }
-    // host view of the level-0 double buffers
+    // host view of the level-0 double buffers: the iterations of the last
+    // segment (since the last re-centring) that ran
     c.cur_level = 0;
     c.iters_in_level = counts[0];
-    c.flip = counts[0] % 2 == 1;
+    {
+        const int m = recentre_every(c), kl = counts[0];
+        const int seg = (m > 0 && kl > 0) ? kl - m * ((kl - 1) / m) : kl;
+        c.flip = seg % 2 == 1;
+        c.since_lin = seg;
+    }
     if (flag) {
         c.cur_level = -1;
         return fail(&c, PBA_E_NUMERIC, "reduced pose system is not positive definite");
@@ -699,8 +742,10 @@ pba_status load_frames(Ctx &c, int n_frames, int width, int height, const float 
     HIPCHK(dalloc(c.d_flag, sizeof(int)));
     HIPCHK(dalloc(c.d_gate, sizeof(int)));
     HIPCHK(dalloc(c.d_count, PBA_MAX_LEVELS * sizeof(int)));
+    HIPCHK(dalloc(c.d_count_base, PBA_MAX_LEVELS * sizeof(int)));
     HIPCHK(hipMemsetAsync(c.d_flag, 0, sizeof(int), c.stream));
     HIPCHK(hipMemsetAsync(c.d_count, 0, PBA_MAX_LEVELS * sizeof(int), c.stream));
+    HIPCHK(hipMemsetAsync(c.d_count_base, 0, PBA_MAX_LEVELS * sizeof(int), c.stream));
     HIPCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize(c.stream));
     dfree(staging);

@@ -147,6 +147,7 @@ struct Ctx {
     bool have_frames = false, have_points = false;
     int cur_level = -1;            // level whose linearization / frozen set is current
     int iters_in_level = 0;
+    int since_lin = 0;   // iterations since the level's (re-)linearization
 
     // frames
     int F = 0, W = 0, H = 0;
@@ -216,6 +217,7 @@ struct Ctx {
     int *d_flag = nullptr;                             // device error flag (non-SPD)
     int *d_gate = nullptr;                             // 1 while the current solve level runs
     int *d_count = nullptr;                            // iterations run per level [PBA_MAX_LEVELS]
+    int *d_count_base = nullptr;                       // of those, before the level's last re-centring
     double *d_du_part = nullptr;                       // depth-update block maxima [blocks][2]
     double *d_pairK0 = nullptr;                        // [Pn][8] level-0 intrinsics of host and target
     int *d_pc_slot = nullptr;  // [pair chunks][PAIR_CHUNK][4] observation (-1: none), point, point's range
@@ -257,7 +259,7 @@ template <typename T> struct Launch {
     static void ic_linearize(hipStream_t s, Ctx &c, int level);
     // e0 / e1 (optional): events recorded by the dispatch itself at the kernel's start and end
     // level start: gate / flag / count, p(0) copies, relative poses at p(0) (one launch)
-    static void level_begin(hipStream_t s, Ctx &c, int level, bool clear_flag);
+    static void level_begin(hipStream_t s, Ctx &c, int level, bool clear_flag, bool recentre = false);
     static void ic_residual(hipStream_t s, Ctx &c, int level, const double *geo_cur, hipEvent_t e0 = nullptr,
                             hipEvent_t e1 = nullptr);
     static void ic_residual_shape(hipStream_t s, Ctx &c, int level, const double *geo_cur, LaunchShape sh,

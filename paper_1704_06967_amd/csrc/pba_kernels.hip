@@ -115,19 +115,26 @@ __global__ void k_relpose(int Pn, const int *__restrict__ pair_host, const int *
 // Start of a level, one launch: the level's gate, failure flag (cleared with
 // clear_flag) and iteration count; p(0) copies of the poses and inverse depths;
 // the relative poses of every pair at p(0), kept as the IC linearization point
-// (geo0, rel0) and as the current iterate (geo_a, rel_a).
+// (geo0, rel0) and as the current iterate (geo_a, rel_a). With recentre set
+// (proxy re-centring inside a level) the gate, flag and count are left as they
+// are, nothing happens once the gate is closed, and count_base receives the
+// iterations run so far (the pose buffers alternate from this point on).
 template <typename T>
 __global__ void k_level_begin(int F, int N, int Pn, const double *__restrict__ poses, double *__restrict__ poses0,
                               const double *__restrict__ depth, double *__restrict__ depth0,
                               const int *__restrict__ pair_host, const int *__restrict__ pair_target,
                               double *__restrict__ geo0, T *__restrict__ rel0, double *__restrict__ geo_a,
                               T *__restrict__ rel_a, int *__restrict__ gate, int *__restrict__ flag,
-                              int *__restrict__ count, int clear_flag) {
+                              int *__restrict__ count, int *__restrict__ count_base, int clear_flag, int recentre) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i == 0) {
+    if (recentre) {
+        if (*gate == 0) return;
+        if (i == 0) *count_base = *count;
+    } else if (i == 0) {
         if (clear_flag) *flag = 0;
         *gate = *flag == 0 ? 1 : 0;
         *count = 0;
+        *count_base = 0;
     }
     if (i < 12 * F) poses0[i] = poses[i];
     if (i < N) depth0[i] = depth[i];
@@ -644,6 +651,7 @@ struct ConvArgs {
     double conv_px;
     int *gate, *count;
     const int *flag;
+    const int *count_base;   // iterations before the last re-centring of the level
 };
 
 // Statistics of an iteration from the block maxima (largest point-centre
@@ -916,7 +924,7 @@ static ResArgs<T> res_args(Ctx &c, int level, const double *geo_cur) {
 }
 
 static ConvArgs conv_args(Ctx &c, double *stat, double conv_px, int level) {
-    return ConvArgs{c.d_wstat, c.nwin, stat, conv_px, c.d_gate, c.d_count + level, c.d_flag};
+    return ConvArgs{c.d_wstat, c.nwin, stat, conv_px, c.d_gate, c.d_count + level, c.d_flag, c.d_count_base + level};
 }
 
 // Gradient records of the current iteration: the compact IC records or the
@@ -967,12 +975,13 @@ void Launch<T>::make_template(hipStream_t s, Ctx &c, int level) {
 }
 
 template <typename T>
-void Launch<T>::level_begin(hipStream_t s, Ctx &c, int level, bool clear_flag) {
+void Launch<T>::level_begin(hipStream_t s, Ctx &c, int level, bool clear_flag, bool recentre) {
     const int m = std::max(std::max(12 * c.F, c.N), std::max(c.st.n_pairs, 1));
     k_level_begin<T><<<nblk(m, 256), 256, 0, s>>>(c.F, c.N, c.st.n_pairs, c.d_poses, c.d_poses0, c.d_depth,
                                                   c.d_depth0, c.d_pair_host, c.d_pair_target, c.d_geo0,
                                                   (T *)c.d_rel0, c.d_geo_a, (T *)c.d_rel_a, c.d_gate, c.d_flag,
-                                                  c.d_count + level, clear_flag ? 1 : 0);
+                                                  c.d_count + level, c.d_count_base + level, clear_flag ? 1 : 0,
+                                                  recentre ? 1 : 0);
     CHECK_LAUNCH();
 }
 
@@ -1151,7 +1160,7 @@ __global__ __launch_bounds__(256) void k_conv(const double *__restrict__ part, i
     }
     if (np == 0) return;
     __syncthreads();
-    if (threadIdx.x == 0) ran = *cv.count;
+    if (threadIdx.x == 0) ran = *cv.count - *cv.count_base;
     __syncthreads();
     if (ran & 1)
         for (int e = threadIdx.x; e < np; e += blockDim.x) pose[e] = pose_alt[e];
@@ -1160,11 +1169,13 @@ __global__ __launch_bounds__(256) void k_conv(const double *__restrict__ part, i
 // Start of a batch of iterations: clear the level's iteration count and
 // (clear_flag) the failure flag, and open the gate unless a failure is flagged
 // (a kernel, so that it can be captured in a graph).
-__global__ void k_open(int *__restrict__ gate, int *__restrict__ flag, int *__restrict__ count, int clear_flag) {
+__global__ void k_open(int *__restrict__ gate, int *__restrict__ flag, int *__restrict__ count,
+                       int *__restrict__ count_base, int clear_flag) {
     if (threadIdx.x == 0) {
         if (clear_flag) *flag = 0;
         *gate = *flag == 0 ? 1 : 0;
         *count = 0;
+        *count_base = 0;
     }
 }
 
@@ -1175,7 +1186,7 @@ void launch_conv(hipStream_t s, Ctx &c, double *stat, double conv_px, int nparts
 }
 
 void launch_open(hipStream_t s, Ctx &c, int level, bool clear_flag) {
-    k_open<<<1, 64, 0, s>>>(c.d_gate, c.d_flag, c.d_count + level, clear_flag ? 1 : 0);
+    k_open<<<1, 64, 0, s>>>(c.d_gate, c.d_flag, c.d_count + level, c.d_count_base + level, clear_flag ? 1 : 0);
     CHECK_LAUNCH();
 }
 

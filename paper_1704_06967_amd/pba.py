@@ -33,7 +33,7 @@ class pba_config(C.Structure):
         ("mode", C.c_int32), ("precision", C.c_int32), ("n_levels", C.c_int32), ("pattern_n", C.c_int32),
         ("pattern_uv", C.c_int32 * (2 * PBA_MAX_PATTERN)), ("huber_k", C.c_double), ("damping_rel", C.c_double),
         ("pinned_frame", C.c_int32), ("solver", C.c_int32), ("n_windows", C.c_int32), ("flags", C.c_int32),
-        ("stream", C.c_void_p),
+        ("stream", C.c_void_p), ("recentre_every", C.c_int32),
     ]
 
 
