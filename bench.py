@@ -30,10 +30,11 @@ import numpy as np  # noqa: E402
 
 HBM_PEAK_GBS = 8000.0
 # HBM bytes per level-0 launch of k_ic_residual<float> from two rocprofv3 counter
-# runs (FETCH_SIZE x 2.000 + WRITE_SIZE x 1.000, scales from a 256 MiB device copy;
-# profiles/k_ic_residual_traffic_mid_precision.md), valid for the kernel source with
-# this hash only
-MEASURED_TRAFFIC = {"mid": 24468431, "precision": 202061042, "kernels_sha256_16": "d907afdac7c1cd53"}
+# runs: FETCH_SIZE (bytes the L2 fetched from HBM or the memory-attached last-level
+# cache, i.e. L2 misses) x 2.000 + WRITE_SIZE x 1.000, both scales from a 256 MiB
+# device copy (profiles/k_ic_residual_traffic_mid_precision.md); valid for the
+# kernel source with this hash only
+MEASURED_TRAFFIC = {"mid": 16143360, "precision": 122100736, "kernels_sha256_16": "f339c43964b075a7"}
 
 
 def measured_traffic(workload):
@@ -198,7 +199,13 @@ def rmse_vs_time(pba, scene, mode, precision, conv_px, caps=CAPS, reps=3, recent
     pts = []
     for k in caps:
         s.set_params(p0, d0)
-        s.solve(k, conv_px)  # capture
+        try:
+            s.solve(k, conv_px)  # capture
+        except pba.PbaError as e:
+            # the iteration diverged: the solver stops on an indefinite reduced system
+            pts.append({"cap": k, "error": str(e)})
+            log(f"  {'IC' if mode == pba.PBA_IC_PROXY else 'FC'} recentre={recentre} cap {k}: {e}")
+            break
         ts, res = [], None
         for _ in range(reps):
             s.set_params(p0, d0)
@@ -206,6 +213,10 @@ def rmse_vs_time(pba, scene, mode, precision, conv_px, caps=CAPS, reps=3, recent
             res, _ = s.solve(k, conv_px)
             ts.append(time.perf_counter() - t0)
         r = res.as_dict()
+        if not (np.isfinite(r["final_rmse"]) and r["final_rmse"] > 0):
+            # every residual left the images: the iteration diverged
+            pts.append({"cap": k, "error": f"final RMSE {r['final_rmse']} (no active residual)"})
+            break
         pts.append({"cap": k, "ms": round(float(np.median(ts)) * 1e3, 4), "rmse": r["final_rmse"],
                     "iters": r["iters"][:scene.n_levels], "converged": bool(r["converged"])})
         if all(i < k for i in r["iters"][:scene.n_levels]):
@@ -227,27 +238,31 @@ def equal_rmse_section(pba, scene, precision, conv_px, final_cap, caps=CAPS, rec
               "fc": rmse_vs_time(pba, scene, pba.PBA_FC, precision, conv_px, caps)}
 
     def at_cap(pts):
-        sel = [p for p in pts if p["cap"] <= final_cap]
-        return sel[-1]["rmse"]
+        sel = [p for p in pts if p["cap"] <= final_cap and "rmse" in p]
+        return sel[-1]["rmse"] if sel else None
 
     r_star = max(at_cap(curves["ic"]), at_cap(curves["fc"]))
 
     def first(pts):
-        ok = [p for p in pts if p["rmse"] <= r_star * (1 + 1e-3)]
+        ok = [p for p in pts if "rmse" in p and p["rmse"] <= r_star * (1 + 1e-3)]
         return min(ok, key=lambda p: p["ms"]) if ok else None
 
     out = {"r_star": r_star, "final_cap": final_cap}
     for name, pts in curves.items():
         f = first(pts)
-        best = min(pts, key=lambda p: p["rmse"])
+        good = [p for p in pts if "rmse" in p]
+        best = min(good, key=lambda p: p["rmse"])
         out[name] = {"ms_to_r_star": f["ms"] if f else None, "cap_to_r_star": f["cap"] if f else None,
                      "final_rmse": at_cap(pts), "best_rmse": best["rmse"], "best_cap": best["cap"],
-                     "converged": pts[-1]["converged"], "curve": pts}
+                     "converged": good[-1]["converged"], "diverged_at_cap": pts[-1]["cap"] if "error" in pts[-1]
+                     else None, "curve": pts}
     a, b = out["ic"]["ms_to_r_star"], out["fc"]["ms_to_r_star"]
     out["ic_speedup"] = round(b / a, 3) if a and b else None
     out["note"] = ("whole solves (graph launches) with at most `cap` iterations per level, timed to completion; "
-                   "IC's level-0 RMSE rises after its first few iterations on this workload (its Jacobian departs "
-                   "from -J_FC as host-target baselines widen), so r* is set by IC's final solve")
+                   "IC's level-0 RMSE rises after its first few iterations on this workload (its fixed point is "
+                   "not FC's), so r* is set by IC's final solve; with re-centring the iteration diverges at larger "
+                   "caps (diverged_at_cap: the solver reported an indefinite reduced system or lost every "
+                   "residual)")
     return out
 
 
@@ -341,7 +356,7 @@ def errors_vs_oracle(pba, sc, precision, oracle, iters=ORACLE_LEVEL_ITERS):
     return e
 
 
-def precision_section(pba, steps, max_iters, conv_px, sc=None):
+def precision_section(pba, steps, max_iters, conv_px, sc=None, event_timing=True):
     """The precision workload (120 frames 640x480 around a value-noise torus,
     10 hosts x 20000 points, 6.4M residuals per level-0 iteration, 6F = 720):
     IC in the mixed form (BF16 MFMA pose blocks) timed per solve, and its result
@@ -374,15 +389,17 @@ def precision_section(pba, steps, max_iters, conv_px, sc=None):
         poses, d = s.get_params()
         results[name] = (poses, d)
         s.close()
-        e = pba.Solver(mode=mode, precision=prec, flags=pba.PBA_FLAG_TIMING, **kw)
-        e.set_scene(sc)
-        e.set_params(p0, d0)
-        e.solve(max_iters, conv_px)
-        e.timing()
-        e.set_params(p0, d0)
-        e.solve(max_iters, conv_px)
-        tm = e.timing()
-        e.close()
+        tm = {"residual_ms": [0.0] * 4, "residual_launches": [0] * 4}
+        if event_timing:
+            e = pba.Solver(mode=mode, precision=prec, flags=pba.PBA_FLAG_TIMING, **kw)
+            e.set_scene(sc)
+            e.set_params(p0, d0)
+            e.solve(max_iters, conv_px)
+            e.timing()
+            e.set_params(p0, d0)
+            e.solve(max_iters, conv_px)
+            tm = e.timing()
+            e.close()
         avg_us = tm["residual_ms"][0] / max(1, tm["residual_launches"][0]) * 1e3
         out[name] = {"ms_per_solve": round(float(np.mean(t)) * 1e3, 3), "iters_per_solve": res[-1]["iters"],
                      "gn_iters_per_s": round(iters / float(np.sum(t)), 2),
@@ -597,6 +614,8 @@ def main():
     ap.add_argument("--conv-px", type=float, default=5e-3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-trace", action="store_true", help="skip the equal-RMSE sweeps")
+    ap.add_argument("--no-event-timing", action="store_true",
+                    help="skip the contexts that time kernels with HIP events (the rooflines then read 0)")
     ap.add_argument("--fc-steps", type=int, default=None, help="FC solves to time (default: --steps)")
     ap.add_argument("--no-precision", action="store_true", help="skip the precision-workload section")
     ap.add_argument("--no-oracle-check", action="store_true",
@@ -655,18 +674,22 @@ def main():
     # contexts without graphs time the residual kernels with HIP events
     ic = pba.Solver(mode=pba.PBA_IC_PROXY, flags=pba.PBA_FLAG_GRAPH, **kw)
     fc = pba.Solver(mode=pba.PBA_FC, flags=pba.PBA_FLAG_GRAPH, **kw)
-    ic_ev = pba.Solver(mode=pba.PBA_IC_PROXY, flags=pba.PBA_FLAG_TIMING, **kw)
-    fc_ev = pba.Solver(mode=pba.PBA_FC, flags=pba.PBA_FLAG_TIMING, **kw)
-    for s in (ic, fc, ic_ev, fc_ev):
+    twins = not args.no_event_timing
+    ic_ev = pba.Solver(mode=pba.PBA_IC_PROXY, flags=pba.PBA_FLAG_TIMING, **kw) if twins else None
+    fc_ev = pba.Solver(mode=pba.PBA_FC, flags=pba.PBA_FLAG_TIMING, **kw) if twins else None
+    ctxs = [s for s in (ic, fc, ic_ev, fc_ev) if s is not None]
+    for s in ctxs:
         s.set_scene(scene)
     p0, d0 = scene.poses_init, scene.inv_depth_init
 
     for _ in range(args.warmup):
-        for s in (ic, fc, ic_ev, fc_ev):
+        for s in ctxs:
             s.set_params(p0, d0)
             s.solve(args.max_iters, args.conv_px)
-    ic_ev.timing()
-    fc_ev.timing()
+    zero = {k: [0.0] * 4 for k in ("residual_launches", "residual_ms", "step_launches", "step_ms")}
+    if twins:
+        ic_ev.timing()
+        fc_ev.timing()
     log("warmup done")
 
     ic_t, ic_iters, ic_active, ic_res = run_steps(ic, p0, d0, args.steps, args.max_iters, args.conv_px)
@@ -674,10 +697,12 @@ def main():
     fc_steps = args.fc_steps or args.steps
     fc_t, fc_iters, fc_active, fc_res = run_steps(fc, p0, d0, fc_steps, args.max_iters, args.conv_px)
     log(f"FC: {fc_steps} solves, {np.mean(fc_t) * 1e3:.3f} ms each")
-    run_steps(ic_ev, p0, d0, args.steps, args.max_iters, args.conv_px)
-    ic_tm = ic_ev.timing()
-    run_steps(fc_ev, p0, d0, fc_steps, args.max_iters, args.conv_px)
-    fc_tm = fc_ev.timing()
+    ic_tm, fc_tm = zero, zero
+    if twins:
+        run_steps(ic_ev, p0, d0, args.steps, args.max_iters, args.conv_px)
+        ic_tm = ic_ev.timing()
+        run_steps(fc_ev, p0, d0, fc_steps, args.max_iters, args.conv_px)
+        fc_tm = fc_ev.timing()
 
     total = float(np.sum(ic_t))
     value = ic_iters / total
@@ -743,7 +768,8 @@ def main():
         log(f"equal RMSE (mid): {time.perf_counter() - t0:.1f} s")
     if not args.no_precision:
         line["precision_form"], precision_scene = precision_section(pba, max(1, min(args.steps, 5)), args.max_iters,
-                                                                    args.conv_px, precision_scene)
+                                                                    args.conv_px, precision_scene,
+                                                                    not args.no_event_timing)
         if not args.no_trace:
             t0 = time.perf_counter()
             line["precision_form"]["equal_rmse_fp32"] = equal_rmse_section(pba, precision_scene, pba.PBA_FP32,
@@ -769,7 +795,7 @@ def main():
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
         line["cpu_baseline"] = cpu_baseline(scene)
-    for s in (ic, fc, ic_ev, fc_ev):
+    for s in ctxs:
         s.close()
     print(json.dumps(line), flush=True)
 

@@ -227,7 +227,8 @@ __device__ __forceinline__ bool lin_eval(const ResArgs<T> &a, int o, int j, int 
     const double Rx2 = R[6] * x + R[7] * y + R[8];
     const double vx = Rx0 + d * t[0], vy = Rx1 + d * t[1], vz = Rx2 + d * t[2];
     if (!(host_ok && frozen && d > 0.0 && vz > 0.0)) return false;
-    const double ux = vx / vz, uy = vy / vz;
+    const double iz = 1.0 / vz;   // one FP64 division for the projection
+    const double ux = vx * iz, uy = vy * iz;
     const double qu = Kt[0] * ux + Kt[2], qv = Kt[1] * uy + Kt[3];
     if (!usable(qu, qv, a.W, a.H)) return false;
     const T *imf = a.img + (size_t)f * a.W * a.H;
@@ -550,7 +551,8 @@ __global__ __launch_bounds__(NB) void k_ic_residual(ResArgs<T> a) {
         const double vz = word_d(14) * x + word_d(15) * y + word_d(16) + d * word_d(19);
         const double vx = word_d(8) * x + word_d(9) * y + word_d(10) + d * word_d(17);
         const double vy = word_d(11) * x + word_d(12) * y + word_d(13) + d * word_d(18);
-        const double qu = word_d(4) * (vx / vz) + word_d(6), qv = word_d(5) * (vy / vz) + word_d(7);
+        const double iz = 1.0 / vz;   // one FP64 division for the projection (as lin_eval)
+        const double qu = word_d(4) * (vx * iz) + word_d(6), qv = word_d(5) * (vy * iz) + word_d(7);
         const bool ok = act && d > 0.0 && vz > 0.0 && usable(qu, qv, a.W, a.H);
         double If = 0.0;
         // third step: the target texels
@@ -623,7 +625,8 @@ __global__ __launch_bounds__(BLOCK) void k_evaluate(ResArgs<T> a) {
         if (tp[3] != T(0) && d > 0.0 && vz > 0.0) {
             const double vx = R[0] * x + R[1] * y + R[2] + d * t[0];
             const double vy = R[3] * x + R[4] * y + R[5] + d * t[1];
-            const double qu = Kt[0] * (vx / vz) + Kt[2], qv = Kt[1] * (vy / vz) + Kt[3];
+            const double iz = 1.0 / vz;
+            const double qu = Kt[0] * (vx * iz) + Kt[2], qv = Kt[1] * (vy * iz) + Kt[3];
             if (usable(qu, qv, a.W, a.H)) {
                 const T r = (T)((double)tp[0] - bilinear(a.img + (size_t)f * a.W * a.H, a.W, qu, qv));
                 T w, rho;

@@ -1204,9 +1204,16 @@ static void ic_step_kernel(hipStream_t s, Ctx &c, const double *geo_lin, const d
     // (the convergence kernel at the batch's end copies back after odd counts)
     const bool odd = (c.batch_k & 1) != 0;
     double *p_in = odd ? c.d_poses_alt : c.d_poses, *p_out = odd ? c.d_poses : c.d_poses_alt;
-    // with events: recorded by the dispatch itself (the kernel's own duration)
-    hipExtLaunchKernelGGL(k_ic_step<T>, dim3(1 + nb(c.N, IC_STEP_PTS)), dim3(SOLVE_THREADS), 0, s, e0, e1, 0,
-        c.win(), c.win_frame_off[1], c.win_pair_off[1], c.cfg.pinned_frame, c.d_frame_pair_ptr, c.d_frame_pair_item,
+    // with events: recorded by the dispatch itself (the kernel's own duration);
+    // without, a plain launch
+    const dim3 grid(1 + nb(c.N, IC_STEP_PTS)), block(SOLVE_THREADS);
+    auto launch = [&](auto... kargs) {
+        if (e0 || e1)
+            hipExtLaunchKernelGGL(k_ic_step<T>, grid, block, 0, s, e0, e1, 0, kargs...);
+        else
+            k_ic_step<T><<<grid, block, 0, s>>>(kargs...);
+    };
+    launch(c.win(), c.win_frame_off[1], c.win_pair_off[1], c.cfg.pinned_frame, c.d_frame_pair_ptr, c.d_frame_pair_item,
         c.d_pair_host, c.d_pair_target, c.d_pair_chunk_ptr, c.d_partY, c.d_pairY, geo_lin, c.d_Sinv, p_in, p_out,
         c.d_poses0, c.d_b, c.d_dtheta, c.d_dth_rel, geo_next, rel_next, c.d_wstat, c.d_flag, c.d_gate, c.N,
         c.d_obs_ptr, c.d_obs_pair, c.d_host_uv, c.d_pairK0, rec, gr, IC_REC, c.d_Hdd, geo_old, c.d_depth,
