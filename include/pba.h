@@ -85,15 +85,17 @@ typedef struct {
     int32_t precision;   /* PBA_FP64: all arithmetic in double. PBA_FP32: images,
                             template, residuals r, Huber weights and Jacobians in
                             float; the warp and projection of every patch pixel, the
-                            bilinear interpolant (r is rounded to float once), the
-                            per-observation sums of products (stored as double),
-                            reductions, Schur complement and Cholesky in double.
-                            PBA_MIXED_BF16: as PBA_FP32, except that every pair's
-                            pose-pose block sum w J^T J is contracted on BF16 MFMA:
-                            sqrt(w) J on a fixed-point grid per 64 residuals (three
-                            exact bfloat16 terms), FP32 accumulation that is exact
-                            on that grid, double sums across groups; h and H_dd are
-                            double sums over the same rows */
+                            bilinear interpolants of intensity and gradient (r and
+                            the forward-compositional Jacobian row are rounded to
+                            float once), the per-observation sums of products
+                            (stored as double), reductions, Schur complement and
+                            Cholesky in double. PBA_MIXED_BF16: as PBA_FP32, except
+                            that every pair's pose-pose block sum w J^T J is
+                            contracted on BF16 MFMA: sqrt(w) J on a fixed-point grid
+                            per 64 residuals (four exact bfloat16 terms), FP32
+                            accumulation that is exact on that grid, double sums
+                            across groups; h and H_dd are double sums over the same
+                            rows */
     int32_t n_levels;    /* image pyramid levels, 1..PBA_MAX_LEVELS */
     int32_t pattern_n;   /* patch pixels per point, 1..PBA_MAX_PATTERN */
     int32_t pattern_uv[2 * PBA_MAX_PATTERN]; /* (du, dv) offsets in level pixels, |du|,|dv| <= 4 */

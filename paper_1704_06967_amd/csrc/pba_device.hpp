@@ -4,7 +4,6 @@
 
 #include <hip/hip_runtime.h>
 
-#include <utility>
 
 namespace pba {
 
@@ -27,38 +26,58 @@ __device__ __forceinline__ bool usable(T u, T v, int W, int H) {
 // round the residual r = I0 - I once, at the end (to 1e-9 for |r| ~ 0.01),
 // where an FP32 interpolation would carry ~1e-7 of rounding, and an FP32
 // pixel coordinate near 600 another ~3e-5 px times the gradient.
+// The interpolant from the cell's texels (t00 t01 / t10 t11) and the position's
+// fractions (a along the row, b down the column).
+template <typename T>
+__device__ __forceinline__ double bilerp(double a, double b, T t00, T t01, T t10, T t11) {
+    return (1.0 - a) * (1.0 - b) * (double)t00 + a * (1.0 - b) * (double)t01 + (1.0 - a) * b * (double)t10 +
+           a * b * (double)t11;
+}
+
 template <typename T, typename P>
 __device__ __forceinline__ double bilinear(const T *__restrict__ im, int W, P u, P v) {
     const int j0 = (int)floor(u), i0 = (int)floor(v);
     const double a = (double)u - (double)j0, b = (double)v - (double)i0;
     const T *r0 = im + (size_t)i0 * W + j0;
     const T *r1 = r0 + W;
-    return (1.0 - a) * (1.0 - b) * (double)r0[0] + a * (1.0 - b) * (double)r0[1] + (1.0 - a) * b * (double)r1[0] +
-           a * b * (double)r1[1];
+    return bilerp(a, b, r0[0], r0[1], r1[0], r1[1]);
+}
+
+// Reciprocals. In single precision the hardware's (within 1 ulp), which is
+// what the element type carries anyway; in FP64 the correctly rounded one.
+__device__ __forceinline__ float recip(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double recip(double x) { return 1.0 / x; }
+
+// FP64 reciprocal from the hardware's approximation and two Newton steps
+// (each squares the relative error), within an ulp of 1/x for the positive,
+// normal x of a projection depth.
+__device__ __forceinline__ double recip_nr(double x) {
+    double r = __builtin_amdgcn_rcp(x);
+    r = fma(r, fma(-x, r, 1.0), r);
+    return fma(r, fma(-x, r, 1.0), r);
 }
 
 // Intensity and gradient at (u, v): the gradient is the central difference on
 // the grid, bilinearly interpolated between the four surrounding pixel centres.
-// The intensity as in bilinear (FP64); the gradient in T (it enters J only).
+// Both interpolants in FP64 from the texels (the differences of neighbouring
+// texels are formed in T, exactly when they are within a factor of two), so
+// that a single-precision caller rounds the gradient, or the Jacobian made
+// from it, once: an interpolated gradient that is small against its four
+// corners (and a Jacobian entry that cancels, such as J_d = q . t for a
+// gradient across the epipolar line) would otherwise carry the corners'
+// rounding, amplified.
 template <typename T, typename P>
-__device__ __forceinline__ void bilinear_grad(const T *__restrict__ im, int W, P u, P v, double &I, T &gu, T &gv) {
+__device__ __forceinline__ void bilinear_grad(const T *__restrict__ im, int W, P u, P v, double &I, double &gu,
+                                              double &gv) {
     const int j0 = (int)floor(u), i0 = (int)floor(v);
-    const double ad = (double)u - (double)j0, bd = (double)v - (double)i0;
-    const T a = (T)ad, b = (T)bd;
+    const double a = (double)u - (double)j0, b = (double)v - (double)i0;
     const T *rm = im + (size_t)(i0 - 1) * W + j0;  // row i0-1
     const T *r0 = rm + W;
     const T *r1 = r0 + W;
     const T *r2 = r1 + W;
-    const T i00 = r0[0], i01 = r0[1], i10 = r1[0], i11 = r1[1];
-    const T gu00 = T(0.5) * (r0[1] - r0[-1]), gu01 = T(0.5) * (r0[2] - r0[0]);
-    const T gu10 = T(0.5) * (r1[1] - r1[-1]), gu11 = T(0.5) * (r1[2] - r1[0]);
-    const T gv00 = T(0.5) * (r1[0] - rm[0]), gv01 = T(0.5) * (r1[1] - rm[1]);
-    const T gv10 = T(0.5) * (r2[0] - r0[0]), gv11 = T(0.5) * (r2[1] - r0[1]);
-    const T w00 = (T(1) - a) * (T(1) - b), w01 = a * (T(1) - b), w10 = (T(1) - a) * b, w11 = a * b;
-    I = (1.0 - ad) * (1.0 - bd) * (double)i00 + ad * (1.0 - bd) * (double)i01 + (1.0 - ad) * bd * (double)i10 +
-        ad * bd * (double)i11;
-    gu = w00 * gu00 + w01 * gu01 + w10 * gu10 + w11 * gu11;
-    gv = w00 * gv00 + w01 * gv01 + w10 * gv10 + w11 * gv11;
+    I = bilerp(a, b, r0[0], r0[1], r1[0], r1[1]);
+    gu = 0.5 * bilerp(a, b, r0[1] - r0[-1], r0[2] - r0[0], r1[1] - r1[-1], r1[2] - r1[0]);
+    gv = 0.5 * bilerp(a, b, r1[0] - rm[0], r1[1] - rm[1], r2[0] - r0[0], r2[1] - r0[1]);
 }
 
 // Huber IRLS weight and norm (eq:energy).
@@ -69,7 +88,10 @@ __device__ __forceinline__ void huber(T r, T k, T &w, T &rho) {
         w = T(1);
         rho = T(0.5) * r * r;
     } else {
-        w = k / a;
+        if constexpr (sizeof(T) == 4)
+            w = k * recip(a);
+        else
+            w = k / a;
         rho = k * a - T(0.5) * k * k;
     }
 }
@@ -80,14 +102,15 @@ __device__ __forceinline__ void huber(T r, T k, T &w, T &rho) {
 //   M = R0^T (zb I - t0 e3^T),  zb = [R0 x~ + d0 t0]_z / d0.
 // With q = (1/zb)(a0, a1, -a0 x - a1 y) and m = M^T q = zb R0 q - (t0 . R0 q) e3
 // the row is J_w = (R0 x~) x m, J_t = d0 m, J_d = m . t0.
+// id0 = 1 / d0 (formed once per point by the caller).
 template <typename T>
-__device__ __forceinline__ void ic_jacobian(T x, T y, const T *R0, const T *t0, T d0, T gu, T gv, T fx, T fy,
-                                            T J[7]) {
+__device__ __forceinline__ void ic_jacobian(T x, T y, const T *R0, const T *t0, T d0, T id0, T gu, T gv, T fx,
+                                            T fy, T J[7]) {
     const T Rx0 = R0[0] * x + R0[1] * y + R0[2];
     const T Rx1 = R0[3] * x + R0[4] * y + R0[5];
     const T Rx2 = R0[6] * x + R0[7] * y + R0[8];
-    const T zb = (Rx2 + d0 * t0[2]) / d0;
-    const T iz = T(1) / zb;
+    const T zb = (Rx2 + d0 * t0[2]) * id0;
+    const T iz = recip(zb);
     const T a0 = fx * gu, a1 = fy * gv;
     const T q0 = a0 * iz, q1 = a1 * iz, q2 = -(a0 * x + a1 * y) * iz;
     const T Rq0 = R0[0] * q0 + R0[1] * q1 + R0[2] * q2;
@@ -391,49 +414,6 @@ __device__ __forceinline__ T half_sum32(T v) {
     v = row_sum16(v);
     const T a = lane_value(v, 0) + lane_value(v, 16), b = lane_value(v, 32) + lane_value(v, 48);
     return (threadIdx.x & 32) ? b : a;
-}
-
-// Lane S of each aligned group of 8 lanes, read by every lane of the group:
-// ds_swizzle in bit-mask mode (within each 32 lanes the source is
-// (lane & 0x18) | S). An inactive source lane reads as 0, so the whole group
-// must be active.
-template <int S>
-__device__ __forceinline__ float bcast8(float v) {
-    static_assert(S >= 0 && S < 8, "a lane of the group of 8");
-    return __int_as_float(__builtin_amdgcn_ds_swizzle(__float_as_int(v), 0x18 | (S << 5)));
-}
-template <int S>
-__device__ __forceinline__ double bcast8(double v) {
-    static_assert(S >= 0 && S < 8, "a lane of the group of 8");
-    const long long b = __double_as_longlong(v);
-    const int lo = __builtin_amdgcn_ds_swizzle((int)b, 0x18 | (S << 5));
-    const int hi = __builtin_amdgcn_ds_swizzle((int)(b >> 32), 0x18 | (S << 5));
-    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
-}
-
-// Words of 16-byte slices spread over a group of 8 lanes, read by every lane
-// of the group: lane l of the group holds slice l in s0 and slice l + 8 in s1;
-// out[k] = word k % 4 of slice k / 4 (ds_swizzle in bit-mask mode, as bcast8).
-template <typename V, int... K>
-__device__ __forceinline__ void bcast8_words(const V &s0, const V &s1, int *out, std::integer_sequence<int, K...>) {
-    ((out[K] = __builtin_amdgcn_ds_swizzle(K < 32 ? s0[K % 4] : s1[K % 4], 0x18 | (((K / 4) % 8) << 5))), ...);
-}
-
-// Words B + k of the same layout, into out[B + k].
-template <int B, typename V, int... K>
-__device__ __forceinline__ void bcast8_words_range(const V &s0, const V &s1, int *out,
-                                                   std::integer_sequence<int, K...>) {
-    ((out[B + K] = __builtin_amdgcn_ds_swizzle((B + K) < 32 ? s0[(B + K) % 4] : s1[(B + K) % 4],
-                                               0x18 | ((((B + K) / 4) % 8) << 5))),
-     ...);
-}
-
-// Words B + k of the same slice layout, all from s1 (slices 8 and up): out[k]
-// = word (B + k) % 4 of slice (B + k) / 4.
-template <int B, typename V, int... K>
-__device__ __forceinline__ void bcast8_words_from(const V &s1, int *out, std::integer_sequence<int, K...>) {
-    static_assert(B >= 32, "words of the second slice register");
-    ((out[K] = __builtin_amdgcn_ds_swizzle(s1[(B + K) % 4], 0x18 | ((((B + K) / 4) % 8) << 5))), ...);
 }
 
 }  // namespace pba

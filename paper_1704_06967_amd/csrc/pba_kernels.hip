@@ -77,9 +77,11 @@ __global__ void k_template(int N, int P, PatternArg pat, const float *__restrict
     const T v = ((T)host_uv[2 * n + 1] + T(0.5)) * scale - T(0.5) + (T)pat.dv[j];
     T I = 0, gu = 0, gv = 0, ok = 0;
     if (usable(u, v, W, H)) {
-        double Id;
-        bilinear_grad(img + (size_t)host_frame[n] * W * H, W, u, v, Id, gu, gv);
+        double Id, gud, gvd;
+        bilinear_grad(img + (size_t)host_frame[n] * W * H, W, u, v, Id, gud, gvd);
         I = (T)Id;
+        gu = (T)gud;
+        gv = (T)gvd;
         ok = 1;
     }
     tmpl[4 * idx + 0] = I;
@@ -193,8 +195,8 @@ __device__ __forceinline__ void template_xy(const ResArgs<T> &a, int n, int j, c
                                             double &y) {
     const double u = ((double)a.host_uv[2 * n] + 0.5) * a.scale - 0.5 + (double)a.pat.du[j];
     const double v = ((double)a.host_uv[2 * n + 1] + 0.5) * a.scale - 0.5 + (double)a.pat.dv[j];
-    x = (u - Kh[2]) / Kh[0];
-    y = (v - Kh[3]) / Kh[1];
+    x = (u - Kh[2]) * (1.0 / Kh[0]);
+    y = (v - Kh[3]) * (1.0 / Kh[1]);
 }
 
 // Linearization of one residual (observation o, patch pixel j), shared by the
@@ -233,15 +235,18 @@ __device__ __forceinline__ bool lin_eval(const ResArgs<T> &a, int o, int j, int 
     if (!usable(qu, qv, a.W, a.H)) return false;
     const T *imf = a.img + (size_t)f * a.W * a.H;
     double If;
-    T gu, gv;
     if (IC) {
         If = bilinear(imf, a.W, qu, qv);
         const T *R0 = a.rel0 + REL_STRIDE * pr;
-        ic_jacobian((T)x, (T)y, R0, R0 + 9, (T)a.depth0[n], gu0, gv0, (T)Kh[0], (T)Kh[1], J);
+        const T d0 = (T)a.depth0[n];
+        ic_jacobian((T)x, (T)y, R0, R0 + 9, d0, recip(d0), gu0, gv0, (T)Kh[0], (T)Kh[1], J);
     } else {
+        // the row in FP64 from the FP64 gradient, rounded to T once
+        double gu, gv, Jd[7];
         bilinear_grad(imf, a.W, qu, qv, If, gu, gv);
-        const T tt[3] = {(T)t[0], (T)t[1], (T)t[2]};
-        fc_jacobian((T)Rx0, (T)Rx1, (T)Rx2, (T)vz, (T)ux, (T)uy, tt, (T)d, gu, gv, (T)Kt[0], (T)Kt[1], J);
+        fc_jacobian(Rx0, Rx1, Rx2, vz, ux, uy, t, d, gu, gv, Kt[0], Kt[1], Jd);
+#pragma unroll
+        for (int p = 0; p < 7; ++p) J[p] = (T)Jd[p];
     }
     r = (T)((double)I0 - If);   // rounded once (bilinear)
     huber(r, a.huber_k, w, rho);
@@ -322,14 +327,17 @@ __global__ __launch_bounds__(NB) void k_linearize(ResArgs<T> a, int write_mask) 
 // order), so that a wavefront's 64 residuals (8 observations x 8 patch pixels)
 // belong to one pair. The rows u = sqrt(w) J_theta of a 64-residual group are
 // put on a fixed-point grid per component p: with S_p the power of two at or
-// above the group's largest |u_p|, u_p / S_p = hi + mid + lo, each term an
-// integer (|k| <= 128) times 2^-7, 2^-15 and 2^-23, i.e. exactly a bfloat16
-// (the quantized row differs from u by at most 2^-24 S_p). Every product of
-// two such terms is an integer multiple of one unit per term pair, and 64 of
-// them (two 16x16x32 MFMAs) sum to below 2^21 units, so the FP32 accumulation
-// of v_mfma_f32_16x16x32_bf16 is exact whatever its internal order: the nine
-// term products are kept in five accumulators by unit (hi hi; hi mid + mid hi;
-// hi lo + mid mid + lo hi; mid lo + lo mid; lo lo) and added, scaled by
+// above the group's largest |u_p|, u_p / S_p = t0 + t1 + t2 + t3, term k an
+// integer (|i| <= 128) times 2^-(7 + 8k), i.e. exactly a bfloat16 (the
+// quantized row differs from u by at most 2^-32 S_p: a residual whose |u_p| is
+// 1e-3 of the group's largest keeps 2e-7 relative, where three terms left
+// 6e-5, enough to move the FC iterates of weakly constrained points by 2e-5
+// in inverse depth after 5 iterations). Every product of two such terms is an
+// integer multiple of one unit per term pair (unit k + l), and the at most 4 x
+// 64 products of one unit in a group (two 16x16x32 MFMAs per term pair) sum
+// to below 2^22 units, so the FP32 accumulation of v_mfma_f32_16x16x32_bf16
+// is exact whatever its internal order: the sixteen term products are kept in
+// seven accumulators by unit and added, smallest unit first, scaled by
 // S_p S_q, in FP64. The pose block is thus the exact Gram of the quantized
 // rows, and h and H_dd of the record are FP64 sums over the same quantized
 // rows: the per-point blocks of the depth Schur complement stay consistent
@@ -347,8 +355,8 @@ __global__ __launch_bounds__(BLOCK) void k_linearize_mixed(ResArgs<float> a, int
                                                            const int *__restrict__ chunk_end,
                                                            const int *__restrict__ pair_obs_idx,
                                                            double *__restrict__ partH) {
-    constexpr int NS = 3;  // fixed-point terms hi, mid, lo
-    constexpr int NU = 5;  // accumulators by unit: term index sum 0..4
+    constexpr int NS = 4;  // fixed-point terms
+    constexpr int NU = 7;  // accumulators by unit: term index sum 0..6
     // per wavefront: the terms of u^T as 16 x 64 bfloat16 (rows 6..15 stay zero)
     __shared__ __attribute__((aligned(16))) __bf16 ut[BLOCK / 64][NS][16][64];
     __shared__ double wsum[BLOCK / 64][36];
@@ -380,16 +388,19 @@ __global__ __launch_bounds__(BLOCK) void k_linearize_mixed(ResArgs<float> a, int
             int ex = 0;
             (void)frexp(m, &ex);                     // m < 2^ex (m = 0: ex = 0)
             scale[p] = ldexp(1.0, ex);
-            const double v = u / scale[p];           // |v| < 1, exact (power-of-two scale)
-            const double hi = rint(v * 128.0) * (1.0 / 128.0);
-            const double r1 = v - hi;                // exact, |r1| <= 2^-8
-            const double mid = rint(r1 * 32768.0) * (1.0 / 32768.0);
-            const double r2 = r1 - mid;              // exact, |r2| <= 2^-16
-            const double lo = rint(r2 * 8388608.0) * (1.0 / 8388608.0);
-            uq[p] = scale[p] * ((hi + mid) + lo);    // exact
-            ut[wv][0][p][lane] = (__bf16)(float)hi;  // each term exactly a bfloat16
-            ut[wv][1][p][lane] = (__bf16)(float)mid;
-            ut[wv][2][p][lane] = (__bf16)(float)lo;
+            double rem = u / scale[p];               // |rem| < 1, exact (power-of-two scale)
+            double q = 0.0;
+#pragma unroll
+            for (int t = 0; t < NS; ++t) {
+                // term t: rem rounded to a multiple of 2^-(7 + 8t); the
+                // remainder stays exact, |rem| <= 2^-(8 + 8t)
+                const double g = ldexp(1.0, 7 + 8 * t);
+                const double term = rint(rem * g) / g;
+                rem -= term;
+                q += term;                           // exact (fits in 53 bits)
+                ut[wv][t][p][lane] = (__bf16)(float)term;   // exactly a bfloat16
+            }
+            uq[p] = scale[p] * q;                    // exact
         }
         // per-observation fields (all but the pose-pose block: REC_h .. REC_CNT,
         // which are contiguous), FP64 sums as in k_linearize, h and H_dd over
@@ -465,142 +476,108 @@ __global__ __launch_bounds__(BLOCK) void k_linearize_mixed(ResArgs<float> a, int
 }
 
 // IC iteration: residuals at the current parameters, Huber weights, and
-// g = J^T W r with the constant proxy Jacobian (Sec. 3.5 steps 1-2). NB threads
-// per workgroup, tiles of NB / 8 observations, grid-stride over the tiles.
-// Three dependent memory steps per residual: the observation (with the gate),
-// then the point, pair pose and pair camera data, then the target texels. The
-// ten sums of an observation go out as one contiguous record (two stores per
-// wavefront).
+// g = J^T W r with the constant proxy Jacobian (Sec. 3.5 steps 1-2). One
+// thread per observation: it loads the pair's data (host and target
+// intrinsics, the current relative pose, the relative pose at p(0)) and the
+// point's once, runs the observation's patch pixels in batches of IC_PB, and
+// keeps the ten FP64 sums in registers, so no cross-lane reduction and no
+// broadcast is needed; the threads of a wavefront share the pair loads
+// through the caches. In a batch every load is issued first (templates and
+// texels; a pixel that does not contribute reads the in-bounds cell at (1, 1)
+// and is masked), then the arithmetic runs. NB threads per workgroup, tiles
+// of NB observations, grid-stride over the tiles in the XCD-aware order; the
+// ten sums go out as the observation's contiguous record.
+constexpr int IC_PB = 4;
+
 template <typename T, int NB>
 __global__ __launch_bounds__(NB) void k_ic_residual(ResArgs<T> a) {
-    const int ntiles = (a.O + NB / 8 - 1) / (NB / 8);
+    if (__builtin_amdgcn_readfirstlane(__hip_atomic_load(a.gate, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) == 0)
+        return;
+    const int ntiles = (a.O + NB - 1) / NB;
     for (int it = blockIdx.x; it < ntiles; it += gridDim.x) {
-        const int tile = xcd_tile(it, ntiles);
-        const int gid = tile * NB + threadIdx.x;
-        const int o = gid >> 3, j = gid & 7;
-        const bool in = o < a.O;
-        const int n = in ? a.obs_point[o] : 0, pr = in ? a.obs_pair[o] : 0;
-        const unsigned m = in ? (unsigned)a.mask[o] : 0u;
-        // the gate as a vector load, in flight together with the observation's
-        const int gv = __hip_atomic_load(a.gate, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        if (__builtin_amdgcn_readfirstlane(gv) == 0) return;
-        double c[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};   // FP64 products and sums (see obs_sum_field)
-        // second step: every load that depends only on (n, pr, j), issued
-        // before any branch. The pair's data (FP64 intrinsics of host and
-        // target, FP64 relative pose at the current iterate, the relative pose
-        // at p(0) in T for the Jacobian: 13 (FP32) or 16 (FP64) slices of 16
-        // bytes) and the point's host pixel and inverse depths are loaded once
-        // per observation, lane j taking slices j and j + 8 (lanes 0-2:
-        // host_uv, depth, depth0), and read across the observation's 8 lanes:
-        // the per-CU return path is what bounds this step.
-        constexpr int NSL = 10 + (12 * (int)sizeof(T)) / 16;
-        typedef int I4 __attribute__((ext_vector_type(4)));
-        const bool act = in && j < a.P && ((m >> j) & 1);
-        I4 sl0 = {0, 0, 0, 0}, sl1 = {0, 0, 0, 0};
-        double pt = 0.0;
-        if (in && m != 0u) {
-            auto slice = [&](int k) -> const I4 * {
-                if (k < 4) return reinterpret_cast<const I4 *>(a.pcam + 8 * pr + 2 * k);
-                if (k < 10) return reinterpret_cast<const I4 *>(a.geo + GEO_STRIDE * pr + 2 * (k - 4));
-                return reinterpret_cast<const I4 *>(a.rel0 + REL_STRIDE * pr) + (k - 10);
-            };
-            sl0 = *slice(j);
-            if (j + 8 < NSL) sl1 = *slice(j + 8);
-            if (j < 3)
-                pt = j == 0 ? *reinterpret_cast<const double *>(a.host_uv + 2 * n) : (j == 1 ? a.depth[n] : a.depth0[n]);
-        }
-        T tp[4] = {0, 0, 0, 0};
-        int f = 0;
-        if (act) {
+        const int o = xcd_tile(it, ntiles) * NB + threadIdx.x;
+        if (o >= a.O) continue;
+        const unsigned m = a.mask[o];
+        double c[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+        if (m != 0u) {
+            const int n = a.obs_point[o], pr = a.obs_pair[o];
+            const int f = a.pair_target[pr];
+            double K[8], G[12];   // host fx fy cx cy, target fx fy cx cy; current relative R (row-major), t
+            T R0[12];             // relative R, t at p(0)
 #pragma unroll
-            for (int k = 0; k < 4; ++k) tp[k] = a.tmpl[4 * ((size_t)n * a.P + j) + k];
-            f = a.pair_target[pr];
-        }
-        // keep the compiler from sinking these loads into the branches below
-        // (the pins follow every load, so that all of them are in flight)
-        pin_reg(sl0);
-        pin_reg(sl1);
-        pin_reg(pt);
-        pin_reg(f);
-#pragma unroll
-        for (int k = 0; k < 4; ++k) pin_reg(tp[k]);
-        // the group's camera and current-pose words (slices 0-9), read by the
-        // whole wavefront; the warp runs on every lane (no memory access),
-        // then the texels are gathered where the residual is usable
-        int q[40];
-        bcast8_words(sl0, sl1, q, std::make_integer_sequence<int, 8>{});
-        auto word_d = [&](int k) { return __hiloint2double(q[2 * k + 1], q[2 * k]); };
-        const double uv = bcast8<0>(pt), d = bcast8<1>(pt);
-        const long long uvb = __double_as_longlong(uv);
-        const double hu = (double)__int_as_float((int)uvb), hv = (double)__int_as_float((int)(uvb >> 32));
-        // pattern offset of lane j by selects (no lane-indexed argument loads)
-        int du = a.pat.du[0], dv = a.pat.dv[0];
-#pragma unroll
-        for (int k = 1; k < 8; ++k) {
-            du = j == k ? a.pat.du[k] : du;
-            dv = j == k ? a.pat.dv[k] : dv;
-        }
-        // the warp in FP64 (as template_xy and lin_eval); cam: host, target
-        // (fx, fy, cx, cy) in words 0-15, R and t in words 16-39
-        const double u = (hu + 0.5) * a.scale - 0.5 + (double)du;
-        const double v = (hv + 0.5) * a.scale - 0.5 + (double)dv;
-        const double x = (u - word_d(2)) / word_d(0), y = (v - word_d(3)) / word_d(1);
-        // the rest of the words once x and y are formed
-        pin_reg(sl0);
-        bcast8_words_range<8>(sl0, sl1, q, std::make_integer_sequence<int, 32>{});
-        const double vz = word_d(14) * x + word_d(15) * y + word_d(16) + d * word_d(19);
-        const double vx = word_d(8) * x + word_d(9) * y + word_d(10) + d * word_d(17);
-        const double vy = word_d(11) * x + word_d(12) * y + word_d(13) + d * word_d(18);
-        const double iz = 1.0 / vz;   // one FP64 division for the projection (as lin_eval)
-        const double qu = word_d(4) * (vx * iz) + word_d(6), qv = word_d(5) * (vy * iz) + word_d(7);
-        const bool ok = act && d > 0.0 && vz > 0.0 && usable(qu, qv, a.W, a.H);
-        double If = 0.0;
-        // third step: the target texels
-        if (ok) If = bilinear(a.img + (size_t)f * a.W * a.H, a.W, qu, qv);
-        // the p(0) pose words (slices 10 and up, all in sl1) only now, so that
-        // they are not held in registers across the warp
-        pin_reg(sl1);
-        constexpr int NR0 = 12 * (int)sizeof(T) / 4;
-        int q0[NR0];
-        bcast8_words_from<40>(sl1, q0, std::make_integer_sequence<int, NR0>{});
-        const double dd0 = bcast8<2>(pt);
-        if (ok) {
-            T R0[12];
+            for (int k = 0; k < 8; ++k) K[k] = a.pcam[8 * pr + k];
 #pragma unroll
             for (int k = 0; k < 12; ++k) {
-                if constexpr (sizeof(T) == 8)
-                    R0[k] = (T)__hiloint2double(q0[2 * k + 1], q0[2 * k]);
-                else
-                    R0[k] = (T)__int_as_float(q0[k]);
+                G[k] = a.geo[GEO_STRIDE * pr + k];
+                R0[k] = a.rel0[REL_STRIDE * pr + k];
             }
-            const T r = (T)((double)tp[0] - If);   // rounded once (bilinear)
-            T w, rho;
-            huber(r, a.huber_k, w, rho);
-            T J[7];
-            ic_jacobian((T)x, (T)y, R0, R0 + 9, (T)dd0, tp[1], tp[2], (T)word_d(0), (T)word_d(1), J);
-            const double wr = (double)w * r;
+            const double d = a.depth[n];
+            const T d0 = (T)a.depth0[n], id0 = recip(d0);
+            const double uc = ((double)a.host_uv[2 * n] + 0.5) * a.scale - 0.5;
+            const double vc = ((double)a.host_uv[2 * n + 1] + 0.5) * a.scale - 0.5;
+            const double ifx = 1.0 / K[0], ify = 1.0 / K[1];
+            const T fx = (T)K[0], fy = (T)K[1];
+            const T *img = a.img + (size_t)f * a.W * a.H;
+            const T *tmpl = a.tmpl + 4 * (size_t)n * a.P;
 #pragma unroll
-            for (int p = 0; p < 7; ++p) c[p] = wr * J[p];
-            c[7] = rho;
-            c[8] = (double)r * r;
-            c[9] = 1.0;
-        }
+            for (int j0 = 0; j0 < 8; j0 += IC_PB) {
+                bool ok[IC_PB];
+                double fa[IC_PB], fb[IC_PB];
+                T xs[IC_PB], ys[IC_PB], tq[IC_PB][3], tx[IC_PB][4];
+                // first step: the warps (FP64, as template_xy and lin_eval) and the loads
 #pragma unroll
-        for (int p = 0; p < 10; ++p) {
-            pin_reg(c[p]);
-            c[p] = wave_sum8(c[p]);
-        }
-        // every lane of the observation holds the sums: lane j stores field j
-        // (and lanes 0, 1 fields 8, 9), rounded to T once
-        double v0 = c[0];
+                for (int i = 0; i < IC_PB; ++i) {
+                    const int j = j0 + i;
+                    ok[i] = false;
+                    if (j >= a.P) continue;
+                    const T *tp = tmpl + 4 * j;
+                    tq[i][0] = tp[0];
+                    tq[i][1] = tp[1];
+                    tq[i][2] = tp[2];
+                    const double x = (uc + (double)a.pat.du[j] - K[2]) * ifx;
+                    const double y = (vc + (double)a.pat.dv[j] - K[3]) * ify;
+                    const double vz = G[6] * x + G[7] * y + G[8] + d * G[11];
+                    const double vx = G[0] * x + G[1] * y + G[2] + d * G[9];
+                    const double vy = G[3] * x + G[4] * y + G[5] + d * G[10];
+                    const double iz = recip_nr(vz);
+                    const double qu = K[4] * (vx * iz) + K[6], qv = K[5] * (vy * iz) + K[7];
+                    ok[i] = ((m >> j) & 1u) && d > 0.0 && vz > 0.0 && usable(qu, qv, a.W, a.H);
+                    const double su = ok[i] ? qu : 1.0, sv = ok[i] ? qv : 1.0;
+                    const double fu = floor(su), fv = floor(sv);
+                    const int cj = (int)fu, ci = (int)fv;
+                    fa[i] = su - fu;
+                    fb[i] = sv - fv;
+                    const T *r0 = img + (size_t)ci * a.W + cj;
+                    tx[i][0] = r0[0];
+                    tx[i][1] = r0[1];
+                    tx[i][2] = r0[a.W];
+                    tx[i][3] = r0[a.W + 1];
+                    xs[i] = (T)x;
+                    ys[i] = (T)y;
+                }
+                // second step: residual (rounded once), Huber weight, proxy
+                // Jacobian and the FP64 products and sums
 #pragma unroll
-        for (int p = 1; p < 8; ++p) v0 = j == p ? c[p] : v0;
-        const double v1 = j == 0 ? c[8] : c[9];
-        if (in) {
-            double *rec = a.icr + (size_t)o * IC_REC;
-            rec[j] = v0;
-            if (j < 2) rec[8 + j] = v1;
+                for (int i = 0; i < IC_PB; ++i) {
+                    if (!ok[i]) continue;
+                    const double If = bilerp(fa[i], fb[i], tx[i][0], tx[i][1], tx[i][2], tx[i][3]);
+                    const T r = (T)((double)tq[i][0] - If);
+                    T w, rho;
+                    huber(r, a.huber_k, w, rho);
+                    T J[7];
+                    ic_jacobian(xs[i], ys[i], R0, R0 + 9, d0, id0, tq[i][1], tq[i][2], fx, fy, J);
+                    const double wr = (double)w * r;
+#pragma unroll
+                    for (int p = 0; p < 7; ++p) c[p] += wr * (double)J[p];
+                    c[7] += (double)rho;
+                    c[8] += (double)r * r;
+                    c[9] += 1.0;
+                }
+            }
         }
+        double *rec = a.icr + (size_t)o * IC_REC;
+#pragma unroll
+        for (int p = 0; p < IC_REC; ++p) rec[p] = c[p];
     }
 }
 
@@ -1008,8 +985,8 @@ static void launch_ev(K kernel, unsigned g, unsigned b, hipStream_t s, hipEvent_
 
 // Grid of a launch shape: one tile of nb / 8 observations per workgroup, or a
 // persistent grid of grid_mult workgroups per compute unit striding over them.
-static unsigned shape_grid(const Ctx &c, LaunchShape sh) {
-    const size_t tiles = ((size_t)c.O * LANES_PER_OBS + sh.block - 1) / sh.block;
+static unsigned shape_grid(const Ctx &c, LaunchShape sh, int lanes_per_obs = LANES_PER_OBS) {
+    const size_t tiles = ((size_t)c.O * lanes_per_obs + sh.block - 1) / sh.block;
     if (sh.grid_mult <= 0) return (unsigned)tiles;
     return (unsigned)std::min<size_t>(tiles, (size_t)sh.grid_mult * c.n_cu);
 }
@@ -1068,7 +1045,7 @@ void Launch<T>::ic_residual_shape(hipStream_t s, Ctx &c, int level, const double
                                   hipEvent_t e0, hipEvent_t e1) {
     if (c.O == 0) return;
     ResArgs<T> a = res_args<T>(c, level, geo_cur);
-    const unsigned g = shape_grid(c, sh);
+    const unsigned g = shape_grid(c, sh, 1);
     switch (sh.block) {
         case 64: launch_ev(k_ic_residual<T, 64>, g, 64, s, e0, e1, a); break;
         case 128: launch_ev(k_ic_residual<T, 128>, g, 128, s, e0, e1, a); break;

@@ -146,3 +146,46 @@ def test_autotune_keeps_results(wins, mode):
         pb, db = b.get_params(w)
         np.testing.assert_array_equal(pa, pb)
         np.testing.assert_array_equal(da, db)
+
+
+@pytest.fixture(scope="module")
+def full_windows():
+    # the first three windows of the benchmark's batch, at the batched
+    # workload's size: 1280x720, 5-9 keyframes, 1000-3000 points per keyframe
+    return [scenes.window(i) for i in range(3)]
+
+
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("mode", ["ic", "fc"])
+def test_batched_mixed_full_size_vs_oracle(full_windows, mode):
+    """The batched workload's launch configuration (mixed form, one context
+    for all windows, autotuned residual launch shape, the solve captured as one
+    HIP graph, 5 iterations without the convergence test) against the FP64
+    oracle's 5 iterations of each window: every pose and every inverse depth
+    within the contract's bars, and the batch's photometric RMSE (over all
+    windows' usable residuals) within 1e-4."""
+    nw = len(full_windows)
+    b = make(nw, mode, pba.PBA_MIXED_BF16, flags=pba.PBA_FLAG_GRAPH)
+    load(b, full_windows)
+    b.autotune(0, 3)
+    for w, sc in enumerate(full_windows):
+        b.set_params(sc.poses_init, sc.inv_depth_init, window=w)
+    b.solve(5, 0.0)
+    ev = b.evaluate(0)
+    sq, cnt = 0.0, 0
+    for w, sc in enumerate(full_windows):
+        gn = GaussNewton(Problem.from_scene(sc), mode)
+        gn.iterate(0, 5)
+        pb, db = b.get_params(w)
+        rot = rot_err(pb, gn.poses).max()
+        trans = trans_rel_err(pb, gn.poses).max()
+        ok, q99, worst = depth_errors_ok(db, gn.d)
+        print(f"batched mixed {mode} window {w} ({sc.n_frames} keyframes, {sc.n_points} points, {sc.n_obs} "
+              f"observations): rot {rot:.2e} rad, trans {trans:.2e}, inv depth p99 {q99:.2e} max {worst:.2e}")
+        assert rot <= 1e-5 and trans <= 1e-5, w
+        assert ok, (w, q99, worst)
+        oev = gn.evaluate(0)
+        sq += oev["sq"]
+        cnt += oev["n_active"]
+    assert ev["n_active"] == cnt
+    assert abs(ev["rmse"] / np.sqrt(sq / cnt) - 1) <= 1e-4
