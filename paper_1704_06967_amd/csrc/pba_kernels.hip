@@ -1,9 +1,10 @@
 // HIP kernels of libpba for CDNA4 (gfx950, wave64).
 //
-// Residual-level kernels put one observation (point n seen in frame f) on 8
-// consecutive lanes, one lane per patch pixel, 8 observations per wavefront.
-// Each observation reduces its lanes with cross-lane DPP moves and writes one
-// record of Gauss-Newton blocks in relative-pose coordinates. Every later
+// The linearization kernels put one observation (point n seen in frame f) on
+// 8 consecutive lanes, one lane per patch pixel, 8 observations per
+// wavefront; each observation reduces its lanes with cross-lane DPP moves and
+// writes one record of Gauss-Newton blocks in relative-pose coordinates. The
+// IC iteration's residual pass runs one observation per thread. Every later
 // reduction (per point, per pair, per frame) runs in a fixed order in FP64, so
 // results are bitwise reproducible run to run (no floating-point atomics).
 #include <hip/hip_ext.h>
@@ -476,18 +477,126 @@ __global__ __launch_bounds__(BLOCK) void k_linearize_mixed(ResArgs<float> a, int
 }
 
 // IC iteration: residuals at the current parameters, Huber weights, and
-// g = J^T W r with the constant proxy Jacobian (Sec. 3.5 steps 1-2). One
-// thread per observation: it loads the pair's data (host and target
-// intrinsics, the current relative pose, the relative pose at p(0)) and the
-// point's once, runs the observation's patch pixels in batches of IC_PB, and
-// keeps the ten FP64 sums in registers, so no cross-lane reduction and no
-// broadcast is needed; the threads of a wavefront share the pair loads
-// through the caches. In a batch every load is issued first (templates and
-// texels; a pixel that does not contribute reads the in-bounds cell at (1, 1)
-// and is masked), then the arithmetic runs. NB threads per workgroup, tiles
-// of NB observations, grid-stride over the tiles in the XCD-aware order; the
-// ten sums go out as the observation's contiguous record.
-constexpr int IC_PB = 4;
+// g = J^T W r with the constant proxy Jacobian (Sec. 3.5 steps 1-2), per
+// observation the ten FP64 sums of its patch pixels' products (J_theta w r,
+// J_d w r, the Huber norm, r^2, the count). One thread per observation: it
+// loads the pair's data (host and target intrinsics, the current relative
+// pose, the relative pose at p(0)) and the point's once, runs the patch
+// pixels in pairs (every load of a pair issued first) and keeps the ten sums
+// in registers, so no cross-lane reduction and no broadcast is needed; the
+// threads of a wavefront share the pair loads through the caches. NB threads
+// per workgroup, tiles of NB observations, grid-stride over the tiles in the
+// XCD-aware order; the ten sums go out as the observation's contiguous record.
+
+// The observation's data: the pair's projection and p(0) pose, the point's
+// pixel and inverse depths.
+template <typename T>
+struct IcObs {
+    double Q[12];            // (qu vz, qv vz, vz) = Q (x, y, 1, d)
+    double cx, cy, ifx, ify; // host intrinsics: principal point, 1 / focal lengths
+    double uc, vc, d;        // level pixel of the point, current inverse depth
+    T R0[12];                // relative R (row-major), t at p(0)
+    T d0, id0, fx, fy;       // inverse depth at p(0) and its reciprocal, host focal lengths
+    const T *img, *tmpl;     // target level image, the point's template records
+    unsigned m;              // pixels usable at p(0)
+};
+
+template <typename T>
+__device__ __forceinline__ void ic_obs_load(const ResArgs<T> &a, int o, IcObs<T> &ob) {
+    const int n = a.obs_point[o], pr = a.obs_pair[o];
+    const int f = a.pair_target[pr];
+    double K[8], G[12];   // host fx fy cx cy, target fx fy cx cy; current relative R (row-major), t
+#pragma unroll
+    for (int k = 0; k < 8; ++k) K[k] = a.pcam[8 * pr + k];
+#pragma unroll
+    for (int k = 0; k < 12; ++k) {
+        G[k] = a.geo[GEO_STRIDE * pr + k];
+        ob.R0[k] = a.rel0[REL_STRIDE * pr + k];
+    }
+    ob.d = a.depth[n];
+    ob.d0 = (T)a.depth0[n];
+    ob.id0 = recip(ob.d0);
+    ob.uc = ((double)a.host_uv[2 * n] + 0.5) * a.scale - 0.5;
+    ob.vc = ((double)a.host_uv[2 * n + 1] + 0.5) * a.scale - 0.5;
+    ob.ifx = 1.0 / K[0];
+    ob.ify = 1.0 / K[1];
+    ob.cx = K[2];
+    ob.cy = K[3];
+    ob.fx = (T)K[0];
+    ob.fy = (T)K[1];
+    // rows of diag(fx_t, fy_t, 1) [R | t] + (cx_t, cy_t, 0) e3^T [R | t]: the
+    // warp and projection of lin_eval with the target intrinsics folded in
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        ob.Q[k] = K[4] * G[k] + K[6] * G[6 + k];
+        ob.Q[4 + k] = K[5] * G[3 + k] + K[7] * G[6 + k];
+        ob.Q[8 + k] = G[6 + k];
+    }
+    ob.Q[3] = K[4] * G[9] + K[6] * G[11];
+    ob.Q[7] = K[5] * G[10] + K[7] * G[11];
+    ob.Q[11] = G[11];
+    ob.img = a.img + (size_t)f * a.W * a.H;
+    ob.tmpl = a.tmpl + 4 * (size_t)n * a.P;
+}
+
+// First step of patch pixel j: the warp (FP64, as template_xy and lin_eval),
+// the template and texel loads. A pixel that does not contribute reads the
+// in-bounds cell at (1, 1) and is masked.
+template <typename T>
+struct IcPix {
+    bool ok;
+    double fa, fb;   // the position's fractions in its cell
+    T x, y, tq[3], tx[4];
+};
+
+template <typename T>
+__device__ __forceinline__ void ic_pixel_load(const ResArgs<T> &a, const IcObs<T> &ob, int j, IcPix<T> &px) {
+    const T *tp = ob.tmpl + 4 * j;
+    px.tq[0] = tp[0];
+    px.tq[1] = tp[1];
+    px.tq[2] = tp[2];
+    const double x = (ob.uc + (double)a.pat.du[j] - ob.cx) * ob.ifx;
+    const double y = (ob.vc + (double)a.pat.dv[j] - ob.cy) * ob.ify;
+    const double vz = ob.Q[8] * x + ob.Q[9] * y + ob.Q[10] + ob.d * ob.Q[11];
+    const double hu = ob.Q[0] * x + ob.Q[1] * y + ob.Q[2] + ob.d * ob.Q[3];
+    const double hv = ob.Q[4] * x + ob.Q[5] * y + ob.Q[6] + ob.d * ob.Q[7];
+    const double iz = recip_nr(vz);
+    const double qu = hu * iz, qv = hv * iz;
+    px.ok = ((ob.m >> j) & 1u) && ob.d > 0.0 && vz > 0.0 && usable(qu, qv, a.W, a.H);
+    const double su = px.ok ? qu : 1.0, sv = px.ok ? qv : 1.0;
+    const double fu = floor(su), fv = floor(sv);
+    const int cj = (int)fu, ci = (int)fv;
+    px.fa = su - fu;
+    px.fb = sv - fv;
+    const T *r0 = ob.img + (size_t)ci * a.W + cj;
+    px.tx[0] = r0[0];
+    px.tx[1] = r0[1];
+    px.tx[2] = r0[a.W];
+    px.tx[3] = r0[a.W + 1];
+    px.x = (T)x;
+    px.y = (T)y;
+}
+
+// Second step: residual (rounded once), Huber weight, proxy Jacobian and the
+// pixel's ten FP64 products, added to c (nothing when it does not contribute).
+template <typename T>
+__device__ __forceinline__ void ic_pixel_add(const ResArgs<T> &a, const IcObs<T> &ob, const IcPix<T> &px,
+                                             double (&c)[IC_REC]) {
+    if (px.ok) {
+        const double If = bilerp(px.fa, px.fb, px.tx[0], px.tx[1], px.tx[2], px.tx[3]);
+        const T r = (T)((double)px.tq[0] - If);
+        T w, rho;
+        huber(r, a.huber_k, w, rho);
+        T J[7];
+        ic_jacobian(px.x, px.y, ob.R0, ob.R0 + 9, ob.d0, ob.id0, px.tq[1], px.tq[2], ob.fx, ob.fy, J);
+        const double wr = (double)w * r;
+#pragma unroll
+        for (int k = 0; k < 7; ++k) c[k] += wr * (double)J[k];
+        c[7] += (double)rho;
+        c[8] += (double)r * r;
+        c[9] += 1.0;
+    }
+}
 
 template <typename T, int NB>
 __global__ __launch_bounds__(NB) void k_ic_residual(ResArgs<T> a) {
@@ -497,89 +606,29 @@ __global__ __launch_bounds__(NB) void k_ic_residual(ResArgs<T> a) {
     for (int it = blockIdx.x; it < ntiles; it += gridDim.x) {
         const int o = xcd_tile(it, ntiles) * NB + threadIdx.x;
         if (o >= a.O) continue;
-        const unsigned m = a.mask[o];
-        double c[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
-        if (m != 0u) {
-            const int n = a.obs_point[o], pr = a.obs_pair[o];
-            const int f = a.pair_target[pr];
-            double K[8], G[12];   // host fx fy cx cy, target fx fy cx cy; current relative R (row-major), t
-            T R0[12];             // relative R, t at p(0)
+        IcObs<T> ob;
+        ob.m = a.mask[o];
+        double c[IC_REC] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+        if (ob.m != 0u) {
+            ic_obs_load(a, o, ob);
 #pragma unroll
-            for (int k = 0; k < 8; ++k) K[k] = a.pcam[8 * pr + k];
+            for (int j0 = 0; j0 < 8; j0 += 2) {
+                IcPix<T> px[2];
 #pragma unroll
-            for (int k = 0; k < 12; ++k) {
-                G[k] = a.geo[GEO_STRIDE * pr + k];
-                R0[k] = a.rel0[REL_STRIDE * pr + k];
-            }
-            const double d = a.depth[n];
-            const T d0 = (T)a.depth0[n], id0 = recip(d0);
-            const double uc = ((double)a.host_uv[2 * n] + 0.5) * a.scale - 0.5;
-            const double vc = ((double)a.host_uv[2 * n + 1] + 0.5) * a.scale - 0.5;
-            const double ifx = 1.0 / K[0], ify = 1.0 / K[1];
-            const T fx = (T)K[0], fy = (T)K[1];
-            const T *img = a.img + (size_t)f * a.W * a.H;
-            const T *tmpl = a.tmpl + 4 * (size_t)n * a.P;
-#pragma unroll
-            for (int j0 = 0; j0 < 8; j0 += IC_PB) {
-                bool ok[IC_PB];
-                double fa[IC_PB], fb[IC_PB];
-                T xs[IC_PB], ys[IC_PB], tq[IC_PB][3], tx[IC_PB][4];
-                // first step: the warps (FP64, as template_xy and lin_eval) and the loads
-#pragma unroll
-                for (int i = 0; i < IC_PB; ++i) {
-                    const int j = j0 + i;
-                    ok[i] = false;
-                    if (j >= a.P) continue;
-                    const T *tp = tmpl + 4 * j;
-                    tq[i][0] = tp[0];
-                    tq[i][1] = tp[1];
-                    tq[i][2] = tp[2];
-                    const double x = (uc + (double)a.pat.du[j] - K[2]) * ifx;
-                    const double y = (vc + (double)a.pat.dv[j] - K[3]) * ify;
-                    const double vz = G[6] * x + G[7] * y + G[8] + d * G[11];
-                    const double vx = G[0] * x + G[1] * y + G[2] + d * G[9];
-                    const double vy = G[3] * x + G[4] * y + G[5] + d * G[10];
-                    const double iz = recip_nr(vz);
-                    const double qu = K[4] * (vx * iz) + K[6], qv = K[5] * (vy * iz) + K[7];
-                    ok[i] = ((m >> j) & 1u) && d > 0.0 && vz > 0.0 && usable(qu, qv, a.W, a.H);
-                    const double su = ok[i] ? qu : 1.0, sv = ok[i] ? qv : 1.0;
-                    const double fu = floor(su), fv = floor(sv);
-                    const int cj = (int)fu, ci = (int)fv;
-                    fa[i] = su - fu;
-                    fb[i] = sv - fv;
-                    const T *r0 = img + (size_t)ci * a.W + cj;
-                    tx[i][0] = r0[0];
-                    tx[i][1] = r0[1];
-                    tx[i][2] = r0[a.W];
-                    tx[i][3] = r0[a.W + 1];
-                    xs[i] = (T)x;
-                    ys[i] = (T)y;
+                for (int i = 0; i < 2; ++i) {
+                    px[i].ok = false;
+                    if (j0 + i < a.P) ic_pixel_load(a, ob, j0 + i, px[i]);
                 }
-                // second step: residual (rounded once), Huber weight, proxy
-                // Jacobian and the FP64 products and sums
-#pragma unroll
-                for (int i = 0; i < IC_PB; ++i) {
-                    if (!ok[i]) continue;
-                    const double If = bilerp(fa[i], fb[i], tx[i][0], tx[i][1], tx[i][2], tx[i][3]);
-                    const T r = (T)((double)tq[i][0] - If);
-                    T w, rho;
-                    huber(r, a.huber_k, w, rho);
-                    T J[7];
-                    ic_jacobian(xs[i], ys[i], R0, R0 + 9, d0, id0, tq[i][1], tq[i][2], fx, fy, J);
-                    const double wr = (double)w * r;
-#pragma unroll
-                    for (int p = 0; p < 7; ++p) c[p] += wr * (double)J[p];
-                    c[7] += (double)rho;
-                    c[8] += (double)r * r;
-                    c[9] += 1.0;
-                }
+                ic_pixel_add(a, ob, px[0], c);
+                ic_pixel_add(a, ob, px[1], c);
             }
         }
         double *rec = a.icr + (size_t)o * IC_REC;
 #pragma unroll
-        for (int p = 0; p < IC_REC; ++p) rec[p] = c[p];
+        for (int k = 0; k < IC_REC; ++k) rec[k] = c[k];
     }
 }
+
 
 // Energy and RMSE at the current parameters over the residuals usable at those
 // parameters (fresh set); writes the record's statistics fields only.
