@@ -266,6 +266,39 @@ def equal_rmse_section(pba, scene, precision, conv_px, final_cap, caps=CAPS, rec
     return out
 
 
+def converged_section(pba, precision, max_iters=40, conv_px=5e-3, reps=10):
+    """IC and FC run to convergence (the Sec. 4.1 test at every level) on a
+    variant of the mid workload on which IC's fixed point is FC's: targets
+    within +-2 frames (24 degrees) and no image noise (on mid itself the wider
+    baselines and the noise move IC's fixed point away from FC's). Each solve
+    is one graph launch, timed to its end (median of `reps`)."""
+    import scenes
+
+    sc = scenes.mid(reach=2, noise_sigma=0.0)
+    out = {"workload": "mid geometry, targets within +-2 frames (24 deg), no image noise: 5 hosts x 4000 points, "
+                       f"{sc.n_obs} observations; at most {max_iters} iterations per level, convergence at "
+                       f"{conv_px} px", "points": sc.n_points, "observations": sc.n_obs}
+    for name, mode in (("ic", pba.PBA_IC_PROXY), ("fc", pba.PBA_FC)):
+        s = pba.Solver(mode=mode, precision=precision, flags=pba.PBA_FLAG_GRAPH, n_levels=sc.n_levels,
+                       pattern=sc.pattern, huber_k=sc.huber_k)
+        s.set_scene(sc)
+        s.solve(max_iters, conv_px)  # capture
+        ts, res = [], None
+        for _ in range(reps):
+            s.set_params(sc.poses_init, sc.inv_depth_init)
+            t0 = time.perf_counter()
+            res, _ = s.solve(max_iters, conv_px)
+            ts.append(time.perf_counter() - t0)
+        r = res.as_dict()
+        s.close()
+        out[name] = {"ms_per_solve": round(float(np.median(ts)) * 1e3, 4), "iters": r["iters"][:sc.n_levels],
+                     "converged": bool(r["converged"]), "final_rmse": r["final_rmse"]}
+    ic, fc = out["ic"], out["fc"]
+    out["rmse_ic_over_fc"] = ic["final_rmse"] / fc["final_rmse"]
+    out["ic_speedup_to_convergence"] = round(fc["ms_per_solve"] / ic["ms_per_solve"], 3)
+    return out
+
+
 def cpu_model():
     try:
         with open("/proc/cpuinfo") as f:
@@ -766,6 +799,10 @@ def main():
         t0 = time.perf_counter()
         line["equal_rmse"] = equal_rmse_section(pba, scene, pba.PBA_FP32, args.conv_px, args.max_iters)
         log(f"equal RMSE (mid): {time.perf_counter() - t0:.1f} s")
+    if not args.no_trace:
+        t0 = time.perf_counter()
+        line["equal_rmse_converged"] = converged_section(pba, pba.PBA_FP32)
+        log(f"converged solves: {time.perf_counter() - t0:.1f} s: {line['equal_rmse_converged']}")
     if not args.no_precision:
         line["precision_form"], precision_scene = precision_section(pba, max(1, min(args.steps, 5)), args.max_iters,
                                                                     args.conv_px, precision_scene,

@@ -264,17 +264,19 @@ def tiny(seed=1, n_points=500, width=320, height=240):
                   lambda h, n: [1, 2, 3], 1, 0.0, seed, perturb="fixed")
 
 
-def mid(seed=2, n_per_host=4000, width=640, height=480, n_frames=30):
+def mid(seed=2, n_per_host=4000, width=640, height=480, n_frames=30, reach=3, noise_sigma=2.0 / 255.0):
     """Ellipsoid (1.0/0.8/0.6), 30 cameras on a full orbit of radius 3, hosts
-    0,6,12,18,24, targets the visible frames within +-3, 3 levels, noise 2/255."""
+    0,6,12,18,24, targets the visible frames within +-reach (3: up to 36
+    degrees from the host), 3 levels, image noise sigma noise_sigma (2/255)."""
     objs = [Ellipsoid((0, 0, 0), (1.0, 0.8, 0.6), seed + 100)]
     poses = _orbit(n_frames, 3.0, 0.8, 0.0, 360.0 / n_frames)
     hosts = list(range(0, n_frames - 5, 6))[:5]
+    offsets = [k for k in range(-reach, reach + 1) if k != 0]
 
     def targets(h, n):
-        return sorted({(h + k) % n_frames for k in (-3, -2, -1, 1, 2, 3)})
+        return sorted({(h + k) % n_frames for k in offsets})
 
-    return _build("mid", objs, poses, width, height, hosts, n_per_host, targets, 3, 2.0 / 255.0, seed)
+    return _build("mid", objs, poses, width, height, hosts, n_per_host, targets, 3, noise_sigma, seed)
 
 
 def precision(seed=3, n_per_host=20000, width=640, height=480, n_frames=120):
