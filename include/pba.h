@@ -74,7 +74,7 @@ enum { PBA_FP64 = 0, PBA_FP32 = 1, PBA_MIXED_BF16 = 2 };      /* pba_config.prec
  * preconditioner's training loss exactly, P^_i = (I + G_i)^{-1} (the bound of any network) */
 enum { PBA_SOLVER_CHOL = 0, PBA_SOLVER_PCG_JACOBI = 1, PBA_SOLVER_PCG_LEARNED = 2, PBA_SOLVER_PCG_BLOCKOPT = 3 };
 enum { PBA_HOST = 0, PBA_DEVICE = 1 };                        /* memory of input pointers */
-enum { PBA_FLAG_TIMING = 1, PBA_FLAG_GRAPH = 2 };             /* pba_config.flags */
+enum { PBA_FLAG_TIMING = 1, PBA_FLAG_GRAPH = 2, PBA_FLAG_LANE_PER_PIXEL = 4 };   /* pba_config.flags */
 
 #define PBA_MAX_PATTERN 8
 #define PBA_MAX_LEVELS 4
@@ -120,7 +120,13 @@ typedef struct {
                             max_iters and conv_px; the graph is dropped (and captured
                             again when needed) when points are set, when max_iters
                             or conv_px change, and when pba_autotune picks a launch
-                            shape. pba_iterate never uses the graph */
+                            shape. pba_iterate never uses the graph.
+                            PBA_FLAG_LANE_PER_PIXEL: the IC residual pass starts with
+                            one lane per patch pixel (8 per observation) instead of one
+                            thread per observation (pba_autotune may pick either); the
+                            two add an observation's pixel products in different
+                            orders, so results agree to the rounding of those FP64
+                            sums */
     void *stream;        /* hipStream_t to run on, or NULL for a library-owned stream */
     int32_t recentre_every; /* proxy re-centring (Sec. 3.6: the proxy update holds near
                             p(0)): with m > 0, IC re-linearizes after every m
@@ -261,11 +267,15 @@ pba_status pba_set_params(pba_ctx *ctx, int32_t window, const double *poses, con
 #define PBA_TUNE_MAX 16
 typedef struct {
     int32_t n_candidates;
-    int32_t block[PBA_TUNE_MAX];     /* threads per workgroup (tiles of block / 8 observations) */
+    int32_t block[PBA_TUNE_MAX];     /* threads per workgroup (tiles of block / lanes observations) */
     int32_t grid_mult[PBA_TUNE_MAX]; /* 0: one tile per workgroup; m > 0: persistent grid of m
                                         workgroups per compute unit striding over the tiles */
     double us[PBA_TUNE_MAX];         /* mean time per launch (microseconds, HIP events) */
     int32_t chosen;                  /* index of the fastest, now used by the context */
+    int32_t lanes[PBA_TUNE_MAX];     /* threads per observation: IC 1 (one thread runs the
+                                        observation's patch pixels) or 8 (one per pixel; the
+                                        sums agree to the rounding of FP64 sums of 8 terms);
+                                        FC 8 */
 } pba_tune_report;
 
 /* Project autotuner: (re)starts `level` at the current parameters, times every

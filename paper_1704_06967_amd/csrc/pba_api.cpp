@@ -178,7 +178,7 @@ std::string validate_config(const pba_config *cfg) {
     if (cfg->pinned_frame < -1) return "pinned_frame must be >= -1";
     if (cfg->solver != PBA_SOLVER_CHOL) return "solver must be PBA_SOLVER_CHOL (PCG: pba_solve_reduced)";
     if (cfg->n_windows < 1 || cfg->n_windows > PBA_MAX_WINDOWS) return "n_windows must be in 1..PBA_MAX_WINDOWS";
-    if (cfg->flags & ~(PBA_FLAG_TIMING | PBA_FLAG_GRAPH)) return "unknown flag bits";
+    if (cfg->flags & ~(PBA_FLAG_TIMING | PBA_FLAG_GRAPH | PBA_FLAG_LANE_PER_PIXEL)) return "unknown flag bits";
     if (cfg->recentre_every < 0 || cfg->recentre_every > 1000) return "recentre_every must be in 0..1000";
     return "";
 }
@@ -1156,6 +1156,7 @@ pba_status pba_create(const pba_config *cfg, pba_ctx **out) {
     pba_ctx *ctx = new pba_ctx();
     Ctx &c = ctx->c;
     c.cfg = *cfg;
+    if (cfg->flags & PBA_FLAG_LANE_PER_PIXEL) c.tune_res.lanes = 8;
     c.device = dev;
     c.P = cfg->pattern_n;
     c.real_size = cfg->precision == PBA_FP64 ? sizeof(double) : sizeof(float);
@@ -1503,9 +1504,12 @@ pba_status pba_autotune(pba_ctx *ctx, int32_t level, int32_t reps, pba_tune_repo
         if (out) *out = rep;
         return PBA_OK;
     }
-    std::vector<LaunchShape> cand = {{64, 0}, {128, 0}, {256, 0}, {512, 0}, {256, 2}, {256, 4}, {256, 8}, {512, 2},
-                                      {512, 4}};
-    if (ic) cand.push_back({1024, 0});
+    std::vector<LaunchShape> cand;
+    if (ic)   // a thread per observation, then a lane per patch pixel
+        cand = {{64, 0, 1}, {128, 0, 1}, {256, 0, 1}, {512, 0, 1}, {1024, 0, 1}, {256, 2, 1}, {256, 4, 1},
+                {128, 0, 8}, {256, 0, 8}, {512, 0, 8}, {256, 2, 8}, {256, 4, 8}};
+    else
+        cand = {{64, 0}, {128, 0}, {256, 0}, {512, 0}, {256, 2}, {256, 4}, {256, 8}, {512, 2}, {512, 4}};
     if ((st = ensure_events(c, 2)) != PBA_OK) return st;
     hipEvent_t e0 = c.ev_pool[0], e1 = c.ev_pool[1];
     const double *geo = c.flip ? c.d_geo_b : c.d_geo_a;
@@ -1535,6 +1539,7 @@ pba_status pba_autotune(pba_ctx *ctx, int32_t level, int32_t reps, pba_tune_repo
         HIPCHK(hipEventElapsedTime(&ms, e0, e1));
         rep.block[k] = cand[k].block;
         rep.grid_mult[k] = cand[k].grid_mult;
+        rep.lanes[k] = ic ? cand[k].lanes : 8;
         rep.us[k] = 1e3 * ms / reps;
         if (rep.us[k] < rep.us[best]) best = (int)k;
     }

@@ -4,6 +4,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <utility>
+
 
 namespace pba {
 
@@ -414,6 +416,49 @@ __device__ __forceinline__ T half_sum32(T v) {
     v = row_sum16(v);
     const T a = lane_value(v, 0) + lane_value(v, 16), b = lane_value(v, 32) + lane_value(v, 48);
     return (threadIdx.x & 32) ? b : a;
+}
+
+// Lane S of each aligned group of 8 lanes, read by every lane of the group:
+// ds_swizzle in bit-mask mode (within each 32 lanes the source is
+// (lane & 0x18) | S). An inactive source lane reads as 0, so the whole group
+// must be active.
+template <int S>
+__device__ __forceinline__ float bcast8(float v) {
+    static_assert(S >= 0 && S < 8, "a lane of the group of 8");
+    return __int_as_float(__builtin_amdgcn_ds_swizzle(__float_as_int(v), 0x18 | (S << 5)));
+}
+template <int S>
+__device__ __forceinline__ double bcast8(double v) {
+    static_assert(S >= 0 && S < 8, "a lane of the group of 8");
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_ds_swizzle((int)b, 0x18 | (S << 5));
+    const int hi = __builtin_amdgcn_ds_swizzle((int)(b >> 32), 0x18 | (S << 5));
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// Words of 16-byte slices spread over a group of 8 lanes, read by every lane
+// of the group: lane l of the group holds slice l in s0 and slice l + 8 in s1;
+// out[k] = word k % 4 of slice k / 4 (ds_swizzle in bit-mask mode, as bcast8).
+template <typename V, int... K>
+__device__ __forceinline__ void bcast8_words(const V &s0, const V &s1, int *out, std::integer_sequence<int, K...>) {
+    ((out[K] = __builtin_amdgcn_ds_swizzle(K < 32 ? s0[K % 4] : s1[K % 4], 0x18 | (((K / 4) % 8) << 5))), ...);
+}
+
+// Words B + k of the same layout, into out[B + k].
+template <int B, typename V, int... K>
+__device__ __forceinline__ void bcast8_words_range(const V &s0, const V &s1, int *out,
+                                                   std::integer_sequence<int, K...>) {
+    ((out[B + K] = __builtin_amdgcn_ds_swizzle((B + K) < 32 ? s0[(B + K) % 4] : s1[(B + K) % 4],
+                                               0x18 | ((((B + K) / 4) % 8) << 5))),
+     ...);
+}
+
+// Words B + k of the same slice layout, all from s1 (slices 8 and up): out[k]
+// = word (B + k) % 4 of slice (B + k) / 4.
+template <int B, typename V, int... K>
+__device__ __forceinline__ void bcast8_words_from(const V &s1, int *out, std::integer_sequence<int, K...>) {
+    static_assert(B >= 32, "words of the second slice register");
+    ((out[K] = __builtin_amdgcn_ds_swizzle(s1[(B + K) % 4], 0x18 | ((((B + K) / 4) % 8) << 5))), ...);
 }
 
 }  // namespace pba

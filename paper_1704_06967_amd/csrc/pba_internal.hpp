@@ -74,6 +74,7 @@ struct WinArgs {
 struct LaunchShape {
     int block = 256;
     int grid_mult = 0;
+    int lanes = 1;   // IC residual pass: threads per observation (1 or 8)
 };
 
 // Learned block preconditioner (network 22 -> 256 -> 256 -> 21) and PCG state.

@@ -501,23 +501,10 @@ struct IcObs {
     unsigned m;              // pixels usable at p(0)
 };
 
+// The pair's part of the observation's data from its intrinsics K (host fx
+// fy cx cy, target fx fy cx cy) and current relative pose G (R row-major, t).
 template <typename T>
-__device__ __forceinline__ void ic_obs_load(const ResArgs<T> &a, int o, IcObs<T> &ob) {
-    const int n = a.obs_point[o], pr = a.obs_pair[o];
-    const int f = a.pair_target[pr];
-    double K[8], G[12];   // host fx fy cx cy, target fx fy cx cy; current relative R (row-major), t
-#pragma unroll
-    for (int k = 0; k < 8; ++k) K[k] = a.pcam[8 * pr + k];
-#pragma unroll
-    for (int k = 0; k < 12; ++k) {
-        G[k] = a.geo[GEO_STRIDE * pr + k];
-        ob.R0[k] = a.rel0[REL_STRIDE * pr + k];
-    }
-    ob.d = a.depth[n];
-    ob.d0 = (T)a.depth0[n];
-    ob.id0 = recip(ob.d0);
-    ob.uc = ((double)a.host_uv[2 * n] + 0.5) * a.scale - 0.5;
-    ob.vc = ((double)a.host_uv[2 * n + 1] + 0.5) * a.scale - 0.5;
+__device__ __forceinline__ void ic_obs_pair(const double (&K)[8], const double (&G)[12], IcObs<T> &ob) {
     ob.ifx = 1.0 / K[0];
     ob.ify = 1.0 / K[1];
     ob.cx = K[2];
@@ -535,6 +522,33 @@ __device__ __forceinline__ void ic_obs_load(const ResArgs<T> &a, int o, IcObs<T>
     ob.Q[3] = K[4] * G[9] + K[6] * G[11];
     ob.Q[7] = K[5] * G[10] + K[7] * G[11];
     ob.Q[11] = G[11];
+}
+
+// The point's pixel at the level and its inverse depths.
+template <typename T>
+__device__ __forceinline__ void ic_obs_point(const ResArgs<T> &a, float hu, float hv, double d, double d0,
+                                             IcObs<T> &ob) {
+    ob.uc = ((double)hu + 0.5) * a.scale - 0.5;
+    ob.vc = ((double)hv + 0.5) * a.scale - 0.5;
+    ob.d = d;
+    ob.d0 = (T)d0;
+    ob.id0 = recip(ob.d0);
+}
+
+template <typename T>
+__device__ __forceinline__ void ic_obs_load(const ResArgs<T> &a, int o, IcObs<T> &ob) {
+    const int n = a.obs_point[o], pr = a.obs_pair[o];
+    const int f = a.pair_target[pr];
+    double K[8], G[12];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) K[k] = a.pcam[8 * pr + k];
+#pragma unroll
+    for (int k = 0; k < 12; ++k) {
+        G[k] = a.geo[GEO_STRIDE * pr + k];
+        ob.R0[k] = a.rel0[REL_STRIDE * pr + k];
+    }
+    ic_obs_pair(K, G, ob);
+    ic_obs_point(a, a.host_uv[2 * n], a.host_uv[2 * n + 1], a.depth[n], a.depth0[n], ob);
     ob.img = a.img + (size_t)f * a.W * a.H;
     ob.tmpl = a.tmpl + 4 * (size_t)n * a.P;
 }
@@ -550,11 +564,18 @@ struct IcPix {
 };
 
 template <typename T>
-__device__ __forceinline__ void ic_pixel_load(const ResArgs<T> &a, const IcObs<T> &ob, int j, IcPix<T> &px) {
+__device__ __forceinline__ void ic_pixel_template(const IcObs<T> &ob, int j, IcPix<T> &px) {
     const T *tp = ob.tmpl + 4 * j;
     px.tq[0] = tp[0];
     px.tq[1] = tp[1];
     px.tq[2] = tp[2];
+}
+
+// (with_template false: px.tq already holds the pixel's template record)
+template <typename T>
+__device__ __forceinline__ void ic_pixel_load(const ResArgs<T> &a, const IcObs<T> &ob, int j, IcPix<T> &px,
+                                              bool with_template = true) {
+    if (with_template) ic_pixel_template(ob, j, px);
     const double x = (ob.uc + (double)a.pat.du[j] - ob.cx) * ob.ifx;
     const double y = (ob.vc + (double)a.pat.dv[j] - ob.cy) * ob.ify;
     const double vz = ob.Q[8] * x + ob.Q[9] * y + ob.Q[10] + ob.d * ob.Q[11];
@@ -626,6 +647,106 @@ __global__ __launch_bounds__(NB) void k_ic_residual(ResArgs<T> a) {
         double *rec = a.icr + (size_t)o * IC_REC;
 #pragma unroll
         for (int k = 0; k < IC_REC; ++k) rec[k] = c[k];
+    }
+}
+
+// The same pass with one lane per patch pixel (8 lanes per observation, 8
+// times the wavefronts): the pair's data (intrinsics, current pose, p(0)
+// pose: 13 slices of 16 bytes in the FP32 form, 16 in FP64) and the point's
+// pixel and inverse depths are loaded once per observation, lane j taking
+// slices j and j + 8 (lanes 0-2 the point's), and read across the 8 lanes by
+// ds_swizzle; each lane forms its pixel's products with the arithmetic
+// above, and a butterfly over the 8 lanes adds them. The sums agree with the
+// thread-per-observation pass to the rounding of FP64 sums of 8 terms (the
+// order of the additions differs); the autotuner picks between the two.
+template <typename T, int NB>
+__global__ __launch_bounds__(NB) void k_ic_residual8(ResArgs<T> a) {
+    if (__builtin_amdgcn_readfirstlane(__hip_atomic_load(a.gate, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) == 0)
+        return;
+    const int ntiles = (a.O + NB / 8 - 1) / (NB / 8);
+    for (int it = blockIdx.x; it < ntiles; it += gridDim.x) {
+        const int gid = xcd_tile(it, ntiles) * NB + threadIdx.x;
+        const int o = gid >> 3, j = gid & 7;
+        const bool in = o < a.O;
+        const int n = in ? a.obs_point[o] : 0, pr = in ? a.obs_pair[o] : 0;
+        IcObs<T> ob;
+        ob.m = in ? (unsigned)a.mask[o] : 0u;
+        constexpr int NSL = 10 + (12 * (int)sizeof(T)) / 16;
+        typedef int I4 __attribute__((ext_vector_type(4)));
+        I4 sl0 = {0, 0, 0, 0}, sl1 = {0, 0, 0, 0};
+        double pt = 0.0;
+        int f = 0;
+        if (ob.m != 0u) {
+            auto slice = [&](int k) -> const I4 * {
+                if (k < 4) return reinterpret_cast<const I4 *>(a.pcam + 8 * pr + 2 * k);
+                if (k < 10) return reinterpret_cast<const I4 *>(a.geo + GEO_STRIDE * pr + 2 * (k - 4));
+                return reinterpret_cast<const I4 *>(a.rel0 + REL_STRIDE * pr) + (k - 10);
+            };
+            sl0 = *slice(j);
+            if (j + 8 < NSL) sl1 = *slice(j + 8);
+            if (j < 3)
+                pt = j == 0 ? *reinterpret_cast<const double *>(a.host_uv + 2 * n) : (j == 1 ? a.depth[n] : a.depth0[n]);
+            f = a.pair_target[pr];
+        }
+        ob.tmpl = a.tmpl + 4 * (size_t)n * a.P;
+        IcPix<T> px;
+        px.ok = false;
+        px.tq[0] = px.tq[1] = px.tq[2] = T(0);
+        if (ob.m != 0u && j < a.P) ic_pixel_template(ob, j, px);
+        // keep the compiler from sinking these loads into the branches below
+        pin_reg(sl0);
+        pin_reg(sl1);
+        pin_reg(pt);
+        pin_reg(f);
+#pragma unroll
+        for (int k = 0; k < 3; ++k) pin_reg(px.tq[k]);
+        // intrinsics and current pose (words 0-39), the point's pixel and depth
+        int q[40];
+        bcast8_words(sl0, sl1, q, std::make_integer_sequence<int, 40>{});
+        double K[8], G[12];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) K[k] = __hiloint2double(q[2 * k + 1], q[2 * k]);
+#pragma unroll
+        for (int k = 0; k < 12; ++k) G[k] = __hiloint2double(q[17 + 2 * k], q[16 + 2 * k]);
+        const double uv = bcast8<0>(pt), d = bcast8<1>(pt);
+        const long long uvb = __double_as_longlong(uv);
+        ic_obs_pair(K, G, ob);
+        ob.uc = ((double)__int_as_float((int)uvb) + 0.5) * a.scale - 0.5;
+        ob.vc = ((double)__int_as_float((int)(uvb >> 32)) + 0.5) * a.scale - 0.5;
+        ob.d = d;
+        ob.img = a.img + (size_t)f * a.W * a.H;
+        if (ob.m != 0u && j < a.P) ic_pixel_load(a, ob, j, px, false);
+        // the p(0) pose (slices 10 and up, all in sl1) only now, so that it
+        // is not held in registers across the loads
+        pin_reg(sl1);
+        constexpr int NR0 = 12 * (int)sizeof(T) / 4;
+        int q0[NR0];
+        bcast8_words_from<40>(sl1, q0, std::make_integer_sequence<int, NR0>{});
+#pragma unroll
+        for (int k = 0; k < 12; ++k) {
+            if constexpr (sizeof(T) == 8)
+                ob.R0[k] = (T)__hiloint2double(q0[2 * k + 1], q0[2 * k]);
+            else
+                ob.R0[k] = (T)__int_as_float(q0[k]);
+        }
+        ob.d0 = (T)bcast8<2>(pt);
+        ob.id0 = recip(ob.d0);
+        double p[IC_REC] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+        ic_pixel_add(a, ob, px, p);
+#pragma unroll
+        for (int k = 0; k < IC_REC; ++k) {
+            pin_reg(p[k]);   // every lane of the group ends with the same sum
+            p[k] = wave_sum8(p[k]);
+        }
+        double v0 = p[0];
+#pragma unroll
+        for (int k = 1; k < 8; ++k) v0 = j == k ? p[k] : v0;
+        const double v1 = j == 0 ? p[8] : p[9];
+        if (in) {
+            double *rec = a.icr + (size_t)o * IC_REC;
+            rec[j] = v0;
+            if (j < 2) rec[8 + j] = v1;
+        }
     }
 }
 
@@ -1094,13 +1215,21 @@ void Launch<T>::ic_residual_shape(hipStream_t s, Ctx &c, int level, const double
                                   hipEvent_t e0, hipEvent_t e1) {
     if (c.O == 0) return;
     ResArgs<T> a = res_args<T>(c, level, geo_cur);
-    const unsigned g = shape_grid(c, sh, 1);
-    switch (sh.block) {
-        case 64: launch_ev(k_ic_residual<T, 64>, g, 64, s, e0, e1, a); break;
-        case 128: launch_ev(k_ic_residual<T, 128>, g, 128, s, e0, e1, a); break;
-        case 512: launch_ev(k_ic_residual<T, 512>, g, 512, s, e0, e1, a); break;
-        case 1024: launch_ev(k_ic_residual<T, 1024>, g, 1024, s, e0, e1, a); break;
-        default: launch_ev(k_ic_residual<T, 256>, g, 256, s, e0, e1, a); break;
+    const unsigned g = shape_grid(c, sh, sh.lanes == 8 ? 8 : 1);
+    if (sh.lanes == 8) {
+        switch (sh.block) {
+            case 128: launch_ev(k_ic_residual8<T, 128>, g, 128, s, e0, e1, a); break;
+            case 512: launch_ev(k_ic_residual8<T, 512>, g, 512, s, e0, e1, a); break;
+            default: launch_ev(k_ic_residual8<T, 256>, g, 256, s, e0, e1, a); break;
+        }
+    } else {
+        switch (sh.block) {
+            case 64: launch_ev(k_ic_residual<T, 64>, g, 64, s, e0, e1, a); break;
+            case 128: launch_ev(k_ic_residual<T, 128>, g, 128, s, e0, e1, a); break;
+            case 512: launch_ev(k_ic_residual<T, 512>, g, 512, s, e0, e1, a); break;
+            case 1024: launch_ev(k_ic_residual<T, 1024>, g, 1024, s, e0, e1, a); break;
+            default: launch_ev(k_ic_residual<T, 256>, g, 256, s, e0, e1, a); break;
+        }
     }
     CHECK_LAUNCH();
 }

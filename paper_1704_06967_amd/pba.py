@@ -19,7 +19,7 @@ PBA_SOLVER_CHOL, PBA_SOLVER_PCG_JACOBI, PBA_SOLVER_PCG_LEARNED, PBA_SOLVER_PCG_B
 PBA_PC_N_PARAMS = 77077
 PBA_HOST, PBA_DEVICE = 0, 1
 PBA_NOALLOC_MAX_N = 768
-PBA_FLAG_TIMING, PBA_FLAG_GRAPH = 1, 2
+PBA_FLAG_TIMING, PBA_FLAG_GRAPH, PBA_FLAG_LANE_PER_PIXEL = 1, 2, 4
 PBA_MAX_PATTERN = 8
 PBA_MAX_LEVELS = 4
 PBA_MAX_WINDOWS = 4096
@@ -72,14 +72,16 @@ PBA_TUNE_MAX = 16
 
 class pba_tune_report(C.Structure):
     _fields_ = [("n_candidates", C.c_int32), ("block", C.c_int32 * PBA_TUNE_MAX),
-                ("grid_mult", C.c_int32 * PBA_TUNE_MAX), ("us", C.c_double * PBA_TUNE_MAX), ("chosen", C.c_int32)]
+                ("grid_mult", C.c_int32 * PBA_TUNE_MAX), ("us", C.c_double * PBA_TUNE_MAX), ("chosen", C.c_int32),
+                ("lanes", C.c_int32 * PBA_TUNE_MAX)]
 
     def as_dict(self):
         n = self.n_candidates
-        return {"candidates": [{"block": self.block[i], "grid_mult": self.grid_mult[i], "us": self.us[i]}
-                               for i in range(n)],
-                "chosen": {"block": self.block[self.chosen], "grid_mult": self.grid_mult[self.chosen],
-                           "us": self.us[self.chosen]} if n else None}
+
+        def shape(i):
+            return {"block": self.block[i], "grid_mult": self.grid_mult[i], "lanes": self.lanes[i], "us": self.us[i]}
+
+        return {"candidates": [shape(i) for i in range(n)], "chosen": shape(self.chosen) if n else None}
 
 
 class pba_train_config(C.Structure):

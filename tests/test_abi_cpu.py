@@ -36,6 +36,7 @@ def test_struct_layout_matches_c(tmp_path):
         "pba_iter_stats": [f for f, _ in pba.pba_iter_stats._fields_],
         "pba_result": [f for f, _ in pba.pba_result._fields_],
         "pba_timing": [f for f, _ in pba.pba_timing._fields_],
+        "pba_tune_report": [f for f, _ in pba.pba_tune_report._fields_],
     }
     lines = ['#include <stdio.h>', '#include <stddef.h>', f'#include "{HEADER}"', "int main(void){"]
     for s, fs in fields.items():
