@@ -191,3 +191,33 @@ def test_training_lowers_block_loss_and_reports_pcg_iterations():
           f"{ro['iters']} (learned / Jacobi {rl['iters'] / rj['iters']:.3f}); block loss Jacobi "
           f"{np.trace(Gh, axis1=1, axis2=2).mean():.4g}, learned {l_net.mean():.4g}, minimizer {l_opt.mean():.4g}; "
           f"training {rep['jacobi_loss']:.4g} -> {rep['trained_loss']:.4g} on {G.shape[0]} blocks")
+
+
+@pytest.mark.timeout(600)
+def test_reduced_solvers_at_learned_size():
+    """The reduced-system solvers at the learned workload's size (300 frames,
+    6F = 1800, S of the FC linearization at level 0 of the full 850 k-point
+    scene, FP64): the tiled Cholesky solve and block-Jacobi PCG against the
+    dense solve and the oracle's PCG of the same S. S itself is checked
+    against the oracle at 6F = 240 and 720 (same kernels, fewer tiles)."""
+    sc = scenes.learned()
+    s = pba.Solver(mode=pba.PBA_FC, precision=pba.PBA_FP64, n_levels=sc.n_levels, pattern=sc.pattern,
+                   huber_k=sc.huber_k)
+    s.set_scene(sc)
+    s.iterate(0, 1)
+    S, b = s.fetch(pba.PBA_DBG_S), s.fetch(pba.PBA_DBG_B)
+    assert S.shape == (1800, 1800)
+    # blocks (a, b) and (b, a) are assembled separately: symmetric to rounding
+    assert np.abs(S - S.T).max() <= 1e-12 * np.abs(S).max()
+    x_ref = np.linalg.solve(S, -b)
+    rc, xc = s.solve_reduced(pba.PBA_SOLVER_CHOL)
+    assert rc["rel_residual"] <= 1e-10
+    # forward error within the conditioning's reach of the backward error
+    cond = np.linalg.cond(S)
+    assert np.linalg.norm(xc - x_ref) <= max(1e-7, 1e-14 * cond) * np.linalg.norm(x_ref)
+    rj, xj = s.solve_reduced(pba.PBA_SOLVER_PCG_JACOBI, tol=1e-8, max_iters=10000)
+    _, k_o, _ = LP.pcg(S, -b, LP.jacobi_blocks(S), tol=1e-8)
+    print(f"6F = 1800: cond(S) {cond:.3e}, block-Jacobi PCG {rj['iters']} iterations (oracle {k_o})")
+    assert rj["converged"] == 1 and rj["fallback"] == 0 and rj["rel_residual"] <= 1e-8
+    assert abs(rj["iters"] - k_o) <= max(2, k_o // 50)
+    s.close()
