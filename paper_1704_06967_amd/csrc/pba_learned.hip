@@ -500,25 +500,31 @@ __global__ __launch_bounds__(1024) void k_pcg_init(int n, const double *__restri
 }
 
 // q = S p over PCG_ROWS rows per workgroup (a wavefront per row), and the
-// workgroup's part of p.q.
-__global__ __launch_bounds__(256) void k_pcg_matvec(int n, const double *__restrict__ S, const double *__restrict__ p,
-                                                    double *__restrict__ q, double *__restrict__ part,
-                                                    const int *__restrict__ st) {
+// workgroup's part of p.q. A lane reads two columns per step (16-byte loads:
+// n = 6 F is even, so every row starts 16-byte aligned), four steps unrolled
+// so that their loads are in flight together.
+__global__ __launch_bounds__(64 * PCG_ROWS) void k_pcg_matvec(int n, const double *__restrict__ S,
+                                                              const double *__restrict__ p, double *__restrict__ q,
+                                                              double *__restrict__ part, const int *__restrict__ st) {
     __shared__ double red[PCG_ROWS];
     if (st[0]) return;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    for (int rr = wv; rr < PCG_ROWS; rr += 4) {
-        const int row = PCG_ROWS * blockIdx.x + rr;
-        double s = 0.0;
-        if (row < n) {
-            const double *Sr = S + (size_t)row * n;
-            for (int c = lane; c < n; c += 64) s += Sr[c] * p[c];
+    const int row = PCG_ROWS * blockIdx.x + wv;
+    double s = 0.0;
+    if (row < n) {
+        const double2 *S2 = reinterpret_cast<const double2 *>(S + (size_t)row * n);
+        const double2 *p2 = reinterpret_cast<const double2 *>(p);
+        const int n2 = n >> 1;
+#pragma unroll 4
+        for (int c = lane; c < n2; c += 64) {
+            const double2 a = S2[c], b = p2[c];
+            s += a.x * b.x + a.y * b.y;
         }
-        for (int o = 32; o >= 1; o >>= 1) s += __shfl_xor(s, o, 64);
-        if (lane == 0) {
-            if (row < n) q[row] = s;
-            red[rr] = row < n ? s * p[row] : 0.0;
-        }
+    }
+    for (int o = 32; o >= 1; o >>= 1) s += __shfl_xor(s, o, 64);
+    if (lane == 0) {
+        if (row < n) q[row] = s;
+        red[wv] = row < n ? s * p[row] : 0.0;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -680,7 +686,7 @@ void pcg_iterations(hipStream_t s, Ctx &c, int n, int k, double tol) {
     PcState &p = c.pc;
     const int parts = (n + PCG_ROWS - 1) / PCG_ROWS;
     for (int i = 0; i < k; ++i) {
-        k_pcg_matvec<<<parts, 256, 0, s>>>(n, c.d_S, p.p, p.q, p.part, p.st);
+        k_pcg_matvec<<<parts, 64 * PCG_ROWS, 0, s>>>(n, c.d_S, p.p, p.q, p.part, p.st);
         k_pcg_update<<<1, 1024, 0, s>>>(n, parts, p.part, p.P, p.x, p.r, p.z, p.p, p.q, p.sc, p.st, tol * tol);
     }
 }
