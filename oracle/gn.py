@@ -20,6 +20,16 @@ behind the camera, gets weight 0 for that iteration); p(0) is re-centred at
 the start of every pyramid level; the convergence test (Sec. 4.1) takes the
 largest level-0 pixel displacement of any observation's point centre.
 
+Dropping a keyframe (sliding window, dynamic Hessian): the paper notes that
+the IC Hessian must be formed again whenever a keyframe joins or leaves the
+window, and that a dynamic Hessian would save that (Sec. 4.2). drop_frame(f)
+takes frame f's observations out of the window (those it hosts and those in
+which it is the target; the frame stays as an unconstrained block, the
+points it hosts stay with no observation) and, mid-level, forms the IC
+system again from the rows of J and the weights W0 kept at p(0) without
+linearizing the remaining residuals again: the result equals the level
+set-up of the reduced problem at the same p(0).
+
 Proxy re-centring (hybrid schedule): the final update equations of Sec. 3.6
 rest on approximations that hold while the parameters stay near p(0) (the
 proxy depth taken as 1/d0 and d0/d taken as 1). With recentre_every = m > 0
@@ -85,6 +95,8 @@ class GaussNewton:
         self.d = prob.inv_depth_init.copy()
         self.level = None
         self.history = []
+        # observations still in the window (drop_frame), in the problem's order
+        self.obs_live = np.ones(prob.obs_frame.shape[0], bool)
 
     # ---- level start: p(0), frozen residual set, and (IC) the constant system
     def start_level(self, level):
@@ -96,17 +108,38 @@ class GaussNewton:
         self.poses0 = self.poses.copy()
         self.d0 = self.d.copy()
         r0, valid0, _, _ = RS.warp_residuals(P, L, self.poses0, self.d0)
-        self.frozen = valid0
+        self.frozen = valid0 & self.obs_live[L.res_obs]
         if self.mode == "ic":
-            J = RS.ic_jacobian(L, self.poses0, self.d0)
-            J[~self.frozen] = 0.0
-            self.J_rel = J
-            w0 = RS.huber_weight(r0, P.huber_k) * self.frozen
+            self.J0 = RS.ic_jacobian(L, self.poses0, self.d0)
+            self.w0 = RS.huber_weight(r0, P.huber_k)
             self.A0, self.B0 = SV.pair_maps(L, self.poses0)
-            self.Jabs = SV.absolute_jacobian(L, J, self.A0, self.B0, P.n_frames, P.n_points)
-            H, _ = SV.normal_equations(self.Jabs, w0, np.where(self.frozen, r0, 0.0))
-            self.H = H
-            self.red = SV.Reduced(H, P.n_frames, P.damping_rel, P.pinned_frame)
+            self._ic_system()
+
+    def _ic_system(self):
+        """H = J^T W0 J over the frozen residuals and its reduced system, from
+        the rows of J and the weights kept at p(0)."""
+        P, L = self.prob, self.L
+        J = np.where(self.frozen[:, None], self.J0, 0.0)
+        self.J_rel = J
+        self.Jabs = SV.absolute_jacobian(L, J, self.A0, self.B0, P.n_frames, P.n_points)
+        H, _ = SV.normal_equations(self.Jabs, np.where(self.frozen, self.w0, 0.0), np.zeros(self.frozen.shape))
+        self.H = H
+        self.red = SV.Reduced(H, P.n_frames, P.damping_rel, P.pinned_frame)
+
+    def drop_frame(self, f):
+        """Take frame f's observations out of the window: every observation
+        of a point hosted by f and every observation with target f. Within a
+        level the frozen residual set loses them and (IC) the system is formed
+        again from the rows kept at p(0), without a new linearization."""
+        P = self.prob
+        assert 0 <= f < P.n_frames and f != P.pinned_frame, "the gauge frame cannot be dropped"
+        counts = np.diff(P.obs_ptr)
+        obs_host = np.repeat(P.host_frame, counts)
+        self.obs_live &= ~((obs_host == f) | (P.obs_frame == f))
+        if self.level is not None:
+            self.frozen &= self.obs_live[self.L.res_obs]
+            if self.mode == "ic":
+                self._ic_system()
 
     # ---- one Gauss-Newton iteration at the current level
     def step(self):
@@ -151,7 +184,8 @@ class GaussNewton:
             Rn, tn, dn = G.ic_update(R, t, self.d, R0, self.d0, dth6[:, :3], dth6[:, 3:], dd)
             self.poses = G.pack(Rn, tn)
             self.d = dn
-        st["max_disp_px"] = RS.max_centre_displacement(L, poses_before, d_before, self.poses, self.d)
+        st["max_disp_px"] = RS.max_centre_displacement(L, poses_before, d_before, self.poses, self.d,
+                                                       live=self.obs_live)
         st["step_pose"] = float(np.max(np.abs(dth))) if dth.size else 0.0
         st["step_depth"] = float(np.max(np.abs(dd))) if dd.size else 0.0
         self.history.append(st)
@@ -180,6 +214,7 @@ class GaussNewton:
         P = self.prob
         L = P.layout(level)
         r, valid, _, _ = RS.warp_residuals(P, L, self.poses, self.d)
+        valid = valid & self.obs_live[L.res_obs]
         r = np.where(valid, r, 0.0)
         n = int(valid.sum())
         return {"energy": float(np.sum(RS.huber_rho(r, P.huber_k) * valid)), "sq": float(np.sum(r * r)),

@@ -148,13 +148,16 @@ def centre_pixels(layout, poses, d):
     return q, ok
 
 
-def max_centre_displacement(layout, poses_a, d_a, poses_b, d_b):
+def max_centre_displacement(layout, poses_a, d_a, poses_b, d_b, live=None):
     """Convergence measure of Sec. 4.1: the largest change, in level-0 pixels,
     of the reprojected point centres between parameters a and b, over every
-    observation whose centre lies in front of the target camera under both.
-    The measure does not depend on the pyramid level being iterated."""
+    observation whose centre lies in front of the target camera under both
+    (and, with `live`, that is still in the window). The measure does not
+    depend on the pyramid level being iterated."""
     qa, oka = centre_pixels(layout, poses_a, d_a)
     qb, okb = centre_pixels(layout, poses_b, d_b)
     ok = oka & okb
+    if live is not None:
+        ok = ok & live
     disp = np.hypot(qb[:, 0] - qa[:, 0], qb[:, 1] - qa[:, 1])
     return float(np.max(np.where(ok, disp, 0.0))) if ok.size else 0.0
