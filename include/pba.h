@@ -261,6 +261,26 @@ pba_status pba_get_params(pba_ctx *ctx, int32_t window, double *poses, double *i
  * iterate restarts the level. */
 pba_status pba_set_params(pba_ctx *ctx, int32_t window, const double *poses, const double *inv_depth);
 
+/* Sliding window, keyframe drop (Sec. 4.2: the IC Hessian has to be formed
+ * again whenever a keyframe joins or leaves the window; a dynamic Hessian
+ * avoids that). Takes frame `frame` (0..frames of the window - 1, not the
+ * pinned frame) of window `window` out of the window: every observation of a
+ * point that the frame hosts and every observation whose target it is. The
+ * frame keeps its pose and the points keep their depths, no longer
+ * constrained (their steps are zero); iteration statistics, the convergence
+ * test and pba_evaluate skip the dropped observations from now on. Within an
+ * IC level the reduced system is formed again without a new linearization:
+ * the pair blocks, h and H_dd are summed from the per-observation records kept
+ * at the level's p(0), then the depth Schur complement, its Cholesky factor
+ * and inverse (PBA_MIXED_BF16, whose pose blocks come from its MFMA
+ * contraction, linearizes again at p(0)); the result equals the level's set-up
+ * at p(0) of the problem without those observations. FC takes the drop at its
+ * next iteration. A dropped frame cannot come back (set the points again).
+ * Synchronous. Errors: PBA_E_INVALID (window, frame or pinned frame),
+ * PBA_E_STATE (frames or points not set), PBA_E_NUMERIC (the new reduced
+ * system is not positive definite). */
+pba_status pba_drop_frame(pba_ctx *ctx, int32_t window, int32_t frame);
+
 /* Result of pba_autotune: the launch shapes tried for the per-iteration
  * residual kernel (IC: the residual / J^T W r kernel; FC: the linearization
  * kernel) and their measured mean launch time. */

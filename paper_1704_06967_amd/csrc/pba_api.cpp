@@ -118,6 +118,7 @@ void release_points(Ctx &c) {
     for (int **p : {&c.d_win_pair_off, &c.d_win_point_off, &c.d_point_win}) dfree(*p);
     dfree(c.d_host_uv);
     dfree(c.d_mask);
+    dfree(c.d_obs_live);
     dfree(c.d_rec);
     dfree(c.d_depth);
     dfree(c.d_depth0);
@@ -316,6 +317,30 @@ std::string build_structure(Ctx &c, const std::vector<int> &host_frame, const st
 }
 
 // ---- level start and iterations, per element type
+
+// The IC system of the level at p(0): J (Sec. 3.4) and W0, H = J^T W0 J, the
+// depth Schur complement, its Cholesky factor and inverse. With linearize
+// false (a keyframe dropped mid-level) the pair blocks, h and H_dd are summed
+// again from the per-observation records kept at p(0) (those of dropped
+// observations are zero) and the residuals are not evaluated again; the
+// mixed form, whose pose blocks come from its MFMA contraction rather than
+// from the records, linearizes again at p(0).
+template <typename T>
+void ic_system(Ctx &c, int level, bool linearize) {
+    hipStream_t s = c.stream;
+    if (is_mixed(c)) {
+        launch_linearize_mixed(s, c, level, true, c.d_geo0, true);
+    } else {
+        if (linearize) Launch<T>::ic_linearize(s, c, level);
+        Launch<T>::pair_reduce_H(s, c);
+    }
+    Launch<T>::point_reduce(s, c, true);
+    launch_mu(s, c, c.d_geo0);
+    launch_gram(s, c, c.d_geo0, c.d_rec, true);
+    launch_assemble_s(s, c, c.d_geo0);
+    launch_ic_factor(s, c);
+    launch_ic_inverse(s, c);
+}
 // Opens the level's gate (clear_flag: also clears the failure flag) and sets up
 // the level. recentre: proxy re-centring inside the level (IC): the same set-up
 // at the current parameters, gated (no effect once the level's gate is closed),
@@ -330,19 +355,7 @@ pba_status start_level(Ctx &c, int level, bool clear_flag, bool recentre = false
     Launch<T>::level_begin(s, c, level, clear_flag, recentre);
     c.flip = false;
     if (c.cfg.mode == PBA_IC_PROXY) {
-        // J (Sec. 3.4) and W0 at p(0); H = J^T W0 J, depth Schur complement, Cholesky, inverse
-        if (is_mixed(c)) {
-            launch_linearize_mixed(s, c, level, true, c.d_geo0, true);
-        } else {
-            Launch<T>::ic_linearize(s, c, level);
-            Launch<T>::pair_reduce_H(s, c);
-        }
-        Launch<T>::point_reduce(s, c, true);
-        launch_mu(s, c, c.d_geo0);
-        launch_gram(s, c, c.d_geo0, c.d_rec, true);
-        launch_assemble_s(s, c, c.d_geo0);
-        launch_ic_factor(s, c);
-        launch_ic_inverse(s, c);
+        ic_system<T>(c, level, true);
         c.s_valid = true;
     } else {
         c.s_valid = false;
@@ -880,6 +893,8 @@ pba_status load_points_ordered(Ctx &c, int n_points, const std::vector<int> &hf,
     const size_t rs = c.real_size;
     const int Pn = s.n_pairs;
     HIPCHK(dalloc(c.d_mask, std::max<size_t>(1, O)));
+    HIPCHK(dalloc(c.d_obs_live, std::max<size_t>(1, O)));
+    HIPCHK(hipMemsetAsync(c.d_obs_live, 1, std::max<size_t>(1, O), c.stream));
     HIPCHK(dalloc(c.d_rec, (size_t)O * REC_STRIDE * sizeof(double)));   // records: FP64 for every element type
     HIPCHK(dalloc(c.d_geo0, (size_t)Pn * GEO_STRIDE * sizeof(double)));
     HIPCHK(dalloc(c.d_geo_a, (size_t)Pn * GEO_STRIDE * sizeof(double)));
@@ -1432,6 +1447,35 @@ pba_status pba_set_params(pba_ctx *ctx, int32_t window, const double *poses, con
     }
     HIPCHK(hipStreamSynchronize(c.stream));
     c.cur_level = -1;
+    return PBA_OK;
+}
+
+pba_status pba_drop_frame(pba_ctx *ctx, int32_t window, int32_t frame) {
+    if (!ctx) return fail(nullptr, PBA_E_INVALID, "ctx is NULL");
+    Ctx &c = ctx->c;
+    if (window < 0 || window >= c.cfg.n_windows) return fail(&c, PBA_E_INVALID, "window must be in 0..n_windows-1");
+    pba_status st;
+    if ((st = ready(ctx)) != PBA_OK) return st;
+    const int f0 = c.win_frame_off[window], nf = c.win_frame_off[window + 1] - f0;
+    if (frame < 0 || frame >= nf) return fail(&c, PBA_E_INVALID, "frame out of range for the window");
+    if (frame == c.cfg.pinned_frame) return fail(&c, PBA_E_INVALID, "the gauge (pinned) frame cannot be dropped");
+    launch_drop_frame(c.stream, c, f0 + frame);
+    if (c.cfg.mode == PBA_IC_PROXY && c.cur_level >= 0 && c.s_valid) {
+        // mid-level: the system again from the records kept at p(0)
+        launch_open(c.stream, c, c.cur_level, true);
+        if (is_fp64(c))
+            ic_system<double>(c, c.cur_level, false);
+        else
+            ic_system<float>(c, c.cur_level, false);
+    }
+    HIPCHK(hipStreamSynchronize(c.stream));
+    HIPCHK(hipGetLastError());
+    int flag = 0;
+    HIPCHK(hipMemcpy(&flag, c.d_flag, sizeof(int), hipMemcpyDeviceToHost));
+    if (flag) {
+        c.cur_level = -1;
+        return fail(&c, PBA_E_NUMERIC, "reduced pose system is not positive definite");
+    }
     return PBA_OK;
 }
 

@@ -54,13 +54,15 @@ __device__ __forceinline__ DepthPoint depth_point(int N, int n0, const int *__re
 // and depth step of the block, valid in thread 0. pt: the thread's point data
 // (depth_point); with gate / flag given, the gate is read right after it and
 // false comes back when it is closed (nothing written). dth_rel [pair][6] and
-// geo_new [pair][GEO_STRIDE] may live in LDS.
+// geo_new [pair][GEO_STRIDE] may live in LDS. live: the observations still in
+// the window (the displacement skips the others).
 template <typename T, int NT>
 __device__ __forceinline__ bool depth_points(
     int N, int n0, int ic, const DepthPoint &pt, const int *__restrict__ obs_pair,
     const double *__restrict__ pairK0, const double *__restrict__ rec, const double *__restrict__ gr, int gs,
     const double *dth_rel, const double *__restrict__ geo_old, const double *geo_new, double *__restrict__ depth,
-    const int *gate, const int *flag, double *lds, double &mdisp_out, double &mstep_out) {
+    const int *gate, const int *flag, double *lds, double &mdisp_out, double &mstep_out,
+    const uint8_t *__restrict__ live) {
     constexpr int NPTS = NT / DU_SLOTS, NW = NT / 64;
     static_assert(NW <= 16, "the block maxima are taken over one row of 16 lanes");
     double(*sp)[DU_SLOTS][2] = reinterpret_cast<double(*)[DU_SLOTS][2]>(lds);
@@ -117,7 +119,7 @@ __device__ __forceinline__ bool depth_points(
             qq[s2][0] = Kp[4] * vx / vzs + Kp[6];
             qq[s2][1] = Kp[5] * vy / vzs + Kp[7];
         }
-        if (ok) mdisp = fmax(mdisp, hypot(qq[1][0] - qq[0][0], qq[1][1] - qq[0][1]));
+        if (ok && live[o]) mdisp = fmax(mdisp, hypot(qq[1][0] - qq[0][0], qq[1][1] - qq[0][1]));
     }
     mdisp = wave_max(mdisp);
     mstep = wave_max(mstep);

@@ -195,6 +195,7 @@ struct Ctx {
         *d_pchunk_begin = nullptr, *d_pchunk_end = nullptr, *d_pair_chunk_ptr = nullptr;
     float *d_host_uv = nullptr;                        // [N][2]
     uint8_t *d_mask = nullptr;                         // [O]
+    uint8_t *d_obs_live = nullptr;                     // [O] 1 while the observation is in the window (pba_drop_frame)
     void *d_rec = nullptr;                             // double [O][REC_STRIDE]
     void *d_icr = nullptr;                             // double [O][IC_REC] gradient records of the IC iterations
     double *d_geo0 = nullptr, *d_geo_a = nullptr, *d_geo_b = nullptr;   // [Pn][GEO_STRIDE]
@@ -319,6 +320,7 @@ void launch_ic_step(hipStream_t s, Ctx &c, const double *geo_lin, const double *
 int du_nparts(const Ctx &c);   // blocks of the depth step (parts of its convergence maxima)
 // count[level] = 0, optionally flag = 0, then gate = (flag == 0)
 void launch_open(hipStream_t s, Ctx &c, int level, bool clear_flag);
+void launch_drop_frame(hipStream_t s, Ctx &c, int frame);
 void launch_ic_inverse(hipStream_t s, Ctx &c);
 void launch_tchol(hipStream_t s, Ctx &c, bool copy = true);   // (copy S to d_Sfac and) factor d_Sfac in tiles
 void launch_tinv(hipStream_t s, Ctx &c);    // S^{-1} from the tiled factor

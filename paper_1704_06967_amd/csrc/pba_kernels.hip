@@ -179,6 +179,7 @@ struct ResArgs {
     const T *rel0;       // relative poses at p(0) (IC Jacobian)
     const double *depth, *depth0;
     uint8_t *mask;
+    const uint8_t *live; // 1 while the observation is in the window
     double *rec;         // per-observation records (FP64 for every element type)
     const double *pcam;  // per pair: host and target level intrinsics (fx, fy, cx, cy) x 2
     double *icr;         // IC iterations: per observation g (6), g_d, energy, sum r^2, count (FP64)
@@ -218,8 +219,9 @@ __device__ __forceinline__ bool lin_eval(const ResArgs<T> &a, int o, int j, int 
     const T *tp = a.tmpl + 4 * ((size_t)n * a.P + j);
     const T I0 = tp[0], gu0 = tp[1], gv0 = tp[2];
     const bool host_ok = tp[3] != T(0);
-    bool frozen = true;
-    if (!write_mask) frozen = (a.mask[o] >> j) & 1;
+    // the frozen set: written from the usable residuals of the observations
+    // still in the window, or read
+    const bool frozen = write_mask ? a.live[o] != 0 : ((a.mask[o] >> j) & 1) != 0;
     double x, y;
     template_xy(a, n, j, Kh, x, y);
     const double *R = a.geo + GEO_STRIDE * pr;
@@ -769,7 +771,7 @@ __global__ __launch_bounds__(BLOCK) void k_evaluate(ResArgs<T> a) {
         const double *t = R + 9;
         const double d = a.depth[n];
         const double vz = R[6] * x + R[7] * y + R[8] + d * t[2];
-        if (tp[3] != T(0) && d > 0.0 && vz > 0.0) {
+        if (tp[3] != T(0) && a.live[o] && d > 0.0 && vz > 0.0) {
             const double vx = R[0] * x + R[1] * y + R[2] + d * t[0];
             const double vy = R[3] * x + R[4] * y + R[5] + d * t[1];
             const double iz = 1.0 / vz;
@@ -1022,13 +1024,13 @@ __global__ __launch_bounds__(256) void k_depth_update(
     const double *__restrict__ gr, int gs, const double *__restrict__ Hdd, const double *__restrict__ dth_rel,
     const double *__restrict__ geo_old, const double *__restrict__ geo_new, double *__restrict__ depth,
     const double *__restrict__ depth0, double *__restrict__ part, const int *__restrict__ gate,
-    const int *__restrict__ flag) {
+    const int *__restrict__ flag, const uint8_t *__restrict__ live) {
     __shared__ double lds[depth_lds_doubles(256)];
     double md = 0.0, ms = 0.0;
     const int n0 = blockIdx.x * DU_PTS;
     const DepthPoint pt = depth_point<false>(N, n0, obs_ptr, host_uv, Hdd, depth, depth0);
     if (!depth_points<T, 256>(N, n0, ic, pt, obs_pair, pairK0, rec, gr, gs, dth_rel, geo_old, geo_new, depth, gate,
-                              flag, lds, md, ms))
+                              flag, lds, md, ms, live))
         return;
     if (threadIdx.x == 0) {
         part[2 * blockIdx.x] = md;
@@ -1066,6 +1068,7 @@ static ResArgs<T> res_args(Ctx &c, int level, const double *geo_cur) {
     a.depth = c.d_depth;
     a.depth0 = c.d_depth0;
     a.mask = c.d_mask;
+    a.live = c.d_obs_live;
     a.rec = (double *)c.d_rec;
     a.pcam = (const double *)c.lv[level].pcam;
     a.icr = (double *)c.d_icr;
@@ -1176,7 +1179,9 @@ static void launch_linearize_shape(hipStream_t s, const Ctx &c, const ResArgs<T>
 template <typename T>
 void Launch<T>::ic_linearize(hipStream_t s, Ctx &c, int level) {
     if (c.O == 0) return;
+    // at p(0): the poses and the inverse depths of the level's linearization
     ResArgs<T> a = res_args<T>(c, level, c.d_geo0);
+    a.depth = c.d_depth0;
     launch_linearize_shape<T, true>(s, c, a, 1, LaunchShape{});
     CHECK_LAUNCH();
 }
@@ -1195,6 +1200,7 @@ void launch_linearize_mixed(hipStream_t s, Ctx &c, int level, bool ic, const dou
     const int nch = (int)c.st.pchunk_begin.size();
     if (c.O == 0 || nch == 0) return;
     ResArgs<float> a = res_args<float>(c, level, geo_cur);
+    if (ic) a.depth = c.d_depth0;   // IC linearizes at p(0)
     if (ic)
         launch_ev(k_linearize_mixed<true>, nch, BLOCK, s, e0, e1, a, 1, (const int *)c.d_pchunk_begin,
                   (const int *)c.d_pchunk_end, (const int *)c.d_pair_obs_idx, c.d_partH);
@@ -1295,7 +1301,7 @@ void Launch<T>::depth_update(hipStream_t s, Ctx &c, const double *geo_old, const
         k_depth_update<T><<<nb, 256, 0, s>>>(c.N, c.cfg.mode == PBA_IC_PROXY ? 1 : 0, c.d_obs_ptr, c.d_obs_pair,
                                              c.d_host_uv, c.d_pairK0, (const double *)c.d_rec, gr, gs, c.d_Hdd,
                                              c.d_dth_rel, geo_old, geo_new, c.d_depth, c.d_depth0, c.d_du_part,
-                                             c.d_gate, c.d_flag);
+                                             c.d_gate, c.d_flag, c.d_obs_live);
     CHECK_LAUNCH();
     if (finish) launch_conv(s, c, stat, conv_px, du_nparts(c), level);
 }
@@ -1335,6 +1341,30 @@ __global__ void k_open(int *__restrict__ gate, int *__restrict__ flag, int *__re
         *count = 0;
         *count_base = 0;
     }
+}
+
+// Keyframe drop (sliding window): every observation of a point hosted by
+// frame f or with target f leaves the window: its live flag and frozen
+// pixels are cleared and its record zeroed, so that sums over the records
+// (pair blocks, h, H_dd, the gradient) no longer see it.
+__global__ void k_drop_frame(int O, int f, const int *__restrict__ obs_pair, const int *__restrict__ pair_host,
+                             const int *__restrict__ pair_target, uint8_t *__restrict__ live,
+                             uint8_t *__restrict__ mask, double *__restrict__ rec) {
+    const int o = blockIdx.x * blockDim.x + threadIdx.x;
+    if (o >= O) return;
+    const int p = obs_pair[o];
+    if (pair_host[p] != f && pair_target[p] != f) return;
+    live[o] = 0;
+    mask[o] = 0;
+    double *r = rec + (size_t)o * REC_STRIDE;
+    for (int k = 0; k < REC_STRIDE; ++k) r[k] = 0.0;
+}
+
+void launch_drop_frame(hipStream_t s, Ctx &c, int frame) {
+    if (c.O == 0) return;
+    k_drop_frame<<<nblk(c.O, 256), 256, 0, s>>>(c.O, frame, c.d_obs_pair, c.d_pair_host, c.d_pair_target,
+                                                c.d_obs_live, c.d_mask, (double *)c.d_rec);
+    CHECK_LAUNCH();
 }
 
 void launch_conv(hipStream_t s, Ctx &c, double *stat, double conv_px, int nparts, int level, bool pose_sync) {

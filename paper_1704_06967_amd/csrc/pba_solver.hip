@@ -1057,7 +1057,7 @@ __global__ __launch_bounds__(SOLVE_THREADS) void k_ic_step(
     const double *__restrict__ pairK0, const double *__restrict__ rec, const double *__restrict__ gr, int gs,
     const double *__restrict__ Hdd, const double *__restrict__ geo_old, double *__restrict__ depth,
     const double *__restrict__ depth0, double *__restrict__ part, const int *__restrict__ step_sel, int sel_ncw,
-    int nch) {
+    int nch, const uint8_t *__restrict__ live) {
     __shared__ double lds[LDS_DOUBLES];
     __shared__ double red[64 + 2 * LDS_MAX_N + 2];
     const bool writer = blockIdx.x == 0;
@@ -1080,7 +1080,7 @@ __global__ __launch_bounds__(SOLVE_THREADS) void k_ic_step(
     const double *c_out = lds + LDS_DOUBLES - solve_out_doubles(P, true);
     double md = 0.0, ms = 0.0;
     depth_points<T, SOLVE_THREADS>(N, b * IC_STEP_PTS, 1, pt, obs_pair, pairK0, rec, gr, gs, c_out + GEO_STRIDE * P,
-                                   geo_old, c_out, depth, nullptr, nullptr, lds, md, ms);
+                                   geo_old, c_out, depth, nullptr, nullptr, lds, md, ms, live);
     if (threadIdx.x == 0) {
         part[2 * b] = md;
         part[2 * b + 1] = ms;
@@ -1217,7 +1217,7 @@ static void ic_step_kernel(hipStream_t s, Ctx &c, const double *geo_lin, const d
         c.d_pair_host, c.d_pair_target, c.d_pair_chunk_ptr, c.d_partY, c.d_pairY, geo_lin, c.d_Sinv, p_in, p_out,
         c.d_poses0, c.d_b, c.d_dtheta, c.d_dth_rel, geo_next, rel_next, c.d_wstat, c.d_flag, c.d_gate, c.N,
         c.d_obs_ptr, c.d_obs_pair, c.d_host_uv, c.d_pairK0, rec, gr, IC_REC, c.d_Hdd, geo_old, c.d_depth,
-        c.d_depth0, c.d_du_part, c.d_step_sel, step_sel_ncw(c), (int)c.st.pchunk_begin.size());
+        c.d_depth0, c.d_du_part, c.d_step_sel, step_sel_ncw(c), (int)c.st.pchunk_begin.size(), c.d_obs_live);
 }
 
 void launch_ic_step(hipStream_t s, Ctx &c, const double *geo_lin, const double *geo_old, double *geo_next,

@@ -126,6 +126,7 @@ _sig = {
     "pba_evaluate": (C.c_int, [_P, C.c_int32, C.POINTER(pba_iter_stats)]),
     "pba_get_params": (C.c_int, [_P, C.c_int32, _P, _P]),
     "pba_set_params": (C.c_int, [_P, C.c_int32, _P, _P]),
+    "pba_drop_frame": (C.c_int, [_P, C.c_int32, C.c_int32]),
     "pba_debug_fetch": (C.c_int, [_P, C.c_int32, _P, C.c_size_t]),
     "pba_get_timing": (C.c_int, [_P, C.POINTER(pba_timing)]),
     "pba_autotune": (C.c_int, [_P, C.c_int32, C.c_int32, C.POINTER(pba_tune_report)]),
@@ -273,6 +274,9 @@ class Solver:
     def set_params(self, poses, inv_depth, window=0):
         self._chk(pba_set_params(self.ctx, window, _ptr(np.ascontiguousarray(poses, np.float64)),
                                  _ptr(np.ascontiguousarray(inv_depth, np.float64))))
+
+    def drop_frame(self, frame, window=0):
+        self._chk(pba_drop_frame(self.ctx, window, frame))
 
     def fetch(self, what):
         n6 = 6 * self.F
