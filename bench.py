@@ -299,6 +299,34 @@ def converged_section(pba, precision, max_iters=40, conv_px=5e-3, reps=10):
     return out
 
 
+def dynamic_section(pba, scene, reps=10, frame=13):
+    """Sliding-window keyframe drop on the mid workload (FP32, IC at level 0):
+    the time of pba_drop_frame, which forms the reduced system again from the
+    records kept at p(0), against the time of a level start, which
+    linearizes every residual first (both synchronous calls, median of
+    `reps`)."""
+    kw = dict(mode=pba.PBA_IC_PROXY, precision=pba.PBA_FP32, n_levels=scene.n_levels, pattern=scene.pattern,
+              huber_k=scene.huber_k)
+    drop_ms, start_ms = [], []
+    for _ in range(reps):
+        s = pba.Solver(**kw)
+        s.set_scene(scene)
+        s.iterate(0, 2)
+        t0 = time.perf_counter()
+        s.drop_frame(frame)
+        drop_ms.append((time.perf_counter() - t0) * 1e3)
+        s.set_params(scene.poses_init, scene.inv_depth_init)
+        t0 = time.perf_counter()
+        s.iterate(0, 0)   # the level start alone (linearization, Schur complement, factor, inverse)
+        start_ms.append((time.perf_counter() - t0) * 1e3)
+        s.close()
+    d, st = float(np.median(drop_ms)), float(np.median(start_ms))
+    return {"workload": f"mid, IC FP32 at level 0: drop frame {frame} after 2 iterations", "drop_ms": round(d, 4),
+            "level_start_ms": round(st, 4), "drop_over_level_start": round(d / st, 3),
+            "note": "host wall time of the synchronous calls (median); the drop sums the pair blocks, h and H_dd "
+                    "again from the records at p(0) instead of linearizing every residual"}
+
+
 def cpu_model():
     try:
         with open("/proc/cpuinfo") as f:
@@ -799,6 +827,9 @@ def main():
         t0 = time.perf_counter()
         line["equal_rmse"] = equal_rmse_section(pba, scene, pba.PBA_FP32, args.conv_px, args.max_iters)
         log(f"equal RMSE (mid): {time.perf_counter() - t0:.1f} s")
+    t0 = time.perf_counter()
+    line["dynamic_hessian"] = dynamic_section(pba, scene)
+    log(f"keyframe drop: {line['dynamic_hessian']} ({time.perf_counter() - t0:.1f} s)")
     if not args.no_trace:
         t0 = time.perf_counter()
         line["equal_rmse_converged"] = converged_section(pba, pba.PBA_FP32)
