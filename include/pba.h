@@ -261,9 +261,9 @@ pba_status pba_get_params(pba_ctx *ctx, int32_t window, double *poses, double *i
  * iterate restarts the level. */
 pba_status pba_set_params(pba_ctx *ctx, int32_t window, const double *poses, const double *inv_depth);
 
-/* Sliding window, keyframe drop (Sec. 4.2: the IC Hessian has to be formed
- * again whenever a keyframe joins or leaves the window; a dynamic Hessian
- * avoids that). Takes frame `frame` (0..frames of the window - 1, not the
+/* Sliding window, keyframe drop (Sec. 4.2: in the DSO integration every
+ * change of the keyframe set still cost a new Hessian; a dynamic Hessian is
+ * named as the next speed-up). Takes frame `frame` (0..frames of the window - 1, not the
  * pinned frame) of window `window` out of the window: every observation of a
  * point that the frame hosts and every observation whose target it is. The
  * frame keeps its pose and the points keep their depths, no longer

@@ -20,9 +20,9 @@ behind the camera, gets weight 0 for that iteration); p(0) is re-centred at
 the start of every pyramid level; the convergence test (Sec. 4.1) takes the
 largest level-0 pixel displacement of any observation's point centre.
 
-Dropping a keyframe (sliding window, dynamic Hessian): the paper notes that
-the IC Hessian must be formed again whenever a keyframe joins or leaves the
-window, and that a dynamic Hessian would save that (Sec. 4.2). drop_frame(f)
+Dropping a keyframe (sliding window, dynamic Hessian): in the DSO
+integration of Sec. 4.2 every change of the keyframe set still cost a new
+Hessian, and a dynamic one is named as the next speed-up. drop_frame(f)
 takes frame f's observations out of the window (those it hosts and those in
 which it is the target; the frame stays as an unconstrained block, the
 points it hosts stay with no observation) and, mid-level, forms the IC

@@ -1,6 +1,6 @@
-"""Pins of the oracle's keyframe drop (sliding window, dynamic Hessian;
-Sec. 4.2 notes that the IC Hessian must be formed again whenever a keyframe
-joins or leaves the window). GaussNewton.drop_frame(f) takes f's observations
+"""Pins of the oracle's keyframe drop (sliding window, dynamic Hessian; in
+the DSO integration of Sec. 4.2 every change of the keyframe set still cost
+a new Hessian). GaussNewton.drop_frame(f) takes f's observations
 out of the window and, mid-level, forms the IC system again from the rows of
 J and the weights W0 kept at p(0). It is pinned to the level set-up of the
 reduced problem (the observations removed from the input, the frame and the
