@@ -29,85 +29,37 @@ sys.path.insert(0, ROOT)
 import numpy as np  # noqa: E402
 
 HBM_PEAK_GBS = 8000.0
-# HBM bytes per level-0 launch of k_ic_residual<float> from two rocprofv3 counter
-# runs: FETCH_SIZE (bytes the L2 fetched from HBM or the memory-attached last-level
-# cache, i.e. L2 misses) x 2.000 + WRITE_SIZE x 1.000, both scales from a 256 MiB
-# device copy (profiles/k_ic_residual_traffic_mid_precision.md); valid for the
-# kernel source with this hash only
-MEASURED_TRAFFIC = {"mid": 16214835, "precision": 121940378, "kernels_sha256_16": "733d7651c8517ba0"}
+# L2-miss bytes per level-0 launch from two rocprofv3 counter runs: FETCH_SIZE
+# (bytes the L2 fetched from HBM or the memory-attached last-level cache) x 2.000
+# + WRITE_SIZE x 1.000, both scales from a 256 MiB device copy
+# (profiles/ic_iteration_kernels_traffic_mid_precision.md); valid only for the kernel
+# sources whose combined hash is given
+MEASURED_TRAFFIC = {"k_ic_residual": {"mid": 17164595, "precision": 128364544},
+                    "k_ic_step": {"mid": 11062170},
+                    "sources_sha256_16": "0685b77fa31d64ed"}
+KERNEL_SOURCES = ("pba_kernels.hip", "pba_solver.hip", "pba_depth.hpp", "pba_device.hpp", "pba_internal.hpp")
 
 
-def measured_traffic(workload):
-    ksrc = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_1704_06967_amd", "csrc", "pba_kernels.hip")
-    sha = hashlib.sha256(open(ksrc, "rb").read()).hexdigest()[:16]
-    return MEASURED_TRAFFIC[workload] if sha == MEASURED_TRAFFIC["kernels_sha256_16"] else None
+def kernel_sources_sha():
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_1704_06967_amd", "csrc", f),
+                  "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
 
 
-METRIC = "GN iters/s & residuals/s, IC-proxy vs FC on same GPU at equal final photo-RMSE"
-
-
-def log(*a):
-    print(*a, file=sys.stderr, flush=True)
-
-
-def level_pixels(scene, level):
-    """Level-`level` target pixels of every residual at the scene's starting
-    parameters (host patch pixel -> warp -> projection), for byte counting."""
-    P = scene.pattern.shape[0]
-    N = scene.n_points
-    obs_point = np.repeat(np.arange(N), np.diff(scene.obs_ptr))
-    host = scene.host_frame[obs_point]
-    tgt = scene.obs_frame
-    s = 2.0 ** level
-    K = scene.intrinsics
-    uv = (scene.host_uv[obs_point].astype(float) + 0.5) / s - 0.5
-    pu = uv[:, None, 0] + scene.pattern[None, :, 0]
-    pv = uv[:, None, 1] + scene.pattern[None, :, 1]
-    Kh, Kt = K[host] / np.array([s, s, 1, 1]), K[tgt] / np.array([s, s, 1, 1])
-    Kh[:, 2:] = (K[host, 2:] + 0.5) / s - 0.5
-    Kt[:, 2:] = (K[tgt, 2:] + 0.5) / s - 0.5
-    x = (pu - Kh[:, None, 2]) / Kh[:, None, 0]
-    y = (pv - Kh[:, None, 3]) / Kh[:, None, 1]
-    Rp = scene.poses_init[:, :9].reshape(-1, 3, 3)
-    tp = scene.poses_init[:, 9:]
-    R = Rp[tgt] @ np.swapaxes(Rp[host], 1, 2)
-    t = tp[tgt] - np.einsum("oij,oj->oi", R, tp[host])
-    d = scene.inv_depth_init[obs_point]
-    v = (R[:, None, :, 0] * x[..., None] + R[:, None, :, 1] * y[..., None] + R[:, None, :, 2]
-         + d[:, None, None] * t[:, None, :])
-    qu = Kt[:, None, 0] * v[..., 0] / v[..., 2] + Kt[:, None, 2]
-    qv = Kt[:, None, 1] * v[..., 1] / v[..., 2] + Kt[:, None, 3]
-    return tgt, qu, qv
-
-
-def _pairs(scene):
-    """(host, target) pair of every observation and the number of distinct pairs."""
-    host = scene.host_frame[np.repeat(np.arange(scene.n_points), np.diff(scene.obs_ptr))]
-    key = host.astype(np.int64) * scene.n_frames + scene.obs_frame
-    uniq, counts = np.unique(key, return_counts=True)
-    return uniq.size, counts
-
-
-def _unique_texels(scene, level, halo):
-    """Distinct target texels of the bilinear footprints at the starting
-    parameters: 2 x 2 (halo 0) or the 4 x 4 of the interpolated central
-    differences (halo 1)."""
-    F, H, W = scene.images.shape
-    Wl, Hl = W >> level, H >> level
-    tgt, qu, qv = level_pixels(scene, level)
-    ok = (qu >= 1) & (qu <= Wl - 3) & (qv >= 1) & (qv <= Hl - 3)
-    j0 = np.floor(qu[ok]).astype(np.int64)
-    i0 = np.floor(qv[ok]).astype(np.int64)
-    f = np.broadcast_to(tgt[:, None], qu.shape)[ok].astype(np.int64)
-    base = (f * Hl + i0) * Wl + j0
-    offs = [di * Wl + dj for di in range(-halo, 2 + halo) for dj in range(-halo, 2 + halo)]
-    return int(np.unique(np.concatenate([base + o for o in offs])).size)
+def measured_traffic(kernel, workload):
+    if kernel_sources_sha() != MEASURED_TRAFFIC["sources_sha256_16"]:
+        return None
+    return MEASURED_TRAFFIC[kernel].get(workload)
 
 
 def ic_residual_bytes(scene, level=0, real=4):
     """Algorithmic bytes of one launch of the IC residual kernel at `level`:
     per observation its point and pair index, mask byte and the 10-value FP64
-    record it writes; per observed point its pixel, two depths and the 8 template
+    record it writes and its g_d once more (contiguous, for the depth
+    readers); per observed point its pixel, two depths and the 8 template
     records (I0, gradient, usable); per pair the FP64 level intrinsics of host
     and target (8 values), the FP64 current relative pose (12) and the
     relative pose at p(0) in the element type (12); the target texels touched
@@ -119,7 +71,7 @@ def ic_residual_bytes(scene, level=0, real=4):
     texels = _unique_texels(scene, level, 0)
     reads = (O * (4 + 4 + 1) + n_obs_pts * (8 + 8 + 8 + P * 4 * real) + n_pairs * (8 * 8 + 12 * 8 + 12 * real)
              + texels * real)
-    writes = O * 10 * 8   # FP64 sums for every element type
+    writes = O * 11 * 8   # FP64 sums for every element type
     return {"bytes": int(reads + writes), "reads": int(reads), "writes": int(writes), "unique_texels": int(texels),
             "observations": O, "residual_slots": O * 8}
 
@@ -471,7 +423,7 @@ def precision_section(pba, steps, max_iters, conv_px, sc=None, event_timing=True
             out["residual_roofline"] = {"kernel": "k_ic_residual<float> (level 0)", "bound": "hbm",
                                         "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                                         "frac": round(gbs / HBM_PEAK_GBS, 4),
-                                        "traffic": measured_traffic("precision"), "avg_launch_us": round(avg_us, 3),
+                                        "traffic": measured_traffic("k_ic_residual", "precision"), "avg_launch_us": round(avg_us, 3),
                                         "algorithmic_bytes_per_launch": nb["bytes"], "bytes_detail": nb}
         log(f"precision {name}: {out[name]['ms_per_solve']} ms per solve, residual kernel {avg_us:.1f} us")
     out["ic_mixed_vs_fp64"] = param_errors(*results["ic_mixed"], *results["ic_fp64"])
@@ -776,10 +728,11 @@ def main():
     nb_res = ic_residual_bytes(scene, 0, 4)
     res_l0 = ic_tm["residual_launches"][0]
     res_ms = ic_tm["residual_ms"][0] / max(1, res_l0)
-    rl_res = roofline_obj("k_ic_residual<float> (level 0)", nb_res, res_ms, res_l0, measured_traffic("mid"))
+    rl_res = roofline_obj("k_ic_residual<float> (level 0)", nb_res, res_ms, res_l0, measured_traffic("k_ic_residual", "mid"))
     step_l0 = ic_tm["step_launches"][0]
     step_ms = ic_tm["step_ms"][0] / max(1, step_l0)
     rl_step = roofline_obj("k_ic_step<float> (level 0)", ic_step_bytes(scene, 4), step_ms, step_l0,
+                           measured_traffic("k_ic_step", "mid"),
                            note="one launch per iteration: the reduced solve (S^-1 b) and the pose update in "
                                 "every workgroup, then each depth workgroup's depth step; bound by dependent "
                                 "load latency and the per-CU return rate, not HBM bandwidth")

@@ -123,12 +123,13 @@ void release_points(Ctx &c) {
     dfree(c.d_depth);
     dfree(c.d_depth0);
     for (double **p : {&c.d_geo0, &c.d_geo_a, &c.d_geo_b, &c.d_pairH, &c.d_pairY, &c.d_Hdd, &c.d_gd,
-                       &c.d_gram, &c.d_dth_rel, &c.d_partH, &c.d_partY, &c.d_obsmap})
+                       &c.d_gram, &c.d_dth_rel, &c.d_partH, &c.d_partY, &c.d_obsmap, &c.d_hc})
         dfree(*p);
     dfree(c.d_rel0);
     dfree(c.d_rel_a);
     dfree(c.d_rel_b);
     dfree(c.d_icr);
+    dfree(c.d_gdo);
     for (int l = 0; l < PBA_MAX_LEVELS; ++l) {
         dfree(c.lv[l].tmpl);
         dfree(c.lv[l].pcam);
@@ -907,6 +908,7 @@ pba_status load_points_ordered(Ctx &c, int n_points, const std::vector<int> &hf,
     HIPCHK(dalloc(c.d_partH, s.pchunk_begin.size() * 21 * sizeof(double)));
     HIPCHK(dalloc(c.d_partY, s.pchunk_begin.size() * 9 * sizeof(double)));
     HIPCHK(dalloc(c.d_obsmap, (size_t)O * 12 * sizeof(double)));
+    HIPCHK(dalloc(c.d_hc, (size_t)O * 6 * sizeof(double)));
     HIPCHK(dalloc(c.d_Hdd, (size_t)n_points * sizeof(double)));
     HIPCHK(dalloc(c.d_gd, (size_t)n_points * sizeof(double)));
     HIPCHK(dalloc(c.d_gram, s.gram_floats * sizeof(double)));
@@ -963,6 +965,7 @@ pba_status load_points_ordered(Ctx &c, int n_points, const std::vector<int> &hf,
         }
     }
     HIPCHK(dalloc(c.d_icr, (size_t)O * IC_REC * sizeof(double)));
+    HIPCHK(dalloc(c.d_gdo, (size_t)O * sizeof(double)));
     for (int l = 0; l < c.cfg.n_levels; ++l) {
         HIPCHK(dalloc(c.lv[l].tmpl, (size_t)n_points * c.P * 4 * rs));
         HIPCHK(dalloc(c.lv[l].pcam, (size_t)std::max(1, Pn) * 8 * sizeof(double)));

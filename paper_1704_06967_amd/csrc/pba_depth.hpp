@@ -54,12 +54,13 @@ __device__ __forceinline__ DepthPoint depth_point(int N, int n0, const int *__re
 // and depth step of the block, valid in thread 0. pt: the thread's point data
 // (depth_point); with gate / flag given, the gate is read right after it and
 // false comes back when it is closed (nothing written). dth_rel [pair][6] and
-// geo_new [pair][GEO_STRIDE] may live in LDS. live: the observations still in
-// the window (the displacement skips the others).
+// geo_new [pair][GEO_STRIDE] may live in LDS. hc: h_o, 6 values per
+// observation; gd: g_d per observation, stride gds. live: the observations
+// still in the window (the displacement skips the others).
 template <typename T, int NT>
 __device__ __forceinline__ bool depth_points(
     int N, int n0, int ic, const DepthPoint &pt, const int *__restrict__ obs_pair,
-    const double *__restrict__ pairK0, const double *__restrict__ rec, const double *__restrict__ gr, int gs,
+    const double *__restrict__ pairK0, const double *__restrict__ hc, const double *__restrict__ gd, int gds,
     const double *dth_rel, const double *__restrict__ geo_old, const double *geo_new, double *__restrict__ depth,
     const int *gate, const int *flag, double *lds, double &mdisp_out, double &mstep_out,
     const uint8_t *__restrict__ live) {
@@ -80,10 +81,14 @@ __device__ __forceinline__ bool depth_points(
     // g_d,n and h_n^T dtheta, slot-parallel over the point's observations
     double s = 0.0, g = 0.0;
     for (int o = o0 + slot; o < o1; o += DU_SLOTS) {
-        const double *r = rec + (size_t)o * REC_STRIDE;
+        const double2 *h2 = reinterpret_cast<const double2 *>(hc + 6 * (size_t)o);
         const double *dr = dth_rel + 6 * obs_pair[o];
-        g += (double)gr[(size_t)o * gs + GR_GD];
-        for (int k = 0; k < 6; ++k) s += (double)r[REC_h + k] * dr[k];
+        g += gd[(size_t)o * gds];
+        for (int k = 0; k < 3; ++k) {
+            const double2 hk = h2[k];
+            s += hk.x * dr[2 * k];
+            s += hk.y * dr[2 * k + 1];
+        }
     }
     sp[q][slot][0] = g;
     sp[q][slot][1] = s;

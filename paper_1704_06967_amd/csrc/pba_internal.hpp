@@ -198,12 +198,14 @@ struct Ctx {
     uint8_t *d_obs_live = nullptr;                     // [O] 1 while the observation is in the window (pba_drop_frame)
     void *d_rec = nullptr;                             // double [O][REC_STRIDE]
     void *d_icr = nullptr;                             // double [O][IC_REC] gradient records of the IC iterations
+    double *d_gdo = nullptr;                           // [O] their g_d field again, contiguous
     double *d_geo0 = nullptr, *d_geo_a = nullptr, *d_geo_b = nullptr;   // [Pn][GEO_STRIDE]
     void *d_rel0 = nullptr, *d_rel_a = nullptr, *d_rel_b = nullptr;      // T [Pn][REL_STRIDE]
     double *d_pairH = nullptr;                         // [Pn][21]
     double *d_pairY = nullptr;                         // [Pn][9] (6 + e, sq, cnt)
     double *d_partH = nullptr, *d_partY = nullptr;     // per pair chunk partials [nch][21], [nch][9]
     double *d_obsmap = nullptr;                        // [O][12] observation couplings for the Gram
+    double *d_hc = nullptr;                            // [O][6] h_o of the last system (relative coordinates)
     double *d_Hdd = nullptr, *d_gd = nullptr;          // [N] (Hdd damped after assembly)
     double *d_mu = nullptr;                            // [nwin][2] mu_p, mu_d
     double *d_gram = nullptr;                          // chunk partials

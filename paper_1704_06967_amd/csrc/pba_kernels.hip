@@ -183,6 +183,7 @@ struct ResArgs {
     double *rec;         // per-observation records (FP64 for every element type)
     const double *pcam;  // per pair: host and target level intrinsics (fx, fy, cx, cy) x 2
     double *icr;         // IC iterations: per observation g (6), g_d, energy, sum r^2, count (FP64)
+    double *gdo;         // IC iterations: g_d again, one value per observation (for the depth readers)
     const int *gate;     // device flag: 0 = the solve has converged, skip the work
 };
 
@@ -649,6 +650,7 @@ __global__ __launch_bounds__(NB) void k_ic_residual(ResArgs<T> a) {
         double *rec = a.icr + (size_t)o * IC_REC;
 #pragma unroll
         for (int k = 0; k < IC_REC; ++k) rec[k] = c[k];
+        a.gdo[o] = c[GR_GD];
     }
 }
 
@@ -748,6 +750,7 @@ __global__ __launch_bounds__(NB) void k_ic_residual8(ResArgs<T> a) {
             double *rec = a.icr + (size_t)o * IC_REC;
             rec[j] = v0;
             if (j < 2) rec[8 + j] = v1;
+            if (j == GR_GD) a.gdo[o] = v0;
         }
     }
 }
@@ -922,11 +925,12 @@ __global__ __launch_bounds__(PAIR_CHUNK) void k_pair_chunk_H(const int4 *__restr
 // Per chunk of one pair's observations (at most PAIR_CHUNK, one per thread):
 // reduced right-hand side contribution sum_o (g_o - h_o g_d,n / H_dd,n) (depth
 // elimination of the gradient) and the energy statistics. gr / gs: gradient
-// records (GR_* fields) and their stride; h_o from the full record; prange: the
-// observation range of each observation's point.
+// records (GR_* fields) and their stride; gd / gds: g_d of every observation
+// and its stride; hc: h_o, 6 values per observation.
 template <typename T>
-__global__ __launch_bounds__(PAIR_CHUNK) void k_pair_chunk_y(const int4 *__restrict__ slot, const double *__restrict__ rec,
+__global__ __launch_bounds__(PAIR_CHUNK) void k_pair_chunk_y(const int4 *__restrict__ slot, const double *__restrict__ hc,
                                                              const double *__restrict__ gr, int gs,
+                                                             const double *__restrict__ gd, int gds,
                                                              const double *__restrict__ Hdd,
                                                              double *__restrict__ partY, const int *__restrict__ gate,
                                                              const double *__restrict__ du_part, int du_nparts,
@@ -956,13 +960,17 @@ __global__ __launch_bounds__(PAIR_CHUNK) void k_pair_chunk_y(const int4 *__restr
     for (int k = 0; k < 9; ++k) v[k] = 0.0;
     if (live && sd.x >= 0) {
         const int o = sd.x, n = sd.y, q0 = sd.z, q1 = sd.w;
-        const double *r = rec + (size_t)o * REC_STRIDE;
+        const double2 *h2 = reinterpret_cast<const double2 *>(hc + 6 * (size_t)o);
         const double *g = gr + (size_t)o * gs;
         double gdn = 0.0;  // g_d,n: the point's records in order (bitwise the per-point sum)
 #pragma unroll 4
-        for (int q = q0; q < q1; ++q) gdn += (double)gr[(size_t)q * gs + GR_GD];
+        for (int q = q0; q < q1; ++q) gdn += gd[(size_t)q * gds];
         const double s = gdn / Hdd[n];
-        for (int k = 0; k < 6; ++k) v[k] += (double)g[GR_G + k] - (double)r[REC_h + k] * s;
+        for (int k = 0; k < 3; ++k) {
+            const double2 hk = h2[k];
+            v[2 * k] += (double)g[GR_G + 2 * k] - hk.x * s;
+            v[2 * k + 1] += (double)g[GR_G + 2 * k + 1] - hk.y * s;
+        }
         v[6] += (double)g[GR_E];
         v[7] += (double)g[GR_SQ];
         v[8] += (double)g[GR_CNT];
@@ -1020,8 +1028,8 @@ __global__ void k_sum_parts3(int np, const double *__restrict__ part, double *__
 template <typename T>
 __global__ __launch_bounds__(256) void k_depth_update(
     int N, int ic, const int *__restrict__ obs_ptr, const int *__restrict__ obs_pair,
-    const float *__restrict__ host_uv, const double *__restrict__ pairK0, const double *__restrict__ rec,
-    const double *__restrict__ gr, int gs, const double *__restrict__ Hdd, const double *__restrict__ dth_rel,
+    const float *__restrict__ host_uv, const double *__restrict__ pairK0, const double *__restrict__ hc,
+    const double *__restrict__ gd, int gds, const double *__restrict__ Hdd, const double *__restrict__ dth_rel,
     const double *__restrict__ geo_old, const double *__restrict__ geo_new, double *__restrict__ depth,
     const double *__restrict__ depth0, double *__restrict__ part, const int *__restrict__ gate,
     const int *__restrict__ flag, const uint8_t *__restrict__ live) {
@@ -1029,7 +1037,7 @@ __global__ __launch_bounds__(256) void k_depth_update(
     double md = 0.0, ms = 0.0;
     const int n0 = blockIdx.x * DU_PTS;
     const DepthPoint pt = depth_point<false>(N, n0, obs_ptr, host_uv, Hdd, depth, depth0);
-    if (!depth_points<T, 256>(N, n0, ic, pt, obs_pair, pairK0, rec, gr, gs, dth_rel, geo_old, geo_new, depth, gate,
+    if (!depth_points<T, 256>(N, n0, ic, pt, obs_pair, pairK0, hc, gd, gds, dth_rel, geo_old, geo_new, depth, gate,
                               flag, lds, md, ms, live))
         return;
     if (threadIdx.x == 0) {
@@ -1072,6 +1080,7 @@ static ResArgs<T> res_args(Ctx &c, int level, const double *geo_cur) {
     a.rec = (double *)c.d_rec;
     a.pcam = (const double *)c.lv[level].pcam;
     a.icr = (double *)c.d_icr;
+    a.gdo = c.d_gdo;
     a.gate = c.d_gate;
     return a;
 }
@@ -1090,6 +1099,18 @@ static void grad_records(const Ctx &c, const double *&gr, int &gs) {
     } else {
         gr = (const double *)c.d_rec + REC_G;
         gs = REC_STRIDE;
+    }
+}
+
+// g_d of every observation of the current iteration and its stride: the
+// contiguous copy the IC residual pass writes, or the full record's field (FC).
+static void grad_gd(const Ctx &c, const double *&gd, int &gds) {
+    if (c.cfg.mode == PBA_IC_PROXY) {
+        gd = c.d_gdo;
+        gds = 1;
+    } else {
+        gd = (const double *)c.d_rec + REC_GD;
+        gds = REC_STRIDE;
     }
 }
 
@@ -1283,7 +1304,10 @@ void Launch<T>::pair_reduce_y(hipStream_t s, Ctx &c, double *prev_stat, double c
     const double *gr;
     int gs;
     grad_records<T>(c, gr, gs);
-    k_pair_chunk_y<T><<<nch, PAIR_CHUNK, 0, s>>>((const int4 *)c.d_pc_slot, (const double *)c.d_rec, gr, gs, c.d_Hdd,
+    const double *gd;
+    int gds;
+    grad_gd(c, gd, gds);
+    k_pair_chunk_y<T><<<nch, PAIR_CHUNK, 0, s>>>((const int4 *)c.d_pc_slot, c.d_hc, gr, gs, gd, gds, c.d_Hdd,
                                                  c.d_partY, c.d_gate, prev_stat ? c.d_du_part : nullptr,
                                                  du_nparts(c), conv_args(c, prev_stat, conv_px, level));
     CHECK_LAUNCH();
@@ -1294,12 +1318,12 @@ template <typename T>
 void Launch<T>::depth_update(hipStream_t s, Ctx &c, const double *geo_old, const double *geo_new, double *stat,
                              double conv_px, int level, bool finish) {
     const int nb = (int)nblk(c.N, DU_PTS);
-    const double *gr;
-    int gs;
-    grad_records<T>(c, gr, gs);
+    const double *gd;
+    int gds;
+    grad_gd(c, gd, gds);
     if (c.N > 0)
         k_depth_update<T><<<nb, 256, 0, s>>>(c.N, c.cfg.mode == PBA_IC_PROXY ? 1 : 0, c.d_obs_ptr, c.d_obs_pair,
-                                             c.d_host_uv, c.d_pairK0, (const double *)c.d_rec, gr, gs, c.d_Hdd,
+                                             c.d_host_uv, c.d_pairK0, c.d_hc, gd, gds, c.d_Hdd,
                                              c.d_dth_rel, geo_old, geo_new, c.d_depth, c.d_depth0, c.d_du_part,
                                              c.d_gate, c.d_flag, c.d_obs_live);
     CHECK_LAUNCH();

@@ -123,17 +123,23 @@ __global__ void k_damp_hdd(int N, double *__restrict__ Hdd, const double *__rest
 
 // Coupling of every observation to its target and host poses in absolute
 // coordinates, scaled for the Schur Gram: (A^T h_o, B^T h_o) / sqrt(H_dd,n).
+// hc receives h_o itself, 6 contiguous values per observation, for the
+// system's readers of h alone (the rhs pair sums and the depth step), which
+// would otherwise take it out of the 40-value records.
 template <typename T>
 __global__ __launch_bounds__(256) void k_obs_map(int O, const int *__restrict__ obs_point,
                                                  const int *__restrict__ obs_pair, const T *__restrict__ rec,
                                                  const double *__restrict__ Hdd, const double *__restrict__ geo,
-                                                 double *__restrict__ map, const int *__restrict__ gate) {
+                                                 double *__restrict__ map, double *__restrict__ hc,
+                                                 const int *__restrict__ gate) {
     if (*gate == 0) return;
     const int o = blockIdx.x * blockDim.x + threadIdx.x;
     if (o >= O) return;
     const T *h = rec + (size_t)o * REC_STRIDE + REC_h;
     double hv[6], ua[6], ub[6];
     for (int a = 0; a < 6; ++a) hv[a] = (double)h[a];
+    double2 *hco = reinterpret_cast<double2 *>(hc + 6 * (size_t)o);
+    for (int a = 0; a < 3; ++a) hco[a] = make_double2(hv[2 * a], hv[2 * a + 1]);
     const double *g = geo + GEO_STRIDE * obs_pair[o];
     apply_At(g, hv, ua);
     apply_Bt(g, hv, ub);
@@ -1054,7 +1060,7 @@ __global__ __launch_bounds__(SOLVE_THREADS) void k_ic_step(
     double *__restrict__ dth_all, double *__restrict__ dth_rel, double *__restrict__ geo_next,
     T *__restrict__ rel_next, double *__restrict__ wstat, int *__restrict__ flag, int *__restrict__ gate, int N,
     const int *__restrict__ obs_ptr, const int *__restrict__ obs_pair, const float *__restrict__ host_uv,
-    const double *__restrict__ pairK0, const double *__restrict__ rec, const double *__restrict__ gr, int gs,
+    const double *__restrict__ pairK0, const double *__restrict__ hc, const double *__restrict__ gd, int gds,
     const double *__restrict__ Hdd, const double *__restrict__ geo_old, double *__restrict__ depth,
     const double *__restrict__ depth0, double *__restrict__ part, const int *__restrict__ step_sel, int sel_ncw,
     int nch, const uint8_t *__restrict__ live) {
@@ -1079,7 +1085,7 @@ __global__ __launch_bounds__(SOLVE_THREADS) void k_ic_step(
     const int P = one_P;
     const double *c_out = lds + LDS_DOUBLES - solve_out_doubles(P, true);
     double md = 0.0, ms = 0.0;
-    depth_points<T, SOLVE_THREADS>(N, b * IC_STEP_PTS, 1, pt, obs_pair, pairK0, rec, gr, gs, c_out + GEO_STRIDE * P,
+    depth_points<T, SOLVE_THREADS>(N, b * IC_STEP_PTS, 1, pt, obs_pair, pairK0, hc, gd, gds, c_out + GEO_STRIDE * P,
                                    geo_old, c_out, depth, nullptr, nullptr, lds, md, ms, live);
     if (threadIdx.x == 0) {
         part[2 * b] = md;
@@ -1124,10 +1130,10 @@ void launch_gram(hipStream_t s, Ctx &c, const double *geo, const void *rec, bool
     if (nch == 0 || c.O == 0) return;
     if (rec_double)
         k_obs_map<double><<<nb(c.O, 256), 256, 0, s>>>(c.O, c.d_obs_point, c.d_obs_pair, (const double *)rec,
-                                                       c.d_Hdd, geo, c.d_obsmap, c.d_gate);
+                                                       c.d_Hdd, geo, c.d_obsmap, c.d_hc, c.d_gate);
     else
         k_obs_map<float><<<nb(c.O, 256), 256, 0, s>>>(c.O, c.d_obs_point, c.d_obs_pair, (const float *)rec,
-                                                      c.d_Hdd, geo, c.d_obsmap, c.d_gate);
+                                                      c.d_Hdd, geo, c.d_obsmap, c.d_hc, c.d_gate);
     k_gram<<<nch, 256, 0, s>>>(c.d_chunk_host, c.d_chunk_begin, c.d_chunk_end, c.d_chunk_off, c.d_host_m,
                                c.d_host_pts, c.d_obs_ptr, c.d_obs_pair, c.d_pair_local, c.d_obsmap, c.d_gram,
                                c.d_gate);
@@ -1199,7 +1205,6 @@ int du_nparts(const Ctx &c) {
 template <typename T>
 static void ic_step_kernel(hipStream_t s, Ctx &c, const double *geo_lin, const double *geo_old, double *geo_next,
                            T *rel_next, hipEvent_t e0, hipEvent_t e1) {
-    const double *rec = (const double *)c.d_rec, *gr = (const double *)c.d_icr;
     // iteration k of a batch reads pose buffer k mod 2 and writes the other
     // (the convergence kernel at the batch's end copies back after odd counts)
     const bool odd = (c.batch_k & 1) != 0;
@@ -1216,7 +1221,7 @@ static void ic_step_kernel(hipStream_t s, Ctx &c, const double *geo_lin, const d
     launch(c.win(), c.win_frame_off[1], c.win_pair_off[1], c.cfg.pinned_frame, c.d_frame_pair_ptr, c.d_frame_pair_item,
         c.d_pair_host, c.d_pair_target, c.d_pair_chunk_ptr, c.d_partY, c.d_pairY, geo_lin, c.d_Sinv, p_in, p_out,
         c.d_poses0, c.d_b, c.d_dtheta, c.d_dth_rel, geo_next, rel_next, c.d_wstat, c.d_flag, c.d_gate, c.N,
-        c.d_obs_ptr, c.d_obs_pair, c.d_host_uv, c.d_pairK0, rec, gr, IC_REC, c.d_Hdd, geo_old, c.d_depth,
+        c.d_obs_ptr, c.d_obs_pair, c.d_host_uv, c.d_pairK0, c.d_hc, c.d_gdo, 1, c.d_Hdd, geo_old, c.d_depth,
         c.d_depth0, c.d_du_part, c.d_step_sel, step_sel_ncw(c), (int)c.st.pchunk_begin.size(), c.d_obs_live);
 }
 

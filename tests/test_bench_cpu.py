@@ -1,5 +1,5 @@
-"""Host-side contract of bench.py (no GPU): the one-GPU guard, and measured HBM
-traffic reported only for the kernel source the counters were taken on."""
+"""Host-side contract of bench.py (no GPU): the one-GPU guard, and measured L2-miss
+traffic reported only for the kernel sources the counters were taken on."""
 import hashlib
 import os
 import subprocess
@@ -16,12 +16,22 @@ def test_more_than_one_gpu_is_refused_before_any_device_work():
     assert r.stdout == ""   # no result line
 
 
-def test_measured_traffic_follows_the_kernel_source(monkeypatch):
+def test_measured_traffic_follows_the_kernel_sources(monkeypatch):
     import bench
-    src = os.path.join(ROOT, "paper_1704_06967_amd", "csrc", "pba_kernels.hip")
-    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
-    monkeypatch.setitem(bench.MEASURED_TRAFFIC, "kernels_sha256_16", sha)
-    assert bench.measured_traffic("mid") == bench.MEASURED_TRAFFIC["mid"]
-    assert bench.measured_traffic("precision") == bench.MEASURED_TRAFFIC["precision"]
-    monkeypatch.setitem(bench.MEASURED_TRAFFIC, "kernels_sha256_16", "0" * 16)
-    assert bench.measured_traffic("mid") is None
+    h = hashlib.sha256()
+    for f in ("pba_kernels.hip", "pba_solver.hip", "pba_depth.hpp", "pba_device.hpp", "pba_internal.hpp"):
+        h.update(open(os.path.join(ROOT, "paper_1704_06967_amd", "csrc", f), "rb").read())
+    monkeypatch.setitem(bench.MEASURED_TRAFFIC, "sources_sha256_16", h.hexdigest()[:16])
+    assert bench.measured_traffic("k_ic_residual", "mid") == bench.MEASURED_TRAFFIC["k_ic_residual"]["mid"]
+    assert bench.measured_traffic("k_ic_residual", "precision") == bench.MEASURED_TRAFFIC["k_ic_residual"]["precision"]
+    assert bench.measured_traffic("k_ic_step", "mid") == bench.MEASURED_TRAFFIC["k_ic_step"]["mid"]
+    assert bench.measured_traffic("k_ic_step", "precision") is None   # not measured
+    monkeypatch.setitem(bench.MEASURED_TRAFFIC, "sources_sha256_16", "0" * 16)
+    assert bench.measured_traffic("k_ic_residual", "mid") is None
+    assert bench.measured_traffic("k_ic_step", "mid") is None
+
+
+def test_measured_traffic_matches_the_committed_sources():
+    import bench
+    assert bench.measured_traffic("k_ic_step", "mid") is not None, \
+        "a kernel source changed after the traffic counters were taken: measure again"
