@@ -22,6 +22,9 @@ Photometric Bundle Adjustment" (arXiv 1704.06967):
   * gn.py         - the FC and IC-proxy Gauss-Newton loops (Sec. 3.5 steps
                     1-4) over a coarse-to-fine pyramid, convergence test
                     (Sec. 4.1).
+  * frontend.py   - the base solution's first steps (Sec. 4.1): Harris
+                    corners, robust KLT tracking, geometric bundle adjustment
+                    with outlier removal.
 Readings of passages where the paper is silent or garbled are listed in the
 docstrings where they are applied.
 """
