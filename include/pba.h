@@ -281,6 +281,85 @@ pba_status pba_set_params(pba_ctx *ctx, int32_t window, const double *poses, con
  * system is not positive definite). */
 pba_status pba_drop_frame(pba_ctx *ctx, int32_t window, int32_t frame);
 
+/* ---- Front end for p(0): the first three steps of the base solution of
+ * Sec. 4.1 (Harris corners, robust KLT tracking, geometric bundle adjustment
+ * with outlier removal). Its fourth step, the forward-compositional
+ * photometric bundle adjustment, is pba_solve on a PBA_FC context. The paper
+ * names the methods and gives no parameters; the readings are stated per
+ * call. All arrays of these calls are host memory, owned by the caller. */
+
+#define PBA_FE_MAX_CELLS 8192   /* corner cells per image that one call takes */
+#define PBA_FE_MAX_RADIUS 5     /* tracking window of at most 11 x 11 pixels */
+
+/* Harris corners of level 0 of frame `frame` of window `window` (after
+ * pba_set_frames). The image is quantized to 8 bits (rint(I * 255) in single
+ * precision, clamped to 0..255); gx, gy are the central differences times
+ * two; Sxx, Syy, Sxy their products summed over a 5 x 5 box; the response
+ * R = 16 (Sxx Syy - Sxy^2) - (Sxx + Syy)^2 (kappa = 1/16, scaled by 16) is an
+ * exact integer. A candidate lies at least max(margin, 4) pixels inside the
+ * image, has R > min_response and is a 3 x 3 maximum (strictly above the
+ * neighbours before it in raster order, not below those after it). Each cell
+ * of cell x cell pixels (2..16) keeps its best candidate (largest R, then
+ * first in raster order), and the max_corners best cells come back, best
+ * first: uv [max_corners][2] (column, row), response [max_corners] (may be
+ * NULL), *n_out their number. The image may hold at most PBA_FE_MAX_CELLS
+ * cells. Synchronous. Errors: PBA_E_INVALID (ranges, NULL outputs),
+ * PBA_E_STATE (no frames), PBA_E_DEVICE / PBA_E_OOM. */
+pba_status pba_fe_corners(pba_ctx *ctx, int32_t window, int32_t frame, int32_t cell, int32_t margin,
+                          int64_t min_response, int32_t max_corners, int32_t *uv, int64_t *response,
+                          int32_t *n_out);
+
+/* Track status codes of pba_fe_track. */
+#define PBA_TRACK_OK 0
+#define PBA_TRACK_LOW_TEXTURE 1   /* smaller eigenvalue of H / window pixels below min_eig */
+#define PBA_TRACK_LEFT_IMAGE 2    /* a window left the usable area u in [1, W-3], v in [1, H-3] */
+#define PBA_TRACK_FB 3            /* tracked back, it missed the start by more than fb_px */
+
+/* Robust tracks of n points: the window of (2 radius + 1)^2 pixels around
+ * host_uv[i] (level-0 pixels) in frame host_frame[i] into frame
+ * target_frame[i] of window `window`, from the predicted level-0 position
+ * guess_uv[i]. Translational Lucas-Kanade in inverse-compositional form over
+ * the context's pyramid, coarsest level first (the displacement doubles from
+ * one level to the next): per level the window's bilinear intensities T and
+ * gradients G in the host (central differences, bilinearly interpolated),
+ * H = sum G G^T, then n_iters updates d <- d - H^{-1} sum G (I_target(x + d) - T).
+ * The position found is tracked back into the host the same way; the track is
+ * kept if that returns within fb_px. FP64 arithmetic on the context's images.
+ * Outputs: uv_out [n][2] (level-0 position in the target), status_out [n]
+ * (PBA_TRACK_*), fb_out [n] (forward-backward distance; may be NULL).
+ * radius 1..PBA_FE_MAX_RADIUS, n_iters 1..100. Synchronous. Errors:
+ * PBA_E_INVALID (ranges, non-finite positions, NULL arrays), PBA_E_STATE,
+ * PBA_E_DEVICE / PBA_E_OOM. */
+pba_status pba_fe_track(pba_ctx *ctx, int32_t window, int32_t n, const int32_t *host_frame, const double *host_uv,
+                        const int32_t *target_frame, const double *guess_uv, int32_t radius, int32_t n_iters,
+                        double min_eig, double fb_px, double *uv_out, int32_t *status_out, double *fb_out);
+
+/* The tracked level-0 position of every observation of pba_set_points
+ * (obs_uv [n_obs][2], the CSR order of that call), for pba_geo_solve.
+ * One-window contexts only (window 0). Errors: PBA_E_INVALID (window, n_obs
+ * not the observation count, non-finite), PBA_E_STATE (no points). */
+pba_status pba_set_tracks(pba_ctx *ctx, int32_t window, int32_t n_obs, const double *obs_uv);
+
+/* Geometric bundle adjustment of the poses and inverse depths from the
+ * current parameters: one 2-D residual e = pi_f(R x~ + d t) - z per
+ * observation (level-0 pixels; the relative pose and inverse depth of
+ * eq:warp; z its pba_set_tracks position), the Huber weight of |e| with
+ * threshold huber_px on both rows, and otherwise the FC iteration: its
+ * normal equations, gauge pin, damping, depth Schur complement, Cholesky,
+ * update and convergence test (largest point-centre displacement below
+ * conv_px, at most max_iters iterations). With outlier_px > 0 the
+ * observations whose |e| exceeds it (or whose point lies behind the camera)
+ * are then removed and the solve runs again. The context keeps the result
+ * as its parameters. out->iters[0] / [1]: iterations of the two passes;
+ * final_energy / final_rmse / final_active: Huber energy, RMS reprojection
+ * error (pixels) and count of the inliers at the end; inliers [n_obs] (may
+ * be NULL): 1 for the observations kept. Synchronous. Errors: PBA_E_STATE
+ * (no tracks), PBA_E_INVALID, PBA_E_NUMERIC (reduced system not positive
+ * definite), PBA_E_NOT_CONVERGED (the last pass hit max_iters; parameters
+ * and outputs are still written). */
+pba_status pba_geo_solve(pba_ctx *ctx, int32_t max_iters, double conv_px, double huber_px, double outlier_px,
+                         uint8_t *inliers, pba_result *out);
+
 /* Result of pba_autotune: the launch shapes tried for the per-iteration
  * residual kernel (IC: the residual / J^T W r kernel; FC: the linearization
  * kernel) and their measured mean launch time. */

@@ -130,6 +130,8 @@ void release_points(Ctx &c) {
     dfree(c.d_rel_b);
     dfree(c.d_icr);
     dfree(c.d_gdo);
+    dfree(c.d_obs_z);
+    dfree(c.d_geo_in);
     for (int l = 0; l < PBA_MAX_LEVELS; ++l) {
         dfree(c.lv[l].tmpl);
         dfree(c.lv[l].pcam);
@@ -395,12 +397,14 @@ pba_status one_iteration(Ctx &c, int level, double *stat, hipEvent_t ev0, hipEve
         else
             launch_solve(s, c, c.d_geo0, geo_next, rel_next, is_fp64(c), stat);
     } else {
-        if (is_mixed(c))
+        if (c.geo_mode)
+            launch_geo_linearize(s, c, geo_cur, ev0, ev1);   // reprojection error (front end)
+        else if (is_mixed(c))
             launch_linearize_mixed(s, c, level, false, geo_cur, c.iters_in_level == 0, ev0, ev1);
         else
             Launch<T>::fc_linearize(s, c, level, geo_cur, c.iters_in_level == 0, ev0, ev1);
         Launch<T>::point_reduce(s, c, true);
-        if (!is_mixed(c)) Launch<T>::pair_reduce_H(s, c);
+        if (c.geo_mode || !is_mixed(c)) Launch<T>::pair_reduce_H(s, c);
         launch_mu(s, c, geo_cur);
         launch_gram(s, c, geo_cur, c.d_rec, true);
         launch_assemble_s(s, c, geo_cur);
@@ -1479,6 +1483,219 @@ pba_status pba_drop_frame(pba_ctx *ctx, int32_t window, int32_t frame) {
         c.cur_level = -1;
         return fail(&c, PBA_E_NUMERIC, "reduced pose system is not positive definite");
     }
+    return PBA_OK;
+}
+
+// ---- front end (Sec. 4.1 base solution: corners, tracks, geometric BA)
+
+pba_status pba_fe_corners(pba_ctx *ctx, int32_t window, int32_t frame, int32_t cell, int32_t margin,
+                          int64_t min_response, int32_t max_corners, int32_t *uv, int64_t *response,
+                          int32_t *n_out) {
+    if (!ctx) return fail(nullptr, PBA_E_INVALID, "ctx is NULL");
+    Ctx &c = ctx->c;
+    if (!uv || !n_out) return fail(&c, PBA_E_INVALID, "uv and n_out must not be NULL");
+    if (!c.have_frames) return fail(&c, PBA_E_STATE, "pba_set_frames must be called first");
+    if (window < 0 || window >= c.nwin) return fail(&c, PBA_E_INVALID, "window must be in 0..n_windows-1");
+    const int f0 = c.win_frame_off[window], nf = c.win_frame_off[window + 1] - f0;
+    if (frame < 0 || frame >= nf) return fail(&c, PBA_E_INVALID, "frame out of range for the window");
+    if (cell < 2 || cell > 16) return fail(&c, PBA_E_INVALID, "cell must be in 2..16");
+    if (margin < 0) return fail(&c, PBA_E_INVALID, "margin must be >= 0");
+    if (max_corners < 0) return fail(&c, PBA_E_INVALID, "max_corners must be >= 0");
+    const int W = c.lv[0].W, H = c.lv[0].H;
+    const long long ncells = (long long)((W + cell - 1) / cell) * ((H + cell - 1) / cell);
+    if (ncells > PBA_FE_MAX_CELLS) return fail(&c, PBA_E_INVALID, "more than PBA_FE_MAX_CELLS cells: use larger cells");
+    *n_out = 0;
+    if (max_corners == 0) return PBA_OK;
+    long long *R = nullptr, *cell_R = nullptr, *resp = nullptr;
+    int *cell_idx = nullptr, *duv = nullptr, *count = nullptr;
+    hipError_t e = hipSuccess;
+    if ((e = dalloc(R, (size_t)W * H * sizeof(long long))) == hipSuccess &&
+        (e = dalloc(cell_R, (size_t)ncells * sizeof(long long))) == hipSuccess &&
+        (e = dalloc(cell_idx, (size_t)ncells * sizeof(int))) == hipSuccess &&
+        (e = dalloc(duv, (size_t)max_corners * 2 * sizeof(int))) == hipSuccess &&
+        (e = dalloc(resp, (size_t)max_corners * sizeof(long long))) == hipSuccess &&
+        (e = dalloc(count, sizeof(int))) == hipSuccess) {
+        launch_fe_corners(c.stream, c, f0 + frame, cell, margin, min_response, max_corners, R, cell_R, cell_idx,
+                          duv, resp, count);
+        int n = 0;
+        if ((e = hipMemcpyAsync(&n, count, sizeof(int), hipMemcpyDeviceToHost, c.stream)) == hipSuccess &&
+            (e = hipStreamSynchronize(c.stream)) == hipSuccess && n > 0) {
+            if ((e = hipMemcpyAsync(uv, duv, (size_t)n * 2 * sizeof(int), hipMemcpyDeviceToHost, c.stream)) ==
+                    hipSuccess &&
+                response)
+                e = hipMemcpyAsync(response, resp, (size_t)n * sizeof(long long), hipMemcpyDeviceToHost, c.stream);
+            if (e == hipSuccess) e = hipStreamSynchronize(c.stream);
+        }
+        if (e == hipSuccess) e = hipGetLastError();
+        if (e == hipSuccess) *n_out = n;
+    }
+    for (long long **p : {&R, &cell_R, &resp}) dfree(*p);
+    for (int **p : {&cell_idx, &duv, &count}) dfree(*p);
+    if (e != hipSuccess) return fail(&c, PBA_E_DEVICE, std::string("HIP error: ") + hipGetErrorString(e));
+    return PBA_OK;
+}
+
+pba_status pba_fe_track(pba_ctx *ctx, int32_t window, int32_t n, const int32_t *host_frame, const double *host_uv,
+                        const int32_t *target_frame, const double *guess_uv, int32_t radius, int32_t n_iters,
+                        double min_eig, double fb_px, double *uv_out, int32_t *status_out, double *fb_out) {
+    if (!ctx) return fail(nullptr, PBA_E_INVALID, "ctx is NULL");
+    Ctx &c = ctx->c;
+    if (!c.have_frames) return fail(&c, PBA_E_STATE, "pba_set_frames must be called first");
+    if (window < 0 || window >= c.nwin) return fail(&c, PBA_E_INVALID, "window must be in 0..n_windows-1");
+    if (n < 0) return fail(&c, PBA_E_INVALID, "n must be >= 0");
+    if (n == 0) return PBA_OK;
+    if (!host_frame || !host_uv || !target_frame || !guess_uv || !uv_out || !status_out)
+        return fail(&c, PBA_E_INVALID, "input and output arrays must not be NULL");
+    if (radius < 1 || radius > PBA_FE_MAX_RADIUS) return fail(&c, PBA_E_INVALID, "radius must be in 1..PBA_FE_MAX_RADIUS");
+    if (n_iters < 1 || n_iters > 100) return fail(&c, PBA_E_INVALID, "n_iters must be in 1..100");
+    if (!(min_eig >= 0.0) || !(fb_px >= 0.0)) return fail(&c, PBA_E_INVALID, "min_eig and fb_px must be >= 0");
+    const int f0 = c.win_frame_off[window], nf = c.win_frame_off[window + 1] - f0;
+    std::vector<int> hf(n), tf(n);
+    for (int i = 0; i < n; ++i) {
+        if (host_frame[i] < 0 || host_frame[i] >= nf || target_frame[i] < 0 || target_frame[i] >= nf)
+            return fail(&c, PBA_E_INVALID, "frame index out of range for the window");
+        hf[i] = f0 + host_frame[i];
+        tf[i] = f0 + target_frame[i];
+    }
+    if (!finite_all(host_uv, 2 * (size_t)n) || !finite_all(guess_uv, 2 * (size_t)n))
+        return fail(&c, PBA_E_INVALID, "positions must be finite");
+    int *dh = nullptr, *dt = nullptr, *dst = nullptr;
+    double *dxu = nullptr, *dg = nullptr, *dout = nullptr, *dfb = nullptr;
+    hipError_t e = hipSuccess;
+    std::vector<double> fb(n);
+    if ((e = dalloc(dh, (size_t)n * sizeof(int))) == hipSuccess && (e = dalloc(dt, (size_t)n * sizeof(int))) == hipSuccess &&
+        (e = dalloc(dst, (size_t)n * sizeof(int))) == hipSuccess &&
+        (e = dalloc(dxu, (size_t)n * 2 * sizeof(double))) == hipSuccess &&
+        (e = dalloc(dg, (size_t)n * 2 * sizeof(double))) == hipSuccess &&
+        (e = dalloc(dout, (size_t)n * 2 * sizeof(double))) == hipSuccess &&
+        (e = dalloc(dfb, (size_t)n * sizeof(double))) == hipSuccess &&
+        (e = hipMemcpyAsync(dh, hf.data(), (size_t)n * sizeof(int), hipMemcpyHostToDevice, c.stream)) == hipSuccess &&
+        (e = hipMemcpyAsync(dt, tf.data(), (size_t)n * sizeof(int), hipMemcpyHostToDevice, c.stream)) == hipSuccess &&
+        (e = hipMemcpyAsync(dxu, host_uv, (size_t)n * 2 * sizeof(double), hipMemcpyHostToDevice, c.stream)) ==
+            hipSuccess &&
+        (e = hipMemcpyAsync(dg, guess_uv, (size_t)n * 2 * sizeof(double), hipMemcpyHostToDevice, c.stream)) ==
+            hipSuccess) {
+        launch_fe_track(c.stream, c, n, dh, dxu, dt, dg, radius, n_iters, min_eig, fb_px, c.cfg.n_levels, dout, dst,
+                        dfb);
+        if ((e = hipGetLastError()) == hipSuccess &&
+            (e = hipMemcpyAsync(uv_out, dout, (size_t)n * 2 * sizeof(double), hipMemcpyDeviceToHost, c.stream)) ==
+                hipSuccess &&
+            (e = hipMemcpyAsync(status_out, dst, (size_t)n * sizeof(int), hipMemcpyDeviceToHost, c.stream)) ==
+                hipSuccess &&
+            (e = hipMemcpyAsync(fb.data(), dfb, (size_t)n * sizeof(double), hipMemcpyDeviceToHost, c.stream)) ==
+                hipSuccess)
+            e = hipStreamSynchronize(c.stream);
+    }
+    for (int **p : {&dh, &dt, &dst}) dfree(*p);
+    for (double **p : {&dxu, &dg, &dout, &dfb}) dfree(*p);
+    if (e != hipSuccess) return fail(&c, PBA_E_DEVICE, std::string("HIP error: ") + hipGetErrorString(e));
+    if (fb_out) std::memcpy(fb_out, fb.data(), (size_t)n * sizeof(double));
+    return PBA_OK;
+}
+
+pba_status pba_set_tracks(pba_ctx *ctx, int32_t window, int32_t n_obs, const double *obs_uv) {
+    if (!ctx) return fail(nullptr, PBA_E_INVALID, "ctx is NULL");
+    Ctx &c = ctx->c;
+    pba_status st;
+    if ((st = ready(ctx)) != PBA_OK) return st;
+    if (c.nwin != 1 || window != 0) return fail(&c, PBA_E_INVALID, "tracks are taken by one-window contexts (window 0)");
+    if (n_obs != c.O) return fail(&c, PBA_E_INVALID, "n_obs must equal the observations of pba_set_points");
+    if (n_obs > 0 && !obs_uv) return fail(&c, PBA_E_INVALID, "obs_uv is NULL");
+    if (!finite_all(obs_uv, 2 * (size_t)n_obs)) return fail(&c, PBA_E_INVALID, "obs_uv must be finite");
+    std::vector<double> z(2 * (size_t)c.O);
+    for (int o = 0; o < c.O; ++o) {
+        const int oc = c.obs_caller[o];
+        z[2 * (size_t)o] = obs_uv[2 * (size_t)oc];
+        z[2 * (size_t)o + 1] = obs_uv[2 * (size_t)oc + 1];
+    }
+    HIPCHK(upload(c, c.d_obs_z, z));
+    dfree(c.d_geo_in);
+    HIPCHK(dalloc(c.d_geo_in, std::max<size_t>(1, c.O)));
+    HIPCHK(hipStreamSynchronize(c.stream));
+    return PBA_OK;
+}
+
+pba_status pba_geo_solve(pba_ctx *ctx, int32_t max_iters, double conv_px, double huber_px, double outlier_px,
+                         uint8_t *inliers, pba_result *out) {
+    if (!ctx) return fail(nullptr, PBA_E_INVALID, "ctx is NULL");
+    Ctx &c = ctx->c;
+    pba_status st;
+    if ((st = ready(ctx)) != PBA_OK) return st;
+    if (!c.d_obs_z && c.O > 0) return fail(&c, PBA_E_STATE, "pba_set_tracks must be called first");
+    if (max_iters < 1) return fail(&c, PBA_E_INVALID, "max_iters must be >= 1");
+    if (!(conv_px >= 0.0) || !(huber_px > 0.0)) return fail(&c, PBA_E_INVALID, "conv_px >= 0 and huber_px > 0 required");
+    if (!(outlier_px > 0.0) && outlier_px != 0.0) return fail(&c, PBA_E_INVALID, "outlier_px must be >= 0");
+    pba_result res;
+    std::memset(&res, 0, sizeof(res));
+    std::vector<pba_iter_stats> stats((size_t)max_iters);
+    // the FC iteration on the reprojection error at level 0; the context's own
+    // mode comes back on every return, and its next photometric call starts a
+    // level afresh
+    struct ModeGuard {
+        Ctx &c;
+        int mode;
+        ~ModeGuard() {
+            c.cfg.mode = mode;
+            c.geo_mode = false;
+            c.cur_level = -1;
+            c.s_valid = false;
+        }
+    } guard{c, c.cfg.mode};
+    c.cfg.mode = PBA_FC;
+    c.geo_mode = true;
+    c.geo_huber = huber_px;
+    c.cur_level = -1;
+    if (c.O > 0) HIPCHK(hipMemsetAsync(c.d_geo_in, 1, (size_t)c.O, c.stream));
+    // relative geometry of every pair at the current poses, into the buffer the
+    // next iteration reads
+    auto current_geo = [&c]() {
+        double *geo = c.flip ? c.d_geo_b : c.d_geo_a;
+        if (is_fp64(c))
+            Launch<double>::relpose(c.stream, c, c.d_poses, geo, (double *)(c.flip ? c.d_rel_b : c.d_rel_a));
+        else
+            Launch<float>::relpose(c.stream, c, c.d_poses, geo, (float *)(c.flip ? c.d_rel_b : c.d_rel_a));
+        return geo;
+    };
+    const int passes = outlier_px > 0.0 ? 2 : 1;
+    for (int pass = 0; pass < passes && st == PBA_OK; ++pass) {
+        if (pass == 1) launch_geo_outliers(c.stream, c, current_geo(), outlier_px);
+        st = do_start_level(c, 0);
+        int ran = 0;
+        if (st == PBA_OK) st = run_iterations(c, 0, max_iters, stats.data(), conv_px, &ran);
+        if (st == PBA_OK) {
+            res.iters[pass] = ran;
+            res.total_iters += ran;
+            res.converged = ran > 0 && stats[(size_t)ran - 1].max_disp_px < conv_px;
+        }
+    }
+    if (st == PBA_OK) {
+        // energy and RMS reprojection error over the inliers at the final parameters
+        launch_open(c.stream, c, 0, true);
+        launch_geo_linearize(c.stream, c, current_geo());
+        if (c.eval_cap < sum_stats_doubles(c)) {
+            dfree(c.d_eval);
+            HIPCHK(dalloc(c.d_eval, sum_stats_doubles(c) * sizeof(double)));
+            c.eval_cap = sum_stats_doubles(c);
+        }
+        double h[3] = {0.0, 0.0, 0.0};
+        if (c.O > 0) {
+            launch_sum_stats(c.stream, c, c.d_rec, true, c.d_eval);
+            HIPCHK(hipMemcpyAsync(h, c.d_eval, sizeof(h), hipMemcpyDeviceToHost, c.stream));
+        }
+        std::vector<uint8_t> in((size_t)c.O);
+        if (inliers && c.O > 0)
+            HIPCHK(hipMemcpyAsync(in.data(), c.d_geo_in, (size_t)c.O, hipMemcpyDeviceToHost, c.stream));
+        HIPCHK(hipStreamSynchronize(c.stream));
+        HIPCHK(hipGetLastError());
+        res.final_energy = h[0];
+        res.final_active = (int64_t)std::llround(h[2]);
+        res.final_rmse = res.final_active > 0 ? std::sqrt(h[1] / (double)res.final_active) : 0.0;
+        if (inliers)
+            for (int o = 0; o < c.O; ++o) inliers[c.obs_caller[o]] = in[(size_t)o];
+    }
+    if (st != PBA_OK) return st;
+    if (out) *out = res;
+    if (!res.converged) return fail(&c, PBA_E_NOT_CONVERGED, "the geometric solve did not reach conv_px");
     return PBA_OK;
 }
 

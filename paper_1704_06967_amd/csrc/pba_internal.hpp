@@ -226,6 +226,12 @@ struct Ctx {
     double *d_pairK0 = nullptr;                        // [Pn][8] level-0 intrinsics of host and target
     int *d_pc_slot = nullptr;  // [pair chunks][PAIR_CHUNK][4] observation (-1: none), point, point's range
 
+    // front end: geometric bundle adjustment on tracked positions
+    double *d_obs_z = nullptr;     // [O][2] tracked level-0 position of every observation
+    uint8_t *d_geo_in = nullptr;   // [O] 1 while the observation is a geometric inlier
+    bool geo_mode = false;         // the FC iteration linearizes the reprojection error
+    double geo_huber = 1.0;        // its Huber threshold (level-0 pixels)
+
     // current double-buffer orientation
     bool flip = false;
 
@@ -330,5 +336,16 @@ void launch_tinv(hipStream_t s, Ctx &c);    // S^{-1} from the tiled factor
 pba_status fail_global(pba_status s, const std::string &msg);
 void launch_copy_d(hipStream_t s, const double *src, double *dst, size_t n);  // device copy as a kernel
 void launch_fill(hipStream_t s, double *p, size_t n, double v, const int *gate);
+
+// front end (pba_frontend.hip): corners of one frame (R: [H][W] response scratch,
+// cell_R / cell_idx: per-cell scratch), tracks, geometric BA records and outliers
+void launch_fe_corners(hipStream_t s, Ctx &c, int frame, int cell, int margin, long long min_resp, int K,
+                       long long *R, long long *cell_R, int *cell_idx, int *uv, long long *resp, int *count);
+void launch_fe_track(hipStream_t s, Ctx &c, int n, const int *host, const double *host_uv, const int *target,
+                     const double *guess, int radius, int n_iters, double min_eig, double fb_px, int levels,
+                     double *out_uv, int *out_status, double *out_fb);
+void launch_geo_linearize(hipStream_t s, Ctx &c, const double *geo_cur, hipEvent_t e0 = nullptr,
+                          hipEvent_t e1 = nullptr);
+void launch_geo_outliers(hipStream_t s, Ctx &c, const double *geo_cur, double limit);
 
 }  // namespace pba

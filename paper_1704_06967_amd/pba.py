@@ -23,6 +23,8 @@ PBA_FLAG_TIMING, PBA_FLAG_GRAPH, PBA_FLAG_LANE_PER_PIXEL = 1, 2, 4
 PBA_MAX_PATTERN = 8
 PBA_MAX_LEVELS = 4
 PBA_MAX_WINDOWS = 4096
+PBA_FE_MAX_CELLS, PBA_FE_MAX_RADIUS = 8192, 5
+PBA_TRACK_OK, PBA_TRACK_LOW_TEXTURE, PBA_TRACK_LEFT_IMAGE, PBA_TRACK_FB = 0, 1, 2, 3
 PBA_DBG_S, PBA_DBG_B, PBA_DBG_OBS_REC, PBA_DBG_TEMPLATE, PBA_DBG_HDD, PBA_DBG_MASK, PBA_DBG_DTHETA = 1, 2, 3, 4, 5, 6, 7
 PBA_DBG_PAIR_H, PBA_DBG_PAIRS = 8, 9
 REC_STRIDE = 40
@@ -127,6 +129,12 @@ _sig = {
     "pba_get_params": (C.c_int, [_P, C.c_int32, _P, _P]),
     "pba_set_params": (C.c_int, [_P, C.c_int32, _P, _P]),
     "pba_drop_frame": (C.c_int, [_P, C.c_int32, C.c_int32]),
+    "pba_fe_corners": (C.c_int, [_P, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_int64, C.c_int32, _P, _P,
+                                 C.POINTER(C.c_int32)]),
+    "pba_fe_track": (C.c_int, [_P, C.c_int32, C.c_int32, _P, _P, _P, _P, C.c_int32, C.c_int32, C.c_double,
+                               C.c_double, _P, _P, _P]),
+    "pba_set_tracks": (C.c_int, [_P, C.c_int32, C.c_int32, _P]),
+    "pba_geo_solve": (C.c_int, [_P, C.c_int32, C.c_double, C.c_double, C.c_double, _P, C.POINTER(pba_result)]),
     "pba_debug_fetch": (C.c_int, [_P, C.c_int32, _P, C.c_size_t]),
     "pba_get_timing": (C.c_int, [_P, C.POINTER(pba_timing)]),
     "pba_autotune": (C.c_int, [_P, C.c_int32, C.c_int32, C.POINTER(pba_tune_report)]),
@@ -277,6 +285,45 @@ class Solver:
 
     def drop_frame(self, frame, window=0):
         self._chk(pba_drop_frame(self.ctx, window, frame))
+
+    # ---- front end (corners, tracks, geometric bundle adjustment)
+
+    def corners(self, frame, cell=8, margin=8, min_response=0, max_corners=2000, window=0):
+        """(uv [K, 2] int32 as (column, row), response [K] int64), best first."""
+        uv = np.zeros((max(1, max_corners), 2), np.int32)
+        resp = np.zeros(max(1, max_corners), np.int64)
+        n = C.c_int32()
+        self._chk(pba_fe_corners(self.ctx, window, frame, cell, margin, int(min_response), max_corners, _ptr(uv),
+                                 _ptr(resp), C.byref(n)))
+        return uv[: n.value].copy(), resp[: n.value].copy()
+
+    def track(self, host_frame, host_uv, target_frame, guess_uv, radius=4, n_iters=10, min_eig=1e-6, fb_px=0.5,
+              window=0):
+        """(positions [T, 2], status [T], forward-backward distance [T])."""
+        hf = np.ascontiguousarray(host_frame, np.int32).reshape(-1)
+        tf = np.ascontiguousarray(target_frame, np.int32).reshape(-1)
+        xu = np.ascontiguousarray(host_uv, np.float64).reshape(-1, 2)
+        gu = np.ascontiguousarray(guess_uv, np.float64).reshape(-1, 2)
+        n = hf.shape[0]
+        out = np.zeros((n, 2))
+        st = np.zeros(n, np.int32)
+        fb = np.zeros(n)
+        self._chk(pba_fe_track(self.ctx, window, n, _ptr(hf), _ptr(xu), _ptr(tf), _ptr(gu), radius, n_iters,
+                               min_eig, fb_px, _ptr(out), _ptr(st), _ptr(fb)))
+        return out, st, fb
+
+    def set_tracks(self, obs_uv, window=0):
+        z = np.ascontiguousarray(obs_uv, np.float64).reshape(-1, 2)
+        self._chk(pba_set_tracks(self.ctx, window, z.shape[0], _ptr(z)))
+
+    def geo_solve(self, max_iters, conv_px=5e-3, huber_px=2.0, outlier_px=0.0):
+        """(pba_result, status, inliers [O] uint8); PBA_E_NOT_CONVERGED is returned, not raised."""
+        res = pba_result()
+        inl = np.zeros(max(1, self.O), np.uint8)
+        s = pba_geo_solve(self.ctx, max_iters, conv_px, huber_px, outlier_px, _ptr(inl), C.byref(res))
+        if s not in (PBA_OK, PBA_E_NOT_CONVERGED):
+            self._chk(s)
+        return res, s, inl[: self.O].copy()
 
     def fetch(self, what):
         n6 = 6 * self.F

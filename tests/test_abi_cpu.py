@@ -131,6 +131,8 @@ def test_create_accepts_documented_limits(field, value):
     if os.path.exists("/dev/kfd"):
         pytest.skip("a GPU is present")
     assert header_define("PBA_MAX_WINDOWS") == pba.PBA_MAX_WINDOWS
+    assert header_define("PBA_FE_MAX_CELLS") == pba.PBA_FE_MAX_CELLS
+    assert header_define("PBA_FE_MAX_RADIUS") == pba.PBA_FE_MAX_RADIUS
     cfg = pba.default_config()
     setattr(cfg, field, pba.PBA_MAX_WINDOWS if value is None else value)
     h = C.c_void_p()
