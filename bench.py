@@ -55,6 +55,67 @@ def measured_traffic(kernel, workload):
     return MEASURED_TRAFFIC[kernel].get(workload)
 
 
+METRIC = "GN iters/s & residuals/s, IC-proxy vs FC on same GPU at equal final photo-RMSE"
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def level_pixels(scene, level):
+    """Level-`level` target pixels of every residual at the scene's starting
+    parameters (host patch pixel -> warp -> projection), for byte counting."""
+    P = scene.pattern.shape[0]
+    N = scene.n_points
+    obs_point = np.repeat(np.arange(N), np.diff(scene.obs_ptr))
+    host = scene.host_frame[obs_point]
+    tgt = scene.obs_frame
+    s = 2.0 ** level
+    K = scene.intrinsics
+    uv = (scene.host_uv[obs_point].astype(float) + 0.5) / s - 0.5
+    pu = uv[:, None, 0] + scene.pattern[None, :, 0]
+    pv = uv[:, None, 1] + scene.pattern[None, :, 1]
+    Kh, Kt = K[host] / np.array([s, s, 1, 1]), K[tgt] / np.array([s, s, 1, 1])
+    Kh[:, 2:] = (K[host, 2:] + 0.5) / s - 0.5
+    Kt[:, 2:] = (K[tgt, 2:] + 0.5) / s - 0.5
+    x = (pu - Kh[:, None, 2]) / Kh[:, None, 0]
+    y = (pv - Kh[:, None, 3]) / Kh[:, None, 1]
+    Rp = scene.poses_init[:, :9].reshape(-1, 3, 3)
+    tp = scene.poses_init[:, 9:]
+    R = Rp[tgt] @ np.swapaxes(Rp[host], 1, 2)
+    t = tp[tgt] - np.einsum("oij,oj->oi", R, tp[host])
+    d = scene.inv_depth_init[obs_point]
+    v = (R[:, None, :, 0] * x[..., None] + R[:, None, :, 1] * y[..., None] + R[:, None, :, 2]
+         + d[:, None, None] * t[:, None, :])
+    qu = Kt[:, None, 0] * v[..., 0] / v[..., 2] + Kt[:, None, 2]
+    qv = Kt[:, None, 1] * v[..., 1] / v[..., 2] + Kt[:, None, 3]
+    return tgt, qu, qv
+
+
+def _pairs(scene):
+    """(host, target) pair of every observation and the number of distinct pairs."""
+    host = scene.host_frame[np.repeat(np.arange(scene.n_points), np.diff(scene.obs_ptr))]
+    key = host.astype(np.int64) * scene.n_frames + scene.obs_frame
+    uniq, counts = np.unique(key, return_counts=True)
+    return uniq.size, counts
+
+
+def _unique_texels(scene, level, halo):
+    """Distinct target texels of the bilinear footprints at the starting
+    parameters: 2 x 2 (halo 0) or the 4 x 4 of the interpolated central
+    differences (halo 1)."""
+    F, H, W = scene.images.shape
+    Wl, Hl = W >> level, H >> level
+    tgt, qu, qv = level_pixels(scene, level)
+    ok = (qu >= 1) & (qu <= Wl - 3) & (qv >= 1) & (qv <= Hl - 3)
+    j0 = np.floor(qu[ok]).astype(np.int64)
+    i0 = np.floor(qv[ok]).astype(np.int64)
+    f = np.broadcast_to(tgt[:, None], qu.shape)[ok].astype(np.int64)
+    base = (f * Hl + i0) * Wl + j0
+    offs = [di * Wl + dj for di in range(-halo, 2 + halo) for dj in range(-halo, 2 + halo)]
+    return int(np.unique(np.concatenate([base + o for o in offs])).size)
+
+
 def ic_residual_bytes(scene, level=0, real=4):
     """Algorithmic bytes of one launch of the IC residual kernel at `level`:
     per observation its point and pair index, mask byte and the 10-value FP64
@@ -277,6 +338,104 @@ def dynamic_section(pba, scene, reps=10, frame=13):
             "level_start_ms": round(st, 4), "drop_over_level_start": round(d / st, 3),
             "note": "host wall time of the synchronous calls (median); the drop sums the pair blocks, h and H_dd "
                     "again from the records at p(0) instead of linearizing every residual"}
+
+
+def _predicted_positions(scene, poses, inv_depth):
+    """Level-0 pixel of every observation's point centre in its target frame
+    under the given parameters (the tracker's prediction)."""
+    obs_point = np.repeat(np.arange(scene.n_points), np.diff(scene.obs_ptr))
+    hf = scene.host_frame[obs_point]
+    tf = scene.obs_frame
+    K = scene.intrinsics
+    c = scene.host_uv[obs_point].astype(float)
+    x = np.stack([(c[:, 0] - K[hf, 2]) / K[hf, 0], (c[:, 1] - K[hf, 3]) / K[hf, 1], np.ones(len(c))], 1)
+    Rh, th = poses[hf, :9].reshape(-1, 3, 3), poses[hf, 9:]
+    Rf, tf_ = poses[tf, :9].reshape(-1, 3, 3), poses[tf, 9:]
+    R = Rf @ np.swapaxes(Rh, 1, 2)
+    t = tf_ - np.einsum("nij,nj->ni", R, th)
+    v = np.einsum("nij,nj->ni", R, x) + inv_depth[obs_point][:, None] * t
+    return np.stack([K[tf, 0] * v[:, 0] / v[:, 2] + K[tf, 2], K[tf, 1] * v[:, 1] / v[:, 2] + K[tf, 3]], 1)
+
+
+def _pose_errors(poses, ref):
+    e = param_errors(poses, np.ones(1), ref, np.ones(1))
+    return {"rot_max_rad": e["rot_max_rad"], "trans_rel_max": e["trans_rel_max"]}
+
+
+def frontend_section(pba, scene, reps=5, corners_per_frame=2000):
+    """The base solution of Sec. 4.1 on the mid workload, stage by stage: Harris
+    corners of every host frame; robust tracks of the workload's points from
+    their host into each target, predicted from the starting parameters;
+    geometric BA of the tracked observations (FP64, FC iteration, one outlier
+    removal); then the FC photometric solve from its result (the fourth step).
+    Host wall time of the synchronous calls (median of `reps` for the first
+    three)."""
+    kw = dict(n_levels=scene.n_levels, pattern=scene.pattern, huber_k=scene.huber_k)
+    s = pba.Solver(mode=pba.PBA_FC, precision=pba.PBA_FP64, **kw)
+    s.set_frames(scene.images, scene.intrinsics, scene.poses_init)
+    hosts = sorted(set(int(h) for h in scene.host_frame))
+    t_c, n_c = [], []
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        for h in hosts:
+            uv, _ = s.corners(h, cell=8, margin=8, max_corners=corners_per_frame)
+            n_c.append(uv.shape[0])
+        t_c.append((time.perf_counter() - t0) * 1e3 / len(hosts))
+    obs_point = np.repeat(np.arange(scene.n_points), np.diff(scene.obs_ptr))
+    obs_host = scene.host_frame[obs_point].astype(np.int32)
+    obs_target = scene.obs_frame.astype(np.int32)
+    guess = _predicted_positions(scene, scene.poses_init, scene.inv_depth_init)
+    xs = scene.host_uv[obs_point].astype(float)
+    t_t = []
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        pos, st, fb = s.track(obs_host, xs, obs_target, guess, radius=4, n_iters=10, min_eig=1e-6, fb_px=0.5)
+        t_t.append((time.perf_counter() - t0) * 1e3)
+    ok = st == pba.PBA_TRACK_OK
+    # points and observations of the tracks that held
+    keep_pt = np.zeros(scene.n_points, bool)
+    keep_pt[obs_point[ok]] = True
+    cnt = np.bincount(obs_point[ok], minlength=scene.n_points)[keep_pt]
+    optr = np.concatenate([[0], np.cumsum(cnt)]).astype(np.int32)
+    hf, huv = scene.host_frame[keep_pt], scene.host_uv[keep_pt]
+    d0 = scene.inv_depth_init[keep_pt]
+    s.set_points(hf, huv, d0, optr, obs_target[ok])
+    t_g, res = [], None
+    for _ in range(reps):
+        s.set_params(scene.poses_init, d0)
+        s.set_tracks(pos[ok])
+        t0 = time.perf_counter()
+        res, status, inl = s.geo_solve(30, conv_px=5e-3, huber_px=2.0, outlier_px=3.0)
+        t_g.append((time.perf_counter() - t0) * 1e3)
+    poses_g, d_g = s.get_params()
+    s.close()
+    out = {
+        "workload": f"mid: {len(hosts)} host frames 640x480; {obs_point.size} tracks (each workload observation, "
+                    "predicted from the starting parameters); FP64",
+        "corners": {"ms_per_frame": round(float(np.median(t_c)), 4), "per_frame": int(np.median(n_c)),
+                    "cell": 8, "max_corners": corners_per_frame},
+        "tracks": {"ms": round(float(np.median(t_t)), 4), "n": int(obs_point.size), "ok": int(ok.sum()),
+                   "status_counts": np.bincount(st, minlength=4).tolist(), "radius": 4, "iters_per_level": 10,
+                   "levels": scene.n_levels},
+        "geometric_ba": {"ms": round(float(np.median(t_g)), 4), "points": int(keep_pt.sum()),
+                         "observations": int(ok.sum()), "iters": [res.iters[0], res.iters[1]],
+                         "converged": bool(res.converged), "rmse_px": res.final_rmse,
+                         "inliers": int(res.final_active)},
+        "pose_error_vs_truth": {"start": _pose_errors(scene.poses_init, scene.poses_gt),
+                                "geometric": _pose_errors(poses_g, scene.poses_gt)},
+        "note": "host wall time of the synchronous calls, allocation and host copies included",
+    }
+    # step 4: the FC photometric solve from the geometric result
+    f = pba.Solver(mode=pba.PBA_FC, precision=pba.PBA_FP32, **kw)
+    f.set_frames(scene.images, scene.intrinsics, poses_g)
+    f.set_points(hf, huv, d_g, optr, obs_target[ok])
+    t0 = time.perf_counter()
+    r, _ = f.solve(10, 5e-3)
+    poses_p, _ = f.get_params()
+    out["photometric_fc"] = {"ms": round((time.perf_counter() - t0) * 1e3, 4), "iters": list(r.iters[:scene.n_levels]),
+                             "final_rmse": r.final_rmse, **_pose_errors(poses_p, scene.poses_gt)}
+    f.close()
+    return out
 
 
 def cpu_model():
@@ -634,6 +793,7 @@ def main():
     ap.add_argument("--no-oracle-check", action="store_true",
                     help="skip the precision workload's comparison with the FP64 oracle")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-windows section")
+    ap.add_argument("--no-frontend", action="store_true", help="skip the front-end (base solution) section")
     ap.add_argument("--windows", type=int, default=64, help="windows of the batched section")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-preconditioner section")
     ap.add_argument("--train-systems", type=int, default=2000, help="reduced systems harvested for training")
@@ -783,6 +943,10 @@ def main():
     t0 = time.perf_counter()
     line["dynamic_hessian"] = dynamic_section(pba, scene)
     log(f"keyframe drop: {line['dynamic_hessian']} ({time.perf_counter() - t0:.1f} s)")
+    if not args.no_frontend:
+        t0 = time.perf_counter()
+        line["frontend"] = frontend_section(pba, scene)
+        log(f"front end: {time.perf_counter() - t0:.1f} s: {line['frontend']}")
     if not args.no_trace:
         t0 = time.perf_counter()
         line["equal_rmse_converged"] = converged_section(pba, pba.PBA_FP32)

@@ -30,3 +30,10 @@ def test_measured_traffic_follows_the_kernel_sources(monkeypatch):
     assert bench.measured_traffic("k_ic_residual", "mid") is None
     assert bench.measured_traffic("k_ic_step", "mid") is None
 
+
+
+def test_module_level_helpers_are_defined():
+    import bench
+    for name in ("METRIC", "log", "level_pixels", "_pairs", "_unique_texels", "frontend_section",
+                 "_predicted_positions", "roofline_obj", "measured_traffic"):
+        assert hasattr(bench, name), name
