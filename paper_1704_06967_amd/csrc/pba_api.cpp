@@ -1507,16 +1507,17 @@ pba_status pba_fe_corners(pba_ctx *ctx, int32_t window, int32_t frame, int32_t c
     *n_out = 0;
     if (max_corners == 0) return PBA_OK;
     long long *R = nullptr, *cell_R = nullptr, *resp = nullptr;
-    int *cell_idx = nullptr, *duv = nullptr, *count = nullptr;
+    int *cell_idx = nullptr, *rank = nullptr, *duv = nullptr, *count = nullptr;
     hipError_t e = hipSuccess;
     if ((e = dalloc(R, (size_t)W * H * sizeof(long long))) == hipSuccess &&
         (e = dalloc(cell_R, (size_t)ncells * sizeof(long long))) == hipSuccess &&
         (e = dalloc(cell_idx, (size_t)ncells * sizeof(int))) == hipSuccess &&
+        (e = dalloc(rank, (size_t)ncells * sizeof(int))) == hipSuccess &&
         (e = dalloc(duv, (size_t)max_corners * 2 * sizeof(int))) == hipSuccess &&
         (e = dalloc(resp, (size_t)max_corners * sizeof(long long))) == hipSuccess &&
         (e = dalloc(count, sizeof(int))) == hipSuccess) {
         launch_fe_corners(c.stream, c, f0 + frame, cell, margin, min_response, max_corners, R, cell_R, cell_idx,
-                          duv, resp, count);
+                          rank, duv, resp, count);
         int n = 0;
         if ((e = hipMemcpyAsync(&n, count, sizeof(int), hipMemcpyDeviceToHost, c.stream)) == hipSuccess &&
             (e = hipStreamSynchronize(c.stream)) == hipSuccess && n > 0) {
@@ -1530,7 +1531,7 @@ pba_status pba_fe_corners(pba_ctx *ctx, int32_t window, int32_t frame, int32_t c
         if (e == hipSuccess) *n_out = n;
     }
     for (long long **p : {&R, &cell_R, &resp}) dfree(*p);
-    for (int **p : {&cell_idx, &duv, &count}) dfree(*p);
+    for (int **p : {&cell_idx, &rank, &duv, &count}) dfree(*p);
     if (e != hipSuccess) return fail(&c, PBA_E_DEVICE, std::string("HIP error: ") + hipGetErrorString(e));
     return PBA_OK;
 }

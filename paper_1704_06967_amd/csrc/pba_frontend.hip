@@ -135,52 +135,47 @@ __global__ __launch_bounds__(256) void k_cell_best(const long long *__restrict__
     }
 }
 
-constexpr int TOPK_MAX = 8192;   // cells one sorting workgroup takes
+// The K best cell winners, best first. A candidate's rank is the number of
+// candidates that rank before it: every pair is compared once, the grid
+// covering (candidate tile, comparison tile), each block staging its
+// comparison tile in LDS and adding its counts to the ranks (integer atomics,
+// so the sums do not depend on their order). The ranks of the candidates are
+// a permutation, so the candidate of rank r < K alone writes output r, and
+// count = min(K, candidates) by an atomic maximum (rank and count start at 0).
+constexpr int RANK_TILE = 256;
 
-// The K best cell winners, best first (one workgroup: bitonic sort of the
-// cells in LDS, padded to a power of two with empty entries).
-__global__ __launch_bounds__(1024) void k_corner_topk(const long long *__restrict__ cell_R,
-                                                      const int *__restrict__ cell_idx, int n, int P, int W, int K,
-                                                      int *__restrict__ uv, long long *__restrict__ resp,
-                                                      int *__restrict__ count) {
-    __shared__ long long kr[TOPK_MAX];
-    __shared__ int ki[TOPK_MAX];
-    for (int i = threadIdx.x; i < P; i += blockDim.x) {
-        kr[i] = i < n ? cell_R[i] : LLONG_MIN;
-        ki[i] = i < n ? cell_idx[i] : -1;
-    }
+__global__ __launch_bounds__(RANK_TILE) void k_corner_rank(const long long *__restrict__ cell_R,
+                                                           const int *__restrict__ cell_idx, int n,
+                                                           int *__restrict__ rank) {
+    __shared__ long long tr[RANK_TILE];
+    __shared__ int ti[RANK_TILE];
+    const int i = blockIdx.x * RANK_TILE + threadIdx.x;
+    const int j = blockIdx.y * RANK_TILE + threadIdx.x;
+    tr[threadIdx.x] = j < n ? cell_R[j] : LLONG_MIN;
+    ti[threadIdx.x] = j < n ? cell_idx[j] : -1;
     __syncthreads();
-    for (int k = 2; k <= P; k <<= 1)
-        for (int j = k >> 1; j > 0; j >>= 1) {
-            for (int i = threadIdx.x; i < P; i += blockDim.x) {
-                const int l = i ^ j;
-                if (l > i) {
-                    const bool first = (i & k) == 0;   // this run keeps the better entry at i
-                    const bool swap = first ? ranks_before(kr[l], ki[l], kr[i], ki[i])
-                                            : ranks_before(kr[i], ki[i], kr[l], ki[l]);
-                    if (swap) {
-                        const long long tr = kr[i];
-                        const int ti = ki[i];
-                        kr[i] = kr[l];
-                        ki[i] = ki[l];
-                        kr[l] = tr;
-                        ki[l] = ti;
-                    }
-                }
-            }
-            __syncthreads();
-        }
-    // the candidates form a prefix of the sorted list
-    const int lim = min(K, P);
-    for (int i = threadIdx.x; i < lim; i += blockDim.x) {
-        const bool v = ki[i] >= 0;
-        if (v) {
-            uv[2 * i] = ki[i] % W;
-            uv[2 * i + 1] = ki[i] / W;
-            resp[i] = kr[i];
-        }
-        if (v && (i + 1 == lim || ki[i + 1] < 0)) *count = i + 1;
-        if (i == 0 && !v) *count = 0;
+    if (i >= n) return;
+    const long long ri = cell_R[i];
+    const int ii = cell_idx[i];
+    if (ii < 0) return;
+    const int m = min(RANK_TILE, n - (int)blockIdx.y * RANK_TILE);
+    int cnt = 0;
+    for (int k = 0; k < m; ++k) cnt += ranks_before(tr[k], ti[k], ri, ii) ? 1 : 0;
+    if (cnt) atomicAdd(rank + i, cnt);
+}
+
+__global__ __launch_bounds__(256) void k_corner_emit(const long long *__restrict__ cell_R,
+                                                     const int *__restrict__ cell_idx, const int *__restrict__ rank,
+                                                     int n, int W, int K, int *__restrict__ uv,
+                                                     long long *__restrict__ resp, int *__restrict__ count) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int ii = cell_idx[i], r = rank[i];
+    if (ii >= 0 && r < K) {
+        uv[2 * r] = ii % W;
+        uv[2 * r + 1] = ii / W;
+        resp[r] = cell_R[i];
+        atomicMax(count, r + 1);
     }
 }
 
@@ -405,7 +400,8 @@ static inline unsigned nblocks(size_t n, unsigned b) { return (unsigned)((n + b 
 static inline bool is_fp64(const Ctx &c) { return c.cfg.precision == PBA_FP64; }
 
 void launch_fe_corners(hipStream_t s, Ctx &c, int frame, int cell, int margin, long long min_resp, int K,
-                       long long *R, long long *cell_R, int *cell_idx, int *uv, long long *resp, int *count) {
+                       long long *R, long long *cell_R, int *cell_idx, int *rank, int *uv, long long *resp,
+                       int *count) {
     const int W = c.lv[0].W, H = c.lv[0].H;
     const dim3 grid(nblocks(W, HR_TW), nblocks(H, HR_TH));
     if (is_fp64(c))
@@ -415,9 +411,11 @@ void launch_fe_corners(hipStream_t s, Ctx &c, int frame, int cell, int margin, l
     const int ncx = (W + cell - 1) / cell, ncy = (H + cell - 1) / cell, n = ncx * ncy;
     // a candidate's 3 x 3 neighbours lie in the response's defined region
     k_cell_best<<<n, 256, 0, s>>>(R, W, H, cell, margin < 4 ? 4 : margin, min_resp, ncx, cell_R, cell_idx);
-    int P = 1;
-    while (P < n) P <<= 1;
-    k_corner_topk<<<1, 1024, 0, s>>>(cell_R, cell_idx, n, P, W, K, uv, resp, count);
+    (void)hipMemsetAsync(count, 0, sizeof(int), s);
+    (void)hipMemsetAsync(rank, 0, (size_t)n * sizeof(int), s);
+    const unsigned nt = nblocks(n, RANK_TILE);
+    k_corner_rank<<<dim3(nt, nt), RANK_TILE, 0, s>>>(cell_R, cell_idx, n, rank);
+    k_corner_emit<<<nblocks(n, 256), 256, 0, s>>>(cell_R, cell_idx, rank, n, W, K, uv, resp, count);
 }
 
 void launch_fe_track(hipStream_t s, Ctx &c, int n, const int *host, const double *host_uv, const int *target,

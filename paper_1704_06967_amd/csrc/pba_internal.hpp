@@ -338,9 +338,10 @@ void launch_copy_d(hipStream_t s, const double *src, double *dst, size_t n);  //
 void launch_fill(hipStream_t s, double *p, size_t n, double v, const int *gate);
 
 // front end (pba_frontend.hip): corners of one frame (R: [H][W] response scratch,
-// cell_R / cell_idx: per-cell scratch), tracks, geometric BA records and outliers
+// cell_R / cell_idx / rank: per-cell scratch), tracks, geometric BA records and outliers
 void launch_fe_corners(hipStream_t s, Ctx &c, int frame, int cell, int margin, long long min_resp, int K,
-                       long long *R, long long *cell_R, int *cell_idx, int *uv, long long *resp, int *count);
+                       long long *R, long long *cell_R, int *cell_idx, int *rank, int *uv, long long *resp,
+                       int *count);
 void launch_fe_track(hipStream_t s, Ctx &c, int n, const int *host, const double *host_uv, const int *target,
                      const double *guess, int radius, int n_iters, double min_eig, double fb_px, int levels,
                      double *out_uv, int *out_status, double *out_fb);
