@@ -34,9 +34,9 @@ HBM_PEAK_GBS = 8000.0
 # + WRITE_SIZE x 1.000, both scales from a 256 MiB device copy
 # (profiles/ic_iteration_kernels_traffic_mid_precision.md); valid only for the kernel
 # sources whose combined hash is given
-MEASURED_TRAFFIC = {"k_ic_residual": {"mid": 17164595, "precision": 128364544},
+MEASURED_TRAFFIC = {"k_ic_residual": {"mid": 17164595, "precision": 128371917},
                     "k_ic_step": {"mid": 11062170},
-                    "sources_sha256_16": "0685b77fa31d64ed"}
+                    "sources_sha256_16": "5241330df0b5690d"}
 KERNEL_SOURCES = ("pba_kernels.hip", "pba_solver.hip", "pba_depth.hpp", "pba_device.hpp", "pba_internal.hpp")
 
 
