@@ -25,6 +25,8 @@ Photometric Bundle Adjustment" (arXiv 1704.06967):
   * frontend.py   - the base solution's first steps (Sec. 4.1): Harris
                     corners, robust KLT tracking, geometric bundle adjustment
                     with outlier removal.
+  * affine.py     - per-frame affine brightness (log-gain and offset) in the
+                    FC iteration, the photometric modelling Sec. 2 names.
 Readings of passages where the paper is silent or garbled are listed in the
 docstrings where they are applied.
 """
