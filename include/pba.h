@@ -281,6 +281,35 @@ pba_status pba_set_params(pba_ctx *ctx, int32_t window, const double *poses, con
  * system is not positive definite). */
 pba_status pba_drop_frame(pba_ctx *ctx, int32_t window, int32_t frame);
 
+/* Per-frame affine brightness in the FC iteration. The method assumes
+ * brightness constancy (Sec. 3, eq:energy); its prior-art discussion (Sec. 2)
+ * notes that direct methods elsewhere model the photometric response
+ * explicitly. Model (a reading; the paper gives none): frame f has a log-gain
+ * a_f and an offset b_f, and the residual of a patch pixel of a point hosted
+ * by h and observed by f is
+ *     r = I_h(x) - b_h - e^{a_h - a_f} (I_f(W(x; p)) - b_f),
+ * the paper's residual at a = b = 0. pba_set_affine(ctx, ab) with ab = host
+ * double [F][2] (a_f, b_f per frame, level-independent) turns the model on:
+ * from then on pba_iterate, pba_solve and pba_evaluate of this context run
+ * the joint Gauss-Newton iteration over 6 pose and 2 brightness parameters
+ * per frame and the inverse depths (the depths eliminated by their Schur
+ * complement, the 8F x 8F system solved by Cholesky, all in FP64; the pinned
+ * frame keeps its pose and brightness; the brightness block is damped by
+ * damping_rel times the mean of its diagonal; the brightness update is
+ * additive), one host-synchronized iteration at a time. The frozen residual
+ * set, Huber weights, pose and depth damping and the convergence test are the
+ * FC iteration's. ab = NULL turns the model off (the parameters are kept for
+ * pba_get_affine). Needs mode PBA_FC, precision PBA_FP64 or PBA_FP32 and one
+ * window; pba_set_frames with another frame count resets the brightness to
+ * zero. Errors: PBA_E_INVALID (mode, precision, windows, non-finite values),
+ * PBA_E_STATE (frames or points not set); pba_iterate and pba_solve return
+ * PBA_E_NUMERIC when the joint system is not positive definite (the
+ * parameters are then left as they were). */
+pba_status pba_set_affine(pba_ctx *ctx, const double *ab);
+/* The current brightness parameters, host double [F][2] (zeros before
+ * pba_set_affine). Errors: PBA_E_INVALID (ab NULL), PBA_E_STATE (no frames). */
+pba_status pba_get_affine(pba_ctx *ctx, double *ab);
+
 /* ---- Front end for p(0): the first three steps of the base solution of
  * Sec. 4.1 (Harris corners, robust KLT tracking, geometric bundle adjustment
  * with outlier removal). Its fourth step, the forward-compositional

@@ -8,7 +8,8 @@ import tempfile
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpba.so")
-SOURCES = ["pba_kernels.hip", "pba_solver.hip", "pba_dense.hip", "pba_learned.hip", "pba_frontend.hip", "pba_api.cpp"]
+SOURCES = ["pba_kernels.hip", "pba_solver.hip", "pba_dense.hip", "pba_learned.hip", "pba_frontend.hip", "pba_affine.hip",
+           "pba_api.cpp"]
 ARCH = "gfx950"
 # -packed-fp32-ops keeps the compiler from emitting packed FP32 instructions.
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang",

@@ -1,0 +1,448 @@
+// Per-frame affine brightness in the forward-compositional iteration.
+//
+// Reading (the paper names explicit photometric modelling, as in DSO, in its
+// prior-art discussion, Sec. 2, and gives no model): frame f has a log-gain
+// a_f and an offset b_f; the target intensity is brought into the host's
+// photometric units before it is compared with the template,
+//     r = I_h(x) - b_h - g (I_f(W(x; p)) - b_f),   g = e^{a_h - a_f},
+// the paper's residual at a = b = 0. Its derivatives: the FC Jacobian of the
+// plain residual times g for the geometry, and (-g (I_f - b_f), -1,
+// g (I_f - b_f), g) for (a_h, b_h, a_f, b_f). The unknowns are 6 pose and 2
+// brightness parameters per frame and the inverse depths.
+//
+// One iteration: each observation's FC record (pose-pose block, h, H_dd,
+// gradients; read by the FC kernels, which form the pose part of the depth
+// Schur complement as before) and its brightness record (pose-brightness and
+// brightness-brightness blocks, the brightness-depth coupling and gradient);
+// then the 8F x 8F reduced system: the pose block from the FC assembly, the
+// rest added per point (its direct blocks and its Schur terms; FP64 atomic
+// adds, so these sums are not bitwise reproducible between runs), the
+// brightness damping (damping_rel times the mean of the brightness diagonal)
+// and the pin (the pinned frame's 8 rows); the tiled Cholesky solve; the
+// pose, brightness and depth updates and the convergence measure. All
+// arithmetic in FP64 (the images and templates in the context's type).
+#include <climits>
+
+#include "pba_device.hpp"
+#include "pba_affine.hpp"
+#include "pba_internal.hpp"
+
+namespace pba {
+
+template <typename T>
+struct AffArgs {
+    int O, P, W, H;
+    double scale, huber_k;
+    int du[8], dv[8];
+    const int *obs_point, *obs_pair, *pair_host, *pair_target;
+    const float *host_uv;
+    const T *img, *tmpl;
+    const double *geo, *pcam, *depth, *ab;
+    uint8_t *mask;
+    const uint8_t *live;
+    double *rec, *arec;
+};
+
+// mode 0: linearize over the frozen set; 1: decide the frozen set at these
+// parameters, then linearize; 2: statistics over the set usable at these
+// parameters only (the mask is not touched)
+template <typename T>
+__global__ __launch_bounds__(256) void k_aff_linearize(AffArgs<T> a, int mode) {
+    const int o = blockIdx.x * blockDim.x + threadIdx.x;
+    if (o >= a.O) return;
+    const int n = a.obs_point[o], p = a.obs_pair[o];
+    const int h = a.pair_host[p], f = a.pair_target[p];
+    const double *g = a.geo + GEO_STRIDE * p, *K = a.pcam + 8 * p;
+    const double d = a.depth[n];
+    const double ah = a.ab[2 * h], bh = a.ab[2 * h + 1], af = a.ab[2 * f], bf = a.ab[2 * f + 1];
+    const double gain = exp(ah - af);
+    const T *img = a.img + (size_t)f * a.W * a.H;
+    double H21[21], hv[6], hdd = 0.0, gv6[6], gd = 0.0, E = 0.0, SQ = 0.0, CNT = 0.0;
+    double C[24], Pp[10], hp[4], gp[4];
+    for (int k = 0; k < 21; ++k) H21[k] = 0.0;
+    for (int k = 0; k < 6; ++k) hv[k] = gv6[k] = 0.0;
+    for (int k = 0; k < 24; ++k) C[k] = 0.0;
+    for (int k = 0; k < 10; ++k) Pp[k] = 0.0;
+    for (int k = 0; k < 4; ++k) hp[k] = gp[k] = 0.0;
+    unsigned m = mode == 0 ? (unsigned)a.mask[o] : 0u;
+    const bool live = a.live[o] != 0;
+    for (int j = 0; j < a.P; ++j) {
+        const T *tp = a.tmpl + 4 * ((size_t)n * a.P + j);
+        const double u = ((double)a.host_uv[2 * n] + 0.5) * a.scale - 0.5 + (double)a.du[j];
+        const double v = ((double)a.host_uv[2 * n + 1] + 0.5) * a.scale - 0.5 + (double)a.dv[j];
+        const double x = (u - K[2]) / K[0], y = (v - K[3]) / K[1];
+        const double Rx0 = g[0] * x + g[1] * y + g[2], Rx1 = g[3] * x + g[4] * y + g[5];
+        const double Rx2 = g[6] * x + g[7] * y + g[8];
+        const double v0 = Rx0 + d * g[9], v1 = Rx1 + d * g[10], vz = Rx2 + d * g[11];
+        const bool front = vz > 0.0;
+        const double vzs = front ? vz : 1.0;
+        const double ux = v0 / vzs, uy = v1 / vzs;
+        const double qu = K[4] * ux + K[6], qv = K[5] * uy + K[7];
+        const bool ok_now = (double)tp[3] != 0.0 && d > 0.0 && front && usable(qu, qv, a.W, a.H);
+        if (mode == 1 && ok_now) m |= 1u << j;
+        const bool use = live && ok_now && (mode == 2 || ((m >> j) & 1u));
+        if (!use) continue;
+        double If, gu, gvv;
+        bilinear_grad(img, a.W, qu, qv, If, gu, gvv);
+        const double r = (double)tp[0] - bh - gain * (If - bf);
+        double w, rho;
+        huber(r, a.huber_k, w, rho);
+        E += rho;
+        SQ += r * r;
+        CNT += 1.0;
+        if (mode == 2) continue;
+        double J[7];
+        const double t3[3] = {g[9], g[10], g[11]};
+        fc_jacobian(Rx0, Rx1, Rx2, vz, ux, uy, t3, d, gu, gvv, K[4], K[5], J);
+        for (int k = 0; k < 7; ++k) J[k] *= gain;
+        const double e = gain * (If - bf);
+        const double Jp[4] = {-e, -1.0, e, gain};
+        int t = 0;
+        for (int i = 0; i < 6; ++i)
+            for (int k = i; k < 6; ++k) H21[t++] += w * J[i] * J[k];
+        for (int i = 0; i < 6; ++i) {
+            hv[i] += w * J[i] * J[6];
+            gv6[i] += w * J[i] * r;
+            for (int k = 0; k < 4; ++k) C[4 * i + k] += w * J[i] * Jp[k];
+        }
+        hdd += w * J[6] * J[6];
+        gd += w * J[6] * r;
+        t = 0;
+        for (int i = 0; i < 4; ++i) {
+            for (int k = i; k < 4; ++k) Pp[t++] += w * Jp[i] * Jp[k];
+            hp[i] += w * Jp[i] * J[6];
+            gp[i] += w * Jp[i] * r;
+        }
+    }
+    if (mode == 1) a.mask[o] = (uint8_t)m;
+    double *rc = a.rec + (size_t)o * REC_STRIDE;
+    rc[REC_E] = E;
+    rc[REC_SQ] = SQ;
+    rc[REC_CNT] = CNT;
+    if (mode == 2) return;
+    for (int k = 0; k < 21; ++k) rc[REC_H + k] = H21[k];
+    for (int k = 0; k < 6; ++k) {
+        rc[REC_h + k] = hv[k];
+        rc[REC_G + k] = gv6[k];
+    }
+    rc[REC_HDD] = hdd;
+    rc[REC_GD] = gd;
+    double *ar = a.arec + (size_t)o * AFF_STRIDE;
+    for (int k = 0; k < 24; ++k) ar[AFF_C + k] = C[k];
+    for (int k = 0; k < 10; ++k) ar[AFF_P + k] = Pp[k];
+    for (int k = 0; k < 4; ++k) {
+        ar[AFF_h + k] = hp[k];
+        ar[AFF_G + k] = gp[k];
+    }
+}
+
+// The reduced system's rows and columns beyond the pose block, and the whole
+// right-hand side, added per point (one thread each): the point's direct
+// pose-brightness and brightness-brightness blocks and gradients, mapped to
+// absolute coordinates, then its Schur terms over its frames (host and
+// targets), u_i u_j^T / H_dd and u_i g_d / H_dd, with u the point's coupling
+// to each frame's pose (A^T h or the sum of B^T h) and brightness. The
+// pose-pose block and its Schur terms come from the FC assembly.
+__global__ __launch_bounds__(256) void k_aff_points(int N, int F, const int *__restrict__ obs_ptr,
+                                                    const int *__restrict__ obs_pair,
+                                                    const int *__restrict__ pair_host,
+                                                    const int *__restrict__ pair_target,
+                                                    const double *__restrict__ geo, const double *__restrict__ rec,
+                                                    const double *__restrict__ arec, const double *__restrict__ Hdd,
+                                                    const double *__restrict__ gdn, double *__restrict__ M,
+                                                    double *__restrict__ b, double *__restrict__ diag_phi) {
+    const int n = blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= N) return;
+    const int o0 = obs_ptr[n], o1 = obs_ptr[n + 1];
+    if (o1 <= o0) return;
+    const int n8 = 8 * F, F6 = 6 * F;
+    const double iH = 1.0 / Hdd[n], gd = gdn[n];
+    const int h = pair_host[obs_pair[o0]];
+    double uth[6] = {0, 0, 0, 0, 0, 0}, uph[2] = {0.0, 0.0};
+    for (int o = o0; o < o1; ++o) {
+        const int p = obs_pair[o], f = pair_target[p];
+        const double *gm = geo + GEO_STRIDE * p;
+        const double *rc = rec + (size_t)o * REC_STRIDE, *ar = arec + (size_t)o * AFF_STRIDE;
+        double tb[6], ta[6];
+        apply_Bt(gm, rc + REC_h, tb);
+        for (int i = 0; i < 6; ++i) uth[i] += tb[i];
+        uph[0] += ar[AFF_h];
+        uph[1] += ar[AFF_h + 1];
+        // direct pose-brightness blocks (columns a_h, b_h, a_f, b_f)
+        int col[4] = {F6 + 2 * h, F6 + 2 * h + 1, F6 + 2 * f, F6 + 2 * f + 1};
+        for (int k = 0; k < 4; ++k) {
+            double c[6];
+            for (int i = 0; i < 6; ++i) c[i] = ar[AFF_C + 4 * i + k];
+            apply_At(gm, c, ta);
+            apply_Bt(gm, c, tb);
+            for (int i = 0; i < 6; ++i) {
+                atomicAdd(M + (size_t)(6 * f + i) * n8 + col[k], ta[i]);
+                atomicAdd(M + (size_t)col[k] * n8 + 6 * f + i, ta[i]);
+                atomicAdd(M + (size_t)(6 * h + i) * n8 + col[k], tb[i]);
+                atomicAdd(M + (size_t)col[k] * n8 + 6 * h + i, tb[i]);
+            }
+        }
+        // direct brightness-brightness block
+        int t = 0;
+        for (int i = 0; i < 4; ++i)
+            for (int k = i; k < 4; ++k, ++t) {
+                const double v = ar[AFF_P + t];
+                atomicAdd(M + (size_t)col[i] * n8 + col[k], v);
+                if (i != k)
+                    atomicAdd(M + (size_t)col[k] * n8 + col[i], v);
+                else
+                    atomicAdd(diag_phi + (col[i] - F6), v);
+            }
+        // gradients
+        apply_At(gm, rc + REC_G, ta);
+        apply_Bt(gm, rc + REC_G, tb);
+        for (int i = 0; i < 6; ++i) {
+            atomicAdd(b + 6 * f + i, ta[i]);
+            atomicAdd(b + 6 * h + i, tb[i]);
+        }
+        for (int k = 0; k < 4; ++k) atomicAdd(b + col[k], ar[AFF_G + k]);
+    }
+    // Schur terms over the point's frames: index 0 the host, then one per observation
+    const int m = o1 - o0;
+    for (int i = 0; i <= m; ++i) {
+        int fi;
+        double ti[6], pi[2];
+        if (i == 0) {
+            fi = h;
+            for (int k = 0; k < 6; ++k) ti[k] = uth[k];
+            pi[0] = uph[0];
+            pi[1] = uph[1];
+        } else {
+            const int o = o0 + i - 1, p = obs_pair[o];
+            fi = pair_target[p];
+            apply_At(geo + GEO_STRIDE * p, rec + (size_t)o * REC_STRIDE + REC_h, ti);
+            pi[0] = arec[(size_t)o * AFF_STRIDE + AFF_h + 2];
+            pi[1] = arec[(size_t)o * AFF_STRIDE + AFF_h + 3];
+        }
+        for (int k = 0; k < 6; ++k) atomicAdd(b + 6 * fi + k, -ti[k] * gd * iH);
+        for (int k = 0; k < 2; ++k) atomicAdd(b + F6 + 2 * fi + k, -pi[k] * gd * iH);
+        for (int j = 0; j <= m; ++j) {
+            int fj;
+            double pj[2];
+            if (j == 0) {
+                fj = h;
+                pj[0] = uph[0];
+                pj[1] = uph[1];
+            } else {
+                const int o = o0 + j - 1;
+                fj = pair_target[obs_pair[o]];
+                pj[0] = arec[(size_t)o * AFF_STRIDE + AFF_h + 2];
+                pj[1] = arec[(size_t)o * AFF_STRIDE + AFF_h + 3];
+            }
+            for (int k = 0; k < 6; ++k)
+                for (int l = 0; l < 2; ++l) {
+                    const double v = -ti[k] * pj[l] * iH;
+                    atomicAdd(M + (size_t)(6 * fi + k) * n8 + F6 + 2 * fj + l, v);
+                    atomicAdd(M + (size_t)(F6 + 2 * fj + l) * n8 + 6 * fi + k, v);
+                }
+            for (int k = 0; k < 2; ++k)
+                for (int l = 0; l < 2; ++l)
+                    atomicAdd(M + (size_t)(F6 + 2 * fi + k) * n8 + F6 + 2 * fj + l, -pi[k] * pj[l] * iH);
+        }
+    }
+}
+
+// M <- 0 and the pose block <- the FC assembly's damped, pinned S; b, the
+// brightness diagonal and the maxima <- 0.
+__global__ void k_aff_clear(int F, const double *__restrict__ S, double *__restrict__ M, double *__restrict__ b,
+                            double *__restrict__ diag_phi, unsigned long long *__restrict__ maxb) {
+    const int n8 = 8 * F, F6 = 6 * F;
+    const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e < (size_t)n8 * n8) {
+        const int r = (int)(e / n8), c = (int)(e % n8);
+        M[e] = (r < F6 && c < F6) ? S[(size_t)r * F6 + c] : 0.0;
+    }
+    if (e < (size_t)n8) b[e] = 0.0;
+    if (e < (size_t)2 * F) diag_phi[e] = 0.0;
+    if (e < 4) maxb[e] = 0ull;
+}
+
+// Brightness damping (damping_rel times the mean of the brightness diagonal
+// before the pin; damping_rel when that mean is 0) and the pin of frame
+// `pinned`: its 8 rows and columns become the identity, its rhs 0. One block.
+__global__ void k_aff_finish(int F, int pinned, double damping_rel, double *__restrict__ M, double *__restrict__ b,
+                             const double *__restrict__ diag_phi) {
+    __shared__ double mu;
+    const int n8 = 8 * F, F6 = 6 * F;
+    if (threadIdx.x == 0) {
+        double sdg = 0.0;
+        for (int k = 0; k < 2 * F; ++k) sdg += diag_phi[k];
+        const double mean = F > 0 ? sdg / (2.0 * F) : 0.0;
+        mu = mean > 0.0 ? damping_rel * mean : damping_rel;
+    }
+    __syncthreads();
+    for (int k = threadIdx.x; k < 2 * F; k += blockDim.x) M[(size_t)(F6 + k) * n8 + F6 + k] += mu;
+    __syncthreads();
+    if (pinned < 0 || pinned >= F) return;
+    for (int q = 0; q < 8; ++q) {
+        const int r = q < 6 ? 6 * pinned + q : F6 + 2 * pinned + (q - 6);
+        for (int c = threadIdx.x; c < n8; c += blockDim.x) {
+            M[(size_t)r * n8 + c] = 0.0;
+            M[(size_t)c * n8 + r] = 0.0;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            M[(size_t)r * n8 + r] = 1.0;
+            b[r] = 0.0;
+        }
+        __syncthreads();
+    }
+}
+
+// Pose (FC increment) and brightness updates of every frame; the old poses go
+// to poses_old. Nothing when the solve failed (flag set).
+__global__ void k_aff_frames(int F, const double *__restrict__ x, double *__restrict__ poses,
+                             double *__restrict__ poses_old, double *__restrict__ ab, const int *__restrict__ flag) {
+    const int f = blockIdx.x * blockDim.x + threadIdx.x;
+    if (f >= F || *flag) return;
+    double *P = poses + 12 * f;
+    for (int k = 0; k < 12; ++k) poses_old[12 * f + k] = P[k];
+    const double *dx = x + 6 * f;
+    double dR[9], R[9];
+    so3_exp(dx, dR);
+    mat3_mul(dR, P, R);
+    for (int k = 0; k < 9; ++k) P[k] = R[k];
+    for (int k = 0; k < 3; ++k) P[9 + k] += dx[3 + k];
+    ab[2 * f] += x[6 * F + 2 * f];
+    ab[2 * f + 1] += x[6 * F + 2 * f + 1];
+}
+
+// Depth back-substitution dd = -(g_d + h^T (A dth_f + B dth_h) + h_phi^T dphi) / H_dd
+// per point, then the largest point-centre displacement (old parameters
+// against new, level-0 camera) and the largest depth step (maxb[0], maxb[1],
+// as the bits of non-negative doubles).
+__global__ __launch_bounds__(256) void k_aff_depths(int N, int F, const int *__restrict__ obs_ptr,
+                                                    const int *__restrict__ obs_pair,
+                                                    const int *__restrict__ pair_host,
+                                                    const int *__restrict__ pair_target,
+                                                    const double *__restrict__ geo_old,
+                                                    const double *__restrict__ poses,
+                                                    const double *__restrict__ pairK0,
+                                                    const float *__restrict__ host_uv,
+                                                    const double *__restrict__ rec, const double *__restrict__ arec,
+                                                    const double *__restrict__ Hdd, const double *__restrict__ gdn,
+                                                    const double *__restrict__ x, double *__restrict__ depth,
+                                                    const uint8_t *__restrict__ live,
+                                                    unsigned long long *__restrict__ maxb,
+                                                    const int *__restrict__ flag) {
+    const int n = blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= N || *flag) return;
+    const int o0 = obs_ptr[n], o1 = obs_ptr[n + 1];
+    const int F6 = 6 * F;
+    double s = gdn[n];
+    for (int o = o0; o < o1; ++o) {
+        const int p = obs_pair[o], h = pair_host[p], f = pair_target[p];
+        const double *gm = geo_old + GEO_STRIDE * p;
+        double ra[6], rb[6];
+        apply_A(gm, x + 6 * f, ra);
+        apply_B(gm, x + 6 * h, rb);
+        const double *hv = rec + (size_t)o * REC_STRIDE + REC_h;
+        for (int k = 0; k < 6; ++k) s += hv[k] * (ra[k] + rb[k]);
+        const double *hp = arec + (size_t)o * AFF_STRIDE + AFF_h;
+        s += hp[0] * x[F6 + 2 * h] + hp[1] * x[F6 + 2 * h + 1] + hp[2] * x[F6 + 2 * f] + hp[3] * x[F6 + 2 * f + 1];
+    }
+    const double d_old = depth[n];
+    const double dd = o1 > o0 ? -s / Hdd[n] : 0.0;
+    const double d_new = d_old + dd;
+    depth[n] = d_new;
+    double md = 0.0;
+    for (int o = o0; o < o1; ++o) {
+        if (!live[o]) continue;
+        const int p = obs_pair[o], h = pair_host[p], f = pair_target[p];
+        const double *Kp = pairK0 + 8 * p;
+        const double xx = ((double)host_uv[2 * n] - Kp[2]) / Kp[0], yy = ((double)host_uv[2 * n + 1] - Kp[3]) / Kp[1];
+        // old: the pair geometry of the iteration; new: from the updated poses
+        const double *Ph = poses + 12 * h, *Pf = poses + 12 * f;
+        double Rn[9], tn[3];
+        mat3_mul_bt(Pf, Ph, Rn);
+        for (int k = 0; k < 3; ++k) tn[k] = Pf[9 + k] - (Rn[3 * k] * Ph[9] + Rn[3 * k + 1] * Ph[10] + Rn[3 * k + 2] * Ph[11]);
+        const double *go = geo_old + GEO_STRIDE * p;
+        double q[2][2];
+        bool ok = true;
+        for (int w = 0; w < 2; ++w) {
+            const double *R = w ? Rn : go;
+            const double *t = w ? tn : go + 9;
+            const double dd2 = w ? d_new : d_old;
+            const double vx = R[0] * xx + R[1] * yy + R[2] + dd2 * t[0];
+            const double vy = R[3] * xx + R[4] * yy + R[5] + dd2 * t[1];
+            const double vz = R[6] * xx + R[7] * yy + R[8] + dd2 * t[2];
+            ok = ok && vz > 0.0;
+            const double vzs = vz > 0.0 ? vz : 1.0;
+            q[w][0] = Kp[4] * vx / vzs + Kp[6];
+            q[w][1] = Kp[5] * vy / vzs + Kp[7];
+        }
+        if (ok) md = fmax(md, hypot(q[1][0] - q[0][0], q[1][1] - q[0][1]));
+    }
+    atomicMax(maxb, (unsigned long long)__double_as_longlong(md));
+    atomicMax(maxb + 1, (unsigned long long)__double_as_longlong(fabs(dd)));
+}
+
+// ------------------------------------------------------------ launchers
+
+static inline unsigned nblk(size_t n, unsigned b) { return (unsigned)((n + b - 1) / b); }
+
+template <typename T>
+static AffArgs<T> aff_args(Ctx &c, const AffBufs &ab, int level, const double *geo) {
+    AffArgs<T> a{};
+    a.O = c.O;
+    a.P = c.cfg.pattern_n;
+    a.W = c.lv[level].W;
+    a.H = c.lv[level].H;
+    a.scale = 1.0 / (double)(1 << level);
+    a.huber_k = c.cfg.huber_k;
+    for (int j = 0; j < 8; ++j) {
+        a.du[j] = j < a.P ? c.cfg.pattern_uv[2 * j] : 0;
+        a.dv[j] = j < a.P ? c.cfg.pattern_uv[2 * j + 1] : 0;
+    }
+    a.obs_point = c.d_obs_point;
+    a.obs_pair = c.d_obs_pair;
+    a.pair_host = c.d_pair_host;
+    a.pair_target = c.d_pair_target;
+    a.host_uv = c.d_host_uv;
+    a.img = (const T *)c.lv[level].img;
+    a.tmpl = (const T *)c.lv[level].tmpl;
+    a.geo = geo;
+    a.pcam = (const double *)c.lv[level].pcam;
+    a.depth = c.d_depth;
+    a.ab = ab.ab;
+    a.mask = c.d_mask;
+    a.live = c.d_obs_live;
+    a.rec = (double *)c.d_rec;
+    a.arec = ab.arec;
+    return a;
+}
+
+void launch_aff_linearize(hipStream_t s, Ctx &c, const AffBufs &ab, int level, const double *geo, int mode) {
+    if (c.O == 0) return;
+    if (c.cfg.precision == PBA_FP64)
+        k_aff_linearize<double><<<nblk(c.O, 256), 256, 0, s>>>(aff_args<double>(c, ab, level, geo), mode);
+    else
+        k_aff_linearize<float><<<nblk(c.O, 256), 256, 0, s>>>(aff_args<float>(c, ab, level, geo), mode);
+}
+
+void launch_aff_system(hipStream_t s, Ctx &c, const AffBufs &a, const double *geo) {
+    const int F = c.F, n8 = 8 * F;
+    k_aff_clear<<<nblk((size_t)n8 * n8, 256), 256, 0, s>>>(F, c.d_S, a.M, a.b, a.dphi, a.maxb);
+    if (c.N > 0)
+        k_aff_points<<<nblk(c.N, 256), 256, 0, s>>>(c.N, F, c.d_obs_ptr, c.d_obs_pair, c.d_pair_host, c.d_pair_target,
+                                                    geo, (const double *)c.d_rec, a.arec, c.d_Hdd, c.d_gd, a.M, a.b,
+                                                    a.dphi);
+    k_aff_finish<<<1, 256, 0, s>>>(F, c.cfg.pinned_frame, c.cfg.damping_rel, a.M, a.b, a.dphi);
+}
+
+void launch_aff_update(hipStream_t s, Ctx &c, const AffBufs &a, const double *geo_old) {
+    const int F = c.F;
+    k_aff_frames<<<nblk(F, 64), 64, 0, s>>>(F, a.x, c.d_poses, a.poses_old, a.ab, a.flag);
+    if (c.N > 0)
+        k_aff_depths<<<nblk(c.N, 256), 256, 0, s>>>(c.N, F, c.d_obs_ptr, c.d_obs_pair, c.d_pair_host, c.d_pair_target,
+                                                    geo_old, c.d_poses, c.d_pairK0, c.d_host_uv,
+                                                    (const double *)c.d_rec, a.arec, c.d_Hdd, c.d_gd, a.x, c.d_depth,
+                                                    c.d_obs_live, a.maxb, a.flag);
+}
+
+}  // namespace pba

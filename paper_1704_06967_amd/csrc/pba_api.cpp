@@ -16,6 +16,7 @@
 #include <string>
 #include <vector>
 
+#include "pba_affine.hpp"
 #include "pba_internal.hpp"
 
 using namespace pba;
@@ -39,6 +40,7 @@ struct pba_ctx {
     std::vector<WinStage> stage;     // n_windows > 1 only
     bool dirty = false;              // staged inputs not yet assembled
     int stage_W = 0, stage_H = 0;
+    AffBufs aff;                     // per-frame affine brightness (pba_set_affine)
 };
 
 namespace {
@@ -1112,6 +1114,152 @@ pba_status pc_upload_samples(Ctx &c, int m, const float *G) {
     return PBA_OK;
 }
 
+// ---- per-frame affine brightness in the FC iteration (pba_set_affine)
+
+void aff_release(AffBufs &a) {
+    for (double **p : {&a.ab, &a.arec, &a.M, &a.fac, &a.Linv, &a.b, &a.x, &a.dphi, &a.poses_old, &a.stats}) dfree(*p);
+    dfree(a.maxb);
+    dfree(a.flag);
+    a = AffBufs();
+}
+
+// Buffers for the context's current frames and observations; the brightness
+// parameters are kept while the frame count is unchanged, else set to zero.
+pba_status aff_ensure(Ctx &c, AffBufs &a) {
+    if (a.ab && a.F == c.F && a.O == c.O) return PBA_OK;
+    const bool keep_ab = a.ab && a.F == c.F;
+    const size_t n8 = 8 * (size_t)c.F, nt = (n8 + TCHOL_TILE - 1) / TCHOL_TILE, d = sizeof(double);
+    if (!keep_ab) {
+        HIPCHK(dalloc(a.ab, 2 * (size_t)c.F * d));
+        HIPCHK(hipMemsetAsync(a.ab, 0, 2 * (size_t)c.F * d, c.stream));
+    }
+    HIPCHK(dalloc(a.arec, (size_t)c.O * AFF_STRIDE * d));
+    HIPCHK(dalloc(a.M, n8 * n8 * d));
+    HIPCHK(dalloc(a.fac, n8 * n8 * d));
+    HIPCHK(dalloc(a.Linv, nt * TCHOL_TILE * TCHOL_TILE * d));
+    HIPCHK(dalloc(a.b, n8 * d));
+    HIPCHK(dalloc(a.x, n8 * d));
+    HIPCHK(dalloc(a.dphi, 2 * (size_t)c.F * d));
+    HIPCHK(dalloc(a.poses_old, 12 * (size_t)c.F * d));
+    HIPCHK(dalloc(a.stats, sum_stats_doubles(c) * d));
+    HIPCHK(dalloc(a.maxb, 4 * sizeof(unsigned long long)));
+    HIPCHK(dalloc(a.flag, 2 * sizeof(int)));
+    HIPCHK(hipMemsetAsync(a.flag, 0, 2 * sizeof(int), c.stream));
+    a.F = c.F;
+    a.O = c.O;
+    return PBA_OK;
+}
+
+std::string aff_check(const Ctx &c) {
+    if (c.cfg.mode != PBA_FC) return "the brightness model runs in the FC iteration (mode PBA_FC)";
+    if (c.cfg.precision == PBA_MIXED_BF16) return "the brightness model needs PBA_FP64 or PBA_FP32";
+    if (c.nwin != 1) return "the brightness model takes one window (n_windows = 1)";
+    return "";
+}
+
+// Residual statistics of the brightness model at the current parameters over
+// the residuals usable there (level's template), into out (energy, sq, count).
+template <typename T>
+pba_status aff_evaluate(Ctx &c, AffBufs &a, int level, double out[3]) {
+    hipStream_t s = c.stream;
+    if (!c.lv[level].tmpl_valid) {
+        Launch<T>::make_template(s, c, level);
+        c.lv[level].tmpl_valid = true;
+    }
+    double *geo = c.flip ? c.d_geo_b : c.d_geo_a;
+    Launch<T>::relpose(s, c, c.d_poses, geo, (T *)(c.flip ? c.d_rel_b : c.d_rel_a));
+    launch_aff_linearize(s, c, a, level, geo, 2);
+    if (c.O > 0)
+        launch_sum_stats(s, c, c.d_rec, true, a.stats);
+    else
+        launch_fill(s, a.stats, 3, 0.0, nullptr);
+    HIPCHK(hipMemcpyAsync(out, a.stats, 3 * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    HIPCHK(hipGetLastError());
+    return PBA_OK;
+}
+
+// One joint iteration at `level` (the level started): the records, the FC
+// assembly of the pose block, the joint system, its solve and the updates;
+// synchronizes and fills *out.
+template <typename T>
+pba_status aff_iteration(Ctx &c, AffBufs &a, int level, pba_iter_stats *out) {
+    hipStream_t s = c.stream;
+    double *geo = c.d_geo_a;
+    launch_aff_linearize(s, c, a, level, geo, c.iters_in_level == 0 ? 1 : 0);
+    Launch<T>::point_reduce(s, c, true);
+    Launch<T>::pair_reduce_H(s, c);
+    launch_mu(s, c, geo);
+    launch_gram(s, c, geo, c.d_rec, true);
+    launch_assemble_s(s, c, geo);
+    if (c.O > 0)
+        launch_sum_stats(s, c, c.d_rec, true, a.stats);
+    else
+        launch_fill(s, a.stats, 3, 0.0, nullptr);
+    launch_aff_system(s, c, a, geo);
+    const int n8 = 8 * c.F;
+    launch_dense_solve(s, n8, a.M, a.fac, a.Linv, a.b, a.x, a.flag);
+    launch_aff_update(s, c, a, geo);
+    Launch<T>::relpose(s, c, c.d_poses, geo, (T *)c.d_rel_a);   // the pair geometry of the new parameters
+    double st3[3];
+    unsigned long long mx[2];
+    int flag = 0;
+    std::vector<double> x((size_t)n8);
+    HIPCHK(hipMemcpyAsync(st3, a.stats, sizeof(st3), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(mx, a.maxb, sizeof(mx), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(&flag, a.flag, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(x.data(), a.x, x.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    HIPCHK(hipGetLastError());
+    c.s_valid = false;   // d_S holds the pose block only
+    if (flag) return fail(&c, PBA_E_NUMERIC, "joint pose-brightness system is not positive definite");
+    double mp = 0.0;
+    for (int i = 0; i < 6 * c.F; ++i) mp = std::max(mp, std::fabs(x[(size_t)i]));
+    if (out) {
+        std::memset(out, 0, sizeof(*out));
+        out->level = level;
+        out->iter = c.iters_in_level;
+        out->n_active = (int64_t)std::llround(st3[2]);
+        out->energy = st3[0];
+        out->sq = st3[1];
+        out->rmse = out->n_active > 0 ? std::sqrt(st3[1] / (double)out->n_active) : 0.0;
+        double dv[2];
+        std::memcpy(dv, mx, sizeof(dv));
+        out->max_disp_px = dv[0];
+        out->max_step_pose = mp;
+        out->max_step_depth = dv[1];
+    }
+    c.iters_in_level++;
+    return PBA_OK;
+}
+
+// Up to n_iters joint iterations at `level` (started), stopping after the
+// first whose displacement is below conv_px (conv_px >= 0).
+pba_status aff_run(Ctx &c, AffBufs &a, int level, int n_iters, double conv_px, pba_iter_stats *out, int *ran) {
+    pba_status st;
+    if ((st = aff_ensure(c, a)) != PBA_OK) return st;
+    launch_open(c.stream, c, level, true);
+    // the current pair geometry in the first buffer
+    if (is_fp64(c))
+        Launch<double>::relpose(c.stream, c, c.d_poses, c.d_geo_a, (double *)c.d_rel_a);
+    else
+        Launch<float>::relpose(c.stream, c, c.d_poses, c.d_geo_a, (float *)c.d_rel_a);
+    c.flip = false;
+    int k = 0;
+    for (; k < n_iters; ++k) {
+        pba_iter_stats it;
+        st = is_fp64(c) ? aff_iteration<double>(c, a, level, &it) : aff_iteration<float>(c, a, level, &it);
+        if (st != PBA_OK) break;
+        if (out) out[k] = it;
+        if (conv_px >= 0.0 && it.max_disp_px < conv_px) {
+            ++k;
+            break;
+        }
+    }
+    if (ran) *ran = k;
+    return st;
+}
+
 std::string pc_system_check(Ctx &c) {
     if (c.nwin != 1) return "the reduced-system solvers take one window (n_windows = 1)";
     if (!c.s_valid) return "no reduced system assembled yet (run an iteration first)";
@@ -1209,6 +1357,7 @@ void pba_destroy(pba_ctx *ctx) {
     release_frames(c);
     dfree(c.d_eval);
     release_pc(c);
+    aff_release(ctx->aff);
     for (hipEvent_t e : c.ev_pool) (void)hipEventDestroy(e);
     if (c.own_stream && c.stream) (void)hipStreamDestroy(c.stream);
     delete ctx;
@@ -1342,6 +1491,7 @@ pba_status pba_iterate(pba_ctx *ctx, int32_t level, int32_t n_iters, pba_iter_st
     pba_status st;
     if ((st = ready(ctx)) != PBA_OK) return st;
     if (c.cur_level != level && (st = do_start_level(c, level)) != PBA_OK) return st;
+    if (ctx->aff.on) return aff_run(c, ctx->aff, level, n_iters, -1.0, stats, nullptr);
     return run_iterations(c, level, n_iters, stats);
 }
 
@@ -1353,6 +1503,19 @@ pba_status pba_evaluate(pba_ctx *ctx, int32_t level, pba_iter_stats *out) {
     pba_status st;
     if ((st = ready(ctx)) != PBA_OK) return st;
     hipStream_t s = c.stream;
+    if (ctx->aff.on) {
+        double h[3];
+        if ((st = aff_ensure(c, ctx->aff)) != PBA_OK) return st;
+        st = is_fp64(c) ? aff_evaluate<double>(c, ctx->aff, level, h) : aff_evaluate<float>(c, ctx->aff, level, h);
+        if (st != PBA_OK) return st;
+        std::memset(out, 0, sizeof(*out));
+        out->level = level;
+        out->n_active = (int64_t)std::llround(h[2]);
+        out->energy = h[0];
+        out->sq = h[1];
+        out->rmse = out->n_active > 0 ? std::sqrt(h[1] / (double)out->n_active) : 0.0;
+        return PBA_OK;
+    }
     // relative poses at the current parameters go to the buffer the next iteration reads
     double *geo = c.flip ? c.d_geo_b : c.d_geo_a;
     if (c.eval_cap < sum_stats_doubles(c)) {
@@ -1394,7 +1557,22 @@ pba_status pba_solve(pba_ctx *ctx, int32_t max_iters_per_level, double conv_px, 
     if ((st = ready(ctx)) != PBA_OK) return st;
     pba_result res;
     std::memset(&res, 0, sizeof(res));
-    if ((st = solve_batch(c, max_iters_per_level, conv_px, res)) != PBA_OK) return st;
+    if (ctx->aff.on) {
+        // coarse to fine, one synchronized iteration at a time
+        std::vector<pba_iter_stats> its((size_t)max_iters_per_level);
+        for (int level = c.cfg.n_levels - 1; level >= 0; --level) {
+            if ((st = do_start_level(c, level)) != PBA_OK) return st;
+            int k = 0;
+            st = aff_run(c, ctx->aff, level, max_iters_per_level, conv_px, its.data(), &k);
+            for (int i = 0; i < k; ++i) res.active_residuals += its[(size_t)i].n_active;
+            res.iters[level] = k;
+            res.total_iters += k;
+            if (st != PBA_OK) return st;
+            if (level == 0) res.converged = (k > 0 && its[(size_t)k - 1].max_disp_px < conv_px) ? 1 : 0;
+        }
+    } else if ((st = solve_batch(c, max_iters_per_level, conv_px, res)) != PBA_OK) {
+        return st;
+    }
     pba_iter_stats ev;
     if ((st = pba_evaluate(ctx, 0, &ev)) != PBA_OK) return st;
     res.final_energy = ev.energy;
@@ -1483,6 +1661,40 @@ pba_status pba_drop_frame(pba_ctx *ctx, int32_t window, int32_t frame) {
         c.cur_level = -1;
         return fail(&c, PBA_E_NUMERIC, "reduced pose system is not positive definite");
     }
+    return PBA_OK;
+}
+
+pba_status pba_set_affine(pba_ctx *ctx, const double *ab) {
+    if (!ctx) return fail(nullptr, PBA_E_INVALID, "ctx is NULL");
+    Ctx &c = ctx->c;
+    if (!ab) {
+        ctx->aff.on = false;
+        return PBA_OK;
+    }
+    pba_status st;
+    if ((st = ready(ctx)) != PBA_OK) return st;
+    const std::string why = aff_check(c);
+    if (!why.empty()) return fail(&c, PBA_E_INVALID, why);
+    if (!finite_all(ab, 2 * (size_t)c.F)) return fail(&c, PBA_E_INVALID, "brightness parameters not finite");
+    if ((st = aff_ensure(c, ctx->aff)) != PBA_OK) return st;
+    HIPCHK(hipMemcpyAsync(ctx->aff.ab, ab, 2 * (size_t)c.F * sizeof(double), hipMemcpyHostToDevice, c.stream));
+    HIPCHK(hipStreamSynchronize(c.stream));
+    ctx->aff.on = true;
+    return PBA_OK;
+}
+
+pba_status pba_get_affine(pba_ctx *ctx, double *ab) {
+    if (!ctx) return fail(nullptr, PBA_E_INVALID, "ctx is NULL");
+    Ctx &c = ctx->c;
+    if (!ab) return fail(&c, PBA_E_INVALID, "ab is NULL");
+    if (!c.have_frames) return fail(&c, PBA_E_STATE, "pba_set_frames must be called first");
+    const size_t n = 2 * (size_t)c.F;
+    if (!ctx->aff.ab || ctx->aff.F != c.F) {
+        std::fill(ab, ab + n, 0.0);
+        return PBA_OK;
+    }
+    HIPCHK(hipMemcpyAsync(ab, ctx->aff.ab, n * sizeof(double), hipMemcpyDeviceToHost, c.stream));
+    HIPCHK(hipStreamSynchronize(c.stream));
     return PBA_OK;
 }
 

@@ -3,6 +3,7 @@
 // and trailing products run on FP64 MFMA (v_mfma_f64_16x16x4), the inverse of
 // every diagonal factor tile, and tile-blocked triangular solves built on them.
 #include "pba_device.hpp"
+#include "pba_affine.hpp"
 #include "pba_internal.hpp"
 #include "pba_tile.hpp"
 
@@ -633,6 +634,14 @@ __global__ void k_noalloc_begin(int n, const double *__restrict__ S, double *__r
 
 __global__ void k_noalloc_info(const int *__restrict__ flag, int *__restrict__ info) {
     if (threadIdx.x == 0) *info = *flag ? 1 : 0;
+}
+
+void launch_dense_solve(hipStream_t s, int n, const double *M, double *fac, double *Linv, const double *b, double *x,
+                        int *flag) {
+    const size_t nn = (size_t)n * n;
+    k_noalloc_begin<<<(unsigned)std::min<size_t>(1024, (nn + 255) / 256), 256, 0, s>>>(n, M, fac, flag, flag + 1);
+    tchol_ptrs(s, n, M, fac, Linv, flag, flag + 1);
+    tsolve_ptrs(s, n, fac, Linv, b, x, flag);
 }
 
 }  // namespace pba

@@ -129,6 +129,8 @@ _sig = {
     "pba_get_params": (C.c_int, [_P, C.c_int32, _P, _P]),
     "pba_set_params": (C.c_int, [_P, C.c_int32, _P, _P]),
     "pba_drop_frame": (C.c_int, [_P, C.c_int32, C.c_int32]),
+    "pba_set_affine": (C.c_int, [_P, _P]),
+    "pba_get_affine": (C.c_int, [_P, _P]),
     "pba_fe_corners": (C.c_int, [_P, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_int64, C.c_int32, _P, _P,
                                  C.POINTER(C.c_int32)]),
     "pba_fe_track": (C.c_int, [_P, C.c_int32, C.c_int32, _P, _P, _P, _P, C.c_int32, C.c_int32, C.c_double,
@@ -285,6 +287,20 @@ class Solver:
 
     def drop_frame(self, frame, window=0):
         self._chk(pba_drop_frame(self.ctx, window, frame))
+
+    def set_affine(self, ab):
+        """Per-frame brightness (a_f, b_f) [F, 2]; turns the brightness model
+        on for iterate / solve / evaluate. None turns it off."""
+        if ab is None:
+            self._chk(pba_set_affine(self.ctx, None))
+            return
+        ab = np.ascontiguousarray(ab, np.float64).reshape(-1, 2)
+        self._chk(pba_set_affine(self.ctx, _ptr(ab)))
+
+    def get_affine(self):
+        ab = np.zeros((self.Fw[0], 2))
+        self._chk(pba_get_affine(self.ctx, _ptr(ab)))
+        return ab
 
     # ---- front end (corners, tracks, geometric bundle adjustment)
 

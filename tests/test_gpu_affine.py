@@ -1,0 +1,173 @@
+"""GPU parity of the per-frame affine brightness model in the FC iteration
+(pba_set_affine) against the FP64 oracle (oracle/affine.py) on brightened
+scenes, through the C ABI.
+
+Tolerances: one iteration from a common state in FP64 agrees to rounding
+(1e-10 on poses and brightness, 1e-9 relative on inverse depths); over several
+iterations the rounding is amplified by the joint system's condition number,
+as in the plain FC parity tests (1e-7). FP32 images and templates against the
+FP64 oracle: 1e-5, the measurement contract's bar.
+"""
+import dataclasses
+
+import numpy as np
+import pytest
+
+import scenes
+from oracle import affine as AF
+from oracle.gn import Problem
+from scenes.brightness import brighten, seeded_ab
+from scenes.planar import planar
+
+pytestmark = pytest.mark.gpu
+
+pba = pytest.importorskip("paper_1704_06967_amd.pba")
+
+
+def brightened(sc, seed):
+    """The scene rendered with seeded per-frame brightness, starting from the
+    true geometry with the brightness unknown (a = b = 0)."""
+    ab = seeded_ab(sc.n_frames, seed)
+    return dataclasses.replace(sc, images=brighten(sc.images, ab), poses_init=sc.poses_gt.copy(),
+                               inv_depth_init=sc.inv_depth_gt.copy()), ab
+
+
+def make(sc, precision=0):
+    s = pba.Solver(mode=pba.PBA_FC, precision=precision, n_levels=sc.n_levels, pattern=sc.pattern,
+                   huber_k=sc.huber_k)
+    s.set_scene(sc)
+    s.set_affine(np.zeros((sc.n_frames, 2)))
+    return s
+
+
+@pytest.fixture(scope="module")
+def tiny_b():
+    return brightened(scenes.tiny(), 6)
+
+
+def planar2():
+    # two levels; on this affine-in-pixels scene brightness and geometry trade
+    # off (the brightness found is not the rendered one), parity still holds
+    return brightened(planar(n_levels=2, n_frames=4), 5)
+
+
+def _check_stats(st, ref, rtol):
+    assert st["n_active"] == ref["n_active"]
+    np.testing.assert_allclose(st["energy"], ref["energy"], rtol=rtol)
+    np.testing.assert_allclose(st["sq"], ref["sq"], rtol=rtol)
+
+
+@pytest.mark.parametrize("case, level", [("tiny", 0), ("planar", 1), ("planar", 0)])
+def test_affine_one_iteration_fp64(tiny_b, case, level):
+    sc, _ = tiny_b if case == "tiny" else planar2()
+    s = make(sc)
+    st = s.iterate(level, 1)[0]
+    gn = AF.AffineFC(Problem.from_scene(sc))
+    ref = gn.iterate(level, 1)[0]
+    _check_stats(st, ref, 1e-11)
+    poses, d = s.get_params()
+    np.testing.assert_allclose(poses, gn.poses, atol=1e-10)
+    np.testing.assert_allclose(d, gn.d, rtol=1e-9)
+    np.testing.assert_allclose(s.get_affine(), gn.ab, atol=1e-10)
+    np.testing.assert_allclose(st["max_disp_px"], ref["max_disp_px"], rtol=1e-7, atol=1e-9)
+    np.testing.assert_allclose(st["max_step_pose"], ref["step_pose"], rtol=1e-7, atol=1e-12)
+    np.testing.assert_allclose(st["max_step_depth"], ref["step_depth"], rtol=1e-7, atol=1e-12)
+
+
+def test_affine_iterations_track_oracle_fp64(tiny_b):
+    sc, ab_true = tiny_b
+    s = make(sc)
+    gn = AF.AffineFC(Problem.from_scene(sc))
+    for k in range(8):
+        st = s.iterate(0, 1)[0]
+        ref = gn.iterate(0, 1)[0]
+        _check_stats(st, ref, 1e-7)
+        poses, d = s.get_params()
+        np.testing.assert_allclose(poses, gn.poses, atol=1e-7)
+        np.testing.assert_allclose(d, gn.d, rtol=1e-7, atol=1e-9)
+        np.testing.assert_allclose(s.get_affine(), gn.ab, atol=1e-7)
+    # and the brightness found is the one the images were rendered with
+    assert np.abs(s.get_affine() - ab_true).max() < 2e-2
+    ev = s.evaluate(0)
+    r, valid, _, _, _ = AF.affine_residuals(gn.prob, gn.prob.layout(0), gn.poses, gn.d, gn.ab)
+    assert ev["n_active"] == int(valid.sum())
+    np.testing.assert_allclose(ev["sq"], float(np.sum(r[valid] ** 2)), rtol=1e-6)
+
+
+def test_affine_mid_small_one_iteration_fp64():
+    # 30 frames: the 240 x 240 joint system spans 8 tiles of the tiled
+    # Cholesky, the last one ragged (240 = 7 x 32 + 16)
+    sc, _ = brightened(scenes.mid(n_per_host=300), 8)
+    s = make(sc)
+    st = s.iterate(0, 1)[0]
+    gn = AF.AffineFC(Problem.from_scene(sc))
+    ref = gn.iterate(0, 1)[0]
+    _check_stats(st, ref, 1e-10)
+    poses, d = s.get_params()
+    np.testing.assert_allclose(poses, gn.poses, atol=1e-9)
+    np.testing.assert_allclose(d, gn.d, rtol=1e-8, atol=1e-10)
+    np.testing.assert_allclose(s.get_affine(), gn.ab, atol=1e-9)
+
+
+def test_affine_solve_planar_matches_oracle():
+    # coarse-to-fine solve: the same iteration counts per level as the oracle
+    # (6 at level 1, 3 at level 0 on this problem) and the same result
+    sc, _ = planar2()
+    s = make(sc)
+    res, status = s.solve(12, 1e-5)
+    gn = AF.AffineFC(Problem.from_scene(sc))
+    iters = gn.solve(12, 1e-5)
+    assert [res.iters[lv] for lv in reversed(range(sc.n_levels))] == iters
+    assert status == pba.PBA_OK and res.converged == 1
+    poses, d = s.get_params()
+    np.testing.assert_allclose(poses, gn.poses, atol=1e-8)
+    np.testing.assert_allclose(d, gn.d, rtol=1e-8)
+    np.testing.assert_allclose(s.get_affine(), gn.ab, atol=1e-8)
+
+
+def test_affine_one_iteration_fp32(tiny_b):
+    sc, _ = tiny_b
+    s = make(sc, precision=1)
+    st = s.iterate(0, 1)[0]
+    gn = AF.AffineFC(Problem.from_scene(sc))
+    ref = gn.iterate(0, 1)[0]
+    assert abs(st["n_active"] - ref["n_active"]) <= 2
+    np.testing.assert_allclose(st["sq"], ref["sq"], rtol=1e-4)
+    poses, d = s.get_params()
+    np.testing.assert_allclose(poses, gn.poses, atol=1e-5)
+    np.testing.assert_allclose(d, gn.d, rtol=1e-5)
+    np.testing.assert_allclose(s.get_affine(), gn.ab, atol=1e-5)
+
+
+def test_affine_off_restores_the_plain_iteration(tiny_b):
+    # the model off again: iterations are the plain FC ones, brightness kept
+    sc, _ = tiny_b
+    a = make(sc)
+    a.iterate(0, 1)
+    kept = a.get_affine()
+    a.set_affine(None)
+    poses, d = a.get_params()
+    a.set_params(poses, d)   # the level starts again at these parameters
+    b = pba.Solver(mode=pba.PBA_FC, precision=0, n_levels=sc.n_levels, pattern=sc.pattern, huber_k=sc.huber_k)
+    b.set_scene(sc, poses=poses, inv_depth=d)
+    sa = a.iterate(0, 2)
+    sb = b.iterate(0, 2)
+    for x, y in zip(sa, sb):
+        assert x["n_active"] == y["n_active"]
+        np.testing.assert_allclose(x["energy"], y["energy"], rtol=1e-12)
+    np.testing.assert_allclose(a.get_params()[0], b.get_params()[0], atol=1e-12)
+    np.testing.assert_array_equal(a.get_affine(), kept)
+
+
+def test_affine_rejects_ic_and_mixed(tiny_b):
+    sc, _ = tiny_b
+    for mode, prec in ((pba.PBA_IC_PROXY, 0), (pba.PBA_FC, 2)):
+        s = pba.Solver(mode=mode, precision=prec, n_levels=sc.n_levels, pattern=sc.pattern, huber_k=sc.huber_k)
+        s.set_scene(sc)
+        with pytest.raises(pba.PbaError):
+            s.set_affine(np.zeros((sc.n_frames, 2)))
+    s = make(sc)
+    bad = np.zeros((sc.n_frames, 2))
+    bad[1, 0] = np.nan
+    with pytest.raises(pba.PbaError):
+        s.set_affine(bad)
