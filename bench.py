@@ -340,6 +340,72 @@ def dynamic_section(pba, scene, reps=10, frame=13):
                     "again from the records at p(0) instead of linearizing every residual"}
 
 
+def aff_linearize_bytes(scene, level=0, real=4):
+    """Algorithmic bytes of one launch of the joint (brightness) linearization:
+    per observation its point and pair indices, window flag and frozen-set
+    mask, its FC record (38 values) and brightness record (42 values, FP64)
+    written; per observed point its pixel, depth and template (P x 4 values);
+    per pair its geometry (12 doubles), level intrinsics (8 doubles) and the
+    brightness of its two frames (4 doubles); the 4 x 4 texel footprints of
+    the interpolated gradients once."""
+    O = scene.n_obs
+    P = scene.pattern.shape[0]
+    n_obs_pts = int(np.count_nonzero(np.diff(scene.obs_ptr)))
+    n_pairs, _ = _pairs(scene)
+    texels = _unique_texels(scene, level, 1)
+    reads = O * (4 + 4 + 1 + 1) + n_obs_pts * (8 + 8 + P * 4 * real) + n_pairs * (12 + 8 + 4) * 8 + texels * real
+    writes = O * (38 + 42) * 8
+    return {"bytes": int(reads + writes), "reads": int(reads), "writes": int(writes), "unique_texels": int(texels),
+            "observations": O}
+
+
+def affine_section(pba, scene, iters=10, reps=3):
+    """Per-frame affine brightness in the FC iteration on the mid workload
+    rendered with seeded brightness (FP32 images, FP64 system), from the true
+    geometry with the brightness unknown: host wall time of one synchronized
+    joint iteration at level 0 (median over `reps` runs of `iters`), the plain
+    FC iteration on the same images beside it, and the joint linearization's
+    launch time (HIP events) against its algorithmic bytes."""
+    import dataclasses
+    from scenes.brightness import brighten, seeded_ab
+    ab = seeded_ab(scene.n_frames, 11)
+    sc = dataclasses.replace(scene, images=brighten(scene.images, ab), poses_init=scene.poses_gt,
+                             inv_depth_init=scene.inv_depth_gt)
+    kw = dict(mode=pba.PBA_FC, precision=pba.PBA_FP32, n_levels=sc.n_levels, pattern=sc.pattern,
+              huber_k=sc.huber_k, flags=pba.PBA_FLAG_TIMING)
+    aff_ms, fc_ms, lin_ms, lin_n, rmse = [], [], 0.0, 0, None
+    for _ in range(reps):
+        s = pba.Solver(**kw)
+        s.set_scene(sc)
+        s.set_affine(np.zeros((sc.n_frames, 2)))
+        s.iterate(0, 1)                      # level start, frozen set
+        t0 = time.perf_counter()
+        st = s.iterate(0, iters)
+        aff_ms.append((time.perf_counter() - t0) * 1e3 / iters)
+        tm = s.timing()
+        lin_ms, lin_n = tm["residual_ms"][0], tm["residual_launches"][0]
+        ab_err = float(np.abs(s.get_affine() - ab).max())
+        rmse = st[-1]["rmse"]
+        s.close()
+        p = pba.Solver(**kw)
+        p.set_scene(sc)
+        p.iterate(0, 1)
+        t0 = time.perf_counter()
+        sp = p.iterate(0, iters)
+        fc_ms.append((time.perf_counter() - t0) * 1e3 / iters)
+        plain_rmse = sp[-1]["rmse"]
+        p.close()
+    avg = lin_ms / max(1, lin_n)
+    return {"workload": f"mid rendered with per-frame brightness (|a| <= 0.15, |b| <= 0.05), FC FP32 at level 0, "
+                        f"{iters} iterations from the true geometry",
+            "ms_per_joint_iteration": round(float(np.median(aff_ms)), 4),
+            "ms_per_plain_fc_iteration": round(float(np.median(fc_ms)), 4),
+            "rmse_after": rmse, "plain_fc_rmse_after": plain_rmse, "brightness_max_err": ab_err,
+            "roofline": roofline_obj("k_aff_linearize", aff_linearize_bytes(sc), avg, lin_n),
+            "note": "joint iterations are host-synchronized one at a time; the plain FC iterations run as one "
+                    "enqueued batch"}
+
+
 def _predicted_positions(scene, poses, inv_depth):
     """Level-0 pixel of every observation's point centre in its target frame
     under the given parameters (the tracker's prediction)."""
@@ -794,6 +860,7 @@ def main():
                     help="skip the precision workload's comparison with the FP64 oracle")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-windows section")
     ap.add_argument("--no-frontend", action="store_true", help="skip the front-end (base solution) section")
+    ap.add_argument("--no-affine", action="store_true", help="skip the affine-brightness section")
     ap.add_argument("--windows", type=int, default=64, help="windows of the batched section")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-preconditioner section")
     ap.add_argument("--train-systems", type=int, default=2000, help="reduced systems harvested for training")
@@ -943,6 +1010,10 @@ def main():
     t0 = time.perf_counter()
     line["dynamic_hessian"] = dynamic_section(pba, scene)
     log(f"keyframe drop: {line['dynamic_hessian']} ({time.perf_counter() - t0:.1f} s)")
+    if not args.no_affine:
+        t0 = time.perf_counter()
+        line["affine_brightness"] = affine_section(pba, scene)
+        log(f"affine brightness: {time.perf_counter() - t0:.1f} s: {line['affine_brightness']}")
     if not args.no_frontend:
         t0 = time.perf_counter()
         line["frontend"] = frontend_section(pba, scene)

@@ -111,6 +111,7 @@ typedef struct {
                             they are solved together: one launch per step over all
                             windows, a block-diagonal reduced system */
     int32_t flags;       /* PBA_FLAG_TIMING: time the per-iteration residual kernel
+                            (with pba_set_affine: the joint linearization)
                             with HIP events (read with pba_get_timing; not recorded
                             while PBA_FLAG_GRAPH replays a graph).
                             PBA_FLAG_GRAPH: pba_solve captures its whole coarse-to-fine

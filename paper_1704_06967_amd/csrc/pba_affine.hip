@@ -15,12 +15,14 @@
 // Schur complement as before) and its brightness record (pose-brightness and
 // brightness-brightness blocks, the brightness-depth coupling and gradient);
 // then the 8F x 8F reduced system: the pose block from the FC assembly, the
-// rest added per point (its direct blocks and its Schur terms; FP64 atomic
-// adds, so these sums are not bitwise reproducible between runs), the
-// brightness damping (damping_rel times the mean of the brightness diagonal)
-// and the pin (the pinned frame's 8 rows); the tiled Cholesky solve; the
+// rest summed in LDS per host chunk (a host frame's points: their direct
+// blocks and their Schur terms) and added once per chunk (FP64 atomic adds,
+// so these sums are not bitwise reproducible between runs), the brightness
+// damping (damping_rel times the mean of the brightness diagonal) and the pin
+// (the pinned frame's 8 rows); the tiled Cholesky solve; the
 // pose, brightness and depth updates and the convergence measure. All
 // arithmetic in FP64 (the images and templates in the context's type).
+#include <algorithm>
 #include <climits>
 
 #include "pba_device.hpp"
@@ -136,114 +138,240 @@ __global__ __launch_bounds__(256) void k_aff_linearize(AffArgs<T> a, int mode) {
     }
 }
 
-// The reduced system's rows and columns beyond the pose block, and the whole
-// right-hand side, added per point (one thread each): the point's direct
-// pose-brightness and brightness-brightness blocks and gradients, mapped to
-// absolute coordinates, then its Schur terms over its frames (host and
-// targets), u_i u_j^T / H_dd and u_i g_d / H_dd, with u the point's coupling
-// to each frame's pose (A^T h or the sum of B^T h) and brightness. The
-// pose-pose block and its Schur terms come from the FC assembly.
-__global__ __launch_bounds__(256) void k_aff_points(int N, int F, const int *__restrict__ obs_ptr,
-                                                    const int *__restrict__ obs_pair,
-                                                    const int *__restrict__ pair_host,
-                                                    const int *__restrict__ pair_target,
-                                                    const double *__restrict__ geo, const double *__restrict__ rec,
-                                                    const double *__restrict__ arec, const double *__restrict__ Hdd,
-                                                    const double *__restrict__ gdn, double *__restrict__ M,
-                                                    double *__restrict__ b, double *__restrict__ diag_phi) {
-    const int n = blockIdx.x * blockDim.x + threadIdx.x;
-    if (n >= N) return;
-    const int o0 = obs_ptr[n], o1 = obs_ptr[n + 1];
-    if (o1 <= o0) return;
-    const int n8 = 8 * F, F6 = 6 * F;
-    const double iH = 1.0 / Hdd[n], gd = gdn[n];
-    const int h = pair_host[obs_pair[o0]];
-    double uth[6] = {0, 0, 0, 0, 0, 0}, uph[2] = {0.0, 0.0};
-    for (int o = o0; o < o1; ++o) {
-        const int p = obs_pair[o], f = pair_target[p];
-        const double *gm = geo + GEO_STRIDE * p;
-        const double *rc = rec + (size_t)o * REC_STRIDE, *ar = arec + (size_t)o * AFF_STRIDE;
-        double tb[6], ta[6];
-        apply_Bt(gm, rc + REC_h, tb);
-        for (int i = 0; i < 6; ++i) uth[i] += tb[i];
-        uph[0] += ar[AFF_h];
-        uph[1] += ar[AFF_h + 1];
-        // direct pose-brightness blocks (columns a_h, b_h, a_f, b_f)
-        int col[4] = {F6 + 2 * h, F6 + 2 * h + 1, F6 + 2 * f, F6 + 2 * f + 1};
-        for (int k = 0; k < 4; ++k) {
-            double c[6];
-            for (int i = 0; i < 6; ++i) c[i] = ar[AFF_C + 4 * i + k];
-            apply_At(gm, c, ta);
-            apply_Bt(gm, c, tb);
-            for (int i = 0; i < 6; ++i) {
-                atomicAdd(M + (size_t)(6 * f + i) * n8 + col[k], ta[i]);
-                atomicAdd(M + (size_t)col[k] * n8 + 6 * f + i, ta[i]);
-                atomicAdd(M + (size_t)(6 * h + i) * n8 + col[k], tb[i]);
-                atomicAdd(M + (size_t)col[k] * n8 + 6 * h + i, tb[i]);
-            }
-        }
-        // direct brightness-brightness block
-        int t = 0;
-        for (int i = 0; i < 4; ++i)
-            for (int k = i; k < 4; ++k, ++t) {
-                const double v = ar[AFF_P + t];
-                atomicAdd(M + (size_t)col[i] * n8 + col[k], v);
-                if (i != k)
-                    atomicAdd(M + (size_t)col[k] * n8 + col[i], v);
-                else
-                    atomicAdd(diag_phi + (col[i] - F6), v);
-            }
-        // gradients
-        apply_At(gm, rc + REC_G, ta);
-        apply_Bt(gm, rc + REC_G, tb);
-        for (int i = 0; i < 6; ++i) {
-            atomicAdd(b + 6 * f + i, ta[i]);
-            atomicAdd(b + 6 * h + i, tb[i]);
-        }
-        for (int k = 0; k < 4; ++k) atomicAdd(b + col[k], ar[AFF_G + k]);
+constexpr int AFF_EMAX = MAX_HOST_TARGETS + 1;
+constexpr int AFF_LDS_MAX = 65536;   // bytes of dynamic LDS per workgroup
+constexpr int AFF_GROUP = 32;        // lanes per point in k_aff_schur (two points per wavefront)
+constexpr int AFF_DIRECT = 44;       // values summed per pair: C (24), P (10), G_phi (4), g (6)
+static_assert(MAX_HOST_TARGETS < AFF_GROUP, "one lane per observation of a point");
+
+__device__ __forceinline__ double group_sum_d(double v) {   // over aligned groups of AFF_GROUP lanes
+#pragma unroll
+    for (int off = AFF_GROUP / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, WAVE);
+    return v;
+}
+
+// The direct terms of the brightness rows, summed per pair chunk (the
+// observations of one pair; one thread each) and added to the reduced system
+// once per chunk in absolute coordinates: the pose-brightness blocks (A^T C
+// for the target's pose, B^T C for the host's), the brightness-brightness
+// block, the brightness gradients and the pose gradients (A^T g, B^T g).
+__global__ __launch_bounds__(PAIR_CHUNK) void k_aff_pairs(int F, const int *__restrict__ pchunk_begin,
+                                                          const int *__restrict__ pchunk_end,
+                                                          const int *__restrict__ pair_obs_idx,
+                                                          const int *__restrict__ obs_pair,
+                                                          const int *__restrict__ pair_host,
+                                                          const int *__restrict__ pair_target,
+                                                          const double *__restrict__ geo,
+                                                          const double *__restrict__ rec,
+                                                          const double *__restrict__ arec, double *__restrict__ M,
+                                                          double *__restrict__ b, double *__restrict__ diag_phi) {
+    __shared__ double part[PAIR_CHUNK / WAVE][AFF_DIRECT];
+    __shared__ double tot[AFF_DIRECT];
+    const int k0 = pchunk_begin[blockIdx.x], k1 = pchunk_end[blockIdx.x];
+    const int idx = k0 + (int)threadIdx.x;
+    double v[AFF_DIRECT];
+    if (idx < k1) {
+        const int o = pair_obs_idx[idx];
+        const double *ar = arec + (size_t)o * AFF_STRIDE, *rc = rec + (size_t)o * REC_STRIDE;
+#pragma unroll
+        for (int i = 0; i < 34; ++i) v[i] = ar[AFF_C + i];   // C and P are contiguous
+#pragma unroll
+        for (int i = 0; i < 4; ++i) v[34 + i] = ar[AFF_G + i];
+#pragma unroll
+        for (int i = 0; i < 6; ++i) v[38 + i] = rc[REC_G + i];
+    } else {
+#pragma unroll
+        for (int i = 0; i < AFF_DIRECT; ++i) v[i] = 0.0;
     }
-    // Schur terms over the point's frames: index 0 the host, then one per observation
-    const int m = o1 - o0;
-    for (int i = 0; i <= m; ++i) {
-        int fi;
-        double ti[6], pi[2];
-        if (i == 0) {
-            fi = h;
-            for (int k = 0; k < 6; ++k) ti[k] = uth[k];
-            pi[0] = uph[0];
-            pi[1] = uph[1];
-        } else {
-            const int o = o0 + i - 1, p = obs_pair[o];
-            fi = pair_target[p];
-            apply_At(geo + GEO_STRIDE * p, rec + (size_t)o * REC_STRIDE + REC_h, ti);
-            pi[0] = arec[(size_t)o * AFF_STRIDE + AFF_h + 2];
-            pi[1] = arec[(size_t)o * AFF_STRIDE + AFF_h + 3];
+    const int w = threadIdx.x / WAVE, lane = threadIdx.x % WAVE;
+#pragma unroll
+    for (int i = 0; i < AFF_DIRECT; ++i) {
+        double x = v[i];
+#pragma unroll
+        for (int off = WAVE / 2; off > 0; off >>= 1) x += __shfl_xor(x, off, WAVE);
+        if (lane == 0) part[w][i] = x;
+    }
+    __syncthreads();
+    if (threadIdx.x < AFF_DIRECT) {
+        double x = 0.0;
+        for (int q = 0; q < (int)(blockDim.x / WAVE); ++q) x += part[q][threadIdx.x];
+        tot[threadIdx.x] = x;
+    }
+    __syncthreads();
+    if (k1 <= k0) return;
+    const int p = obs_pair[pair_obs_idx[k0]], h = pair_host[p], f = pair_target[p];
+    const double *gm = geo + GEO_STRIDE * p;
+    const int F6 = 6 * F;
+    const size_t n8 = 8 * (size_t)F;
+    const int col[4] = {F6 + 2 * h, F6 + 2 * h + 1, F6 + 2 * f, F6 + 2 * f + 1};   // (a_h, b_h, a_f, b_f)
+    const int t = threadIdx.x;
+    if (t < 4) {   // column t of C: pose-brightness blocks
+        double cv[6], ta[6], tb[6];
+        for (int i = 0; i < 6; ++i) cv[i] = tot[4 * i + t];
+        apply_At(gm, cv, ta);
+        apply_Bt(gm, cv, tb);
+        for (int i = 0; i < 6; ++i) {
+            unsafeAtomicAdd(M + (size_t)col[t] * n8 + 6 * f + i, ta[i]);
+            unsafeAtomicAdd(M + (size_t)(6 * f + i) * n8 + col[t], ta[i]);
+            unsafeAtomicAdd(M + (size_t)col[t] * n8 + 6 * h + i, tb[i]);
+            unsafeAtomicAdd(M + (size_t)(6 * h + i) * n8 + col[t], tb[i]);
         }
-        for (int k = 0; k < 6; ++k) atomicAdd(b + 6 * fi + k, -ti[k] * gd * iH);
-        for (int k = 0; k < 2; ++k) atomicAdd(b + F6 + 2 * fi + k, -pi[k] * gd * iH);
-        for (int j = 0; j <= m; ++j) {
-            int fj;
-            double pj[2];
-            if (j == 0) {
-                fj = h;
-                pj[0] = uph[0];
-                pj[1] = uph[1];
-            } else {
-                const int o = o0 + j - 1;
-                fj = pair_target[obs_pair[o]];
-                pj[0] = arec[(size_t)o * AFF_STRIDE + AFF_h + 2];
-                pj[1] = arec[(size_t)o * AFF_STRIDE + AFF_h + 3];
+        unsafeAtomicAdd(b + col[t], tot[34 + t]);
+    } else if (t == 4) {   // brightness-brightness block
+        int q = 0;
+        for (int i = 0; i < 4; ++i)
+            for (int k = i; k < 4; ++k, ++q) {
+                const double x = tot[24 + q];
+                unsafeAtomicAdd(M + (size_t)col[i] * n8 + col[k], x);
+                if (i != k)
+                    unsafeAtomicAdd(M + (size_t)col[k] * n8 + col[i], x);
+                else
+                    unsafeAtomicAdd(diag_phi + (col[i] - F6), x);
             }
-            for (int k = 0; k < 6; ++k)
-                for (int l = 0; l < 2; ++l) {
-                    const double v = -ti[k] * pj[l] * iH;
-                    atomicAdd(M + (size_t)(6 * fi + k) * n8 + F6 + 2 * fj + l, v);
-                    atomicAdd(M + (size_t)(F6 + 2 * fj + l) * n8 + 6 * fi + k, v);
-                }
-            for (int k = 0; k < 2; ++k)
-                for (int l = 0; l < 2; ++l)
-                    atomicAdd(M + (size_t)(F6 + 2 * fi + k) * n8 + F6 + 2 * fj + l, -pi[k] * pj[l] * iH);
+    } else if (t == 5) {   // pose gradients
+        double ta[6], tb[6];
+        apply_At(gm, tot + 38, ta);
+        apply_Bt(gm, tot + 38, tb);
+        for (int i = 0; i < 6; ++i) {
+            unsafeAtomicAdd(b + 6 * f + i, ta[i]);
+            unsafeAtomicAdd(b + 6 * h + i, tb[i]);
         }
+    }
+}
+
+// The depth Schur terms of the brightness rows and of the whole right-hand
+// side, over the points of one host chunk (points of one host frame; one
+// workgroup each): -u_i u_j^T / H_dd and -u_i g_d / H_dd over a point's frames
+// (host and targets), with u the point's coupling to a frame's pose (A^T h, or
+// the sum of B^T h for the host) and brightness. Each group of AFF_GROUP lanes
+// takes one point at a time: its lanes take the point's observations (the
+// couplings), then the entries of its Schur terms, which are distinct within
+// the group. The sums run in LDS over the host's frame set (host and its
+// targets) and are added to the global system once per chunk. The pose-pose
+// terms come from the FC assembly.
+// Dynamic LDS for frame sets of at most Emax frames and `groups` groups: BB,
+// BP, rb, rp, U (doubles), then Ue and fr (ints).
+static inline size_t aff_schur_lds(int Emax, int groups) {
+    const size_t nb = 2 * (size_t)Emax, np = 6 * (size_t)Emax;
+    return (nb * nb + nb * np + nb + np + (size_t)groups * (Emax + 1) * 8) * sizeof(double) +
+           ((size_t)groups * (Emax + 1) + Emax) * sizeof(int);
+}
+
+__global__ __launch_bounds__(1024) void k_aff_schur(
+    int F, int Emax, const int *__restrict__ chunk_host, const int *__restrict__ chunk_begin,
+    const int *__restrict__ chunk_end, const int *__restrict__ host_m, const int *__restrict__ hosts,
+    const int *__restrict__ host_pts, const int *__restrict__ obs_ptr, const int *__restrict__ obs_pair,
+    const int *__restrict__ pair_local, const int *__restrict__ pair_target, const double *__restrict__ geo,
+    const double *__restrict__ rec, const double *__restrict__ arec, const double *__restrict__ Hdd,
+    const double *__restrict__ gdn, double *__restrict__ M, double *__restrict__ b) {
+    extern __shared__ double lds[];
+    const int groups = blockDim.x / AFF_GROUP;
+    const int nbm = 2 * Emax, npm = 6 * Emax;
+    double *BB = lds;                    // brightness x brightness [nb][nb]
+    double *BP = BB + nbm * nbm;         // brightness x pose [nb][np]
+    double *rb = BP + nbm * npm, *rp = rb + nbm;
+    double *Ub = rp + npm;               // per group: t (6), p (2) per slot of its point [groups][Emax + 1][8]
+    int *Ueb = (int *)(Ub + (size_t)groups * (Emax + 1) * 8);   // frame-set index of each slot (slot 0: the host)
+    int *fr = Ueb + groups * (Emax + 1);  // frame of each frame-set index [Emax]
+    const int ch = blockIdx.x, hi = chunk_host[ch];
+    const int E = min(host_m[hi] + 1, Emax), nb = 2 * E, np = 6 * E;
+    for (int i = threadIdx.x; i < nb * nb; i += blockDim.x) BB[i] = 0.0;
+    for (int i = threadIdx.x; i < nb * np; i += blockDim.x) BP[i] = 0.0;
+    for (int i = threadIdx.x; i < np; i += blockDim.x) rp[i] = 0.0;
+    for (int i = threadIdx.x; i < nb; i += blockDim.x) rb[i] = 0.0;
+    for (int i = threadIdx.x; i < Emax; i += blockDim.x) fr[i] = i == 0 ? hosts[hi] : -1;
+    __syncthreads();
+    const int g = threadIdx.x / AFF_GROUP, lane = threadIdx.x % AFF_GROUP;
+    double(*U)[8] = (double(*)[8])(Ub + (size_t)g * (Emax + 1) * 8);
+    int *Ue = Ueb + g * (Emax + 1);
+    const int q0 = chunk_begin[ch], q1 = chunk_end[ch];
+    for (int base = q0; base < q1; base += groups) {
+        const int q = base + g;
+        int n = 0, o0 = 0, m = -1;   // m: observations of the group's point (-1: none)
+        if (q < q1) {
+            n = host_pts[q];
+            o0 = obs_ptr[n];
+            m = min(obs_ptr[n + 1] - o0, E - 1);
+        }
+        const double iH = m >= 0 ? 1.0 / Hdd[n] : 0.0, gd = m >= 0 ? gdn[n] : 0.0;
+        // lane j: observation o0 + j (slot 1 + j)
+        double tb[6] = {0, 0, 0, 0, 0, 0}, ph0 = 0.0, ph1 = 0.0;
+        if (lane < m) {
+            const int o = o0 + lane, p = obs_pair[o];
+            const int e = 1 + pair_local[p];
+            const bool in = e < E;   // (the structure keeps every host within AFF_EMAX frames)
+            if (in) fr[e] = pair_target[p];   // the same value from every writer
+            const double *gm = geo + GEO_STRIDE * p;
+            const double *hv = rec + (size_t)o * REC_STRIDE + REC_h, *ar = arec + (size_t)o * AFF_STRIDE;
+            double ta[6];
+            apply_At(gm, hv, ta);
+            apply_Bt(gm, hv, tb);
+            ph0 = ar[AFF_h];
+            ph1 = ar[AFF_h + 1];
+            for (int k = 0; k < 6; ++k) U[1 + lane][k] = ta[k];
+            U[1 + lane][6] = ar[AFF_h + 2];
+            U[1 + lane][7] = ar[AFF_h + 3];
+            Ue[1 + lane] = in ? e : -1;
+        }
+        // the host's coupling: sums over the point's observations
+        for (int k = 0; k < 6; ++k) tb[k] = group_sum_d(tb[k]);
+        ph0 = group_sum_d(ph0);
+        ph1 = group_sum_d(ph1);
+        if (lane == 0 && m >= 0) {
+            for (int k = 0; k < 6; ++k) U[0][k] = tb[k];
+            U[0][6] = ph0;
+            U[0][7] = ph1;
+            Ue[0] = 0;
+        }
+        __syncthreads();
+        // (m + 1)^2 slot pairs x 16 entries, then (m + 1) x 8 right-hand side entries
+        const int S = m + 1, nS = S * S * 16, total = nS + S * 8;
+        for (int idx = lane; idx < total; idx += AFF_GROUP) {
+            if (idx < nS) {
+                const int pr = idx >> 4, c = idx & 15, si = pr / S, sj = pr % S;
+                const int ei = Ue[si], ej = Ue[sj];
+                if (ei < 0 || ej < 0) continue;
+                if (c < 12) {
+                    const int k = c >> 1, l = c & 1;
+                    atomicAdd(BP + (2 * ej + l) * np + 6 * ei + k, -U[si][k] * U[sj][6 + l] * iH);
+                } else {
+                    const int k = (c - 12) >> 1, l = c & 1;
+                    atomicAdd(BB + (2 * ei + k) * nb + 2 * ej + l, -U[si][6 + k] * U[sj][6 + l] * iH);
+                }
+            } else {
+                const int r = idx - nS, si = r >> 3, c = r & 7, ei = Ue[si];
+                if (ei < 0) continue;
+                const double v = -U[si][c] * gd * iH;
+                if (c < 6)
+                    atomicAdd(rp + 6 * ei + c, v);
+                else
+                    atomicAdd(rb + 2 * ei + (c - 6), v);
+            }
+        }
+        __syncthreads();
+    }
+    // once per chunk into the global system (hardware FP64 atomics on device memory)
+    const int F6 = 6 * F;
+    const size_t n8 = 8 * (size_t)F;
+    for (int i = threadIdx.x; i < nb * nb; i += blockDim.x) {
+        const int r = i / nb, cc = i % nb, fa = fr[r >> 1], fb = fr[cc >> 1];
+        if (BB[i] == 0.0 || fa < 0 || fb < 0) continue;
+        unsafeAtomicAdd(M + (size_t)(F6 + 2 * fa + (r & 1)) * n8 + F6 + 2 * fb + (cc & 1), BB[i]);
+    }
+    for (int i = threadIdx.x; i < nb * np; i += blockDim.x) {
+        const int r = i / np, cc = i % np, fa = fr[r >> 1], fb = fr[cc / 6];
+        if (BP[i] == 0.0 || fa < 0 || fb < 0) continue;
+        const size_t R = F6 + 2 * fa + (r & 1), C = 6 * fb + cc % 6;
+        unsafeAtomicAdd(M + R * n8 + C, BP[i]);
+        unsafeAtomicAdd(M + C * n8 + R, BP[i]);
+    }
+    for (int i = threadIdx.x; i < nb; i += blockDim.x) {
+        const int fa = fr[i >> 1];
+        if (fa >= 0 && rb[i] != 0.0) unsafeAtomicAdd(b + F6 + 2 * fa + (i & 1), rb[i]);
+    }
+    for (int i = threadIdx.x; i < np; i += blockDim.x) {
+        const int fa = fr[i / 6];
+        if (fa >= 0 && rp[i] != 0.0) unsafeAtomicAdd(b + 6 * fa + i % 6, rp[i]);
     }
 }
 
@@ -428,10 +556,23 @@ void launch_aff_linearize(hipStream_t s, Ctx &c, const AffBufs &ab, int level, c
 void launch_aff_system(hipStream_t s, Ctx &c, const AffBufs &a, const double *geo) {
     const int F = c.F, n8 = 8 * F;
     k_aff_clear<<<nblk((size_t)n8 * n8, 256), 256, 0, s>>>(F, c.d_S, a.M, a.b, a.dphi, a.maxb);
-    if (c.N > 0)
-        k_aff_points<<<nblk(c.N, 256), 256, 0, s>>>(c.N, F, c.d_obs_ptr, c.d_obs_pair, c.d_pair_host, c.d_pair_target,
-                                                    geo, (const double *)c.d_rec, a.arec, c.d_Hdd, c.d_gd, a.M, a.b,
-                                                    a.dphi);
+    const int npc = (int)c.st.pchunk_begin.size();
+    if (npc > 0)
+        k_aff_pairs<<<npc, PAIR_CHUNK, 0, s>>>(F, c.d_pchunk_begin, c.d_pchunk_end, c.d_pair_obs_idx, c.d_obs_pair,
+                                               c.d_pair_host, c.d_pair_target, geo, (const double *)c.d_rec, a.arec,
+                                               a.M, a.b, a.dphi);
+    const int nch = (int)c.st.chunk_host.size();
+    if (nch > 0) {
+        int Emax = 1;
+        for (int m : c.st.host_m) Emax = std::max(Emax, std::min(m + 1, AFF_EMAX));
+        // as many groups (points in flight) as the LDS allows, 32 at most
+        int groups = 32;
+        while (groups > 1 && aff_schur_lds(Emax, groups) > AFF_LDS_MAX) groups /= 2;
+        k_aff_schur<<<nch, groups * AFF_GROUP, aff_schur_lds(Emax, groups), s>>>(
+            F, Emax, c.d_chunk_host, c.d_chunk_begin, c.d_chunk_end, c.d_host_m, c.d_host_frames, c.d_host_pts,
+            c.d_obs_ptr, c.d_obs_pair, c.d_pair_local, c.d_pair_target, geo, (const double *)c.d_rec, a.arec,
+            c.d_Hdd, c.d_gd, a.M, a.b);
+    }
     k_aff_finish<<<1, 256, 0, s>>>(F, c.cfg.pinned_frame, c.cfg.damping_rel, a.M, a.b, a.dphi);
 }
 

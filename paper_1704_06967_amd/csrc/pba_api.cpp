@@ -1186,7 +1186,13 @@ template <typename T>
 pba_status aff_iteration(Ctx &c, AffBufs &a, int level, pba_iter_stats *out) {
     hipStream_t s = c.stream;
     double *geo = c.d_geo_a;
+    // PBA_FLAG_TIMING: HIP events around the linearization (the residual kernel)
+    const bool timing = (c.cfg.flags & PBA_FLAG_TIMING) != 0;
+    pba_status st;
+    if (timing && (st = ensure_events(c, 2)) != PBA_OK) return st;
+    if (timing) HIPCHK(hipEventRecord(c.ev_pool[0], s));
     launch_aff_linearize(s, c, a, level, geo, c.iters_in_level == 0 ? 1 : 0);
+    if (timing) HIPCHK(hipEventRecord(c.ev_pool[1], s));
     Launch<T>::point_reduce(s, c, true);
     Launch<T>::pair_reduce_H(s, c);
     launch_mu(s, c, geo);
@@ -1212,6 +1218,13 @@ pba_status aff_iteration(Ctx &c, AffBufs &a, int level, pba_iter_stats *out) {
     HIPCHK(hipStreamSynchronize(s));
     HIPCHK(hipGetLastError());
     c.s_valid = false;   // d_S holds the pose block only
+    if (timing) {
+        float ms = 0.f;
+        HIPCHK(hipEventElapsedTime(&ms, c.ev_pool[0], c.ev_pool[1]));
+        c.t_ms[level] += ms;
+        c.t_launches[level]++;
+        c.t_res[level] += (int64_t)c.O * LANES_PER_OBS;
+    }
     if (flag) return fail(&c, PBA_E_NUMERIC, "joint pose-brightness system is not positive definite");
     double mp = 0.0;
     for (int i = 0; i < 6 * c.F; ++i) mp = std::max(mp, std::fabs(x[(size_t)i]));
