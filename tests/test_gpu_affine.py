@@ -171,3 +171,35 @@ def test_affine_rejects_ic_and_mixed(tiny_b):
     bad[1, 0] = np.nan
     with pytest.raises(pba.PbaError):
         s.set_affine(bad)
+
+
+def test_affine_mid_full_first_records_fp32():
+    # the bench's workload and configuration (mid, 120000 observations, FP32
+    # images, level 0): every observation's FC record of the first joint
+    # iteration (gain-scaled geometry rows), the frozen mask and the iteration
+    # statistics against the oracle's rows at the same start. The FP32
+    # templates carry ~2e-6 of rounding into r, hence 1e-5 of each field's
+    # largest magnitude.
+    from oracle import residuals as RS
+    from tests.oracle_refs import obs_records
+    sc, _ = brightened(scenes.mid(), 11)
+    s = make(sc, precision=1)
+    st = s.iterate(0, 1)[0]
+    P = Problem.from_scene(sc)
+    L = P.layout(0)
+    ab0 = np.zeros((sc.n_frames, 2))
+    r, act, q, If, g = AF.affine_residuals(P, L, sc.poses_init, sc.inv_depth_init, ab0)
+    r = np.where(act, r, 0.0)
+    w = RS.huber_weight(r, sc.huber_k) * act
+    Jg, _ = AF.affine_jacobian(P, L, sc.poses_init, sc.inv_depth_init, ab0, q, If, g)
+    Jg[~act] = 0.0
+    ref = obs_records(L, Jg, w, r, act, sc.huber_k)
+    rec = s.fetch(pba.PBA_DBG_OBS_REC)
+    scale = np.abs(ref).max(0) + 1e-30
+    np.testing.assert_allclose(rec[:, :38] / scale[:38], ref[:, :38] / scale[:38], atol=1e-5)
+    mask = s.fetch(pba.PBA_DBG_MASK)
+    ref_mask = np.zeros(L.n_obs, np.uint8)
+    np.bitwise_or.at(ref_mask, L.res_obs, (act.astype(np.uint8) << L.res_pat.astype(np.uint8)))
+    assert np.array_equal(mask, ref_mask)
+    assert st["n_active"] == int(act.sum())
+    np.testing.assert_allclose(st["sq"], float(np.sum(r * r)), rtol=1e-5)
