@@ -48,10 +48,19 @@ struct AffArgs {
 // mode 0: linearize over the frozen set; 1: decide the frozen set at these
 // parameters, then linearize; 2: statistics over the set usable at these
 // parameters only (the mask is not touched)
+// One thread per observation over its patch pixels. The two records of a
+// wavefront's 64 observations are contiguous in memory; they are staged in LDS
+// and stored by the wavefront as consecutive doubles (a thread's own stores
+// would land 320 and 336 bytes apart between lanes). A lane past the last
+// observation repeats the last one and stores nothing.
+constexpr int AFF_LIN_THREADS = 128;
+
 template <typename T>
-__global__ __launch_bounds__(256) void k_aff_linearize(AffArgs<T> a, int mode) {
-    const int o = blockIdx.x * blockDim.x + threadIdx.x;
-    if (o >= a.O) return;
+__global__ __launch_bounds__(AFF_LIN_THREADS) void k_aff_linearize(AffArgs<T> a, int mode) {
+    __shared__ double stage[AFF_LIN_THREADS / WAVE][WAVE][AFF_STRIDE];
+    const int o_raw = blockIdx.x * blockDim.x + threadIdx.x;
+    const bool has = o_raw < a.O;
+    const int o = has ? o_raw : a.O - 1;
     const int n = a.obs_point[o], p = a.obs_pair[o];
     const int h = a.pair_host[p], f = a.pair_target[p];
     const double *g = a.geo + GEO_STRIDE * p, *K = a.pcam + 8 * p;
@@ -116,26 +125,44 @@ __global__ __launch_bounds__(256) void k_aff_linearize(AffArgs<T> a, int mode) {
             gp[i] += w * Jp[i] * r;
         }
     }
-    if (mode == 1) a.mask[o] = (uint8_t)m;
-    double *rc = a.rec + (size_t)o * REC_STRIDE;
-    rc[REC_E] = E;
-    rc[REC_SQ] = SQ;
-    rc[REC_CNT] = CNT;
-    if (mode == 2) return;
-    for (int k = 0; k < 21; ++k) rc[REC_H + k] = H21[k];
+    if (mode == 1 && has) a.mask[o] = (uint8_t)m;
+    if (mode == 2) {
+        if (has) {
+            double *rc = a.rec + (size_t)o * REC_STRIDE;
+            rc[REC_E] = E;
+            rc[REC_SQ] = SQ;
+            rc[REC_CNT] = CNT;
+        }
+        return;
+    }
+    const int w = threadIdx.x / WAVE, lane = threadIdx.x % WAVE;
+    const int o_first = blockIdx.x * blockDim.x + w * WAVE;
+    const int cnt = max(0, min(WAVE, a.O - o_first));
+    double *row = stage[w][lane];
+    for (int k = 0; k < 21; ++k) row[REC_H + k] = H21[k];
     for (int k = 0; k < 6; ++k) {
-        rc[REC_h + k] = hv[k];
-        rc[REC_G + k] = gv6[k];
+        row[REC_h + k] = hv[k];
+        row[REC_G + k] = gv6[k];
     }
-    rc[REC_HDD] = hdd;
-    rc[REC_GD] = gd;
-    double *ar = a.arec + (size_t)o * AFF_STRIDE;
-    for (int k = 0; k < 24; ++k) ar[AFF_C + k] = C[k];
-    for (int k = 0; k < 10; ++k) ar[AFF_P + k] = Pp[k];
+    row[REC_HDD] = hdd;
+    row[REC_GD] = gd;
+    row[REC_E] = E;
+    row[REC_SQ] = SQ;
+    row[REC_CNT] = CNT;
+    for (int k = REC_CNT + 1; k < REC_STRIDE; ++k) row[k] = 0.0;
+    __syncthreads();
+    double *dst = a.rec + (size_t)o_first * REC_STRIDE;
+    for (int i = lane; i < cnt * REC_STRIDE; i += WAVE) dst[i] = stage[w][i / REC_STRIDE][i % REC_STRIDE];
+    __syncthreads();
+    for (int k = 0; k < 24; ++k) row[AFF_C + k] = C[k];
+    for (int k = 0; k < 10; ++k) row[AFF_P + k] = Pp[k];
     for (int k = 0; k < 4; ++k) {
-        ar[AFF_h + k] = hp[k];
-        ar[AFF_G + k] = gp[k];
+        row[AFF_h + k] = hp[k];
+        row[AFF_G + k] = gp[k];
     }
+    __syncthreads();
+    dst = a.arec + (size_t)o_first * AFF_STRIDE;
+    for (int i = lane; i < cnt * AFF_STRIDE; i += WAVE) dst[i] = stage[w][i / AFF_STRIDE][i % AFF_STRIDE];
 }
 
 constexpr int AFF_EMAX = MAX_HOST_TARGETS + 1;
@@ -548,9 +575,9 @@ static AffArgs<T> aff_args(Ctx &c, const AffBufs &ab, int level, const double *g
 void launch_aff_linearize(hipStream_t s, Ctx &c, const AffBufs &ab, int level, const double *geo, int mode) {
     if (c.O == 0) return;
     if (c.cfg.precision == PBA_FP64)
-        k_aff_linearize<double><<<nblk(c.O, 256), 256, 0, s>>>(aff_args<double>(c, ab, level, geo), mode);
+        k_aff_linearize<double><<<nblk(c.O, AFF_LIN_THREADS), AFF_LIN_THREADS, 0, s>>>(aff_args<double>(c, ab, level, geo), mode);
     else
-        k_aff_linearize<float><<<nblk(c.O, 256), 256, 0, s>>>(aff_args<float>(c, ab, level, geo), mode);
+        k_aff_linearize<float><<<nblk(c.O, AFF_LIN_THREADS), AFF_LIN_THREADS, 0, s>>>(aff_args<float>(c, ab, level, geo), mode);
 }
 
 void launch_aff_system(hipStream_t s, Ctx &c, const AffBufs &a, const double *geo) {
