@@ -98,6 +98,8 @@ def test_null_arguments():
     assert pba.pba_iterate(None, 0, 1, None) == pba.PBA_E_INVALID
     assert pba.pba_set_frames(None, 0, 1, 8, 8, None, None, None, 0) == pba.PBA_E_INVALID
     assert pba.pba_evaluate(None, 0, None) == pba.PBA_E_INVALID
+    assert pba.pba_set_affine(None, None) == pba.PBA_E_INVALID
+    assert pba.pba_get_affine(None, None) == pba.PBA_E_INVALID
     pba.pba_destroy(None)
 
 
