@@ -362,8 +362,8 @@ def aff_linearize_bytes(scene, level=0, real=4):
 def affine_section(pba, scene, iters=10, reps=3):
     """Per-frame affine brightness in the FC iteration on the mid workload
     rendered with seeded brightness (FP32 images, FP64 system), from the true
-    geometry with the brightness unknown: host wall time of one synchronized
-    joint iteration at level 0 (median over `reps` runs of `iters`), the plain
+    geometry with the brightness unknown: host wall time per joint iteration
+    at level 0 (median over `reps` runs of `iters`), the plain
     FC iteration on the same images beside it, and the joint linearization's
     launch time (HIP events) against its algorithmic bytes."""
     import dataclasses
@@ -402,8 +402,7 @@ def affine_section(pba, scene, iters=10, reps=3):
             "ms_per_plain_fc_iteration": round(float(np.median(fc_ms)), 4),
             "rmse_after": rmse, "plain_fc_rmse_after": plain_rmse, "brightness_max_err": ab_err,
             "roofline": roofline_obj("k_aff_linearize", aff_linearize_bytes(sc), avg, lin_n),
-            "note": "joint iterations are host-synchronized one at a time; the plain FC iterations run as one "
-                    "enqueued batch"}
+            "note": "both enqueue the iterations of a call as one batch (one host synchronization)"}
 
 
 def _predicted_positions(scene, poses, inv_depth):

@@ -15,9 +15,10 @@
 // Schur complement as before) and its brightness record (pose-brightness and
 // brightness-brightness blocks, the brightness-depth coupling and gradient);
 // then the 8F x 8F reduced system: the pose block from the FC assembly, the
-// rest summed in LDS per host chunk (a host frame's points: their direct
-// blocks and their Schur terms) and added once per chunk (FP64 atomic adds,
-// so these sums are not bitwise reproducible between runs), the brightness
+// direct terms of the brightness rows and of the right-hand side summed per
+// pair chunk, their depth Schur terms summed in LDS per host chunk, each
+// chunk's sums added once (FP64 atomic adds, so these sums are not bitwise
+// reproducible between runs), the brightness
 // damping (damping_rel times the mean of the brightness diagonal) and the pin
 // (the pinned frame's 8 rows); the tiled Cholesky solve; the
 // pose, brightness and depth updates and the convergence measure. All
@@ -43,11 +44,12 @@ struct AffArgs {
     uint8_t *mask;
     const uint8_t *live;
     double *rec, *arec;
+    const int *gate;   // 0: the level has converged or failed, skip the work (modes 0 and 1)
 };
 
-// mode 0: linearize over the frozen set; 1: decide the frozen set at these
-// parameters, then linearize; 2: statistics over the set usable at these
-// parameters only (the mask is not touched)
+// Both records of every observation. mode 0: linearize over the frozen set;
+// 1: decide the frozen set at these parameters, then linearize; 2: statistics
+// over the set usable at these parameters only (the mask is not touched).
 // One thread per observation over its patch pixels. The two records of a
 // wavefront's 64 observations are contiguous in memory; they are staged in LDS
 // and stored by the wavefront as consecutive doubles (a thread's own stores
@@ -58,6 +60,7 @@ constexpr int AFF_LIN_THREADS = 128;
 template <typename T>
 __global__ __launch_bounds__(AFF_LIN_THREADS) void k_aff_linearize(AffArgs<T> a, int mode) {
     __shared__ double stage[AFF_LIN_THREADS / WAVE][WAVE][AFF_STRIDE];
+    if (mode != 2 && *a.gate == 0) return;
     const int o_raw = blockIdx.x * blockDim.x + threadIdx.x;
     const bool has = o_raw < a.O;
     const int o = has ? o_raw : a.O - 1;
@@ -191,8 +194,10 @@ __global__ __launch_bounds__(PAIR_CHUNK) void k_aff_pairs(int F, const int *__re
                                                           const double *__restrict__ geo,
                                                           const double *__restrict__ rec,
                                                           const double *__restrict__ arec, double *__restrict__ M,
-                                                          double *__restrict__ b, double *__restrict__ diag_phi) {
+                                                          double *__restrict__ b, double *__restrict__ diag_phi,
+                                                          const int *__restrict__ gate) {
     __shared__ double part[PAIR_CHUNK / WAVE][AFF_DIRECT];
+    if (*gate == 0) return;
     __shared__ double tot[AFF_DIRECT];
     const int k0 = pchunk_begin[blockIdx.x], k1 = pchunk_end[blockIdx.x];
     const int idx = k0 + (int)threadIdx.x;
@@ -290,8 +295,9 @@ __global__ __launch_bounds__(1024) void k_aff_schur(
     const int *__restrict__ host_pts, const int *__restrict__ obs_ptr, const int *__restrict__ obs_pair,
     const int *__restrict__ pair_local, const int *__restrict__ pair_target, const double *__restrict__ geo,
     const double *__restrict__ rec, const double *__restrict__ arec, const double *__restrict__ Hdd,
-    const double *__restrict__ gdn, double *__restrict__ M, double *__restrict__ b) {
+    const double *__restrict__ gdn, double *__restrict__ M, double *__restrict__ b, const int *__restrict__ gate) {
     extern __shared__ double lds[];
+    if (*gate == 0) return;
     const int groups = blockDim.x / AFF_GROUP;
     const int nbm = 2 * Emax, npm = 6 * Emax;
     double *BB = lds;                    // brightness x brightness [nb][nb]
@@ -405,7 +411,9 @@ __global__ __launch_bounds__(1024) void k_aff_schur(
 // M <- 0 and the pose block <- the FC assembly's damped, pinned S; b, the
 // brightness diagonal and the maxima <- 0.
 __global__ void k_aff_clear(int F, const double *__restrict__ S, double *__restrict__ M, double *__restrict__ b,
-                            double *__restrict__ diag_phi, unsigned long long *__restrict__ maxb) {
+                            double *__restrict__ diag_phi, unsigned long long *__restrict__ maxb,
+                            const int *__restrict__ gate) {
+    if (*gate == 0) return;
     const int n8 = 8 * F, F6 = 6 * F;
     const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (e < (size_t)n8 * n8) {
@@ -421,7 +429,8 @@ __global__ void k_aff_clear(int F, const double *__restrict__ S, double *__restr
 // before the pin; damping_rel when that mean is 0) and the pin of frame
 // `pinned`: its 8 rows and columns become the identity, its rhs 0. One block.
 __global__ void k_aff_finish(int F, int pinned, double damping_rel, double *__restrict__ M, double *__restrict__ b,
-                             const double *__restrict__ diag_phi) {
+                             const double *__restrict__ diag_phi, const int *__restrict__ gate) {
+    if (*gate == 0) return;
     __shared__ double mu;
     const int n8 = 8 * F, F6 = 6 * F;
     if (threadIdx.x == 0) {
@@ -537,6 +546,43 @@ __global__ __launch_bounds__(256) void k_aff_depths(int N, int F, const int *__r
     atomicMax(maxb + 1, (unsigned long long)__double_as_longlong(fabs(dd)));
 }
 
+// End of a joint iteration: its statistics slot (energy, sum r^2 and count
+// at the linearization, the displacement, the largest pose and depth steps),
+// the level's iteration count, and the gate: closed after a failed solve
+// (flag 1, also raised in the context's failure flag) or, with conv_px >= 0,
+// after the first iteration whose displacement is below conv_px. One block.
+__global__ void k_aff_stat(int F, const double *__restrict__ x, const double *__restrict__ sums,
+                           const unsigned long long *__restrict__ maxb, const int *__restrict__ flag,
+                           int *__restrict__ gate, int *__restrict__ count, int *__restrict__ ctx_flag,
+                           double *__restrict__ stat, double conv_px) {
+    __shared__ double red[1024 / WAVE];
+    if (*gate == 0) return;
+    if (*flag == 1) {
+        if (threadIdx.x == 0) {
+            *ctx_flag = 1;
+            *gate = 0;
+        }
+        return;
+    }
+    double mp = 0.0;
+    for (int i = threadIdx.x; i < 6 * F; i += blockDim.x) mp = fmax(mp, fabs(x[i]));
+#pragma unroll
+    for (int off = WAVE / 2; off > 0; off >>= 1) mp = fmax(mp, __shfl_xor(mp, off, WAVE));
+    if (threadIdx.x % WAVE == 0) red[threadIdx.x / WAVE] = mp;
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    for (int w = 1; w < (int)(blockDim.x / WAVE); ++w) mp = fmax(mp, red[w]);
+    const double disp = __longlong_as_double((long long)maxb[0]);
+    stat[ST_E] = sums[0];
+    stat[ST_SQ] = sums[1];
+    stat[ST_CNT] = sums[2];
+    stat[ST_DISP] = disp;
+    stat[ST_STEP_P] = mp;
+    stat[ST_STEP_D] = __longlong_as_double((long long)maxb[1]);
+    *count += 1;
+    if (conv_px >= 0.0 && disp < conv_px) *gate = 0;
+}
+
 // ------------------------------------------------------------ launchers
 
 static inline unsigned nblk(size_t n, unsigned b) { return (unsigned)((n + b - 1) / b); }
@@ -569,6 +615,7 @@ static AffArgs<T> aff_args(Ctx &c, const AffBufs &ab, int level, const double *g
     a.live = c.d_obs_live;
     a.rec = (double *)c.d_rec;
     a.arec = ab.arec;
+    a.gate = c.d_gate;
     return a;
 }
 
@@ -582,12 +629,12 @@ void launch_aff_linearize(hipStream_t s, Ctx &c, const AffBufs &ab, int level, c
 
 void launch_aff_system(hipStream_t s, Ctx &c, const AffBufs &a, const double *geo) {
     const int F = c.F, n8 = 8 * F;
-    k_aff_clear<<<nblk((size_t)n8 * n8, 256), 256, 0, s>>>(F, c.d_S, a.M, a.b, a.dphi, a.maxb);
+    k_aff_clear<<<nblk((size_t)n8 * n8, 256), 256, 0, s>>>(F, c.d_S, a.M, a.b, a.dphi, a.maxb, c.d_gate);
     const int npc = (int)c.st.pchunk_begin.size();
     if (npc > 0)
         k_aff_pairs<<<npc, PAIR_CHUNK, 0, s>>>(F, c.d_pchunk_begin, c.d_pchunk_end, c.d_pair_obs_idx, c.d_obs_pair,
                                                c.d_pair_host, c.d_pair_target, geo, (const double *)c.d_rec, a.arec,
-                                               a.M, a.b, a.dphi);
+                                               a.M, a.b, a.dphi, c.d_gate);
     const int nch = (int)c.st.chunk_host.size();
     if (nch > 0) {
         int Emax = 1;
@@ -598,9 +645,9 @@ void launch_aff_system(hipStream_t s, Ctx &c, const AffBufs &a, const double *ge
         k_aff_schur<<<nch, groups * AFF_GROUP, aff_schur_lds(Emax, groups), s>>>(
             F, Emax, c.d_chunk_host, c.d_chunk_begin, c.d_chunk_end, c.d_host_m, c.d_host_frames, c.d_host_pts,
             c.d_obs_ptr, c.d_obs_pair, c.d_pair_local, c.d_pair_target, geo, (const double *)c.d_rec, a.arec,
-            c.d_Hdd, c.d_gd, a.M, a.b);
+            c.d_Hdd, c.d_gd, a.M, a.b, c.d_gate);
     }
-    k_aff_finish<<<1, 256, 0, s>>>(F, c.cfg.pinned_frame, c.cfg.damping_rel, a.M, a.b, a.dphi);
+    k_aff_finish<<<1, 256, 0, s>>>(F, c.cfg.pinned_frame, c.cfg.damping_rel, a.M, a.b, a.dphi, c.d_gate);
 }
 
 void launch_aff_update(hipStream_t s, Ctx &c, const AffBufs &a, const double *geo_old) {
@@ -611,6 +658,11 @@ void launch_aff_update(hipStream_t s, Ctx &c, const AffBufs &a, const double *ge
                                                     geo_old, c.d_poses, c.d_pairK0, c.d_host_uv,
                                                     (const double *)c.d_rec, a.arec, c.d_Hdd, c.d_gd, a.x, c.d_depth,
                                                     c.d_obs_live, a.maxb, a.flag);
+}
+
+void launch_aff_stat(hipStream_t s, Ctx &c, const AffBufs &a, int level, double *stat, double conv_px) {
+    k_aff_stat<<<1, 256, 0, s>>>(c.F, a.x, a.stats, a.maxb, a.flag, c.d_gate, c.d_count + level, c.d_flag, stat,
+                                 conv_px);
 }
 
 }  // namespace pba

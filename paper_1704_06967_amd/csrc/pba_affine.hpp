@@ -29,7 +29,7 @@ struct AffBufs {
     double *poses_old = nullptr;        // [F][12]
     double *stats = nullptr;            // sum_stats_doubles(c): E, SQ, CNT and block partials
     unsigned long long *maxb = nullptr; // [4] displacement, depth step (bits of non-negative doubles)
-    int *flag = nullptr;                // [2] failure flag, gate of the solve
+    int *flag = nullptr;                // [2] solve flag (0 solved, 1 not positive definite, 2 skipped), its gate
 };
 
 // mode 0: linearize over the frozen set; 1: decide the frozen set (written to
@@ -41,9 +41,13 @@ void launch_aff_linearize(hipStream_t s, Ctx &c, const AffBufs &a, int level, co
 void launch_aff_system(hipStream_t s, Ctx &c, const AffBufs &a, const double *geo);
 // pose, brightness and depth updates from a.x and the convergence maxima
 void launch_aff_update(hipStream_t s, Ctx &c, const AffBufs &a, const double *geo_old);
-// x = -M^{-1} b by the tiled Cholesky factorization (flag[0] = 0 on entry,
-// set when M is not positive definite; x is then not written)
+// x = -M^{-1} b by the tiled Cholesky factorization while `gate` is open
+// (flag[0] = 0 on entry, 1 when M is not positive definite; x is then not
+// written); with the gate closed nothing is solved and flag[0] = 2
 void launch_dense_solve(hipStream_t s, int n, const double *M, double *fac, double *Linv, const double *b, double *x,
-                        int *flag);
+                        int *flag, const int *gate);
+// end of a joint iteration: statistics slot `stat`, the level's count, gate
+// (see k_aff_stat)
+void launch_aff_stat(hipStream_t s, Ctx &c, const AffBufs &a, int level, double *stat, double conv_px);
 
 }  // namespace pba

@@ -1179,20 +1179,18 @@ pba_status aff_evaluate(Ctx &c, AffBufs &a, int level, double out[3]) {
     return PBA_OK;
 }
 
-// One joint iteration at `level` (the level started): the records, the FC
-// assembly of the pose block, the joint system, its solve and the updates;
-// synchronizes and fills *out.
+// One joint iteration at `level` (the level started), enqueued: the records,
+// the FC assembly of the pose block, the joint system, its solve, the
+// updates and the iteration's end (statistics slot `stat`, count, gate). e0 /
+// e1 (optional): events around the linearization.
 template <typename T>
-pba_status aff_iteration(Ctx &c, AffBufs &a, int level, pba_iter_stats *out) {
+void aff_enqueue(Ctx &c, AffBufs &a, int level, bool first, double *stat, double conv_px, hipEvent_t e0,
+                 hipEvent_t e1) {
     hipStream_t s = c.stream;
     double *geo = c.d_geo_a;
-    // PBA_FLAG_TIMING: HIP events around the linearization (the residual kernel)
-    const bool timing = (c.cfg.flags & PBA_FLAG_TIMING) != 0;
-    pba_status st;
-    if (timing && (st = ensure_events(c, 2)) != PBA_OK) return st;
-    if (timing) HIPCHK(hipEventRecord(c.ev_pool[0], s));
-    launch_aff_linearize(s, c, a, level, geo, c.iters_in_level == 0 ? 1 : 0);
-    if (timing) HIPCHK(hipEventRecord(c.ev_pool[1], s));
+    if (e0) (void)hipEventRecord(e0, s);
+    launch_aff_linearize(s, c, a, level, geo, first ? 1 : 0);
+    if (e1) (void)hipEventRecord(e1, s);
     Launch<T>::point_reduce(s, c, true);
     Launch<T>::pair_reduce_H(s, c);
     launch_mu(s, c, geo);
@@ -1203,54 +1201,22 @@ pba_status aff_iteration(Ctx &c, AffBufs &a, int level, pba_iter_stats *out) {
     else
         launch_fill(s, a.stats, 3, 0.0, nullptr);
     launch_aff_system(s, c, a, geo);
-    const int n8 = 8 * c.F;
-    launch_dense_solve(s, n8, a.M, a.fac, a.Linv, a.b, a.x, a.flag);
+    launch_dense_solve(s, 8 * c.F, a.M, a.fac, a.Linv, a.b, a.x, a.flag, c.d_gate);
     launch_aff_update(s, c, a, geo);
-    Launch<T>::relpose(s, c, c.d_poses, geo, (T *)c.d_rel_a);   // the pair geometry of the new parameters
-    double st3[3];
-    unsigned long long mx[2];
-    int flag = 0;
-    std::vector<double> x((size_t)n8);
-    HIPCHK(hipMemcpyAsync(st3, a.stats, sizeof(st3), hipMemcpyDeviceToHost, s));
-    HIPCHK(hipMemcpyAsync(mx, a.maxb, sizeof(mx), hipMemcpyDeviceToHost, s));
-    HIPCHK(hipMemcpyAsync(&flag, a.flag, sizeof(int), hipMemcpyDeviceToHost, s));
-    HIPCHK(hipMemcpyAsync(x.data(), a.x, x.size() * sizeof(double), hipMemcpyDeviceToHost, s));
-    HIPCHK(hipStreamSynchronize(s));
-    HIPCHK(hipGetLastError());
-    c.s_valid = false;   // d_S holds the pose block only
-    if (timing) {
-        float ms = 0.f;
-        HIPCHK(hipEventElapsedTime(&ms, c.ev_pool[0], c.ev_pool[1]));
-        c.t_ms[level] += ms;
-        c.t_launches[level]++;
-        c.t_res[level] += (int64_t)c.O * LANES_PER_OBS;
-    }
-    if (flag) return fail(&c, PBA_E_NUMERIC, "joint pose-brightness system is not positive definite");
-    double mp = 0.0;
-    for (int i = 0; i < 6 * c.F; ++i) mp = std::max(mp, std::fabs(x[(size_t)i]));
-    if (out) {
-        std::memset(out, 0, sizeof(*out));
-        out->level = level;
-        out->iter = c.iters_in_level;
-        out->n_active = (int64_t)std::llround(st3[2]);
-        out->energy = st3[0];
-        out->sq = st3[1];
-        out->rmse = out->n_active > 0 ? std::sqrt(st3[1] / (double)out->n_active) : 0.0;
-        double dv[2];
-        std::memcpy(dv, mx, sizeof(dv));
-        out->max_disp_px = dv[0];
-        out->max_step_pose = mp;
-        out->max_step_depth = dv[1];
-    }
-    c.iters_in_level++;
-    return PBA_OK;
+    launch_aff_stat(s, c, a, level, stat, conv_px);
+    Launch<T>::relpose(s, c, c.d_poses, geo, (T *)c.d_rel_a);   // the pair geometry of the current parameters
 }
 
-// Up to n_iters joint iterations at `level` (started), stopping after the
-// first whose displacement is below conv_px (conv_px >= 0).
+// Up to n_iters joint iterations at `level` (started) without host
+// synchronization in between; with conv_px >= 0 the device stops after the
+// first whose displacement is below conv_px. One synchronization at the end;
+// *ran = the iterations that ran.
 pba_status aff_run(Ctx &c, AffBufs &a, int level, int n_iters, double conv_px, pba_iter_stats *out, int *ran) {
     pba_status st;
     if ((st = aff_ensure(c, a)) != PBA_OK) return st;
+    if ((st = ensure_stats(c, n_iters)) != PBA_OK) return st;
+    const bool timing = (c.cfg.flags & PBA_FLAG_TIMING) != 0;
+    if (timing && (st = ensure_events(c, 2 * (size_t)n_iters)) != PBA_OK) return st;
     launch_open(c.stream, c, level, true);
     // the current pair geometry in the first buffer
     if (is_fp64(c))
@@ -1258,19 +1224,38 @@ pba_status aff_run(Ctx &c, AffBufs &a, int level, int n_iters, double conv_px, p
     else
         Launch<float>::relpose(c.stream, c, c.d_poses, c.d_geo_a, (float *)c.d_rel_a);
     c.flip = false;
-    int k = 0;
-    for (; k < n_iters; ++k) {
-        pba_iter_stats it;
-        st = is_fp64(c) ? aff_iteration<double>(c, a, level, &it) : aff_iteration<float>(c, a, level, &it);
-        if (st != PBA_OK) break;
-        if (out) out[k] = it;
-        if (conv_px >= 0.0 && it.max_disp_px < conv_px) {
-            ++k;
-            break;
-        }
+    const int it0 = c.iters_in_level;
+    for (int k = 0; k < n_iters; ++k) {
+        hipEvent_t e0 = timing ? c.ev_pool[2 * k] : nullptr, e1 = timing ? c.ev_pool[2 * k + 1] : nullptr;
+        double *stat = c.d_stats + (size_t)k * ST_STRIDE;
+        if (is_fp64(c))
+            aff_enqueue<double>(c, a, level, it0 + k == 0, stat, conv_px, e0, e1);
+        else
+            aff_enqueue<float>(c, a, level, it0 + k == 0, stat, conv_px, e0, e1);
     }
-    if (ran) *ran = k;
-    return st;
+    HIPCHK(hipGetLastError());
+    std::vector<double> hs((size_t)n_iters * ST_STRIDE);
+    int flag = 0, count = 0;
+    if (n_iters > 0)
+        HIPCHK(hipMemcpyAsync(hs.data(), c.d_stats, hs.size() * sizeof(double), hipMemcpyDeviceToHost, c.stream));
+    HIPCHK(hipMemcpyAsync(&flag, c.d_flag, sizeof(int), hipMemcpyDeviceToHost, c.stream));
+    HIPCHK(hipMemcpyAsync(&count, c.d_count + level, sizeof(int), hipMemcpyDeviceToHost, c.stream));
+    HIPCHK(hipStreamSynchronize(c.stream));
+    HIPCHK(hipGetLastError());
+    c.s_valid = false;   // d_S holds the pose block only
+    c.iters_in_level = it0 + count;
+    if (timing)
+        for (int k = 0; k < count; ++k) {
+            float ms = 0.f;
+            HIPCHK(hipEventElapsedTime(&ms, c.ev_pool[2 * k], c.ev_pool[2 * k + 1]));
+            c.t_ms[level] += ms;
+            c.t_launches[level]++;
+            c.t_res[level] += (int64_t)c.O * LANES_PER_OBS;
+        }
+    if (out) fill_stats(hs.data(), level, it0, count, out);
+    if (ran) *ran = count;
+    if (flag) return fail(&c, PBA_E_NUMERIC, "joint pose-brightness system is not positive definite");
+    return PBA_OK;
 }
 
 std::string pc_system_check(Ctx &c) {

@@ -636,10 +636,25 @@ __global__ void k_noalloc_info(const int *__restrict__ flag, int *__restrict__ i
     if (threadIdx.x == 0) *info = *flag ? 1 : 0;
 }
 
-void launch_dense_solve(hipStream_t s, int n, const double *M, double *fac, double *Linv, const double *b, double *x,
-                        int *flag) {
+// Copy M into the factor buffer; flag = 0 and the solve's gate open while
+// `gate` is open, else flag = 2 (no solve; the kernels that read the flag skip).
+__global__ void k_dense_begin(int n, const double *__restrict__ M, double *__restrict__ fac, int *__restrict__ flag,
+                              const int *__restrict__ gate) {
+    const int open = *gate != 0;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        flag[0] = open ? 0 : 2;
+        flag[1] = open;
+    }
+    if (!open) return;
     const size_t nn = (size_t)n * n;
-    k_noalloc_begin<<<(unsigned)std::min<size_t>(1024, (nn + 255) / 256), 256, 0, s>>>(n, M, fac, flag, flag + 1);
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < nn; i += (size_t)gridDim.x * blockDim.x)
+        fac[i] = M[i];
+}
+
+void launch_dense_solve(hipStream_t s, int n, const double *M, double *fac, double *Linv, const double *b, double *x,
+                        int *flag, const int *gate) {
+    const size_t nn = (size_t)n * n;
+    k_dense_begin<<<(unsigned)std::min<size_t>(1024, (nn + 255) / 256), 256, 0, s>>>(n, M, fac, flag, gate);
     tchol_ptrs(s, n, M, fac, Linv, flag, flag + 1);
     tsolve_ptrs(s, n, fac, Linv, b, x, flag);
 }
