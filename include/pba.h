@@ -298,8 +298,9 @@ pba_status pba_drop_frame(pba_ctx *ctx, int32_t window, int32_t frame);
  * frame keeps its pose and brightness; the brightness block is damped by
  * damping_rel times the mean of its diagonal; the brightness update is
  * additive), the iterations of a call enqueued with one host synchronization
- * at the end (pba_solve: one per level; a device gate stops a level at
- * conv_px). The frozen residual
+ * at the end (pba_solve: its whole coarse-to-fine schedule, a device gate
+ * stopping each level at conv_px, captured as one HIP graph with
+ * PBA_FLAG_GRAPH). The frozen residual
  * set, Huber weights, pose and depth damping and the convergence test are the
  * FC iteration's. ab = NULL turns the model off (the parameters are kept for
  * pba_get_affine). Needs mode PBA_FC, precision PBA_FP64 or PBA_FP32 and one

@@ -562,13 +562,35 @@ pba_status do_start_level(Ctx &c, int level) {
 // each with the device convergence gate) enqueued without host synchronization;
 // with PBA_FLAG_GRAPH it is captured once as a HIP graph and replayed. Level l's
 // statistics go to d_stats[(n_levels - 1 - l) * max_iters + k].
-pba_status enqueue_solve(Ctx &c, int max_iters, double conv_px, bool events) {
+template <typename T>
+void aff_enqueue(Ctx &c, AffBufs &a, int level, bool first, double *stat, double conv_px, hipEvent_t e0,
+                 hipEvent_t e1);
+
+// aff: the joint pose-brightness iteration (pba_set_affine) instead of the plain one
+pba_status enqueue_solve(Ctx &c, int max_iters, double conv_px, bool events, AffBufs *aff = nullptr) {
     for (int level = c.cfg.n_levels - 1; level >= 0; --level) {
         // a failure at a coarser level keeps the gate closed for the rest
         const bool clear = level == c.cfg.n_levels - 1;
         pba_status st = is_fp64(c) ? start_level<double>(c, level, clear) : start_level<float>(c, level, clear);
         if (st != PBA_OK) return st;
         const int slot = c.cfg.n_levels - 1 - level;
+        if (aff) {
+            // the pair geometry of the current parameters in the first buffer
+            if (is_fp64(c))
+                Launch<double>::relpose(c.stream, c, c.d_poses, c.d_geo_a, (double *)c.d_rel_a);
+            else
+                Launch<float>::relpose(c.stream, c, c.d_poses, c.d_geo_a, (float *)c.d_rel_a);
+            c.flip = false;
+            for (int k = 0; k < max_iters; ++k) {
+                const size_t idx = (size_t)slot * max_iters + k;
+                hipEvent_t e0 = events ? c.ev_pool[4 * idx] : nullptr, e1 = events ? c.ev_pool[4 * idx + 1] : nullptr;
+                if (is_fp64(c))
+                    aff_enqueue<double>(c, *aff, level, k == 0, c.d_stats + idx * ST_STRIDE, conv_px, e0, e1);
+                else
+                    aff_enqueue<float>(c, *aff, level, k == 0, c.d_stats + idx * ST_STRIDE, conv_px, e0, e1);
+            }
+            continue;
+        }
         const int m = recentre_every(c);
         for (int k = 0; k < max_iters; ++k) {
             // proxy re-centring every m iterations (gated: nothing once the level
@@ -590,7 +612,7 @@ pba_status enqueue_solve(Ctx &c, int max_iters, double conv_px, bool events) {
     return PBA_OK;
 }
 
-pba_status solve_batch(Ctx &c, int max_iters, double conv_px, pba_result &res) {
+pba_status solve_batch(Ctx &c, int max_iters, double conv_px, pba_result &res, AffBufs *aff = nullptr) {
     pba_status st;
     const int L = c.cfg.n_levels;
     if ((st = ensure_stats(c, L * max_iters)) != PBA_OK) return st;
@@ -611,7 +633,7 @@ pba_status solve_batch(Ctx &c, int max_iters, double conv_px, pba_result &res) {
             drop_graph(c);
             hipGraph_t g = nullptr;
             HIPCHK(hipStreamBeginCapture(c.stream, hipStreamCaptureModeThreadLocal));
-            st = enqueue_solve(c, max_iters, conv_px, false);
+            st = enqueue_solve(c, max_iters, conv_px, false, aff);
             hipError_t e = hipStreamEndCapture(c.stream, &g);
             if (st != PBA_OK) {
                 if (g) (void)hipGraphDestroy(g);
@@ -625,7 +647,7 @@ pba_status solve_batch(Ctx &c, int max_iters, double conv_px, pba_result &res) {
             c.graph_conv = conv_px;
         }
         HIPCHK(hipGraphLaunch(c.solve_graph, c.stream));
-    } else if ((st = enqueue_solve(c, max_iters, conv_px, timing)) != PBA_OK) {
+    } else if ((st = enqueue_solve(c, max_iters, conv_px, timing, aff)) != PBA_OK) {
         return st;
     }
     std::vector<double> hs((size_t)L * max_iters * ST_STRIDE);
@@ -645,7 +667,7 @@ pba_status solve_batch(Ctx &c, int max_iters, double conv_px, pba_result &res) {
                 c.t_ms[level] += ms;
                 c.t_launches[level]++;
                 c.t_res[level] += (int64_t)c.O * LANES_PER_OBS;
-                if (c.cfg.mode == PBA_IC_PROXY && ic_fused(c)) {
+                if (!aff && c.cfg.mode == PBA_IC_PROXY && ic_fused(c)) {
                     HIPCHK(hipEventElapsedTime(&ms, c.ev_pool[4 * idx + 2], c.ev_pool[4 * idx + 3]));
                     c.t_step_ms[level] += ms;
                     c.t_step_launches[level]++;
@@ -664,7 +686,10 @@ pba_status solve_batch(Ctx &c, int max_iters, double conv_px, pba_result &res) {
     // segment (since the last re-centring) that ran
     c.cur_level = 0;
     c.iters_in_level = counts[0];
-    {
+    if (aff) {
+        c.flip = false;   // the joint iteration keeps the pair geometry in the first buffer
+        c.s_valid = false;
+    } else {
         const int m = recentre_every(c), kl = counts[0];
         const int seg = (m > 0 && kl > 0) ? kl - m * ((kl - 1) / m) : kl;
         c.flip = seg % 2 == 1;
@@ -1127,6 +1152,7 @@ void aff_release(AffBufs &a) {
 // parameters are kept while the frame count is unchanged, else set to zero.
 pba_status aff_ensure(Ctx &c, AffBufs &a) {
     if (a.ab && a.F == c.F && a.O == c.O) return PBA_OK;
+    drop_graph(c);   // a captured solve holds the old buffers
     const bool keep_ab = a.ab && a.F == c.F;
     const size_t n8 = 8 * (size_t)c.F, nt = (n8 + TCHOL_TILE - 1) / TCHOL_TILE, d = sizeof(double);
     if (!keep_ab) {
@@ -1555,22 +1581,9 @@ pba_status pba_solve(pba_ctx *ctx, int32_t max_iters_per_level, double conv_px, 
     if ((st = ready(ctx)) != PBA_OK) return st;
     pba_result res;
     std::memset(&res, 0, sizeof(res));
-    if (ctx->aff.on) {
-        // coarse to fine, one synchronized iteration at a time
-        std::vector<pba_iter_stats> its((size_t)max_iters_per_level);
-        for (int level = c.cfg.n_levels - 1; level >= 0; --level) {
-            if ((st = do_start_level(c, level)) != PBA_OK) return st;
-            int k = 0;
-            st = aff_run(c, ctx->aff, level, max_iters_per_level, conv_px, its.data(), &k);
-            for (int i = 0; i < k; ++i) res.active_residuals += its[(size_t)i].n_active;
-            res.iters[level] = k;
-            res.total_iters += k;
-            if (st != PBA_OK) return st;
-            if (level == 0) res.converged = (k > 0 && its[(size_t)k - 1].max_disp_px < conv_px) ? 1 : 0;
-        }
-    } else if ((st = solve_batch(c, max_iters_per_level, conv_px, res)) != PBA_OK) {
+    if (ctx->aff.on && (st = aff_ensure(c, ctx->aff)) != PBA_OK) return st;
+    if ((st = solve_batch(c, max_iters_per_level, conv_px, res, ctx->aff.on ? &ctx->aff : nullptr)) != PBA_OK)
         return st;
-    }
     pba_iter_stats ev;
     if ((st = pba_evaluate(ctx, 0, &ev)) != PBA_OK) return st;
     res.final_energy = ev.energy;
@@ -1666,6 +1679,7 @@ pba_status pba_set_affine(pba_ctx *ctx, const double *ab) {
     if (!ctx) return fail(nullptr, PBA_E_INVALID, "ctx is NULL");
     Ctx &c = ctx->c;
     if (!ab) {
+        if (ctx->aff.on) drop_graph(c);
         ctx->aff.on = false;
         return PBA_OK;
     }
@@ -1677,6 +1691,7 @@ pba_status pba_set_affine(pba_ctx *ctx, const double *ab) {
     if ((st = aff_ensure(c, ctx->aff)) != PBA_OK) return st;
     HIPCHK(hipMemcpyAsync(ctx->aff.ab, ab, 2 * (size_t)c.F * sizeof(double), hipMemcpyHostToDevice, c.stream));
     HIPCHK(hipStreamSynchronize(c.stream));
+    if (!ctx->aff.on) drop_graph(c);
     ctx->aff.on = true;
     return PBA_OK;
 }

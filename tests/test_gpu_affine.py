@@ -32,9 +32,9 @@ def brightened(sc, seed):
                                inv_depth_init=sc.inv_depth_gt.copy()), ab
 
 
-def make(sc, precision=0):
+def make(sc, precision=0, flags=0):
     s = pba.Solver(mode=pba.PBA_FC, precision=precision, n_levels=sc.n_levels, pattern=sc.pattern,
-                   huber_k=sc.huber_k)
+                   huber_k=sc.huber_k, flags=flags)
     s.set_scene(sc)
     s.set_affine(np.zeros((sc.n_frames, 2)))
     return s
@@ -123,6 +123,30 @@ def test_affine_solve_planar_matches_oracle():
     np.testing.assert_allclose(poses, gn.poses, atol=1e-8)
     np.testing.assert_allclose(d, gn.d, rtol=1e-8)
     np.testing.assert_allclose(s.get_affine(), gn.ab, atol=1e-8)
+
+
+def test_affine_solve_graph_replays():
+    # the coarse-to-fine joint solve captured as one HIP graph and replayed
+    # from the start three times (parameters and brightness reset between
+    # replays) gives the enqueued solve's iteration counts and result (to
+    # rounding: the brightness rows are FP64 atomic sums, whose order varies
+    # between runs, amplified by this scene's brightness-geometry trade-off)
+    sc, _ = planar2()
+    ref = make(sc)
+    r0, _ = ref.solve(12, 1e-5)
+    p0, d0 = ref.get_params()
+    g = make(sc, flags=pba.PBA_FLAG_GRAPH)
+    zero = np.zeros((sc.n_frames, 2))
+    for _ in range(3):
+        g.set_params(sc.poses_init, sc.inv_depth_init)
+        g.set_affine(zero)
+        r, status = g.solve(12, 1e-5)
+        assert status == pba.PBA_OK and list(r.iters) == list(r0.iters)
+        p, d = g.get_params()
+        np.testing.assert_allclose(p, p0, atol=1e-8)
+        np.testing.assert_allclose(d, d0, rtol=1e-8)
+        np.testing.assert_allclose(g.get_affine(), ref.get_affine(), atol=1e-8)
+        np.testing.assert_allclose(r.final_rmse, r0.final_rmse, rtol=1e-8)
 
 
 def test_affine_one_iteration_fp32(tiny_b):
