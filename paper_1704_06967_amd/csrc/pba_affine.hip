@@ -273,23 +273,20 @@ __global__ __launch_bounds__(PAIR_CHUNK) void k_aff_pairs(int F, const int *__re
 
 // The depth Schur terms of the brightness rows and of the whole right-hand
 // side, over the points of one host chunk (points of one host frame; one
-// workgroup each): -u_i u_j^T / H_dd and -u_i g_d / H_dd over a point's frames
-// (host and targets), with u the point's coupling to a frame's pose (A^T h, or
-// the sum of B^T h for the host) and brightness. Each group of AFF_GROUP lanes
-// takes one point at a time: its lanes take the point's observations (the
-// couplings), then the entries of its Schur terms, which are distinct within
-// the group. The sums run in LDS over the host's frame set (host and its
-// targets) and are added to the global system once per chunk. The pose-pose
-// terms come from the FC assembly.
-// Dynamic LDS for frame sets of at most Emax frames and `groups` groups: BB,
-// BP, rb, rp, U (doubles), then Ue and fr (ints).
-static inline size_t aff_schur_lds(int Emax, int groups) {
-    const size_t nb = 2 * (size_t)Emax, np = 6 * (size_t)Emax;
-    return (nb * nb + nb * np + nb + np + (size_t)groups * (Emax + 1) * 8) * sizeof(double) +
-           ((size_t)groups * (Emax + 1) + Emax) * sizeof(int);
-}
+// workgroup each): with u_p the point's couplings over the host's frame set
+// (host and targets; per frame its pose, A^T h or for the host the sum of
+// B^T h, and its brightness, h_phi), the brightness rows get
+// -sum_p u_p,phi u_p^T / H_dd and the right-hand side -sum_p u_p g_d / H_dd.
+// The couplings of a batch of points go to LDS as the rows of a matrix U
+// (points x 8E, zero where a point does not observe a frame; one 32-lane
+// group per point, one lane per observation), then the threads form the
+// entries of the 2E x 8E block and of the 8E right-hand side as dot products
+// over the batch's rows and add them to the global system (once per chunk
+// when the chunk fits one batch: up to 128 points for frame sets of 7
+// frames, 48 for the largest). The pose-pose terms come from the FC assembly.
+constexpr int AFF_SCHUR_THREADS = 1024, AFF_SCHUR_GROUPS = AFF_SCHUR_THREADS / AFF_GROUP;
 
-__global__ __launch_bounds__(1024) void k_aff_schur(
+__global__ __launch_bounds__(AFF_SCHUR_THREADS) void k_aff_schur(
     int F, int Emax, const int *__restrict__ chunk_host, const int *__restrict__ chunk_begin,
     const int *__restrict__ chunk_end, const int *__restrict__ host_m, const int *__restrict__ hosts,
     const int *__restrict__ host_pts, const int *__restrict__ obs_ptr, const int *__restrict__ obs_pair,
@@ -298,113 +295,83 @@ __global__ __launch_bounds__(1024) void k_aff_schur(
     const double *__restrict__ gdn, double *__restrict__ M, double *__restrict__ b, const int *__restrict__ gate) {
     extern __shared__ double lds[];
     if (*gate == 0) return;
-    const int groups = blockDim.x / AFF_GROUP;
-    const int nbm = 2 * Emax, npm = 6 * Emax;
-    double *BB = lds;                    // brightness x brightness [nb][nb]
-    double *BP = BB + nbm * nbm;         // brightness x pose [nb][np]
-    double *rb = BP + nbm * npm, *rp = rb + nbm;
-    double *Ub = rp + npm;               // per group: t (6), p (2) per slot of its point [groups][Emax + 1][8]
-    int *Ueb = (int *)(Ub + (size_t)groups * (Emax + 1) * 8);   // frame-set index of each slot (slot 0: the host)
-    int *fr = Ueb + groups * (Emax + 1);  // frame of each frame-set index [Emax]
     const int ch = blockIdx.x, hi = chunk_host[ch];
-    const int E = min(host_m[hi] + 1, Emax), nb = 2 * E, np = 6 * E;
-    for (int i = threadIdx.x; i < nb * nb; i += blockDim.x) BB[i] = 0.0;
-    for (int i = threadIdx.x; i < nb * np; i += blockDim.x) BP[i] = 0.0;
-    for (int i = threadIdx.x; i < np; i += blockDim.x) rp[i] = 0.0;
-    for (int i = threadIdx.x; i < nb; i += blockDim.x) rb[i] = 0.0;
+    const int E = min(host_m[hi] + 1, Emax), nb = 2 * E, n8 = 8 * E, n6 = 6 * E;
+    int *fr = (int *)lds;                           // frame of each frame-set index [Emax]
+    double *wv = lds + (Emax + 1) / 2 + 1;          // per batch row: 1 / H_dd, then g_d / H_dd
+    // rows of U per batch: as many as the dynamic LDS holds
+    const int Pb = min(128, (int)((AFF_LDS_MAX / sizeof(double) - ((Emax + 1) / 2 + 1)) / (n8 + 2)));
+    double *gv = wv + Pb, *U = gv + Pb;             // U [Pb][8E]: pose (6e + k), then brightness (6E + 2e + l)
     for (int i = threadIdx.x; i < Emax; i += blockDim.x) fr[i] = i == 0 ? hosts[hi] : -1;
-    __syncthreads();
+    const int nent = nb * n8, ntot = nent + n8;     // brightness-row entries, then right-hand side entries
+    const int F6 = 6 * F;
+    const size_t N8 = 8 * (size_t)F;
     const int g = threadIdx.x / AFF_GROUP, lane = threadIdx.x % AFF_GROUP;
-    double(*U)[8] = (double(*)[8])(Ub + (size_t)g * (Emax + 1) * 8);
-    int *Ue = Ueb + g * (Emax + 1);
     const int q0 = chunk_begin[ch], q1 = chunk_end[ch];
-    for (int base = q0; base < q1; base += groups) {
-        const int q = base + g;
-        int n = 0, o0 = 0, m = -1;   // m: observations of the group's point (-1: none)
-        if (q < q1) {
-            n = host_pts[q];
-            o0 = obs_ptr[n];
-            m = min(obs_ptr[n + 1] - o0, E - 1);
-        }
-        const double iH = m >= 0 ? 1.0 / Hdd[n] : 0.0, gd = m >= 0 ? gdn[n] : 0.0;
-        // lane j: observation o0 + j (slot 1 + j)
-        double tb[6] = {0, 0, 0, 0, 0, 0}, ph0 = 0.0, ph1 = 0.0;
-        if (lane < m) {
-            const int o = o0 + lane, p = obs_pair[o];
-            const int e = 1 + pair_local[p];
-            const bool in = e < E;   // (the structure keeps every host within AFF_EMAX frames)
-            if (in) fr[e] = pair_target[p];   // the same value from every writer
-            const double *gm = geo + GEO_STRIDE * p;
-            const double *hv = rec + (size_t)o * REC_STRIDE + REC_h, *ar = arec + (size_t)o * AFF_STRIDE;
-            double ta[6];
-            apply_At(gm, hv, ta);
-            apply_Bt(gm, hv, tb);
-            ph0 = ar[AFF_h];
-            ph1 = ar[AFF_h + 1];
-            for (int k = 0; k < 6; ++k) U[1 + lane][k] = ta[k];
-            U[1 + lane][6] = ar[AFF_h + 2];
-            U[1 + lane][7] = ar[AFF_h + 3];
-            Ue[1 + lane] = in ? e : -1;
-        }
-        // the host's coupling: sums over the point's observations
-        for (int k = 0; k < 6; ++k) tb[k] = group_sum_d(tb[k]);
-        ph0 = group_sum_d(ph0);
-        ph1 = group_sum_d(ph1);
-        if (lane == 0 && m >= 0) {
-            for (int k = 0; k < 6; ++k) U[0][k] = tb[k];
-            U[0][6] = ph0;
-            U[0][7] = ph1;
-            Ue[0] = 0;
-        }
+    for (int sb = q0; sb < q1; sb += Pb) {
+        const int rows = min(Pb, q1 - sb);
+        __syncthreads();   // the previous batch's rows are no longer read
+        for (int i = threadIdx.x; i < rows * n8; i += blockDim.x) U[i] = 0.0;
         __syncthreads();
-        // (m + 1)^2 slot pairs x 16 entries, then (m + 1) x 8 right-hand side entries
-        const int S = m + 1, nS = S * S * 16, total = nS + S * 8;
-        for (int idx = lane; idx < total; idx += AFF_GROUP) {
-            if (idx < nS) {
-                const int pr = idx >> 4, c = idx & 15, si = pr / S, sj = pr % S;
-                const int ei = Ue[si], ej = Ue[sj];
-                if (ei < 0 || ej < 0) continue;
-                if (c < 12) {
-                    const int k = c >> 1, l = c & 1;
-                    atomicAdd(BP + (2 * ej + l) * np + 6 * ei + k, -U[si][k] * U[sj][6 + l] * iH);
-                } else {
-                    const int k = (c - 12) >> 1, l = c & 1;
-                    atomicAdd(BB + (2 * ei + k) * nb + 2 * ej + l, -U[si][6 + k] * U[sj][6 + l] * iH);
+        for (int row = g; row < rows; row += AFF_SCHUR_GROUPS) {
+            const int n = host_pts[sb + row];
+            const int o0 = obs_ptr[n], m = min(obs_ptr[n + 1] - o0, E - 1);
+            double *u = U + (size_t)row * n8;
+            double tb[6] = {0, 0, 0, 0, 0, 0}, ph0 = 0.0, ph1 = 0.0;
+            if (lane < m) {
+                const int o = o0 + lane, p = obs_pair[o];
+                const int e = 1 + pair_local[p];
+                const double *gm = geo + GEO_STRIDE * p;
+                const double *hv = rec + (size_t)o * REC_STRIDE + REC_h, *ar = arec + (size_t)o * AFF_STRIDE;
+                apply_Bt(gm, hv, tb);
+                ph0 = ar[AFF_h];
+                ph1 = ar[AFF_h + 1];
+                if (e < E) {   // (the structure keeps every host within AFF_EMAX frames)
+                    fr[e] = pair_target[p];   // the same value from every writer
+                    double ta[6];
+                    apply_At(gm, hv, ta);
+                    for (int k = 0; k < 6; ++k) u[6 * e + k] = ta[k];
+                    u[n6 + 2 * e] = ar[AFF_h + 2];
+                    u[n6 + 2 * e + 1] = ar[AFF_h + 3];
                 }
-            } else {
-                const int r = idx - nS, si = r >> 3, c = r & 7, ei = Ue[si];
-                if (ei < 0) continue;
-                const double v = -U[si][c] * gd * iH;
-                if (c < 6)
-                    atomicAdd(rp + 6 * ei + c, v);
-                else
-                    atomicAdd(rb + 2 * ei + (c - 6), v);
+            }
+            for (int k = 0; k < 6; ++k) tb[k] = group_sum_d(tb[k]);
+            ph0 = group_sum_d(ph0);
+            ph1 = group_sum_d(ph1);
+            if (lane == 0) {
+                for (int k = 0; k < 6; ++k) u[k] = tb[k];
+                u[n6] = ph0;
+                u[n6 + 1] = ph1;
+                const double iH = 1.0 / Hdd[n];
+                wv[row] = iH;
+                gv[row] = gdn[n] * iH;
             }
         }
         __syncthreads();
-    }
-    // once per chunk into the global system (hardware FP64 atomics on device memory)
-    const int F6 = 6 * F;
-    const size_t n8 = 8 * (size_t)F;
-    for (int i = threadIdx.x; i < nb * nb; i += blockDim.x) {
-        const int r = i / nb, cc = i % nb, fa = fr[r >> 1], fb = fr[cc >> 1];
-        if (BB[i] == 0.0 || fa < 0 || fb < 0) continue;
-        unsafeAtomicAdd(M + (size_t)(F6 + 2 * fa + (r & 1)) * n8 + F6 + 2 * fb + (cc & 1), BB[i]);
-    }
-    for (int i = threadIdx.x; i < nb * np; i += blockDim.x) {
-        const int r = i / np, cc = i % np, fa = fr[r >> 1], fb = fr[cc / 6];
-        if (BP[i] == 0.0 || fa < 0 || fb < 0) continue;
-        const size_t R = F6 + 2 * fa + (r & 1), C = 6 * fb + cc % 6;
-        unsafeAtomicAdd(M + R * n8 + C, BP[i]);
-        unsafeAtomicAdd(M + C * n8 + R, BP[i]);
-    }
-    for (int i = threadIdx.x; i < nb; i += blockDim.x) {
-        const int fa = fr[i >> 1];
-        if (fa >= 0 && rb[i] != 0.0) unsafeAtomicAdd(b + F6 + 2 * fa + (i & 1), rb[i]);
-    }
-    for (int i = threadIdx.x; i < np; i += blockDim.x) {
-        const int fa = fr[i / 6];
-        if (fa >= 0 && rp[i] != 0.0) unsafeAtomicAdd(b + 6 * fa + i % 6, rp[i]);
+        // the batch's sums, into the global system (hardware FP64 atomics on device memory)
+        for (int i = threadIdx.x; i < ntot; i += blockDim.x) {
+            const int c = i < nent ? i % n8 : i - nent;
+            double sum = 0.0;
+            if (i < nent) {
+                const int r = i / n8;
+                for (int q = 0; q < rows; ++q) sum += U[q * n8 + n6 + r] * U[q * n8 + c] * wv[q];
+            } else {
+                for (int q = 0; q < rows; ++q) sum += U[q * n8 + c] * gv[q];
+            }
+            if (sum == 0.0) continue;
+            const int fc = c < n6 ? fr[c / 6] : fr[(c - n6) >> 1];
+            if (fc < 0) continue;
+            const size_t C = c < n6 ? (size_t)(6 * fc + c % 6) : (size_t)(F6 + 2 * fc + ((c - n6) & 1));
+            if (i >= nent) {
+                unsafeAtomicAdd(b + C, -sum);
+                continue;
+            }
+            const int r = i / n8, fa = fr[r >> 1];
+            if (fa < 0) continue;
+            const size_t R = F6 + 2 * fa + (r & 1);
+            unsafeAtomicAdd(M + R * N8 + C, -sum);
+            if (c < n6) unsafeAtomicAdd(M + C * N8 + R, -sum);
+        }
     }
 }
 
@@ -639,10 +606,7 @@ void launch_aff_system(hipStream_t s, Ctx &c, const AffBufs &a, const double *ge
     if (nch > 0) {
         int Emax = 1;
         for (int m : c.st.host_m) Emax = std::max(Emax, std::min(m + 1, AFF_EMAX));
-        // as many groups (points in flight) as the LDS allows, 32 at most
-        int groups = 32;
-        while (groups > 1 && aff_schur_lds(Emax, groups) > AFF_LDS_MAX) groups /= 2;
-        k_aff_schur<<<nch, groups * AFF_GROUP, aff_schur_lds(Emax, groups), s>>>(
+        k_aff_schur<<<nch, AFF_SCHUR_THREADS, AFF_LDS_MAX, s>>>(
             F, Emax, c.d_chunk_host, c.d_chunk_begin, c.d_chunk_end, c.d_host_m, c.d_host_frames, c.d_host_pts,
             c.d_obs_ptr, c.d_obs_pair, c.d_pair_local, c.d_pair_target, geo, (const double *)c.d_rec, a.arec,
             c.d_Hdd, c.d_gd, a.M, a.b, c.d_gate);
