@@ -38,11 +38,15 @@ MEASURED_TRAFFIC = {"k_ic_residual": {"mid": 17164595, "precision": 128371917},
                     "k_ic_step": {"mid": 11062170},
                     "sources_sha256_16": "5241330df0b5690d"}
 KERNEL_SOURCES = ("pba_kernels.hip", "pba_solver.hip", "pba_depth.hpp", "pba_device.hpp", "pba_internal.hpp")
+# the same for the joint pose-brightness linearization (mid workload rendered
+# with per-frame brightness; profiles/aff_linearize_traffic_mid.md)
+MEASURED_TRAFFIC_AFFINE = {"k_aff_linearize": {"mid": 93969920}, "sources_sha256_16": "99c380c06b139b79"}
+AFFINE_SOURCES = ("pba_affine.hip", "pba_affine.hpp", "pba_device.hpp", "pba_internal.hpp")
 
 
-def kernel_sources_sha():
+def kernel_sources_sha(files=KERNEL_SOURCES):
     h = hashlib.sha256()
-    for f in KERNEL_SOURCES:
+    for f in files:
         with open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_1704_06967_amd", "csrc", f),
                   "rb") as fh:
             h.update(fh.read())
@@ -50,9 +54,12 @@ def kernel_sources_sha():
 
 
 def measured_traffic(kernel, workload):
-    if kernel_sources_sha() != MEASURED_TRAFFIC["sources_sha256_16"]:
+    table, files = MEASURED_TRAFFIC, KERNEL_SOURCES
+    if kernel in MEASURED_TRAFFIC_AFFINE:
+        table, files = MEASURED_TRAFFIC_AFFINE, AFFINE_SOURCES
+    if kernel_sources_sha(files) != table["sources_sha256_16"]:
         return None
-    return MEASURED_TRAFFIC[kernel].get(workload)
+    return table[kernel].get(workload)
 
 
 METRIC = "GN iters/s & residuals/s, IC-proxy vs FC on same GPU at equal final photo-RMSE"
@@ -401,7 +408,8 @@ def affine_section(pba, scene, iters=10, reps=3):
             "ms_per_joint_iteration": round(float(np.median(aff_ms)), 4),
             "ms_per_plain_fc_iteration": round(float(np.median(fc_ms)), 4),
             "rmse_after": rmse, "plain_fc_rmse_after": plain_rmse, "brightness_max_err": ab_err,
-            "roofline": roofline_obj("k_aff_linearize", aff_linearize_bytes(sc), avg, lin_n),
+            "roofline": roofline_obj("k_aff_linearize", aff_linearize_bytes(sc), avg, lin_n,
+                                     traffic=measured_traffic("k_aff_linearize", "mid")),
             "note": "both enqueue the iterations of a call as one batch (one host synchronization)"}
 
 

@@ -29,6 +29,15 @@ def test_measured_traffic_follows_the_kernel_sources(monkeypatch):
     monkeypatch.setitem(bench.MEASURED_TRAFFIC, "sources_sha256_16", "0" * 16)
     assert bench.measured_traffic("k_ic_residual", "mid") is None
     assert bench.measured_traffic("k_ic_step", "mid") is None
+    # the joint linearization has a table of its own, keyed on its own sources
+    h = hashlib.sha256()
+    for f in ("pba_affine.hip", "pba_affine.hpp", "pba_device.hpp", "pba_internal.hpp"):
+        h.update(open(os.path.join(ROOT, "paper_1704_06967_amd", "csrc", f), "rb").read())
+    monkeypatch.setitem(bench.MEASURED_TRAFFIC_AFFINE, "sources_sha256_16", h.hexdigest()[:16])
+    assert bench.measured_traffic("k_aff_linearize", "mid") == bench.MEASURED_TRAFFIC_AFFINE["k_aff_linearize"]["mid"]
+    assert bench.measured_traffic("k_aff_linearize", "precision") is None
+    monkeypatch.setitem(bench.MEASURED_TRAFFIC_AFFINE, "sources_sha256_16", "0" * 16)
+    assert bench.measured_traffic("k_aff_linearize", "mid") is None
 
 
 
