@@ -81,6 +81,7 @@ class AffineFC:
         self.poses = prob.poses_init.copy()
         self.d = prob.inv_depth_init.copy()
         self.ab = np.zeros((F, 2)) if ab is None else np.asarray(ab, float).copy()
+        self.obs_live = np.ones(len(prob.obs_frame), bool)   # observations still in the window
         self.level = None
         self.history = []
 
@@ -89,7 +90,19 @@ class AffineFC:
         self.level = level
         self.L = P.layout(level)
         _, valid0, _, _, _ = affine_residuals(P, self.L, self.poses, self.d, self.ab)
-        self.frozen = valid0
+        self.frozen = valid0 & self.obs_live[self.L.res_obs]
+
+    def drop_frame(self, f):
+        """Keyframe drop (sliding window, Sec. 4.2), as in the plain iteration:
+        every observation of a point hosted by f and every observation with
+        target f leave the window; from the next step the frozen residual set
+        and the convergence measure skip them."""
+        P = self.prob
+        assert 0 <= f < P.n_frames and f != P.pinned_frame, "the gauge frame cannot be dropped"
+        obs_host = np.repeat(P.host_frame, np.diff(P.obs_ptr))
+        self.obs_live &= ~((obs_host == f) | (P.obs_frame == f))
+        if self.level is not None:
+            self.frozen &= self.obs_live[self.L.res_obs]
 
     def step(self):
         P, L = self.prob, self.L
@@ -138,7 +151,7 @@ class AffineFC:
         self.poses = G.pack(Rn, tn)
         self.ab = self.ab + dx[F6:].reshape(-1, 2)
         self.d = self.d + dd
-        st["max_disp_px"] = RS.max_centre_displacement(L, before_p, before_d, self.poses, self.d)
+        st["max_disp_px"] = RS.max_centre_displacement(L, before_p, before_d, self.poses, self.d, self.obs_live)
         st["step_pose"] = float(np.max(np.abs(dx[:F6]))) if F6 else 0.0
         st["step_brightness"] = float(np.max(np.abs(dx[F6:]))) if F else 0.0
         st["step_depth"] = float(np.max(np.abs(dd))) if dd.size else 0.0

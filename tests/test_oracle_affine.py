@@ -123,3 +123,26 @@ def test_brightness_model_beats_the_plain_fc_on_a_brightened_scene():
     aff.iterate(0, 8)
     assert aff.history[-1]["rmse"] < 0.5 * plain.history[-1]["rmse"]
     assert np.abs(aff.ab - ab).max() < 2e-2
+
+
+@pytest.mark.parametrize("f", [1, 3])
+def test_affine_drop_equals_reduced_problem(f):
+    # dropping a frame's observations equals solving the problem whose input
+    # lacks them (frames and points kept), a path that shares none of the
+    # drop's code: the same statistics and steps
+    from tests.test_oracle_dynamic import reduced_scene_arrays
+    sc = scenes.tiny()
+    ab = seeded_ab(sc.n_frames, 6)
+    img = brighten(sc.images, ab)
+    a = AF.AffineFC(_problem(sc, img, sc.poses_gt, sc.inv_depth_gt))
+    a.drop_frame(f)
+    ptr, frames = reduced_scene_arrays(sc, f)
+    b = AF.AffineFC(Problem(img, sc.intrinsics, sc.poses_gt, sc.host_frame, sc.host_uv, sc.inv_depth_gt, ptr,
+                            frames, sc.pattern, n_levels=sc.n_levels, huber_k=sc.huber_k))
+    for sa, sb in zip(a.iterate(0, 3), b.iterate(0, 3)):
+        assert sa["n_active"] == sb["n_active"]
+        assert abs(sa["energy"] / sb["energy"] - 1) <= 1e-12
+        assert abs(sa["max_disp_px"] - sb["max_disp_px"]) <= 1e-9 * max(1.0, sb["max_disp_px"])
+    np.testing.assert_allclose(a.poses, b.poses, rtol=0, atol=1e-11)
+    np.testing.assert_allclose(a.d, b.d, rtol=1e-10)
+    np.testing.assert_allclose(a.ab, b.ab, rtol=0, atol=1e-11)
