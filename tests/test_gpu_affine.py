@@ -227,3 +227,22 @@ def test_affine_mid_full_first_records_fp32():
     assert np.array_equal(mask, ref_mask)
     assert st["n_active"] == int(act.sum())
     np.testing.assert_allclose(st["sq"], float(np.sum(r * r)), rtol=1e-5)
+
+
+@pytest.mark.parametrize("f", [1, 3])
+def test_affine_after_keyframe_drop_fp64(tiny_b, f):
+    # the brightness model with a frame dropped from the window
+    # (pba_drop_frame) against the oracle's drop: the frame's observations
+    # leave the frozen set and the convergence measure
+    sc, _ = tiny_b
+    s = make(sc)
+    s.drop_frame(f)
+    gn = AF.AffineFC(Problem.from_scene(sc))
+    gn.drop_frame(f)
+    for st, ref in zip(s.iterate(0, 3), gn.iterate(0, 3)):
+        _check_stats(st, ref, 1e-9)
+        np.testing.assert_allclose(st["max_disp_px"], ref["max_disp_px"], rtol=1e-7, atol=1e-9)
+    poses, d = s.get_params()
+    np.testing.assert_allclose(poses, gn.poses, atol=1e-9)
+    np.testing.assert_allclose(d, gn.d, rtol=1e-8, atol=1e-10)
+    np.testing.assert_allclose(s.get_affine(), gn.ab, atol=1e-9)
