@@ -308,7 +308,8 @@ pba_status pba_drop_frame(pba_ctx *ctx, int32_t window, int32_t frame);
  * zero. Errors: PBA_E_INVALID (mode, precision, windows, non-finite values),
  * PBA_E_STATE (frames or points not set); pba_iterate and pba_solve return
  * PBA_E_NUMERIC when the joint system is not positive definite (the
- * parameters are then left as they were). */
+ * failing iteration leaves the parameters as the previous one left them, and
+ * the level stops there). */
 pba_status pba_set_affine(pba_ctx *ctx, const double *ab);
 /* The current brightness parameters, host double [F][2] (zeros before
  * pba_set_affine). Errors: PBA_E_INVALID (ab NULL), PBA_E_STATE (no frames). */
