@@ -120,8 +120,9 @@ typedef struct {
                             call and replays it on later calls with the same
                             max_iters and conv_px; the graph is dropped (and captured
                             again when needed) when points are set, when max_iters
-                            or conv_px change, and when pba_autotune picks a launch
-                            shape. pba_iterate never uses the graph.
+                            or conv_px change, when pba_autotune picks a launch
+                            shape, and when pba_set_affine turns the brightness
+                            model on or off. pba_iterate never uses the graph.
                             PBA_FLAG_LANE_PER_PIXEL: the IC residual pass starts with
                             one lane per patch pixel (8 per observation) instead of one
                             thread per observation (pba_autotune may pick either); the
